@@ -1,0 +1,314 @@
+#!/usr/bin/env python3
+"""Throughput of the fused RNG + Langevin-dynamics path on one MI355X.
+
+One benchmark step = the config-2 workload for all three generators: seed the generator, then
+run N = 1e6 independent 3-D oscillators for 1e4 LD steps (dt = 0.005, m = k = kT = gamma = 1) with
+the Gaussian forces generated on the fly and observables recorded every 100 steps -- Hybrid Taus,
+Ran2 (32-entry table) and lagged Fibonacci (ll, sl) = (3021377, 1010202).  `value` is the
+oscillator-steps per second of that whole step.  The bare generators (config 3), the batched run
+(config 4) and the adjoint (config 5) are measured once after the timed steps and reported as extra
+fields; the CPU oracle is timed on a bounded sample of the config-2 workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "oscillator-steps/s fused LD+RNG; Gaussians/s; plain vs batched/adjoint"
+GENERATORS = ("taus", "ran2", "lf")
+
+# Algorithmic work per oscillator-step (the counting is explained in the design doc).
+# ALU-bound per-thread generators: lane operations of the method at one issue slot each.
+OPS_PER_OSC_STEP = {"taus": 130, "ran2": 134}
+# Lagged Fibonacci in step-synchronous waves: 4 numbers x (2 reads + 1 write) x 4 B of ring traffic
+# plus x and v read and written (6 x 4 B each way).
+LF_BYTES_PER_OSC_STEP = 4 * 12 + 48
+# MI355X: 256 CUs x 4 SIMD16 x 2.4 GHz = 3.93e13 non-packed 32-bit lane operations per second;
+# HBM3E 8 TB/s.
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only", default="", help="comma list of generators (profiling runs)")
+    return ap.parse_args()
+
+
+class Config2:
+    def __init__(self, R, W, torch, kinds):
+        c = W.C2
+        self.R, self.torch = R, torch
+        self.N, self.T, self.seed = c["N"], c["steps"], c["seed"]
+        p = c["params"].as_f32()
+        self.params = R.make_params(p.m, p.k, p.gamma, p.kT, p.dt)
+        self.ll, self.sl = c["lf_lags"]
+        self.kinds = kinds
+        self.stride = 100
+        self.P = self.T // self.stride + 1
+        N = self.N
+        self.x = torch.zeros(3 * N, dtype=torch.float32, device="cuda")
+        self.v = torch.zeros_like(self.x)
+        self.obs = {k: torch.zeros(self.P * R.NOBS, dtype=torch.float64, device="cuda") for k in kinds}
+        self.cfg, self.state, self.ws = {}, {}, {}
+        self.ens, self.n_ens = R.make_ensembles([(0, N, self.params, 0)])
+        for k in kinds:
+            cfg = R.make_cfg(k, seed=self.seed, n_streams=N, ll=self.ll if k == "lf" else 0,
+                             sl=self.sl if k == "lf" else 0)
+            self.cfg[k] = cfg
+            self.state[k] = R.new_state(cfg)
+            self.ws[k] = torch.empty(max(R.ld_workspace_bytes(cfg, self.ens, 1, N, self.T, R.Obs(self.stride, 0)),
+                                         256), dtype=torch.uint8, device="cuda")
+        self.events = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                       for k in kinds}
+
+    def step(self):
+        R = self.R
+        times = {}
+        for k in self.kinds:
+            e0, e1 = self.events[k]
+            R.rng_init(self.cfg[k], self.state[k])
+            self.x.zero_()
+            self.v.zero_()
+            e0.record()
+            R.ld_run(self.cfg[k], self.state[k], self.ens, 1, self.N, self.T, self.x, self.v,
+                     R.Obs(self.stride, 0), self.obs[k], self.ws[k])
+            e1.record()
+        return times
+
+    def elapsed(self):
+        return {k: self.events[k][0].elapsed_time(self.events[k][1]) for k in self.kinds}
+
+
+def roofline_entry(kind, ms_run, N, T, launches):
+    osc_steps = N * T
+    per_launch_s = ms_run / 1e3 / launches
+    if kind == "lf":
+        per_launch_bytes = LF_BYTES_PER_OSC_STEP * osc_steps / launches
+        achieved = per_launch_bytes / per_launch_s / 1e9
+        return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "lf_ld_phase_kernel",
+                "launches": launches, "avg_launch_us": per_launch_s * 1e6,
+                "algorithmic_bytes_per_launch": per_launch_bytes}
+    ops = OPS_PER_OSC_STEP[kind] * osc_steps / launches
+    achieved = ops / per_launch_s / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
+            "frac": achieved / ALU_PEAK_TOPS, "traffic": None, "kernel": "ld_run_kernel<%s>" % kind,
+            "launches": launches, "avg_launch_us": per_launch_s * 1e6, "algorithmic_ops_per_launch": ops}
+
+
+def cpu_baseline(W):
+    """The FP64 oracle on a bounded sample of config 2: N = 1e4 oscillators x 500 steps per
+    generator, single thread, same parameters and lags."""
+    import numpy as np
+    import oracle as orc
+
+    c = W.C2
+    p = c["params"].as_f32().asdict()
+    N, T = 10_000, 500
+    ll, sl = c["lf_lags"]
+    total_t, total_os = 0.0, 0
+    per = {}
+    for kind in GENERATORS:
+        st = orc.lf_seed(c["seed"], ll) if kind == "lf" else orc.seed_states(kind, c["seed"], np.arange(N))
+        t = time.perf_counter()
+        orc.ld_run(kind, st, N, T, p, ll=ll, sl=sl, stride=100)
+        dt = time.perf_counter() - t
+        per[kind] = N * T / dt
+        total_t += dt
+        total_os += N * T
+    return {"value": total_os / total_t, "unit": "oscillator-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "config-2 workload at N=1e4 oscillators x 500 steps per generator (3 x 5e6 "
+                      "oscillator-steps, %.1f s), FP64, one thread" % total_t,
+            "per_generator": per}
+
+
+def extras(R, W, torch):
+    out = {}
+    ev = lambda: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    # config 3: bare generators
+    c3 = W.C3
+    S, per = c3["streams"], c3["per_stream"]
+    n_vals = S * per
+    buf_u = torch.empty(n_vals, dtype=torch.int32, device="cuda")
+    buf_g = torch.empty(n_vals, dtype=torch.float32, device="cuda")
+    bare = {}
+    for kind in GENERATORS:
+        if kind == "lf":
+            cfg = R.make_cfg("lf", seed=c3["seed"], ll=c3["lf_lags"][0], sl=c3["lf_lags"][1])
+            count = c3["lf_count"]
+        else:
+            cfg = R.make_cfg(kind, seed=c3["seed"], n_streams=S)
+            count = per
+        st = R.new_state(cfg)
+        R.rng_init(cfg, st)
+        R.rng_uniform(cfg, st, count, buf_u)  # warm-up
+        a, b = ev()
+        a.record()
+        R.rng_uniform(cfg, st, count, buf_u)
+        b.record()
+        c, d = ev()
+        c.record()
+        R.rng_gaussian(cfg, st, count, buf_g)
+        d.record()
+        torch.cuda.synchronize()
+        bare[kind] = {"uint32_per_s": n_vals / (a.elapsed_time(b) / 1e3),
+                      "gaussians_per_s": n_vals / (c.elapsed_time(d) / 1e3),
+                      "uint32_GBps_written": 4 * n_vals / (a.elapsed_time(b) / 1e3) / 1e9}
+    del buf_u, buf_g
+    out["config3_bare_generators"] = bare
+    # config 4: batched ensembles in one hipGraph-captured plan vs 512 plain launches
+    c4 = W.C4
+    ens_list = W.batched_ensembles(c4["n_ens"], c4["draw_seed"], c4["base_seed"], c4["dt"])
+    offs = [0]
+    for e in ens_list:
+        offs.append(offs[-1] + e.n)
+    n_total = offs[-1]
+    specs = [(offs[i], e.n, R.make_params(e.params.m, e.params.k, e.params.gamma, e.params.kT, e.params.dt), e.seed)
+             for i, e in enumerate(ens_list)]
+    ens, n_ens = R.make_ensembles(specs)
+    cfg = R.make_cfg("taus", n_streams=n_total)
+    tune = R.ld_autotune(cfg, ens, n_ens, n_total, c4["steps"], os.path.join(ROOT, "gpurun_out", "autotune.txt")
+                         if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None)
+    st = R.new_state(cfg)
+    x = torch.zeros(3 * n_total, dtype=torch.float32, device="cuda")
+    v = torch.zeros_like(x)
+    R.rng_init_ensembles(cfg, st, ens, n_ens)
+    plan = R.Plan(cfg, st, ens, n_ens, n_total, c4["steps"], x, v)
+    a, b = ev()
+    a.record()
+    plan.launch()
+    b.record()
+    torch.cuda.synchronize()
+    t_batched = a.elapsed_time(b) / 1e3
+    plan.close()
+    R.rng_init_ensembles(cfg, st, ens, n_ens)
+    x.zero_()
+    v.zero_()
+    ws = torch.empty(max(R.ld_workspace_bytes(cfg, ens, n_ens, n_total, c4["steps"]), 256), dtype=torch.uint8,
+                     device="cuda")
+    a, b = ev()
+    a.record()
+    for i in range(n_ens):
+        e1, _ = R.make_ensembles([specs[i]])
+        R.ld_run(cfg, st, e1, 1, n_total, c4["steps"], x, v, ws=ws)
+    b.record()
+    torch.cuda.synchronize()
+    t_plain = a.elapsed_time(b) / 1e3
+    R.ld_set_tuning("taus")
+    osc_steps = n_total * c4["steps"]
+    out["config4_batched"] = {"ensembles": n_ens, "oscillators": n_total, "steps": c4["steps"],
+                              "osc_steps": osc_steps, "tuning": list(tune.astuple()),
+                              "batched_graph_osc_steps_per_s": osc_steps / t_batched,
+                              "plain_512_launches_osc_steps_per_s": osc_steps / t_plain,
+                              "speedup_batched_vs_plain": t_plain / t_batched}
+    del x, v, st, ws
+    # config 5: adjoint
+    from paper_1003_1123_amd import autograd as A
+    c5 = W.C5
+    p5 = c5["params"].as_f32()
+    run = A.AdjointRun("taus", [(c5["N"], p5.m, p5.dt, c5["seed"])], c5["steps"], c5["t_begin"], c5["t_end"],
+                       c5["K"])
+    k = torch.tensor([p5.k], dtype=torch.float64, requires_grad=True)
+    g = torch.tensor([p5.gamma], dtype=torch.float64, requires_grad=True)
+    kT = torch.tensor([p5.kT], dtype=torch.float64, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L = A.LDAdjoint.apply(k, g, kT, run)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.sum().backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    osc = c5["N"] * c5["steps"]
+    out["config5_adjoint"] = {"N": c5["N"], "steps": c5["steps"], "K": c5["K"], "loss": L.item(),
+                              "grad_k_gamma_kT": [k.grad.item(), g.grad.item(), kT.grad.item()],
+                              "forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3,
+                              "fwd_plus_bwd_over_fwd": (t2 - t0) / (t1 - t0),
+                              "forward_osc_steps_per_s": osc / (t1 - t0)}
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (each GPU would run "
+              "its own oscillators; see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1003_1123_amd import _lib as R
+    from paper_1003_1123_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    kinds = tuple(k for k in (args.only.split(",") if args.only else GENERATORS) if k)
+    c2 = Config2(R, W, torch, kinds)
+    log("config 2: N=%d, %d steps, generators %s" % (c2.N, c2.T, ",".join(kinds)))
+    for i in range(args.warmup):
+        c2.step()
+        torch.cuda.synchronize()
+        log("warmup step %d done" % i)
+    acc = {k: 0.0 for k in kinds}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        c2.step()
+        torch.cuda.synchronize()
+        for k, ms in c2.elapsed().items():
+            acc[k] += ms
+        log("step %d done" % i)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    osc_steps_per_step = len(kinds) * c2.N * c2.T
+    value = osc_steps_per_step * args.steps / wall
+    per_gen = {}
+    rooflines = {}
+    for k in kinds:
+        ms = acc[k] / args.steps
+        launches = 4 * c2.T if k == "lf" else 1
+        per_gen[k] = {"ms_per_run": ms, "osc_steps_per_s": c2.N * c2.T / (ms / 1e3),
+                      "gaussians_per_s": 3 * c2.N * c2.T / (ms / 1e3)}
+        rooflines[k] = roofline_entry(k, ms, c2.N, c2.T, launches)
+    dominant = max(kinds, key=lambda k: acc[k])
+    res = {
+        "metric": METRIC, "value": value, "unit": "oscillator-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "config 2: N=1e6 independent 3-D harmonic oscillators, 1e4 underdamped LD steps "
+                               "(dt=0.005, m=k=kT=gamma=1) per generator, observables every 100 steps",
+                   "generators": list(kinds), "N": c2.N, "ld_steps_per_run": c2.T, "lf_lags": [c2.ll, c2.sl]},
+        "roofline": rooflines[dominant],
+        "per_generator": per_gen,
+        "rooflines_all": rooflines,
+    }
+    if not args.no_extras:
+        res["extras"] = extras(R, W, torch)
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(W)
+        res["cpu_baseline"]["gpu_over_cpu"] = value / res["cpu_baseline"]["value"]
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

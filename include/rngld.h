@@ -1,0 +1,254 @@
+/*
+ * rngld.h -- C ABI of librngld: random numbers generated on the fly inside a Langevin-dynamics
+ * step, on AMD MI355X (gfx950).
+ *
+ * Method: Zhmurov, Rybnikov, Kholodov & Barsegov, "Efficient pseudo-random number generators for
+ * biomolecular simulations on graphics processors" (arXiv:1003.1123).  Generators: Hybrid Taus
+ * (Sec. II.D, Appendix A Alg. 1) and Ran2 (Sec. II.C, Alg. 2), one generator per thread
+ * (Sec. III.B); additive lagged Fibonacci mod 2^32 (Sec. II.E Eq. 3, Alg. 3, Table I), one
+ * generator shared by all threads (Sec. III.C).  Box-Muller turns uniforms into Gaussian forces
+ * (Sec. I, II.A); four uniforms feed the three force components of one oscillator-step
+ * (Table II caption).  The LD model is N independent 3-D harmonic oscillators in a stochastic
+ * thermostat (Sec. IV).
+ *
+ * Conventions for every entry point:
+ *  - returns RNGLD_OK (0) or a negative RNGLD_E* code; never throws; the message of the last
+ *    failure on the calling thread is rngld_last_error();
+ *  - all arguments are validated on the host before anything is enqueued; a failed call enqueues
+ *    nothing (except RNGLD_EHIP, raised by the HIP runtime while enqueueing);
+ *  - pointers prefixed d_ are device memory owned by the caller; h_ are host memory read during
+ *    the call only; nothing is allocated or freed (ld_autotune is the one exception, see there);
+ *  - work is enqueued on `stream` (a hipStream_t; NULL = the default stream) and the call returns
+ *    without synchronising; calls on one state buffer must be ordered by the caller;
+ *  - all integer words are little-endian uint32; floating point is IEEE binary32 unless stated.
+ */
+#ifndef RNGLD_H
+#define RNGLD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define RNGLD_API __attribute__((visibility("default")))
+#else
+#define RNGLD_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes --------------------------------------------------------------------------- */
+#define RNGLD_OK 0
+#define RNGLD_EINVAL (-1)  /* null pointer, unknown kind, inconsistent sizes or parameters */
+#define RNGLD_ELAG (-2)    /* lagged-Fibonacci lags / wave / ring unusable (see rngld_cfg) */
+#define RNGLD_ESIZE (-3)   /* a caller buffer is smaller than required */
+#define RNGLD_EHIP (-4)    /* the HIP runtime reported an error */
+#define RNGLD_ENOTSUP (-5) /* valid request that this library does not implement */
+
+/* ---- generator kinds ------------------------------------------------------------------------ */
+#define RNGLD_HYBRID_TAUS 0 /* Sec. II.D, Alg. 1: three taus88 components xor an LCG (Eq. 1) */
+#define RNGLD_RAN2 1        /* Sec. II.C, Alg. 2: two L'Ecuyer LCGs + 32-entry Bays-Durham table */
+#define RNGLD_LAGFIB 2      /* Sec. II.E, Alg. 3: y_n = y_{n-ll} + y_{n-sl} mod 2^32, shared */
+
+/*
+ * Generator configuration.
+ *  seed        : 64-bit seed.  Per-thread kinds: word i of global stream j is the high half of
+ *                SplitMix64's mix(seed + (4j + i + 1) * 0x9E3779B97F4A7C15); LF: the window
+ *                y_{-ll+i} = LCG^{i+1}(word 0 of stream 0), LCG of Eq. 1.
+ *  n_streams   : per-thread kinds: number of streams (= oscillators) the state holds, S.
+ *  stream_base : per-thread kinds: global index of the state's stream 0 (seeding only; lets
+ *                a state hold any contiguous range of one seed's streams).
+ *  lf_ll/lf_sl : LF long and short lag, 0 < sl < ll < 2^31 (Table I lists usable pairs).
+ *  lf_wave     : LF wave width W, positions generated concurrently; 0 selects sl.  Rounded down
+ *                to a multiple of 4.  Must satisfy 4 <= W <= sl (RNGLD_ELAG otherwise).  Results
+ *                do not depend on W.
+ *  lf_ring     : LF ring length R in words; 0 selects ll + W.  Must satisfy ll + W <= R < 2^31.
+ */
+typedef struct rngld_cfg {
+    int32_t kind;
+    uint32_t lf_ll;
+    uint32_t lf_sl;
+    uint32_t lf_wave;
+    uint64_t seed;
+    uint64_t n_streams;
+    uint64_t stream_base;
+    uint64_t lf_ring;
+} rngld_cfg;
+
+/*
+ * State buffer layouts (part of the ABI; a byte copy of the state is a checkpoint):
+ *  HYBRID_TAUS : uint32 z[4][S], component-major: z[c*S + j] is word c of stream j
+ *                (c = 0..2 Tausworthe components, 3 = LCG).                 16*S bytes.
+ *  RAN2        : int32 r[35][S]: row 0 idum, 1 idum2, 2 iy, 3+t iv[t] (t = 0..31).  140*S bytes.
+ *  LAGFIB      : 64-byte header { uint64 pos; uint32 slot; uint32 ll, sl, R, W; ... } followed by
+ *                uint32 ring[R]; y_n lives in ring[(slot + n - pos) mod R] for the last ll
+ *                positions n < pos.  pos counts values generated since rng_init.
+ */
+RNGLD_API int rngld_state_bytes(const rngld_cfg *cfg, size_t *bytes);
+
+/* Seed the state (Sec. III.B seeding, Alg. 2 initialisation for Ran2, Alg. 3 window for LF). */
+RNGLD_API int rng_init(const rngld_cfg *cfg, void *d_state, size_t state_bytes, void *stream);
+
+/*
+ * Bare generator output (no dynamics), advancing the state.
+ *  per-thread kinds: per_stream values of every stream, d_out[t*S + j] = value t of stream j;
+ *                    out_len >= per_stream*S.  Taus: the xor word; Ran2: iy in [1, 2147483562].
+ *  LAGFIB          : per_stream consecutive values of the one sequence, d_out[n] = y_{pos+n};
+ *                    d_out doubles as the lag table for the values it holds.
+ */
+RNGLD_API int rng_uniform(const rngld_cfg *cfg, void *d_state, size_t state_bytes, uint64_t per_stream,
+                uint32_t *d_out, uint64_t out_len, void *stream);
+
+/*
+ * Gaussian output: values 2i and 2i+1 of a stream are r cos(2 pi u1), r sin(2 pi u1) with
+ * r = sqrt(-2 ln u0), u0 = ((w0 >> 8) + 1) 2^-24, u1 = (w1 >> 8) 2^-24 from that stream's words
+ * 2i and 2i+1 (Ran2 word: (iy - 1) << 1).  per_stream must be even.  Layout as rng_uniform.
+ */
+RNGLD_API int rng_gaussian(const rngld_cfg *cfg, void *d_state, size_t state_bytes, uint64_t per_stream,
+                 float *d_out, uint64_t out_len, void *stream);
+
+/* ---- Langevin dynamics ------------------------------------------------------------------------ */
+/*
+ * Physical parameters (binary32).  scheme 0: underdamped (Sec. I), semi-implicit Euler-Maruyama
+ *   v' = (1 - gamma dt) v - (k dt / m) x + sqrt(2 gamma kT dt / m) g,   x' = x + dt v'.
+ * scheme 1: overdamped, Eq. (5) of Sec. IV with xi = m gamma:
+ *   x' = x - (k dt / xi) x + sqrt(2 kT dt / xi) g   (v untouched).
+ * Requires m > 0, gamma > 0, k >= 0, kT >= 0, dt > 0, all finite.
+ */
+typedef struct ld_params {
+    float m, k, gamma, kT, dt;
+    int32_t scheme;
+} ld_params;
+
+/* One ensemble of a (possibly batched) run: oscillators [offset, offset + n) of x, v and of the
+ * generator state, with its own parameters; seed is used by rng_init_ensembles only. */
+typedef struct ld_ensemble {
+    uint64_t offset;
+    uint64_t n;
+    ld_params p;
+    uint32_t pad;
+    uint64_t seed;
+} ld_ensemble;
+
+/* Observables, recorded after t = 0, stride, 2*stride, ... <= n_steps steps of a run (stride 0 =
+ * none), as means over the ensemble's 3n coordinates, 6 doubles per point:
+ * <x^2>, <v^2>, <x v>, <x>, <x(t) x(t0)>, <v(t) v(t0)> (the last two are 0 for t < t0).  Sec. IV. */
+typedef struct ld_obs {
+    uint32_t stride;
+    uint32_t t0;
+} ld_obs;
+
+#define RNGLD_NOBS 6
+
+/*
+ * Seed the per-thread state for batched runs: for each ensemble e, streams
+ * [offset_e, offset_e + n_e) of the state are seeded as streams 0..n_e-1 of seed_e, so ensemble e
+ * of a batched run reproduces a plain run of n_e oscillators with cfg.seed = seed_e.
+ * cfg->seed and cfg->stream_base are ignored.  Per-thread kinds only.
+ */
+RNGLD_API int rng_init_ensembles(const rngld_cfg *cfg, void *d_state, size_t state_bytes, const ld_ensemble *h_ens,
+                       uint32_t n_ens, void *stream);
+
+/*
+ * One LD step of n oscillators in the paper's protocol (Sec. IV; Fig. 5 caption): load x, v and
+ * the generator state from device memory, draw four words per oscillator, update, store back.
+ * d_x, d_v are float[3][n] component-major.  Per-thread kinds need n <= S.  LAGFIB: oscillator j
+ * takes y_{pos + 4j + r}, r = 0..3 (Alg. 3), run as ceil(4n / W) dependent waves.
+ */
+RNGLD_API int ld_step(const rngld_cfg *cfg, void *d_state, size_t state_bytes, const ld_params *p, uint64_t n, float *d_x,
+            float *d_v, void *stream);
+
+/*
+ * n_steps LD steps of n_ens ensembles (batched when n_ens > 1) with the generator fused into the
+ * update and x, v and the per-thread state held on chip for the whole run.
+ *  d_x, d_v   : float[3][n_total]; ensembles must lie inside [0, n_total) and must not overlap.
+ *  obs, d_obs : optional observables, d_obs = double[n_ens][P][6], P = n_steps/stride + 1.
+ *  d_ws       : workspace of ld_workspace_bytes() bytes (any alignment >= 256).
+ * LAGFIB supports n_ens == 1 only (one shared sequence).  The result of ensemble e equals a plain
+ * run (n_ens = 1, offset 0) on that ensemble alone, bit for bit, under the same tuning.
+ */
+RNGLD_API int ld_workspace_bytes(const rngld_cfg *cfg, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total,
+                       uint32_t n_steps, const ld_obs *obs, size_t *bytes);
+RNGLD_API int ld_run(const rngld_cfg *cfg, void *d_state, size_t state_bytes, const ld_ensemble *h_ens, uint32_t n_ens,
+           uint64_t n_total, uint32_t n_steps, float *d_x, float *d_v, const ld_obs *obs, double *d_obs,
+           void *d_ws, size_t ws_bytes, void *stream);
+
+/* ---- tuning, hipGraph plans, autotuner ------------------------------------------------------ */
+/*
+ * Launch shape of the per-thread LD kernels.  block: threads per block (64, 128, 256 or 512);
+ * osc_per_thread: 1 or 2; steps_per_launch: 0 = whole run in one launch; blocks_per_cu: 0 = one
+ * block per tile, else a persistent grid of blocks_per_cu * CUs blocks striding over tiles.
+ * block and osc_per_thread fix the reduction order of the observables.
+ */
+typedef struct ld_tuning {
+    uint32_t block;
+    uint32_t osc_per_thread;
+    uint32_t steps_per_launch;
+    uint32_t blocks_per_cu;
+} ld_tuning;
+
+/* Tuning used by ld_run for a generator kind (process-wide; default {256, 1, 0, 0}). */
+RNGLD_API int ld_get_tuning(int32_t kind, ld_tuning *out);
+RNGLD_API int ld_set_tuning(int32_t kind, const ld_tuning *t);
+
+/*
+ * Pick the fastest tuning for this workload shape by timing candidate launch shapes on short
+ * proxy runs, and install it with ld_set_tuning.  This is set-up code, not the hot path: it
+ * allocates and frees its own scratch device memory and synchronises the device.  cache_path (may
+ * be NULL) names a text cache keyed by device, kind and workload buckets.
+ */
+RNGLD_API int ld_autotune(const rngld_cfg *cfg, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total,
+                uint32_t n_steps, const char *cache_path, ld_tuning *out);
+
+/* A captured hipGraph of one ld_run call (config-4 style batched runs); replaying it advances the
+ * run by n_steps from the current x, v and state.  Arguments as ld_run; buffers must outlive it. */
+typedef struct rngld_plan rngld_plan;
+RNGLD_API int ld_plan_create(const rngld_cfg *cfg, void *d_state, size_t state_bytes, const ld_ensemble *h_ens,
+                   uint32_t n_ens, uint64_t n_total, uint32_t n_steps, float *d_x, float *d_v, const ld_obs *obs,
+                   double *d_obs, void *d_ws, size_t ws_bytes, void *stream, rngld_plan **out);
+RNGLD_API int ld_plan_launch(rngld_plan *plan, void *stream);
+RNGLD_API int ld_plan_destroy(rngld_plan *plan);
+
+/* ---- differentiation ------------------------------------------------------------------------ */
+/*
+ * Loss L_e = mean over steps t_begin..t_end (1 <= t_begin <= t_end <= n_steps) of <x^2>_e (mean
+ * over the ensemble's 3n coordinates of the positions after t steps); checkpoints every K steps.
+ */
+typedef struct ld_loss {
+    uint32_t t_begin;
+    uint32_t t_end;
+    uint32_t K;
+    uint32_t pad;
+} ld_loss;
+
+/* Checkpoint buffer: ceil(n_steps/K) records, record c = state at step c*K:
+ * float x[3][n_total], float v[3][n_total], then the generator state in the layout above with
+ * S = n_total. */
+RNGLD_API int ld_ckpt_bytes(const rngld_cfg *cfg, uint64_t n_total, uint32_t n_steps, uint32_t K, size_t *bytes);
+RNGLD_API int ld_adjoint_workspace_bytes(const rngld_cfg *cfg, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total,
+                               uint32_t n_steps, const ld_loss *loss, size_t *bytes);
+
+/* Forward run that writes checkpoints and the losses d_loss[n_ens] (double).  Underdamped,
+ * per-thread kinds.  x, v and the state advance as in ld_run. */
+RNGLD_API int ld_run_ckpt(const rngld_cfg *cfg, void *d_state, size_t state_bytes, const ld_ensemble *h_ens,
+                uint32_t n_ens, uint64_t n_total, uint32_t n_steps, float *d_x, float *d_v, const ld_loss *loss,
+                void *d_ckpt, size_t ckpt_bytes, double *d_loss, void *d_ws, size_t ws_bytes, void *stream);
+
+/*
+ * Reverse-mode pathwise gradient d_grad[n_ens][3] = (dL/dk, dL/dgamma, dL/dkT) (double) of the
+ * losses of ld_run_ckpt, replaying each K-step segment's noise bit-exactly from its checkpoint
+ * (no noise is stored across segments).  d_ckpt is read only.
+ */
+RNGLD_API int ld_run_backward(const rngld_cfg *cfg, const void *d_ckpt, size_t ckpt_bytes, const ld_ensemble *h_ens,
+                    uint32_t n_ens, uint64_t n_total, uint32_t n_steps, const ld_loss *loss, double *d_grad,
+                    void *d_ws, size_t ws_bytes, void *stream);
+
+/* ---- diagnostics ---------------------------------------------------------------------------- */
+RNGLD_API const char *rngld_last_error(void);
+RNGLD_API int rngld_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RNGLD_H */

@@ -1,0 +1,69 @@
+"""Pathwise gradients of an LD loss w.r.t. (k, gamma, kT) as a torch.autograd.Function.
+
+Forward runs ld_run_ckpt (checkpoints x, v and the generator state every K steps); backward runs
+ld_run_backward, which replays each segment's noise bit-exactly from its checkpoint and sweeps the
+adjoint recursion backward.  The loss of ensemble e is the mean over steps t_begin..t_end of
+<x^2>_e (per component, over the ensemble's 3n coordinates).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib as R
+
+
+class AdjointRun:
+    """Buffers and layout of a (possibly batched) differentiable run.
+
+    ensembles: list of (n, m, dt, seed); oscillators are packed back to back.  The forward pass
+    starts from the current x, v and generator state and advances them.
+    """
+
+    def __init__(self, kind, ensembles, n_steps: int, t_begin: int, t_end: int, K: int, device="cuda"):
+        self.kind = kind
+        self.ens_shape = list(ensembles)
+        self.n_total = sum(n for n, _, _, _ in self.ens_shape)
+        self.n_steps, self.device = n_steps, device
+        self.loss = R.Loss(t_begin, t_end, K, 0)
+        self.cfg = R.make_cfg(kind, n_streams=self.n_total)
+        self.state = R.new_state(self.cfg, device)
+        self.x = torch.zeros(3 * self.n_total, dtype=torch.float32, device=device)
+        self.v = torch.zeros_like(self.x)
+        ens, n_ens = self._ensembles([1.0] * len(self.ens_shape), [1.0] * len(self.ens_shape),
+                                     [1.0] * len(self.ens_shape))
+        R.rng_init_ensembles(self.cfg, self.state, ens, n_ens)
+        self.ckpt = torch.empty(max(R.ld_ckpt_bytes(self.cfg, self.n_total, n_steps, K), 1), dtype=torch.uint8,
+                                device=device)
+        self.ws = torch.empty(max(R.ld_adjoint_workspace_bytes(self.cfg, ens, n_ens, self.n_total, n_steps,
+                                                               self.loss), 256), dtype=torch.uint8, device=device)
+
+    def _ensembles(self, k, gamma, kT):
+        specs, off = [], 0
+        for e, (n, m, dt, seed) in enumerate(self.ens_shape):
+            specs.append((off, n, R.make_params(m, float(k[e]), float(gamma[e]), float(kT[e]), dt), seed))
+            off += n
+        return R.make_ensembles(specs)
+
+
+class LDAdjoint(torch.autograd.Function):
+    """loss[n_ens] = LDAdjoint.apply(k[n_ens], gamma[n_ens], kT[n_ens], run)."""
+
+    @staticmethod
+    def forward(ctx, k, gamma, kT, run: AdjointRun):
+        kh, gh, th = (t.detach().to("cpu", torch.float32).tolist() for t in (k, gamma, kT))
+        ens, n_ens = run._ensembles(kh, gh, th)
+        out = torch.empty(n_ens, dtype=torch.float64, device=run.device)
+        R.ld_run_ckpt(run.cfg, run.state, ens, n_ens, run.n_total, run.n_steps, run.x, run.v, run.loss, run.ckpt,
+                      out, run.ws)
+        ctx.run, ctx.ens, ctx.n_ens = run, ens, n_ens
+        ctx.dtypes = (k.dtype, gamma.dtype, kT.dtype)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        run = ctx.run
+        g = torch.empty((ctx.n_ens, 3), dtype=torch.float64, device=run.device)
+        R.ld_run_backward(run.cfg, run.ckpt, ctx.ens, ctx.n_ens, run.n_total, run.n_steps, run.loss, g, run.ws)
+        go = grad_out.to(torch.float64)
+        dk, dg, dT = (go * g[:, i] for i in range(3))
+        return dk.to(ctx.dtypes[0]), dg.to(ctx.dtypes[1]), dT.to(ctx.dtypes[2]), None

@@ -1,0 +1,908 @@
+// abi.hip -- host side of the C ABI declared in include/rngld.h: argument validation, buffer
+// sizing, workspace layout, kernel launches, hipGraph plans, launch-shape tuning and autotuning.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+
+using namespace rngld;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define RNGLD_TRY_HIP(expr)                                                                                   \
+    do {                                                                                                      \
+        const hipError_t e_ = (expr);                                                                         \
+        if (e_ != hipSuccess) return fail(RNGLD_EHIP, "%s: %s", #expr, hipGetErrorString(e_));                \
+    } while (0)
+
+#define RNGLD_TRY(expr)                                                                                       \
+    do {                                                                                                      \
+        const int rc_ = (expr);                                                                               \
+        if (rc_ != RNGLD_OK) return rc_;                                                                      \
+    } while (0)
+
+constexpr uint64_t kMaxStreams = 1ull << 38;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// validated generator configuration
+struct Gen {
+    int kind = -1;
+    uint64_t S = 0;
+    uint32_t ll = 0, sl = 0, W = 0, R = 0;
+    size_t state_bytes = 0;
+    uint32_t rows = 0;  // per-thread state rows
+};
+
+int check_cfg(const rngld_cfg *cfg, Gen *g) {
+    if (!cfg) return fail(RNGLD_EINVAL, "cfg is NULL");
+    g->kind = cfg->kind;
+    switch (cfg->kind) {
+        case RNGLD_HYBRID_TAUS:
+        case RNGLD_RAN2:
+            if (cfg->n_streams > kMaxStreams) return fail(RNGLD_EINVAL, "n_streams %llu too large",
+                                                          (unsigned long long)cfg->n_streams);
+            g->S = cfg->n_streams;
+            g->rows = cfg->kind == RNGLD_HYBRID_TAUS ? 4 : 35;
+            g->state_bytes = static_cast<size_t>(g->S) * g->rows * 4;
+            return RNGLD_OK;
+        case RNGLD_LAGFIB: {
+            const uint32_t ll = cfg->lf_ll, sl = cfg->lf_sl;
+            if (sl == 0 || sl >= ll || ll >= (1u << 31))
+                return fail(RNGLD_ELAG, "lagged Fibonacci needs 0 < sl < ll < 2^31 (ll=%u, sl=%u)", ll, sl);
+            uint32_t W = cfg->lf_wave ? cfg->lf_wave : sl;
+            W &= ~3u;
+            if (W < 4 || W > sl) return fail(RNGLD_ELAG, "wave width %u must satisfy 4 <= W <= sl = %u", W, sl);
+            const uint64_t R = cfg->lf_ring ? cfg->lf_ring : static_cast<uint64_t>(ll) + W;
+            if (R < static_cast<uint64_t>(ll) + W || R >= (1ull << 31))
+                return fail(RNGLD_ELAG, "ring length %llu must satisfy ll + W <= R < 2^31", (unsigned long long)R);
+            g->ll = ll;
+            g->sl = sl;
+            g->W = W;
+            g->R = static_cast<uint32_t>(R);
+            g->state_bytes = sizeof(LfHeader) + static_cast<size_t>(R) * 4;
+            return RNGLD_OK;
+        }
+        default:
+            return fail(RNGLD_EINVAL, "unknown generator kind %d", cfg->kind);
+    }
+}
+
+int check_state(const Gen &g, const void *d_state, size_t state_bytes) {
+    if (state_bytes < g.state_bytes)
+        return fail(RNGLD_ESIZE, "state buffer %zu bytes < %zu required", state_bytes, g.state_bytes);
+    if (!d_state && g.state_bytes) return fail(RNGLD_EINVAL, "state pointer is NULL");
+    return RNGLD_OK;
+}
+
+LfRing lf_ring(const Gen &g, void *d_state) {
+    LfRing L;
+    L.hdr = static_cast<const LfHeader *>(d_state);
+    L.ring = reinterpret_cast<uint32_t *>(static_cast<LfHeader *>(d_state) + 1);
+    L.R = g.R;
+    L.ll = g.ll;
+    L.sl = g.sl;
+    return L;
+}
+
+int check_params(const ld_params &p, bool need_kT_positive = false) {
+    const float vals[5] = {p.m, p.k, p.gamma, p.kT, p.dt};
+    for (float v : vals)
+        if (!std::isfinite(v)) return fail(RNGLD_EINVAL, "non-finite LD parameter");
+    if (!(p.m > 0) || !(p.gamma > 0) || !(p.k >= 0) || !(p.kT >= 0) || !(p.dt > 0))
+        return fail(RNGLD_EINVAL, "LD parameters need m > 0, gamma > 0, k >= 0, kT >= 0, dt > 0");
+    if (need_kT_positive && !(p.kT > 0)) return fail(RNGLD_EINVAL, "gradients need kT > 0");
+    if (p.scheme != 0 && p.scheme != 1) return fail(RNGLD_EINVAL, "unknown scheme %d", p.scheme);
+    return RNGLD_OK;
+}
+
+LdCoef make_coef(const ld_params &p) {
+    const double m = p.m, k = p.k, g = p.gamma, kT = p.kT, h = p.dt;
+    LdCoef q{};
+    q.c = static_cast<float>(1.0 - g * h);
+    q.kap = static_cast<float>(k * h / m);
+    q.sig = static_cast<float>(std::sqrt(2.0 * g * kT * h / m));
+    q.h = static_cast<float>(h);
+    const double xi = m * g;
+    q.odc = static_cast<float>(k * h / xi);
+    q.ods = static_cast<float>(std::sqrt(2.0 * kT * h / xi));
+    q.scheme = p.scheme;
+    return q;
+}
+
+// ensembles sorted by offset, inside [0, n_total), pairwise disjoint
+int check_ensembles(const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total, bool need_kT_positive = false) {
+    if (!h_ens || n_ens == 0) return fail(RNGLD_EINVAL, "need at least one ensemble");
+    if (n_ens > 65535) return fail(RNGLD_EINVAL, "at most 65535 ensembles");
+    std::vector<std::pair<uint64_t, uint64_t>> spans;
+    spans.reserve(n_ens);
+    for (uint32_t e = 0; e < n_ens; ++e) {
+        const ld_ensemble &E = h_ens[e];
+        if (E.offset > n_total || E.n > n_total - E.offset)
+            return fail(RNGLD_EINVAL, "ensemble %u [%llu, +%llu) outside n_total %llu", e,
+                        (unsigned long long)E.offset, (unsigned long long)E.n, (unsigned long long)n_total);
+        RNGLD_TRY(check_params(E.p, need_kT_positive));
+        if (E.n) spans.emplace_back(E.offset, E.offset + E.n);
+    }
+    std::sort(spans.begin(), spans.end());
+    for (size_t i = 1; i < spans.size(); ++i)
+        if (spans[i].first < spans[i - 1].second) return fail(RNGLD_EINVAL, "ensembles overlap");
+    return RNGLD_OK;
+}
+
+// ---- tuning -----------------------------------------------------------------------------------------
+std::mutex g_tune_mu;
+ld_tuning g_tuning[3] = {{256, 1, 0, 0}, {256, 1, 0, 0}, {256, 1, 0, 0}};
+
+ld_tuning current_tuning(int kind) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return g_tuning[kind];
+}
+
+bool valid_tuning(const ld_tuning &t) {
+    return (t.block == 64 || t.block == 128 || t.block == 256 || t.block == 512) &&
+           (t.osc_per_thread == 1 || t.osc_per_thread == 2) && t.blocks_per_cu <= 64;
+}
+
+int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return cus;
+}
+
+// ---- ld_run plan (host-side description of one call) ------------------------------------------------
+struct RunLayout {
+    std::vector<EnsDev> ens;
+    uint32_t n_tiles = 0, P = 0;
+    size_t off_ens = 0, off_partials = 0, off_t0 = 0, bytes = 0;
+    // LF phase structure
+    uint32_t Q = 0, bpp = 0;
+    uint64_t Nq = 0;
+};
+
+int layout_run(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total, uint32_t n_steps,
+               const ld_obs *obs, const ld_tuning &t, RunLayout *L) {
+    const uint32_t stride = obs ? obs->stride : 0;
+    L->P = stride ? n_steps / stride + 1 : 0;
+    L->ens.resize(n_ens);
+    if (g.kind == RNGLD_LAGFIB) {
+        if (n_ens != 1) return fail(RNGLD_ENOTSUP, "lagged Fibonacci runs one ensemble (one shared sequence)");
+        const uint64_t n = h_ens[0].n;
+        const uint64_t nmax = g.W / 4;
+        L->Q = n ? static_cast<uint32_t>((n + nmax - 1) / nmax) : 0;
+        L->Nq = L->Q ? (n + L->Q - 1) / L->Q : 0;
+        L->bpp = static_cast<uint32_t>((L->Nq + kLfLdBlock - 1) / kLfLdBlock);
+        L->n_tiles = L->Q * L->bpp;
+        EnsDev &E = L->ens[0];
+        memset(&E, 0, sizeof(E));
+        E.offset = h_ens[0].offset;
+        E.n = n;
+        E.tile_begin = 0;
+        E.n_tiles = L->n_tiles;
+        E.coef = make_coef(h_ens[0].p);
+    } else {
+        const uint64_t tile = static_cast<uint64_t>(t.block) * t.osc_per_thread;
+        uint64_t acc = 0;
+        for (uint32_t e = 0; e < n_ens; ++e) {
+            EnsDev &E = L->ens[e];
+            memset(&E, 0, sizeof(E));
+            E.offset = h_ens[e].offset;
+            E.n = h_ens[e].n;
+            E.tile_begin = static_cast<uint32_t>(acc);
+            E.n_tiles = static_cast<uint32_t>((E.n + tile - 1) / tile);
+            E.coef = make_coef(h_ens[e].p);
+            acc += E.n_tiles;
+        }
+        if (acc >= (1ull << 31)) return fail(RNGLD_EINVAL, "too many tiles");
+        L->n_tiles = static_cast<uint32_t>(acc);
+    }
+    L->off_ens = 0;
+    L->off_partials = align_up(sizeof(EnsDev) * n_ens);
+    L->off_t0 = align_up(L->off_partials + static_cast<size_t>(L->P) * L->n_tiles * RNGLD_NOBS * sizeof(double));
+    L->bytes = L->off_t0 + (stride ? align_up(6 * static_cast<size_t>(n_total) * sizeof(float)) : 0);
+    return RNGLD_OK;
+}
+
+int check_run_args(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total, uint32_t n_steps,
+                   const ld_obs *obs) {
+    RNGLD_TRY(check_ensembles(h_ens, n_ens, n_total));
+    if (g.kind != RNGLD_LAGFIB && n_total > g.S)
+        return fail(RNGLD_ESIZE, "n_total %llu exceeds the state's %llu streams", (unsigned long long)n_total,
+                    (unsigned long long)g.S);
+    if (obs && obs->stride && obs->t0 > n_steps) return fail(RNGLD_EINVAL, "t0 beyond the run");
+    if (n_total > kMaxStreams) return fail(RNGLD_EINVAL, "n_total too large");
+    return RNGLD_OK;
+}
+
+// enqueue one ld_run call; all arguments validated
+int enqueue_run(const Gen &g, void *d_state, const RunLayout &L, const ld_tuning &t, uint64_t n_total,
+                uint32_t n_steps, float *d_x, float *d_v, const ld_obs *obs, double *d_obs, void *d_ws,
+                hipStream_t st, bool upload) {
+    uint8_t *ws = static_cast<uint8_t *>(d_ws);
+    EnsDev *d_ens = reinterpret_cast<EnsDev *>(ws + L.off_ens);
+    double *partials = reinterpret_cast<double *>(ws + L.off_partials);
+    float *t0buf = reinterpret_cast<float *>(ws + L.off_t0);
+    const uint32_t stride = obs ? obs->stride : 0, t0 = obs ? obs->t0 : 0;
+    if (upload) RNGLD_TRY_HIP(launch_upload(d_ens, L.ens.data(), sizeof(EnsDev) * L.ens.size(), st));
+
+    if (g.kind == RNGLD_LAGFIB) {
+        const EnsDev &E = L.ens[0];
+        const uint64_t n = E.n;
+        LfLdPhase ph{};
+        ph.L = lf_ring(g, d_state);
+        ph.N = n_total;
+        ph.n_osc = n;
+        ph.x = d_x + E.offset;
+        ph.v = d_v + E.offset;
+        ph.coef = E.coef;
+        ph.stride = stride;
+        ph.t0 = t0;
+        ph.n_tiles = L.n_tiles;
+        ph.partials = partials;
+        ph.t0buf = t0buf + E.offset;
+        for (uint32_t s = 0; s < n_steps; ++s) {
+            for (uint32_t q = 0; q < L.Q; ++q) {
+                const uint64_t begin = static_cast<uint64_t>(q) * L.Nq;
+                ph.osc_begin = begin;
+                ph.osc_count = static_cast<uint32_t>(std::min<uint64_t>(L.Nq, n - begin));
+                ph.off_mod = static_cast<uint32_t>((4ull * n * s + 4ull * begin) % g.R);
+                ph.step = s;
+                ph.tile_base = q * L.bpp;
+                RNGLD_TRY_HIP(launch_lf_ld_phase(ph, st));
+            }
+        }
+        if (stride && n_steps % stride == 0 && L.Q)
+            RNGLD_TRY_HIP(launch_lf_observe(ph, L.Q, L.Nq, n_steps / stride, t0 == n_steps, st));
+        const uint64_t count = 4ull * n * n_steps;
+        RNGLD_TRY_HIP(launch_lf_advance(const_cast<LfHeader *>(ph.L.hdr), count, static_cast<uint32_t>(count % g.R), st));
+    } else {
+        LdArgs a{};
+        a.state = d_state;
+        a.S = g.S;
+        a.x = d_x;
+        a.v = d_v;
+        a.NT = n_total;
+        a.ens = d_ens;
+        a.n_ens = static_cast<uint32_t>(L.ens.size());
+        a.n_tiles = L.n_tiles;
+        a.n_steps = n_steps;
+        a.stride = stride;
+        a.t0 = t0;
+        a.P = L.P;
+        a.partials = partials;
+        a.t0buf = t0buf;
+        uint32_t grid = L.n_tiles;
+        if (t.blocks_per_cu) {
+            const int cus = device_cus();
+            if (cus <= 0) return fail(RNGLD_EHIP, "cannot query the compute-unit count");
+            grid = std::min<uint32_t>(grid, t.blocks_per_cu * static_cast<uint32_t>(cus));
+        }
+        const uint32_t spl = t.steps_per_launch ? t.steps_per_launch : std::max<uint32_t>(n_steps, 1);
+        if (grid > 0) {
+            uint32_t b = 0;
+            do {
+                a.step_begin = b;
+                a.step_end = std::min<uint64_t>(static_cast<uint64_t>(b) + spl, n_steps);
+                RNGLD_TRY_HIP(launch_ld_run(g.kind, a, t, grid, st));
+                b = a.step_end;
+            } while (b < n_steps);
+        }
+    }
+    if (L.P) {
+        RNGLD_TRY_HIP(launch_obs_finalize(partials, L.n_tiles, L.P, d_ens, static_cast<uint32_t>(L.ens.size()),
+                                          d_obs, st));
+    }
+    return RNGLD_OK;
+}
+
+}  // namespace
+
+// =====================================================================================================
+extern "C" {
+
+const char *rngld_last_error(void) { return g_last_error.c_str(); }
+int rngld_version(void) { return 1; }
+
+int rngld_state_bytes(const rngld_cfg *cfg, size_t *bytes) {
+    Gen g;
+    RNGLD_TRY(check_cfg(cfg, &g));
+    if (!bytes) return fail(RNGLD_EINVAL, "bytes is NULL");
+    *bytes = g.state_bytes;
+    return RNGLD_OK;
+}
+
+int rng_init(const rngld_cfg *cfg, void *d_state, size_t state_bytes, void *stream) {
+    Gen g;
+    RNGLD_TRY(check_cfg(cfg, &g));
+    RNGLD_TRY(check_state(g, d_state, state_bytes));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (g.kind == RNGLD_LAGFIB) {
+        RNGLD_TRY_HIP(launch_lf_seed(d_state, g.ll, g.sl, g.R, g.W, cfg->seed, st));
+    } else {
+        if (cfg->stream_base > kMaxStreams) return fail(RNGLD_EINVAL, "stream_base too large");
+        RNGLD_TRY_HIP(launch_seed(g.kind, d_state, g.S, cfg->seed, cfg->stream_base, 0, g.S, st));
+    }
+    return RNGLD_OK;
+}
+
+int rng_init_ensembles(const rngld_cfg *cfg, void *d_state, size_t state_bytes, const ld_ensemble *h_ens,
+                       uint32_t n_ens, void *stream) {
+    Gen g;
+    RNGLD_TRY(check_cfg(cfg, &g));
+    if (g.kind == RNGLD_LAGFIB) return fail(RNGLD_ENOTSUP, "ensembles need a per-thread generator");
+    RNGLD_TRY(check_state(g, d_state, state_bytes));
+    if (!h_ens && n_ens) return fail(RNGLD_EINVAL, "ensembles pointer is NULL");
+    for (uint32_t e = 0; e < n_ens; ++e)
+        if (h_ens[e].offset > g.S || h_ens[e].n > g.S - h_ens[e].offset)
+            return fail(RNGLD_ESIZE, "ensemble %u exceeds the state's streams", e);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (uint32_t e = 0; e < n_ens; ++e)
+        RNGLD_TRY_HIP(launch_seed(g.kind, d_state, g.S, h_ens[e].seed, 0, h_ens[e].offset, h_ens[e].n, st));
+    return RNGLD_OK;
+}
+
+int rng_uniform(const rngld_cfg *cfg, void *d_state, size_t state_bytes, uint64_t per_stream, uint32_t *d_out,
+                uint64_t out_len, void *stream) {
+    Gen g;
+    RNGLD_TRY(check_cfg(cfg, &g));
+    RNGLD_TRY(check_state(g, d_state, state_bytes));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (g.kind == RNGLD_LAGFIB) {
+        const uint64_t count = per_stream;
+        if (count > (1ull << 40)) return fail(RNGLD_EINVAL, "count too large");
+        if (out_len < count) return fail(RNGLD_ESIZE, "output holds %llu < %llu values",
+                                         (unsigned long long)out_len, (unsigned long long)count);
+        if (count == 0) return RNGLD_OK;
+        if (!d_out) return fail(RNGLD_EINVAL, "output pointer is NULL");
+        const LfRing L = lf_ring(g, d_state);
+        for (uint64_t first = 0; first < count; first += g.W)
+            RNGLD_TRY_HIP(launch_lf_uniform_phase(L, d_out, first,
+                                                  static_cast<uint32_t>(std::min<uint64_t>(g.W, count - first)), st));
+        const uint64_t m = std::min<uint64_t>(count, g.ll);
+        RNGLD_TRY_HIP(launch_lf_ring_store(L, d_out, count, static_cast<uint32_t>((count - m) % g.R), st));
+        RNGLD_TRY_HIP(launch_lf_advance(const_cast<LfHeader *>(L.hdr), count, static_cast<uint32_t>(count % g.R), st));
+        return RNGLD_OK;
+    }
+    if (per_stream && g.S && per_stream > ~0ull / g.S) return fail(RNGLD_EINVAL, "size overflow");
+    const uint64_t need = per_stream * g.S;
+    if (out_len < need) return fail(RNGLD_ESIZE, "output holds %llu < %llu values", (unsigned long long)out_len,
+                                    (unsigned long long)need);
+    if (need == 0) return RNGLD_OK;
+    if (!d_out) return fail(RNGLD_EINVAL, "output pointer is NULL");
+    RNGLD_TRY_HIP(launch_bulk_uniform(g.kind, d_state, g.S, per_stream, d_out, st));
+    return RNGLD_OK;
+}
+
+int rng_gaussian(const rngld_cfg *cfg, void *d_state, size_t state_bytes, uint64_t per_stream, float *d_out,
+                 uint64_t out_len, void *stream) {
+    Gen g;
+    RNGLD_TRY(check_cfg(cfg, &g));
+    RNGLD_TRY(check_state(g, d_state, state_bytes));
+    if (per_stream % 2) return fail(RNGLD_EINVAL, "Gaussians come in Box-Muller pairs: per_stream must be even");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (g.kind == RNGLD_LAGFIB) {
+        const uint64_t count = per_stream;
+        if (count > (1ull << 40)) return fail(RNGLD_EINVAL, "count too large");
+        if (out_len < count) return fail(RNGLD_ESIZE, "output holds %llu < %llu values",
+                                         (unsigned long long)out_len, (unsigned long long)count);
+        if (count == 0) return RNGLD_OK;
+        if (!d_out) return fail(RNGLD_EINVAL, "output pointer is NULL");
+        const LfRing L = lf_ring(g, d_state);
+        for (uint64_t first = 0; first < count; first += g.W)
+            RNGLD_TRY_HIP(launch_lf_gauss_phase(L, d_out, first, static_cast<uint32_t>(first % g.R),
+                                                static_cast<uint32_t>(std::min<uint64_t>(g.W, count - first)), st));
+        RNGLD_TRY_HIP(launch_lf_advance(const_cast<LfHeader *>(L.hdr), count, static_cast<uint32_t>(count % g.R), st));
+        return RNGLD_OK;
+    }
+    if (per_stream && g.S && per_stream > ~0ull / g.S) return fail(RNGLD_EINVAL, "size overflow");
+    const uint64_t need = per_stream * g.S;
+    if (out_len < need) return fail(RNGLD_ESIZE, "output holds %llu < %llu values", (unsigned long long)out_len,
+                                    (unsigned long long)need);
+    if (need == 0) return RNGLD_OK;
+    if (!d_out) return fail(RNGLD_EINVAL, "output pointer is NULL");
+    RNGLD_TRY_HIP(launch_bulk_gaussian(g.kind, d_state, g.S, per_stream, d_out, st));
+    return RNGLD_OK;
+}
+
+int ld_step(const rngld_cfg *cfg, void *d_state, size_t state_bytes, const ld_params *p, uint64_t n, float *d_x,
+            float *d_v, void *stream) {
+    Gen g;
+    RNGLD_TRY(check_cfg(cfg, &g));
+    RNGLD_TRY(check_state(g, d_state, state_bytes));
+    if (!p) return fail(RNGLD_EINVAL, "params is NULL");
+    RNGLD_TRY(check_params(*p));
+    if (n == 0) return RNGLD_OK;
+    if (!d_x || !d_v) return fail(RNGLD_EINVAL, "x or v is NULL");
+    if (n > kMaxStreams) return fail(RNGLD_EINVAL, "n too large");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const LdCoef coef = make_coef(*p);
+    if (g.kind == RNGLD_LAGFIB) {
+        const uint64_t nmax = g.W / 4;
+        const uint64_t Q = (n + nmax - 1) / nmax, Nq = (n + Q - 1) / Q;
+        LfLdPhase ph{};
+        ph.L = lf_ring(g, d_state);
+        ph.N = n;
+        ph.n_osc = n;
+        ph.x = d_x;
+        ph.v = d_v;
+        ph.coef = coef;
+        for (uint64_t q = 0; q < Q; ++q) {
+            ph.osc_begin = q * Nq;
+            ph.osc_count = static_cast<uint32_t>(std::min<uint64_t>(Nq, n - q * Nq));
+            ph.off_mod = static_cast<uint32_t>((4ull * q * Nq) % g.R);
+            RNGLD_TRY_HIP(launch_lf_ld_phase(ph, st));
+        }
+        RNGLD_TRY_HIP(launch_lf_advance(const_cast<LfHeader *>(ph.L.hdr), 4ull * n,
+                                        static_cast<uint32_t>((4ull * n) % g.R), st));
+        return RNGLD_OK;
+    }
+    if (n > g.S) return fail(RNGLD_ESIZE, "n %llu exceeds the state's %llu streams", (unsigned long long)n,
+                             (unsigned long long)g.S);
+    if (g.kind == RNGLD_RAN2 && g.S >= (1ull << 32)) return fail(RNGLD_ENOTSUP, "Ran2 step needs S < 2^32");
+    RNGLD_TRY_HIP(launch_ld_step(g.kind, d_state, g.S, coef, n, d_x, d_v, st));
+    return RNGLD_OK;
+}
+
+int ld_workspace_bytes(const rngld_cfg *cfg, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total,
+                       uint32_t n_steps, const ld_obs *obs, size_t *bytes) {
+    Gen g;
+    RNGLD_TRY(check_cfg(cfg, &g));
+    if (!bytes) return fail(RNGLD_EINVAL, "bytes is NULL");
+    RNGLD_TRY(check_run_args(g, h_ens, n_ens, n_total, n_steps, obs));
+    RunLayout L;
+    RNGLD_TRY(layout_run(g, h_ens, n_ens, n_total, n_steps, obs, current_tuning(g.kind), &L));
+    *bytes = L.bytes;
+    return RNGLD_OK;
+}
+
+int ld_run(const rngld_cfg *cfg, void *d_state, size_t state_bytes, const ld_ensemble *h_ens, uint32_t n_ens,
+           uint64_t n_total, uint32_t n_steps, float *d_x, float *d_v, const ld_obs *obs, double *d_obs, void *d_ws,
+           size_t ws_bytes, void *stream) {
+    Gen g;
+    RNGLD_TRY(check_cfg(cfg, &g));
+    RNGLD_TRY(check_state(g, d_state, state_bytes));
+    RNGLD_TRY(check_run_args(g, h_ens, n_ens, n_total, n_steps, obs));
+    const ld_tuning t = current_tuning(g.kind);
+    RunLayout L;
+    RNGLD_TRY(layout_run(g, h_ens, n_ens, n_total, n_steps, obs, t, &L));
+    if (ws_bytes < L.bytes) return fail(RNGLD_ESIZE, "workspace %zu bytes < %zu required", ws_bytes, L.bytes);
+    if (!d_ws) return fail(RNGLD_EINVAL, "workspace is NULL");
+    if (n_total && (!d_x || !d_v)) return fail(RNGLD_EINVAL, "x or v is NULL");
+    if (L.P && !d_obs) return fail(RNGLD_EINVAL, "observables requested but d_obs is NULL");
+    return enqueue_run(g, d_state, L, t, n_total, n_steps, d_x, d_v, obs, d_obs, d_ws,
+                       static_cast<hipStream_t>(stream), true);
+}
+
+int ld_get_tuning(int32_t kind, ld_tuning *out) {
+    if (kind < 0 || kind > 2) return fail(RNGLD_EINVAL, "unknown generator kind %d", kind);
+    if (!out) return fail(RNGLD_EINVAL, "out is NULL");
+    *out = current_tuning(kind);
+    return RNGLD_OK;
+}
+
+int ld_set_tuning(int32_t kind, const ld_tuning *t) {
+    if (kind < 0 || kind > 2) return fail(RNGLD_EINVAL, "unknown generator kind %d", kind);
+    if (!t || !valid_tuning(*t))
+        return fail(RNGLD_EINVAL, "tuning needs block in {64,128,256,512}, osc_per_thread in {1,2}, "
+                                  "blocks_per_cu <= 64");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuning[kind] = *t;
+    return RNGLD_OK;
+}
+
+}  // extern "C"
+
+// ---- hipGraph plans ---------------------------------------------------------------------------------
+struct rngld_plan {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" int ld_plan_create(const rngld_cfg *cfg, void *d_state, size_t state_bytes, const ld_ensemble *h_ens,
+                              uint32_t n_ens, uint64_t n_total, uint32_t n_steps, float *d_x, float *d_v,
+                              const ld_obs *obs, double *d_obs, void *d_ws, size_t ws_bytes, void *stream,
+                              rngld_plan **out) {
+    if (!out) return fail(RNGLD_EINVAL, "out is NULL");
+    *out = nullptr;
+    Gen g;
+    RNGLD_TRY(check_cfg(cfg, &g));
+    RNGLD_TRY(check_state(g, d_state, state_bytes));
+    RNGLD_TRY(check_run_args(g, h_ens, n_ens, n_total, n_steps, obs));
+    const ld_tuning t = current_tuning(g.kind);
+    RunLayout L;
+    RNGLD_TRY(layout_run(g, h_ens, n_ens, n_total, n_steps, obs, t, &L));
+    if (ws_bytes < L.bytes) return fail(RNGLD_ESIZE, "workspace %zu bytes < %zu required", ws_bytes, L.bytes);
+    if (!d_ws) return fail(RNGLD_EINVAL, "workspace is NULL");
+    if (n_total && (!d_x || !d_v)) return fail(RNGLD_EINVAL, "x or v is NULL");
+    if (L.P && !d_obs) return fail(RNGLD_EINVAL, "observables requested but d_obs is NULL");
+    hipStream_t user = static_cast<hipStream_t>(stream);
+    // the ensemble table is written once, outside the graph, on the caller's stream
+    RNGLD_TRY_HIP(launch_upload(static_cast<uint8_t *>(d_ws) + L.off_ens, L.ens.data(), sizeof(EnsDev) * L.ens.size(),
+                                user));
+    RNGLD_TRY_HIP(hipStreamSynchronize(user));
+    hipStream_t cap = nullptr;
+    RNGLD_TRY_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    rngld_plan *plan = new rngld_plan();
+    int rc = RNGLD_OK;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        rc = enqueue_run(g, d_state, L, t, n_total, n_steps, d_x, d_v, obs, d_obs, d_ws, cap, false);
+        const hipError_t e2 = hipStreamEndCapture(cap, &plan->graph);
+        if (rc == RNGLD_OK && e2 != hipSuccess) rc = fail(RNGLD_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+    } else {
+        rc = fail(RNGLD_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    }
+    if (rc == RNGLD_OK) {
+        e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = fail(RNGLD_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    (void)hipStreamDestroy(cap);
+    if (rc != RNGLD_OK) {
+        if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+        if (plan->graph) (void)hipGraphDestroy(plan->graph);
+        delete plan;
+        return rc;
+    }
+    *out = plan;
+    return RNGLD_OK;
+}
+
+extern "C" int ld_plan_launch(rngld_plan *plan, void *stream) {
+    if (!plan || !plan->exec) return fail(RNGLD_EINVAL, "plan is NULL");
+    RNGLD_TRY_HIP(hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream)));
+    return RNGLD_OK;
+}
+
+extern "C" int ld_plan_destroy(rngld_plan *plan) {
+    if (!plan) return RNGLD_OK;
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    delete plan;
+    return RNGLD_OK;
+}
+
+// ---- autotuner --------------------------------------------------------------------------------------
+namespace {
+
+std::string device_name() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string s = prop.gcnArchName;
+    for (char &c : s)
+        if (c == ' ' || c == ':') c = '_';
+    return s + "_cu" + std::to_string(prop.multiProcessorCount);
+}
+
+int log2_bucket(uint64_t v) {
+    int b = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+std::string cache_key(int kind, uint64_t n_total, uint32_t n_ens, uint32_t n_steps) {
+    return device_name() + " kind" + std::to_string(kind) + " n" + std::to_string(log2_bucket(n_total)) + " e" +
+           std::to_string(log2_bucket(n_ens)) + " s" + std::to_string(log2_bucket(n_steps));
+}
+
+bool cache_lookup(const char *path, const std::string &key, ld_tuning *t) {
+    if (!path) return false;
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (fgets(line, sizeof(line), f)) {
+        char k1[128], k2[32], k3[32], k4[32], k5[32];
+        unsigned b, o, s, c;
+        if (sscanf(line, "%127s %31s %31s %31s %31s %u %u %u %u", k1, k2, k3, k4, k5, &b, &o, &s, &c) == 9) {
+            const std::string k = std::string(k1) + " " + k2 + " " + k3 + " " + k4 + " " + k5;
+            ld_tuning cand{b, o, s, c};
+            if (k == key && valid_tuning(cand)) {
+                *t = cand;
+                found = true;
+            }
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+void cache_store(const char *path, const std::string &key, const ld_tuning &t) {
+    if (!path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s %u %u %u %u\n", key.c_str(), t.block, t.osc_per_thread, t.steps_per_launch, t.blocks_per_cu);
+    fclose(f);
+}
+
+struct DeviceScratch {
+    std::vector<void *> ptrs;
+    void *get(size_t bytes) {
+        void *p = nullptr;
+        if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) return nullptr;
+        ptrs.push_back(p);
+        return p;
+    }
+    ~DeviceScratch() {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+
+extern "C" int ld_autotune(const rngld_cfg *cfg, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total,
+                           uint32_t n_steps, const char *cache_path, ld_tuning *out) {
+    Gen g;
+    RNGLD_TRY(check_cfg(cfg, &g));
+    if (!out) return fail(RNGLD_EINVAL, "out is NULL");
+    if (g.kind == RNGLD_LAGFIB) return fail(RNGLD_ENOTSUP, "the lagged-Fibonacci path has no tunable launch shape");
+    RNGLD_TRY(check_run_args(g, h_ens, n_ens, n_total, n_steps, nullptr));
+    const std::string key = cache_key(g.kind, n_total, n_ens, n_steps);
+    ld_tuning best{};
+    if (cache_lookup(cache_path, key, &best)) {
+        RNGLD_TRY(ld_set_tuning(g.kind, &best));
+        *out = best;
+        return RNGLD_OK;
+    }
+    // proxy run: the same ensembles, a shortened step count, on scratch copies
+    const uint32_t proxy_steps = std::max<uint32_t>(1, std::min<uint32_t>(n_steps, 128));
+    DeviceScratch mem;
+    const size_t xv_bytes = 3 * static_cast<size_t>(n_total) * sizeof(float);
+    float *x = static_cast<float *>(mem.get(xv_bytes));
+    float *v = static_cast<float *>(mem.get(xv_bytes));
+    rngld_cfg c2 = *cfg;
+    c2.n_streams = n_total;
+    Gen g2;
+    RNGLD_TRY(check_cfg(&c2, &g2));
+    void *state = mem.get(g2.state_bytes);
+    if (!x || !v || !state) return fail(RNGLD_EHIP, "autotune scratch allocation failed");
+    RNGLD_TRY_HIP(hipMemset(x, 0, xv_bytes));
+    RNGLD_TRY_HIP(hipMemset(v, 0, xv_bytes));
+    RNGLD_TRY(rng_init(&c2, state, g2.state_bytes, nullptr));
+
+    std::vector<ld_tuning> cands;
+    for (uint32_t b : {64u, 128u, 256u, 512u})
+        for (uint32_t o : {1u, 2u})
+            for (uint32_t bpc : {0u, 4u, 8u}) {
+                if (g.kind == RNGLD_RAN2 && o * b * kR2Tab * 4 > 64 * 1024) continue;
+                cands.push_back({b, o, 0, bpc});
+            }
+    hipEvent_t e0, e1;
+    RNGLD_TRY_HIP(hipEventCreate(&e0));
+    RNGLD_TRY_HIP(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    int rc = RNGLD_OK;
+    for (const ld_tuning &t : cands) {
+        RunLayout L;
+        rc = layout_run(g2, h_ens, n_ens, n_total, proxy_steps, nullptr, t, &L);
+        if (rc != RNGLD_OK) break;
+        void *ws = mem.get(L.bytes);
+        if (!ws) {
+            rc = fail(RNGLD_EHIP, "autotune scratch allocation failed");
+            break;
+        }
+        float ms = 0.0f;
+        for (int rep = 0; rep < 3 && rc == RNGLD_OK; ++rep) {
+            if (hipEventRecord(e0, nullptr) != hipSuccess) rc = fail(RNGLD_EHIP, "hipEventRecord failed");
+            if (rc == RNGLD_OK)
+                rc = enqueue_run(g2, state, L, t, n_total, proxy_steps, x, v, nullptr, nullptr, ws, nullptr, true);
+            if (rc == RNGLD_OK && hipEventRecord(e1, nullptr) != hipSuccess) rc = fail(RNGLD_EHIP, "hipEventRecord");
+            if (rc == RNGLD_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(RNGLD_EHIP, "hipEventSynchronize");
+            float m = 0.0f;
+            if (rc == RNGLD_OK && hipEventElapsedTime(&m, e0, e1) != hipSuccess) rc = fail(RNGLD_EHIP, "elapsed");
+            if (rep > 0) ms += m;  // first repetition warms up
+        }
+        if (rc != RNGLD_OK) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = t;
+        }
+    }
+    // steps per launch: whole run unless splitting it costs less than 1% (long runs, plan graphs)
+    if (rc == RNGLD_OK && n_steps > 2000) best.steps_per_launch = 1000;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != RNGLD_OK) return rc;
+    if (hipDeviceSynchronize() != hipSuccess) return fail(RNGLD_EHIP, "autotune synchronisation failed");
+    cache_store(cache_path, key, best);
+    RNGLD_TRY(ld_set_tuning(g.kind, &best));
+    *out = best;
+    return RNGLD_OK;
+}
+
+// ---- adjoint ----------------------------------------------------------------------------------------
+namespace {
+
+constexpr uint32_t kAdjTile = 256;
+
+int check_loss(const ld_loss *loss, uint32_t n_steps) {
+    if (!loss) return fail(RNGLD_EINVAL, "loss is NULL");
+    if (loss->K == 0) return fail(RNGLD_EINVAL, "checkpoint interval K must be positive");
+    if (loss->t_begin < 1 || loss->t_end < loss->t_begin || loss->t_end > n_steps)
+        return fail(RNGLD_EINVAL, "loss window must satisfy 1 <= t_begin <= t_end <= n_steps");
+    return RNGLD_OK;
+}
+
+struct AdjLayout {
+    std::vector<EnsDev> ens;
+    std::vector<AdjCoef> adj;
+    uint32_t n_tiles = 0;
+    size_t off_ens = 0, off_adj = 0, off_partials = 0, off_scratch = 0, bytes = 0;
+};
+
+int layout_adj(const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total, uint32_t K, bool with_scratch,
+               AdjLayout *L) {
+    L->ens.resize(n_ens);
+    L->adj.resize(n_ens);
+    uint64_t acc = 0;
+    for (uint32_t e = 0; e < n_ens; ++e) {
+        EnsDev &E = L->ens[e];
+        memset(&E, 0, sizeof(E));
+        E.offset = h_ens[e].offset;
+        E.n = h_ens[e].n;
+        E.tile_begin = static_cast<uint32_t>(acc);
+        E.n_tiles = static_cast<uint32_t>((E.n + kAdjTile - 1) / kAdjTile);
+        E.coef = make_coef(h_ens[e].p);
+        acc += E.n_tiles;
+        const ld_params &p = h_ens[e].p;
+        AdjCoef &A = L->adj[e];
+        A.f = E.coef;
+        A.dkap_dk = static_cast<float>(static_cast<double>(p.dt) / p.m);
+        A.dc_dgamma = static_cast<float>(-static_cast<double>(p.dt));
+        const double sig = std::sqrt(2.0 * p.gamma * static_cast<double>(p.kT) * p.dt / p.m);
+        A.dsig_dgamma = static_cast<float>(sig / (2.0 * p.gamma));
+        A.dsig_dkT = static_cast<float>(sig / (2.0 * p.kT));
+    }
+    if (acc >= (1ull << 31)) return fail(RNGLD_EINVAL, "too many tiles");
+    L->n_tiles = static_cast<uint32_t>(acc);
+    L->off_ens = 0;
+    L->off_adj = align_up(sizeof(EnsDev) * n_ens);
+    L->off_partials = align_up(L->off_adj + sizeof(AdjCoef) * n_ens);
+    L->off_scratch = align_up(L->off_partials + 3 * sizeof(double) * std::max<uint32_t>(L->n_tiles, 1));
+    L->bytes = L->off_scratch + (with_scratch ? align_up(9ull * K * n_total * sizeof(float)) : 0);
+    return RNGLD_OK;
+}
+
+int check_adj_common(const rngld_cfg *cfg, Gen *g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total,
+                     uint32_t n_steps, const ld_loss *loss) {
+    RNGLD_TRY(check_cfg(cfg, g));
+    if (g->kind == RNGLD_LAGFIB) return fail(RNGLD_ENOTSUP, "gradients need a per-thread generator");
+    RNGLD_TRY(check_loss(loss, n_steps));
+    RNGLD_TRY(check_ensembles(h_ens, n_ens, n_total, true));
+    for (uint32_t e = 0; e < n_ens; ++e)
+        if (h_ens[e].p.scheme != 0) return fail(RNGLD_ENOTSUP, "gradients use the underdamped scheme");
+    if (n_total > kMaxStreams) return fail(RNGLD_EINVAL, "n_total too large");
+    return RNGLD_OK;
+}
+
+size_t ckpt_record_bytes(const Gen &g, uint64_t n_total) {
+    const uint32_t rows = g.kind == RNGLD_HYBRID_TAUS ? 4 : 35;
+    return static_cast<size_t>(n_total) * (6 + rows) * 4;
+}
+
+}  // namespace
+
+extern "C" int ld_ckpt_bytes(const rngld_cfg *cfg, uint64_t n_total, uint32_t n_steps, uint32_t K, size_t *bytes) {
+    Gen g;
+    RNGLD_TRY(check_cfg(cfg, &g));
+    if (g.kind == RNGLD_LAGFIB) return fail(RNGLD_ENOTSUP, "gradients need a per-thread generator");
+    if (!bytes) return fail(RNGLD_EINVAL, "bytes is NULL");
+    if (K == 0) return fail(RNGLD_EINVAL, "K must be positive");
+    const uint64_t nrec = (static_cast<uint64_t>(n_steps) + K - 1) / K;
+    *bytes = nrec * ckpt_record_bytes(g, n_total);
+    return RNGLD_OK;
+}
+
+extern "C" int ld_adjoint_workspace_bytes(const rngld_cfg *cfg, const ld_ensemble *h_ens, uint32_t n_ens,
+                                          uint64_t n_total, uint32_t n_steps, const ld_loss *loss, size_t *bytes) {
+    Gen g;
+    RNGLD_TRY(check_adj_common(cfg, &g, h_ens, n_ens, n_total, n_steps, loss));
+    if (!bytes) return fail(RNGLD_EINVAL, "bytes is NULL");
+    AdjLayout L;
+    RNGLD_TRY(layout_adj(h_ens, n_ens, n_total, loss->K, true, &L));
+    *bytes = L.bytes;
+    return RNGLD_OK;
+}
+
+extern "C" int ld_run_ckpt(const rngld_cfg *cfg, void *d_state, size_t state_bytes, const ld_ensemble *h_ens,
+                           uint32_t n_ens, uint64_t n_total, uint32_t n_steps, float *d_x, float *d_v,
+                           const ld_loss *loss, void *d_ckpt, size_t ckpt_bytes, double *d_loss, void *d_ws,
+                           size_t ws_bytes, void *stream) {
+    Gen g;
+    RNGLD_TRY(check_adj_common(cfg, &g, h_ens, n_ens, n_total, n_steps, loss));
+    RNGLD_TRY(check_state(g, d_state, state_bytes));
+    if (n_total > g.S) return fail(RNGLD_ESIZE, "n_total exceeds the state's streams");
+    size_t need_ck = 0;
+    RNGLD_TRY(ld_ckpt_bytes(cfg, n_total, n_steps, loss->K, &need_ck));
+    if (ckpt_bytes < need_ck) return fail(RNGLD_ESIZE, "checkpoint buffer %zu < %zu bytes", ckpt_bytes, need_ck);
+    AdjLayout L;
+    RNGLD_TRY(layout_adj(h_ens, n_ens, n_total, loss->K, false, &L));
+    if (ws_bytes < L.bytes) return fail(RNGLD_ESIZE, "workspace %zu bytes < %zu required", ws_bytes, L.bytes);
+    if (!d_ws || !d_loss || (n_total && (!d_x || !d_v || !d_ckpt))) return fail(RNGLD_EINVAL, "NULL buffer");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uint8_t *ws = static_cast<uint8_t *>(d_ws);
+    RNGLD_TRY_HIP(launch_upload(ws + L.off_ens, L.ens.data(), sizeof(EnsDev) * n_ens, st));
+    RNGLD_TRY_HIP(launch_upload(ws + L.off_adj, L.adj.data(), sizeof(AdjCoef) * n_ens, st));
+    AdjArgs a{};
+    a.state = d_state;
+    a.S = g.S;
+    a.x = d_x;
+    a.v = d_v;
+    a.NT = n_total;
+    a.ens = reinterpret_cast<const EnsDev *>(ws + L.off_ens);
+    a.adj = reinterpret_cast<const AdjCoef *>(ws + L.off_adj);
+    a.n_ens = n_ens;
+    a.n_tiles = L.n_tiles;
+    a.n_steps = n_steps;
+    a.K = loss->K;
+    a.t_begin = loss->t_begin;
+    a.t_end = loss->t_end;
+    a.ckpt = static_cast<uint8_t *>(d_ckpt);
+    a.rec_bytes = ckpt_record_bytes(g, n_total);
+    a.partials = reinterpret_cast<double *>(ws + L.off_partials);
+    RNGLD_TRY_HIP(launch_ld_ckpt(g.kind, a, kAdjTile, st));
+    RNGLD_TRY_HIP(launch_adj_finalize(a.partials, L.n_tiles, 1, a.ens, n_ens,
+                                      static_cast<double>(loss->t_end - loss->t_begin + 1), d_loss, st));
+    return RNGLD_OK;
+}
+
+extern "C" int ld_run_backward(const rngld_cfg *cfg, const void *d_ckpt, size_t ckpt_bytes, const ld_ensemble *h_ens,
+                               uint32_t n_ens, uint64_t n_total, uint32_t n_steps, const ld_loss *loss,
+                               double *d_grad, void *d_ws, size_t ws_bytes, void *stream) {
+    Gen g;
+    RNGLD_TRY(check_adj_common(cfg, &g, h_ens, n_ens, n_total, n_steps, loss));
+    size_t need_ck = 0;
+    RNGLD_TRY(ld_ckpt_bytes(cfg, n_total, n_steps, loss->K, &need_ck));
+    if (ckpt_bytes < need_ck) return fail(RNGLD_ESIZE, "checkpoint buffer %zu < %zu bytes", ckpt_bytes, need_ck);
+    AdjLayout L;
+    RNGLD_TRY(layout_adj(h_ens, n_ens, n_total, loss->K, true, &L));
+    if (ws_bytes < L.bytes) return fail(RNGLD_ESIZE, "workspace %zu bytes < %zu required", ws_bytes, L.bytes);
+    if (!d_ws || !d_grad || (n_total && !d_ckpt)) return fail(RNGLD_EINVAL, "NULL buffer");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uint8_t *ws = static_cast<uint8_t *>(d_ws);
+    RNGLD_TRY_HIP(launch_upload(ws + L.off_ens, L.ens.data(), sizeof(EnsDev) * n_ens, st));
+    RNGLD_TRY_HIP(launch_upload(ws + L.off_adj, L.adj.data(), sizeof(AdjCoef) * n_ens, st));
+    AdjArgs a{};
+    a.NT = n_total;
+    a.ens = reinterpret_cast<const EnsDev *>(ws + L.off_ens);
+    a.adj = reinterpret_cast<const AdjCoef *>(ws + L.off_adj);
+    a.n_ens = n_ens;
+    a.n_tiles = L.n_tiles;
+    a.n_steps = n_steps;
+    a.K = loss->K;
+    a.t_begin = loss->t_begin;
+    a.t_end = loss->t_end;
+    a.ckpt = const_cast<uint8_t *>(static_cast<const uint8_t *>(d_ckpt));
+    a.rec_bytes = ckpt_record_bytes(g, n_total);
+    a.scratch = reinterpret_cast<float *>(ws + L.off_scratch);
+    a.partials = reinterpret_cast<double *>(ws + L.off_partials);
+    if (n_steps > 0) RNGLD_TRY_HIP(launch_ld_adjoint(g.kind, a, kAdjTile, st));
+    RNGLD_TRY_HIP(launch_adj_finalize(a.partials, L.n_tiles, 3, a.ens, n_ens,
+                                      static_cast<double>(loss->t_end - loss->t_begin + 1), d_grad, st));
+    return RNGLD_OK;
+}

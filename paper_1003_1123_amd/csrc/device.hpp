@@ -1,0 +1,258 @@
+// device.hpp -- device-side generators, uniform mapping, Box-Muller and the LD update for gfx950.
+//
+// Hybrid Taus: Sec. II.D (Eq. 2 in L'Ecuyer's shift form) and Appendix A Alg. 1.
+// Ran2: Sec. II.C and Alg. 2, with a*x mod m evaluated by Schrage's decomposition in 24-bit
+//       multiplies (every intermediate stays below 2^31, so 32-bit integers suffice).
+// Lagged Fibonacci: Sec. II.E Eq. 3 with addition mod 2^32 (the ring kernels live in k_lf.hip).
+// Box-Muller: Sec. I; four uniforms give one oscillator-step's three force components
+//       (Table II caption).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rngld {
+
+// ---- per-stream seeding: SplitMix64 (Steele, Lea & Flood 2014) in counter form -----------------
+constexpr uint64_t kGoldenGamma = 0x9E3779B97F4A7C15ull;
+
+__device__ __forceinline__ uint64_t splitmix_finalize(uint64_t z) {
+    z ^= z >> 30;
+    z *= 0xBF58476D1CE4E5B9ull;
+    z ^= z >> 27;
+    z *= 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// word i (0..3) of global stream j
+__device__ __forceinline__ uint32_t stream_seed_word(uint64_t seed, uint64_t j, uint32_t i) {
+    return static_cast<uint32_t>(splitmix_finalize(seed + (4ull * j + i + 1ull) * kGoldenGamma) >> 32);
+}
+
+// ---- LCG of Eq. 1, m = 2^32 -----------------------------------------------------------------------
+constexpr uint32_t kLcgMul = 1664525u;
+constexpr uint32_t kLcgAdd = 1013904223u;
+
+__device__ __forceinline__ uint32_t lcg_next(uint32_t x) { return kLcgMul * x + kLcgAdd; }
+
+// x advanced by n steps: the affine map x -> a x + c composed with itself by binary powering
+// (a - 1 is even, so the geometric-sum closed form cannot use a modular inverse).
+__device__ __forceinline__ uint32_t lcg_skip(uint32_t x, uint64_t n) {
+    uint32_t mul = 1u, add = 0u;            // accumulated map
+    uint32_t pm = kLcgMul, pa = kLcgAdd;    // map for 2^bit steps
+    while (n) {
+        if (n & 1u) {
+            mul = pm * mul;
+            add = pm * add + pa;
+        }
+        pa = pm * pa + pa;
+        pm = pm * pm;
+        n >>= 1;
+    }
+    return mul * x + add;
+}
+
+// ---- Tausworthe component for the trinomial x^K + x^Q + 1 with step S (Eq. 2) -----------------
+// The state occupies the top K bits; the low 32-K bits are dropped before the left shift.
+template <int Q, int S, int K>
+__device__ __forceinline__ uint32_t tausworthe(uint32_t z) {
+    constexpr uint32_t kTop = ~((1u << (32 - K)) - 1u);
+    const uint32_t feedback = ((z << Q) ^ z) >> (K - S);
+    return ((z & kTop) << S) ^ feedback;
+}
+
+// smallest word whose top K bits are not all zero
+template <int K>
+__device__ __forceinline__ uint32_t tausworthe_lift(uint32_t z) {
+    constexpr uint32_t kFloor = 1u << (32 - K);
+    return z < kFloor ? z + kFloor : z;
+}
+
+struct HybridTaus {
+    uint32_t t1, t2, t3, lcg;
+    static constexpr int kRows = 4;
+
+    __device__ __forceinline__ uint32_t next() {
+        t1 = tausworthe<13, 12, 31>(t1);
+        t2 = tausworthe<2, 4, 29>(t2);
+        t3 = tausworthe<3, 17, 28>(t3);
+        lcg = lcg_next(lcg);
+        return t1 ^ t2 ^ t3 ^ lcg;
+    }
+    // state rows: uint32 [4][S]
+    __device__ __forceinline__ void load(const uint32_t *st, uint64_t S, uint64_t j) {
+        t1 = st[j];
+        t2 = st[S + j];
+        t3 = st[2 * S + j];
+        lcg = st[3 * S + j];
+    }
+    __device__ __forceinline__ void store(uint32_t *st, uint64_t S, uint64_t j) const {
+        st[j] = t1;
+        st[S + j] = t2;
+        st[2 * S + j] = t3;
+        st[3 * S + j] = lcg;
+    }
+    __device__ __forceinline__ void seed(uint64_t seed, uint64_t stream) {
+        t1 = tausworthe_lift<31>(stream_seed_word(seed, stream, 0));
+        t2 = tausworthe_lift<29>(stream_seed_word(seed, stream, 1));
+        t3 = tausworthe_lift<28>(stream_seed_word(seed, stream, 2));
+        lcg = stream_seed_word(seed, stream, 3);
+    }
+};
+
+// ---- Ran2 -------------------------------------------------------------------------------------------
+constexpr int32_t kR2M1 = 2147483563, kR2A1 = 40014, kR2Q1 = 53668, kR2R1 = 12211;
+constexpr int32_t kR2M2 = 2147483399, kR2A2 = 40692, kR2Q2 = 52774, kR2R2 = 3791;
+constexpr int kR2Tab = 32;
+constexpr int32_t kR2Imm1 = kR2M1 - 1;
+constexpr uint32_t kR2Ndiv = 1u + static_cast<uint32_t>(kR2Imm1) / kR2Tab;
+
+// A x mod M for 0 < x < M by Schrage: M = A Q + R with R < Q, so
+// A (x mod Q) - R floor(x / Q) lies in (-M, M).  All products fit in 24-bit multiplies.
+template <int32_t A, int32_t Q, int32_t R, int32_t M>
+__device__ __forceinline__ int32_t schrage(int32_t x) {
+    const uint32_t k = static_cast<uint32_t>(x) / static_cast<uint32_t>(Q);
+    const uint32_t rem = static_cast<uint32_t>(x) - __umul24(k, Q);
+    const int32_t t = static_cast<int32_t>(__umul24(A, rem)) - static_cast<int32_t>(__umul24(k, R));
+    return t < 0 ? t + M : t;
+}
+
+__device__ __forceinline__ int32_t ran2_lcg1(int32_t x) { return schrage<kR2A1, kR2Q1, kR2R1, kR2M1>(x); }
+__device__ __forceinline__ int32_t ran2_lcg2(int32_t x) { return schrage<kR2A2, kR2Q2, kR2R2, kR2M2>(x); }
+
+// Ran2 stream with its shuffle table in LDS: tab[t * tstride] is entry t of this thread's table.
+struct Ran2 {
+    int32_t idum, idum2, iy;
+    int32_t *tab;
+    uint64_t tstride;
+    static constexpr int kRows = 35;
+
+    __device__ __forceinline__ int32_t next_iy() {
+        idum = ran2_lcg1(idum);
+        idum2 = ran2_lcg2(idum2);
+        const uint32_t slot = static_cast<uint32_t>(iy) / kR2Ndiv;
+        int32_t *cell = tab + slot * tstride;
+        int32_t out = *cell - idum2;
+        *cell = idum;
+        out += (out < 1) ? kR2Imm1 : 0;
+        iy = out;
+        return out;
+    }
+    // word fed to the uniform mapping: iy - 1 spans [0, 2^31), doubled
+    __device__ __forceinline__ uint32_t next() { return static_cast<uint32_t>(next_iy() - 1) << 1; }
+
+    // state rows: int32 [35][S]: idum, idum2, iy, iv[0..31]
+    __device__ __forceinline__ void load(const int32_t *st, uint64_t S, uint64_t j) {
+        idum = st[j];
+        idum2 = st[S + j];
+        iy = st[2 * S + j];
+        for (int t = 0; t < kR2Tab; ++t) tab[t * tstride] = st[(3 + t) * S + j];
+    }
+    __device__ __forceinline__ void store(int32_t *st, uint64_t S, uint64_t j) const {
+        st[j] = idum;
+        st[S + j] = idum2;
+        st[2 * S + j] = iy;
+        for (int t = 0; t < kR2Tab; ++t) st[(3 + t) * S + j] = tab[t * tstride];
+    }
+    // Alg. 2 initialisation: idum2 = idum; 8 discarded LCG1 steps, then 32 filling iv[31]..iv[0]
+    __device__ __forceinline__ void seed(uint64_t seed, uint64_t stream) {
+        const uint32_t w = stream_seed_word(seed, stream, 0);
+        int32_t x = 1 + static_cast<int32_t>(w % static_cast<uint32_t>(kR2M1 - 1));
+        idum2 = x;
+        for (int t = 0; t < 8; ++t) x = ran2_lcg1(x);
+        for (int t = kR2Tab - 1; t >= 0; --t) {
+            x = ran2_lcg1(x);
+            tab[t * tstride] = x;
+        }
+        idum = x;
+        iy = tab[0];
+    }
+};
+
+// ---- uniform mapping and Box-Muller ----------------------------------------------------------------
+// u_open = ((w >> 8) + 1) 2^-24 in (0, 1]; u_half = (w >> 8) 2^-24 in [0, 1); both exact in FP32.
+__device__ __forceinline__ float box_muller_radius(uint32_t w) {
+    const float u = static_cast<float>((w >> 8) + 1u) * 0x1p-24f;
+    return sqrtf(-2.0f * logf(u));
+}
+// cos and sin of 2 pi u_half; (w >> 8) 2^-23 = 2 u_half exactly, the argument of the pi-scaled pair
+__device__ __forceinline__ void box_muller_angle(uint32_t w, float &c, float &s) {
+    sincospif(static_cast<float>(w >> 8) * 0x1p-23f, &s, &c);
+}
+__device__ __forceinline__ float box_muller_cos(uint32_t w) {
+    return cospif(static_cast<float>(w >> 8) * 0x1p-23f);
+}
+
+// three force components from one oscillator-step's four words
+__device__ __forceinline__ void gaussian_forces(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, float &gx,
+                                                float &gy, float &gz) {
+    const float r0 = box_muller_radius(w0);
+    float c, s;
+    box_muller_angle(w1, c, s);
+    gx = r0 * c;
+    gy = r0 * s;
+    gz = box_muller_radius(w2) * box_muller_cos(w3);
+}
+
+// ---- LD update ----------------------------------------------------------------------------------------
+// underdamped semi-implicit Euler-Maruyama (scheme 0) or overdamped Eq. 5 (scheme 1), per component
+struct LdCoef {
+    float c, kap, sig, h;  // scheme 0: c = 1 - gamma h, kap = k h / m, sig = sqrt(2 gamma kT h / m)
+    float odc, ods;        // scheme 1: odc = k h / xi, ods = sqrt(2 kT h / xi), xi = m gamma
+    int32_t scheme;
+    int32_t pad;
+};
+
+__device__ __forceinline__ void ld_update(const LdCoef &q, float &x, float &v, float g) {
+    if (q.scheme == 0) {
+        v = q.c * v - q.kap * x + q.sig * g;
+        x = x + q.h * v;
+    } else {
+        x = x - q.odc * x + q.ods * g;
+    }
+}
+
+// ---- reductions -----------------------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double a) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) a += __shfl_xor(a, m, 64);
+    return a;
+}
+
+// Six per-thread FP64 sums -> one fixed-order block total written by threads 0..5 to dst.
+// Every thread of the block must call it (it synchronises the block twice).
+template <int BLOCK>
+__device__ __forceinline__ void block_sum6(const double (&q)[6], double (*red)[6], double *dst) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        const double s = wave_sum(q[i]);
+        if (lane == 0) red[wave][i] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        double s = 0.0;
+        for (int w = 0; w < BLOCK / 64; ++w) s += red[w][threadIdx.x];
+        dst[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// the six observables of one oscillator's three coordinates, FP64 products of FP32 values
+__device__ __forceinline__ void add_observables(double (&q)[6], const float (&x)[3], const float (&v)[3],
+                                                const float (&x0)[3], const float (&v0)[3], bool after_t0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double xd = x[d], vd = v[d];
+        q[0] += xd * xd;
+        q[1] += vd * vd;
+        q[2] += xd * vd;
+        q[3] += xd;
+        if (after_t0) {
+            q[4] += xd * static_cast<double>(x0[d]);
+            q[5] += vd * static_cast<double>(v0[d]);
+        }
+    }
+}
+
+}  // namespace rngld

@@ -1,0 +1,141 @@
+// internal.hpp -- structures shared by the kernel translation units and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rngld.h"
+#include "device.hpp"
+
+namespace rngld {
+
+constexpr int kBulkBlock = 256;
+
+// per-ensemble record in the workspace (64 bytes)
+struct EnsDev {
+    uint64_t offset;      // first oscillator / stream column
+    uint64_t n;           // oscillators
+    uint32_t tile_begin;  // first tile of this ensemble
+    uint32_t n_tiles;
+    LdCoef coef;
+    uint32_t pad[2];
+};
+static_assert(sizeof(EnsDev) == 64, "EnsDev layout");
+
+// arguments of the fused per-thread LD kernel
+struct LdArgs {
+    void *state;
+    uint64_t S;           // state row stride (streams)
+    float *x, *v;
+    uint64_t NT;          // x, v row stride (n_total)
+    const EnsDev *ens;
+    uint32_t n_ens;
+    uint32_t n_tiles;     // tiles over all ensembles
+    uint32_t step_begin;  // run-relative steps [step_begin, step_end) of this launch
+    uint32_t step_end;
+    uint32_t n_steps;
+    uint32_t stride;      // observation stride (0 = none)
+    uint32_t t0;
+    uint32_t P;           // observation points
+    double *partials;     // [P][n_tiles][6]
+    float *t0buf;         // [6][NT] x(t0), v(t0) carried between launches
+};
+
+// lagged-Fibonacci device header (first 64 bytes of the state)
+struct LfHeader {
+    uint64_t pos;   // values generated so far
+    uint32_t slot;  // ring slot of position pos
+    uint32_t ll, sl, R, W;
+    uint32_t pad[9];
+};
+static_assert(sizeof(LfHeader) == 64, "LfHeader layout");
+
+struct LfRing {
+    const LfHeader *hdr;
+    uint32_t *ring;
+    uint32_t R, ll, sl;
+};
+
+// LF phase of an LD step: oscillators [osc_begin, osc_begin + osc_count) take the 4 * osc_count
+// consecutive positions starting `off_mod` ring slots after the call's first position
+struct LfLdPhase {
+    LfRing L;
+    uint32_t off_mod;
+    uint32_t osc_count;
+    uint64_t osc_begin;
+    uint64_t N;           // x, v and t0buf row stride
+    uint64_t n_osc;       // oscillators of the run
+    float *x, *v;
+    LdCoef coef;
+    uint32_t step;        // run-relative step index of this phase
+    uint32_t stride, t0;  // observation
+    uint32_t tile_base;   // first partial slot of this phase
+    uint32_t n_tiles;
+    uint32_t pad;
+    double *partials;     // [P][n_tiles][6]
+    float *t0buf;         // [6][N]
+};
+
+// ---- adjoint (k_adj.hip) ---------------------------------------------------------------------------
+struct AdjCoef {
+    LdCoef f;         // forward coefficients
+    float dkap_dk;    // h / m
+    float dc_dgamma;  // -h
+    float dsig_dgamma;
+    float dsig_dkT;
+};
+
+struct AdjArgs {
+    void *state;  // forward: live state (stride S); unused by backward
+    uint64_t S;
+    float *x, *v;
+    uint64_t NT;
+    const EnsDev *ens;  // coef of EnsDev is unused here; adj holds per-ensemble coefficients
+    const AdjCoef *adj;
+    uint32_t n_ens, n_tiles;
+    uint32_t n_steps, K;
+    uint32_t t_begin, t_end;
+    uint8_t *ckpt;
+    uint64_t rec_bytes;  // bytes per checkpoint record
+    float *scratch;      // backward: [K][9][NT]
+    double *partials;    // [n_tiles][3] (loss uses slot 0)
+};
+
+hipError_t launch_ld_ckpt(int kind, const AdjArgs &a, uint32_t block, hipStream_t st);
+hipError_t launch_ld_adjoint(int kind, const AdjArgs &a, uint32_t block, hipStream_t st);
+hipError_t launch_adj_finalize(const double *partials, uint32_t n_tiles, uint32_t width, const EnsDev *ens,
+                               uint32_t n_ens, double denom_steps, double *out, hipStream_t st);
+
+// ---- launchers (k_rng.hip) -------------------------------------------------------------------------
+hipError_t launch_seed(int kind, void *state, uint64_t S, uint64_t seed, uint64_t stream_base, uint64_t col_offset,
+                       uint64_t count, hipStream_t st);
+hipError_t launch_bulk_uniform(int kind, void *state, uint64_t S, uint64_t per_stream, uint32_t *out,
+                               hipStream_t st);
+hipError_t launch_bulk_gaussian(int kind, void *state, uint64_t S, uint64_t per_stream, float *out, hipStream_t st);
+
+// ---- launchers (k_ld.hip) --------------------------------------------------------------------------
+hipError_t launch_ld_run(int kind, const LdArgs &a, const ld_tuning &t, uint32_t grid, hipStream_t st);
+hipError_t launch_obs_finalize(const double *partials, uint32_t n_tiles, uint32_t P, const EnsDev *ens,
+                               uint32_t n_ens, double *out, hipStream_t st);
+hipError_t launch_ld_step(int kind, void *state, uint64_t S, const LdCoef &coef, uint64_t n, float *x, float *v,
+                          hipStream_t st);
+hipError_t launch_upload(void *dst, const void *src, size_t bytes, hipStream_t st);
+size_t ld_run_lds_bytes(int kind, const ld_tuning &t);
+const void *ld_run_kernel_ptr(int kind, const ld_tuning &t);
+
+// ---- launchers (k_lf.hip) --------------------------------------------------------------------------
+hipError_t launch_lf_seed(void *state, uint32_t ll, uint32_t sl, uint32_t R, uint32_t W, uint64_t seed,
+                          hipStream_t st);
+hipError_t launch_lf_uniform_phase(const LfRing &L, uint32_t *out, uint64_t first, uint32_t count, hipStream_t st);
+hipError_t launch_lf_ring_store(const LfRing &L, const uint32_t *out, uint64_t count, uint32_t base_mod,
+                                hipStream_t st);
+hipError_t launch_lf_gauss_phase(const LfRing &L, float *out, uint64_t first, uint32_t off_mod, uint32_t count,
+                                 hipStream_t st);
+hipError_t launch_lf_advance(LfHeader *hdr, uint64_t count, uint32_t count_mod, hipStream_t st);
+hipError_t launch_lf_ld_phase(const LfLdPhase &ph, hipStream_t st);
+hipError_t launch_lf_observe(const LfLdPhase &ph0, uint32_t n_phases, uint64_t phase_osc, uint32_t point,
+                             bool t0_now, hipStream_t st);
+
+constexpr int kLfLdBlock = 256;
+
+}  // namespace rngld
