@@ -141,10 +141,13 @@ def cpu_baseline(W):
             "per_generator": per}
 
 
-def extras(R, W, torch):
-    out = {}
-    ev = lambda: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-    # config 3: bare generators
+def _ev(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def extra_config3(R, W, torch):
+    """Bare generators: 2^30 uint32 and 2^30 Gaussians per generator."""
+    ev = lambda: _ev(torch)
     c3 = W.C3
     S, per = c3["streams"], c3["per_stream"]
     n_vals = S * per
@@ -174,8 +177,12 @@ def extras(R, W, torch):
                       "gaussians_per_s": n_vals / (c.elapsed_time(d) / 1e3),
                       "uint32_GBps_written": 4 * n_vals / (a.elapsed_time(b) / 1e3) / 1e9}
     del buf_u, buf_g
-    out["config3_bare_generators"] = bare
-    # config 4: batched ensembles in one hipGraph-captured plan vs 512 plain launches
+    return bare
+
+
+def extra_config4(R, W, torch):
+    """512 uneven ensembles in one hipGraph-captured plan vs 512 plain ld_run launches."""
+    ev = lambda: _ev(torch)
     c4 = W.C4
     ens_list = W.batched_ensembles(c4["n_ens"], c4["draw_seed"], c4["base_seed"], c4["dt"])
     offs = [0]
@@ -215,13 +222,17 @@ def extras(R, W, torch):
     t_plain = a.elapsed_time(b) / 1e3
     R.ld_set_tuning("taus")
     osc_steps = n_total * c4["steps"]
-    out["config4_batched"] = {"ensembles": n_ens, "oscillators": n_total, "steps": c4["steps"],
+    res = {"ensembles": n_ens, "oscillators": n_total, "steps": c4["steps"],
                               "osc_steps": osc_steps, "tuning": list(tune.astuple()),
                               "batched_graph_osc_steps_per_s": osc_steps / t_batched,
                               "plain_512_launches_osc_steps_per_s": osc_steps / t_plain,
                               "speedup_batched_vs_plain": t_plain / t_batched}
     del x, v, st, ws
-    # config 5: adjoint
+    return res
+
+
+def extra_config5(R, W, torch):
+    """Adjoint: forward with checkpoints, backward with replay; fwd+bwd over fwd time."""
     from paper_1003_1123_amd import autograd as A
     c5 = W.C5
     p5 = c5["params"].as_f32()
@@ -239,11 +250,23 @@ def extras(R, W, torch):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     osc = c5["N"] * c5["steps"]
-    out["config5_adjoint"] = {"N": c5["N"], "steps": c5["steps"], "K": c5["K"], "loss": L.item(),
+    return {"N": c5["N"], "steps": c5["steps"], "K": c5["K"], "loss": L.item(),
                               "grad_k_gamma_kT": [k.grad.item(), g.grad.item(), kT.grad.item()],
                               "forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3,
                               "fwd_plus_bwd_over_fwd": (t2 - t0) / (t1 - t0),
                               "forward_osc_steps_per_s": osc / (t1 - t0)}
+
+
+def extras(R, W, torch):
+    out = {}
+    for name, fn in (("config3_bare_generators", extra_config3), ("config4_batched", extra_config4),
+                     ("config5_adjoint", extra_config5)):
+        try:
+            out[name] = fn(R, W, torch)
+            log("%s: %s" % (name, json.dumps(out[name])))
+        except Exception as e:  # reported in the JSON line, never hidden
+            out[name] = {"error": "%s: %s" % (type(e).__name__, e)}
+            log("%s failed: %s" % (name, e))
     return out
 
 
@@ -302,6 +325,8 @@ def main():
         "per_generator": per_gen,
         "rooflines_all": rooflines,
     }
+    log("config 2 value %.4g osc-steps/s; per generator ms: %s" %
+        (value, {k: round(v["ms_per_run"], 2) for k, v in per_gen.items()}))
     if not args.no_extras:
         res["extras"] = extras(R, W, torch)
     if not args.no_cpu:

@@ -108,6 +108,14 @@ RNGLD_API int rng_uniform(const rngld_cfg *cfg, void *d_state, size_t state_byte
 RNGLD_API int rng_gaussian(const rngld_cfg *cfg, void *d_state, size_t state_bytes, uint64_t per_stream,
                  float *d_out, uint64_t out_len, void *stream);
 
+/*
+ * The Box-Muller transform the generators apply (Sec. I), on caller-supplied word pairs:
+ * d_out[2i] = r cos(2 pi u1), d_out[2i+1] = r sin(2 pi u1) with r = sqrt(-2 ln u0),
+ * u0 = ((d_words[2i] >> 8) + 1) 2^-24, u1 = (d_words[2i+1] >> 8) 2^-24.  Lets the transform be
+ * checked over its whole 24-bit input domain independently of any generator.
+ */
+RNGLD_API int rng_box_muller(const uint32_t *d_words, uint64_t n_pairs, float *d_out, void *stream);
+
 /* ---- Langevin dynamics ------------------------------------------------------------------------ */
 /*
  * Physical parameters (binary32).  scheme 0: underdamped (Sec. I), semi-implicit Euler-Maruyama

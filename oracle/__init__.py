@@ -72,6 +72,7 @@ def lib():
                 "orc_u_half": (dbl, [u32]),
                 "orc_bm_radius": (dbl, [u32]),
                 "orc_box_muller": (None, [u32, u32, vp, vp]),
+                "orc_box_muller_many": (None, [vp, u64, vp]),
                 "orc_uniform_streams": (C.c_int, [C.c_int, vp, u64, u64, vp]),
                 "orc_gaussian_streams": (C.c_int, [C.c_int, vp, u64, u64, vp]),
                 "orc_lf_gaussian": (C.c_int, [u32, u32, vp, u64, vp]),
@@ -165,6 +166,14 @@ def box_muller(w0: int, w1: int):
     g0, g1 = C.c_double(), C.c_double()
     lib().orc_box_muller(w0, w1, C.byref(g0), C.byref(g1))
     return g0.value, g1.value
+
+
+def box_muller_many(words: np.ndarray) -> np.ndarray:
+    """Box-Muller pairs of consecutive words, FP64."""
+    words = np.ascontiguousarray(words, dtype=np.uint32)
+    out = np.zeros(max(words.size, 1))
+    lib().orc_box_muller_many(_p(words), words.size // 2, _p(out))
+    return out[:words.size]
 
 
 # ---------------------------------------------------------------------------------------------

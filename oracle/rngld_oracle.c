@@ -360,6 +360,12 @@ void orc_box_muller(uint32_t w0, uint32_t w1, double *g0, double *g1)
     *g1 = r * sin(theta);
 }
 
+/* Box-Muller of n word pairs: out[2i], out[2i+1] from words[2i], words[2i+1]. */
+void orc_box_muller_many(const uint32_t *words, uint64_t n_pairs, double *out)
+{
+    for (uint64_t i = 0; i < n_pairs; ++i) orc_box_muller(words[2 * i], words[2 * i + 1], &out[2 * i], &out[2 * i + 1]);
+}
+
 /* ------------------------------------------------------------------------------------------- */
 /* Bulk streams.  kind: 0 = Hybrid Taus, 1 = Ran2 (per-stream states), 2 = lagged Fibonacci
  * (one shared window).  Per-stream output layout out[t*S + j] = value t of stream j.

@@ -85,6 +85,7 @@ def _load():
         "ld_adjoint_workspace_bytes": [P(Cfg), P(Ensemble), u32, u64, u32, P(Loss), P(sz)],
         "ld_run_ckpt": [P(Cfg), vp, sz, P(Ensemble), u32, u64, u32, vp, vp, P(Loss), vp, sz, vp, vp, sz, vp],
         "ld_run_backward": [P(Cfg), vp, sz, P(Ensemble), u32, u64, u32, P(Loss), vp, vp, sz, vp],
+        "rng_box_muller": [vp, u64, vp, vp],
         "rngld_version": [],
     }
     for name, args in sigs.items():
@@ -101,7 +102,7 @@ lib = _load()
 ENTRY_POINTS = ("rngld_state_bytes", "rng_init", "rng_init_ensembles", "rng_uniform", "rng_gaussian", "ld_step",
                 "ld_workspace_bytes", "ld_run", "ld_get_tuning", "ld_set_tuning", "ld_autotune", "ld_plan_create",
                 "ld_plan_launch", "ld_plan_destroy", "ld_ckpt_bytes", "ld_adjoint_workspace_bytes", "ld_run_ckpt",
-                "ld_run_backward", "rngld_last_error", "rngld_version")
+                "ld_run_backward", "rng_box_muller", "rngld_last_error", "rngld_version")
 
 
 def _check(rc: int, func: str):
@@ -186,6 +187,13 @@ def rng_uniform(cfg: Cfg, state: torch.Tensor, per_stream: int, out: torch.Tenso
 def rng_gaussian(cfg: Cfg, state: torch.Tensor, per_stream: int, out: torch.Tensor):
     _check(lib.rng_gaussian(C.byref(cfg), _dev(state, torch.uint8, "state"), _nbytes(state), per_stream,
                             _dev(out, torch.float32, "out"), out.numel(), _stream()), "rng_gaussian")
+
+
+def rng_box_muller(words: torch.Tensor, out: torch.Tensor):
+    """out[2i], out[2i+1] = Box-Muller pair of words[2i], words[2i+1]."""
+    n_pairs = words.numel() // 2
+    _check(lib.rng_box_muller(_dev(words, (torch.uint32, torch.int32), "words"), n_pairs,
+                              _dev(out, torch.float32, "out", 2 * n_pairs), _stream()), "rng_box_muller")
 
 
 def ld_step(cfg: Cfg, state: torch.Tensor, params: Params, n: int, x: torch.Tensor, v: torch.Tensor):

@@ -56,7 +56,7 @@ class LDAdjoint(torch.autograd.Function):
         R.ld_run_ckpt(run.cfg, run.state, ens, n_ens, run.n_total, run.n_steps, run.x, run.v, run.loss, run.ckpt,
                       out, run.ws)
         ctx.run, ctx.ens, ctx.n_ens = run, ens, n_ens
-        ctx.dtypes = (k.dtype, gamma.dtype, kT.dtype)
+        ctx.meta = tuple((t.dtype, t.device) for t in (k, gamma, kT))
         return out
 
     @staticmethod
@@ -64,6 +64,6 @@ class LDAdjoint(torch.autograd.Function):
         run = ctx.run
         g = torch.empty((ctx.n_ens, 3), dtype=torch.float64, device=run.device)
         R.ld_run_backward(run.cfg, run.ckpt, ctx.ens, ctx.n_ens, run.n_total, run.n_steps, run.loss, g, run.ws)
-        go = grad_out.to(torch.float64)
-        dk, dg, dT = (go * g[:, i] for i in range(3))
-        return dk.to(ctx.dtypes[0]), dg.to(ctx.dtypes[1]), dT.to(ctx.dtypes[2]), None
+        go = grad_out.to(device=run.device, dtype=torch.float64)
+        grads = [(go * g[:, i]).to(device=dev, dtype=dt) for i, (dt, dev) in enumerate(ctx.meta)]
+        return grads[0], grads[1], grads[2], None

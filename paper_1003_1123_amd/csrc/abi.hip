@@ -426,6 +426,14 @@ int rng_gaussian(const rngld_cfg *cfg, void *d_state, size_t state_bytes, uint64
     return RNGLD_OK;
 }
 
+int rng_box_muller(const uint32_t *d_words, uint64_t n_pairs, float *d_out, void *stream) {
+    if (n_pairs == 0) return RNGLD_OK;
+    if (!d_words || !d_out) return fail(RNGLD_EINVAL, "words or output is NULL");
+    if (n_pairs > (1ull << 40)) return fail(RNGLD_EINVAL, "too many pairs");
+    RNGLD_TRY_HIP(launch_box_muller(d_words, n_pairs, d_out, static_cast<hipStream_t>(stream)));
+    return RNGLD_OK;
+}
+
 int ld_step(const rngld_cfg *cfg, void *d_state, size_t state_bytes, const ld_params *p, uint64_t n, float *d_x,
             float *d_v, void *stream) {
     Gen g;

@@ -67,6 +67,43 @@ __device__ __forceinline__ void record_point(const float (&x)[OPT][3], const flo
     block_sum6<BLOCK>(q, red, dst);
 }
 
+// the step loop of one tile, with the integrator scheme fixed at compile time
+template <int SCHEME, int BLOCK, int OPT, class Gen>
+__device__ __forceinline__ void run_steps(const LdArgs &a, const LdCoef &q, uint32_t tile, Gen (&g)[OPT],
+                                          float (&x)[OPT][3], float (&v)[OPT][3], float (&x0)[OPT][3],
+                                          float (&v0)[OPT][3], const bool (&act)[OPT], double (*red)[kNobs]) {
+    uint32_t next_obs = 0xFFFFFFFFu;
+    if (a.stride) next_obs = ((a.step_begin + a.stride - 1) / a.stride) * a.stride;
+    for (uint32_t s = a.step_begin; s < a.step_end; ++s) {
+        if (s == a.t0) {
+#pragma unroll
+            for (int k = 0; k < OPT; ++k)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    x0[k][d] = x[k][d];
+                    v0[k][d] = v[k][d];
+                }
+        }
+        if (s == next_obs) {
+            double *dst = a.partials + (static_cast<uint64_t>(s / a.stride) * a.n_tiles + tile) * kNobs;
+            record_point<BLOCK, OPT>(x, v, x0, v0, act, s >= a.t0, red, dst);
+            next_obs += a.stride;
+        }
+#pragma unroll
+        for (int k = 0; k < OPT; ++k) {
+            const uint32_t w0 = g[k].next();
+            const uint32_t w1 = g[k].next();
+            const uint32_t w2 = g[k].next();
+            const uint32_t w3 = g[k].next();
+            float gx, gy, gz;
+            gaussian_forces(w0, w1, w2, w3, gx, gy, gz);
+            ld_update_s<SCHEME>(q, x[k][0], v[k][0], gx);
+            ld_update_s<SCHEME>(q, x[k][1], v[k][1], gy);
+            ld_update_s<SCHEME>(q, x[k][2], v[k][2], gz);
+        }
+    }
+}
+
 template <class Gen, int BLOCK, int OPT>
 __global__ __launch_bounds__(BLOCK) void ld_run_kernel(LdArgs a) {
     extern __shared__ int32_t lds_tables[];  // Ran2: [OPT][32][BLOCK]
@@ -116,36 +153,10 @@ __global__ __launch_bounds__(BLOCK) void ld_run_kernel(LdArgs a) {
             }
         }
 
-        uint32_t next_obs = 0xFFFFFFFFu;
-        if (a.stride) next_obs = ((a.step_begin + a.stride - 1) / a.stride) * a.stride;
-        for (uint32_t s = a.step_begin; s < a.step_end; ++s) {
-            if (s == a.t0) {
-#pragma unroll
-                for (int k = 0; k < OPT; ++k)
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        x0[k][d] = x[k][d];
-                        v0[k][d] = v[k][d];
-                    }
-            }
-            if (s == next_obs) {
-                double *dst = a.partials + (static_cast<uint64_t>(s / a.stride) * a.n_tiles + tile) * kNobs;
-                record_point<BLOCK, OPT>(x, v, x0, v0, act, s >= a.t0, red, dst);
-                next_obs += a.stride;
-            }
-#pragma unroll
-            for (int k = 0; k < OPT; ++k) {
-                const uint32_t w0 = g[k].next();
-                const uint32_t w1 = g[k].next();
-                const uint32_t w2 = g[k].next();
-                const uint32_t w3 = g[k].next();
-                float gx, gy, gz;
-                gaussian_forces(w0, w1, w2, w3, gx, gy, gz);
-                ld_update(q, x[k][0], v[k][0], gx);
-                ld_update(q, x[k][1], v[k][1], gy);
-                ld_update(q, x[k][2], v[k][2], gz);
-            }
-        }
+        if (q.scheme == 0)
+            run_steps<0, BLOCK, OPT>(a, q, tile, g, x, v, x0, v0, act, red);
+        else
+            run_steps<1, BLOCK, OPT>(a, q, tile, g, x, v, x0, v0, act, red);
         if (a.step_end == a.n_steps) {
             const uint32_t s = a.n_steps;
             if (s == a.t0) {

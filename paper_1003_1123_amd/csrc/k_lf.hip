@@ -31,6 +31,7 @@ __global__ __launch_bounds__(kBulkBlock) void lf_seed_kernel(LfHeader *hdr, uint
         hdr->sl = sl;
         hdr->R = R;
         hdr->W = W;
+        for (int k = 0; k < 9; ++k) hdr->pad[k] = 0u;
     }
     if (i >= R) return;
     const uint32_t x0 = stream_seed_word(seed, 0, 0);

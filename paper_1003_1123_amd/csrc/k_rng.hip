@@ -95,6 +95,17 @@ __global__ __launch_bounds__(kBulkBlock) void ran2_gaussian_kernel(int32_t *st, 
     g.store(st, S, j);
 }
 
+__global__ __launch_bounds__(kBulkBlock) void box_muller_kernel(const uint32_t *words, uint64_t n_pairs,
+                                                                float *out) {
+    const uint64_t i = blockIdx.x * static_cast<uint64_t>(kBulkBlock) + threadIdx.x;
+    if (i >= n_pairs) return;
+    const float r = box_muller_radius(words[2 * i]);
+    float c, s;
+    box_muller_angle(words[2 * i + 1], c, s);
+    out[2 * i] = r * c;
+    out[2 * i + 1] = r * s;
+}
+
 inline dim3 grid_for(uint64_t n) { return dim3(static_cast<unsigned>((n + kBulkBlock - 1) / kBulkBlock)); }
 
 }  // namespace
@@ -127,6 +138,12 @@ hipError_t launch_bulk_gaussian(int kind, void *state, uint64_t S, uint64_t per_
         taus_gaussian_kernel<<<grid_for(S), kBulkBlock, 0, st>>>(static_cast<uint32_t *>(state), S, per_stream, out);
     else
         ran2_gaussian_kernel<<<grid_for(S), kBulkBlock, 0, st>>>(static_cast<int32_t *>(state), S, per_stream, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_box_muller(const uint32_t *words, uint64_t n_pairs, float *out, hipStream_t st) {
+    if (n_pairs == 0) return hipSuccess;
+    box_muller_kernel<<<grid_for(n_pairs), kBulkBlock, 0, st>>>(words, n_pairs, out);
     return hipGetLastError();
 }
 

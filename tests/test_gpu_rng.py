@@ -207,3 +207,21 @@ def test_lf_config3_one_stream_of_2_30():
     R.rng_uniform(cfg, st, 1000, nxt)
     assert np.array_equal(_u32(nxt), orc.lf_generate(ll, sl, win, 1000))
     del out
+
+
+# ---------------------------------------------------------------------------------------------
+# the transform over its whole input domain
+
+def test_box_muller_exhaustive_24_bit_domain():
+    """Every 24-bit radius input (angle 0) and every 24-bit angle input (largest radius) against the
+    FP64 oracle: the worst case of each factor, so every Gaussian the library can produce is within
+    the bound."""
+    k = np.arange(2**24, dtype=np.uint32) << np.uint32(8)
+    for words in (np.stack([k, np.zeros_like(k)], 1).ravel(), np.stack([np.zeros_like(k), k], 1).ravel()):
+        d = torch.as_tensor(words.view(np.int32), device="cuda")
+        out = torch.empty(words.size, dtype=torch.float32, device="cuda")
+        R.rng_box_muller(d, out)
+        ref = orc.box_muller_many(words)
+        err = float(np.max(np.abs(out.cpu().numpy().astype(np.float64) - ref)))
+        _say("box-muller exhaustive max abs err", err)
+        assert err <= GAUSS_TOL
