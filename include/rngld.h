@@ -172,7 +172,10 @@ RNGLD_API int ld_step(const rngld_cfg *cfg, void *d_state, size_t state_bytes, c
  * update and x, v and the per-thread state held on chip for the whole run.
  *  d_x, d_v   : float[3][n_total]; ensembles must lie inside [0, n_total) and must not overlap.
  *  obs, d_obs : optional observables, d_obs = double[n_ens][P][6], P = n_steps/stride + 1.
- *  d_ws       : workspace of ld_workspace_bytes() bytes (any alignment >= 256).
+ *  d_ws       : workspace of ld_workspace_bytes() bytes (any alignment >= 256).  Its first four
+ *               bytes are a uint32 status word: nonzero after a lagged-Fibonacci dataflow run that
+ *               gave up waiting for a dependency (the run's results are then invalid); read it
+ *               after synchronising the stream.
  * LAGFIB supports n_ens == 1 only (one shared sequence).  The result of ensemble e equals a plain
  * run (n_ens = 1, offset 0) on that ensemble alone, bit for bit, under the same tuning.
  */
@@ -194,9 +197,11 @@ typedef struct ld_tuning {
     uint32_t osc_per_thread;
     uint32_t steps_per_launch;
     uint32_t blocks_per_cu;
+    uint32_t lf_waves; /* LAGFIB only: 0 = one persistent dataflow launch when the ring is exactly
+                          ll + sl words (lf_wave = sl), 1 = one launch per wave */
 } ld_tuning;
 
-/* Tuning used by ld_run for a generator kind (process-wide; default {256, 1, 0, 0}). */
+/* Tuning used by ld_run for a generator kind (process-wide; default {256, 1, 0, 0, 0}). */
 RNGLD_API int ld_get_tuning(int32_t kind, ld_tuning *out);
 RNGLD_API int ld_set_tuning(int32_t kind, const ld_tuning *t);
 

@@ -50,10 +50,10 @@ class Obs(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("block", C.c_uint32), ("osc_per_thread", C.c_uint32), ("steps_per_launch", C.c_uint32),
-                ("blocks_per_cu", C.c_uint32)]
+                ("blocks_per_cu", C.c_uint32), ("lf_waves", C.c_uint32)]
 
     def astuple(self):
-        return (self.block, self.osc_per_thread, self.steps_per_launch, self.blocks_per_cu)
+        return (self.block, self.osc_per_thread, self.steps_per_launch, self.blocks_per_cu, self.lf_waves)
 
 
 class Loss(C.Structure):
@@ -223,14 +223,20 @@ def ld_run(cfg: Cfg, state: torch.Tensor, ens, n_ens: int, n_total: int, n_steps
     return ws
 
 
+def ws_status(ws: torch.Tensor) -> int:
+    """The workspace status word (synchronises): nonzero after a dataflow run that gave up a wait."""
+    torch.cuda.current_stream().synchronize()
+    return int(ws[:4].cpu().numpy().view("<u4")[0])
+
+
 def ld_get_tuning(kind) -> Tuning:
     t = Tuning()
     _check(lib.ld_get_tuning(KINDS.get(kind, kind) if isinstance(kind, str) else kind, C.byref(t)), "ld_get_tuning")
     return t
 
 
-def ld_set_tuning(kind, block=256, osc_per_thread=1, steps_per_launch=0, blocks_per_cu=0):
-    t = Tuning(block, osc_per_thread, steps_per_launch, blocks_per_cu)
+def ld_set_tuning(kind, block=256, osc_per_thread=1, steps_per_launch=0, blocks_per_cu=0, lf_waves=0):
+    t = Tuning(block, osc_per_thread, steps_per_launch, blocks_per_cu, lf_waves)
     _check(lib.ld_set_tuning(KINDS.get(kind, kind) if isinstance(kind, str) else kind, C.byref(t)), "ld_set_tuning")
 
 

@@ -153,7 +153,7 @@ int check_ensembles(const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total, 
 
 // ---- tuning -----------------------------------------------------------------------------------------
 std::mutex g_tune_mu;
-ld_tuning g_tuning[3] = {{256, 1, 0, 0}, {256, 1, 0, 0}, {256, 1, 0, 0}};
+ld_tuning g_tuning[3] = {{256, 1, 0, 0, 0}, {256, 1, 0, 0, 0}, {256, 1, 0, 0, 0}};
 
 ld_tuning current_tuning(int kind) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -162,7 +162,7 @@ ld_tuning current_tuning(int kind) {
 
 bool valid_tuning(const ld_tuning &t) {
     return (t.block == 64 || t.block == 128 || t.block == 256 || t.block == 512) &&
-           (t.osc_per_thread == 1 || t.osc_per_thread == 2) && t.blocks_per_cu <= 64;
+           (t.osc_per_thread == 1 || t.osc_per_thread == 2) && t.blocks_per_cu <= 64 && t.lf_waves <= 1;
 }
 
 int device_cus() {
@@ -173,13 +173,17 @@ int device_cus() {
 }
 
 // ---- ld_run plan (host-side description of one call) ------------------------------------------------
+// Workspace of ld_run: [status word | padding to 256] [EnsDev table] [partials] [x(t0), v(t0)]
+// [LF dataflow progress flags].  The layout does not depend on the device.
 struct RunLayout {
     std::vector<EnsDev> ens;
     uint32_t n_tiles = 0, P = 0;
-    size_t off_ens = 0, off_partials = 0, off_t0 = 0, bytes = 0;
-    // LF phase structure
+    size_t off_ens = 0, off_partials = 0, off_t0 = 0, off_progress = 0, bytes = 0;
+    // LF wave structure
     uint32_t Q = 0, bpp = 0;
     uint64_t Nq = 0;
+    // LF dataflow structure
+    uint32_t flow_tiles = 0;
 };
 
 int layout_run(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total, uint32_t n_steps,
@@ -194,7 +198,8 @@ int layout_run(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t 
         L->Q = n ? static_cast<uint32_t>((n + nmax - 1) / nmax) : 0;
         L->Nq = L->Q ? (n + L->Q - 1) / L->Q : 0;
         L->bpp = static_cast<uint32_t>((L->Nq + kLfLdBlock - 1) / kLfLdBlock);
-        L->n_tiles = L->Q * L->bpp;
+        L->flow_tiles = static_cast<uint32_t>((n + (1u << kLfFlowBlockLog2) - 1) >> kLfFlowBlockLog2);
+        L->n_tiles = std::max(L->Q * L->bpp, L->flow_tiles);  // partial slots for either mode
         EnsDev &E = L->ens[0];
         memset(&E, 0, sizeof(E));
         E.offset = h_ens[0].offset;
@@ -218,10 +223,11 @@ int layout_run(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t 
         if (acc >= (1ull << 31)) return fail(RNGLD_EINVAL, "too many tiles");
         L->n_tiles = static_cast<uint32_t>(acc);
     }
-    L->off_ens = 0;
-    L->off_partials = align_up(sizeof(EnsDev) * n_ens);
+    L->off_ens = kAlign;
+    L->off_partials = align_up(L->off_ens + sizeof(EnsDev) * n_ens);
     L->off_t0 = align_up(L->off_partials + static_cast<size_t>(L->P) * L->n_tiles * RNGLD_NOBS * sizeof(double));
-    L->bytes = L->off_t0 + (stride ? align_up(6 * static_cast<size_t>(n_total) * sizeof(float)) : 0);
+    L->off_progress = L->off_t0 + (stride ? align_up(6 * static_cast<size_t>(n_total) * sizeof(float)) : 0);
+    L->bytes = L->off_progress + align_up(sizeof(uint32_t) * L->flow_tiles);
     return RNGLD_OK;
 }
 
@@ -237,15 +243,83 @@ int check_run_args(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint6
 }
 
 // enqueue one ld_run call; all arguments validated
+// the dataflow LF run: returns hipSuccess when launched, hipErrorCooperativeLaunchTooLarge (or
+// another error) when it could not be; the caller then falls back to waves
+hipError_t try_lf_flow(const Gen &g, void *d_state, const RunLayout &L, uint32_t n_steps, float *d_x, float *d_v,
+                       uint64_t n_total, uint32_t stride, uint32_t t0, double *partials, uint32_t *status,
+                       uint32_t *progress, hipStream_t st) {
+    const EnsDev &E = L.ens[0];
+    const uint32_t Ct = L.flow_tiles;
+    uint32_t kmax = 0, grid = 0;
+    for (uint32_t k : {1u, 2u, 4u, 8u}) {
+        const uint32_t need = (Ct + k - 1) / k;
+        const uint32_t cap = lf_flow_max_grid(k);
+        if (cap && need <= cap) {
+            kmax = k;
+            grid = need;
+            break;
+        }
+    }
+    if (!kmax) return hipErrorCooperativeLaunchTooLarge;
+    LfFlowArgs a{};
+    a.L = lf_ring(g, d_state);
+    a.geom = lf_flow_geom(E.n, kLfFlowBlockLog2, g.ll, g.sl);
+    a.x = d_x + E.offset;
+    a.v = d_v + E.offset;
+    a.N = n_total;
+    a.n = E.n;
+    a.coef = E.coef;
+    a.n_steps = n_steps;
+    a.step_adv = static_cast<uint32_t>((4ull * E.n) % g.R);
+    a.spin_limit = 1u << 20;
+    a.stride = stride;
+    a.t0 = t0;
+    a.pstride = L.n_tiles;
+    a.progress = progress;
+    a.status = status;
+    a.partials = partials;
+    hipError_t e = launch_fill_u32(progress, Ct, 0u, st);
+    if (e != hipSuccess) return e;
+    return launch_lf_flow(a, grid, kmax, st);
+}
+
 int enqueue_run(const Gen &g, void *d_state, const RunLayout &L, const ld_tuning &t, uint64_t n_total,
                 uint32_t n_steps, float *d_x, float *d_v, const ld_obs *obs, double *d_obs, void *d_ws,
-                hipStream_t st, bool upload) {
+                hipStream_t st, bool upload, bool allow_flow = true) {
     uint8_t *ws = static_cast<uint8_t *>(d_ws);
     EnsDev *d_ens = reinterpret_cast<EnsDev *>(ws + L.off_ens);
     double *partials = reinterpret_cast<double *>(ws + L.off_partials);
     float *t0buf = reinterpret_cast<float *>(ws + L.off_t0);
+    uint32_t *status = reinterpret_cast<uint32_t *>(ws);
     const uint32_t stride = obs ? obs->stride : 0, t0 = obs ? obs->t0 : 0;
-    if (upload) RNGLD_TRY_HIP(launch_upload(d_ens, L.ens.data(), sizeof(EnsDev) * L.ens.size(), st));
+    RNGLD_TRY_HIP(launch_fill_u32(status, 1, 0u, st));
+
+    if (g.kind == RNGLD_LAGFIB && allow_flow && !t.lf_waves && g.R == g.ll + g.sl &&
+        g.R >= (4u << kLfFlowBlockLog2) && L.ens[0].n > 0) {
+        // one persistent launch for the whole run; observables are tiled by dataflow tile
+        std::vector<EnsDev> ens = L.ens;
+        ens[0].n_tiles = L.flow_tiles;
+        RNGLD_TRY_HIP(launch_upload(d_ens, ens.data(), sizeof(EnsDev), st));
+        const hipError_t e = try_lf_flow(g, d_state, L, n_steps, d_x, d_v, n_total, stride, t0, partials, status,
+                                         reinterpret_cast<uint32_t *>(ws + L.off_progress), st);
+        if (e == hipSuccess) {
+            const uint64_t count = 4ull * ens[0].n * n_steps;
+            RNGLD_TRY_HIP(launch_lf_advance(static_cast<LfHeader *>(d_state), count,
+                                            static_cast<uint32_t>(count % g.R), st));
+            if (L.P)
+                RNGLD_TRY_HIP(launch_obs_finalize(partials, L.n_tiles, L.P, d_ens, 1, d_obs, st));
+            return RNGLD_OK;
+        }
+        if (e != hipErrorCooperativeLaunchTooLarge) return fail(RNGLD_EHIP, "dataflow launch: %s", hipGetErrorString(e));
+        (void)hipGetLastError();  // the waves below take over
+    }
+    if (g.kind == RNGLD_LAGFIB) {
+        std::vector<EnsDev> ens = L.ens;
+        ens[0].n_tiles = L.Q * L.bpp;
+        RNGLD_TRY_HIP(launch_upload(d_ens, ens.data(), sizeof(EnsDev), st));
+    } else if (upload) {
+        RNGLD_TRY_HIP(launch_upload(d_ens, L.ens.data(), sizeof(EnsDev) * L.ens.size(), st));
+    }
 
     if (g.kind == RNGLD_LAGFIB) {
         const EnsDev &E = L.ens[0];
@@ -556,7 +630,7 @@ extern "C" int ld_plan_create(const rngld_cfg *cfg, void *d_state, size_t state_
     int rc = RNGLD_OK;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        rc = enqueue_run(g, d_state, L, t, n_total, n_steps, d_x, d_v, obs, d_obs, d_ws, cap, false);
+        rc = enqueue_run(g, d_state, L, t, n_total, n_steps, d_x, d_v, obs, d_obs, d_ws, cap, false, false);
         const hipError_t e2 = hipStreamEndCapture(cap, &plan->graph);
         if (rc == RNGLD_OK && e2 != hipSuccess) rc = fail(RNGLD_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
     } else {

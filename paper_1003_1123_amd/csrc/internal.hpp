@@ -6,6 +6,7 @@
 
 #include "../../include/rngld.h"
 #include "device.hpp"
+#include "lf_flow.hpp"
 
 namespace rngld {
 
@@ -76,6 +77,24 @@ struct LfLdPhase {
     float *t0buf;         // [6][N]
 };
 
+// persistent dataflow LD run over the shared lagged-Fibonacci sequence (k_lf.hip)
+struct LfFlowArgs {
+    LfRing L;
+    LfFlowGeom geom;
+    float *x, *v;         // first oscillator of the run; row stride N
+    uint64_t N;
+    uint64_t n;           // oscillators
+    LdCoef coef;
+    uint32_t n_steps;
+    uint32_t step_adv;    // (4n) mod R
+    uint32_t spin_limit;  // polls of one dependency before the run gives up
+    uint32_t stride, t0;  // observation
+    uint32_t pstride;     // row stride (tiles) of partials
+    uint32_t *progress;   // [n_ctiles]: steps completed per tile, zero before the launch
+    uint32_t *status;     // [0]: nonzero once a wait gave up (the run is then invalid)
+    double *partials;     // [P][pstride][6]
+};
+
 // ---- adjoint (k_adj.hip) ---------------------------------------------------------------------------
 struct AdjCoef {
     LdCoef f;         // forward coefficients
@@ -138,5 +157,13 @@ hipError_t launch_lf_observe(const LfLdPhase &ph0, uint32_t n_phases, uint64_t p
                              bool t0_now, hipStream_t st);
 
 constexpr int kLfLdBlock = 256;
+constexpr int kLfFlowBlockLog2 = 8;  // 256 oscillators per dataflow tile
+
+// launch the dataflow kernel with `grid` co-resident blocks of 2^kLfFlowBlockLog2 threads, each
+// owning at most kmax tiles; hipErrorCooperativeLaunchTooLarge means the grid does not fit
+hipError_t launch_lf_flow(const LfFlowArgs &a, uint32_t grid, uint32_t kmax, hipStream_t st);
+// largest co-resident grid for a kmax instance (0 if none)
+uint32_t lf_flow_max_grid(uint32_t kmax);
+hipError_t launch_fill_u32(uint32_t *dst, uint64_t count, uint32_t value, hipStream_t st);
 
 }  // namespace rngld

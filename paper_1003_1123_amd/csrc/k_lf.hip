@@ -182,6 +182,165 @@ __global__ __launch_bounds__(BLOCK) void lf_observe_kernel(LfLdPhase ph, uint32_
     block_sum6<BLOCK>(q, red, ph.partials + (static_cast<uint64_t>(point) * ph.n_tiles + blockIdx.x) * 6);
 }
 
+// ---- persistent dataflow run ----------------------------------------------------------------------
+// One cooperative launch runs every LD step.  Block g owns tiles c = g, g + G, ... of every step (a
+// tile = 256 oscillators = 1024 consecutive positions) and keeps their x, v in registers.  It
+// processes its tiles in sequence order; before a tile it waits until the tiles holding the
+// tile's sources (positions sl and ll back) have been completed, then generates the tile's 1024
+// numbers into the ring, updates its oscillators and publishes progress[c] = step + 1.
+//  * No deadlock: dependencies point to earlier positions, each block handles its tiles in
+//    position order, and all blocks are co-resident (cooperative launch), so the earliest
+//    unfinished tile can always run.
+//  * No ring hazard: with R = ll + sl, slot(p) holds p - ll - sl, whose only readers are the
+//    positions p - sl and p - ll -- exactly the sources this tile waits for.  Any schedule the
+//    flags allow therefore reproduces the sequential sequence.
+//  * Visibility across the 8 XCDs' L2 caches: the producer's agent-scope release (L2 write-back)
+//    after a block barrier, the consumer's agent-scope acquire (invalidate) before a barrier.
+//  * Every wait is bounded: after spin_limit polls, or when another block has given up, the
+//    block stops, and status[0] records the failure.
+__device__ __forceinline__ bool lf_wait_progress(uint32_t *progress, uint32_t c, uint32_t need, uint32_t *status,
+                                                 uint32_t spin_limit) {
+    uint32_t spins = 0;
+    while (__hip_atomic_load(progress + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+        if (++spins > spin_limit ||
+            __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+            __hip_atomic_store(status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return true;
+}
+
+template <int BLOCK, int KMAX>
+__global__ __launch_bounds__(BLOCK) void lf_ld_flow_kernel(LfFlowArgs a) {
+    __shared__ double red[BLOCK / 64][6];
+    __shared__ uint32_t s_abort;
+    const uint32_t G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
+    const uint32_t R = a.L.R, Ct = a.geom.n_ctiles;
+    float x[KMAX][3], v[KMAX][3], x0[KMAX][3], v0[KMAX][3];
+    uint32_t toff[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        const uint32_t c = g + k * G;
+        const uint64_t o = static_cast<uint64_t>(c) * BLOCK + tid;
+        const bool act = c < Ct && o < a.n;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            x[k][d] = act ? a.x[d * a.N + o] : 0.0f;
+            v[k][d] = act ? a.v[d * a.N + o] : 0.0f;
+            x0[k][d] = v0[k][d] = 0.0f;
+        }
+        toff[k] = static_cast<uint32_t>((4ull * BLOCK * c) % R);
+    }
+    if (tid == 0) s_abort = 0u;
+    uint32_t slot_s = a.L.hdr->slot;  // ring slot of the current step's first position
+    __syncthreads();
+    bool stop = false;
+    for (uint32_t s = 0; s < a.n_steps && !stop; ++s) {
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            const uint32_t c = g + k * G;
+            if (c >= Ct) break;
+            const uint64_t first = static_cast<uint64_t>(c) * BLOCK;
+            const uint32_t count = static_cast<uint32_t>(first + BLOCK <= a.n ? BLOCK : a.n - first);
+            if (tid == 0) {
+                const bool ok = lf_tile_sources(a.geom, s, c, count, [&](uint32_t s2, uint32_t c2) {
+                    return lf_wait_progress(a.progress, c2, s2 + 1, a.status, a.spin_limit);
+                });
+                if (!ok) s_abort = 1u;
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            __syncthreads();
+            if (s_abort) {
+                stop = true;
+                break;
+            }
+            const bool act = tid < count;
+            if (s == a.t0) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    x0[k][d] = x[k][d];
+                    v0[k][d] = v[k][d];
+                }
+            }
+            if (a.stride && s % a.stride == 0) {
+                double q[6] = {0, 0, 0, 0, 0, 0};
+                if (act) add_observables(q, x[k], v[k], x0[k], v0[k], s >= a.t0);
+                block_sum6<BLOCK>(q, red, a.partials + (static_cast<uint64_t>(s / a.stride) * a.pstride + c) * 6);
+            }
+            if (act) {
+                uint32_t slot = wrap_once(wrap_once(slot_s + toff[k], R) + 4 * tid, R);
+                uint32_t w[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    w[r] = a.L.ring[back(slot, a.L.ll, R)] + a.L.ring[back(slot, a.L.sl, R)];
+                    a.L.ring[slot] = w[r];
+                    slot = wrap_once(slot + 1, R);
+                }
+                float gf[3];
+                gaussian_forces(w[0], w[1], w[2], w[3], gf[0], gf[1], gf[2]);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) ld_update(a.coef, x[k][d], v[k][d], gf[d]);
+            }
+            __syncthreads();  // every ring write of the tile is issued before the release
+            if (tid == 0) __hip_atomic_store(a.progress + c, s + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        slot_s = wrap_once(slot_s + a.step_adv, R);
+    }
+    if (!stop && a.stride && a.n_steps % a.stride == 0) {
+        const uint32_t s = a.n_steps;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            const uint32_t c = g + k * G;
+            if (c >= Ct) break;
+            const uint64_t first = static_cast<uint64_t>(c) * BLOCK;
+            const bool act = first + tid < a.n;
+            if (s == a.t0) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    x0[k][d] = x[k][d];
+                    v0[k][d] = v[k][d];
+                }
+            }
+            double q[6] = {0, 0, 0, 0, 0, 0};
+            if (act) add_observables(q, x[k], v[k], x0[k], v0[k], s >= a.t0);
+            block_sum6<BLOCK>(q, red, a.partials + (static_cast<uint64_t>(s / a.stride) * a.pstride + c) * 6);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        const uint32_t c = g + k * G;
+        const uint64_t o = static_cast<uint64_t>(c) * BLOCK + tid;
+        if (c < Ct && o < a.n)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                a.x[d * a.N + o] = x[k][d];
+                a.v[d * a.N + o] = v[k][d];
+            }
+    }
+}
+
+__global__ __launch_bounds__(kBulkBlock) void fill_u32_kernel(uint32_t *dst, uint64_t count, uint32_t value) {
+    const uint64_t i = blockIdx.x * static_cast<uint64_t>(kBulkBlock) + threadIdx.x;
+    if (i < count) dst[i] = value;
+}
+
+template <int KMAX>
+const void *lf_flow_fn() {
+    return reinterpret_cast<const void *>(&lf_ld_flow_kernel<(1 << kLfFlowBlockLog2), KMAX>);
+}
+
+const void *lf_flow_fn_for(uint32_t kmax) {
+    switch (kmax) {
+        case 1: return lf_flow_fn<1>();
+        case 2: return lf_flow_fn<2>();
+        case 4: return lf_flow_fn<4>();
+        case 8: return lf_flow_fn<8>();
+        default: return nullptr;
+    }
+}
+
 inline dim3 grid_for(uint64_t n, int block = kBulkBlock) {
     return dim3(static_cast<unsigned>((n + block - 1) / block));
 }
@@ -235,6 +394,30 @@ hipError_t launch_lf_observe(const LfLdPhase &ph0, uint32_t n_phases, uint64_t p
     if (bpp == 0 || n_phases == 0) return hipSuccess;
     lf_observe_kernel<kLfLdBlock><<<dim3(n_phases * bpp), kLfLdBlock, 0, st>>>(ph0, bpp, phase_osc, point, t0_now);
     return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *dst, uint64_t count, uint32_t value, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    fill_u32_kernel<<<grid_for(count), kBulkBlock, 0, st>>>(dst, count, value);
+    return hipGetLastError();
+}
+
+uint32_t lf_flow_max_grid(uint32_t kmax) {
+    const void *fn = lf_flow_fn_for(kmax);
+    if (!fn) return 0;
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 1 << kLfFlowBlockLog2, 0) != hipSuccess) return 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return static_cast<uint32_t>(per_cu) * static_cast<uint32_t>(cus);
+}
+
+hipError_t launch_lf_flow(const LfFlowArgs &a, uint32_t grid, uint32_t kmax, hipStream_t st) {
+    const void *fn = lf_flow_fn_for(kmax);
+    if (!fn) return hipErrorInvalidValue;
+    LfFlowArgs copy = a;
+    void *args[] = {&copy};
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(1 << kLfFlowBlockLog2), args, 0, st);
 }
 
 }  // namespace rngld

@@ -37,7 +37,7 @@ def test_only_the_c_abi_is_exported():
 
 def test_struct_layouts_match_header():
     assert C.sizeof(R.Cfg) == 48 and C.sizeof(R.Params) == 24 and C.sizeof(R.Ensemble) == 56
-    assert C.sizeof(R.Obs) == 8 and C.sizeof(R.Tuning) == 16 and C.sizeof(R.Loss) == 16
+    assert C.sizeof(R.Obs) == 8 and C.sizeof(R.Tuning) == 20 and C.sizeof(R.Loss) == 16
     assert R.Ensemble.seed.offset == 48 and R.Ensemble.p.offset == 16
 
 
@@ -103,7 +103,7 @@ def test_run_validation_and_workspace_sizing():
     obs = R.Obs(10, 50)
     assert R.lib.ld_workspace_bytes(C.byref(c), ens, n, 1000, 100, C.byref(obs), C.byref(ws)) == R.OK
     tiles = 3 + 2  # 256-oscillator tiles
-    assert ws.value >= tiles * 11 * 6 * 8 + 6 * 1000 * 4
+    assert ws.value >= 256 + tiles * 11 * 6 * 8 + 6 * 1000 * 4
     # overlapping ensembles
     bad, nb = R.make_ensembles([(0, 600, p, 1), (500, 400, p, 2)])
     assert R.lib.ld_workspace_bytes(C.byref(c), bad, nb, 1000, 100, None, C.byref(ws)) == R.EINVAL
@@ -126,15 +126,17 @@ def test_run_validation_and_workspace_sizing():
 
 def test_tuning_roundtrip_and_validation():
     t = R.ld_get_tuning("taus")
-    assert t.astuple() == (256, 1, 0, 0)
+    assert t.astuple() == (256, 1, 0, 0, 0)
     with pytest.raises(R.RngldError):
         R.ld_set_tuning("taus", block=100)
     with pytest.raises(R.RngldError):
         R.ld_set_tuning("taus", osc_per_thread=3)
     R.ld_set_tuning("ran2", block=128, osc_per_thread=2, steps_per_launch=50, blocks_per_cu=4)
-    assert R.ld_get_tuning("ran2").astuple() == (128, 2, 50, 4)
+    assert R.ld_get_tuning("ran2").astuple() == (128, 2, 50, 4, 0)
     R.ld_set_tuning("ran2")
-    assert R.ld_get_tuning("ran2").astuple() == (256, 1, 0, 0)
+    assert R.ld_get_tuning("ran2").astuple() == (256, 1, 0, 0, 0)
+    with pytest.raises(R.RngldError):
+        R.ld_set_tuning("lf", lf_waves=2)
 
 
 def test_adjoint_sizing_and_validation():

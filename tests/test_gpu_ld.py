@@ -283,3 +283,54 @@ def test_overdamped_scheme_matches_oracle():
     assert _close(x.cpu().numpy().reshape(3, N), xr, math.sqrt(pp.kT / pp.k))[0]
     assert torch.equal(v, torch.zeros_like(v))
     del rng
+
+
+# ---------------------------------------------------------------------------------------------
+# lagged Fibonacci: persistent dataflow run vs one launch per wave
+
+@pytest.mark.parametrize("n,lags,T", [(1000, (2281, 1252), 200), (1, (2281, 1252), 2000), (3001, (9689, 5502), 150),
+                                      (257, (4423, 3004), 300), (100_000, (132049, 54454), 60)])
+def test_lf_dataflow_equals_waves_and_oracle(n, lags, T):
+    ll, sl = lags
+    pp = W.LDParams(k=1.1, gamma=0.9, kT=1.0, dt=0.01).as_f32()
+    p = _params(pp)
+    ens, n_ens = R.make_ensembles([(0, n, p, 0)])
+    stride, t0 = 10, T // 2
+    P = T // stride + 1
+    res = {}
+    for waves in (0, 1):
+        R.ld_set_tuning("lf", lf_waves=waves)
+        try:
+            cfg, st, x, v = _setup("lf", n, ll=ll, sl=sl)
+            ob = torch.zeros(P * R.NOBS, dtype=torch.float64, device="cuda")
+            ws = R.ld_run(cfg, st, ens, n_ens, n, T, x, v, R.Obs(stride, t0), ob)
+            assert R.ws_status(ws) == 0
+            res[waves] = (x, v, st, ob)
+        finally:
+            R.ld_set_tuning("lf")
+    _say("lf dataflow", n, lags, T)
+    assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])
+    assert torch.equal(res[0][2], res[1][2])
+    xo, vo, oo = orc.ld_run("lf", orc.lf_seed(1234, ll), n, T, pp.asdict(), stride=stride, t0=t0, ll=ll, sl=sl)
+    assert _close(res[0][0].cpu().numpy().reshape(3, n), xo, math.sqrt(pp.kT / pp.k))[0]
+    assert _close(res[0][1].cpu().numpy().reshape(3, n), vo, math.sqrt(pp.kT / pp.m))[0]
+    g_obs = res[0][3].cpu().numpy().reshape(P, R.NOBS)
+    assert np.all(np.abs(g_obs - oo) <= 2 * REL * (np.abs(oo) + 1.0))
+
+
+def test_lf_dataflow_resume_and_mixed_calls():
+    """Dataflow runs continue the one sequence across calls and interleave with bare draws."""
+    n, ll, sl = 2000, 2281, 1252
+    p = _params(W.LDParams())
+    ens, n_ens = R.make_ensembles([(0, n, p, 0)])
+    cfg, st, x, v = _setup("lf", n, ll=ll, sl=sl)
+    R.ld_run(cfg, st, ens, n_ens, n, 37, x, v)
+    extra = torch.empty(1001, dtype=torch.int32, device="cuda")
+    R.rng_uniform(cfg, st, 1001, extra)
+    R.ld_run(cfg, st, ens, n_ens, n, 23, x, v)
+    torch.cuda.synchronize()
+    win = orc.lf_seed(1234, ll)
+    xo, vo, _ = orc.ld_run("lf", win, n, 37, W.LDParams().as_f32().asdict(), ll=ll, sl=sl)
+    assert np.array_equal(extra.cpu().numpy().view(np.uint32), orc.lf_generate(ll, sl, win, 1001))
+    xo, vo, _ = orc.ld_run("lf", win, n, 23, W.LDParams().as_f32().asdict(), xo, vo, ll=ll, sl=sl)
+    assert _close(x.cpu().numpy().reshape(3, n), xo, 1.0)[0]
