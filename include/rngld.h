@@ -63,7 +63,8 @@ extern "C" {
  *  lf_wave     : LF wave width W, positions generated concurrently; 0 selects sl.  Rounded down
  *                to a multiple of 4.  Must satisfy 4 <= W <= sl (RNGLD_ELAG otherwise).  Results
  *                do not depend on W.
- *  lf_ring     : LF ring length R in words; 0 selects ll + W.  Must satisfy ll + W <= R < 2^31.
+ *  lf_ring     : LF ring length R in words; 0 selects ll + sl.  Must satisfy ll + W <= R < 2^31.
+ *                With R = ll + sl a fused LD run can use one persistent dataflow launch.
  */
 typedef struct rngld_cfg {
     int32_t kind;
@@ -174,8 +175,9 @@ RNGLD_API int ld_step(const rngld_cfg *cfg, void *d_state, size_t state_bytes, c
  *  obs, d_obs : optional observables, d_obs = double[n_ens][P][6], P = n_steps/stride + 1.
  *  d_ws       : workspace of ld_workspace_bytes() bytes (any alignment >= 256).  Its first four
  *               bytes are a uint32 status word: nonzero after a lagged-Fibonacci dataflow run that
- *               gave up waiting for a dependency (the run's results are then invalid); read it
- *               after synchronising the stream.
+ *               gave up waiting for a dependency (the run's results are then invalid); the next
+ *               four bytes say which lagged-Fibonacci path ran (1 = dataflow, 2 = waves).  Read
+ *               them after synchronising the stream.
  * LAGFIB supports n_ens == 1 only (one shared sequence).  The result of ensemble e equals a plain
  * run (n_ens = 1, offset 0) on that ensemble alone, bit for bit, under the same tuning.
  */

@@ -229,6 +229,15 @@ def ws_status(ws: torch.Tensor) -> int:
     return int(ws[:4].cpu().numpy().view("<u4")[0])
 
 
+LF_PATHS = {1: "dataflow", 2: "waves"}
+
+
+def ws_lf_path(ws: torch.Tensor) -> str:
+    """Which lagged-Fibonacci path the last run on this workspace took (synchronises)."""
+    torch.cuda.current_stream().synchronize()
+    return LF_PATHS.get(int(ws[4:8].cpu().numpy().view("<u4")[0]), "none")
+
+
 def ld_get_tuning(kind) -> Tuning:
     t = Tuning()
     _check(lib.ld_get_tuning(KINDS.get(kind, kind) if isinstance(kind, str) else kind, C.byref(t)), "ld_get_tuning")

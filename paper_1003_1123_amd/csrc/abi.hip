@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -42,6 +43,7 @@ int fail(int code, const char *fmt, ...) {
     } while (0)
 
 constexpr uint64_t kMaxStreams = 1ull << 38;
+constexpr uint32_t kPathDataflow = 1, kPathWaves = 2;  // workspace word 1 after an LF run
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -74,7 +76,8 @@ int check_cfg(const rngld_cfg *cfg, Gen *g) {
             uint32_t W = cfg->lf_wave ? cfg->lf_wave : sl;
             W &= ~3u;
             if (W < 4 || W > sl) return fail(RNGLD_ELAG, "wave width %u must satisfy 4 <= W <= sl = %u", W, sl);
-            const uint64_t R = cfg->lf_ring ? cfg->lf_ring : static_cast<uint64_t>(ll) + W;
+            // default ring ll + sl: enough for any wave width, and the size the dataflow run needs
+            const uint64_t R = cfg->lf_ring ? cfg->lf_ring : static_cast<uint64_t>(ll) + sl;
             if (R < static_cast<uint64_t>(ll) + W || R >= (1ull << 31))
                 return fail(RNGLD_ELAG, "ring length %llu must satisfy ll + W <= R < 2^31", (unsigned long long)R);
             g->ll = ll;
@@ -243,11 +246,19 @@ int check_run_args(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint6
 }
 
 // enqueue one ld_run call; all arguments validated
+bool debug_enabled() {
+    static const bool on = [] {
+        const char *e = getenv("RNGLD_DEBUG");
+        return e && *e && *e != '0';
+    }();
+    return on;
+}
+
 // the dataflow LF run: returns hipSuccess when launched, hipErrorCooperativeLaunchTooLarge (or
 // another error) when it could not be; the caller then falls back to waves
 hipError_t try_lf_flow(const Gen &g, void *d_state, const RunLayout &L, uint32_t n_steps, float *d_x, float *d_v,
-                       uint64_t n_total, uint32_t stride, uint32_t t0, double *partials, uint32_t *status,
-                       uint32_t *progress, hipStream_t st) {
+                       uint64_t n_total, uint32_t stride, uint32_t t0, double *partials, float *t0buf,
+                       uint32_t *status, uint32_t *progress, hipStream_t st) {
     const EnsDev &E = L.ens[0];
     const uint32_t Ct = L.flow_tiles;
     uint32_t kmax = 0, grid = 0;
@@ -260,6 +271,9 @@ hipError_t try_lf_flow(const Gen &g, void *d_state, const RunLayout &L, uint32_t
             break;
         }
     }
+    if (debug_enabled())
+        fprintf(stderr, "[rngld] LF dataflow: tiles %u, kmax %u, grid %u (caps %u/%u/%u/%u)\n", Ct, kmax, grid,
+                lf_flow_max_grid(1), lf_flow_max_grid(2), lf_flow_max_grid(4), lf_flow_max_grid(8));
     if (!kmax) return hipErrorCooperativeLaunchTooLarge;
     LfFlowArgs a{};
     a.L = lf_ring(g, d_state);
@@ -275,6 +289,7 @@ hipError_t try_lf_flow(const Gen &g, void *d_state, const RunLayout &L, uint32_t
     a.stride = stride;
     a.t0 = t0;
     a.pstride = L.n_tiles;
+    a.t0buf = t0buf;
     a.progress = progress;
     a.status = status;
     a.partials = partials;
@@ -292,17 +307,20 @@ int enqueue_run(const Gen &g, void *d_state, const RunLayout &L, const ld_tuning
     float *t0buf = reinterpret_cast<float *>(ws + L.off_t0);
     uint32_t *status = reinterpret_cast<uint32_t *>(ws);
     const uint32_t stride = obs ? obs->stride : 0, t0 = obs ? obs->t0 : 0;
-    RNGLD_TRY_HIP(launch_fill_u32(status, 1, 0u, st));
+    RNGLD_TRY_HIP(launch_fill_u32(status, 2, 0u, st));  // status, path
 
     if (g.kind == RNGLD_LAGFIB && allow_flow && !t.lf_waves && g.R == g.ll + g.sl &&
-        g.R >= (4u << kLfFlowBlockLog2) && L.ens[0].n > 0) {
+        g.sl >= (4u << kLfFlowBlockLog2) && L.ens[0].n > 0) {  // sources never inside the tile itself
         // one persistent launch for the whole run; observables are tiled by dataflow tile
         std::vector<EnsDev> ens = L.ens;
         ens[0].n_tiles = L.flow_tiles;
         RNGLD_TRY_HIP(launch_upload(d_ens, ens.data(), sizeof(EnsDev), st));
-        const hipError_t e = try_lf_flow(g, d_state, L, n_steps, d_x, d_v, n_total, stride, t0, partials, status,
+        const hipError_t e = try_lf_flow(g, d_state, L, n_steps, d_x, d_v, n_total, stride, t0, partials,
+                                         t0buf + L.ens[0].offset, status,
                                          reinterpret_cast<uint32_t *>(ws + L.off_progress), st);
+        if (debug_enabled()) fprintf(stderr, "[rngld] LF dataflow launch: %s\n", hipGetErrorString(e));
         if (e == hipSuccess) {
+            RNGLD_TRY_HIP(launch_fill_u32(status + 1, 1, kPathDataflow, st));
             const uint64_t count = 4ull * ens[0].n * n_steps;
             RNGLD_TRY_HIP(launch_lf_advance(static_cast<LfHeader *>(d_state), count,
                                             static_cast<uint32_t>(count % g.R), st));
@@ -317,6 +335,7 @@ int enqueue_run(const Gen &g, void *d_state, const RunLayout &L, const ld_tuning
         std::vector<EnsDev> ens = L.ens;
         ens[0].n_tiles = L.Q * L.bpp;
         RNGLD_TRY_HIP(launch_upload(d_ens, ens.data(), sizeof(EnsDev), st));
+        RNGLD_TRY_HIP(launch_fill_u32(status + 1, 1, kPathWaves, st));
     } else if (upload) {
         RNGLD_TRY_HIP(launch_upload(d_ens, L.ens.data(), sizeof(EnsDev) * L.ens.size(), st));
     }

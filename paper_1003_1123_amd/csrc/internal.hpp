@@ -93,6 +93,7 @@ struct LfFlowArgs {
     uint32_t *progress;   // [n_ctiles]: steps completed per tile, zero before the launch
     uint32_t *status;     // [0]: nonzero once a wait gave up (the run is then invalid)
     double *partials;     // [P][pstride][6]
+    float *t0buf;         // [6][N] x(t0), v(t0)
 };
 
 // ---- adjoint (k_adj.hip) ---------------------------------------------------------------------------

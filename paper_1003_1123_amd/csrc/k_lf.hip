@@ -194,10 +194,22 @@ __global__ __launch_bounds__(BLOCK) void lf_observe_kernel(LfLdPhase ph, uint32_
 //  * No ring hazard: with R = ll + sl, slot(p) holds p - ll - sl, whose only readers are the
 //    positions p - sl and p - ll -- exactly the sources this tile waits for.  Any schedule the
 //    flags allow therefore reproduces the sequential sequence.
-//  * Visibility across the 8 XCDs' L2 caches: the producer's agent-scope release (L2 write-back)
-//    after a block barrier, the consumer's agent-scope acquire (invalidate) before a barrier.
+//  * Visibility across the 8 XCDs' (mutually non-coherent) L2 caches: every access to the shared
+//    ring is a device-scope (agent) access, so ring stores write through to the device coherence
+//    point and ring loads read from it, never from a stale XCD L2 line.  A producer waits for its
+//    block's ring stores to complete (s_waitcnt, then a block barrier) before storing the
+//    progress flag; a consumer observes the flag before a block barrier and only then issues its
+//    ring loads.  This avoids agent-scope release/acquire fences, which write back / invalidate
+//    a whole XCD L2 each time and made every tile cost tens of microseconds.
 //  * Every wait is bounded: after spin_limit polls, or when another block has given up, the
 //    block stops, and status[0] records the failure.
+__device__ __forceinline__ uint32_t ring_load(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void ring_store(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ bool lf_wait_progress(uint32_t *progress, uint32_t c, uint32_t need, uint32_t *status,
                                                  uint32_t spin_limit) {
     uint32_t spins = 0;
@@ -214,42 +226,55 @@ __device__ __forceinline__ bool lf_wait_progress(uint32_t *progress, uint32_t c,
 
 template <int BLOCK, int KMAX>
 __global__ __launch_bounds__(BLOCK) void lf_ld_flow_kernel(LfFlowArgs a) {
+    // x, v of the block's tiles stay on chip in LDS ([tile][component][lane], conflict-free), so
+    // the register count does not grow with the tiles a block owns; x(t0), v(t0) live in t0buf
+    __shared__ float xv[KMAX][6][BLOCK];
+    __shared__ uint32_t words[4 * BLOCK];  // the current tile's numbers, in sequence order
     __shared__ double red[BLOCK / 64][6];
     __shared__ uint32_t s_abort;
+    __shared__ uint32_t s_toff[KMAX];  // (4 B c) mod R of the block's k-th tile
     const uint32_t G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
     const uint32_t R = a.L.R, Ct = a.geom.n_ctiles;
-    float x[KMAX][3], v[KMAX][3], x0[KMAX][3], v0[KMAX][3];
-    uint32_t toff[KMAX];
-#pragma unroll
+    if (tid == 0) {
+        uint32_t off = static_cast<uint32_t>((4ull * BLOCK * g) % R);
+        const uint32_t step = static_cast<uint32_t>((4ull * BLOCK * G) % R);
+        for (int k = 0; k < KMAX; ++k) {
+            s_toff[k] = off;
+            off = wrap_once(off + step, R);
+        }
+    }
     for (int k = 0; k < KMAX; ++k) {
         const uint32_t c = g + k * G;
         const uint64_t o = static_cast<uint64_t>(c) * BLOCK + tid;
         const bool act = c < Ct && o < a.n;
-#pragma unroll
         for (int d = 0; d < 3; ++d) {
-            x[k][d] = act ? a.x[d * a.N + o] : 0.0f;
-            v[k][d] = act ? a.v[d * a.N + o] : 0.0f;
-            x0[k][d] = v0[k][d] = 0.0f;
+            xv[k][d][tid] = act ? a.x[d * a.N + o] : 0.0f;
+            xv[k][3 + d][tid] = act ? a.v[d * a.N + o] : 0.0f;
         }
-        toff[k] = static_cast<uint32_t>((4ull * BLOCK * c) % R);
     }
     if (tid == 0) s_abort = 0u;
     uint32_t slot_s = a.L.hdr->slot;  // ring slot of the current step's first position
     __syncthreads();
     bool stop = false;
     for (uint32_t s = 0; s < a.n_steps && !stop; ++s) {
-#pragma unroll
         for (int k = 0; k < KMAX; ++k) {
             const uint32_t c = g + k * G;
             if (c >= Ct) break;
             const uint64_t first = static_cast<uint64_t>(c) * BLOCK;
             const uint32_t count = static_cast<uint32_t>(first + BLOCK <= a.n ? BLOCK : a.n - first);
-            if (tid == 0) {
-                const bool ok = lf_tile_sources(a.geom, s, c, count, [&](uint32_t s2, uint32_t c2) {
-                    return lf_wait_progress(a.progress, c2, s2 + 1, a.status, a.spin_limit);
+            // the first wave polls the tile's source tiles in parallel, lane i the i-th of them
+            if (tid < 64) {
+                uint32_t idx = 0, my_c = 0, my_need = 0;
+                lf_tile_sources(a.geom, s, c, count, [&](uint32_t s2, uint32_t c2) {
+                    if (idx == tid) {
+                        my_c = c2;
+                        my_need = s2 + 1;
+                    }
+                    ++idx;
+                    return true;
                 });
-                if (!ok) s_abort = 1u;
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                if (tid < idx && !lf_wait_progress(a.progress, my_c, my_need, a.status, a.spin_limit))
+                    s_abort = 1u;
             }
             __syncthreads();
             if (s_abort) {
@@ -257,66 +282,104 @@ __global__ __launch_bounds__(BLOCK) void lf_ld_flow_kernel(LfFlowArgs a) {
                 break;
             }
             const bool act = tid < count;
-            if (s == a.t0) {
+            const uint64_t o = first + tid;
+            float x[3], v[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                x[d] = xv[k][d][tid];
+                v[d] = xv[k][3 + d][tid];
+            }
+            if (a.stride && s == a.t0 && act)
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    x0[k][d] = x[k][d];
-                    v0[k][d] = v[k][d];
+                    a.t0buf[d * a.N + o] = x[d];
+                    a.t0buf[(3 + d) * a.N + o] = v[d];
                 }
-            }
             if (a.stride && s % a.stride == 0) {
                 double q[6] = {0, 0, 0, 0, 0, 0};
-                if (act) add_observables(q, x[k], v[k], x0[k], v0[k], s >= a.t0);
+                if (act) {
+                    float x0[3] = {0, 0, 0}, v0[3] = {0, 0, 0};
+                    if (s >= a.t0)
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            x0[d] = s == a.t0 ? x[d] : a.t0buf[d * a.N + o];
+                            v0[d] = s == a.t0 ? v[d] : a.t0buf[(3 + d) * a.N + o];
+                        }
+                    add_observables(q, x, v, x0, v0, s >= a.t0);
+                }
                 block_sum6<BLOCK>(q, red, a.partials + (static_cast<uint64_t>(s / a.stride) * a.pstride + c) * 6);
             }
-            if (act) {
-                uint32_t slot = wrap_once(wrap_once(slot_s + toff[k], R) + 4 * tid, R);
-                uint32_t w[4];
+            // generate the tile's 4 count numbers: lane t takes positions t + 256 r (each load and
+            // store instruction is contiguous across the wave); all loads are issued before any
+            // store, which is safe because sl >= 1024 keeps every source outside the tile
+            {
+                const uint32_t base = wrap_once(slot_s + s_toff[k], R);
+                uint32_t sa[4], sb[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    w[r] = a.L.ring[back(slot, a.L.ll, R)] + a.L.ring[back(slot, a.L.sl, R)];
-                    a.L.ring[slot] = w[r];
-                    slot = wrap_once(slot + 1, R);
+                    const uint32_t q = r * BLOCK + tid;
+                    if (q < 4 * count) {
+                        const uint32_t slot = wrap_once(base + q, R);
+                        sa[r] = ring_load(a.L.ring + back(slot, a.L.ll, R));
+                        sb[r] = ring_load(a.L.ring + back(slot, a.L.sl, R));
+                    }
                 }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const uint32_t q = r * BLOCK + tid;
+                    if (q < 4 * count) {
+                        const uint32_t w = sa[r] + sb[r];
+                        ring_store(a.L.ring + wrap_once(base + q, R), w);
+                        words[q] = w;
+                    }
+                }
+            }
+            __syncthreads();  // words[] complete: oscillator t's four words are words[4t .. 4t+3]
+            if (act) {
+                const uint32_t *w = words + 4 * tid;
                 float gf[3];
                 gaussian_forces(w[0], w[1], w[2], w[3], gf[0], gf[1], gf[2]);
 #pragma unroll
-                for (int d = 0; d < 3; ++d) ld_update(a.coef, x[k][d], v[k][d], gf[d]);
+                for (int d = 0; d < 3; ++d) {
+                    ld_update(a.coef, x[d], v[d], gf[d]);
+                    xv[k][d][tid] = x[d];
+                    xv[k][3 + d][tid] = v[d];
+                }
             }
-            __syncthreads();  // every ring write of the tile is issued before the release
-            if (tid == 0) __hip_atomic_store(a.progress + c, s + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_s_waitcnt(0);  // this wave's ring stores have completed
+            __syncthreads();                // ... and so have every other wave's
+            if (tid == 0) __hip_atomic_store(a.progress + c, s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         slot_s = wrap_once(slot_s + a.step_adv, R);
     }
     if (!stop && a.stride && a.n_steps % a.stride == 0) {
         const uint32_t s = a.n_steps;
-#pragma unroll
         for (int k = 0; k < KMAX; ++k) {
             const uint32_t c = g + k * G;
             if (c >= Ct) break;
-            const uint64_t first = static_cast<uint64_t>(c) * BLOCK;
-            const bool act = first + tid < a.n;
-            if (s == a.t0) {
+            const uint64_t o = static_cast<uint64_t>(c) * BLOCK + tid;
+            double q[6] = {0, 0, 0, 0, 0, 0};
+            if (o < a.n) {
+                float x[3], v[3], x0[3], v0[3];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    x0[k][d] = x[k][d];
-                    v0[k][d] = v[k][d];
+                    x[d] = xv[k][d][tid];
+                    v[d] = xv[k][3 + d][tid];
+                    x0[d] = s == a.t0 ? x[d] : a.t0buf[d * a.N + o];
+                    v0[d] = s == a.t0 ? v[d] : a.t0buf[(3 + d) * a.N + o];
                 }
+                add_observables(q, x, v, x0, v0, s >= a.t0);
             }
-            double q[6] = {0, 0, 0, 0, 0, 0};
-            if (act) add_observables(q, x[k], v[k], x0[k], v0[k], s >= a.t0);
             block_sum6<BLOCK>(q, red, a.partials + (static_cast<uint64_t>(s / a.stride) * a.pstride + c) * 6);
         }
     }
-#pragma unroll
     for (int k = 0; k < KMAX; ++k) {
         const uint32_t c = g + k * G;
         const uint64_t o = static_cast<uint64_t>(c) * BLOCK + tid;
         if (c < Ct && o < a.n)
-#pragma unroll
             for (int d = 0; d < 3; ++d) {
-                a.x[d * a.N + o] = x[k][d];
-                a.v[d * a.N + o] = v[k][d];
+                a.x[d * a.N + o] = xv[k][d][tid];
+                a.v[d * a.N + o] = xv[k][3 + d][tid];
             }
     }
 }

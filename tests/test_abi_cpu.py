@@ -52,7 +52,12 @@ def test_state_bytes():
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=2281, sl=1252)), C.byref(out)) == 0
     assert out.value == 64 + 4 * (2281 + 1252)
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=2281, sl=1252, wave=101)), C.byref(out)) == 0
-    assert out.value == 64 + 4 * (2281 + 100)  # wave rounded down to a multiple of 4
+    assert out.value == 64 + 4 * (2281 + 1252)  # default ring ll + sl whatever the wave width
+    assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=2281, sl=1252, wave=101, ring=2400)), C.byref(out)) == 0
+    assert out.value == 64 + 4 * 2400
+    # ring shorter than ll + W (W = 100 after rounding down to a multiple of 4)
+    assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=2281, sl=1252, wave=101, ring=2380)),
+                                   C.byref(out)) == R.ELAG
 
 
 @pytest.mark.parametrize("cfg,code", [

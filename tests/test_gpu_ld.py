@@ -305,6 +305,7 @@ def test_lf_dataflow_equals_waves_and_oracle(n, lags, T):
             ob = torch.zeros(P * R.NOBS, dtype=torch.float64, device="cuda")
             ws = R.ld_run(cfg, st, ens, n_ens, n, T, x, v, R.Obs(stride, t0), ob)
             assert R.ws_status(ws) == 0
+            assert R.ws_lf_path(ws) == ("waves" if waves else "dataflow")
             res[waves] = (x, v, st, ob)
         finally:
             R.ld_set_tuning("lf")
