@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", default="", help="comma list of generators (profiling runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device (a plain copy of known size, for scaling "
+                         "hardware byte counters)")
     return ap.parse_args()
 
 
@@ -285,6 +288,13 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration * 2**18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: %d MiB copied" % args.copy_calibration)
+        del src, dst
     kinds = tuple(k for k in (args.only.split(",") if args.only else GENERATORS) if k)
     c2 = Config2(R, W, torch, kinds)
     log("config 2: N=%d, %d steps, generators %s" % (c2.N, c2.T, ",".join(kinds)))

@@ -83,8 +83,9 @@ typedef struct rngld_cfg {
  *                (c = 0..2 Tausworthe components, 3 = LCG).                 16*S bytes.
  *  RAN2        : int32 r[35][S]: row 0 idum, 1 idum2, 2 iy, 3+t iv[t] (t = 0..31).  140*S bytes.
  *  LAGFIB      : 64-byte header { uint64 pos; uint32 slot; uint32 ll, sl, R, W; ... } followed by
- *                uint32 ring[R]; y_n lives in ring[(slot + n - pos) mod R] for the last ll
- *                positions n < pos.  pos counts values generated since rng_init.
+ *                uint64 ring[R]; y_n lives in ring[(slot + n - pos) mod R] for the last ll
+ *                positions n < pos, as (uint64)(uint32)n << 32 | y_n (value and position tag).
+ *                pos counts values generated since rng_init.  64 + 8 R bytes.
  */
 RNGLD_API int rngld_state_bytes(const rngld_cfg *cfg, size_t *bytes);
 

@@ -84,7 +84,7 @@ int check_cfg(const rngld_cfg *cfg, Gen *g) {
             g->sl = sl;
             g->W = W;
             g->R = static_cast<uint32_t>(R);
-            g->state_bytes = sizeof(LfHeader) + static_cast<size_t>(R) * 4;
+            g->state_bytes = sizeof(LfHeader) + static_cast<size_t>(R) * 8;
             return RNGLD_OK;
         }
         default:
@@ -102,7 +102,7 @@ int check_state(const Gen &g, const void *d_state, size_t state_bytes) {
 LfRing lf_ring(const Gen &g, void *d_state) {
     LfRing L;
     L.hdr = static_cast<const LfHeader *>(d_state);
-    L.ring = reinterpret_cast<uint32_t *>(static_cast<LfHeader *>(d_state) + 1);
+    L.ring = reinterpret_cast<uint64_t *>(static_cast<LfHeader *>(d_state) + 1);
     L.R = g.R;
     L.ll = g.ll;
     L.sl = g.sl;
@@ -176,12 +176,12 @@ int device_cus() {
 }
 
 // ---- ld_run plan (host-side description of one call) ------------------------------------------------
-// Workspace of ld_run: [status word | padding to 256] [EnsDev table] [partials] [x(t0), v(t0)]
-// [LF dataflow progress flags].  The layout does not depend on the device.
+// Workspace of ld_run: [status, path words | padding to 256] [EnsDev table] [partials]
+// [x(t0), v(t0)].  The layout does not depend on the device.
 struct RunLayout {
     std::vector<EnsDev> ens;
     uint32_t n_tiles = 0, P = 0;
-    size_t off_ens = 0, off_partials = 0, off_t0 = 0, off_progress = 0, bytes = 0;
+    size_t off_ens = 0, off_partials = 0, off_t0 = 0, bytes = 0;
     // LF wave structure
     uint32_t Q = 0, bpp = 0;
     uint64_t Nq = 0;
@@ -229,8 +229,7 @@ int layout_run(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t 
     L->off_ens = kAlign;
     L->off_partials = align_up(L->off_ens + sizeof(EnsDev) * n_ens);
     L->off_t0 = align_up(L->off_partials + static_cast<size_t>(L->P) * L->n_tiles * RNGLD_NOBS * sizeof(double));
-    L->off_progress = L->off_t0 + (stride ? align_up(6 * static_cast<size_t>(n_total) * sizeof(float)) : 0);
-    L->bytes = L->off_progress + align_up(sizeof(uint32_t) * L->flow_tiles);
+    L->bytes = L->off_t0 + (stride ? align_up(6 * static_cast<size_t>(n_total) * sizeof(float)) : 0);
     return RNGLD_OK;
 }
 
@@ -258,7 +257,7 @@ bool debug_enabled() {
 // another error) when it could not be; the caller then falls back to waves
 hipError_t try_lf_flow(const Gen &g, void *d_state, const RunLayout &L, uint32_t n_steps, float *d_x, float *d_v,
                        uint64_t n_total, uint32_t stride, uint32_t t0, double *partials, float *t0buf,
-                       uint32_t *status, uint32_t *progress, hipStream_t st) {
+                       uint32_t *status, hipStream_t st) {
     const EnsDev &E = L.ens[0];
     const uint32_t Ct = L.flow_tiles;
     uint32_t kmax = 0, grid = 0;
@@ -290,11 +289,8 @@ hipError_t try_lf_flow(const Gen &g, void *d_state, const RunLayout &L, uint32_t
     a.t0 = t0;
     a.pstride = L.n_tiles;
     a.t0buf = t0buf;
-    a.progress = progress;
     a.status = status;
     a.partials = partials;
-    hipError_t e = launch_fill_u32(progress, Ct, 0u, st);
-    if (e != hipSuccess) return e;
     return launch_lf_flow(a, grid, kmax, st);
 }
 
@@ -316,8 +312,7 @@ int enqueue_run(const Gen &g, void *d_state, const RunLayout &L, const ld_tuning
         ens[0].n_tiles = L.flow_tiles;
         RNGLD_TRY_HIP(launch_upload(d_ens, ens.data(), sizeof(EnsDev), st));
         const hipError_t e = try_lf_flow(g, d_state, L, n_steps, d_x, d_v, n_total, stride, t0, partials,
-                                         t0buf + L.ens[0].offset, status,
-                                         reinterpret_cast<uint32_t *>(ws + L.off_progress), st);
+                                         t0buf + L.ens[0].offset, status, st);
         if (debug_enabled()) fprintf(stderr, "[rngld] LF dataflow launch: %s\n", hipGetErrorString(e));
         if (e == hipSuccess) {
             RNGLD_TRY_HIP(launch_fill_u32(status + 1, 1, kPathDataflow, st));
@@ -360,7 +355,8 @@ int enqueue_run(const Gen &g, void *d_state, const RunLayout &L, const ld_tuning
                 const uint64_t begin = static_cast<uint64_t>(q) * L.Nq;
                 ph.osc_begin = begin;
                 ph.osc_count = static_cast<uint32_t>(std::min<uint64_t>(L.Nq, n - begin));
-                ph.off_mod = static_cast<uint32_t>((4ull * n * s + 4ull * begin) % g.R);
+                ph.pos_rel = 4ull * n * s + 4ull * begin;
+                ph.off_mod = static_cast<uint32_t>(ph.pos_rel % g.R);
                 ph.step = s;
                 ph.tile_base = q * L.bpp;
                 RNGLD_TRY_HIP(launch_lf_ld_phase(ph, st));
@@ -552,7 +548,8 @@ int ld_step(const rngld_cfg *cfg, void *d_state, size_t state_bytes, const ld_pa
         for (uint64_t q = 0; q < Q; ++q) {
             ph.osc_begin = q * Nq;
             ph.osc_count = static_cast<uint32_t>(std::min<uint64_t>(Nq, n - q * Nq));
-            ph.off_mod = static_cast<uint32_t>((4ull * q * Nq) % g.R);
+            ph.pos_rel = 4ull * q * Nq;
+            ph.off_mod = static_cast<uint32_t>(ph.pos_rel % g.R);
             RNGLD_TRY_HIP(launch_lf_ld_phase(ph, st));
         }
         RNGLD_TRY_HIP(launch_lf_advance(const_cast<LfHeader *>(ph.L.hdr), 4ull * n,

@@ -51,9 +51,10 @@ struct LfHeader {
 };
 static_assert(sizeof(LfHeader) == 64, "LfHeader layout");
 
+// ring of R 64-bit slots: low half y_n, high half the low 32 bits of n
 struct LfRing {
     const LfHeader *hdr;
-    uint32_t *ring;
+    uint64_t *ring;
     uint32_t R, ll, sl;
 };
 
@@ -63,6 +64,7 @@ struct LfLdPhase {
     LfRing L;
     uint32_t off_mod;
     uint32_t osc_count;
+    uint64_t pos_rel;     // position of the wave's first number relative to the call's first
     uint64_t osc_begin;
     uint64_t N;           // x, v and t0buf row stride
     uint64_t n_osc;       // oscillators of the run
@@ -87,10 +89,9 @@ struct LfFlowArgs {
     LdCoef coef;
     uint32_t n_steps;
     uint32_t step_adv;    // (4n) mod R
-    uint32_t spin_limit;  // polls of one dependency before the run gives up
+    uint32_t spin_limit;  // polls of one source slot before the run gives up
     uint32_t stride, t0;  // observation
     uint32_t pstride;     // row stride (tiles) of partials
-    uint32_t *progress;   // [n_ctiles]: steps completed per tile, zero before the launch
     uint32_t *status;     // [0]: nonzero once a wait gave up (the run is then invalid)
     double *partials;     // [P][pstride][6]
     float *t0buf;         // [6][N] x(t0), v(t0)

@@ -1,13 +1,19 @@
 // k_lf.hip -- additive lagged Fibonacci, one generator shared by all threads (Sec. III.C; Alg. 3).
 //
-// y_n = y_{n-ll} + y_{n-sl} mod 2^32 (Eq. 3).  The state is a ring of R >= ll + W words in device
-// memory.  A "wave" computes W <= sl consecutive positions concurrently: every source is at least
-// sl positions back, so it belongs to an earlier wave, and no write of the wave overwrites a value
-// a later reader still needs (R >= ll + W).  Waves are separated by kernel boundaries, which on
-// gfx950 also make each wave's writes visible across all XCDs' L2 caches.  This is the
-// device-wide "synchronisation at the end of each step" of Sec. III.A, at wave granularity, and
-// it reproduces the one sequential sequence for any wave width (the paper's Table I rows do not
-// satisfy its own race-free condition ll - sl > RNS N; the ring removes that condition).
+// y_n = y_{n-ll} + y_{n-sl} mod 2^32 (Eq. 3).  The state is a ring of R >= ll + W 64-bit slots in
+// device memory; slot (slot0 + n - pos) mod R holds y_n in its low half and the low 32 bits of n
+// (its "tag") in its high half, written by one 64-bit store.  The tags let a consumer recognise
+// whether a slot already holds the position it needs, which the persistent dataflow run relies on.
+//
+// Two ways to run the dependency structure (a position needs the positions sl and ll back):
+//  * waves: W <= sl consecutive positions per launch; every source is in an earlier wave; kernel
+//    boundaries order the waves and make their writes visible across the XCDs' L2 caches.  This is
+//    the device-wide "synchronisation at the end of each step" of Sec. III.A at wave granularity.
+//    (Table I rows do not satisfy the paper's race-free condition ll - sl > RNS N; the ring removes
+//    that condition.)
+//  * dataflow (fused LD runs, R = ll + sl): one persistent launch; each tile of 1024 positions
+//    waits only for the tags of its own sources (see lf_ld_flow_kernel).
+// Both reproduce the one sequential sequence exactly, for any wave width or schedule.
 #include "internal.hpp"
 
 namespace rngld {
@@ -19,9 +25,15 @@ __device__ __forceinline__ uint32_t wrap_once(uint32_t s, uint32_t R) { return s
 __device__ __forceinline__ uint32_t back(uint32_t slot, uint32_t lag, uint32_t R) {
     return slot >= lag ? slot - lag : slot + (R - lag);
 }
+__device__ __forceinline__ uint64_t pack(uint32_t value, uint32_t tag) {
+    return static_cast<uint64_t>(value) | (static_cast<uint64_t>(tag) << 32);
+}
+__device__ __forceinline__ uint32_t value_of(uint64_t s) { return static_cast<uint32_t>(s); }
+__device__ __forceinline__ uint32_t tag_of(uint64_t s) { return static_cast<uint32_t>(s >> 32); }
 
-// window y_{-ll+i} = LCG^{i+1}(x0) in slots 0..ll-1, position 0 at slot ll; other slots zero
-__global__ __launch_bounds__(kBulkBlock) void lf_seed_kernel(LfHeader *hdr, uint32_t *ring, uint32_t ll,
+// window y_{-ll+i} = LCG^{i+1}(x0) in slots 0..ll-1 (position 0 at slot ll); the other slots get
+// tags one lap back, which no position of the run will ever expect
+__global__ __launch_bounds__(kBulkBlock) void lf_seed_kernel(LfHeader *hdr, uint64_t *ring, uint32_t ll,
                                                              uint32_t sl, uint32_t R, uint32_t W, uint64_t seed) {
     const uint64_t i = blockIdx.x * static_cast<uint64_t>(kBulkBlock) + threadIdx.x;
     if (i == 0) {
@@ -35,7 +47,8 @@ __global__ __launch_bounds__(kBulkBlock) void lf_seed_kernel(LfHeader *hdr, uint
     }
     if (i >= R) return;
     const uint32_t x0 = stream_seed_word(seed, 0, 0);
-    ring[i] = i < ll ? lcg_skip(x0, i + 1) : 0u;
+    const int64_t position = static_cast<int64_t>(i) - ll - (i < ll ? 0 : static_cast<int64_t>(R));
+    ring[i] = pack(i < ll ? lcg_skip(x0, i + 1) : 0u, static_cast<uint32_t>(position));
 }
 
 // one wave of rng_uniform: out[first + t] = y_{pos0 + first + t}; sources at or after pos0 come
@@ -46,15 +59,8 @@ __global__ __launch_bounds__(kBulkBlock) void lf_uniform_phase_kernel(LfRing L, 
     if (t >= count) return;
     const uint64_t i = first + t;
     const uint32_t base = L.hdr->slot;
-    uint32_t a, b;
-    if (i >= L.ll)
-        a = out[i - L.ll];
-    else
-        a = L.ring[back(base, L.ll - static_cast<uint32_t>(i), L.R)];
-    if (i >= L.sl)
-        b = out[i - L.sl];
-    else
-        b = L.ring[back(base, L.sl - static_cast<uint32_t>(i), L.R)];
+    const uint32_t a = i >= L.ll ? out[i - L.ll] : value_of(L.ring[back(base, L.ll - static_cast<uint32_t>(i), L.R)]);
+    const uint32_t b = i >= L.sl ? out[i - L.sl] : value_of(L.ring[back(base, L.sl - static_cast<uint32_t>(i), L.R)]);
     out[i] = a + b;
 }
 
@@ -64,20 +70,22 @@ __global__ __launch_bounds__(kBulkBlock) void lf_ring_store_kernel(LfRing L, con
     const uint32_t t = blockIdx.x * kBulkBlock + threadIdx.x;
     if (t >= m) return;
     const uint32_t slot = wrap_once(wrap_once(L.hdr->slot + base_mod, L.R) + t, L.R);
-    L.ring[slot] = out[count - m + t];
+    const uint64_t i = count - m + t;
+    L.ring[slot] = pack(out[i], static_cast<uint32_t>(L.hdr->pos + i));
 }
 
-// one wave of rng_gaussian: positions off_mod + 2t, +1 (ring slots relative to pos0's slot)
+// one wave of rng_gaussian: positions first + 2t, +1 (ring slots off_mod + 2t, +1 from pos0's)
 __global__ __launch_bounds__(kBulkBlock) void lf_gauss_phase_kernel(LfRing L, float *out, uint64_t first,
                                                                     uint32_t off_mod, uint32_t pairs) {
     const uint32_t t = blockIdx.x * kBulkBlock + threadIdx.x;
     if (t >= pairs) return;
     const uint32_t s0 = wrap_once(wrap_once(L.hdr->slot + off_mod, L.R) + 2 * t, L.R);
     const uint32_t s1 = wrap_once(s0 + 1, L.R);
-    const uint32_t w0 = L.ring[back(s0, L.ll, L.R)] + L.ring[back(s0, L.sl, L.R)];
-    const uint32_t w1 = L.ring[back(s1, L.ll, L.R)] + L.ring[back(s1, L.sl, L.R)];
-    L.ring[s0] = w0;
-    L.ring[s1] = w1;
+    const uint32_t w0 = value_of(L.ring[back(s0, L.ll, L.R)]) + value_of(L.ring[back(s0, L.sl, L.R)]);
+    const uint32_t w1 = value_of(L.ring[back(s1, L.ll, L.R)]) + value_of(L.ring[back(s1, L.sl, L.R)]);
+    const uint32_t tag0 = static_cast<uint32_t>(L.hdr->pos + first + 2 * t);
+    L.ring[s0] = pack(w0, tag0);
+    L.ring[s1] = pack(w1, tag0 + 1);
     const float r = box_muller_radius(w0);
     float c, s;
     box_muller_angle(w1, c, s);
@@ -93,8 +101,8 @@ __global__ void lf_advance_kernel(LfHeader *hdr, uint64_t count, uint32_t count_
     }
 }
 
-// one phase of an LD step: thread t owns oscillator osc_begin + t and positions 4t..4t+3 of the
-// phase (Alg. 3: thread j takes y_{(j + N t) RNS + r}); the observables of the step's starting
+// one wave of an LD step: thread t owns oscillator osc_begin + t and positions 4t..4t+3 of the
+// wave (Alg. 3: thread j takes y_{(j + N t) RNS + r}); the observables of the step's starting
 // state are recorded first when the step is an observation point
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void lf_ld_phase_kernel(LfLdPhase ph) {
@@ -139,11 +147,12 @@ __global__ __launch_bounds__(BLOCK) void lf_ld_phase_kernel(LfLdPhase ph) {
         }
     const uint32_t R = ph.L.R;
     uint32_t slot = wrap_once(wrap_once(ph.L.hdr->slot + ph.off_mod, R) + 4 * t, R);
+    const uint32_t tag0 = static_cast<uint32_t>(ph.L.hdr->pos + ph.pos_rel) + 4 * t;
     uint32_t w[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        w[r] = ph.L.ring[back(slot, ph.L.ll, R)] + ph.L.ring[back(slot, ph.L.sl, R)];
-        ph.L.ring[slot] = w[r];
+        w[r] = value_of(ph.L.ring[back(slot, ph.L.ll, R)]) + value_of(ph.L.ring[back(slot, ph.L.sl, R)]);
+        ph.L.ring[slot] = pack(w[r], tag0 + r);
         slot = wrap_once(slot + 1, R);
     }
     float g[3];
@@ -156,7 +165,7 @@ __global__ __launch_bounds__(BLOCK) void lf_ld_phase_kernel(LfLdPhase ph) {
     }
 }
 
-// observables of the final state, with the same tiling as the phases (one tile per phase block)
+// observables of the final state, with the same tiling as the waves (one tile per wave block)
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void lf_observe_kernel(LfLdPhase ph, uint32_t bpp, uint64_t phase_osc,
                                                            uint32_t point, bool t0_now) {
@@ -183,45 +192,30 @@ __global__ __launch_bounds__(BLOCK) void lf_observe_kernel(LfLdPhase ph, uint32_
 }
 
 // ---- persistent dataflow run ----------------------------------------------------------------------
-// One cooperative launch runs every LD step.  Block g owns tiles c = g, g + G, ... of every step (a
-// tile = 256 oscillators = 1024 consecutive positions) and keeps their x, v in registers.  It
-// processes its tiles in sequence order; before a tile it waits until the tiles holding the
-// tile's sources (positions sl and ll back) have been completed, then generates the tile's 1024
-// numbers into the ring, updates its oscillators and publishes progress[c] = step + 1.
-//  * No deadlock: dependencies point to earlier positions, each block handles its tiles in
-//    position order, and all blocks are co-resident (cooperative launch), so the earliest
-//    unfinished tile can always run.
-//  * No ring hazard: with R = ll + sl, slot(p) holds p - ll - sl, whose only readers are the
-//    positions p - sl and p - ll -- exactly the sources this tile waits for.  Any schedule the
-//    flags allow therefore reproduces the sequential sequence.
-//  * Visibility across the 8 XCDs' (mutually non-coherent) L2 caches: every access to the shared
-//    ring is a device-scope (agent) access, so ring stores write through to the device coherence
-//    point and ring loads read from it, never from a stale XCD L2 line.  A producer waits for its
-//    block's ring stores to complete (s_waitcnt, then a block barrier) before storing the
-//    progress flag; a consumer observes the flag before a block barrier and only then issues its
-//    ring loads.  This avoids agent-scope release/acquire fences, which write back / invalidate
-//    a whole XCD L2 each time and made every tile cost tens of microseconds.
-//  * Every wait is bounded: after spin_limit polls, or when another block has given up, the
-//    block stops, and status[0] records the failure.
-__device__ __forceinline__ uint32_t ring_load(const uint32_t *p) {
+// One cooperative launch runs every LD step.  Block g owns tiles c = g, g + G, ... of every step
+// (a tile = 256 oscillators = 1024 consecutive positions) and keeps their x, v in LDS.  It handles
+// its tiles in sequence order.  For a tile, lane t takes positions t + 256 r: it loads the two
+// source slots of each, and re-loads any whose tag is not yet the expected position, until all
+// sources are present; then it stores the tile's numbers with their tags and, after an LDS
+// transpose, oscillator t's four words drive its Box-Muller forces and LD update.
+//  * No flags and no fences: a slot's tag says whether it holds the position a reader needs.
+//    Ring accesses are device-scope (agent) loads and stores, so they bypass the XCDs' mutually
+//    non-coherent L2 caches; a 64-bit slot is written and read in one access.
+//  * No ring hazard (R = ll + sl): slot(p) previously held p - ll - sl, read only by positions
+//    p - sl and p - ll.  Position p is written only after their tags were seen, and each of them
+//    was stored only after its own sources (p - ll - sl among them) had been loaded.  Symmetrically,
+//    the slots read for p can be rewritten only by p + ll and p + sl, whose producers must first
+//    see position p itself.
+//  * No deadlock: every source lies >= sl >= 1024 positions back, so outside the tile; blocks run
+//    their tiles in position order and are all co-resident (cooperative launch), so the earliest
+//    unfinished tile always has its sources and can run.
+//  * Every wait is bounded: after spin_limit polls, or once another block has given up, a lane
+//    stops waiting, status[0] is set and the run stops (its results are then invalid).
+__device__ __forceinline__ uint64_t ring_load(const uint64_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void ring_store(uint32_t *p, uint32_t v) {
+__device__ __forceinline__ void ring_store(uint64_t *p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ bool lf_wait_progress(uint32_t *progress, uint32_t c, uint32_t need, uint32_t *status,
-                                                 uint32_t spin_limit) {
-    uint32_t spins = 0;
-    while (__hip_atomic_load(progress + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-        if (++spins > spin_limit ||
-            __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-            __hip_atomic_store(status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
-        }
-        __builtin_amdgcn_s_sleep(2);
-    }
-    return true;
 }
 
 template <int BLOCK, int KMAX>
@@ -242,6 +236,7 @@ __global__ __launch_bounds__(BLOCK) void lf_ld_flow_kernel(LfFlowArgs a) {
             s_toff[k] = off;
             off = wrap_once(off + step, R);
         }
+        s_abort = 0u;
     }
     for (int k = 0; k < KMAX; ++k) {
         const uint32_t c = g + k * G;
@@ -252,8 +247,9 @@ __global__ __launch_bounds__(BLOCK) void lf_ld_flow_kernel(LfFlowArgs a) {
             xv[k][3 + d][tid] = act ? a.v[d * a.N + o] : 0.0f;
         }
     }
-    if (tid == 0) s_abort = 0u;
-    uint32_t slot_s = a.L.hdr->slot;  // ring slot of the current step's first position
+    uint32_t slot_s = a.L.hdr->slot;                        // ring slot of the step's first position
+    uint32_t tag_s = static_cast<uint32_t>(a.L.hdr->pos);  // low 32 bits of that position
+    const uint32_t tag_adv = static_cast<uint32_t>(a.geom.four_n);
     __syncthreads();
     bool stop = false;
     for (uint32_t s = 0; s < a.n_steps && !stop; ++s) {
@@ -262,95 +258,96 @@ __global__ __launch_bounds__(BLOCK) void lf_ld_flow_kernel(LfFlowArgs a) {
             if (c >= Ct) break;
             const uint64_t first = static_cast<uint64_t>(c) * BLOCK;
             const uint32_t count = static_cast<uint32_t>(first + BLOCK <= a.n ? BLOCK : a.n - first);
-            // the first wave polls the tile's source tiles in parallel, lane i the i-th of them
-            if (tid < 64) {
-                uint32_t idx = 0, my_c = 0, my_need = 0;
-                lf_tile_sources(a.geom, s, c, count, [&](uint32_t s2, uint32_t c2) {
-                    if (idx == tid) {
-                        my_c = c2;
-                        my_need = s2 + 1;
-                    }
-                    ++idx;
-                    return true;
-                });
-                if (tid < idx && !lf_wait_progress(a.progress, my_c, my_need, a.status, a.spin_limit))
-                    s_abort = 1u;
-            }
-            __syncthreads();
-            if (s_abort) {
-                stop = true;
-                break;
-            }
             const bool act = tid < count;
             const uint64_t o = first + tid;
-            float x[3], v[3];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                x[d] = xv[k][d][tid];
-                v[d] = xv[k][3 + d][tid];
-            }
-            if (a.stride && s == a.t0 && act)
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    a.t0buf[d * a.N + o] = x[d];
-                    a.t0buf[(3 + d) * a.N + o] = v[d];
-                }
-            if (a.stride && s % a.stride == 0) {
+            if (a.stride && s % a.stride == 0) {  // observables of the tile's state before this step
                 double q[6] = {0, 0, 0, 0, 0, 0};
                 if (act) {
-                    float x0[3] = {0, 0, 0}, v0[3] = {0, 0, 0};
-                    if (s >= a.t0)
+                    float x[3], v[3], x0[3] = {0, 0, 0}, v0[3] = {0, 0, 0};
 #pragma unroll
-                        for (int d = 0; d < 3; ++d) {
+                    for (int d = 0; d < 3; ++d) {
+                        x[d] = xv[k][d][tid];
+                        v[d] = xv[k][3 + d][tid];
+                        if (s >= a.t0) {
                             x0[d] = s == a.t0 ? x[d] : a.t0buf[d * a.N + o];
                             v0[d] = s == a.t0 ? v[d] : a.t0buf[(3 + d) * a.N + o];
                         }
+                    }
                     add_observables(q, x, v, x0, v0, s >= a.t0);
                 }
                 block_sum6<BLOCK>(q, red, a.partials + (static_cast<uint64_t>(s / a.stride) * a.pstride + c) * 6);
             }
-            // generate the tile's 4 count numbers: lane t takes positions t + 256 r (each load and
-            // store instruction is contiguous across the wave); all loads are issued before any
-            // store, which is safe because sl >= 1024 keeps every source outside the tile
+            if (a.stride && s == a.t0 && act)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    a.t0buf[d * a.N + o] = xv[k][d][tid];
+                    a.t0buf[(3 + d) * a.N + o] = xv[k][3 + d][tid];
+                }
+            // the tile's 4 count numbers: lane t takes positions q = t + 256 r
             {
                 const uint32_t base = wrap_once(slot_s + s_toff[k], R);
-                uint32_t sa[4], sb[4];
+                const uint32_t tag0 = tag_s + static_cast<uint32_t>(4ull * BLOCK * c);
+                uint32_t src_l[4], src_s[4];
+                uint64_t vl[4], vs[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const uint32_t q = r * BLOCK + tid;
                     if (q < 4 * count) {
                         const uint32_t slot = wrap_once(base + q, R);
-                        sa[r] = ring_load(a.L.ring + back(slot, a.L.ll, R));
-                        sb[r] = ring_load(a.L.ring + back(slot, a.L.sl, R));
+                        src_l[r] = back(slot, a.L.ll, R);
+                        src_s[r] = back(slot, a.L.sl, R);
+                        vl[r] = ring_load(a.L.ring + src_l[r]);
+                        vs[r] = ring_load(a.L.ring + src_s[r]);
                     }
                 }
+                bool ok = true;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const uint32_t q = r * BLOCK + tid;
-                    if (q < 4 * count) {
-                        const uint32_t w = sa[r] + sb[r];
-                        ring_store(a.L.ring + wrap_once(base + q, R), w);
-                        words[q] = w;
+                    if (ok && q < 4 * count) {
+                        const uint32_t want_l = tag0 + q - a.L.ll, want_s = tag0 + q - a.L.sl;
+                        uint32_t spins = 0;
+                        while (tag_of(vl[r]) != want_l || tag_of(vs[r]) != want_s) {
+                            if (++spins > a.spin_limit ||
+                                __hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                                __hip_atomic_store(a.status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                ok = false;
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
+                            if (tag_of(vl[r]) != want_l) vl[r] = ring_load(a.L.ring + src_l[r]);
+                            if (tag_of(vs[r]) != want_s) vs[r] = ring_load(a.L.ring + src_s[r]);
+                        }
+                        if (ok) {
+                            const uint32_t w = value_of(vl[r]) + value_of(vs[r]);
+                            ring_store(a.L.ring + wrap_once(base + q, R), pack(w, tag0 + q));
+                            words[q] = w;
+                        }
                     }
                 }
+                if (!ok) s_abort = 1u;
             }
             __syncthreads();  // words[] complete: oscillator t's four words are words[4t .. 4t+3]
+            if (s_abort) {
+                stop = true;
+                break;
+            }
             if (act) {
                 const uint32_t *w = words + 4 * tid;
                 float gf[3];
                 gaussian_forces(w[0], w[1], w[2], w[3], gf[0], gf[1], gf[2]);
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    ld_update(a.coef, x[d], v[d], gf[d]);
-                    xv[k][d][tid] = x[d];
-                    xv[k][3 + d][tid] = v[d];
+                    float x = xv[k][d][tid], v = xv[k][3 + d][tid];
+                    ld_update(a.coef, x, v, gf[d]);
+                    xv[k][d][tid] = x;
+                    xv[k][3 + d][tid] = v;
                 }
             }
-            __builtin_amdgcn_s_waitcnt(0);  // this wave's ring stores have completed
-            __syncthreads();                // ... and so have every other wave's
-            if (tid == 0) __hip_atomic_store(a.progress + c, s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();  // words[] is free for the next tile
         }
         slot_s = wrap_once(slot_s + a.step_adv, R);
+        tag_s += tag_adv;
     }
     if (!stop && a.stride && a.n_steps % a.stride == 0) {
         const uint32_t s = a.n_steps;
@@ -413,7 +410,7 @@ inline dim3 grid_for(uint64_t n, int block = kBulkBlock) {
 hipError_t launch_lf_seed(void *state, uint32_t ll, uint32_t sl, uint32_t R, uint32_t W, uint64_t seed,
                           hipStream_t st) {
     LfHeader *hdr = static_cast<LfHeader *>(state);
-    uint32_t *ring = reinterpret_cast<uint32_t *>(hdr + 1);
+    uint64_t *ring = reinterpret_cast<uint64_t *>(hdr + 1);
     lf_seed_kernel<<<grid_for(R), kBulkBlock, 0, st>>>(hdr, ring, ll, sl, R, W, seed);
     return hipGetLastError();
 }

@@ -50,11 +50,11 @@ def test_state_bytes():
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("taus", n_streams=1000)), C.byref(out)) == 0 and out.value == 16000
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("ran2", n_streams=1000)), C.byref(out)) == 0 and out.value == 140000
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=2281, sl=1252)), C.byref(out)) == 0
-    assert out.value == 64 + 4 * (2281 + 1252)
+    assert out.value == 64 + 8 * (2281 + 1252)
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=2281, sl=1252, wave=101)), C.byref(out)) == 0
-    assert out.value == 64 + 4 * (2281 + 1252)  # default ring ll + sl whatever the wave width
+    assert out.value == 64 + 8 * (2281 + 1252)  # default ring ll + sl whatever the wave width
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=2281, sl=1252, wave=101, ring=2400)), C.byref(out)) == 0
-    assert out.value == 64 + 4 * 2400
+    assert out.value == 64 + 8 * 2400
     # ring shorter than ll + W (W = 100 after rounding down to a multiple of 4)
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=2281, sl=1252, wave=101, ring=2380)),
                                    C.byref(out)) == R.ELAG
