@@ -26,16 +26,45 @@ sys.path.insert(0, ROOT)
 METRIC = "oscillator-steps/s fused LD+RNG; Gaussians/s; plain vs batched/adjoint"
 GENERATORS = ("taus", "ran2", "lf")
 
-# Algorithmic work per oscillator-step (the counting is explained in the design doc).
-# ALU-bound per-thread generators: lane operations of the method at one issue slot each.
-OPS_PER_OSC_STEP = {"taus": 130, "ran2": 134}
-# Lagged Fibonacci in step-synchronous waves: 4 numbers x (2 reads + 1 write) x 4 B of ring traffic
-# plus x and v read and written (6 x 4 B each way).
-LF_BYTES_PER_OSC_STEP = 4 * 12 + 48
-# MI355X: 256 CUs x 4 SIMD16 x 2.4 GHz = 3.93e13 non-packed 32-bit lane operations per second;
-# HBM3E 8 TB/s.
-ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# Work per oscillator-step (the counting is explained in the design doc).
+# Taus and Ran2 are bound by vector-ALU issue: the lane-instructions that the compiled step loop of
+# ld_run_kernel (underdamped scheme, gfx950) issues per oscillator-step, LDS accesses not counted.
+VALU_PER_OSC_STEP = {"taus": 121, "ran2": 146}
+# VALU lane-operation peak: 256 CUs x 128 lanes per clock x 2.4 GHz (the published 157.3 TFLOP/s FP32
+# vector rate counts an FMA as two flops).
+ALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
+# Lagged Fibonacci: each of the 4 numbers of an oscillator-step reads two earlier numbers and is
+# written once, 4 B each (Alg. 3); the wave path also moves x and v (6 x 4 B each way) per step.
+LF_ALGO_BYTES_PER_OSC_STEP = 4 * 12
+LF_WAVE_XV_BYTES_PER_OSC_STEP = 48
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch) at the config-2
+# workload, scaled by what the same counters read for a plain 1 GiB device copy (FETCH_SIZE 0.5 GiB:
+# factor 2; WRITE_SIZE 1 GiB: factor 1).  Valid only for the kernel sources they were taken on (the
+# SHA-256 of the listed files); otherwise the traffic is reported as null.
+COUNTER_TRAFFIC = {
+    "lf_ld_flow_kernel": {
+        "sources": ("k_lf.hip", "lf_flow.hpp", "device.hpp", "internal.hpp"),
+        "sha256": "cef1bdf38e2bea7d46ea14a80746d841c5d3bbdaea4406f1890c0f2186bcb79a",
+        "fetch_bytes": 334223410 * 1024 * 2, "write_bytes": 327220875 * 1024,
+    },
+}
+
+
+def _sources_sha(names):
+    import hashlib
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_1003_1123_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_traffic(kernel):
+    c = COUNTER_TRAFFIC.get(kernel)
+    if c is None or _sources_sha(c["sources"]) != c["sha256"]:
+        return None
+    return c["fetch_bytes"] + c["write_bytes"]
 
 
 def log(*a):
@@ -101,32 +130,42 @@ class Config2:
         return {k: self.events[k][0].elapsed_time(self.events[k][1]) for k in self.kinds}
 
 
-def roofline_entry(kind, ms_run, N, T, launches):
+def roofline_entry(kind, ms_run, N, T, lf_path=None):
+    """Roofline of one ld_run of N oscillators x T steps.  The events bracket the whole ld_run call;
+    its kernel is all but a few microseconds of it."""
     osc_steps = N * T
-    per_launch_s = ms_run / 1e3 / launches
     if kind == "lf":
-        per_launch_bytes = LF_BYTES_PER_OSC_STEP * osc_steps / launches
+        if lf_path == "dataflow":
+            kernel, launches, per_os = "lf_ld_flow_kernel", 1, LF_ALGO_BYTES_PER_OSC_STEP
+        else:
+            kernel, launches = "lf_ld_phase_kernel", 4 * T
+            per_os = LF_ALGO_BYTES_PER_OSC_STEP + LF_WAVE_XV_BYTES_PER_OSC_STEP
+        per_launch_s = ms_run / 1e3 / launches
+        per_launch_bytes = per_os * osc_steps / launches
         achieved = per_launch_bytes / per_launch_s / 1e9
         return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "lf_ld_phase_kernel",
-                "launches": launches, "avg_launch_us": per_launch_s * 1e6,
-                "algorithmic_bytes_per_launch": per_launch_bytes}
-    ops = OPS_PER_OSC_STEP[kind] * osc_steps / launches
+                "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(kernel), "kernel": kernel,
+                "lf_path": lf_path, "launches": launches, "avg_launch_us": per_launch_s * 1e6,
+                "algorithmic_bytes_per_osc_step": per_os, "algorithmic_bytes_per_launch": per_launch_bytes}
+    per_launch_s = ms_run / 1e3
+    ops = VALU_PER_OSC_STEP[kind] * osc_steps
     achieved = ops / per_launch_s / 1e12
+    kernel = "ld_run_kernel<%s>" % kind
     return {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
-            "frac": achieved / ALU_PEAK_TOPS, "traffic": None, "kernel": "ld_run_kernel<%s>" % kind,
-            "launches": launches, "avg_launch_us": per_launch_s * 1e6, "algorithmic_ops_per_launch": ops}
+            "frac": achieved / ALU_PEAK_TOPS, "traffic": counter_traffic(kernel), "kernel": kernel,
+            "launches": 1, "avg_launch_us": per_launch_s * 1e6,
+            "valu_lane_instr_per_osc_step": VALU_PER_OSC_STEP[kind], "algorithmic_ops_per_launch": ops}
 
 
 def cpu_baseline(W):
-    """The FP64 oracle on a bounded sample of config 2: N = 1e4 oscillators x 500 steps per
+    """The FP64 oracle on a bounded sample of config 2: N = 2e4 oscillators x 1000 steps per
     generator, single thread, same parameters and lags."""
     import numpy as np
     import oracle as orc
 
     c = W.C2
     p = c["params"].as_f32().asdict()
-    N, T = 10_000, 500
+    N, T = 20_000, 1000
     ll, sl = c["lf_lags"]
     total_t, total_os = 0.0, 0
     per = {}
@@ -139,7 +178,7 @@ def cpu_baseline(W):
         total_t += dt
         total_os += N * T
     return {"value": total_os / total_t, "unit": "oscillator-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "config-2 workload at N=1e4 oscillators x 500 steps per generator (3 x 5e6 "
+            "sample": "config-2 workload at N=2e4 oscillators x 1000 steps per generator (3 x 2e7 "
                       "oscillator-steps, %.1f s), FP64, one thread" % total_t,
             "per_generator": per}
 
@@ -319,10 +358,12 @@ def main():
     rooflines = {}
     for k in kinds:
         ms = acc[k] / args.steps
-        launches = 4 * c2.T if k == "lf" else 1
         per_gen[k] = {"ms_per_run": ms, "osc_steps_per_s": c2.N * c2.T / (ms / 1e3),
                       "gaussians_per_s": 3 * c2.N * c2.T / (ms / 1e3)}
-        rooflines[k] = roofline_entry(k, ms, c2.N, c2.T, launches)
+        lf_path = R.ws_lf_path(c2.ws[k]) if k == "lf" else None
+        if k == "lf":
+            per_gen[k]["lf_path"] = lf_path
+        rooflines[k] = roofline_entry(k, ms, c2.N, c2.T, lf_path)
     dominant = max(kinds, key=lambda k: acc[k])
     res = {
         "metric": METRIC, "value": value, "unit": "oscillator-steps/s", "n_gpus": 1, "steps": args.steps,

@@ -74,7 +74,8 @@ __device__ __forceinline__ void run_steps(const LdArgs &a, const LdCoef &q, uint
                                           float (&v0)[OPT][3], const bool (&act)[OPT], double (*red)[kNobs]) {
     uint32_t next_obs = 0xFFFFFFFFu;
     if (a.stride) next_obs = ((a.step_begin + a.stride - 1) / a.stride) * a.stride;
-    for (uint32_t s = a.step_begin; s < a.step_end; ++s) {
+    uint32_t s = a.step_begin;
+    while (s < a.step_end) {
         if (s == a.t0) {
 #pragma unroll
             for (int k = 0; k < OPT; ++k)
@@ -89,17 +90,22 @@ __device__ __forceinline__ void run_steps(const LdArgs &a, const LdCoef &q, uint
             record_point<BLOCK, OPT>(x, v, x0, v0, act, s >= a.t0, red, dst);
             next_obs += a.stride;
         }
+        // steps up to the next event run without any per-step test (stop > s always)
+        uint32_t stop = a.step_end < next_obs ? a.step_end : next_obs;
+        if (a.t0 > s && a.t0 < stop) stop = a.t0;
+        for (; s < stop; ++s) {
 #pragma unroll
-        for (int k = 0; k < OPT; ++k) {
-            const uint32_t w0 = g[k].next();
-            const uint32_t w1 = g[k].next();
-            const uint32_t w2 = g[k].next();
-            const uint32_t w3 = g[k].next();
-            float gx, gy, gz;
-            gaussian_forces(w0, w1, w2, w3, gx, gy, gz);
-            ld_update_s<SCHEME>(q, x[k][0], v[k][0], gx);
-            ld_update_s<SCHEME>(q, x[k][1], v[k][1], gy);
-            ld_update_s<SCHEME>(q, x[k][2], v[k][2], gz);
+            for (int k = 0; k < OPT; ++k) {
+                const uint32_t w0 = g[k].next();
+                const uint32_t w1 = g[k].next();
+                const uint32_t w2 = g[k].next();
+                const uint32_t w3 = g[k].next();
+                float gx, gy, gz;
+                gaussian_forces(w0, w1, w2, w3, gx, gy, gz);
+                ld_update_s<SCHEME>(q, x[k][0], v[k][0], gx);
+                ld_update_s<SCHEME>(q, x[k][1], v[k][1], gy);
+                ld_update_s<SCHEME>(q, x[k][2], v[k][2], gz);
+            }
         }
     }
 }
