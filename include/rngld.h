@@ -63,8 +63,9 @@ extern "C" {
  *  lf_wave     : LF wave width W, positions generated concurrently; 0 selects sl.  Rounded down
  *                to a multiple of 4.  Must satisfy 4 <= W <= sl (RNGLD_ELAG otherwise).  Results
  *                do not depend on W.
- *  lf_ring     : LF ring length R in words; 0 selects ll + sl.  Must satisfy ll + W <= R < 2^31.
- *                With R = ll + sl a fused LD run can use one persistent dataflow launch.
+ *  lf_ring     : LF ring length R in words; 0 selects 2 (ll + sl), or ll + sl when 2 (ll + sl)
+ *                reaches 2^30.  Must satisfy ll + W <= R < 2^31.  A fused LD run uses one
+ *                persistent launch when sl >= 256 and ll + sl <= R < 2^30.
  */
 typedef struct rngld_cfg {
     int32_t kind;
@@ -83,9 +84,8 @@ typedef struct rngld_cfg {
  *                (c = 0..2 Tausworthe components, 3 = LCG).                 16*S bytes.
  *  RAN2        : int32 r[35][S]: row 0 idum, 1 idum2, 2 iy, 3+t iv[t] (t = 0..31).  140*S bytes.
  *  LAGFIB      : 64-byte header { uint64 pos; uint32 slot; uint32 ll, sl, R, W; ... } followed by
- *                uint64 ring[R]; y_n lives in ring[(slot + n - pos) mod R] for the last ll
- *                positions n < pos, as (uint64)(uint32)n << 32 | y_n (value and position tag).
- *                pos counts values generated since rng_init.  64 + 8 R bytes.
+ *                uint32 ring[R]; y_n lives in ring[(slot + n - pos) mod R] for the last ll
+ *                positions n < pos.  pos counts values generated since rng_init.  64 + 4 R bytes.
  */
 RNGLD_API int rngld_state_bytes(const rngld_cfg *cfg, size_t *bytes);
 
@@ -175,10 +175,10 @@ RNGLD_API int ld_step(const rngld_cfg *cfg, void *d_state, size_t state_bytes, c
  *  d_x, d_v   : float[3][n_total]; ensembles must lie inside [0, n_total) and must not overlap.
  *  obs, d_obs : optional observables, d_obs = double[n_ens][P][6], P = n_steps/stride + 1.
  *  d_ws       : workspace of ld_workspace_bytes() bytes (any alignment >= 256).  Its first four
- *               bytes are a uint32 status word: nonzero after a lagged-Fibonacci dataflow run that
- *               gave up waiting for a dependency (the run's results are then invalid); the next
- *               four bytes say which lagged-Fibonacci path ran (1 = dataflow, 2 = waves).  Read
- *               them after synchronising the stream.
+ *               bytes are a uint32 status word: nonzero after a persistent lagged-Fibonacci run
+ *               that gave up waiting for a dependency (the run's results are then invalid); the
+ *               next four bytes say which lagged-Fibonacci path ran (1 = persistent, 2 = waves).
+ *               Read them after synchronising the stream.
  * LAGFIB supports n_ens == 1 only (one shared sequence).  The result of ensemble e equals a plain
  * run (n_ens = 1, offset 0) on that ensemble alone, bit for bit, under the same tuning.
  */
@@ -200,8 +200,8 @@ typedef struct ld_tuning {
     uint32_t osc_per_thread;
     uint32_t steps_per_launch;
     uint32_t blocks_per_cu;
-    uint32_t lf_waves; /* LAGFIB only: 0 = one persistent dataflow launch when the ring is exactly
-                          ll + sl words (lf_wave = sl), 1 = one launch per wave */
+    uint32_t lf_waves; /* LAGFIB only: 0 = one persistent launch when the lags and ring allow it
+                          (see lf_ring), 1 = one launch per wave */
 } ld_tuning;
 
 /* Tuning used by ld_run for a generator kind (process-wide; default {256, 1, 0, 0, 0}). */

@@ -76,15 +76,17 @@ int check_cfg(const rngld_cfg *cfg, Gen *g) {
             uint32_t W = cfg->lf_wave ? cfg->lf_wave : sl;
             W &= ~3u;
             if (W < 4 || W > sl) return fail(RNGLD_ELAG, "wave width %u must satisfy 4 <= W <= sl = %u", W, sl);
-            // default ring ll + sl: enough for any wave width, and the size the dataflow run needs
-            const uint64_t R = cfg->lf_ring ? cfg->lf_ring : static_cast<uint64_t>(ll) + sl;
+            // default ring 2 (ll + sl) (ll + sl when that reaches 2^30): enough for any wave width and
+            // for the persistent LD run with slack between its producers and consumers
+            const uint64_t twice = 2 * (static_cast<uint64_t>(ll) + sl);
+            const uint64_t R = cfg->lf_ring ? cfg->lf_ring : (twice < (1ull << 30) ? twice : static_cast<uint64_t>(ll) + sl);
             if (R < static_cast<uint64_t>(ll) + W || R >= (1ull << 31))
                 return fail(RNGLD_ELAG, "ring length %llu must satisfy ll + W <= R < 2^31", (unsigned long long)R);
             g->ll = ll;
             g->sl = sl;
             g->W = W;
             g->R = static_cast<uint32_t>(R);
-            g->state_bytes = sizeof(LfHeader) + static_cast<size_t>(R) * 8;
+            g->state_bytes = sizeof(LfHeader) + static_cast<size_t>(R) * 4;
             return RNGLD_OK;
         }
         default:
@@ -102,7 +104,7 @@ int check_state(const Gen &g, const void *d_state, size_t state_bytes) {
 LfRing lf_ring(const Gen &g, void *d_state) {
     LfRing L;
     L.hdr = static_cast<const LfHeader *>(d_state);
-    L.ring = reinterpret_cast<uint64_t *>(static_cast<LfHeader *>(d_state) + 1);
+    L.ring = reinterpret_cast<uint32_t *>(static_cast<LfHeader *>(d_state) + 1);
     L.R = g.R;
     L.ll = g.ll;
     L.sl = g.sl;
@@ -185,8 +187,9 @@ struct RunLayout {
     // LF wave structure
     uint32_t Q = 0, bpp = 0;
     uint64_t Nq = 0;
-    // LF dataflow structure
+    // LF persistent run: 64-oscillator tiles, progress words
     uint32_t flow_tiles = 0;
+    size_t off_flags = 0;
 };
 
 int layout_run(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total, uint32_t n_steps,
@@ -201,7 +204,7 @@ int layout_run(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t 
         L->Q = n ? static_cast<uint32_t>((n + nmax - 1) / nmax) : 0;
         L->Nq = L->Q ? (n + L->Q - 1) / L->Q : 0;
         L->bpp = static_cast<uint32_t>((L->Nq + kLfLdBlock - 1) / kLfLdBlock);
-        L->flow_tiles = static_cast<uint32_t>((n + (1u << kLfFlowBlockLog2) - 1) >> kLfFlowBlockLog2);
+        L->flow_tiles = static_cast<uint32_t>((n + 63) / 64);
         L->n_tiles = std::max(L->Q * L->bpp, L->flow_tiles);  // partial slots for either mode
         EnsDev &E = L->ens[0];
         memset(&E, 0, sizeof(E));
@@ -230,6 +233,10 @@ int layout_run(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t 
     L->off_partials = align_up(L->off_ens + sizeof(EnsDev) * n_ens);
     L->off_t0 = align_up(L->off_partials + static_cast<size_t>(L->P) * L->n_tiles * RNGLD_NOBS * sizeof(double));
     L->bytes = L->off_t0 + (stride ? align_up(6 * static_cast<size_t>(n_total) * sizeof(float)) : 0);
+    if (g.kind == RNGLD_LAGFIB) {  // producer and consumer progress words
+        L->off_flags = L->bytes;
+        L->bytes += align_up(2 * static_cast<size_t>(kLfFlowMaxWaves) * kLfFlagStride * sizeof(uint32_t));
+    }
     return RNGLD_OK;
 }
 
@@ -255,43 +262,74 @@ bool debug_enabled() {
 
 // the dataflow LF run: returns hipSuccess when launched, hipErrorCooperativeLaunchTooLarge (or
 // another error) when it could not be; the caller then falls back to waves
-hipError_t try_lf_flow(const Gen &g, void *d_state, const RunLayout &L, uint32_t n_steps, float *d_x, float *d_v,
-                       uint64_t n_total, uint32_t stride, uint32_t t0, double *partials, float *t0buf,
-                       uint32_t *status, hipStream_t st) {
+// The persistent producer/consumer LF run, if this run fits it: returns 1 when launched, 0 when the
+// wave path must run instead, an RNGLD error otherwise.
+int try_lf_flow(const Gen &g, void *d_state, const RunLayout &L, uint32_t n_steps, float *d_x, float *d_v,
+                uint64_t n_total, uint32_t stride, uint32_t t0, double *partials, float *t0buf, uint32_t *flags,
+                uint32_t *status, hipStream_t st) {
     const EnsDev &E = L.ens[0];
-    const uint32_t Ct = L.flow_tiles;
-    uint32_t kmax = 0, grid = 0;
-    for (uint32_t k : {1u, 2u, 4u, 8u}) {
-        const uint32_t need = (Ct + k - 1) / k;
-        const uint32_t cap = lf_flow_max_grid(k);
-        if (cap && need <= cap) {
-            kmax = k;
-            grid = need;
+    const uint64_t n = E.n;
+    if (n == 0 || g.sl < 256 || g.R >= (1u << 30)) return 0;
+    // producers advance one link (sl positions) at a time; the ring must keep the readers of what
+    // they overwrite behind them
+    if (g.R < static_cast<uint64_t>(g.ll) + g.sl || g.R < static_cast<uint64_t>(g.sl) + 255) return 0;
+    const uint64_t Ptot = 4ull * n * n_steps;
+    if ((Ptot + g.sl - 1) / g.sl >= (1ull << 31)) return 0;
+    const int cus = device_cus();
+    if (cus <= 0) return fail(RNGLD_EHIP, "cannot query the compute-unit count");
+    const uint32_t wpb = kLfFlowBlock / 64;
+    // producer waves per block: slices of at most kLfFlowSliceMax offsets cover a link
+    uint32_t np = 1;
+    while (np < wpb - 1 && static_cast<uint64_t>(np) * cus * kLfFlowSliceMax < g.sl) ++np;
+    if (static_cast<uint64_t>(np) * cus * kLfFlowSliceMax < g.sl) return 0;
+    const uint32_t Gp = np * static_cast<uint32_t>(cus), Gc = (wpb - np) * static_cast<uint32_t>(cus);
+    if (Gp > kLfFlowMaxWaves || Gc > kLfFlowMaxWaves) return 0;
+    uint32_t slice_log2 = 6;
+    while ((static_cast<uint64_t>(Gp) << slice_log2) < g.sl) ++slice_log2;
+    const LfFlowGeom geom = lf_flow_geom(n, n_steps, g.ll, g.sl, g.R, slice_log2, Gc);
+    uint32_t kc = 0;
+    for (uint32_t k : {1u, 2u, 4u, 8u})
+        if (geom.Kc <= k) {
+            kc = k;
             break;
         }
-    }
+    if (!kc || static_cast<uint64_t>(n_steps + 1) * geom.Kc >= (1ull << 32)) return 0;
+    const size_t lds = static_cast<size_t>(wpb - np) * (geom.Kc * 384u + 256u) * sizeof(float);
+    if (lds > 160 * 1024) return 0;
     if (debug_enabled())
-        fprintf(stderr, "[rngld] LF dataflow: tiles %u, kmax %u, grid %u (caps %u/%u/%u/%u)\n", Ct, kmax, grid,
-                lf_flow_max_grid(1), lf_flow_max_grid(2), lf_flow_max_grid(4), lf_flow_max_grid(8));
-    if (!kmax) return hipErrorCooperativeLaunchTooLarge;
+        fprintf(stderr, "[rngld] LF persistent run: %d blocks, %u producer + %u consumer waves each, slice %u, "
+                        "%u tiles per consumer (kc %u), LDS %zu\n",
+                cus, np, wpb - np, 1u << slice_log2, geom.Kc, kc, lds);
     LfFlowArgs a{};
     a.L = lf_ring(g, d_state);
-    a.geom = lf_flow_geom(E.n, kLfFlowBlockLog2, g.ll, g.sl);
+    a.geom = geom;
     a.x = d_x + E.offset;
     a.v = d_v + E.offset;
+    a.t0buf = t0buf;
+    a.partials = partials;
+    a.prod = flags;
+    a.cons = flags + static_cast<size_t>(kLfFlowMaxWaves) * kLfFlagStride;
+    a.status = status;
     a.N = n_total;
-    a.n = E.n;
+    a.n = n;
     a.coef = E.coef;
     a.n_steps = n_steps;
-    a.step_adv = static_cast<uint32_t>((4ull * E.n) % g.R);
-    a.spin_limit = 1u << 20;
     a.stride = stride;
     a.t0 = t0;
     a.pstride = L.n_tiles;
-    a.t0buf = t0buf;
-    a.status = status;
-    a.partials = partials;
-    return launch_lf_flow(a, grid, kmax, st);
+    a.spin_limit = 1u << 20;
+    a.np = np;
+    a.step_adv = static_cast<uint32_t>((4ull * n) % g.R);
+    RNGLD_TRY_HIP(launch_fill_u32(a.prod, static_cast<uint64_t>(Gp) * kLfFlagStride, 0u, st));
+    RNGLD_TRY_HIP(launch_fill_u32(a.cons, static_cast<uint64_t>(Gc) * kLfFlagStride, 0u, st));
+    const hipError_t e = launch_lf_flow(a, static_cast<uint32_t>(cus), kc, static_cast<uint32_t>(lds), st);
+    if (debug_enabled()) fprintf(stderr, "[rngld] LF persistent launch: %s\n", hipGetErrorString(e));
+    if (e == hipErrorCooperativeLaunchTooLarge) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    if (e != hipSuccess) return fail(RNGLD_EHIP, "persistent LF launch: %s", hipGetErrorString(e));
+    return 1;
 }
 
 int enqueue_run(const Gen &g, void *d_state, const RunLayout &L, const ld_tuning &t, uint64_t n_total,
@@ -305,16 +343,16 @@ int enqueue_run(const Gen &g, void *d_state, const RunLayout &L, const ld_tuning
     const uint32_t stride = obs ? obs->stride : 0, t0 = obs ? obs->t0 : 0;
     RNGLD_TRY_HIP(launch_fill_u32(status, 2, 0u, st));  // status, path
 
-    if (g.kind == RNGLD_LAGFIB && allow_flow && !t.lf_waves && g.R == g.ll + g.sl &&
-        g.sl >= (4u << kLfFlowBlockLog2) && L.ens[0].n > 0) {  // sources never inside the tile itself
-        // one persistent launch for the whole run; observables are tiled by dataflow tile
+    if (g.kind == RNGLD_LAGFIB && allow_flow && !t.lf_waves) {
+        // one persistent launch for the whole run; observables are tiled by 64-oscillator tile
         std::vector<EnsDev> ens = L.ens;
         ens[0].n_tiles = L.flow_tiles;
         RNGLD_TRY_HIP(launch_upload(d_ens, ens.data(), sizeof(EnsDev), st));
-        const hipError_t e = try_lf_flow(g, d_state, L, n_steps, d_x, d_v, n_total, stride, t0, partials,
-                                         t0buf + L.ens[0].offset, status, st);
-        if (debug_enabled()) fprintf(stderr, "[rngld] LF dataflow launch: %s\n", hipGetErrorString(e));
-        if (e == hipSuccess) {
+        uint32_t *flags = reinterpret_cast<uint32_t *>(ws + L.off_flags);
+        const int r = try_lf_flow(g, d_state, L, n_steps, d_x, d_v, n_total, stride, t0, partials,
+                                  t0buf + L.ens[0].offset, flags, status, st);
+        if (r < 0) return r;
+        if (r == 1) {
             RNGLD_TRY_HIP(launch_fill_u32(status + 1, 1, kPathDataflow, st));
             const uint64_t count = 4ull * ens[0].n * n_steps;
             RNGLD_TRY_HIP(launch_lf_advance(static_cast<LfHeader *>(d_state), count,
@@ -323,8 +361,6 @@ int enqueue_run(const Gen &g, void *d_state, const RunLayout &L, const ld_tuning
                 RNGLD_TRY_HIP(launch_obs_finalize(partials, L.n_tiles, L.P, d_ens, 1, d_obs, st));
             return RNGLD_OK;
         }
-        if (e != hipErrorCooperativeLaunchTooLarge) return fail(RNGLD_EHIP, "dataflow launch: %s", hipGetErrorString(e));
-        (void)hipGetLastError();  // the waves below take over
     }
     if (g.kind == RNGLD_LAGFIB) {
         std::vector<EnsDev> ens = L.ens;

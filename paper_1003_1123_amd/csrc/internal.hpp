@@ -51,10 +51,10 @@ struct LfHeader {
 };
 static_assert(sizeof(LfHeader) == 64, "LfHeader layout");
 
-// ring of R 64-bit slots: low half y_n, high half the low 32 bits of n
+// ring of R 32-bit words: slot (hdr->slot + n - hdr->pos) mod R holds y_n
 struct LfRing {
     const LfHeader *hdr;
-    uint64_t *ring;
+    uint32_t *ring;
     uint32_t R, ll, sl;
 };
 
@@ -80,21 +80,25 @@ struct LfLdPhase {
 };
 
 // persistent dataflow LD run over the shared lagged-Fibonacci sequence (k_lf.hip)
+// the persistent producer/consumer LD run (roles and waits: lf_flow.hpp)
 struct LfFlowArgs {
     LfRing L;
     LfFlowGeom geom;
-    float *x, *v;         // first oscillator of the run; row stride N
+    float *x, *v;          // first oscillator of the run; row stride N
+    float *t0buf;          // [6][N] x(t0), v(t0)
+    double *partials;      // [P][pstride][6], one row entry per 64-oscillator tile
+    uint32_t *prod;        // [producer wave * kLfFlagStride] links done, zero at launch
+    uint32_t *cons;        // [consumer wave * kLfFlagStride] tiles done (Kc per step), zero at launch
+    uint32_t *status;      // [0]: nonzero once a wait gave up (the run is then invalid)
     uint64_t N;
-    uint64_t n;           // oscillators
+    uint64_t n;            // oscillators
     LdCoef coef;
     uint32_t n_steps;
-    uint32_t step_adv;    // (4n) mod R
-    uint32_t spin_limit;  // polls of one source slot before the run gives up
-    uint32_t stride, t0;  // observation
-    uint32_t pstride;     // row stride (tiles) of partials
-    uint32_t *status;     // [0]: nonzero once a wait gave up (the run is then invalid)
-    double *partials;     // [P][pstride][6]
-    float *t0buf;         // [6][N] x(t0), v(t0)
+    uint32_t stride, t0;   // observation
+    uint32_t pstride;
+    uint32_t spin_limit;   // polls of one wait before the run gives up
+    uint32_t np;           // producer waves per block: the block's first np waves
+    uint32_t step_adv;     // (4n) mod R
 };
 
 // ---- adjoint (k_adj.hip) ---------------------------------------------------------------------------
@@ -159,13 +163,13 @@ hipError_t launch_lf_observe(const LfLdPhase &ph0, uint32_t n_phases, uint64_t p
                              bool t0_now, hipStream_t st);
 
 constexpr int kLfLdBlock = 256;
-constexpr int kLfFlowBlockLog2 = 8;  // 256 oscillators per dataflow tile
-
-// launch the dataflow kernel with `grid` co-resident blocks of 2^kLfFlowBlockLog2 threads, each
-// owning at most kmax tiles; hipErrorCooperativeLaunchTooLarge means the grid does not fit
-hipError_t launch_lf_flow(const LfFlowArgs &a, uint32_t grid, uint32_t kmax, hipStream_t st);
-// largest co-resident grid for a kmax instance (0 if none)
-uint32_t lf_flow_max_grid(uint32_t kmax);
+constexpr int kLfFlowBlock = 1024;          // 16 waves per block, one block per CU
+constexpr int kLfFlowSliceMax = 1024;       // producer offsets per link (16 per lane)
+constexpr uint32_t kLfFlowMaxWaves = 8192;  // progress words reserved per role
+constexpr uint32_t kLfFlagStride = 32;       // words between progress words: one 128-byte line each
+// launch the producer/consumer kernel for consumer waves of up to kc tiles each; `lds` bytes of
+// dynamic LDS per block.  hipErrorCooperativeLaunchTooLarge if `grid` blocks cannot be co-resident.
+hipError_t launch_lf_flow(const LfFlowArgs &a, uint32_t grid, uint32_t kc, uint32_t lds, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *dst, uint64_t count, uint32_t value, hipStream_t st);
 
 }  // namespace rngld

@@ -1,9 +1,7 @@
 // k_lf.hip -- additive lagged Fibonacci, one generator shared by all threads (Sec. III.C; Alg. 3).
 //
-// y_n = y_{n-ll} + y_{n-sl} mod 2^32 (Eq. 3).  The state is a ring of R >= ll + W 64-bit slots in
-// device memory; slot (slot0 + n - pos) mod R holds y_n in its low half and the low 32 bits of n
-// (its "tag") in its high half, written by one 64-bit store.  The tags let a consumer recognise
-// whether a slot already holds the position it needs, which the persistent dataflow run relies on.
+// y_n = y_{n-ll} + y_{n-sl} mod 2^32 (Eq. 3).  The state is a ring of R >= ll + W 32-bit words in
+// device memory; slot (slot0 + n - pos) mod R holds y_n.
 //
 // Two ways to run the dependency structure (a position needs the positions sl and ll back):
 //  * waves: W <= sl consecutive positions per launch; every source is in an earlier wave; kernel
@@ -11,8 +9,9 @@
 //    the device-wide "synchronisation at the end of each step" of Sec. III.A at wave granularity.
 //    (Table I rows do not satisfy the paper's race-free condition ll - sl > RNS N; the ring removes
 //    that condition.)
-//  * dataflow (fused LD runs, R = ll + sl): one persistent launch; each tile of 1024 positions
-//    waits only for the tags of its own sources (see lf_ld_flow_kernel).
+//  * producer/consumer (fused LD runs): one persistent launch in which producer waves extend the
+//    sequence slice by slice and consumer waves drive the oscillators, synchronised by progress
+//    words (lf_flow.hpp; lf_pc_kernel below).
 // Both reproduce the one sequential sequence exactly, for any wave width or schedule.
 #include "internal.hpp"
 
@@ -25,15 +24,9 @@ __device__ __forceinline__ uint32_t wrap_once(uint32_t s, uint32_t R) { return s
 __device__ __forceinline__ uint32_t back(uint32_t slot, uint32_t lag, uint32_t R) {
     return slot >= lag ? slot - lag : slot + (R - lag);
 }
-__device__ __forceinline__ uint64_t pack(uint32_t value, uint32_t tag) {
-    return static_cast<uint64_t>(value) | (static_cast<uint64_t>(tag) << 32);
-}
-__device__ __forceinline__ uint32_t value_of(uint64_t s) { return static_cast<uint32_t>(s); }
-__device__ __forceinline__ uint32_t tag_of(uint64_t s) { return static_cast<uint32_t>(s >> 32); }
-
-// window y_{-ll+i} = LCG^{i+1}(x0) in slots 0..ll-1 (position 0 at slot ll); the other slots get
-// tags one lap back, which no position of the run will ever expect
-__global__ __launch_bounds__(kBulkBlock) void lf_seed_kernel(LfHeader *hdr, uint64_t *ring, uint32_t ll,
+// window y_{-ll+i} = LCG^{i+1}(x0) in slots 0..ll-1 (position 0 at slot ll); the other slots are
+// cleared (no position of a run ever reads them before writing them)
+__global__ __launch_bounds__(kBulkBlock) void lf_seed_kernel(LfHeader *hdr, uint32_t *ring, uint32_t ll,
                                                              uint32_t sl, uint32_t R, uint32_t W, uint64_t seed) {
     const uint64_t i = blockIdx.x * static_cast<uint64_t>(kBulkBlock) + threadIdx.x;
     if (i == 0) {
@@ -47,8 +40,7 @@ __global__ __launch_bounds__(kBulkBlock) void lf_seed_kernel(LfHeader *hdr, uint
     }
     if (i >= R) return;
     const uint32_t x0 = stream_seed_word(seed, 0, 0);
-    const int64_t position = static_cast<int64_t>(i) - ll - (i < ll ? 0 : static_cast<int64_t>(R));
-    ring[i] = pack(i < ll ? lcg_skip(x0, i + 1) : 0u, static_cast<uint32_t>(position));
+    ring[i] = i < ll ? lcg_skip(x0, i + 1) : 0u;
 }
 
 // one wave of rng_uniform: out[first + t] = y_{pos0 + first + t}; sources at or after pos0 come
@@ -59,8 +51,8 @@ __global__ __launch_bounds__(kBulkBlock) void lf_uniform_phase_kernel(LfRing L, 
     if (t >= count) return;
     const uint64_t i = first + t;
     const uint32_t base = L.hdr->slot;
-    const uint32_t a = i >= L.ll ? out[i - L.ll] : value_of(L.ring[back(base, L.ll - static_cast<uint32_t>(i), L.R)]);
-    const uint32_t b = i >= L.sl ? out[i - L.sl] : value_of(L.ring[back(base, L.sl - static_cast<uint32_t>(i), L.R)]);
+    const uint32_t a = i >= L.ll ? out[i - L.ll] : L.ring[back(base, L.ll - static_cast<uint32_t>(i), L.R)];
+    const uint32_t b = i >= L.sl ? out[i - L.sl] : L.ring[back(base, L.sl - static_cast<uint32_t>(i), L.R)];
     out[i] = a + b;
 }
 
@@ -71,7 +63,7 @@ __global__ __launch_bounds__(kBulkBlock) void lf_ring_store_kernel(LfRing L, con
     if (t >= m) return;
     const uint32_t slot = wrap_once(wrap_once(L.hdr->slot + base_mod, L.R) + t, L.R);
     const uint64_t i = count - m + t;
-    L.ring[slot] = pack(out[i], static_cast<uint32_t>(L.hdr->pos + i));
+    L.ring[slot] = out[i];
 }
 
 // one wave of rng_gaussian: positions first + 2t, +1 (ring slots off_mod + 2t, +1 from pos0's)
@@ -81,11 +73,10 @@ __global__ __launch_bounds__(kBulkBlock) void lf_gauss_phase_kernel(LfRing L, fl
     if (t >= pairs) return;
     const uint32_t s0 = wrap_once(wrap_once(L.hdr->slot + off_mod, L.R) + 2 * t, L.R);
     const uint32_t s1 = wrap_once(s0 + 1, L.R);
-    const uint32_t w0 = value_of(L.ring[back(s0, L.ll, L.R)]) + value_of(L.ring[back(s0, L.sl, L.R)]);
-    const uint32_t w1 = value_of(L.ring[back(s1, L.ll, L.R)]) + value_of(L.ring[back(s1, L.sl, L.R)]);
-    const uint32_t tag0 = static_cast<uint32_t>(L.hdr->pos + first + 2 * t);
-    L.ring[s0] = pack(w0, tag0);
-    L.ring[s1] = pack(w1, tag0 + 1);
+    const uint32_t w0 = L.ring[back(s0, L.ll, L.R)] + L.ring[back(s0, L.sl, L.R)];
+    const uint32_t w1 = L.ring[back(s1, L.ll, L.R)] + L.ring[back(s1, L.sl, L.R)];
+    L.ring[s0] = w0;
+    L.ring[s1] = w1;
     const float r = box_muller_radius(w0);
     float c, s;
     box_muller_angle(w1, c, s);
@@ -147,12 +138,11 @@ __global__ __launch_bounds__(BLOCK) void lf_ld_phase_kernel(LfLdPhase ph) {
         }
     const uint32_t R = ph.L.R;
     uint32_t slot = wrap_once(wrap_once(ph.L.hdr->slot + ph.off_mod, R) + 4 * t, R);
-    const uint32_t tag0 = static_cast<uint32_t>(ph.L.hdr->pos + ph.pos_rel) + 4 * t;
     uint32_t w[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        w[r] = value_of(ph.L.ring[back(slot, ph.L.ll, R)]) + value_of(ph.L.ring[back(slot, ph.L.sl, R)]);
-        ph.L.ring[slot] = pack(w[r], tag0 + r);
+        w[r] = ph.L.ring[back(slot, ph.L.ll, R)] + ph.L.ring[back(slot, ph.L.sl, R)];
+        ph.L.ring[slot] = w[r];
         slot = wrap_once(slot + 1, R);
     }
     float g[3];
@@ -191,193 +181,450 @@ __global__ __launch_bounds__(BLOCK) void lf_observe_kernel(LfLdPhase ph, uint32_
     block_sum6<BLOCK>(q, red, ph.partials + (static_cast<uint64_t>(point) * ph.n_tiles + blockIdx.x) * 6);
 }
 
-// ---- persistent dataflow run ----------------------------------------------------------------------
-// One cooperative launch runs every LD step.  Block g owns tiles c = g, g + G, ... of every step
-// (a tile = 256 oscillators = 1024 consecutive positions) and keeps their x, v in LDS.  It handles
-// its tiles in sequence order.  For a tile, lane t takes positions t + 256 r: it loads the two
-// source slots of each, and re-loads any whose tag is not yet the expected position, until all
-// sources are present; then it stores the tile's numbers with their tags and, after an LDS
-// transpose, oscillator t's four words drive its Box-Muller forces and LD update.
-//  * No flags and no fences: a slot's tag says whether it holds the position a reader needs.
-//    Ring accesses are device-scope (agent) loads and stores, so they bypass the XCDs' mutually
-//    non-coherent L2 caches; a 64-bit slot is written and read in one access.
-//  * No ring hazard (R = ll + sl): slot(p) previously held p - ll - sl, read only by positions
-//    p - sl and p - ll.  Position p is written only after their tags were seen, and each of them
-//    was stored only after its own sources (p - ll - sl among them) had been loaded.  Symmetrically,
-//    the slots read for p can be rewritten only by p + ll and p + sl, whose producers must first
-//    see position p itself.
-//  * No deadlock: every source lies >= sl >= 1024 positions back, so outside the tile; blocks run
-//    their tiles in position order and are all co-resident (cooperative launch), so the earliest
-//    unfinished tile always has its sources and can run.
-//  * Every wait is bounded: after spin_limit polls, or once another block has given up, a lane
-//    stops waiting, status[0] is set and the run stops (its results are then invalid).
-__device__ __forceinline__ uint64_t ring_load(const uint64_t *p) {
+// ---- persistent producer/consumer run ----------------------------------------------------------
+// One cooperative launch of one 1024-thread block per CU runs every LD step.  The first np waves of
+// a block are producers, the others consumers (roles, waits and the no-deadlock argument:
+// lf_flow.hpp).  No block-wide barrier: every wave works on its own.
+//  * Ring words and progress words are read and written with device-scope (agent) atomics, which
+//    bypass the XCDs' mutually non-coherent L2 caches.  A producer waits for its ring stores to
+//    complete (s_waitcnt) before it stores its progress word; a reader issues its ring loads only
+//    after the progress words it waits for have been seen.  No cache-wide release or acquire fence
+//    is needed.
+//  * A consumer publishes a tile only after its loads have returned, so the slots may then be
+//    rewritten.
+//  * Every wait is bounded: after spin_limit polls, or once another wave has given up, the wave
+//    stops, status[0] is set and the run's results are invalid.
+__device__ __forceinline__ uint32_t agent_load(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void ring_store(uint64_t *p, uint64_t v) {
+__device__ __forceinline__ void agent_store(uint32_t *p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int BLOCK, int KMAX>
-__global__ __launch_bounds__(BLOCK) void lf_ld_flow_kernel(LfFlowArgs a) {
-    // x, v of the block's tiles stay on chip in LDS ([tile][component][lane], conflict-free), so
-    // the register count does not grow with the tiles a block owns; x(t0), v(t0) live in t0buf
-    __shared__ float xv[KMAX][6][BLOCK];
-    __shared__ uint32_t words[4 * BLOCK];  // the current tile's numbers, in sequence order
-    __shared__ double red[BLOCK / 64][6];
-    __shared__ uint32_t s_abort;
-    __shared__ uint32_t s_toff[KMAX];  // (4 B c) mod R of the block's k-th tile
-    const uint32_t G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
-    const uint32_t R = a.L.R, Ct = a.geom.n_ctiles;
-    if (tid == 0) {
-        uint32_t off = static_cast<uint32_t>((4ull * BLOCK * g) % R);
-        const uint32_t step = static_cast<uint32_t>((4ull * BLOCK * G) % R);
-        for (int k = 0; k < KMAX; ++k) {
-            s_toff[k] = off;
-            off = wrap_once(off + step, R);
-        }
-        s_abort = 0u;
+// ring word `idx` (the dataflow run needs R < 2^30, so the byte offset fits 32 bits and the load
+// takes the ring base from scalar registers and one 32-bit offset register)
+__device__ __forceinline__ uint32_t ring_get(const uint32_t *ring, uint32_t idx) {
+    return agent_load(reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(ring) + (idx << 2)));
+}
+__device__ __forceinline__ void ring_put(uint32_t *ring, uint32_t idx, uint32_t v) {
+    agent_store(reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(ring) + (idx << 2)), v);
+}
+
+constexpr int kFlowM = kLfFlowSliceMax / 64;  // producer positions per lane per link
+
+// up to 64 waits of one wave, one per lane; `tile` tags a consumer's wait with its tile
+struct FlowWaits {
+    const uint32_t *flag;
+    uint32_t need;
+    uint32_t tile;
+    uint32_t n;  // collected so far (the same in every lane)
+};
+
+__device__ __forceinline__ void wait_add(FlowWaits &w, uint32_t lane, const uint32_t *flag, uint32_t need,
+                                         uint32_t tile) {
+    if (lane == w.n) {
+        w.flag = flag;
+        w.need = need;
+        w.tile = tile;
     }
-    for (int k = 0; k < KMAX; ++k) {
-        const uint32_t c = g + k * G;
-        const uint64_t o = static_cast<uint64_t>(c) * BLOCK + tid;
-        const bool act = c < Ct && o < a.n;
-        for (int d = 0; d < 3; ++d) {
-            xv[k][d][tid] = act ? a.x[d * a.N + o] : 0.0f;
-            xv[k][3 + d][tid] = act ? a.v[d * a.N + o] : 0.0f;
-        }
-    }
-    uint32_t slot_s = a.L.hdr->slot;                        // ring slot of the step's first position
-    uint32_t tag_s = static_cast<uint32_t>(a.L.hdr->pos);  // low 32 bits of that position
-    const uint32_t tag_adv = static_cast<uint32_t>(a.geom.four_n);
-    __syncthreads();
-    bool stop = false;
-    for (uint32_t s = 0; s < a.n_steps && !stop; ++s) {
-        for (int k = 0; k < KMAX; ++k) {
-            const uint32_t c = g + k * G;
-            if (c >= Ct) break;
-            const uint64_t first = static_cast<uint64_t>(c) * BLOCK;
-            const uint32_t count = static_cast<uint32_t>(first + BLOCK <= a.n ? BLOCK : a.n - first);
-            const bool act = tid < count;
-            const uint64_t o = first + tid;
-            if (a.stride && s % a.stride == 0) {  // observables of the tile's state before this step
-                double q[6] = {0, 0, 0, 0, 0, 0};
-                if (act) {
-                    float x[3], v[3], x0[3] = {0, 0, 0}, v0[3] = {0, 0, 0};
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        x[d] = xv[k][d][tid];
-                        v[d] = xv[k][3 + d][tid];
-                        if (s >= a.t0) {
-                            x0[d] = s == a.t0 ? x[d] : a.t0buf[d * a.N + o];
-                            v0[d] = s == a.t0 ? v[d] : a.t0buf[(3 + d) * a.N + o];
-                        }
-                    }
-                    add_observables(q, x, v, x0, v0, s >= a.t0);
-                }
-                block_sum6<BLOCK>(q, red, a.partials + (static_cast<uint64_t>(s / a.stride) * a.pstride + c) * 6);
+    ++w.n;
+}
+
+// pause between polls, growing with the number of failed polls up to about 0.4 us: pollers
+// must not flood the memory path that the waited-for stores travel on
+__device__ __forceinline__ void poll_pause(uint32_t spins) {
+    const uint32_t n = spins < 16u ? spins : 16u;
+    for (uint32_t i = 0; i < n; ++i) __builtin_amdgcn_s_sleep(8);
+}
+
+// block until every collected wait holds; false if the run gave up
+__device__ __forceinline__ bool wait_all(FlowWaits &w, uint32_t lane, const LfFlowArgs &a) {
+    bool ok = true;
+    if (lane < w.n) {
+        uint32_t spins = 0;
+        while (agent_load(w.flag) < w.need) {
+            if (++spins > a.spin_limit || ((spins & 15u) == 0 && agent_load(a.status) != 0u)) {
+                agent_store(a.status, 1u);
+                ok = false;
+                break;
             }
+            poll_pause(spins);
+        }
+    }
+    w.n = 0;
+    return __all(ok);
+}
+
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t o = __shfl_xor(v, off);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+// Producer p: offsets [p T, min((p+1) T, sl)) of every link; lane takes offsets lane + 64 r.
+// Software-pipelined over links.  When link j is summed, one read of the progress words link j+1
+// waits for and then link j's long-lag loads were issued during link j-1.  If those waits hold,
+// link j's stores are followed at once by the read for link j+2 and link j+1's loads, and
+// s_waitcnt vmcnt(kFlowM + 1) then means that every store of link j has completed (vector memory
+// operations complete in issue order), so link j can be published while link j+1's loads are in
+// flight.  Otherwise link j is published first and only then does the producer block on link
+// j+1's waits: it never blocks with an earlier link unpublished (the no-deadlock argument of
+// lf_flow.hpp with one link per iteration).
+__device__ __forceinline__ uint32_t producer_waits(const LfFlowArgs &a, uint32_t p, uint32_t j, uint32_t o_lo,
+                                                   uint32_t len, int64_t step_R, uint64_t off_R, FlowWaits &w,
+                                                   uint32_t lane, uint32_t round) {
+    uint32_t idx = 0;
+    auto add = [&](const uint32_t *f, uint32_t need) {
+        if (idx - 64u * round < 64u) wait_add(w, lane, f, need, 0);
+        ++idx;
+        return true;
+    };
+    if (len)
+        lf_producer_waits(
+            a.geom, p, j, o_lo, len, step_R, off_R,
+            [&](uint32_t s, uint32_t need) { return add(a.prod + s * kLfFlagStride, need); },
+            [&](uint32_t c, uint32_t need) { return add(a.cons + c * kLfFlagStride, need); });
+    return idx;  // waits in all
+}
+
+// block until every wait of link j holds (64 per round); false if the run gave up
+__device__ __forceinline__ bool producer_wait_link(const LfFlowArgs &a, uint32_t p, uint32_t j, uint32_t o_lo,
+                                                   uint32_t len, int64_t step_R, uint64_t off_R, FlowWaits &w,
+                                                   uint32_t lane) {
+    for (uint32_t round = 0;; ++round) {
+        const uint32_t total = producer_waits(a, p, j, o_lo, len, step_R, off_R, w, lane, round);
+        if (!wait_all(w, lane, a)) return false;
+        if (total <= 64u * (round + 1)) return true;
+    }
+}
+
+__device__ __forceinline__ void lf_producer(const LfFlowArgs &a, uint32_t p, uint32_t lane) {
+    const LfFlowGeom &g = a.geom;
+    if (p >= g.n_slices) return;
+    const uint32_t R = a.L.R, sl = g.sl, ll = a.L.ll;
+    const uint32_t o_lo = p << g.slice_log2;
+    const uint32_t width = ((1u << g.slice_log2) < sl - o_lo) ? (1u << g.slice_log2) : sl - o_lo;
+    uint32_t *ring = a.L.ring;
+    auto link_len = [&](uint32_t j) -> uint32_t {
+        if (j >= g.n_links) return 0u;
+        const uint64_t P_lo = static_cast<uint64_t>(j) * sl + o_lo;
+        return P_lo >= g.Ptot ? 0u : (g.Ptot - P_lo < width ? static_cast<uint32_t>(g.Ptot - P_lo) : width);
+    };
+    uint32_t slot = wrap_once(a.L.hdr->slot + o_lo, R);  // slot of (link j, o_lo)
+    // y_{P - sl} of link 0 comes from the ring, afterwards from the previous link in registers
+    uint32_t chain[kFlowM], src[kFlowM];
+#pragma unroll
+    for (int r = 0; r < kFlowM; ++r) {
+        const uint32_t q = lane + 64u * r;
+        chain[r] = q < width ? ring_get(ring, back(wrap_once(slot + q, R), sl, R)) : 0u;
+    }
+    int64_t step_R;
+    uint64_t off_R;
+    lf_consumer_coord0(g, o_lo, R, step_R, off_R);  // consumer coordinate of (link j, o_lo) - R
+    FlowWaits w;
+    w.n = 0;
+    // kFlowM long-lag loads of a link, always all issued (an unused one reads the link's first
+    // source), so that their count is exact
+    auto load_link = [&](uint32_t slot_j, uint32_t len_j) {
+#pragma unroll
+        for (int r = 0; r < kFlowM; ++r) {
+            const uint32_t q = lane + 64u * r;
+            src[r] = ring_get(ring, back(wrap_once(slot_j + (q < len_j ? q : 0u), R), ll, R));
+        }
+    };
+    // one read of the first 64 progress words link j1 waits for (lanes without a wait read the
+    // status word); it is issued just before a link's loads, so it has returned once they have
+    uint32_t total_poll = 0, seen = 0;
+    auto poll_link = [&](uint32_t j1, int64_t sR, uint64_t oR) {
+        const uint32_t len_j1 = link_len(j1);
+        total_poll = len_j1 ? producer_waits(a, p, j1, o_lo, len_j1, sR, oR, w, lane, 0) : 0u;
+        seen = agent_load(lane < w.n ? w.flag : a.status);
+    };
+    uint32_t len = link_len(0);
+    if (!producer_wait_link(a, p, 0, o_lo, len, step_R, off_R, w, lane)) return;
+    {
+        int64_t sR1 = step_R;
+        uint64_t oR1 = off_R;
+        lf_consumer_coord_next(g, sR1, oR1);
+        poll_link(1, sR1, oR1);
+    }
+    load_link(slot, len);
+    for (uint32_t j = 0; j < g.n_links; ++j) {
+        const uint32_t next_slot = wrap_once(slot + sl, R);
+        int64_t next_sR = step_R;
+        uint64_t next_oR = off_R;
+        lf_consumer_coord_next(g, next_sR, next_oR);
+        const uint32_t next_len = link_len(j + 1);
+        // link j: y_P = y_{P-sl} + y_{P-ll}
+#pragma unroll
+        for (int r = 0; r < kFlowM; ++r) chain[r] += src[r];
+        // link j+1's waits, read before link j's loads (a partial next link takes the plain path)
+        const bool ready = next_len == width && total_poll <= 64u && __all(lane >= w.n || seen >= w.need);
+        w.n = 0;
+        if (len == kLfFlowSliceMax) {
+            // a full slice: straight-line stores, so that no store waits for another (a store in
+            // a branch of its own can make the compiler wait for the previous one)
+#pragma unroll
+            for (int r = 0; r < kFlowM; ++r) ring_put(ring, wrap_once(slot + lane + 64u * r, R), chain[r]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < kFlowM; ++r) {
+                const uint32_t q = lane + 64u * r;
+                if (q < len) ring_put(ring, wrap_once(slot + q, R), chain[r]);
+            }
+        }
+        if (!ready) {
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            if (lane == 0) agent_store(a.prod + p * kLfFlagStride, j + 1);
+            if (!next_len) break;
+            if (!producer_wait_link(a, p, j + 1, o_lo, next_len, next_sR, next_oR, w, lane)) return;
+        }
+        {
+            int64_t sR2 = next_sR;
+            uint64_t oR2 = next_oR;
+            lf_consumer_coord_next(g, sR2, oR2);
+            poll_link(j + 2, sR2, oR2);
+        }
+        load_link(next_slot, next_len);
+        if (ready) {
+            // only the poll and link j+1's kFlowM loads, issued after link j's stores, may still be
+            // outstanding: link j is stored
+            static_assert(kFlowM == 16, "the wait count below");
+            asm volatile("s_waitcnt vmcnt(17)" ::: "memory");
+            if (lane == 0) agent_store(a.prod + p * kLfFlagStride, j + 1);
+        }
+        slot = next_slot;
+        step_R = next_sR;
+        off_R = next_oR;
+        len = next_len;
+    }
+}
+
+// observables of one 64-oscillator tile; lane 0 writes the tile's partial sums
+__device__ __forceinline__ void tile_observe(const LfFlowArgs &a, const float *t0buf, const float *xv, uint32_t lane,
+                                             uint64_t o, bool act, uint32_t s, uint32_t c) {
+    double q[6] = {0, 0, 0, 0, 0, 0};
+    if (act) {
+        float x[3], v[3], x0[3] = {0, 0, 0}, v0[3] = {0, 0, 0};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            x[d] = xv[d * 64 + lane];
+            v[d] = xv[(3 + d) * 64 + lane];
+            if (s >= a.t0) {
+                x0[d] = s == a.t0 ? x[d] : t0buf[d * a.N + o];
+                v0[d] = s == a.t0 ? v[d] : t0buf[(3 + d) * a.N + o];
+            }
+        }
+        add_observables(q, x, v, x0, v0, s >= a.t0);
+    }
+    double *dst = a.partials + (static_cast<uint64_t>(s / a.stride) * a.pstride + c) * 6;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        const double t = wave_sum(q[i]);
+        if (lane == 0) dst[i] = t;
+    }
+}
+
+// Consumer wave cw: tiles c = cw + k Gc of 64 oscillators; x, v in LDS as xv[k][6][64]; tr is a
+// 256-word transpose buffer.  Lane l of a tile drives oscillator 64 c + l.
+// position coordinates of a consumer's tiles: tile k lies 256 k Gc positions after tile 0
+struct TileCursor {
+    int64_t link;   // link and offset in it of the tile's first position
+    uint32_t off;
+    uint32_t slot;  // its ring slot
+};
+
+__device__ __forceinline__ void tile_cursor_next(TileCursor &t, const LfFlowGeom &g, uint32_t dq, uint32_t dr,
+                                                 uint32_t dR, uint32_t R) {
+    t.link += dq;
+    t.off += dr;
+    if (t.off >= g.sl) {
+        t.off -= g.sl;
+        ++t.link;
+    }
+    t.slot = wrap_once(t.slot + dR, R);
+}
+
+template <int KC>
+__device__ __forceinline__ void lf_consumer(const LfFlowArgs &a, uint32_t cw, uint32_t lane, float *xv, uint32_t *tr) {
+    const LfFlowGeom &g = a.geom;
+    const uint32_t R = a.L.R, Gc = g.Gc, Kc = g.Kc;
+    uint32_t *ring = a.L.ring;
+    uint32_t Kw = 0;  // tiles of this wave
+    while (Kw < Kc && cw + Kw * Gc < g.n_ctiles) ++Kw;
+    // 256 Gc positions between consecutive tiles, by the link length and by the ring length
+    const uint64_t gap = 256ull * Gc;
+    const uint32_t dq = static_cast<uint32_t>(gap / g.sl), dr = static_cast<uint32_t>(gap % g.sl);
+    const uint32_t dR = static_cast<uint32_t>(gap % R);
+    TileCursor t0c;  // tile 0 at the current step
+    t0c.link = static_cast<int64_t>((256ull * cw) / g.sl);
+    t0c.off = static_cast<uint32_t>((256ull * cw) % g.sl);
+    t0c.slot = wrap_once(a.L.hdr->slot, R);
+    t0c.slot = wrap_once(t0c.slot + static_cast<uint32_t>((256ull * cw) % R), R);
+#pragma unroll 1
+    for (int k = 0; k < KC; ++k) {
+        if (k >= static_cast<int>(Kw)) break;
+        const uint64_t o = 64ull * (cw + k * Gc) + lane;
+        const bool act = o < a.n;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            xv[(k * 6 + d) * 64 + lane] = act ? a.x[d * a.N + o] : 0.0f;
+            xv[(k * 6 + 3 + d) * 64 + lane] = act ? a.v[d * a.N + o] : 0.0f;
+        }
+    }
+    FlowWaits w;
+    w.n = 0;
+    for (uint32_t s = 0; s < a.n_steps; ++s) {
+        // an opaque copy of the pointer keeps the per-tile addresses from being held in registers
+        // across the loop
+        float *t0buf = a.t0buf;
+        asm volatile("" : "+s"(t0buf));
+        const bool obs_now = a.stride && s % a.stride == 0;
+#pragma unroll 1
+        for (int k = 0; k < KC; ++k) {
+            if (k >= static_cast<int>(Kw)) break;
+            const uint32_t c = cw + k * Gc;
+            const uint64_t o = 64ull * c + lane;
+            const bool act = o < a.n;
+            if (obs_now) tile_observe(a, t0buf, xv + k * 384, lane, o, act, s, c);
             if (a.stride && s == a.t0 && act)
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    a.t0buf[d * a.N + o] = xv[k][d][tid];
-                    a.t0buf[(3 + d) * a.N + o] = xv[k][3 + d][tid];
+                    t0buf[d * a.N + o] = xv[(k * 6 + d) * 64 + lane];
+                    t0buf[(3 + d) * a.N + o] = xv[(k * 6 + 3 + d) * 64 + lane];
                 }
-            // the tile's 4 count numbers: lane t takes positions q = t + 256 r
-            {
-                const uint32_t base = wrap_once(slot_s + s_toff[k], R);
-                const uint32_t tag0 = tag_s + static_cast<uint32_t>(4ull * BLOCK * c);
-                uint32_t src_l[4], src_s[4];
-                uint64_t vl[4], vs[4];
+        }
+        // the step's numbers: poll the waits of the remaining tiles together, load and publish the
+        // prefix of tiles whose waits hold, repeat
+        uint32_t kd = 0, spins = 0;
+        while (kd < Kw) {
+            uint32_t cut = Kw;
+            TileCursor tc = t0c;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const uint32_t q = r * BLOCK + tid;
-                    if (q < 4 * count) {
-                        const uint32_t slot = wrap_once(base + q, R);
-                        src_l[r] = back(slot, a.L.ll, R);
-                        src_s[r] = back(slot, a.L.sl, R);
-                        vl[r] = ring_load(a.L.ring + src_l[r]);
-                        vs[r] = ring_load(a.L.ring + src_s[r]);
+            for (int k = 0; k < KC; ++k) {  // compile-time k keeps the per-tile values in registers
+                if (cut == Kw && k >= static_cast<int>(kd) && k < static_cast<int>(Kw)) {
+                    const uint64_t first = 64ull * (cw + k * Gc);
+                    const uint32_t cnt4 = 4u * static_cast<uint32_t>(first + 64 <= a.n ? 64 : a.n - first);
+                    bool fits = true;
+                    lf_walk_producers(g, tc.link, tc.off, cnt4, [&](uint32_t sl_, uint32_t l) {
+                        if (w.n == 64) {
+                            fits = false;
+                            return false;
+                        }
+                        wait_add(w, lane, a.prod + sl_ * kLfFlagStride, l + 1, k);
+                        return true;
+                    });
+                    if (!fits) cut = k;
+                }
+                tile_cursor_next(tc, g, dq, dr, dR, R);
+            }
+            uint32_t bad = cut;
+            if (lane < w.n && agent_load(w.flag) < w.need) bad = w.tile;
+            w.n = 0;
+            const uint32_t done = wave_min(bad);
+            if (done == kd) {
+                if (++spins > a.spin_limit || ((spins & 15u) == 0 && agent_load(a.status) != 0u)) {
+                    if (lane == 0) agent_store(a.status, 1u);
+                    return;
+                }
+                poll_pause(spins);
+                continue;
+            }
+            spins = 0;
+            // load and drive the ready tiles [kd, done) in halves of at most 4 tiles (bounded
+            // registers); a half is published once its loads have returned
+#pragma unroll
+            for (int k0 = 0; k0 < KC; k0 += 4) {
+                if (k0 + 4 <= static_cast<int>(kd) || k0 >= static_cast<int>(done)) continue;
+                TileCursor tc = t0c;
+#pragma unroll
+                for (int k = 0; k < k0; ++k) tile_cursor_next(tc, g, dq, dr, dR, R);
+                uint32_t words[4][4];
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int k = k0 + kk;
+                    const uint64_t first = 64ull * (cw + k * Gc);
+                    const uint32_t cnt4 =
+                        first < a.n ? 4u * static_cast<uint32_t>(first + 64 <= a.n ? 64 : a.n - first) : 0u;
+                    const bool mine = k < KC && k >= static_cast<int>(kd) && k < static_cast<int>(done);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const uint32_t q = lane + 64u * r;
+                        words[kk][r] = (mine && q < cnt4) ? ring_get(ring, wrap_once(tc.slot + q, R)) : 0u;
+                    }
+                    tile_cursor_next(tc, g, dq, dr, dR, R);
+                }
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the loads have returned: the slots are free
+                const uint32_t upto = static_cast<uint32_t>(k0 + 4) < done ? static_cast<uint32_t>(k0 + 4) : done;
+                if (lane == 0) agent_store(a.cons + cw * kLfFlagStride, s * Kc + upto);
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int k = k0 + kk;
+                    if (k >= KC || k < static_cast<int>(kd) || k >= static_cast<int>(done)) continue;
+                    const uint64_t first = 64ull * (cw + k * Gc);
+                    // lane-contiguous words -> oscillator lane's four words
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) tr[lane + 64 * r] = words[kk][r];
+                    uint32_t u[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) u[r] = tr[4 * lane + r];
+                    if (first + lane < a.n) {
+                        float gf[3];
+                        gaussian_forces(u[0], u[1], u[2], u[3], gf[0], gf[1], gf[2]);
+                        float *t = xv + k * 384;
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            float x = t[d * 64 + lane], v = t[(3 + d) * 64 + lane];
+                            ld_update(a.coef, x, v, gf[d]);
+                            t[d * 64 + lane] = x;
+                            t[(3 + d) * 64 + lane] = v;
+                        }
                     }
                 }
-                bool ok = true;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const uint32_t q = r * BLOCK + tid;
-                    if (ok && q < 4 * count) {
-                        const uint32_t want_l = tag0 + q - a.L.ll, want_s = tag0 + q - a.L.sl;
-                        uint32_t spins = 0;
-                        while (tag_of(vl[r]) != want_l || tag_of(vs[r]) != want_s) {
-                            if (++spins > a.spin_limit ||
-                                __hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                                __hip_atomic_store(a.status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                                ok = false;
-                                break;
-                            }
-                            __builtin_amdgcn_s_sleep(1);
-                            if (tag_of(vl[r]) != want_l) vl[r] = ring_load(a.L.ring + src_l[r]);
-                            if (tag_of(vs[r]) != want_s) vs[r] = ring_load(a.L.ring + src_s[r]);
-                        }
-                        if (ok) {
-                            const uint32_t w = value_of(vl[r]) + value_of(vs[r]);
-                            ring_store(a.L.ring + wrap_once(base + q, R), pack(w, tag0 + q));
-                            words[q] = w;
-                        }
-                    }
-                }
-                if (!ok) s_abort = 1u;
             }
-            __syncthreads();  // words[] complete: oscillator t's four words are words[4t .. 4t+3]
-            if (s_abort) {
-                stop = true;
-                break;
-            }
-            if (act) {
-                const uint32_t *w = words + 4 * tid;
-                float gf[3];
-                gaussian_forces(w[0], w[1], w[2], w[3], gf[0], gf[1], gf[2]);
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    float x = xv[k][d][tid], v = xv[k][3 + d][tid];
-                    ld_update(a.coef, x, v, gf[d]);
-                    xv[k][d][tid] = x;
-                    xv[k][3 + d][tid] = v;
-                }
-            }
-            __syncthreads();  // words[] is free for the next tile
+            kd = done;
         }
-        slot_s = wrap_once(slot_s + a.step_adv, R);
-        tag_s += tag_adv;
+        lf_link_coord_next_step(g, t0c.link, t0c.off);
+        t0c.slot = wrap_once(t0c.slot + a.step_adv, R);
     }
-    if (!stop && a.stride && a.n_steps % a.stride == 0) {
-        const uint32_t s = a.n_steps;
-        for (int k = 0; k < KMAX; ++k) {
-            const uint32_t c = g + k * G;
-            if (c >= Ct) break;
-            const uint64_t o = static_cast<uint64_t>(c) * BLOCK + tid;
-            double q[6] = {0, 0, 0, 0, 0, 0};
-            if (o < a.n) {
-                float x[3], v[3], x0[3], v0[3];
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    x[d] = xv[k][d][tid];
-                    v[d] = xv[k][3 + d][tid];
-                    x0[d] = s == a.t0 ? x[d] : a.t0buf[d * a.N + o];
-                    v0[d] = s == a.t0 ? v[d] : a.t0buf[(3 + d) * a.N + o];
-                }
-                add_observables(q, x, v, x0, v0, s >= a.t0);
-            }
-            block_sum6<BLOCK>(q, red, a.partials + (static_cast<uint64_t>(s / a.stride) * a.pstride + c) * 6);
+    float *t0buf = a.t0buf, *xo = a.x, *vo = a.v;
+    asm volatile("" : "+s"(t0buf), "+s"(xo), "+s"(vo));
+    if (a.stride && a.n_steps % a.stride == 0)
+#pragma unroll 1
+        for (int k = 0; k < KC; ++k) {
+            if (k >= static_cast<int>(Kw)) break;
+            const uint32_t c = cw + k * Gc;
+            const uint64_t o = 64ull * c + lane;
+            tile_observe(a, t0buf, xv + k * 384, lane, o, o < a.n, a.n_steps, c);
         }
-    }
-    for (int k = 0; k < KMAX; ++k) {
-        const uint32_t c = g + k * G;
-        const uint64_t o = static_cast<uint64_t>(c) * BLOCK + tid;
-        if (c < Ct && o < a.n)
+#pragma unroll 1
+    for (int k = 0; k < KC; ++k) {
+        if (k >= static_cast<int>(Kw)) break;
+        const uint64_t o = 64ull * (cw + k * Gc) + lane;
+        if (o < a.n)
+#pragma unroll
             for (int d = 0; d < 3; ++d) {
-                a.x[d * a.N + o] = xv[k][d][tid];
-                a.v[d * a.N + o] = xv[k][3 + d][tid];
+                xo[d * a.N + o] = xv[(k * 6 + d) * 64 + lane];
+                vo[d * a.N + o] = xv[(k * 6 + 3 + d) * 64 + lane];
             }
+    }
+}
+
+template <int KC>
+__global__ __launch_bounds__(kLfFlowBlock) void lf_pc_kernel(LfFlowArgs a) {
+    extern __shared__ float flow_lds[];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wid < a.np) {
+        lf_producer(a, __builtin_amdgcn_readfirstlane(blockIdx.x * a.np + wid), lane);
+    } else {
+        const uint32_t nc = kLfFlowBlock / 64 - a.np, k = wid - a.np;
+        float *base = flow_lds + static_cast<size_t>(k) * (a.geom.Kc * 384u + 256u);
+        lf_consumer<KC>(a, __builtin_amdgcn_readfirstlane(blockIdx.x * nc + k), lane, base,
+                        reinterpret_cast<uint32_t *>(base + a.geom.Kc * 384u));
     }
 }
 
@@ -386,17 +633,17 @@ __global__ __launch_bounds__(kBulkBlock) void fill_u32_kernel(uint32_t *dst, uin
     if (i < count) dst[i] = value;
 }
 
-template <int KMAX>
-const void *lf_flow_fn() {
-    return reinterpret_cast<const void *>(&lf_ld_flow_kernel<(1 << kLfFlowBlockLog2), KMAX>);
+template <int KC>
+const void *lf_pc_fn() {
+    return reinterpret_cast<const void *>(&lf_pc_kernel<KC>);
 }
 
-const void *lf_flow_fn_for(uint32_t kmax) {
-    switch (kmax) {
-        case 1: return lf_flow_fn<1>();
-        case 2: return lf_flow_fn<2>();
-        case 4: return lf_flow_fn<4>();
-        case 8: return lf_flow_fn<8>();
+const void *lf_pc_fn_for(uint32_t kc) {
+    switch (kc) {
+        case 1: return lf_pc_fn<1>();
+        case 2: return lf_pc_fn<2>();
+        case 4: return lf_pc_fn<4>();
+        case 8: return lf_pc_fn<8>();
         default: return nullptr;
     }
 }
@@ -410,7 +657,7 @@ inline dim3 grid_for(uint64_t n, int block = kBulkBlock) {
 hipError_t launch_lf_seed(void *state, uint32_t ll, uint32_t sl, uint32_t R, uint32_t W, uint64_t seed,
                           hipStream_t st) {
     LfHeader *hdr = static_cast<LfHeader *>(state);
-    uint64_t *ring = reinterpret_cast<uint64_t *>(hdr + 1);
+    uint32_t *ring = reinterpret_cast<uint32_t *>(hdr + 1);
     lf_seed_kernel<<<grid_for(R), kBulkBlock, 0, st>>>(hdr, ring, ll, sl, R, W, seed);
     return hipGetLastError();
 }
@@ -462,22 +709,20 @@ hipError_t launch_fill_u32(uint32_t *dst, uint64_t count, uint32_t value, hipStr
     return hipGetLastError();
 }
 
-uint32_t lf_flow_max_grid(uint32_t kmax) {
-    const void *fn = lf_flow_fn_for(kmax);
-    if (!fn) return 0;
-    int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 1 << kLfFlowBlockLog2, 0) != hipSuccess) return 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    return static_cast<uint32_t>(per_cu) * static_cast<uint32_t>(cus);
-}
-
-hipError_t launch_lf_flow(const LfFlowArgs &a, uint32_t grid, uint32_t kmax, hipStream_t st) {
-    const void *fn = lf_flow_fn_for(kmax);
+hipError_t launch_lf_flow(const LfFlowArgs &a, uint32_t grid, uint32_t kc, uint32_t lds, hipStream_t st) {
+    const void *fn = lf_pc_fn_for(kc);
     if (!fn) return hipErrorInvalidValue;
+    // allow more than 64 KiB of dynamic LDS where the runtime asks for it; the occupancy query
+    // below decides whether the block fits
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
+        (void)hipGetLastError();
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kLfFlowBlock, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorCooperativeLaunchTooLarge;
     LfFlowArgs copy = a;
     void *args[] = {&copy};
-    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(1 << kLfFlowBlockLog2), args, 0, st);
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kLfFlowBlock), args, lds, st);
 }
 
 }  // namespace rngld

@@ -1,10 +1,39 @@
-// lf_flow.hpp -- tile geometry of the shared lagged-Fibonacci sequence in a fused LD run.
+// lf_flow.hpp -- who waits for whom in the persistent lagged-Fibonacci LD run.
 //
-// In a run of n oscillators, step s consumes the 4n consecutive positions (s, off), off in [0, 4n),
-// oscillator o taking off = 4o .. 4o+3 (Alg. 3, RNS = 4).  A tile is the 4B positions of B
-// consecutive oscillators of one step (the last tile of a step may be shorter).  Position (s, off)
-// needs the positions sl and ll earlier (Eq. 3); these helpers name the tiles holding them.
-// Plain C++ so that the host code and a CPU test can use it as well as the kernels.
+// The run consumes positions P = 0 .. Ptot-1 of the one sequence y_P = y_{P-ll} + y_{P-sl} mod 2^32
+// (Eq. 3); LD step s takes positions s 4n .. s 4n + 4n - 1, oscillator o the four from s 4n + 4o
+// (Alg. 3 with RNS = 4).  The run is cut into links of sl positions: link j = [j sl, (j+1) sl).
+// Every position of link j depends only on links < j, since both lags are >= sl.
+//
+//  * Producer p owns the slice [p T, min((p+1) T, sl)) of the offsets within every link (T a power
+//    of two).  Its short-lag source y_{P-sl} is its own number of the previous link, so only the
+//    long-lag source y_{P-ll} is read from the ring.  After storing link j it publishes
+//    prod[p] = j + 1 (links done).
+//  * Consumer wave w owns the tiles c = w + k Gc (k < Kc) of 64 oscillators (256 positions) of
+//    every step and handles them in that order; once tile k of step s is loaded it publishes
+//    cons[w] = s Kc + k + 1 (tiles done, counting Kc per step).
+//
+// A producer handles nb links per iteration (nb sl <= ll, so their long-lag sources lie before
+// them) and publishes once per iteration.
+// A ring slot of R >= ll + sl words holds position P; the producer writing P overwrites P - R.
+// The waits that make the run equal to the sequential recurrence, for a producer about to write
+// positions P of link j:
+//   (a) the producers of the sources P - ll (data dependency);
+//   (b) the consumer of P - R (it must have read it);
+//   (c) the producer of P - R + ll, which reads P - R as its long-lag source (it is this producer's
+//       own earlier link when R = ll + sl);
+//   (d) for P - R + sl in link 0: its producer, which reads P - R from the ring once at the start.
+// A consumer of tile (s, c) waits for the producers of its 4 x 64 positions.
+//
+// No deadlock, given R >= ll + nb sl and R >= nb sl + 255: every wait of an iteration over links
+// [j0, j0 + nb) is for producers' iterations that end by link j0 (a: sources lie nb sl back; c: the
+// readers of P - R lie R - ll >= nb sl back; d: P - R + sl in link 0 puts P beyond link nb) or for
+// consumer tiles lying wholly before link j0 (b: a tile ends within 255 positions of P - R).  A
+// consumer tile waits only for the producers of its own positions, and a consumer never holds a
+// loaded tile unpublished while it waits.  So every wait points to earlier work, and with all waves
+// resident the run always progresses.
+//
+// Plain C++, so that the host and a CPU test can use it as well as the kernels.
 #pragma once
 
 #include <stdint.h>
@@ -17,73 +46,178 @@
 
 namespace rngld {
 
+// lag = a * sl + b, 0 <= b < sl
+struct LfLag {
+    uint32_t a, b;
+};
+
 struct LfFlowGeom {
+    uint64_t Ptot;        // positions of the run, 4 n T
     uint64_t four_n;      // positions per LD step
-    uint32_t tile_shift;  // log2(4 B): positions per full tile
-    uint32_t n_ctiles;    // tiles per step, ceil(n / B)
-    uint64_t a_sl, b_sl;  // sl = a_sl * four_n + b_sl, 0 <= b_sl < four_n
-    uint64_t a_ll, b_ll;  // ll likewise
+    uint64_t fourn_q;     // four_n = fourn_q * sl + fourn_r
+    uint64_t sl_q;        // sl = sl_q * four_n + sl_r
+    uint64_t sl_r;
+    uint32_t fourn_r;
+    uint32_t sl;          // link length (the short lag)
+    uint32_t slice_log2;  // producer slice T = 2^slice_log2 offsets
+    uint32_t n_slices;    // ceil(sl / T): producers with work
+    uint32_t n_links;     // ceil(Ptot / sl)
+    uint32_t n_ctiles;    // consumer tiles (64 oscillators) per step
+    uint32_t Gc;          // consumer waves
+    uint32_t Kc;          // tiles per consumer wave per step (its progress counts Kc per step)
+    LfLag ll, R, R_ll, R_sl;  // ll, R, R - ll, R - sl
 };
 
-struct LfTile {
-    int64_t step;  // negative: before the run (already in the ring)
-    uint32_t c;    // tile within the step
-};
+RNGLD_HD inline LfLag lf_lag(uint64_t lag, uint32_t sl) {
+    LfLag L;
+    L.a = static_cast<uint32_t>(lag / sl);
+    L.b = static_cast<uint32_t>(lag % sl);
+    return L;
+}
 
-RNGLD_HD inline LfFlowGeom lf_flow_geom(uint64_t n, uint32_t block_log2, uint32_t ll, uint32_t sl) {
-    LfFlowGeom g;
+inline LfFlowGeom lf_flow_geom(uint64_t n, uint32_t n_steps, uint32_t ll, uint32_t sl, uint32_t R,
+                               uint32_t slice_log2, uint32_t Gc) {
+    // Gc consumer waves, each with ceil(tiles / Gc) tiles per step
+    LfFlowGeom g{};
     g.four_n = 4 * n;
-    g.tile_shift = block_log2 + 2;
-    g.n_ctiles = static_cast<uint32_t>((n + (1ull << block_log2) - 1) >> block_log2);
-    g.a_sl = sl / g.four_n;
-    g.b_sl = sl % g.four_n;
-    g.a_ll = ll / g.four_n;
-    g.b_ll = ll % g.four_n;
+    g.Ptot = g.four_n * n_steps;
+    g.fourn_q = g.four_n / sl;
+    g.fourn_r = static_cast<uint32_t>(g.four_n % sl);
+    g.sl_q = g.four_n ? sl / g.four_n : 0;
+    g.sl_r = g.four_n ? sl % g.four_n : 0;
+    g.sl = sl;
+    g.slice_log2 = slice_log2;
+    g.n_slices = static_cast<uint32_t>((static_cast<uint64_t>(sl) + (1ull << slice_log2) - 1) >> slice_log2);
+    g.n_links = static_cast<uint32_t>((g.Ptot + sl - 1) / sl);
+    g.n_ctiles = static_cast<uint32_t>((n + 63) / 64);
+    g.Gc = Gc;
+    g.Kc = Gc ? (g.n_ctiles + Gc - 1) / Gc : 0;
+    g.ll = lf_lag(ll, sl);
+    g.R = lf_lag(R, sl);
+    g.R_ll = lf_lag(static_cast<uint64_t>(R) - ll, sl);
+    g.R_sl = lf_lag(static_cast<uint64_t>(R) - sl, sl);
     return g;
 }
 
-// tile holding position (s, off) - (a * four_n + b)
-RNGLD_HD inline LfTile lf_tile_back(const LfFlowGeom &g, uint32_t s, uint64_t off, uint64_t a, uint64_t b) {
-    LfTile t;
-    if (off >= b) {
-        t.step = static_cast<int64_t>(s) - static_cast<int64_t>(a);
-        t.c = static_cast<uint32_t>((off - b) >> g.tile_shift);
+// (link, off) of position (j, o) - lag; link < 0 means before the run
+RNGLD_HD inline void lf_back(uint32_t j, uint32_t o, LfLag L, uint32_t sl, int64_t &link, uint32_t &off) {
+    if (o >= L.b) {
+        link = static_cast<int64_t>(j) - L.a;
+        off = o - L.b;
     } else {
-        t.step = static_cast<int64_t>(s) - static_cast<int64_t>(a) - 1;
-        t.c = static_cast<uint32_t>((off + g.four_n - b) >> g.tile_shift);
+        link = static_cast<int64_t>(j) - L.a - 1;
+        off = o + (sl - L.b);
     }
-    return t;
 }
 
-RNGLD_HD inline LfTile lf_tile_next(const LfFlowGeom &g, LfTile t) {
-    if (t.c + 1 < g.n_ctiles) {
-        ++t.c;
-    } else {
-        t.c = 0;
-        ++t.step;
-    }
-    return t;
-}
-
-// Call visit(step, c) for every tile (with step >= 0) holding a position that tile (s, c) of
-// `count` oscillators reads, i.e. positions [off0 - lag, off1 - lag) for lag = sl and lag = ll.
-// Each range spans at most three tiles (a short last tile can sit between two full ones); the
-// loop is bounded accordingly.  Returns false if visit returned false.
+// visit(slice, link) for every producer slice holding a run position of [(link, off), + len),
+// in order; positions before the run or at/after Ptot are skipped.  false if visit returned false.
 template <class Visit>
-RNGLD_HD inline bool lf_tile_sources(const LfFlowGeom &g, uint32_t s, uint32_t c, uint32_t count, Visit &&visit) {
-    const uint64_t off0 = static_cast<uint64_t>(c) << g.tile_shift;
-    const uint64_t off1 = off0 + 4ull * count;  // exclusive
-    const uint64_t lags[2][2] = {{g.a_sl, g.b_sl}, {g.a_ll, g.b_ll}};
-    for (int l = 0; l < 2; ++l) {
-        LfTile t = lf_tile_back(g, s, off0, lags[l][0], lags[l][1]);
-        const LfTile last = lf_tile_back(g, s, off1 - 1, lags[l][0], lags[l][1]);
-        for (int guard = 0; guard < 4; ++guard) {
-            if (t.step >= 0 && !visit(static_cast<uint32_t>(t.step), t.c)) return false;
-            if (t.step == last.step && t.c == last.c) break;
-            t = lf_tile_next(g, t);
+RNGLD_HD inline bool lf_walk_producers(const LfFlowGeom &g, int64_t link, uint32_t off, uint32_t len, Visit &&visit) {
+    while (len > 0) {
+        const uint32_t slice = off >> g.slice_log2;
+        uint32_t end = (slice + 1) << g.slice_log2;
+        if (end > g.sl) end = g.sl;
+        const uint32_t take = end - off < len ? end - off : len;
+        if (link >= 0) {
+            if (static_cast<uint64_t>(link) * g.sl + off >= g.Ptot) return true;
+            if (!visit(slice, static_cast<uint32_t>(link))) return false;
+        }
+        len -= take;
+        off += take;
+        if (off == g.sl) {
+            off = 0;
+            ++link;
         }
     }
     return true;
+}
+
+// visit(wave, need) for every consumer tile holding a run position of [(step, off), + len), where
+// off < four_n is the offset within the step and need = step Kc + k + 1 the wave's progress once
+// that tile (its k-th) is loaded; step < 0 is skipped
+template <class Visit>
+RNGLD_HD inline bool lf_walk_consumers(const LfFlowGeom &g, int64_t step, uint64_t off, uint32_t len, Visit &&visit) {
+    while (len > 0) {
+        const uint64_t tile = off >> 8;
+        uint64_t end = (tile + 1) << 8;
+        if (end > g.four_n) end = g.four_n;
+        const uint32_t take = end - off < len ? static_cast<uint32_t>(end - off) : len;
+        if (step >= 0) {
+            const uint32_t t = static_cast<uint32_t>(tile);
+            const uint32_t k = t / g.Gc;
+            if (!visit(t - k * g.Gc, static_cast<uint32_t>(step) * g.Kc + k + 1)) return false;
+        }
+        len -= take;
+        off += take;
+        if (off == g.four_n) {
+            off = 0;
+            ++step;
+        }
+    }
+    return true;
+}
+
+// (step, offset within the step) of position P - R for P = (0, o): a signed floor division, once
+RNGLD_HD inline void lf_consumer_coord0(const LfFlowGeom &g, uint32_t o, uint64_t R, int64_t &step, uint64_t &off) {
+    const int64_t q = static_cast<int64_t>(o) - static_cast<int64_t>(R);
+    const int64_t fn = static_cast<int64_t>(g.four_n);
+    int64_t s = q / fn;
+    int64_t r = q - s * fn;
+    if (r < 0) {
+        r += fn;
+        --s;
+    }
+    step = s;
+    off = static_cast<uint64_t>(r);
+}
+
+// advance a (step, off) coordinate by one link (sl positions)
+RNGLD_HD inline void lf_consumer_coord_next(const LfFlowGeom &g, int64_t &step, uint64_t &off) {
+    step += static_cast<int64_t>(g.sl_q);
+    off += g.sl_r;
+    if (off >= g.four_n) {
+        off -= g.four_n;
+        ++step;
+    }
+}
+
+// advance a (link, off) coordinate by one LD step (four_n positions)
+RNGLD_HD inline void lf_link_coord_next_step(const LfFlowGeom &g, int64_t &link, uint32_t &off) {
+    link += static_cast<int64_t>(g.fourn_q);
+    const uint64_t o = static_cast<uint64_t>(off) + g.fourn_r;
+    if (o >= g.sl) {
+        off = static_cast<uint32_t>(o - g.sl);
+        ++link;
+    } else {
+        off = static_cast<uint32_t>(o);
+    }
+}
+
+// Every wait of producer p before it writes offsets [o_lo, o_lo + len) of link j (cases (a)-(d)
+// above).  (step_R, off_R) is the consumer coordinate of (j, o_lo) - R.  prod_wait(slice, need) asks
+// for prod[slice] >= need, cons_wait(wave, need) for cons[wave] >= need.
+template <class ProdWait, class ConsWait>
+RNGLD_HD inline bool lf_producer_waits(const LfFlowGeom &g, uint32_t p, uint32_t j, uint32_t o_lo, uint32_t len,
+                                       int64_t step_R, uint64_t off_R, ProdWait &&prod_wait, ConsWait &&cons_wait) {
+    int64_t link;
+    uint32_t off;
+    // (a) sources
+    lf_back(j, o_lo, g.ll, g.sl, link, off);
+    if (!lf_walk_producers(g, link, off, len, [&](uint32_t s, uint32_t l) { return prod_wait(s, l + 1); }))
+        return false;
+    // (b) the consumers of the overwritten positions
+    if (!lf_walk_consumers(g, step_R, off_R, len, [&](uint32_t w, uint32_t need) { return cons_wait(w, need); }))
+        return false;
+    // (c) their long-lag readers
+    lf_back(j, o_lo, g.R_ll, g.sl, link, off);
+    if (!lf_walk_producers(g, link, off, len,
+                           [&](uint32_t s, uint32_t l) { return s == p || prod_wait(s, l + 1); }))
+        return false;
+    // (d) their short-lag readers in link 0
+    lf_back(j, o_lo, g.R_sl, g.sl, link, off);
+    return lf_walk_producers(g, link, off, len,
+                             [&](uint32_t s, uint32_t l) { return l != 0 || s == p || prod_wait(s, 1u); });
 }
 
 }  // namespace rngld

@@ -1,53 +1,335 @@
-// CPU check of the lagged-Fibonacci tile geometry used by the dataflow LD kernel: for every tile
-// of small runs, the tiles lf_tile_sources() names must be exactly the tiles holding the
-// positions that the tile's numbers read (p - sl and p - ll), found here by brute force.
+// CPU check of the waits of the persistent lagged-Fibonacci LD run (lf_flow.hpp).
+//  1. For every producer link and consumer tile of small runs, the waits named by
+//     lf_producer_waits / lf_walk_producers are exactly the ones found by brute force over the
+//     positions involved.
+//  2. The incremental coordinate updates the kernel uses agree with a fresh division.
+//  3. A simulation of the whole protocol under random interleavings: producers read their sources
+//     (after their waits) and write later, consumers read their numbers; every read must find the
+//     position it expects in its ring slot, every value must equal the sequential recurrence, and
+//     the run must always be able to progress (no deadlock).
 #include <cstdio>
+#include <algorithm>
+#include <cstdlib>
+#include <map>
 #include <set>
+#include <tuple>
 #include <utility>
+#include <vector>
 
 #include "../../paper_1003_1123_amd/csrc/lf_flow.hpp"
 
 using namespace rngld;
 
-static int check(uint64_t n, uint32_t block_log2, uint32_t ll, uint32_t sl, uint32_t steps) {
-    const LfFlowGeom g = lf_flow_geom(n, block_log2, ll, sl);
-    const uint64_t B = 1ull << block_log2, four_n = 4 * n;
+typedef std::set<std::tuple<int, uint32_t, uint32_t>> WaitSet;  // (0 prod / 1 cons, index, need)
+
+struct Run {
+    uint64_t n;
+    uint32_t T, ll, sl, R, slice_log2, Gc;
+    LfFlowGeom g;
+    uint64_t Ptot;
+    int64_t slice_of(int64_t P) const { return (P % sl) >> slice_log2; }
+    int64_t link_of(int64_t P) const { return P / sl; }
+    int64_t step_of(int64_t P) const { return P / static_cast<int64_t>(g.four_n); }
+};
+
+static Run make_run(uint64_t n, uint32_t T, uint32_t ll, uint32_t sl, uint32_t R, uint32_t slice_log2, uint32_t Gc) {
+    Run r;
+    r.n = n;
+    r.T = T;
+    r.ll = ll;
+    r.sl = sl;
+    r.R = R;
+    r.slice_log2 = slice_log2;
+    r.Gc = Gc;
+    r.g = lf_flow_geom(n, T, ll, sl, R, slice_log2, Gc);
+    r.Ptot = r.g.Ptot;
+    return r;
+}
+
+// brute-force waits of producer p before writing offsets [o_lo, o_lo + len) of link j
+static WaitSet brute_producer(const Run &r, uint32_t p, uint32_t j, uint32_t o_lo, uint32_t len) {
+    WaitSet w;
+    for (uint32_t o = o_lo; o < o_lo + len; ++o) {
+        const int64_t P = static_cast<int64_t>(j) * r.sl + o;
+        const int64_t src = P - r.ll;
+        if (src >= 0) w.insert({0, static_cast<uint32_t>(r.slice_of(src)), static_cast<uint32_t>(r.link_of(src) + 1)});
+        const int64_t Q = P - r.R;  // overwritten
+        if (Q >= 0) {
+            const uint32_t tile = static_cast<uint32_t>((Q % r.g.four_n) / 256);
+            w.insert({1, tile % r.Gc, static_cast<uint32_t>(r.step_of(Q)) * r.g.Kc + tile / r.Gc + 1});
+        }
+        const int64_t rl = Q + r.ll;  // its long-lag reader
+        if (rl >= 0 && rl < static_cast<int64_t>(r.Ptot) && r.slice_of(rl) != p)
+            w.insert({0, static_cast<uint32_t>(r.slice_of(rl)), static_cast<uint32_t>(r.link_of(rl) + 1)});
+        const int64_t rs = Q + r.sl;  // its short-lag reader, which reads the ring only in link 0
+        if (rs >= 0 && rs < static_cast<int64_t>(r.sl) && rs < static_cast<int64_t>(r.Ptot) && r.slice_of(rs) != p)
+            w.insert({0, static_cast<uint32_t>(r.slice_of(rs)), 1u});
+    }
+    return w;
+}
+
+static uint32_t slice_len(const Run &r, uint32_t p, uint32_t j) {
+    const uint64_t o_lo = static_cast<uint64_t>(p) << r.slice_log2;
+    uint64_t o_hi = o_lo + (1ull << r.slice_log2);
+    if (o_hi > r.sl) o_hi = r.sl;
+    const uint64_t P_lo = static_cast<uint64_t>(j) * r.sl;
+    if (P_lo + o_lo >= r.Ptot) return 0;
+    if (P_lo + o_hi > r.Ptot) o_hi = r.Ptot - P_lo;
+    return static_cast<uint32_t>(o_hi - o_lo);
+}
+
+static int check_waits(const Run &r) {
     int bad = 0;
-    for (uint32_t s = 0; s < steps; ++s)
-        for (uint32_t c = 0; c < g.n_ctiles; ++c) {
-            const uint32_t count = static_cast<uint32_t>((c + 1) * B <= n ? B : n - c * B);
-            std::set<std::pair<int64_t, uint32_t>> brute, got;
-            for (uint64_t off = 4 * c * B; off < 4 * c * B + 4ull * count; ++off) {
-                const int64_t p = static_cast<int64_t>(s * four_n + off);
-                for (int64_t lag : {static_cast<int64_t>(sl), static_cast<int64_t>(ll)}) {
-                    const int64_t q = p - lag;
-                    if (q < 0) continue;
-                    brute.insert({q / static_cast<int64_t>(four_n),
-                                  static_cast<uint32_t>((q % static_cast<int64_t>(four_n)) / (4 * B))});
-                }
+    const LfFlowGeom &g = r.g;
+    for (uint32_t p = 0; p < g.n_slices; ++p) {
+        const uint32_t o_lo = p << r.slice_log2;
+        int64_t sR;
+        uint64_t oR;
+        lf_consumer_coord0(g, o_lo, r.R, sR, oR);
+        for (uint32_t j = 0; j < g.n_links; ++j) {
+            // incremental coordinate vs a fresh division
+            const int64_t Q = static_cast<int64_t>(j) * r.sl + o_lo - r.R;
+            int64_t s_ref = Q / static_cast<int64_t>(g.four_n), o_ref = Q - s_ref * static_cast<int64_t>(g.four_n);
+            if (o_ref < 0) {
+                o_ref += g.four_n;
+                --s_ref;
             }
-            lf_tile_sources(g, s, c, count, [&](uint32_t s2, uint32_t c2) {
-                got.insert({static_cast<int64_t>(s2), c2});
-                return true;
-            });
-            if (brute != got) {
-                if (bad < 5) std::printf("mismatch n=%llu B=%llu ll=%u sl=%u tile (%u,%u)\n", (unsigned long long)n,
-                                         (unsigned long long)B, ll, sl, s, c);
+            if (s_ref != sR || static_cast<uint64_t>(o_ref) != oR) {
+                if (bad < 5) std::printf("coordinate mismatch link %u slice %u\n", j, p);
                 ++bad;
             }
+            const uint32_t len = slice_len(r, p, j);
+            if (len) {
+                WaitSet got;
+                lf_producer_waits(
+                    g, p, j, o_lo, len, sR, oR,
+                    [&](uint32_t s, uint32_t need) { got.insert({0, s, need}); return true; },
+                    [&](uint32_t w, uint32_t need) { got.insert({1, w, need}); return true; });
+                if (got != brute_producer(r, p, j, o_lo, len)) {
+                    if (bad < 5)
+                        std::printf("producer waits differ: n=%llu ll=%u sl=%u R=%u T=%u p=%u link=%u\n",
+                                    (unsigned long long)r.n, r.ll, r.sl, r.R, 1u << r.slice_log2, p, j);
+                    ++bad;
+                }
+            }
+            lf_consumer_coord_next(g, sR, oR);
         }
+    }
+    // consumer tiles
+    for (uint32_t c = 0; c < g.n_ctiles; ++c) {
+        const uint64_t count = (c + 1) * 64ull <= r.n ? 64 : r.n - 64ull * c;
+        int64_t link = static_cast<int64_t>((256ull * c) / r.sl);
+        uint32_t off = static_cast<uint32_t>((256ull * c) % r.sl);
+        for (uint32_t s = 0; s < r.T; ++s) {
+            const uint64_t P0 = s * g.four_n + 256ull * c;
+            if (link != static_cast<int64_t>(P0 / r.sl) || off != P0 % r.sl) {
+                if (bad < 5) std::printf("tile coordinate mismatch\n");
+                ++bad;
+            }
+            WaitSet got, brute;
+            lf_walk_producers(g, link, off, static_cast<uint32_t>(4 * count), [&](uint32_t sl_, uint32_t l) {
+                got.insert({0, sl_, l + 1});
+                return true;
+            });
+            for (uint64_t P = P0; P < P0 + 4 * count; ++P)
+                brute.insert({0, static_cast<uint32_t>(r.slice_of(P)), static_cast<uint32_t>(r.link_of(P) + 1)});
+            if (got != brute) {
+                if (bad < 5) std::printf("consumer waits differ: tile %u step %u\n", c, s);
+                ++bad;
+            }
+            lf_link_coord_next_step(g, link, off);
+        }
+    }
+    return bad;
+}
+
+// ---- protocol simulation ----------------------------------------------------------------------
+static uint64_t rng_state = 88172645463325252ull;
+static uint32_t rnd(uint32_t m) {
+    rng_state ^= rng_state << 13;
+    rng_state ^= rng_state >> 7;
+    rng_state ^= rng_state << 17;
+    return static_cast<uint32_t>(rng_state % m);
+}
+
+static int simulate(const Run &r, uint32_t nb, uint32_t slot0) {
+    const LfFlowGeom &g = r.g;
+    const uint32_t R = r.R;
+    // the sequential sequence: positions -ll .. Ptot-1
+    std::vector<uint32_t> seq(r.ll + r.Ptot);
+    for (uint32_t i = 0; i < r.ll; ++i) seq[i] = 2654435761u * (i + 1) + 12345u;
+    for (uint64_t P = 0; P < r.Ptot; ++P) seq[r.ll + P] = seq[r.ll + P - r.ll] + seq[r.ll + P - r.sl];
+    auto expect = [&](int64_t P) { return seq[static_cast<size_t>(P + r.ll)]; };
+    auto slot = [&](int64_t P) { return static_cast<uint32_t>(((static_cast<int64_t>(slot0) + P) % R + R) % R); };
+    std::vector<int64_t> tag(R);
+    std::vector<uint32_t> val(R);
+    for (int64_t P = -static_cast<int64_t>(R); P < 0; ++P) {
+        tag[slot(P)] = P;
+        val[slot(P)] = P >= -static_cast<int64_t>(r.ll) ? expect(P) : 0u;
+    }
+    const uint32_t Gp = g.n_slices, Gc = r.Gc;
+    std::vector<uint32_t> prod(Gp, 0), cons(Gc, 0);
+    struct Producer {
+        uint32_t j = 0;
+        int phase = 0;  // 0: waits + loads, 1: stores + publish
+        bool init = false;
+        std::vector<uint32_t> chain, src;
+        int64_t sR = 0;
+        uint64_t oR = 0;
+    };
+    std::vector<Producer> P(Gp);
+    for (uint32_t p = 0; p < Gp; ++p) {
+        P[p].chain.assign(1u << r.slice_log2, 0);
+        P[p].src.assign((1u << r.slice_log2) * nb, 0);
+        lf_consumer_coord0(g, p << r.slice_log2, R, P[p].sR, P[p].oR);
+    }
+    std::vector<uint32_t> C(Gc, 0), Ck(Gc, 0);  // next step, next tile of it
+    int bad = 0;
+    auto read = [&](int64_t pos) {
+        const uint32_t s = slot(pos);
+        if (tag[s] != pos) {
+            if (bad < 5) std::printf("stale read: wanted %lld found %lld\n", (long long)pos, (long long)tag[s]);
+            ++bad;
+        }
+        return val[s];
+    };
+    for (;;) {
+        std::vector<std::pair<int, uint32_t>> ready;
+        bool all_done = true;
+        for (uint32_t p = 0; p < Gp; ++p) {
+            Producer &q = P[p];
+            if (q.j >= g.n_links) continue;
+            all_done = false;
+            if (q.phase == 1) {
+                ready.push_back({0, p});
+                continue;
+            }
+            bool ok = true;
+            int64_t sR = q.sR;
+            uint64_t oR = q.oR;
+            for (uint32_t jj = 0; jj < nb && q.j + jj < g.n_links && ok; ++jj) {
+                const uint32_t len = slice_len(r, p, q.j + jj);
+                if (len)
+                    ok = lf_producer_waits(
+                        g, p, q.j + jj, p << r.slice_log2, len, sR, oR,
+                        [&](uint32_t s, uint32_t need) { return prod[s] >= need; },
+                        [&](uint32_t w, uint32_t need) { return cons[w] >= need; });
+                lf_consumer_coord_next(g, sR, oR);
+            }
+            if (ok) ready.push_back({0, p});
+        }
+        for (uint32_t w = 0; w < Gc; ++w) {
+            if (C[w] >= r.T) continue;
+            all_done = false;
+            const uint32_t c = w + Ck[w] * Gc;
+            bool ok = true;
+            if (c < g.n_ctiles) {
+                const uint64_t count = (c + 1) * 64ull <= r.n ? 64 : r.n - 64ull * c;
+                const uint64_t P0 = C[w] * g.four_n + 256ull * c;
+                ok = lf_walk_producers(g, static_cast<int64_t>(P0 / r.sl), static_cast<uint32_t>(P0 % r.sl),
+                                       static_cast<uint32_t>(4 * count),
+                                       [&](uint32_t s, uint32_t l) { return prod[s] >= l + 1; });
+            }
+            if (ok) ready.push_back({1, w});
+        }
+        if (all_done) break;
+        if (ready.empty()) {
+            std::printf("deadlock: n=%llu ll=%u sl=%u R=%u\n", (unsigned long long)r.n, r.ll, r.sl, R);
+            return bad + 1;
+        }
+        const auto pick = ready[rnd(static_cast<uint32_t>(ready.size()))];
+        if (pick.first == 0) {
+            Producer &q = P[pick.second];
+            const uint32_t p = pick.second, o_lo = p << r.slice_log2, Tsl = 1u << r.slice_log2;
+            const uint32_t jn = q.j + nb <= g.n_links ? nb : g.n_links - q.j;
+            if (q.phase == 0) {
+                if (!q.init) {  // short-lag sources of link 0 come from the ring, once
+                    for (uint32_t o = o_lo; o < o_lo + Tsl && o < r.sl; ++o)
+                        q.chain[o - o_lo] = read(static_cast<int64_t>(o) - r.sl);
+                    q.init = true;
+                }
+                for (uint32_t jj = 0; jj < jn; ++jj) {
+                    const uint32_t len = slice_len(r, p, q.j + jj);
+                    for (uint32_t o = o_lo; o < o_lo + len; ++o)
+                        q.src[jj * Tsl + (o - o_lo)] = read(static_cast<int64_t>(q.j + jj) * r.sl + o - r.ll);
+                }
+                q.phase = 1;
+            } else {
+                for (uint32_t jj = 0; jj < jn; ++jj) {
+                    const uint32_t len = slice_len(r, p, q.j + jj);
+                    for (uint32_t o = o_lo; o < o_lo + len; ++o) {
+                        const int64_t pos = static_cast<int64_t>(q.j + jj) * r.sl + o;
+                        uint32_t &ch = q.chain[o - o_lo];
+                        ch += q.src[jj * Tsl + (o - o_lo)];
+                        if (ch != expect(pos)) {
+                            if (bad < 5) std::printf("wrong value at %lld\n", (long long)pos);
+                            ++bad;
+                        }
+                        tag[slot(pos)] = pos;
+                        val[slot(pos)] = ch;
+                    }
+                    lf_consumer_coord_next(g, q.sR, q.oR);
+                }
+                q.j += jn;
+                prod[p] = q.j;
+                q.phase = 0;
+            }
+        } else {
+            const uint32_t w = pick.second;
+            const uint32_t c = w + Ck[w] * Gc;
+            if (c < g.n_ctiles) {
+                const uint64_t count = (c + 1) * 64ull <= r.n ? 64 : r.n - 64ull * c;
+                const uint64_t P0 = C[w] * g.four_n + 256ull * c;
+                for (uint64_t pos = P0; pos < P0 + 4 * count; ++pos)
+                    if (read(static_cast<int64_t>(pos)) != expect(static_cast<int64_t>(pos))) {
+                        if (bad < 5) std::printf("consumer read a wrong value at %llu\n", (unsigned long long)pos);
+                        ++bad;
+                    }
+            }
+            if (c >= g.n_ctiles || Ck[w] + 1 == g.Kc) {  // step done
+                cons[w] = (C[w] + 1) * g.Kc;
+                ++C[w];
+                Ck[w] = 0;
+            } else {
+                cons[w] = C[w] * g.Kc + Ck[w] + 1;
+                ++Ck[w];
+            }
+        }
+    }
     return bad;
 }
 
 int main() {
     int bad = 0;
-    const uint32_t lags[][2] = {{7, 3}, {17, 5}, {2281, 1252}, {4423, 3004}, {9689, 5502}};
-    const uint64_t ns[] = {1, 2, 3, 5, 31, 64, 65, 100, 255, 256, 257, 1000, 3001};
-    for (auto &lag : lags)
-        for (uint64_t n : ns)
-            for (uint32_t bl : {0u, 2u, 6u, 8u}) bad += check(n, bl, lag[0], lag[1], 8);
-    // the configuration-2 shape: ll, sl of Table I's last row, n = 1e6, 256-oscillator tiles
-    bad += check(1000000, 8, 3021377, 1010202, 3);
+    const uint32_t lags[][2] = {{7, 3}, {17, 5}, {31, 13}, {100, 33}, {2281, 1252}, {4423, 3004}};
+    const uint64_t ns[] = {1, 2, 5, 63, 64, 65, 100, 257, 1000};
+    for (auto &lag : lags) {
+        const uint32_t ll = lag[0], sl = lag[1];
+        const uint32_t nbmax = ll / sl >= 2 ? 2 : 1;
+        for (uint32_t nb = 1; nb <= nbmax; ++nb) {
+            // the smallest ring allowed for nb links per iteration, and larger ones
+            const uint32_t Rmin = std::max(ll + nb * sl, nb * sl + 255);
+            for (uint64_t n : ns)
+                for (uint32_t extra : {0u, 1u, 7u, ll + sl}) {
+                    const uint32_t R = Rmin + extra;
+                    for (uint32_t sl2 : {0u, 2u, 6u}) {
+                        if ((1u << sl2) > sl && sl2) continue;
+                        for (uint32_t Gc : {1u, 3u}) {
+                            const uint32_t T = n > 300 ? 3 : 9;
+                            const Run r = make_run(n, T, ll, sl, R, sl2, Gc);
+                            if (nb == 1) bad += check_waits(r);
+                            if (r.Ptot <= 40000 && n <= 257)
+                                for (uint32_t rep = 0; rep < 2; ++rep) bad += simulate(r, nb, rnd(R));
+                        }
+                    }
+                }
+        }
+    }
+    // the configuration-2 shape: Table I's last row, n = 1e6, 1024-offset slices, 3072 consumer waves
+    {
+        const Run r = make_run(1000000, 2, 3021377, 1010202, 2 * (3021377 + 1010202), 10, 3072);
+        bad += check_waits(r);
+    }
     std::printf(bad ? "FAILED %d\n" : "ok\n", bad);
     return bad ? 1 : 0;
 }

@@ -50,11 +50,14 @@ def test_state_bytes():
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("taus", n_streams=1000)), C.byref(out)) == 0 and out.value == 16000
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("ran2", n_streams=1000)), C.byref(out)) == 0 and out.value == 140000
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=2281, sl=1252)), C.byref(out)) == 0
-    assert out.value == 64 + 8 * (2281 + 1252)
+    assert out.value == 64 + 4 * 2 * (2281 + 1252)
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=2281, sl=1252, wave=101)), C.byref(out)) == 0
-    assert out.value == 64 + 8 * (2281 + 1252)  # default ring ll + sl whatever the wave width
+    assert out.value == 64 + 4 * 2 * (2281 + 1252)  # default ring 2 (ll + sl) whatever the wave width
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=2281, sl=1252, wave=101, ring=2400)), C.byref(out)) == 0
-    assert out.value == 64 + 8 * 2400
+    assert out.value == 64 + 4 * 2400
+    # lags whose doubled sum reaches 2^30 fall back to a ring of ll + sl
+    assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=600_000_001, sl=1000)), C.byref(out)) == 0
+    assert out.value == 64 + 4 * (600_000_001 + 1000)
     # ring shorter than ll + W (W = 100 after rounding down to a multiple of 4)
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=2281, sl=1252, wave=101, ring=2380)),
                                    C.byref(out)) == R.ELAG

@@ -1,5 +1,7 @@
-"""CPU check of the tile-dependency geometry of the dataflow lagged-Fibonacci LD kernel
-(paper_1003_1123_amd/csrc/lf_flow.hpp) against brute force; compiled with the host compiler."""
+"""CPU check of the waits of the persistent lagged-Fibonacci LD run (paper_1003_1123_amd/csrc/lf_flow.hpp):
+the waits against brute force, and a simulation of the whole producer/consumer protocol under random
+interleavings (every read finds its position, every value equals the sequential recurrence, no
+deadlock).  Compiled with the host compiler."""
 import os
 import shutil
 import subprocess
@@ -10,7 +12,7 @@ import pytest
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def test_tile_sources_match_brute_force():
+def test_waits_and_protocol_simulation():
     cxx = shutil.which("g++") or shutil.which("c++")
     if cxx is None:
         pytest.skip("no host C++ compiler")
