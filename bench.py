@@ -43,10 +43,10 @@ HBM_PEAK_GBS = 8000.0
 # factor 2; WRITE_SIZE 1 GiB: factor 1).  Valid only for the kernel sources they were taken on (the
 # SHA-256 of the listed files); otherwise the traffic is reported as null.
 COUNTER_TRAFFIC = {
-    "lf_ld_flow_kernel": {
+    "lf_pc_kernel": {
         "sources": ("k_lf.hip", "lf_flow.hpp", "device.hpp", "internal.hpp"),
-        "sha256": "cef1bdf38e2bea7d46ea14a80746d841c5d3bbdaea4406f1890c0f2186bcb79a",
-        "fetch_bytes": 334223410 * 1024 * 2, "write_bytes": 327220875 * 1024,
+        "sha256": "ac6640ab7a98918505c5e03fac6e86d5c86889dbf0adf8b3f3b1fdfda4fac4aa",
+        "fetch_bytes": 170979857 * 1024 * 2, "write_bytes": 193965481 * 1024,
     },
 }
 
@@ -136,7 +136,7 @@ def roofline_entry(kind, ms_run, N, T, lf_path=None):
     osc_steps = N * T
     if kind == "lf":
         if lf_path == "dataflow":
-            kernel, launches, per_os = "lf_ld_flow_kernel", 1, LF_ALGO_BYTES_PER_OSC_STEP
+            kernel, launches, per_os = "lf_pc_kernel", 1, LF_ALGO_BYTES_PER_OSC_STEP
         else:
             kernel, launches = "lf_ld_phase_kernel", 4 * T
             per_os = LF_ALGO_BYTES_PER_OSC_STEP + LF_WAVE_XV_BYTES_PER_OSC_STEP
