@@ -272,7 +272,7 @@ int try_lf_flow(const Gen &g, void *d_state, const RunLayout &L, uint32_t n_step
     if (n == 0 || g.sl < 256 || g.R >= (1u << 30)) return 0;
     // producers advance one link (sl positions) at a time; the ring must keep the readers of what
     // they overwrite behind them
-    if (g.R < static_cast<uint64_t>(g.ll) + g.sl || g.R < static_cast<uint64_t>(g.sl) + 255) return 0;
+    if (g.R < static_cast<uint64_t>(g.ll) + g.sl) return 0;
     const uint64_t Ptot = 4ull * n * n_steps;
     if ((Ptot + g.sl - 1) / g.sl >= (1ull << 31)) return 0;
     const int cus = device_cus();
@@ -284,7 +284,7 @@ int try_lf_flow(const Gen &g, void *d_state, const RunLayout &L, uint32_t n_step
     if (static_cast<uint64_t>(np) * cus * kLfFlowSliceMax < g.sl) return 0;
     const uint32_t Gp = np * static_cast<uint32_t>(cus), Gc = (wpb - np) * static_cast<uint32_t>(cus);
     if (Gp > kLfFlowMaxWaves || Gc > kLfFlowMaxWaves) return 0;
-    uint32_t slice_log2 = 6;
+    uint32_t slice_log2 = 8;  // at least 256 offsets: a consumer tile then spans at most two slices
     while ((static_cast<uint64_t>(Gp) << slice_log2) < g.sl) ++slice_log2;
     const LfFlowGeom geom = lf_flow_geom(n, n_steps, g.ll, g.sl, g.R, slice_log2, Gc);
     uint32_t kc = 0;
@@ -293,7 +293,9 @@ int try_lf_flow(const Gen &g, void *d_state, const RunLayout &L, uint32_t n_step
             kc = k;
             break;
         }
-    if (!kc || static_cast<uint64_t>(n_steps + 1) * geom.Kc >= (1ull << 32)) return 0;
+    if (!kc) return 0;
+    // the ring must also hold a consumer step's positions behind the producers (lf_flow.hpp)
+    if (g.R < static_cast<uint64_t>(g.sl) + 256ull * geom.Kc - 1) return 0;
     const size_t lds = static_cast<size_t>(wpb - np) * (geom.Kc * 384u + 256u) * sizeof(float);
     if (lds > 160 * 1024) return 0;
     if (debug_enabled())

@@ -273,29 +273,41 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t v) {
 // flight.  Otherwise link j is published first and only then does the producer block on link
 // j+1's waits: it never blocks with an earlier link unpublished (the no-deadlock argument of
 // lf_flow.hpp with one link per iteration).
+// The waits of link j, 64 per round: from the steady link on, a full slice takes the fixed
+// template of waits (a) and (c) and walks only the consumers (b); otherwise the general form.
 __device__ __forceinline__ uint32_t producer_waits(const LfFlowArgs &a, uint32_t p, uint32_t j, uint32_t o_lo,
-                                                   uint32_t len, int64_t step_R, uint64_t off_R, FlowWaits &w,
-                                                   uint32_t lane, uint32_t round) {
+                                                   uint32_t len, uint32_t width, const LfWaitTemplate &tpl,
+                                                   int64_t step_R, uint64_t off_R, FlowWaits &w, uint32_t lane,
+                                                   uint32_t round) {
     uint32_t idx = 0;
     auto add = [&](const uint32_t *f, uint32_t need) {
         if (idx - 64u * round < 64u) wait_add(w, lane, f, need, 0);
         ++idx;
         return true;
     };
-    if (len)
+    if (!len) return 0;
+    if (len == width && j >= lf_steady_link(a.geom)) {
+#pragma unroll
+        for (uint32_t i = 0; i < 6; ++i)  // constant indices keep the template in registers
+            if (i < tpl.n)
+                add(a.prod + tpl.slice[i] * kLfFlagStride, static_cast<uint32_t>(static_cast<int64_t>(j) + tpl.d[i]));
+        lf_walk_consumers(a.geom, step_R, off_R, len,
+                          [&](uint32_t c, uint32_t need) { return add(a.cons + c * kLfFlagStride, need); });
+    } else {
         lf_producer_waits(
             a.geom, p, j, o_lo, len, step_R, off_R,
             [&](uint32_t s, uint32_t need) { return add(a.prod + s * kLfFlagStride, need); },
             [&](uint32_t c, uint32_t need) { return add(a.cons + c * kLfFlagStride, need); });
+    }
     return idx;  // waits in all
 }
 
 // block until every wait of link j holds (64 per round); false if the run gave up
 __device__ __forceinline__ bool producer_wait_link(const LfFlowArgs &a, uint32_t p, uint32_t j, uint32_t o_lo,
-                                                   uint32_t len, int64_t step_R, uint64_t off_R, FlowWaits &w,
-                                                   uint32_t lane) {
+                                                   uint32_t len, uint32_t width, const LfWaitTemplate &tpl,
+                                                   int64_t step_R, uint64_t off_R, FlowWaits &w, uint32_t lane) {
     for (uint32_t round = 0;; ++round) {
-        const uint32_t total = producer_waits(a, p, j, o_lo, len, step_R, off_R, w, lane, round);
+        const uint32_t total = producer_waits(a, p, j, o_lo, len, width, tpl, step_R, off_R, w, lane, round);
         if (!wait_all(w, lane, a)) return false;
         if (total <= 64u * (round + 1)) return true;
     }
@@ -324,6 +336,8 @@ __device__ __forceinline__ void lf_producer(const LfFlowArgs &a, uint32_t p, uin
     int64_t step_R;
     uint64_t off_R;
     lf_consumer_coord0(g, o_lo, R, step_R, off_R);  // consumer coordinate of (link j, o_lo) - R
+    LfWaitTemplate tpl;
+    lf_wait_template(g, p, o_lo, width, tpl);
     FlowWaits w;
     w.n = 0;
     // kFlowM long-lag loads of a link, always all issued (an unused one reads the link's first
@@ -340,11 +354,11 @@ __device__ __forceinline__ void lf_producer(const LfFlowArgs &a, uint32_t p, uin
     uint32_t total_poll = 0, seen = 0;
     auto poll_link = [&](uint32_t j1, int64_t sR, uint64_t oR) {
         const uint32_t len_j1 = link_len(j1);
-        total_poll = len_j1 ? producer_waits(a, p, j1, o_lo, len_j1, sR, oR, w, lane, 0) : 0u;
+        total_poll = producer_waits(a, p, j1, o_lo, len_j1, width, tpl, sR, oR, w, lane, 0);
         seen = agent_load(lane < w.n ? w.flag : a.status);
     };
     uint32_t len = link_len(0);
-    if (!producer_wait_link(a, p, 0, o_lo, len, step_R, off_R, w, lane)) return;
+    if (!producer_wait_link(a, p, 0, o_lo, len, width, tpl, step_R, off_R, w, lane)) return;
     {
         int64_t sR1 = step_R;
         uint64_t oR1 = off_R;
@@ -380,7 +394,7 @@ __device__ __forceinline__ void lf_producer(const LfFlowArgs &a, uint32_t p, uin
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
             if (lane == 0) agent_store(a.prod + p * kLfFlagStride, j + 1);
             if (!next_len) break;
-            if (!producer_wait_link(a, p, j + 1, o_lo, next_len, next_sR, next_oR, w, lane)) return;
+            if (!producer_wait_link(a, p, j + 1, o_lo, next_len, width, tpl, next_sR, next_oR, w, lane)) return;
         }
         {
             int64_t sR2 = next_sR;
@@ -430,51 +444,34 @@ __device__ __forceinline__ void tile_observe(const LfFlowArgs &a, const float *t
 
 // Consumer wave cw: tiles c = cw + k Gc of 64 oscillators; x, v in LDS as xv[k][6][64]; tr is a
 // 256-word transpose buffer.  Lane l of a tile drives oscillator 64 c + l.
-// position coordinates of a consumer's tiles: tile k lies 256 k Gc positions after tile 0
-struct TileCursor {
-    int64_t link;   // link and offset in it of the tile's first position
-    uint32_t off;
-    uint32_t slot;  // its ring slot
-};
-
-__device__ __forceinline__ void tile_cursor_next(TileCursor &t, const LfFlowGeom &g, uint32_t dq, uint32_t dr,
-                                                 uint32_t dR, uint32_t R) {
-    t.link += dq;
-    t.off += dr;
-    if (t.off >= g.sl) {
-        t.off -= g.sl;
-        ++t.link;
-    }
-    t.slot = wrap_once(t.slot + dR, R);
-}
-
+// Consumer wave cw: the Kc consecutive tiles cw Kc .. (64 oscillators each, lane l of tile k
+// drives oscillator 64 (cw Kc + k) + l); x, v in LDS as xv[k][6][64]; tr is a 256-word transpose
+// buffer.  Per step: wait for the producers of the wave's positions, load them all, publish, then
+// drive the oscillators.
 template <int KC>
 __device__ __forceinline__ void lf_consumer(const LfFlowArgs &a, uint32_t cw, uint32_t lane, float *xv, uint32_t *tr) {
     const LfFlowGeom &g = a.geom;
-    const uint32_t R = a.L.R, Gc = g.Gc, Kc = g.Kc;
+    const uint32_t R = a.L.R, Kc = g.Kc;
     uint32_t *ring = a.L.ring;
-    uint32_t Kw = 0;  // tiles of this wave
-    while (Kw < Kc && cw + Kw * Gc < g.n_ctiles) ++Kw;
-    // 256 Gc positions between consecutive tiles, by the link length and by the ring length
-    const uint64_t gap = 256ull * Gc;
-    const uint32_t dq = static_cast<uint32_t>(gap / g.sl), dr = static_cast<uint32_t>(gap % g.sl);
-    const uint32_t dR = static_cast<uint32_t>(gap % R);
-    TileCursor t0c;  // tile 0 at the current step
-    t0c.link = static_cast<int64_t>((256ull * cw) / g.sl);
-    t0c.off = static_cast<uint32_t>((256ull * cw) % g.sl);
-    t0c.slot = wrap_once(a.L.hdr->slot, R);
-    t0c.slot = wrap_once(t0c.slot + static_cast<uint32_t>((256ull * cw) % R), R);
+    const uint64_t o0 = 64ull * cw * Kc < a.n ? 64ull * cw * Kc : a.n;
+    const uint64_t o1 = 64ull * (cw + 1) * Kc < a.n ? 64ull * (cw + 1) * Kc : a.n;
+    if (o0 >= o1) return;  // no oscillators: no producer ever waits for this wave
+    const uint32_t cnt = static_cast<uint32_t>(4 * (o1 - o0));  // positions per step
+    const uint32_t Kw = static_cast<uint32_t>((o1 - o0 + 63) / 64);
 #pragma unroll 1
-    for (int k = 0; k < KC; ++k) {
-        if (k >= static_cast<int>(Kw)) break;
-        const uint64_t o = 64ull * (cw + k * Gc) + lane;
-        const bool act = o < a.n;
+    for (uint32_t k = 0; k < Kw; ++k) {
+        const uint64_t o = o0 + 64ull * k + lane;
+        const bool act = o < o1;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             xv[(k * 6 + d) * 64 + lane] = act ? a.x[d * a.N + o] : 0.0f;
             xv[(k * 6 + 3 + d) * 64 + lane] = act ? a.v[d * a.N + o] : 0.0f;
         }
     }
+    // the step's first position 4 o0 + s 4n: its link, offset and ring slot
+    int64_t link = static_cast<int64_t>((4 * o0) / g.sl);
+    uint32_t off = static_cast<uint32_t>((4 * o0) % g.sl);
+    uint32_t slot_s = wrap_once(a.L.hdr->slot + static_cast<uint32_t>((4 * o0) % R), R);
     FlowWaits w;
     w.n = 0;
     for (uint32_t s = 0; s < a.n_steps; ++s) {
@@ -482,129 +479,79 @@ __device__ __forceinline__ void lf_consumer(const LfFlowArgs &a, uint32_t cw, ui
         // across the loop
         float *t0buf = a.t0buf;
         asm volatile("" : "+s"(t0buf));
-        const bool obs_now = a.stride && s % a.stride == 0;
+        if (a.stride && s % a.stride == 0) {
 #pragma unroll 1
+            for (uint32_t k = 0; k < Kw; ++k) {
+                const uint64_t o = o0 + 64ull * k + lane;
+                tile_observe(a, t0buf, xv + k * 384, lane, o, o < o1, s, cw * Kc + k);
+            }
+        }
+        if (a.stride && s == a.t0) {
+#pragma unroll 1
+            for (uint32_t k = 0; k < Kw; ++k) {
+                const uint64_t o = o0 + 64ull * k + lane;
+                if (o < o1)
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        t0buf[d * a.N + o] = xv[(k * 6 + d) * 64 + lane];
+                        t0buf[(3 + d) * a.N + o] = xv[(k * 6 + 3 + d) * 64 + lane];
+                    }
+            }
+        }
+        // the producers of this step's positions (a few slices: one wait per lane)
+        lf_walk_producers(g, link, off, cnt, [&](uint32_t sl_, uint32_t l) {
+            wait_add(w, lane, a.prod + sl_ * kLfFlagStride, l + 1, 0);
+            return true;
+        });
+        if (!wait_all(w, lane, a)) return;
+        uint32_t words[KC][4];
+#pragma unroll
+        for (int k = 0; k < KC; ++k)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint32_t q = 256u * k + lane + 64u * r;
+                words[k][r] = q < cnt ? ring_get(ring, wrap_once(slot_s + q, R)) : 0u;
+            }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the loads have returned: the slots are free
+        if (lane == 0) agent_store(a.cons + cw * kLfFlagStride, s + 1);
+#pragma unroll
         for (int k = 0; k < KC; ++k) {
             if (k >= static_cast<int>(Kw)) break;
-            const uint32_t c = cw + k * Gc;
-            const uint64_t o = 64ull * c + lane;
-            const bool act = o < a.n;
-            if (obs_now) tile_observe(a, t0buf, xv + k * 384, lane, o, act, s, c);
-            if (a.stride && s == a.t0 && act)
+            // lane-contiguous words -> oscillator lane's four words
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tr[lane + 64 * r] = words[k][r];
+            uint32_t u[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) u[r] = tr[4 * lane + r];
+            if (o0 + 64ull * k + lane < o1) {
+                float gf[3];
+                gaussian_forces(u[0], u[1], u[2], u[3], gf[0], gf[1], gf[2]);
+                float *t = xv + k * 384;
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    t0buf[d * a.N + o] = xv[(k * 6 + d) * 64 + lane];
-                    t0buf[(3 + d) * a.N + o] = xv[(k * 6 + 3 + d) * 64 + lane];
+                    float x = t[d * 64 + lane], v = t[(3 + d) * 64 + lane];
+                    ld_update(a.coef, x, v, gf[d]);
+                    t[d * 64 + lane] = x;
+                    t[(3 + d) * 64 + lane] = v;
                 }
+            }
         }
-        // the step's numbers: poll the waits of the remaining tiles together, load and publish the
-        // prefix of tiles whose waits hold, repeat
-        uint32_t kd = 0, spins = 0;
-        while (kd < Kw) {
-            uint32_t cut = Kw;
-            TileCursor tc = t0c;
-#pragma unroll
-            for (int k = 0; k < KC; ++k) {  // compile-time k keeps the per-tile values in registers
-                if (cut == Kw && k >= static_cast<int>(kd) && k < static_cast<int>(Kw)) {
-                    const uint64_t first = 64ull * (cw + k * Gc);
-                    const uint32_t cnt4 = 4u * static_cast<uint32_t>(first + 64 <= a.n ? 64 : a.n - first);
-                    bool fits = true;
-                    lf_walk_producers(g, tc.link, tc.off, cnt4, [&](uint32_t sl_, uint32_t l) {
-                        if (w.n == 64) {
-                            fits = false;
-                            return false;
-                        }
-                        wait_add(w, lane, a.prod + sl_ * kLfFlagStride, l + 1, k);
-                        return true;
-                    });
-                    if (!fits) cut = k;
-                }
-                tile_cursor_next(tc, g, dq, dr, dR, R);
-            }
-            uint32_t bad = cut;
-            if (lane < w.n && agent_load(w.flag) < w.need) bad = w.tile;
-            w.n = 0;
-            const uint32_t done = wave_min(bad);
-            if (done == kd) {
-                if (++spins > a.spin_limit || ((spins & 15u) == 0 && agent_load(a.status) != 0u)) {
-                    if (lane == 0) agent_store(a.status, 1u);
-                    return;
-                }
-                poll_pause(spins);
-                continue;
-            }
-            spins = 0;
-            // load and drive the ready tiles [kd, done) in halves of at most 4 tiles (bounded
-            // registers); a half is published once its loads have returned
-#pragma unroll
-            for (int k0 = 0; k0 < KC; k0 += 4) {
-                if (k0 + 4 <= static_cast<int>(kd) || k0 >= static_cast<int>(done)) continue;
-                TileCursor tc = t0c;
-#pragma unroll
-                for (int k = 0; k < k0; ++k) tile_cursor_next(tc, g, dq, dr, dR, R);
-                uint32_t words[4][4];
-#pragma unroll
-                for (int kk = 0; kk < 4; ++kk) {
-                    const int k = k0 + kk;
-                    const uint64_t first = 64ull * (cw + k * Gc);
-                    const uint32_t cnt4 =
-                        first < a.n ? 4u * static_cast<uint32_t>(first + 64 <= a.n ? 64 : a.n - first) : 0u;
-                    const bool mine = k < KC && k >= static_cast<int>(kd) && k < static_cast<int>(done);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const uint32_t q = lane + 64u * r;
-                        words[kk][r] = (mine && q < cnt4) ? ring_get(ring, wrap_once(tc.slot + q, R)) : 0u;
-                    }
-                    tile_cursor_next(tc, g, dq, dr, dR, R);
-                }
-                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the loads have returned: the slots are free
-                const uint32_t upto = static_cast<uint32_t>(k0 + 4) < done ? static_cast<uint32_t>(k0 + 4) : done;
-                if (lane == 0) agent_store(a.cons + cw * kLfFlagStride, s * Kc + upto);
-#pragma unroll
-                for (int kk = 0; kk < 4; ++kk) {
-                    const int k = k0 + kk;
-                    if (k >= KC || k < static_cast<int>(kd) || k >= static_cast<int>(done)) continue;
-                    const uint64_t first = 64ull * (cw + k * Gc);
-                    // lane-contiguous words -> oscillator lane's four words
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) tr[lane + 64 * r] = words[kk][r];
-                    uint32_t u[4];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) u[r] = tr[4 * lane + r];
-                    if (first + lane < a.n) {
-                        float gf[3];
-                        gaussian_forces(u[0], u[1], u[2], u[3], gf[0], gf[1], gf[2]);
-                        float *t = xv + k * 384;
-#pragma unroll
-                        for (int d = 0; d < 3; ++d) {
-                            float x = t[d * 64 + lane], v = t[(3 + d) * 64 + lane];
-                            ld_update(a.coef, x, v, gf[d]);
-                            t[d * 64 + lane] = x;
-                            t[(3 + d) * 64 + lane] = v;
-                        }
-                    }
-                }
-            }
-            kd = done;
-        }
-        lf_link_coord_next_step(g, t0c.link, t0c.off);
-        t0c.slot = wrap_once(t0c.slot + a.step_adv, R);
+        slot_s = wrap_once(slot_s + a.step_adv, R);
+        lf_link_coord_next_step(g, link, off);
     }
     float *t0buf = a.t0buf, *xo = a.x, *vo = a.v;
     asm volatile("" : "+s"(t0buf), "+s"(xo), "+s"(vo));
-    if (a.stride && a.n_steps % a.stride == 0)
+    if (a.stride && a.n_steps % a.stride == 0) {
 #pragma unroll 1
-        for (int k = 0; k < KC; ++k) {
-            if (k >= static_cast<int>(Kw)) break;
-            const uint32_t c = cw + k * Gc;
-            const uint64_t o = 64ull * c + lane;
-            tile_observe(a, t0buf, xv + k * 384, lane, o, o < a.n, a.n_steps, c);
+        for (uint32_t k = 0; k < Kw; ++k) {
+            const uint64_t o = o0 + 64ull * k + lane;
+            tile_observe(a, t0buf, xv + k * 384, lane, o, o < o1, a.n_steps, cw * Kc + k);
         }
+    }
 #pragma unroll 1
-    for (int k = 0; k < KC; ++k) {
-        if (k >= static_cast<int>(Kw)) break;
-        const uint64_t o = 64ull * (cw + k * Gc) + lane;
-        if (o < a.n)
+    for (uint32_t k = 0; k < Kw; ++k) {
+        const uint64_t o = o0 + 64ull * k + lane;
+        if (o < o1)
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 xo[d * a.N + o] = xv[(k * 6 + d) * 64 + lane];

@@ -9,9 +9,9 @@
 //    of two).  Its short-lag source y_{P-sl} is its own number of the previous link, so only the
 //    long-lag source y_{P-ll} is read from the ring.  After storing link j it publishes
 //    prod[p] = j + 1 (links done).
-//  * Consumer wave w owns the tiles c = w + k Gc (k < Kc) of 64 oscillators (256 positions) of
-//    every step and handles them in that order; once tile k of step s is loaded it publishes
-//    cons[w] = s Kc + k + 1 (tiles done, counting Kc per step).
+//  * Consumer wave w owns the Kc consecutive tiles c = w Kc .. w Kc + Kc - 1 of 64 oscillators
+//    (256 positions each) of every step; once all its numbers of step s are loaded it publishes
+//    cons[w] = s + 1 (steps done).
 //
 // A producer handles nb links per iteration (nb sl <= ll, so their long-lag sources lie before
 // them) and publishes once per iteration.
@@ -23,15 +23,15 @@
 //   (c) the producer of P - R + ll, which reads P - R as its long-lag source (it is this producer's
 //       own earlier link when R = ll + sl);
 //   (d) for P - R + sl in link 0: its producer, which reads P - R from the ring once at the start.
-// A consumer of tile (s, c) waits for the producers of its 4 x 64 positions.
+// A consumer wave's step waits for the producers of its (at most 256 Kc) positions.
 //
-// No deadlock, given R >= ll + nb sl and R >= nb sl + 255: every wait of an iteration over links
-// [j0, j0 + nb) is for producers' iterations that end by link j0 (a: sources lie nb sl back; c: the
-// readers of P - R lie R - ll >= nb sl back; d: P - R + sl in link 0 puts P beyond link nb) or for
-// consumer tiles lying wholly before link j0 (b: a tile ends within 255 positions of P - R).  A
-// consumer tile waits only for the producers of its own positions, and a consumer never holds a
-// loaded tile unpublished while it waits.  So every wait points to earlier work, and with all waves
-// resident the run always progresses.
+// No deadlock, given R >= ll + nb sl and R >= nb sl + 256 Kc - 1: every wait of an iteration over
+// links [j0, j0 + nb) is for producers' iterations that end by link j0 (a: sources lie nb sl back;
+// c: the readers of P - R lie R - ll >= nb sl back; d: P - R + sl in link 0 puts P beyond link nb)
+// or for a consumer step whose positions lie wholly before link j0 (b: a consumer's positions of a
+// step end within 256 Kc - 1 positions of P - R).  A consumer waits only for the producers of its
+// own positions and holds nothing while it waits.  So every wait points to earlier work, and with
+// all waves resident the run always progresses.
 //
 // Plain C++, so that the host and a CPU test can use it as well as the kernels.
 #pragma once
@@ -64,7 +64,7 @@ struct LfFlowGeom {
     uint32_t n_links;     // ceil(Ptot / sl)
     uint32_t n_ctiles;    // consumer tiles (64 oscillators) per step
     uint32_t Gc;          // consumer waves
-    uint32_t Kc;          // tiles per consumer wave per step (its progress counts Kc per step)
+    uint32_t Kc;          // consecutive tiles per consumer wave per step
     LfLag ll, R, R_ll, R_sl;  // ll, R, R - ll, R - sl
 };
 
@@ -133,21 +133,17 @@ RNGLD_HD inline bool lf_walk_producers(const LfFlowGeom &g, int64_t link, uint32
     return true;
 }
 
-// visit(wave, need) for every consumer tile holding a run position of [(step, off), + len), where
-// off < four_n is the offset within the step and need = step Kc + k + 1 the wave's progress once
-// that tile (its k-th) is loaded; step < 0 is skipped
+// visit(wave, need) for every consumer wave holding a run position of [(step, off), + len), where
+// off < four_n is the offset within the step and need = step + 1; step < 0 is skipped
 template <class Visit>
 RNGLD_HD inline bool lf_walk_consumers(const LfFlowGeom &g, int64_t step, uint64_t off, uint32_t len, Visit &&visit) {
+    const uint64_t span = 256ull * g.Kc;  // positions of one wave per step
     while (len > 0) {
-        const uint64_t tile = off >> 8;
-        uint64_t end = (tile + 1) << 8;
+        const uint64_t wave = off / span;
+        uint64_t end = (wave + 1) * span;
         if (end > g.four_n) end = g.four_n;
         const uint32_t take = end - off < len ? static_cast<uint32_t>(end - off) : len;
-        if (step >= 0) {
-            const uint32_t t = static_cast<uint32_t>(tile);
-            const uint32_t k = t / g.Gc;
-            if (!visit(t - k * g.Gc, static_cast<uint32_t>(step) * g.Kc + k + 1)) return false;
-        }
+        if (step >= 0 && !visit(static_cast<uint32_t>(wave), static_cast<uint32_t>(step) + 1)) return false;
         len -= take;
         off += take;
         if (off == g.four_n) {
@@ -218,6 +214,43 @@ RNGLD_HD inline bool lf_producer_waits(const LfFlowGeom &g, uint32_t p, uint32_t
     lf_back(j, o_lo, g.R_sl, g.sl, link, off);
     return lf_walk_producers(g, link, off, len,
                              [&](uint32_t s, uint32_t l) { return l != 0 || s == p || prod_wait(s, 1u); });
+}
+
+// From link lf_steady_link(g) on, waits (a) and (c) of a producer repeat from link to link with
+// every need one higher, and (d) has none: they are need = j + d for a fixed list of (slice, d).
+struct LfWaitTemplate {
+    uint32_t n;
+    uint32_t slice[6];
+    int32_t d[6];
+};
+
+RNGLD_HD inline uint32_t lf_steady_link(const LfFlowGeom &g) { return g.R.a + 2; }  // > R / sl + 1
+
+RNGLD_HD inline void lf_wait_template(const LfFlowGeom &g, uint32_t p, uint32_t o_lo, uint32_t len, LfWaitTemplate &t) {
+    LfFlowGeom open = g;  // positions of the reference link need not lie inside the run
+    open.Ptot = ~0ull;
+    const uint32_t j = lf_steady_link(g);
+    t.n = 0;
+    int64_t link;
+    uint32_t off;
+    for (int i = 0; i < 6; ++i) {
+        t.slice[i] = 0;
+        t.d[i] = 0;
+    }
+    auto rec = [&](uint32_t s, uint32_t l) {
+        const int32_t d = static_cast<int32_t>(static_cast<int64_t>(l) + 1 - static_cast<int64_t>(j));
+        for (int i = 0; i < 6; ++i)  // constant indices (registers on the GPU)
+            if (static_cast<uint32_t>(i) == t.n) {
+                t.slice[i] = s;
+                t.d[i] = d;
+            }
+        ++t.n;
+        return true;
+    };
+    lf_back(j, o_lo, g.ll, g.sl, link, off);
+    lf_walk_producers(open, link, off, len, rec);
+    lf_back(j, o_lo, g.R_ll, g.sl, link, off);
+    lf_walk_producers(open, link, off, len, [&](uint32_t s, uint32_t l) { return s == p || rec(s, l); });
 }
 
 }  // namespace rngld

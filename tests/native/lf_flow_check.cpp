@@ -56,7 +56,7 @@ static WaitSet brute_producer(const Run &r, uint32_t p, uint32_t j, uint32_t o_l
         const int64_t Q = P - r.R;  // overwritten
         if (Q >= 0) {
             const uint32_t tile = static_cast<uint32_t>((Q % r.g.four_n) / 256);
-            w.insert({1, tile % r.Gc, static_cast<uint32_t>(r.step_of(Q)) * r.g.Kc + tile / r.Gc + 1});
+            w.insert({1, tile / r.g.Kc, static_cast<uint32_t>(r.step_of(Q)) + 1});
         }
         const int64_t rl = Q + r.ll;  // its long-lag reader
         if (rl >= 0 && rl < static_cast<int64_t>(r.Ptot) && r.slice_of(rl) != p)
@@ -113,6 +113,40 @@ static int check_waits(const Run &r) {
                 }
             }
             lf_consumer_coord_next(g, sR, oR);
+        }
+    }
+    // steady-state templates of waits (a) and (c) plus the consumer walk (b) = all waits
+    {
+        for (uint32_t p = 0; p < g.n_slices; ++p) {
+            const uint32_t o_lo = p << r.slice_log2;
+            const uint32_t width = std::min<uint32_t>(1u << r.slice_log2, r.sl - o_lo);
+            LfWaitTemplate t;
+            lf_wait_template(g, p, o_lo, width, t);
+            if (t.n > 6) {
+                std::printf("template overflow\n");
+                ++bad;
+                continue;
+            }
+            int64_t sR;
+            uint64_t oR;
+            lf_consumer_coord0(g, o_lo, r.R, sR, oR);
+            for (uint32_t j = 0; j < g.n_links; ++j) {
+                const uint32_t len = slice_len(r, p, j);
+                if (j >= lf_steady_link(g) && len == width) {
+                    WaitSet got, ref;
+                    for (uint32_t i = 0; i < t.n; ++i) got.insert({0, t.slice[i], static_cast<uint32_t>(static_cast<int64_t>(j) + t.d[i])});
+                    lf_walk_consumers(g, sR, oR, len, [&](uint32_t w, uint32_t need) { got.insert({1, w, need}); return true; });
+                    lf_producer_waits(
+                        g, p, j, o_lo, len, sR, oR,
+                        [&](uint32_t s, uint32_t need) { ref.insert({0, s, need}); return true; },
+                        [&](uint32_t w, uint32_t need) { ref.insert({1, w, need}); return true; });
+                    if (got != ref) {
+                        if (bad < 5) std::printf("template waits differ: ll=%u sl=%u R=%u p=%u link=%u\n", r.ll, r.sl, r.R, p, j);
+                        ++bad;
+                    }
+                }
+                lf_consumer_coord_next(g, sR, oR);
+            }
         }
     }
     // consumer tiles
@@ -183,7 +217,13 @@ static int simulate(const Run &r, uint32_t nb, uint32_t slot0) {
         P[p].src.assign((1u << r.slice_log2) * nb, 0);
         lf_consumer_coord0(g, p << r.slice_log2, R, P[p].sR, P[p].oR);
     }
-    std::vector<uint32_t> C(Gc, 0), Ck(Gc, 0);  // next step, next tile of it
+    std::vector<uint32_t> C(Gc, 0);  // next step
+    auto wave_range = [&](uint32_t w, uint64_t &P0, uint64_t &cnt) {  // positions of wave w in step C[w]
+        const uint64_t c0 = static_cast<uint64_t>(w) * g.Kc;
+        const uint64_t o0 = std::min<uint64_t>(64 * c0, r.n), o1 = std::min<uint64_t>(64 * (c0 + g.Kc), r.n);
+        P0 = C[w] * g.four_n + 4 * o0;
+        cnt = 4 * (o1 - o0);
+    };
     int bad = 0;
     auto read = [&](int64_t pos) {
         const uint32_t s = slot(pos);
@@ -221,15 +261,13 @@ static int simulate(const Run &r, uint32_t nb, uint32_t slot0) {
         for (uint32_t w = 0; w < Gc; ++w) {
             if (C[w] >= r.T) continue;
             all_done = false;
-            const uint32_t c = w + Ck[w] * Gc;
+            uint64_t P0, cnt;
+            wave_range(w, P0, cnt);
             bool ok = true;
-            if (c < g.n_ctiles) {
-                const uint64_t count = (c + 1) * 64ull <= r.n ? 64 : r.n - 64ull * c;
-                const uint64_t P0 = C[w] * g.four_n + 256ull * c;
+            if (cnt)
                 ok = lf_walk_producers(g, static_cast<int64_t>(P0 / r.sl), static_cast<uint32_t>(P0 % r.sl),
-                                       static_cast<uint32_t>(4 * count),
+                                       static_cast<uint32_t>(cnt),
                                        [&](uint32_t s, uint32_t l) { return prod[s] >= l + 1; });
-            }
             if (ok) ready.push_back({1, w});
         }
         if (all_done) break;
@@ -276,24 +314,14 @@ static int simulate(const Run &r, uint32_t nb, uint32_t slot0) {
             }
         } else {
             const uint32_t w = pick.second;
-            const uint32_t c = w + Ck[w] * Gc;
-            if (c < g.n_ctiles) {
-                const uint64_t count = (c + 1) * 64ull <= r.n ? 64 : r.n - 64ull * c;
-                const uint64_t P0 = C[w] * g.four_n + 256ull * c;
-                for (uint64_t pos = P0; pos < P0 + 4 * count; ++pos)
-                    if (read(static_cast<int64_t>(pos)) != expect(static_cast<int64_t>(pos))) {
-                        if (bad < 5) std::printf("consumer read a wrong value at %llu\n", (unsigned long long)pos);
-                        ++bad;
-                    }
-            }
-            if (c >= g.n_ctiles || Ck[w] + 1 == g.Kc) {  // step done
-                cons[w] = (C[w] + 1) * g.Kc;
-                ++C[w];
-                Ck[w] = 0;
-            } else {
-                cons[w] = C[w] * g.Kc + Ck[w] + 1;
-                ++Ck[w];
-            }
+            uint64_t P0, cnt;
+            wave_range(w, P0, cnt);
+            for (uint64_t pos = P0; pos < P0 + cnt; ++pos)
+                if (read(static_cast<int64_t>(pos)) != expect(static_cast<int64_t>(pos))) {
+                    if (bad < 5) std::printf("consumer read a wrong value at %llu\n", (unsigned long long)pos);
+                    ++bad;
+                }
+            cons[w] = ++C[w];
         }
     }
     return bad;
@@ -306,15 +334,17 @@ int main() {
     for (auto &lag : lags) {
         const uint32_t ll = lag[0], sl = lag[1];
         const uint32_t nbmax = ll / sl >= 2 ? 2 : 1;
-        for (uint32_t nb = 1; nb <= nbmax; ++nb) {
-            // the smallest ring allowed for nb links per iteration, and larger ones
-            const uint32_t Rmin = std::max(ll + nb * sl, nb * sl + 255);
+        for (uint32_t nb = 1; nb <= nbmax; ++nb)
             for (uint64_t n : ns)
-                for (uint32_t extra : {0u, 1u, 7u, ll + sl}) {
-                    const uint32_t R = Rmin + extra;
-                    for (uint32_t sl2 : {0u, 2u, 6u}) {
-                        if ((1u << sl2) > sl && sl2) continue;
-                        for (uint32_t Gc : {1u, 3u}) {
+                for (uint32_t Gc : {1u, 3u, 7u}) {
+                    // the smallest ring allowed for nb links per iteration and Kc tiles per consumer
+                    // step, and larger ones
+                    const uint32_t Kc = static_cast<uint32_t>(((n + 63) / 64 + Gc - 1) / Gc);
+                    const uint32_t Rmin = std::max(ll + nb * sl, nb * sl + 256 * Kc - 1);
+                    for (uint32_t extra : {0u, 1u, 7u, ll + sl}) {
+                        const uint32_t R = Rmin + extra;
+                        for (uint32_t sl2 : {0u, 2u, 6u, 8u, 10u}) {
+                            if ((1u << sl2) > sl && sl2) continue;
                             const uint32_t T = n > 300 ? 3 : 9;
                             const Run r = make_run(n, T, ll, sl, R, sl2, Gc);
                             if (nb == 1) bad += check_waits(r);
@@ -323,7 +353,6 @@ int main() {
                         }
                     }
                 }
-        }
     }
     // the configuration-2 shape: Table I's last row, n = 1e6, 1024-offset slices, 3072 consumer waves
     {
