@@ -45,8 +45,8 @@ HBM_PEAK_GBS = 8000.0
 COUNTER_TRAFFIC = {
     "lf_pc_kernel": {
         "sources": ("k_lf.hip", "lf_flow.hpp", "device.hpp", "internal.hpp"),
-        "sha256": "ac6640ab7a98918505c5e03fac6e86d5c86889dbf0adf8b3f3b1fdfda4fac4aa",
-        "fetch_bytes": 170979857 * 1024 * 2, "write_bytes": 193965481 * 1024,
+        "sha256": "f66baa73cbd7a41334b64a6c1c54623a8bf1974b52efb6a3cdb1796a1292bff0",
+        "fetch_bytes": 158271630 * 1024 * 2, "write_bytes": 177948728 * 1024,
     },
 }
 
