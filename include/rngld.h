@@ -50,6 +50,7 @@ extern "C" {
 #define RNGLD_HYBRID_TAUS 0 /* Sec. II.D, Alg. 1: three taus88 components xor an LCG (Eq. 1) */
 #define RNGLD_RAN2 1        /* Sec. II.C, Alg. 2: two L'Ecuyer LCGs + 32-entry Bays-Durham table */
 #define RNGLD_LAGFIB 2      /* Sec. II.E, Alg. 3: y_n = y_{n-ll} + y_{n-sl} mod 2^32, shared */
+#define RNGLD_LCG 3         /* Sec. II.B, Eq. 1: Quick-and-Dirty LCG x = a x + c mod 2^32, per thread */
 
 /*
  * Generator configuration.
@@ -66,6 +67,11 @@ extern "C" {
  *  lf_ring     : LF ring length R in words; 0 selects 2 (ll + sl), or ll + sl when 2 (ll + sl)
  *                reaches 2^30.  Must satisfy ll + W <= R < 2^31.  A fused LD run uses one
  *                persistent launch when sl >= 256 and ll + sl <= R < 2^30.
+ *  lcg_leap    : LCG only.  0: stream j starts from its own seed word (word 0 of stream j).  L > 0:
+ *                the streams divide one sequence (cycle division, Sec. III): stream j starts at
+ *                position j * L of the sequence from word 0 of stream 0.  Eq. 1 has a single cycle
+ *                of 2^32, so every stream is a shift of the same sequence; L = 4 makes stream j + 1
+ *                the same as stream j one LD step later (the inter-stream correlation of Fig. 4b).
  */
 typedef struct rngld_cfg {
     int32_t kind;
@@ -76,6 +82,7 @@ typedef struct rngld_cfg {
     uint64_t n_streams;
     uint64_t stream_base;
     uint64_t lf_ring;
+    uint64_t lcg_leap;
 } rngld_cfg;
 
 /*
@@ -83,6 +90,7 @@ typedef struct rngld_cfg {
  *  HYBRID_TAUS : uint32 z[4][S], component-major: z[c*S + j] is word c of stream j
  *                (c = 0..2 Tausworthe components, 3 = LCG).                 16*S bytes.
  *  RAN2        : int32 r[35][S]: row 0 idum, 1 idum2, 2 iy, 3+t iv[t] (t = 0..31).  140*S bytes.
+ *  LCG         : uint32 x[S].  4*S bytes.
  *  LAGFIB      : 64-byte header { uint64 pos; uint32 slot; uint32 ll, sl, R, W; ... } followed by
  *                uint32 ring[R]; y_n lives in ring[(slot + n - pos) mod R] for the last ll
  *                positions n < pos.  pos counts values generated since rng_init.  64 + 4 R bytes.

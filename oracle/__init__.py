@@ -7,7 +7,8 @@ paper's definitions); this module only marshals numpy arrays through ctypes.  Cl
 of the integrator are in :mod:`oracle.moments`.
 
 Generators follow Zhmurov et al., arXiv:1003.1123: Hybrid Taus (Sec. II.D, Appendix A Alg. 1),
-Ran2 (Sec. II.C, Alg. 2), additive lagged Fibonacci (Sec. II.E Eq. 3, Alg. 3, Table I).
+Ran2 (Sec. II.C, Alg. 2), additive lagged Fibonacci (Sec. II.E Eq. 3, Alg. 3, Table I) and the
+per-stream Quick-and-Dirty LCG (Sec. II.B Eq. 1).
 """
 from __future__ import annotations
 
@@ -24,9 +25,9 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
 
-TAUS, RAN2, LF = 0, 1, 2
-KIND_NAMES = {"taus": TAUS, "ran2": RAN2, "lf": LF}
-STATE_WORDS = {TAUS: 4, RAN2: 35}
+TAUS, RAN2, LF, LCG = 0, 1, 2, 3
+KIND_NAMES = {"taus": TAUS, "ran2": RAN2, "lf": LF, "lcg": LCG}
+STATE_WORDS = {TAUS: 4, RAN2: 35, LCG: 1}
 NOBS = 6
 OBS_NAMES = ("x2", "v2", "xv", "x", "cxx", "cvv")
 
@@ -54,6 +55,7 @@ def lib():
                 "orc_lcg_next": (u32, [u32]),
                 "orc_lcg_advance": (u32, [u32, u64]),
                 "orc_lcg_period": (u64, [u32, u64]),
+                "orc_lcg_seed": (None, [u64, u64, u64, vp]),
                 "orc_taus_component": (u32, [u32, C.c_int]),
                 "orc_taus_component_period": (u64, [u32, C.c_int, u64]),
                 "orc_taus_seed": (None, [u64, u64, vp]),
@@ -189,6 +191,17 @@ def taus_seed(seed: int, streams) -> np.ndarray:
     return st
 
 
+def lcg_seed(seed: int, streams, leap: int = 0) -> np.ndarray:
+    """[S, 1] uint32 per-stream LCG states (leap 0: independent seed words; leap > 0: stream j is
+    the stream-0 seed word advanced j * leap steps)."""
+    streams = np.atleast_1d(np.asarray(streams, dtype=np.uint64))
+    st = np.zeros((len(streams), 1), dtype=np.uint32)
+    L = lib()
+    for n, j in enumerate(streams):
+        L.orc_lcg_seed(seed, int(j), leap, _p(st[n]))
+    return st
+
+
 def ran2_seed(seed: int, streams) -> np.ndarray:
     """[S, 35] int32 Ran2 states (idum, idum2, iy, iv[32])."""
     streams = np.atleast_1d(np.asarray(streams, dtype=np.uint64))
@@ -209,8 +222,10 @@ def find_small_seed_word(seed: int, i: int, floor_val: int, start: int = 0, limi
     return int(lib().orc_find_small_seed_word(seed, i, floor_val, start, limit))
 
 
-def seed_states(kind, seed: int, streams) -> np.ndarray:
+def seed_states(kind, seed: int, streams, leap: int = 0) -> np.ndarray:
     kind = _kind(kind)
+    if kind == LCG:
+        return lcg_seed(seed, streams, leap)
     return taus_seed(seed, streams) if kind == TAUS else ran2_seed(seed, streams)
 
 

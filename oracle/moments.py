@@ -53,6 +53,32 @@ def overdamped_stationary(m, k, gamma, kT, dt):
     return b2 / (1.0 - a * a)
 
 
+def overdamped_transient(m, k, gamma, kT, dt, n_steps, x0=0.0):
+    """Mean and variance of one coordinate of the overdamped scheme (Eq. 5),
+    x_{n+1} = a x_n + b g_n with a = 1 - k h / xi, b^2 = 2 kT h / xi, xi = m gamma, from x_0 = x0:
+    mean_n = x0 a^n, var_n = b^2 (1 - a^(2n)) / (1 - a^2).  Arrays over n = 0..n_steps."""
+    xi = m * gamma
+    a = 1.0 - k * dt / xi
+    b2 = 2.0 * kT * dt / xi
+    n = np.arange(n_steps + 1, dtype=float)
+    return x0 * a**n, b2 * (1.0 - a ** (2 * n)) / (1.0 - a * a)
+
+
+def overdamped_cross(m, k, gamma, kT, dt, t0, taus, x0=0.0):
+    """E[x(t0 + tau) x(t0)] = a^tau E[x(t0)^2] (the noise after t0 is independent of x(t0))."""
+    xi = m * gamma
+    a = 1.0 - k * dt / xi
+    mean, var = overdamped_transient(m, k, gamma, kT, dt, t0, x0)
+    return a ** np.asarray(taus, dtype=float) * (var[t0] + mean[t0] ** 2)
+
+
+def overdamped_continuous(k, xi, kT, t, x0):
+    """Sec. IV's exact Brownian-oscillator forms: <R(t)> = R0 exp(-t/tau) and the equilibrium
+    <R(t)R(0)> = (kT/k) exp(-t/tau), tau = xi/k."""
+    e = np.exp(-np.asarray(t, dtype=float) * k / xi)
+    return x0 * e, (kT / k) * e
+
+
 def transient(m, k, gamma, kT, dt, n_steps, z0=(0.0, 0.0)):
     """Mean and covariance after n = 0..n_steps steps from the deterministic state z0.
 

@@ -71,6 +71,23 @@ uint64_t orc_lcg_period(uint32_t x0, uint64_t limit)
     return 0;
 }
 
+/* One LCG per stream (Sec. II.B used as a per-thread generator, Sec. III).  Stream j's state is
+ * one 32-bit word x; each draw returns the next x_n of Eq. (1).  Seeding reading:
+ *   leap = 0: x = the stream's SplitMix64 seed word (independent offsets in the 2^32 cycle);
+ *   leap > 0: x = the stream-0 seed word advanced j * leap steps, i.e. the streams are windows
+ *             of one sequence that start leap values apart (the correlated seeding that the
+ *             Fig. 4b discussion blames for the repeating pattern).
+ * The advance is reduced modulo the full period 2^32, which the tests confirm by brute force. */
+void orc_lcg_seed(uint64_t seed, uint64_t stream, uint64_t leap, uint32_t *state)
+{
+    if (leap == 0) {
+        *state = orc_seed_word(seed, stream, 0);
+        return;
+    }
+    uint64_t n = (stream * leap) & 0xFFFFFFFFULL;
+    *state = orc_lcg_advance(orc_seed_word(seed, 0, 0), n);
+}
+
 /* ------------------------------------------------------------------------------------------- */
 /* Tausworthe (taus88) component, Eq. (2) of Sec. II.D in L'Ecuyer's fast form, for a
  * characteristic trinomial x^k + x^q + 1 and step size s.  The component keeps its state in the
@@ -367,14 +384,21 @@ void orc_box_muller_many(const uint32_t *words, uint64_t n_pairs, double *out)
 }
 
 /* ------------------------------------------------------------------------------------------- */
-/* Bulk streams.  kind: 0 = Hybrid Taus, 1 = Ran2 (per-stream states), 2 = lagged Fibonacci
- * (one shared window).  Per-stream output layout out[t*S + j] = value t of stream j.
+/* Bulk streams.  kind: 0 = Hybrid Taus, 1 = Ran2, 3 = LCG (per-stream states), 2 = lagged
+ * Fibonacci (one shared window).  Per-stream output layout out[t*S + j] = value t of stream j.
  * Ran2 streams yield iy itself as the integer output. */
-enum { ORC_TAUS = 0, ORC_RAN2 = 1, ORC_LF = 2 };
+enum { ORC_TAUS = 0, ORC_RAN2 = 1, ORC_LF = 2, ORC_LCG = 3 };
+
+static uint32_t lcg_stream_next(uint32_t *x)
+{
+    *x = orc_lcg_next(*x);
+    return *x;
+}
 
 static uint32_t next_word_stream(int kind, void *states, uint64_t j)
 {
     if (kind == ORC_TAUS) return orc_taus_next((uint32_t *)states + 4 * j);
+    if (kind == ORC_LCG) return lcg_stream_next((uint32_t *)states + j);
     return ran2_word(orc_ran2_next((int32_t *)states + 35 * j));
 }
 
@@ -385,6 +409,7 @@ int orc_uniform_streams(int kind, void *states, uint64_t S, uint64_t per_stream,
             uint32_t v;
             if (kind == ORC_TAUS) v = orc_taus_next((uint32_t *)states + 4 * j);
             else if (kind == ORC_RAN2) v = (uint32_t)orc_ran2_next((int32_t *)states + 35 * j);
+            else if (kind == ORC_LCG) v = lcg_stream_next((uint32_t *)states + j);
             else return -1;
             out[t * S + j] = v;
         }

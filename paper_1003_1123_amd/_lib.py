@@ -15,10 +15,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librngld.so")
 
 OK, EINVAL, ELAG, ESIZE, EHIP, ENOTSUP = 0, -1, -2, -3, -4, -5
-HYBRID_TAUS, RAN2, LAGFIB = 0, 1, 2
-KINDS = {"taus": HYBRID_TAUS, "ran2": RAN2, "lf": LAGFIB}
+HYBRID_TAUS, RAN2, LAGFIB, LCG = 0, 1, 2, 3
+KINDS = {"taus": HYBRID_TAUS, "ran2": RAN2, "lf": LAGFIB, "lcg": LCG}
 NOBS = 6
-STATE_ROWS = {HYBRID_TAUS: 4, RAN2: 35}
+STATE_ROWS = {HYBRID_TAUS: 4, RAN2: 35, LCG: 1}
 _ERR_NAMES = {EINVAL: "EINVAL", ELAG: "ELAG", ESIZE: "ESIZE", EHIP: "EHIP", ENOTSUP: "ENOTSUP"}
 
 
@@ -31,7 +31,7 @@ class RngldError(RuntimeError):
 class Cfg(C.Structure):
     _fields_ = [("kind", C.c_int32), ("lf_ll", C.c_uint32), ("lf_sl", C.c_uint32), ("lf_wave", C.c_uint32),
                 ("seed", C.c_uint64), ("n_streams", C.c_uint64), ("stream_base", C.c_uint64),
-                ("lf_ring", C.c_uint64)]
+                ("lf_ring", C.c_uint64), ("lcg_leap", C.c_uint64)]
 
 
 class Params(C.Structure):
@@ -118,9 +118,9 @@ def last_error() -> str:
 # argument helpers
 
 def make_cfg(kind, seed: int = 1234, n_streams: int = 0, stream_base: int = 0, ll: int = 0, sl: int = 0,
-             wave: int = 0, ring: int = 0) -> Cfg:
+             wave: int = 0, ring: int = 0, leap: int = 0) -> Cfg:
     k = KINDS[kind] if isinstance(kind, str) else int(kind)
-    return Cfg(k, ll, sl, wave, seed & (2**64 - 1), n_streams, stream_base, ring)
+    return Cfg(k, ll, sl, wave, seed & (2**64 - 1), n_streams, stream_base, ring, leap)
 
 
 def make_params(m=1.0, k=1.0, gamma=1.0, kT=1.0, dt=0.01, scheme: int = 0) -> Params:

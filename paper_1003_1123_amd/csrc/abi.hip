@@ -55,6 +55,7 @@ struct Gen {
     uint32_t ll = 0, sl = 0, W = 0, R = 0;
     size_t state_bytes = 0;
     uint32_t rows = 0;  // per-thread state rows
+    uint64_t leap = 0;  // LCG cycle division (0: independent seed words)
 };
 
 int check_cfg(const rngld_cfg *cfg, Gen *g) {
@@ -63,10 +64,12 @@ int check_cfg(const rngld_cfg *cfg, Gen *g) {
     switch (cfg->kind) {
         case RNGLD_HYBRID_TAUS:
         case RNGLD_RAN2:
+        case RNGLD_LCG:
             if (cfg->n_streams > kMaxStreams) return fail(RNGLD_EINVAL, "n_streams %llu too large",
                                                           (unsigned long long)cfg->n_streams);
             g->S = cfg->n_streams;
-            g->rows = cfg->kind == RNGLD_HYBRID_TAUS ? 4 : 35;
+            g->leap = cfg->kind == RNGLD_LCG ? cfg->lcg_leap : 0;
+            g->rows = cfg->kind == RNGLD_HYBRID_TAUS ? 4 : (cfg->kind == RNGLD_RAN2 ? 35 : 1);
             g->state_bytes = static_cast<size_t>(g->S) * g->rows * 4;
             return RNGLD_OK;
         case RNGLD_LAGFIB: {
@@ -158,7 +161,7 @@ int check_ensembles(const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total, 
 
 // ---- tuning -----------------------------------------------------------------------------------------
 std::mutex g_tune_mu;
-ld_tuning g_tuning[3] = {{256, 1, 0, 0, 0}, {256, 1, 0, 0, 0}, {256, 1, 0, 0, 0}};
+ld_tuning g_tuning[4] = {{256, 1, 0, 0, 0}, {256, 1, 0, 0, 0}, {256, 1, 0, 0, 0}, {256, 1, 0, 0, 0}};
 
 ld_tuning current_tuning(int kind) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -469,7 +472,7 @@ int rng_init(const rngld_cfg *cfg, void *d_state, size_t state_bytes, void *stre
         RNGLD_TRY_HIP(launch_lf_seed(d_state, g.ll, g.sl, g.R, g.W, cfg->seed, st));
     } else {
         if (cfg->stream_base > kMaxStreams) return fail(RNGLD_EINVAL, "stream_base too large");
-        RNGLD_TRY_HIP(launch_seed(g.kind, d_state, g.S, cfg->seed, cfg->stream_base, 0, g.S, st));
+        RNGLD_TRY_HIP(launch_seed(g.kind, d_state, g.S, cfg->seed, cfg->stream_base, 0, g.S, g.leap, st));
     }
     return RNGLD_OK;
 }
@@ -486,7 +489,7 @@ int rng_init_ensembles(const rngld_cfg *cfg, void *d_state, size_t state_bytes, 
             return fail(RNGLD_ESIZE, "ensemble %u exceeds the state's streams", e);
     hipStream_t st = static_cast<hipStream_t>(stream);
     for (uint32_t e = 0; e < n_ens; ++e)
-        RNGLD_TRY_HIP(launch_seed(g.kind, d_state, g.S, h_ens[e].seed, 0, h_ens[e].offset, h_ens[e].n, st));
+        RNGLD_TRY_HIP(launch_seed(g.kind, d_state, g.S, h_ens[e].seed, 0, h_ens[e].offset, h_ens[e].n, g.leap, st));
     return RNGLD_OK;
 }
 
@@ -632,14 +635,14 @@ int ld_run(const rngld_cfg *cfg, void *d_state, size_t state_bytes, const ld_ens
 }
 
 int ld_get_tuning(int32_t kind, ld_tuning *out) {
-    if (kind < 0 || kind > 2) return fail(RNGLD_EINVAL, "unknown generator kind %d", kind);
+    if (kind < 0 || kind > RNGLD_LCG) return fail(RNGLD_EINVAL, "unknown generator kind %d", kind);
     if (!out) return fail(RNGLD_EINVAL, "out is NULL");
     *out = current_tuning(kind);
     return RNGLD_OK;
 }
 
 int ld_set_tuning(int32_t kind, const ld_tuning *t) {
-    if (kind < 0 || kind > 2) return fail(RNGLD_EINVAL, "unknown generator kind %d", kind);
+    if (kind < 0 || kind > RNGLD_LCG) return fail(RNGLD_EINVAL, "unknown generator kind %d", kind);
     if (!t || !valid_tuning(*t))
         return fail(RNGLD_EINVAL, "tuning needs block in {64,128,256,512}, osc_per_thread in {1,2}, "
                                   "blocks_per_cu <= 64");
@@ -927,7 +930,8 @@ int layout_adj(const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total, uint3
 int check_adj_common(const rngld_cfg *cfg, Gen *g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total,
                      uint32_t n_steps, const ld_loss *loss) {
     RNGLD_TRY(check_cfg(cfg, g));
-    if (g->kind == RNGLD_LAGFIB) return fail(RNGLD_ENOTSUP, "gradients need a per-thread generator");
+    if (g->kind != RNGLD_HYBRID_TAUS && g->kind != RNGLD_RAN2)
+        return fail(RNGLD_ENOTSUP, "gradients are implemented for Hybrid Taus and Ran2");
     RNGLD_TRY(check_loss(loss, n_steps));
     RNGLD_TRY(check_ensembles(h_ens, n_ens, n_total, true));
     for (uint32_t e = 0; e < n_ens; ++e)
@@ -946,7 +950,8 @@ size_t ckpt_record_bytes(const Gen &g, uint64_t n_total) {
 extern "C" int ld_ckpt_bytes(const rngld_cfg *cfg, uint64_t n_total, uint32_t n_steps, uint32_t K, size_t *bytes) {
     Gen g;
     RNGLD_TRY(check_cfg(cfg, &g));
-    if (g.kind == RNGLD_LAGFIB) return fail(RNGLD_ENOTSUP, "gradients need a per-thread generator");
+    if (g.kind != RNGLD_HYBRID_TAUS && g.kind != RNGLD_RAN2)
+        return fail(RNGLD_ENOTSUP, "gradients are implemented for Hybrid Taus and Ran2");
     if (!bytes) return fail(RNGLD_EINVAL, "bytes is NULL");
     if (K == 0) return fail(RNGLD_EINVAL, "K must be positive");
     const uint64_t nrec = (static_cast<uint64_t>(n_steps) + K - 1) / K;

@@ -100,6 +100,25 @@ struct HybridTaus {
     }
 };
 
+// ---- Quick-and-Dirty LCG (Eq. 1 with m = 2^32) ------------------------------------------------------
+// One 32-bit word per stream; the output is the updated word.  Seeding: with leap = 0 stream j
+// starts from its own seed word; with leap > 0 the streams divide one sequence (the cycle division
+// of Sec. III): stream j starts at position j * leap of the sequence from seed word (0, 0).
+struct Lcg32 {
+    uint32_t x;
+    static constexpr int kRows = 1;
+
+    __device__ __forceinline__ uint32_t next() {
+        x = lcg_next(x);
+        return x;
+    }
+    __device__ __forceinline__ void load(const uint32_t *st, uint64_t, uint64_t j) { x = st[j]; }
+    __device__ __forceinline__ void store(uint32_t *st, uint64_t, uint64_t j) const { st[j] = x; }
+    __device__ __forceinline__ void seed(uint64_t seed, uint64_t stream, uint64_t leap) {
+        x = leap ? lcg_skip(stream_seed_word(seed, 0, 0), stream * leap) : stream_seed_word(seed, stream, 0);
+    }
+};
+
 // ---- Ran2 -------------------------------------------------------------------------------------------
 constexpr int32_t kR2M1 = 2147483563, kR2A1 = 40014, kR2Q1 = 53668, kR2R1 = 12211;
 constexpr int32_t kR2M2 = 2147483399, kR2A2 = 40692, kR2Q2 = 52774, kR2R2 = 3791;

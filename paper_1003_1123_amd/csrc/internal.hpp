@@ -133,7 +133,7 @@ hipError_t launch_adj_finalize(const double *partials, uint32_t n_tiles, uint32_
 
 // ---- launchers (k_rng.hip) -------------------------------------------------------------------------
 hipError_t launch_seed(int kind, void *state, uint64_t S, uint64_t seed, uint64_t stream_base, uint64_t col_offset,
-                       uint64_t count, hipStream_t st);
+                       uint64_t count, uint64_t leap, hipStream_t st);
 hipError_t launch_bulk_uniform(int kind, void *state, uint64_t S, uint64_t per_stream, uint32_t *out,
                                hipStream_t st);
 hipError_t launch_bulk_gaussian(int kind, void *state, uint64_t S, uint64_t per_stream, float *out, hipStream_t st);

@@ -27,12 +27,19 @@ template <>
 struct IsRan2<Ran2> : std::true_type {};
 
 template <class Gen>
+struct IsLcg : std::false_type {};
+template <>
+struct IsLcg<Lcg32> : std::true_type {};
+
+template <class Gen>
 __device__ __forceinline__ void gen_park(Gen &g) {
     if constexpr (IsRan2<Gen>::value) {
         g.idum = 1;
         g.idum2 = 1;
         g.iy = 1;
         for (int t = 0; t < kR2Tab; ++t) g.tab[t * g.tstride] = 1;
+    } else if constexpr (IsLcg<Gen>::value) {
+        g.x = 0x9E3779B9u;
     } else {
         g.t1 = g.t2 = g.t3 = g.lcg = 0x9E3779B9u;
     }
@@ -199,11 +206,13 @@ __global__ __launch_bounds__(BLOCK) void ld_run_kernel(LdArgs a) {
 }
 
 // ---- paper protocol: one launch per step, state through device memory ------------------------------
-__global__ __launch_bounds__(kBulkBlock) void taus_step_kernel(uint32_t *st, uint64_t S, LdCoef q, uint64_t n,
-                                                               float *x, float *v) {
+// generators whose state is uint32 rows (Hybrid Taus, LCG)
+template <class Gen>
+__global__ __launch_bounds__(kBulkBlock) void u32_step_kernel(uint32_t *st, uint64_t S, LdCoef q, uint64_t n,
+                                                              float *x, float *v) {
     const uint64_t i = blockIdx.x * static_cast<uint64_t>(kBulkBlock) + threadIdx.x;
     if (i >= n) return;
-    HybridTaus g;
+    Gen g;
     g.load(st, S, i);
     const uint32_t w0 = g.next(), w1 = g.next(), w2 = g.next(), w3 = g.next();
     float gf[3];
@@ -288,7 +297,9 @@ struct KernelTable {
 }  // namespace
 
 const void *ld_run_kernel_ptr(int kind, const ld_tuning &t) {
-    return kind == RNGLD_RAN2 ? KernelTable<Ran2>::get(t) : KernelTable<HybridTaus>::get(t);
+    if (kind == RNGLD_RAN2) return KernelTable<Ran2>::get(t);
+    if (kind == RNGLD_LCG) return KernelTable<Lcg32>::get(t);
+    return KernelTable<HybridTaus>::get(t);
 }
 
 size_t ld_run_lds_bytes(int kind, const ld_tuning &t) {
@@ -315,7 +326,9 @@ hipError_t launch_ld_step(int kind, void *state, uint64_t S, const LdCoef &coef,
     if (n == 0) return hipSuccess;
     const dim3 grid(static_cast<unsigned>((n + kBulkBlock - 1) / kBulkBlock));
     if (kind == RNGLD_HYBRID_TAUS)
-        taus_step_kernel<<<grid, kBulkBlock, 0, st>>>(static_cast<uint32_t *>(state), S, coef, n, x, v);
+        u32_step_kernel<HybridTaus><<<grid, kBulkBlock, 0, st>>>(static_cast<uint32_t *>(state), S, coef, n, x, v);
+    else if (kind == RNGLD_LCG)
+        u32_step_kernel<Lcg32><<<grid, kBulkBlock, 0, st>>>(static_cast<uint32_t *>(state), S, coef, n, x, v);
     else
         ran2_step_kernel<<<grid, kBulkBlock, 0, st>>>(static_cast<int32_t *>(state), S, coef, n, x, v);
     return hipGetLastError();

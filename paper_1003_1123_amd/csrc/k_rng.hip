@@ -34,11 +34,23 @@ __global__ __launch_bounds__(kBulkBlock) void ran2_seed_kernel(int32_t *st, uint
     g.store(st, S, col_offset + t);
 }
 
-__global__ __launch_bounds__(kBulkBlock) void taus_uniform_kernel(uint32_t *st, uint64_t S, uint64_t per_stream,
-                                                                  uint32_t *out) {
+__global__ __launch_bounds__(kBulkBlock) void lcg_seed_kernel(uint32_t *st, uint64_t S, uint64_t seed,
+                                                              uint64_t stream_base, uint64_t col_offset,
+                                                              uint64_t count, uint64_t leap) {
+    const uint64_t t = blockIdx.x * static_cast<uint64_t>(kBulkBlock) + threadIdx.x;
+    if (t >= count) return;
+    Lcg32 g;
+    g.seed(seed, stream_base + t, leap);
+    g.store(st, S, col_offset + t);
+}
+
+// generators whose state is uint32 rows (Hybrid Taus, LCG)
+template <class Gen>
+__global__ __launch_bounds__(kBulkBlock) void u32_uniform_kernel(uint32_t *st, uint64_t S, uint64_t per_stream,
+                                                                 uint32_t *out) {
     const uint64_t j = blockIdx.x * static_cast<uint64_t>(kBulkBlock) + threadIdx.x;
     if (j >= S) return;
-    HybridTaus g;
+    Gen g;
     g.load(st, S, j);
     uint32_t *o = out + j;
     for (uint64_t t = 0; t < per_stream; ++t) o[t * S] = g.next();
@@ -72,11 +84,12 @@ __device__ __forceinline__ void gaussian_pairs(Gen &g, uint64_t S, uint64_t per_
     }
 }
 
-__global__ __launch_bounds__(kBulkBlock) void taus_gaussian_kernel(uint32_t *st, uint64_t S, uint64_t per_stream,
-                                                                   float *out) {
+template <class Gen>
+__global__ __launch_bounds__(kBulkBlock) void u32_gaussian_kernel(uint32_t *st, uint64_t S, uint64_t per_stream,
+                                                                  float *out) {
     const uint64_t j = blockIdx.x * static_cast<uint64_t>(kBulkBlock) + threadIdx.x;
     if (j >= S) return;
-    HybridTaus g;
+    Gen g;
     g.load(st, S, j);
     gaussian_pairs(g, S, per_stream, out + j);
     g.store(st, S, j);
@@ -111,9 +124,12 @@ inline dim3 grid_for(uint64_t n) { return dim3(static_cast<unsigned>((n + kBulkB
 }  // namespace
 
 hipError_t launch_seed(int kind, void *state, uint64_t S, uint64_t seed, uint64_t stream_base, uint64_t col_offset,
-                       uint64_t count, hipStream_t st) {
+                       uint64_t count, uint64_t leap, hipStream_t st) {
     if (count == 0) return hipSuccess;
-    if (kind == RNGLD_HYBRID_TAUS)
+    if (kind == RNGLD_LCG)
+        lcg_seed_kernel<<<grid_for(count), kBulkBlock, 0, st>>>(static_cast<uint32_t *>(state), S, seed, stream_base,
+                                                                col_offset, count, leap);
+    else if (kind == RNGLD_HYBRID_TAUS)
         taus_seed_kernel<<<grid_for(count), kBulkBlock, 0, st>>>(static_cast<uint32_t *>(state), S, seed,
                                                                  stream_base, col_offset, count);
     else
@@ -125,8 +141,11 @@ hipError_t launch_seed(int kind, void *state, uint64_t S, uint64_t seed, uint64_
 hipError_t launch_bulk_uniform(int kind, void *state, uint64_t S, uint64_t per_stream, uint32_t *out,
                                hipStream_t st) {
     if (S == 0 || per_stream == 0) return hipSuccess;
-    if (kind == RNGLD_HYBRID_TAUS)
-        taus_uniform_kernel<<<grid_for(S), kBulkBlock, 0, st>>>(static_cast<uint32_t *>(state), S, per_stream, out);
+    if (kind == RNGLD_LCG)
+        u32_uniform_kernel<Lcg32><<<grid_for(S), kBulkBlock, 0, st>>>(static_cast<uint32_t *>(state), S, per_stream, out);
+    else if (kind == RNGLD_HYBRID_TAUS)
+        u32_uniform_kernel<HybridTaus><<<grid_for(S), kBulkBlock, 0, st>>>(static_cast<uint32_t *>(state), S, per_stream,
+                                                                          out);
     else
         ran2_uniform_kernel<<<grid_for(S), kBulkBlock, 0, st>>>(static_cast<int32_t *>(state), S, per_stream, out);
     return hipGetLastError();
@@ -134,8 +153,12 @@ hipError_t launch_bulk_uniform(int kind, void *state, uint64_t S, uint64_t per_s
 
 hipError_t launch_bulk_gaussian(int kind, void *state, uint64_t S, uint64_t per_stream, float *out, hipStream_t st) {
     if (S == 0 || per_stream == 0) return hipSuccess;
-    if (kind == RNGLD_HYBRID_TAUS)
-        taus_gaussian_kernel<<<grid_for(S), kBulkBlock, 0, st>>>(static_cast<uint32_t *>(state), S, per_stream, out);
+    if (kind == RNGLD_LCG)
+        u32_gaussian_kernel<Lcg32><<<grid_for(S), kBulkBlock, 0, st>>>(static_cast<uint32_t *>(state), S, per_stream,
+                                                                      out);
+    else if (kind == RNGLD_HYBRID_TAUS)
+        u32_gaussian_kernel<HybridTaus><<<grid_for(S), kBulkBlock, 0, st>>>(static_cast<uint32_t *>(state), S,
+                                                                           per_stream, out);
     else
         ran2_gaussian_kernel<<<grid_for(S), kBulkBlock, 0, st>>>(static_cast<int32_t *>(state), S, per_stream, out);
     return hipGetLastError();

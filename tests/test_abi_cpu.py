@@ -35,8 +35,15 @@ def test_only_the_c_abi_is_exported():
     assert exported == set(_declared())
 
 
+def test_generator_kinds_match_header():
+    src = open(os.path.join(ROOT, "include", "rngld.h")).read()
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define RNGLD_([A-Z0-9_]+)\s+(-?\d+)", src)}
+    assert {k: defs[n] for k, n in (("taus", "HYBRID_TAUS"), ("ran2", "RAN2"), ("lf", "LAGFIB"), ("lcg", "LCG"))} \
+        == R.KINDS
+
+
 def test_struct_layouts_match_header():
-    assert C.sizeof(R.Cfg) == 48 and C.sizeof(R.Params) == 24 and C.sizeof(R.Ensemble) == 56
+    assert C.sizeof(R.Cfg) == 56 and R.Cfg.lcg_leap.offset == 48 and C.sizeof(R.Params) == 24 and C.sizeof(R.Ensemble) == 56
     assert C.sizeof(R.Obs) == 8 and C.sizeof(R.Tuning) == 20 and C.sizeof(R.Loss) == 16
     assert R.Ensemble.seed.offset == 48 and R.Ensemble.p.offset == 16
 
@@ -49,6 +56,8 @@ def test_state_bytes():
     out = C.c_size_t()
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("taus", n_streams=1000)), C.byref(out)) == 0 and out.value == 16000
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("ran2", n_streams=1000)), C.byref(out)) == 0 and out.value == 140000
+    assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lcg", n_streams=1000)), C.byref(out)) == 0 and out.value == 4000
+    assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lcg", n_streams=7, leap=4)), C.byref(out)) == 0 and out.value == 28
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=2281, sl=1252)), C.byref(out)) == 0
     assert out.value == 64 + 4 * 2 * (2281 + 1252)
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=2281, sl=1252, wave=101)), C.byref(out)) == 0

@@ -39,9 +39,9 @@ def _lf_lags(n):
     return W.lf_lags_for(4 * n)
 
 
-def _setup(kind, N, seed=1234, n_total=None, ll=0, sl=0, x0=None, v0=None):
+def _setup(kind, N, seed=1234, n_total=None, ll=0, sl=0, x0=None, v0=None, leap=0):
     n_total = N if n_total is None else n_total
-    cfg = R.make_cfg(kind, seed=seed, n_streams=n_total, ll=ll, sl=sl)
+    cfg = R.make_cfg(kind, seed=seed, n_streams=n_total, ll=ll, sl=sl, leap=leap)
     st = R.new_state(cfg)
     R.rng_init(cfg, st)
     x = torch.zeros(3 * n_total, dtype=torch.float32, device="cuda")
@@ -59,7 +59,7 @@ def _oracle_states(kind, seed, ids, ll=0):
 # ---------------------------------------------------------------------------------------------
 # config 1: N = 1e4, 1000 steps, observables every 10 steps, C_xx from t0 = 500
 
-@pytest.mark.parametrize("kind", ["taus", "ran2", "lf"])
+@pytest.mark.parametrize("kind", ["taus", "ran2", "lf", "lcg"])
 def test_config1_trajectory_and_observables(kind):
     N, T, stride, t0 = W.C1["N"], W.C1["steps"], W.C1["stride"], W.C1["t0"]
     p = W.C1["params"].as_f32()
@@ -145,7 +145,7 @@ def test_config2_lf_full_size_sampled():
 # ---------------------------------------------------------------------------------------------
 # protocol equivalences
 
-@pytest.mark.parametrize("kind", ["taus", "ran2", "lf"])
+@pytest.mark.parametrize("kind", ["taus", "ran2", "lf", "lcg"])
 def test_resume_is_bit_exact(kind):
     N = 3001
     ll, sl = _lf_lags(N) if kind == "lf" else (0, 0)
@@ -160,7 +160,7 @@ def test_resume_is_bit_exact(kind):
     assert torch.equal(xa, xb) and torch.equal(va, vb) and torch.equal(st_a, st_b)
 
 
-@pytest.mark.parametrize("kind", ["taus", "ran2", "lf"])
+@pytest.mark.parametrize("kind", ["taus", "ran2", "lf", "lcg"])
 def test_step_protocol_matches_oracle_and_fused_run(kind):
     """ld_step (one launch per step, state through device memory: the paper's protocol)."""
     N, T = 1000, 300
@@ -183,7 +183,7 @@ def test_step_protocol_matches_oracle_and_fused_run(kind):
     assert d <= 1e-5
 
 
-@pytest.mark.parametrize("kind", ["taus", "ran2"])
+@pytest.mark.parametrize("kind", ["taus", "ran2", "lcg"])
 def test_batched_equals_plain_bit_exact(kind):
     ens_list = W.batched_ensembles(n_ens=12, n_lo=1, n_hi=3000)
     offs = np.concatenate([[0], np.cumsum([e.n for e in ens_list])])
@@ -335,3 +335,94 @@ def test_lf_dataflow_resume_and_mixed_calls():
     assert np.array_equal(extra.cpu().numpy().view(np.uint32), orc.lf_generate(ll, sl, win, 1001))
     xo, vo, _ = orc.ld_run("lf", win, n, 23, W.LDParams().as_f32().asdict(), xo, vo, ll=ll, sl=sl)
     assert _close(x.cpu().numpy().reshape(3, n), xo, 1.0)[0]
+
+
+def test_lf_ring_size_does_not_change_the_run():
+    """The persistent run at the smallest allowed ring (ll + sl), the default ring and a larger one,
+    and the wave path on a ring too small for the persistent run, give the same trajectory bit for
+    bit."""
+    n, T, ll, sl = 3001, 150, 9689, 5502
+    p = _params(W.LDParams(k=1.3, gamma=0.7, dt=0.01))
+    ens, n_ens = R.make_ensembles([(0, n, p, 0)])
+    ref = None
+    for ring, path in ((ll + sl, "dataflow"), (0, "dataflow"), (4 * (ll + sl), "dataflow"), (ll + 4000, "waves")):
+        cfg = R.make_cfg("lf", seed=77, ll=ll, sl=sl, ring=ring, wave=4000 if ring == ll + 4000 else 0)
+        st = R.new_state(cfg)
+        R.rng_init(cfg, st)
+        x = torch.zeros(3 * n, dtype=torch.float32, device="cuda")
+        v = torch.zeros_like(x)
+        ob = torch.zeros((T // 10 + 1) * R.NOBS, dtype=torch.float64, device="cuda")
+        ws = R.ld_run(cfg, st, ens, n_ens, n, T, x, v, R.Obs(10, T // 3), ob)
+        torch.cuda.synchronize()
+        _say("lf ring", ring, R.ws_lf_path(ws))
+        assert R.ws_status(ws) == 0 and R.ws_lf_path(ws) == path
+        if ref is None:
+            ref = (x.clone(), v.clone(), ob.clone())
+        else:
+            assert torch.equal(x, ref[0]) and torch.equal(v, ref[1])
+            assert torch.allclose(ob, ref[2], rtol=1e-12, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------------------------
+# Sec. IV / Fig. 4: overdamped oscillators started away from the minimum
+
+@pytest.mark.parametrize("kind", ["taus", "ran2", "lf", "lcg"])
+def test_fig4_overdamped_mean_decay_and_correlation(kind):
+    """N = 1e4 oscillators from x0 = 10 in reduced units (tau = xi/k = 100 steps), 2000 overdamped
+    steps (Eq. 5).  The ensemble mean <x(t)> follows x0 a^t and the equilibrium correlation
+    <x(t0 + s) x(t0)> follows <x^2> a^s (the exact discrete forms of Sec. IV's R0 exp(-t/tau) and
+    (kT/k) exp(-t/tau)) within 4.5 standard errors at every observation."""
+    N, T, stride, t0 = 10_000, 2000, 10, 1000
+    pp = W.LDParams(m=1.0, k=1.0, gamma=1.0, kT=1.0, dt=0.01).as_f32()
+    pd = dict(m=float(pp.m), k=float(pp.k), gamma=float(pp.gamma), kT=float(pp.kT), dt=float(pp.dt))
+    ll, sl = _lf_lags(N) if kind == "lf" else (0, 0)
+    x0 = np.full((3, N), 10.0, np.float32)
+    cfg, st, x, v = _setup(kind, N, ll=ll, sl=sl, x0=x0, v0=np.zeros((3, N), np.float32))
+    ens, n_ens = R.make_ensembles([(0, N, _params(pp, scheme=1), 0)])
+    P = T // stride + 1
+    ob = torch.zeros(P * R.NOBS, dtype=torch.float64, device="cuda")
+    R.ld_run(cfg, st, ens, n_ens, N, T, x, v, R.Obs(stride, t0), ob)
+    obs = ob.cpu().numpy().reshape(P, R.NOBS)
+    n = 3 * N
+    steps = np.arange(0, T + 1, stride)
+    mean, var = mom.overdamped_transient(**pd, n_steps=T, x0=10.0)
+    z_mean = np.abs(obs[1:, 3] - mean[steps[1:]]) / np.sqrt(var[steps[1:]] / n)
+    after = steps >= t0
+    c = mom.overdamped_cross(**pd, t0=t0, taus=steps[after] - t0, x0=10.0)
+    s = var[steps[after]] + mean[steps[after]] ** 2
+    z_c = np.abs(obs[after, 4] - c) / np.sqrt((s * s[0] + c**2) / n)
+    # the paper's continuous forms, for the record (O(h) apart from the discrete ones)
+    m_cont, c_cont = mom.overdamped_continuous(pd["k"], pd["m"] * pd["gamma"], pd["kT"], steps * pd["dt"], 10.0)
+    _say("fig4", kind, "max z mean %.2f corr %.2f; <x>(tau) %.4f vs continuous %.4f" %
+         (z_mean.max(), z_c.max(), obs[10, 3], m_cont[10]))
+    assert z_mean.max() < 4.5 and z_c.max() < 4.5
+
+
+def test_fig4_lcg_correlated_seeding_fails_on_the_gpu():
+    """Negative control (Fig. 4b) on the GPU path: LCG streams seeded four values apart along one
+    sequence.  The run matches the oracle given the same seeding, fails the Fig. 4 z test that
+    independent streams pass, and leaves neighbouring oscillators almost fully correlated."""
+    N, T, stride, t0 = 3000, 4000, 20, 800
+    pp = W.LDParams(m=1.0, k=1.0, gamma=1.0, kT=1.0, dt=0.01).as_f32()
+    pd = dict(m=float(pp.m), k=float(pp.k), gamma=float(pp.gamma), kT=float(pp.kT), dt=float(pp.dt))
+    x0 = np.full((3, N), 10.0, np.float32)
+    ens, n_ens = R.make_ensembles([(0, N, _params(pp, scheme=1), 0)])
+    P = T // stride + 1
+    res = {}
+    for leap in (0, 4):
+        cfg, st, x, v = _setup("lcg", N, x0=x0, v0=np.zeros((3, N), np.float32), leap=leap)
+        ob = torch.zeros(P * R.NOBS, dtype=torch.float64, device="cuda")
+        R.ld_run(cfg, st, ens, n_ens, N, T, x, v, R.Obs(stride, t0), ob)
+        obs = ob.cpu().numpy().reshape(P, R.NOBS)
+        xg = x.cpu().numpy().reshape(3, N).astype(np.float64)
+        xr, _, _ = orc.ld_run("lcg", orc.seed_states("lcg", 1234, np.arange(N), leap=leap), N, T, pd, x0,
+                              np.zeros((3, N)), scheme=1)
+        assert _close(xg, xr, math.sqrt(pd["kT"] / pd["k"]))[0], leap
+        steps = np.arange(0, T + 1, stride)
+        mean, var = mom.overdamped_transient(**pd, n_steps=T, x0=10.0)
+        zm = np.max(np.abs(obs[1:, 3] - mean[steps[1:]]) / np.sqrt(var[steps[1:]] / (3 * N)))
+        corr = np.mean([np.corrcoef(xg[d, :-1], xg[d, 1:])[0, 1] for d in range(3)])
+        res[leap] = (float(zm), float(corr))
+    _say("lcg negative control (max z of <x>, neighbour corr):", res)
+    assert res[0][0] < 4.5 and abs(res[0][1]) < 0.1
+    assert res[4][0] > 10 and res[4][1] > 0.9

@@ -34,7 +34,7 @@ def _state_rows(cfg, state):
     return state[:rows * S * 4].cpu().numpy().view(np.uint32).reshape(rows, S)
 
 
-@pytest.mark.parametrize("kind", ["taus", "ran2"])
+@pytest.mark.parametrize("kind", ["taus", "ran2", "lcg"])
 def test_seeding_matches_oracle(kind):
     _say("seeding", kind)
     S = 1000
@@ -47,7 +47,7 @@ def test_seeding_matches_oracle(kind):
     assert np.array_equal(gpu.T, ref)
 
 
-@pytest.mark.parametrize("kind", ["taus", "ran2"])
+@pytest.mark.parametrize("kind", ["taus", "ran2", "lcg"])
 def test_seeding_with_stream_base(kind):
     base = 2**20 - 7
     cfg = R.make_cfg(kind, seed=99, n_streams=13, stream_base=base)
@@ -56,6 +56,20 @@ def test_seeding_with_stream_base(kind):
     gpu = _state_rows(cfg, st)
     ref = orc.seed_states(kind, 99, base + np.arange(13)).view(np.uint32)
     assert np.array_equal(gpu.T, ref)
+
+
+@pytest.mark.parametrize("leap", [1, 4, 1000])
+def test_lcg_leaped_seeding_and_streams(leap):
+    """Correlated LCG seeding: stream j starts j * leap steps past the stream-0 seed word."""
+    S, per, base = 300, 50, 12345
+    cfg = R.make_cfg("lcg", seed=31, n_streams=S, stream_base=base, leap=leap)
+    st = R.new_state(cfg)
+    R.rng_init(cfg, st)
+    ost = orc.seed_states("lcg", 31, base + np.arange(S), leap=leap)
+    assert np.array_equal(_state_rows(cfg, st).T, ost.view(np.uint32))
+    out = torch.empty(S * per, dtype=torch.int32, device="cuda")
+    R.rng_uniform(cfg, st, per, out)
+    assert np.array_equal(_u32(out).reshape(per, S), orc.uniform_streams("lcg", ost, per))
 
 
 def test_taus_seed_lift_streams():
@@ -72,7 +86,7 @@ def test_taus_seed_lift_streams():
         assert gpu[comp] == raw + (1 << (32 - (31, 29, 28)[comp]))
 
 
-@pytest.mark.parametrize("kind", ["taus", "ran2"])
+@pytest.mark.parametrize("kind", ["taus", "ran2", "lcg"])
 @pytest.mark.parametrize("S,per", [(1, 1), (777, 1000), (256, 3)])
 def test_uniform_streams_bit_exact(kind, S, per):
     _say("uniform", kind, S, per)
@@ -93,7 +107,7 @@ def test_uniform_streams_bit_exact(kind, S, per):
     assert np.array_equal(_state_rows(cfg, st).T, ost.view(np.uint32))
 
 
-@pytest.mark.parametrize("kind", ["taus", "ran2"])
+@pytest.mark.parametrize("kind", ["taus", "ran2", "lcg"])
 def test_config3_sampled_streams(kind):
     """2^20 streams x 1024 values in one call; 64 sampled streams checked against the oracle."""
     S, per = W.C3["streams"], W.C3["per_stream"]
@@ -111,7 +125,7 @@ def test_config3_sampled_streams(kind):
     del out
 
 
-@pytest.mark.parametrize("kind", ["taus", "ran2"])
+@pytest.mark.parametrize("kind", ["taus", "ran2", "lcg"])
 def test_first_million_values_of_sampled_streams(kind):
     """The first 10^6 values of 16 sampled config-3 streams, each generated in its own run."""
     ids = W.sampled_streams(W.C3["streams"], 64)[::4]
@@ -127,7 +141,7 @@ def test_first_million_values_of_sampled_streams(kind):
         assert np.array_equal(_u32(out), ref), (kind, j)
 
 
-@pytest.mark.parametrize("kind", ["taus", "ran2"])
+@pytest.mark.parametrize("kind", ["taus", "ran2", "lcg"])
 def test_gaussian_streams_within_tolerance(kind):
     S, per = 777, 1000
     cfg = R.make_cfg(kind, seed=2024, n_streams=S)

@@ -63,6 +63,44 @@ def test_lcg_hull_dobell_full_period():
     assert orc.lcg_period(12345, M32 + 1) == M32
 
 
+def _lcg_jump(x0, n):
+    """Closed-form jump of Eq. (1) with exact integers: a^n x0 + c (a^n - 1)/(a - 1) mod 2^32."""
+    a, c = CONST["lcg_a"][0], CONST["lcg_c"][0]
+    mod = M32 * (a - 1)
+    an = pow(a, n, mod)
+    return (an * x0 + c * ((an - 1) // (a - 1))) % M32
+
+
+def test_lcg_stream_seeding_independent_and_leaped():
+    """Per-stream LCG states: leap 0 takes each stream's own seed word; leap L puts stream j at
+    j*L steps past the stream-0 seed word (checked by the closed-form jump, also past 2^32)."""
+    ids = np.array([0, 1, 2, 17, 2**20 - 1, 2**33 + 5], dtype=np.uint64)
+    st0 = orc.seed_states("lcg", 77, ids)
+    assert st0.shape == (len(ids), 1) and st0.dtype == np.uint32
+    assert [int(v) for v in st0[:, 0]] == [orc.seed_word(77, int(j), 0) for j in ids]
+    x0 = orc.seed_word(77, 0, 0)
+    for leap in (1, 4, 1000):
+        st = orc.seed_states("lcg", 77, ids[:5], leap=leap)
+        assert [int(v) for v in st[:, 0]] == [_lcg_jump(x0, int(j) * leap) for j in ids[:5]]
+    # the reduction of the advance by the period 2^32
+    big = orc.seed_states("lcg", 77, [2**32 + 3], leap=1)
+    assert int(big[0, 0]) == _lcg_jump(x0, 3)
+
+
+def test_lcg_streams_follow_eq1_and_leaped_streams_are_shifted_windows():
+    S, per, leap = 9, 40, 4
+    st = orc.seed_states("lcg", 5, np.arange(S))
+    first = st[:, 0].copy()
+    out = orc.uniform_streams("lcg", st, per)
+    for j in range(S):
+        assert [int(v) for v in out[:, j]] == [_lcg_jump(int(first[j]), t + 1) for t in range(per)]
+    assert np.array_equal(st[:, 0], out[-1])
+    # leap 4: stream j+1 is stream j four values later -- the neighbour-shift that correlates
+    # oscillators driven by such streams
+    out = orc.uniform_streams("lcg", orc.seed_states("lcg", 5, np.arange(S), leap=leap), per)
+    assert np.array_equal(out[:-leap, 1:], out[leap:, :-1])
+
+
 # ---------------------------------------------------------------------------------------------
 # Tausworthe components, Eq. (2): bit-level definition
 

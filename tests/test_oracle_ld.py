@@ -51,6 +51,84 @@ def test_ld_noise_free_is_matrix_power():
         np.testing.assert_allclose(v[d], z[1], rtol=1e-12, atol=1e-13)
 
 
+@pytest.mark.parametrize("kind", ["taus", "lf"])
+def test_overdamped_matches_eq5_given_the_noise(kind):
+    """Overdamped scheme (Eq. 5): x_{n+1} = x_n - (k h / xi) x_n + sqrt(2 kT h / xi) g_n, v untouched."""
+    p = dict(m=1.3, k=0.7, gamma=2.1, kT=0.9, dt=0.02)
+    xi = p["m"] * p["gamma"]
+    N, T = 23, 50
+    rng = np.random.default_rng(11)
+    x0, v0 = rng.normal(size=(3, N)), rng.normal(size=(3, N))
+    ll, sl = (2281, 1252) if kind == "lf" else (0, 0)
+    st_run = orc.lf_seed(5, ll) if kind == "lf" else orc.seed_states(kind, 5, np.arange(N))
+    st_g = st_run.copy()
+    x, v, _ = orc.ld_run(kind, st_run, N, T, p, x0, v0, ll=ll, sl=sl, scheme=1)
+    g = orc.ld_forces(kind, st_g, N, T, ll=ll, sl=sl)
+    z = x0.copy()
+    for n in range(T):
+        z = z - p["k"] * p["dt"] / xi * z + math.sqrt(2 * p["kT"] * p["dt"] / xi) * g[n]
+    np.testing.assert_allclose(x, z, rtol=1e-11, atol=1e-11)
+    np.testing.assert_array_equal(v, v0)
+
+
+def test_overdamped_noise_free_decay_and_closed_forms():
+    """Noise-free overdamped decay is x0 a^n; the discrete closed forms tend to the continuous
+    Brownian-oscillator forms of Sec. IV as h -> 0, and the variance recursion matches them."""
+    p = dict(m=1.0, k=0.5, gamma=2.0, kT=0.0, dt=0.01)
+    N, T = 4, 700
+    x0 = np.full((3, N), 10.0)
+    x, _, _ = orc.ld_run("taus", orc.taus_seed(1, np.arange(N)), N, T, p, x0, np.zeros((3, N)), scheme=1)
+    a = 1.0 - p["k"] * p["dt"] / (p["m"] * p["gamma"])
+    np.testing.assert_allclose(x, 10.0 * a**T, rtol=1e-12)
+    # recursion var_{n+1} = a^2 var_n + b^2 against the closed form
+    q = dict(m=1.0, k=1.0, gamma=1.0, kT=1.3, dt=0.01)
+    mean, var = mom.overdamped_transient(**q, n_steps=400, x0=10.0)
+    a, b2 = 1.0 - q["dt"], 2 * q["kT"] * q["dt"]
+    v_rec, m_rec = 0.0, 10.0
+    for n in range(400):
+        v_rec, m_rec = a * a * v_rec + b2, a * m_rec
+    assert abs(v_rec - var[400]) < 1e-12 and abs(m_rec - mean[400]) < 1e-12
+    assert abs(mom.overdamped_stationary(**q) - var[400] / (1 - a ** 800)) < 1e-12
+    # h -> 0: discrete mean and equilibrium correlation approach R0 exp(-t/tau), (kT/k) exp(-t/tau)
+    t = 2.0
+    for h, tol in ((1e-3, 2e-3), (1e-4, 2e-4)):
+        n = int(round(t / h))
+        qh = dict(q, dt=h)
+        mean_h, _ = mom.overdamped_transient(**qh, n_steps=n, x0=10.0)
+        c_h = mom.overdamped_stationary(**qh) * (1 - h) ** n
+        m_c, c_c = mom.overdamped_continuous(q["k"], 1.0, q["kT"], t, 10.0)
+        assert abs(mean_h[-1] - m_c) / m_c < tol and abs(c_h - c_c) / c_c < tol
+
+
+def _fig4_check(obs, N, T, stride, t0, p, x0):
+    """Ensemble mean decay and equilibrium autocorrelation against the exact discrete forms, each
+    within 4.5 standard errors (3N independent coordinates)."""
+    n = 3 * N
+    steps = np.arange(0, T + 1, stride)
+    mean, var = mom.overdamped_transient(**p, n_steps=T, x0=x0)
+    z_mean = np.abs(obs[:, 3] - mean[steps]) / np.sqrt(np.maximum(var[steps], 1e-300) / n)
+    after = steps >= t0
+    taus = steps[after] - t0
+    c = mom.overdamped_cross(**p, t0=t0, taus=taus, x0=x0)
+    s = var[steps[after]] + mean[steps[after]] ** 2
+    se_c = np.sqrt((s * s[0] + c**2) / n)  # Isserlis, means negligible after equilibration
+    z_c = np.abs(obs[after, 4] - c) / se_c
+    return float(np.max(z_mean[1:])), float(np.max(z_c))
+
+
+@pytest.mark.parametrize("kind", ["taus", "ran2", "lf", "lcg"])
+def test_fig4_overdamped_statistics_oracle(kind):
+    """Sec. IV / Fig. 4 test in reduced units on the oracle: x0 = 10, tau = xi/k = 100 steps."""
+    p = dict(m=1.0, k=1.0, gamma=1.0, kT=1.0, dt=0.01)
+    N, T, stride, t0 = 3000, 1200, 20, 800
+    ll, sl = (132049, 54454) if kind == "lf" else (0, 0)
+    st = orc.lf_seed(1234, ll) if kind == "lf" else orc.seed_states(kind, 1234, np.arange(N))
+    x0 = np.full((3, N), 10.0)
+    _, _, obs = orc.ld_run(kind, st, N, T, p, x0, np.zeros((3, N)), stride=stride, t0=t0, ll=ll, sl=sl, scheme=1)
+    zm, zc = _fig4_check(obs, N, T, stride, t0, p, 10.0)
+    assert zm < 4.5 and zc < 4.5, (zm, zc)
+
+
 def test_forces_use_four_words_per_oscillator_step():
     """(g_x, g_y) from words (w0, w1) and g_z the cosine branch of (w2, w3) (Table II caption)."""
     N, T = 3, 4
@@ -222,3 +300,22 @@ def test_stationary_gradient_closed_form():
     g_cf = mom.stationary_x2_grad(**p)
     np.testing.assert_allclose(g_rec[[0, 2]], g_cf[[0, 2]], rtol=1e-4)
     assert abs(g_rec[1] - g_cf[1]) < 1e-5
+
+
+def test_fig4_lcg_correlated_seeding_fails_the_test():
+    """Negative control (Fig. 4b): LCG streams seeded as windows of one sequence, four values
+    apart, hand each oscillator its neighbour's noise one step later.  The ensemble mean then
+    carries the neighbours' shared noise and fails the same z test that independently seeded
+    streams pass; neighbouring oscillators end up almost fully correlated (about a = 1 - kh/xi)."""
+    p = dict(m=1.0, k=1.0, gamma=1.0, kT=1.0, dt=0.01)
+    N, T, stride, t0 = 3000, 4000, 20, 800
+    x0 = np.full((3, N), 10.0)
+    res = {}
+    for leap in (0, 4):
+        st = orc.seed_states("lcg", 1234, np.arange(N), leap=leap)
+        x, _, obs = orc.ld_run("lcg", st, N, T, p, x0, np.zeros((3, N)), stride=stride, t0=t0, scheme=1)
+        zm, zc = _fig4_check(obs, N, T, stride, t0, p, 10.0)
+        corr = np.mean([np.corrcoef(x[d, :-1], x[d, 1:])[0, 1] for d in range(3)])
+        res[leap] = (zm, zc, corr)
+    assert res[0][0] < 4.5 and res[0][1] < 4.5 and abs(res[0][2]) < 0.1, res
+    assert max(res[4][0], res[4][1]) > 10 and res[4][2] > 0.9, res
