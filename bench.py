@@ -5,9 +5,10 @@ One benchmark step = the config-2 workload for all three generators: seed the ge
 run N = 1e6 independent 3-D oscillators for 1e4 LD steps (dt = 0.005, m = k = kT = gamma = 1) with
 the Gaussian forces generated on the fly and observables recorded every 100 steps -- Hybrid Taus,
 Ran2 (32-entry table) and lagged Fibonacci (ll, sl) = (3021377, 1010202).  `value` is the
-oscillator-steps per second of that whole step.  The bare generators (config 3), the batched run
-(config 4) and the adjoint (config 5) are measured once after the timed steps and reported as extra
-fields; the CPU oracle is timed on a bounded sample of the config-2 workload.
+oscillator-steps per second of that whole step.  The bare generators (config 3, with the per-stream
+LCG as a speed reference), the batched run (config 4), the adjoint (config 5) and the Fig. 6 time
+breakdown over N are measured once after the timed steps and reported as extra fields; the CPU
+oracle is timed on a bounded sample of the config-2 workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu]
 """
@@ -196,7 +197,7 @@ def extra_config3(R, W, torch):
     buf_u = torch.empty(n_vals, dtype=torch.int32, device="cuda")
     buf_g = torch.empty(n_vals, dtype=torch.float32, device="cuda")
     bare = {}
-    for kind in GENERATORS:
+    for kind in GENERATORS + ("lcg",):
         if kind == "lf":
             cfg = R.make_cfg("lf", seed=c3["seed"], ll=c3["lf_lags"][0], sl=c3["lf_lags"][1])
             count = c3["lf_count"]
@@ -299,10 +300,101 @@ def extra_config5(R, W, torch):
                               "forward_osc_steps_per_s": osc / (t1 - t0)}
 
 
+def extra_fig6_breakdown(R, W, torch, cpu=True):
+    """Fig. 6 on this GPU: time per 10^3 LD steps against N for the fused full step of each generator,
+    the dynamics alone (the no-noise kind: same kernel, zero random force), the generator alone (bare
+    uniform streams, 4 words per oscillator-step written to HBM, in chunks), and the paper's
+    one-launch-per-step protocol (ld_step) for Hybrid Taus with and without noise; plus the speedup
+    of the fused step over the FP64 oracle (one thread), whose per-oscillator-step time is measured
+    on about 2e5 oscillator-steps at each N.  Underdamped, h = 0.005, m = k = kT = gamma = 1, from
+    rest, no observables; LF uses the smallest Table I pair with sl > 4N."""
+    import numpy as np
+    Ns = (10**2, 10**3, 10**4, 10**5, 10**6)
+    T = 1000
+    kinds = ("taus", "ran2", "lf", "lcg")
+    pp = W.C2["params"].as_f32()
+    p = R.make_params(pp.m, pp.k, pp.gamma, pp.kT, pp.dt)
+    seed = W.C2["seed"]
+
+    def timed(fn):
+        a, b = _ev(torch)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
+    rows = []
+    chunk_words = 2**28  # bare-stream output buffer: 1 GiB
+    buf = torch.empty(chunk_words, dtype=torch.int32, device="cuda")
+    for N in Ns:
+        row = {"N": N, "full_ms": {}, "rng_only_ms": {}, "cpu_ms": {}, "speedup_vs_cpu": {}}
+        ens, n_ens = R.make_ensembles([(0, N, p, 0)])
+        x = torch.zeros(3 * N, dtype=torch.float32, device="cuda")
+        v = torch.zeros_like(x)
+        ll, sl = W.lf_lags_for(4 * N)
+        for kind in kinds + ("none",):
+            cfg = R.make_cfg(kind, seed=seed, n_streams=N, ll=ll if kind == "lf" else 0,
+                             sl=sl if kind == "lf" else 0)
+            st = R.new_state(cfg)
+            ws = torch.empty(max(R.ld_workspace_bytes(cfg, ens, n_ens, N, T), 256), dtype=torch.uint8,
+                             device="cuda")
+            R.rng_init(cfg, st)
+            R.ld_run(cfg, st, ens, n_ens, N, 8, x, v, ws=ws)  # first launch of this kernel shape
+            x.zero_()
+            v.zero_()
+            ms = timed(lambda: R.ld_run(cfg, st, ens, n_ens, N, T, x, v, ws=ws))
+            if kind == "none":
+                row["dynamics_wo_rng_ms"] = ms
+            else:
+                row["full_ms"][kind] = ms
+            if kind == "lf":
+                row["lf_lags"] = [ll, sl]
+                row["lf_path"] = R.ws_lf_path(ws)
+            if kind != "none":
+                R.rng_init(cfg, st)
+                total = 4 * N * T
+                if kind == "lf":
+                    per_call = min(total, chunk_words)
+                    calls = [(per_call if i + per_call <= total else total - i) for i in range(0, total, per_call)]
+                    run = lambda: [R.rng_uniform(cfg, st, c, buf) for c in calls]
+                else:
+                    per_stream = max(1, min(4 * T, chunk_words // N))
+                    calls = [min(per_stream, 4 * T - i) for i in range(0, 4 * T, per_stream)]
+                    run = lambda: [R.rng_uniform(cfg, st, c, buf) for c in calls]
+                row["rng_only_ms"][kind] = timed(run)
+            del st, ws
+        for kind in ("taus", "none"):
+            cfg = R.make_cfg(kind, seed=seed, n_streams=N)
+            st = R.new_state(cfg)
+            R.rng_init(cfg, st)
+            R.ld_step(cfg, st, p, N, x, v)
+            ms = timed(lambda: [R.ld_step(cfg, st, p, N, x, v) for _ in range(T)])
+            row["step_protocol_ms_" + kind] = ms
+            del st
+        if cpu:
+            import oracle as orc
+            pd = pp.asdict()
+            n_cpu = max(1, 200_000 // N)
+            for kind in kinds:
+                stc = orc.lf_seed(seed, ll) if kind == "lf" else orc.seed_states(kind, seed, np.arange(N))
+                t = time.perf_counter()
+                orc.ld_run(kind, stc, N, n_cpu, pd, ll=ll, sl=sl)
+                per_os = (time.perf_counter() - t) / (N * n_cpu)
+                row["cpu_ms"][kind] = per_os * N * T * 1e3
+                row["speedup_vs_cpu"][kind] = row["cpu_ms"][kind] / row["full_ms"][kind]
+        rows.append(row)
+        log("fig6 N=%d: %s" % (N, json.dumps(row)))
+        del x, v
+    del buf
+    return {"steps": T, "ms_per_1000_steps": rows,
+            "cpu": "FP64 oracle, one thread, %s oscillator-steps per point" % "about 2e5"}
+
+
 def extras(R, W, torch):
     out = {}
     for name, fn in (("config3_bare_generators", extra_config3), ("config4_batched", extra_config4),
-                     ("config5_adjoint", extra_config5)):
+                     ("config5_adjoint", extra_config5), ("fig6_breakdown", extra_fig6_breakdown)):
         try:
             out[name] = fn(R, W, torch)
             log("%s: %s" % (name, json.dumps(out[name])))

@@ -51,6 +51,12 @@ extern "C" {
 #define RNGLD_RAN2 1        /* Sec. II.C, Alg. 2: two L'Ecuyer LCGs + 32-entry Bays-Durham table */
 #define RNGLD_LAGFIB 2      /* Sec. II.E, Alg. 3: y_n = y_{n-ll} + y_{n-sl} mod 2^32, shared */
 #define RNGLD_LCG 3         /* Sec. II.B, Eq. 1: Quick-and-Dirty LCG x = a x + c mod 2^32, per thread */
+#define RNGLD_NO_NOISE 4    /* no generator: the LD step with a zero random force, i.e. the
+                               deterministic dynamics alone (Fig. 6's "dynamics without RNG").
+                               Bit-identical to a run with kT = 0 under any generator.  No state
+                               (0 bytes, d_state may be NULL, n_streams is ignored); rng_init and
+                               rng_init_ensembles do nothing; rng_uniform and rng_gaussian return
+                               RNGLD_ENOTSUP; ld_step, ld_run and plans run; the adjoint does not. */
 
 /*
  * Generator configuration.
@@ -91,6 +97,7 @@ typedef struct rngld_cfg {
  *                (c = 0..2 Tausworthe components, 3 = LCG).                 16*S bytes.
  *  RAN2        : int32 r[35][S]: row 0 idum, 1 idum2, 2 iy, 3+t iv[t] (t = 0..31).  140*S bytes.
  *  LCG         : uint32 x[S].  4*S bytes.
+ *  NO_NOISE    : none.  0 bytes.
  *  LAGFIB      : 64-byte header { uint64 pos; uint32 slot; uint32 ll, sl, R, W; ... } followed by
  *                uint32 ring[R]; y_n lives in ring[(slot + n - pos) mod R] for the last ll
  *                positions n < pos.  pos counts values generated since rng_init.  64 + 4 R bytes.

@@ -15,10 +15,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librngld.so")
 
 OK, EINVAL, ELAG, ESIZE, EHIP, ENOTSUP = 0, -1, -2, -3, -4, -5
-HYBRID_TAUS, RAN2, LAGFIB, LCG = 0, 1, 2, 3
-KINDS = {"taus": HYBRID_TAUS, "ran2": RAN2, "lf": LAGFIB, "lcg": LCG}
+HYBRID_TAUS, RAN2, LAGFIB, LCG, NO_NOISE = 0, 1, 2, 3, 4
+KINDS = {"taus": HYBRID_TAUS, "ran2": RAN2, "lf": LAGFIB, "lcg": LCG, "none": NO_NOISE}
 NOBS = 6
-STATE_ROWS = {HYBRID_TAUS: 4, RAN2: 35, LCG: 1}
+STATE_ROWS = {HYBRID_TAUS: 4, RAN2: 35, LCG: 1, NO_NOISE: 0}
 _ERR_NAMES = {EINVAL: "EINVAL", ELAG: "ELAG", ESIZE: "ESIZE", EHIP: "EHIP", ENOTSUP: "ENOTSUP"}
 
 

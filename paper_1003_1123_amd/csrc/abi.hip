@@ -72,6 +72,11 @@ int check_cfg(const rngld_cfg *cfg, Gen *g) {
             g->rows = cfg->kind == RNGLD_HYBRID_TAUS ? 4 : (cfg->kind == RNGLD_RAN2 ? 35 : 1);
             g->state_bytes = static_cast<size_t>(g->S) * g->rows * 4;
             return RNGLD_OK;
+        case RNGLD_NO_NOISE:  // no state: any number of oscillators
+            g->S = kMaxStreams;
+            g->rows = 0;
+            g->state_bytes = 0;
+            return RNGLD_OK;
         case RNGLD_LAGFIB: {
             const uint32_t ll = cfg->lf_ll, sl = cfg->lf_sl;
             if (sl == 0 || sl >= ll || ll >= (1u << 31))
@@ -161,7 +166,7 @@ int check_ensembles(const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total, 
 
 // ---- tuning -----------------------------------------------------------------------------------------
 std::mutex g_tune_mu;
-ld_tuning g_tuning[4] = {{256, 1, 0, 0, 0}, {256, 1, 0, 0, 0}, {256, 1, 0, 0, 0}, {256, 1, 0, 0, 0}};
+ld_tuning g_tuning[5] = {{256, 1, 0, 0, 0}, {256, 1, 0, 0, 0}, {256, 1, 0, 0, 0}, {256, 1, 0, 0, 0}, {256, 1, 0, 0, 0}};
 
 ld_tuning current_tuning(int kind) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -468,6 +473,7 @@ int rng_init(const rngld_cfg *cfg, void *d_state, size_t state_bytes, void *stre
     RNGLD_TRY(check_cfg(cfg, &g));
     RNGLD_TRY(check_state(g, d_state, state_bytes));
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (g.kind == RNGLD_NO_NOISE) return RNGLD_OK;
     if (g.kind == RNGLD_LAGFIB) {
         RNGLD_TRY_HIP(launch_lf_seed(d_state, g.ll, g.sl, g.R, g.W, cfg->seed, st));
     } else {
@@ -488,6 +494,7 @@ int rng_init_ensembles(const rngld_cfg *cfg, void *d_state, size_t state_bytes, 
         if (h_ens[e].offset > g.S || h_ens[e].n > g.S - h_ens[e].offset)
             return fail(RNGLD_ESIZE, "ensemble %u exceeds the state's streams", e);
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (g.kind == RNGLD_NO_NOISE) return RNGLD_OK;
     for (uint32_t e = 0; e < n_ens; ++e)
         RNGLD_TRY_HIP(launch_seed(g.kind, d_state, g.S, h_ens[e].seed, 0, h_ens[e].offset, h_ens[e].n, g.leap, st));
     return RNGLD_OK;
@@ -497,6 +504,7 @@ int rng_uniform(const rngld_cfg *cfg, void *d_state, size_t state_bytes, uint64_
                 uint64_t out_len, void *stream) {
     Gen g;
     RNGLD_TRY(check_cfg(cfg, &g));
+    if (g.kind == RNGLD_NO_NOISE) return fail(RNGLD_ENOTSUP, "the no-noise kind generates no numbers");
     RNGLD_TRY(check_state(g, d_state, state_bytes));
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (g.kind == RNGLD_LAGFIB) {
@@ -529,6 +537,7 @@ int rng_gaussian(const rngld_cfg *cfg, void *d_state, size_t state_bytes, uint64
                  uint64_t out_len, void *stream) {
     Gen g;
     RNGLD_TRY(check_cfg(cfg, &g));
+    if (g.kind == RNGLD_NO_NOISE) return fail(RNGLD_ENOTSUP, "the no-noise kind generates no numbers");
     RNGLD_TRY(check_state(g, d_state, state_bytes));
     if (per_stream % 2) return fail(RNGLD_EINVAL, "Gaussians come in Box-Muller pairs: per_stream must be even");
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -635,14 +644,14 @@ int ld_run(const rngld_cfg *cfg, void *d_state, size_t state_bytes, const ld_ens
 }
 
 int ld_get_tuning(int32_t kind, ld_tuning *out) {
-    if (kind < 0 || kind > RNGLD_LCG) return fail(RNGLD_EINVAL, "unknown generator kind %d", kind);
+    if (kind < 0 || kind > RNGLD_NO_NOISE) return fail(RNGLD_EINVAL, "unknown generator kind %d", kind);
     if (!out) return fail(RNGLD_EINVAL, "out is NULL");
     *out = current_tuning(kind);
     return RNGLD_OK;
 }
 
 int ld_set_tuning(int32_t kind, const ld_tuning *t) {
-    if (kind < 0 || kind > RNGLD_LCG) return fail(RNGLD_EINVAL, "unknown generator kind %d", kind);
+    if (kind < 0 || kind > RNGLD_NO_NOISE) return fail(RNGLD_EINVAL, "unknown generator kind %d", kind);
     if (!t || !valid_tuning(*t))
         return fail(RNGLD_EINVAL, "tuning needs block in {64,128,256,512}, osc_per_thread in {1,2}, "
                                   "blocks_per_cu <= 64");

@@ -119,6 +119,15 @@ struct Lcg32 {
     }
 };
 
+// ---- no random force ----------------------------------------------------------------------------------
+// The deterministic part of the LD step alone (the "dynamics without random numbers" of Fig. 6): no
+// state, no draws; the kernels use a zero force in place of the Box-Muller output.
+struct NoNoise {
+    static constexpr int kRows = 0;
+    __device__ __forceinline__ void load(const uint32_t *, uint64_t, uint64_t) {}
+    __device__ __forceinline__ void store(uint32_t *, uint64_t, uint64_t) const {}
+};
+
 // ---- Ran2 -------------------------------------------------------------------------------------------
 constexpr int32_t kR2M1 = 2147483563, kR2A1 = 40014, kR2Q1 = 53668, kR2R1 = 12211;
 constexpr int32_t kR2M2 = 2147483399, kR2A2 = 40692, kR2Q2 = 52774, kR2R2 = 3791;

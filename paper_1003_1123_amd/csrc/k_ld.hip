@@ -32,6 +32,25 @@ template <>
 struct IsLcg<Lcg32> : std::true_type {};
 
 template <class Gen>
+struct IsNoNoise : std::false_type {};
+template <>
+struct IsNoNoise<NoNoise> : std::true_type {};
+
+// one oscillator-step's three force components: four words through Box-Muller, or zero
+template <class Gen>
+__device__ __forceinline__ void draw_forces(Gen &g, float &gx, float &gy, float &gz) {
+    if constexpr (IsNoNoise<Gen>::value) {
+        gx = gy = gz = 0.0f;
+    } else {
+        const uint32_t w0 = g.next();
+        const uint32_t w1 = g.next();
+        const uint32_t w2 = g.next();
+        const uint32_t w3 = g.next();
+        gaussian_forces(w0, w1, w2, w3, gx, gy, gz);
+    }
+}
+
+template <class Gen>
 __device__ __forceinline__ void gen_park(Gen &g) {
     if constexpr (IsRan2<Gen>::value) {
         g.idum = 1;
@@ -40,6 +59,7 @@ __device__ __forceinline__ void gen_park(Gen &g) {
         for (int t = 0; t < kR2Tab; ++t) g.tab[t * g.tstride] = 1;
     } else if constexpr (IsLcg<Gen>::value) {
         g.x = 0x9E3779B9u;
+    } else if constexpr (IsNoNoise<Gen>::value) {
     } else {
         g.t1 = g.t2 = g.t3 = g.lcg = 0x9E3779B9u;
     }
@@ -103,12 +123,8 @@ __device__ __forceinline__ void run_steps(const LdArgs &a, const LdCoef &q, uint
         for (; s < stop; ++s) {
 #pragma unroll
             for (int k = 0; k < OPT; ++k) {
-                const uint32_t w0 = g[k].next();
-                const uint32_t w1 = g[k].next();
-                const uint32_t w2 = g[k].next();
-                const uint32_t w3 = g[k].next();
                 float gx, gy, gz;
-                gaussian_forces(w0, w1, w2, w3, gx, gy, gz);
+                draw_forces(g[k], gx, gy, gz);
                 ld_update_s<SCHEME>(q, x[k][0], v[k][0], gx);
                 ld_update_s<SCHEME>(q, x[k][1], v[k][1], gy);
                 ld_update_s<SCHEME>(q, x[k][2], v[k][2], gz);
@@ -206,7 +222,7 @@ __global__ __launch_bounds__(BLOCK) void ld_run_kernel(LdArgs a) {
 }
 
 // ---- paper protocol: one launch per step, state through device memory ------------------------------
-// generators whose state is uint32 rows (Hybrid Taus, LCG)
+// generators whose state is uint32 rows (Hybrid Taus, LCG) or absent (no random force)
 template <class Gen>
 __global__ __launch_bounds__(kBulkBlock) void u32_step_kernel(uint32_t *st, uint64_t S, LdCoef q, uint64_t n,
                                                               float *x, float *v) {
@@ -214,9 +230,8 @@ __global__ __launch_bounds__(kBulkBlock) void u32_step_kernel(uint32_t *st, uint
     if (i >= n) return;
     Gen g;
     g.load(st, S, i);
-    const uint32_t w0 = g.next(), w1 = g.next(), w2 = g.next(), w3 = g.next();
     float gf[3];
-    gaussian_forces(w0, w1, w2, w3, gf[0], gf[1], gf[2]);
+    draw_forces(g, gf[0], gf[1], gf[2]);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         float xd = x[d * n + i], vd = v[d * n + i];
@@ -299,6 +314,7 @@ struct KernelTable {
 const void *ld_run_kernel_ptr(int kind, const ld_tuning &t) {
     if (kind == RNGLD_RAN2) return KernelTable<Ran2>::get(t);
     if (kind == RNGLD_LCG) return KernelTable<Lcg32>::get(t);
+    if (kind == RNGLD_NO_NOISE) return KernelTable<NoNoise>::get(t);
     return KernelTable<HybridTaus>::get(t);
 }
 
@@ -329,6 +345,8 @@ hipError_t launch_ld_step(int kind, void *state, uint64_t S, const LdCoef &coef,
         u32_step_kernel<HybridTaus><<<grid, kBulkBlock, 0, st>>>(static_cast<uint32_t *>(state), S, coef, n, x, v);
     else if (kind == RNGLD_LCG)
         u32_step_kernel<Lcg32><<<grid, kBulkBlock, 0, st>>>(static_cast<uint32_t *>(state), S, coef, n, x, v);
+    else if (kind == RNGLD_NO_NOISE)
+        u32_step_kernel<NoNoise><<<grid, kBulkBlock, 0, st>>>(static_cast<uint32_t *>(state), S, coef, n, x, v);
     else
         ran2_step_kernel<<<grid, kBulkBlock, 0, st>>>(static_cast<int32_t *>(state), S, coef, n, x, v);
     return hipGetLastError();

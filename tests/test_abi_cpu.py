@@ -38,7 +38,8 @@ def test_only_the_c_abi_is_exported():
 def test_generator_kinds_match_header():
     src = open(os.path.join(ROOT, "include", "rngld.h")).read()
     defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define RNGLD_([A-Z0-9_]+)\s+(-?\d+)", src)}
-    assert {k: defs[n] for k, n in (("taus", "HYBRID_TAUS"), ("ran2", "RAN2"), ("lf", "LAGFIB"), ("lcg", "LCG"))} \
+    assert {k: defs[n] for k, n in (("taus", "HYBRID_TAUS"), ("ran2", "RAN2"), ("lf", "LAGFIB"), ("lcg", "LCG"),
+                                           ("none", "NO_NOISE"))} \
         == R.KINDS
 
 
@@ -58,6 +59,7 @@ def test_state_bytes():
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("ran2", n_streams=1000)), C.byref(out)) == 0 and out.value == 140000
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lcg", n_streams=1000)), C.byref(out)) == 0 and out.value == 4000
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lcg", n_streams=7, leap=4)), C.byref(out)) == 0 and out.value == 28
+    assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("none", n_streams=10**6)), C.byref(out)) == 0 and out.value == 0
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=2281, sl=1252)), C.byref(out)) == 0
     assert out.value == 64 + 4 * 2 * (2281 + 1252)
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=2281, sl=1252, wave=101)), C.byref(out)) == 0
@@ -70,6 +72,12 @@ def test_state_bytes():
     # ring shorter than ll + W (W = 100 after rounding down to a multiple of 4)
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=2281, sl=1252, wave=101, ring=2380)),
                                    C.byref(out)) == R.ELAG
+
+
+def test_no_noise_kind_generates_no_numbers():
+    c = R.make_cfg("none")
+    assert R.lib.rng_uniform(C.byref(c), None, 0, 4, None, 0, None) == R.ENOTSUP
+    assert R.lib.rng_gaussian(C.byref(c), None, 0, 4, None, 0, None) == R.ENOTSUP
 
 
 @pytest.mark.parametrize("cfg,code", [

@@ -286,6 +286,67 @@ def test_overdamped_scheme_matches_oracle():
 
 
 # ---------------------------------------------------------------------------------------------
+# dynamics without random numbers (Fig. 6): the no-noise kind
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_no_noise_equals_zero_temperature_and_the_oracle(scheme):
+    """The no-noise kind runs the deterministic part of the step alone: bit-identical to a Taus run
+    with kT = 0 (whose random force is exactly zero), and equal to the FP64 noise-free oracle."""
+    N, T, stride, t0 = 5003, 700, 10, 300
+    pp = W.LDParams(m=1.3, k=0.8, gamma=0.6, kT=0.0, dt=0.01).as_f32()
+    p = _params(pp, scheme)
+    rng = np.random.default_rng(3)
+    x0 = rng.normal(size=(3, N)).astype(np.float32)
+    v0 = rng.normal(size=(3, N)).astype(np.float32)
+    ens, n_ens = R.make_ensembles([(0, N, p, 0)])
+    P = T // stride + 1
+    out = {}
+    for kind in ("none", "taus"):
+        cfg, st, x, v = _setup(kind, N, x0=x0, v0=v0)
+        ob = torch.zeros(P * R.NOBS, dtype=torch.float64, device="cuda")
+        R.ld_run(cfg, st, ens, n_ens, N, T, x, v, R.Obs(stride, t0), ob)
+        torch.cuda.synchronize()
+        out[kind] = (x, v, ob)
+    assert torch.equal(out["none"][0], out["taus"][0]) and torch.equal(out["none"][1], out["taus"][1])
+    assert torch.equal(out["none"][2], out["taus"][2])
+    xr, vr, obr = orc.ld_run("taus", orc.taus_seed(1, np.arange(N)), N, T, pp.asdict(), x0, v0, stride=stride,
+                             t0=t0, scheme=scheme)
+    assert _close(out["none"][0].cpu().numpy().reshape(3, N), xr, 1.0)[0]
+    assert _close(out["none"][1].cpu().numpy().reshape(3, N), vr, 1.0)[0]
+    # the one-launch-per-step protocol gives the same trajectory
+    cfg, st, xs, vs = _setup("none", N, x0=x0, v0=v0)
+    for _ in range(T):
+        R.ld_step(cfg, st, p, N, xs, vs)
+    torch.cuda.synchronize()
+    assert float((xs - out["none"][0]).abs().max()) <= 1e-5 and float((vs - out["none"][1]).abs().max()) <= 1e-5
+
+
+def test_no_noise_batched_plan_and_null_state():
+    N, T = 3000, 64
+    p = _params(W.LDParams(kT=0.0))
+    ens, n_ens = R.make_ensembles([(0, 1000, p, 0), (1000, 2000, p, 0)])
+    cfg = R.make_cfg("none")
+    st = R.new_state(cfg)
+    R.rng_init(cfg, st)
+    R.rng_init_ensembles(cfg, st, ens, n_ens)
+    x = torch.ones(3 * N, dtype=torch.float32, device="cuda")
+    v = torch.zeros_like(x)
+    xb, vb = x.clone(), v.clone()
+    R.ld_run(cfg, st, ens, n_ens, N, T, x, v)
+    plan = R.Plan(cfg, st, ens, n_ens, N, T, xb, vb)
+    plan.launch()
+    torch.cuda.synchronize()
+    plan.close()
+    assert torch.equal(x, xb) and torch.equal(v, vb)
+    # every oscillator starts at x = 1, v = 0 and follows the same deterministic path
+    assert float(x.std()) == 0.0 and float(v.std()) == 0.0
+    xr, vr, _ = orc.ld_run("taus", orc.taus_seed(1, [0]), 1, T, W.LDParams(kT=0.0).as_f32().asdict(),
+                           np.ones((3, 1)), np.zeros((3, 1)))
+    assert _close(x.view(3, N)[:, :1].cpu().numpy(), xr, 1.0)[0]
+    assert _close(v.view(3, N)[:, :1].cpu().numpy(), vr, 1.0)[0]
+
+
+# ---------------------------------------------------------------------------------------------
 # lagged Fibonacci: persistent dataflow run vs one launch per wave
 
 @pytest.mark.parametrize("n,lags,T", [(1000, (2281, 1252), 200), (1, (2281, 1252), 2000), (3001, (9689, 5502), 150),
