@@ -41,29 +41,29 @@ LF_WAVE_XV_BYTES_PER_OSC_STEP = 48
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch) at the config-2
 # workload, scaled by what the same counters read for a plain 1 GiB device copy (FETCH_SIZE 0.5 GiB:
-# factor 2; WRITE_SIZE 1 GiB: factor 1).  Valid only for the kernel sources they were taken on (the
-# SHA-256 of the listed files); otherwise the traffic is reported as null.
+# factor 2; WRITE_SIZE 1 GiB: factor 1).  Valid only for the machine code they were taken on: the
+# SHA-256 of the kernel's gfx950 assembly, which the build records in kernel_isa.json; otherwise the
+# traffic is reported as null.
 COUNTER_TRAFFIC = {
     "lf_pc_kernel": {
-        "sources": ("k_lf.hip", "lf_flow.hpp", "device.hpp", "internal.hpp"),
-        "sha256": "f66baa73cbd7a41334b64a6c1c54623a8bf1974b52efb6a3cdb1796a1292bff0",
+        "isa_sha256": "1ecb45ba17546127a7ae071a4068e5ced6e466a1fbfbe71093015b1d99ca1132",
         "fetch_bytes": 158271630 * 1024 * 2, "write_bytes": 177948728 * 1024,
     },
 }
 
 
-def _sources_sha(names):
-    import hashlib
-    h = hashlib.sha256()
-    for n in names:
-        with open(os.path.join(ROOT, "paper_1003_1123_amd", "csrc", n), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()
+def built_isa(kernel):
+    path = os.path.join(ROOT, "paper_1003_1123_amd", "kernel_isa.json")
+    try:
+        with open(path) as f:
+            return json.load(f).get(kernel, {}).get("sha256")
+    except (OSError, ValueError):
+        return None
 
 
 def counter_traffic(kernel):
     c = COUNTER_TRAFFIC.get(kernel)
-    if c is None or _sources_sha(c["sources"]) != c["sha256"]:
+    if c is None or built_isa(kernel) != c["isa_sha256"]:
         return None
     return c["fetch_bytes"] + c["write_bytes"]
 

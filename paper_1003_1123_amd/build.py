@@ -2,12 +2,18 @@
 
     python -m paper_1003_1123_amd.build          # compiles every csrc/*.hip, links librngld.so
 
-Object files go to <repo>/_build/; the shared library is written next to this file.
+Object files go to <repo>/_build/; the shared library is written next to this file, with
+kernel_isa.json: the SHA-256 of the gfx950 assembly of the kernels whose hardware counters are
+recorded (so a measurement can tell whether the machine code it was taken on is still the one
+built).
 """
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
+import json
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -17,6 +23,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librngld.so")
+ISA_JSON = os.path.join(HERE, "kernel_isa.json")
+# kernels whose machine code is fingerprinted: name -> source file
+FINGERPRINTED = {"lf_pc_kernel": "k_lf.hip", "ld_run_kernel": "k_ld.hip"}
 ARCH = os.environ.get("RNGLD_OFFLOAD_ARCH", "gfx950")
 
 # Packed-FP32 instructions are disabled for all device code (the compiler would otherwise form
@@ -45,6 +54,49 @@ def _compile(src: str) -> str:
     return obj
 
 
+def _function_bodies(asm: str, name: str):
+    """Bodies of the device functions whose mangled symbol contains `name`, with comments and
+    compiler-numbered labels normalised (they change when unrelated functions are added)."""
+    out = {}
+    cur, lines = None, []
+    for line in asm.splitlines():
+        m = re.match(r"^([_A-Za-z0-9.$]+):", line)
+        if cur is None and m and name in m.group(1) and not m.group(1).startswith("."):
+            cur, lines = m.group(1), []
+            continue
+        if cur is not None:
+            if re.match(r"^\.Lfunc_end\d+:", line):
+                out[cur] = "\n".join(lines)
+                cur = None
+                continue
+            t = line.split(";")[0].rstrip()
+            t = re.sub(r"\.LBB\d+_", ".LBB_", t)
+            t = re.sub(r"\.Ltmp\d+", ".Ltmp", t)
+            if t:
+                lines.append(t)
+    return out
+
+
+def fingerprint_kernels() -> dict:
+    """SHA-256 over the sorted assembly bodies of each fingerprinted kernel family."""
+    res = {}
+    for name, src in FINGERPRINTED.items():
+        asm_path = os.path.join(BUILD, src[:-4] + ".gfx950.s")
+        cmd = [hipcc()] + [f for f in FLAGS if f != "-fPIC"] + ["--cuda-device-only", "-S",
+                                                              os.path.join(CSRC, src), "-o", asm_path]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("assembly listing failed: %s\n%s" % (" ".join(cmd), r.stderr))
+        bodies = _function_bodies(open(asm_path).read(), name)
+        if not bodies:
+            raise RuntimeError("no %s in %s" % (name, asm_path))
+        h = hashlib.sha256()
+        for sym in sorted(bodies):
+            h.update(sym.encode() + b"\n" + bodies[sym].encode() + b"\n")
+        res[name] = {"sha256": h.hexdigest(), "functions": len(bodies)}
+    return res
+
+
 def build(verbose: bool = False) -> str:
     """Compile every kernel/ABI source and link librngld.so; always rebuilds."""
     os.makedirs(BUILD, exist_ok=True)
@@ -57,6 +109,9 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))
     os.replace(tmp, LIB)
+    with open(ISA_JSON + ".tmp", "w") as f:
+        json.dump(fingerprint_kernels(), f, indent=1, sort_keys=True)
+    os.replace(ISA_JSON + ".tmp", ISA_JSON)
     if verbose:
         print("built", LIB)
     return LIB
