@@ -80,6 +80,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", default="", help="comma list of generators (profiling runs)")
+    ap.add_argument("--extras", default="", help="comma list of extras to run (profiling runs; default all)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (a plain copy of known size, for scaling "
                          "hardware byte counters)")
@@ -275,29 +276,40 @@ def extra_config4(R, W, torch):
 
 
 def extra_config5(R, W, torch):
-    """Adjoint: forward with checkpoints, backward with replay; fwd+bwd over fwd time."""
+    """Adjoint: forward with checkpoints, backward (register-only for config 5's weak damping, and
+    by segment replay for comparison); fwd+bwd over fwd time.  One untimed pass first loads the
+    kernels and sizes the buffers."""
     from paper_1003_1123_amd import autograd as A
     c5 = W.C5
     p5 = c5["params"].as_f32()
-    run = A.AdjointRun("taus", [(c5["N"], p5.m, p5.dt, c5["seed"])], c5["steps"], c5["t_begin"], c5["t_end"],
-                       c5["K"])
-    k = torch.tensor([p5.k], dtype=torch.float64, requires_grad=True)
-    g = torch.tensor([p5.gamma], dtype=torch.float64, requires_grad=True)
-    kT = torch.tensor([p5.kT], dtype=torch.float64, requires_grad=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    L = A.LDAdjoint.apply(k, g, kT, run)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    L.sum().backward()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    osc = c5["N"] * c5["steps"]
-    return {"N": c5["N"], "steps": c5["steps"], "K": c5["K"], "loss": L.item(),
-                              "grad_k_gamma_kT": [k.grad.item(), g.grad.item(), kT.grad.item()],
-                              "forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3,
-                              "fwd_plus_bwd_over_fwd": (t2 - t0) / (t1 - t0),
-                              "forward_osc_steps_per_s": osc / (t1 - t0)}
+    out = {"N": c5["N"], "steps": c5["steps"], "K": c5["K"]}
+    for replay in (False, True):
+        run = A.AdjointRun("taus", [(c5["N"], p5.m, p5.dt, c5["seed"])], c5["steps"], c5["t_begin"], c5["t_end"],
+                           c5["K"], replay=replay)
+        for rep in range(2):
+            k = torch.tensor([p5.k], dtype=torch.float64, requires_grad=True)
+            g = torch.tensor([p5.gamma], dtype=torch.float64, requires_grad=True)
+            kT = torch.tensor([p5.kT], dtype=torch.float64, requires_grad=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            L = A.LDAdjoint.apply(k, g, kT, run)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            L.sum().backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+        osc = c5["N"] * c5["steps"]
+        scratch = 9 * c5["K"] * c5["N"] * 4
+        res = {"backward_path": "replay" if run.ws.numel() >= scratch else "register-only",
+               "loss": L.item(), "grad_k_gamma_kT": [k.grad.item(), g.grad.item(), kT.grad.item()],
+               "forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3,
+               "fwd_plus_bwd_over_fwd": (t2 - t0) / (t1 - t0), "forward_osc_steps_per_s": osc / (t1 - t0)}
+        if replay:
+            out["replay"] = res
+        else:
+            out.update(res)
+        del run
+    return out
 
 
 def extra_fig6_breakdown(R, W, torch, cpu=True):
@@ -391,10 +403,12 @@ def extra_fig6_breakdown(R, W, torch, cpu=True):
             "cpu": "FP64 oracle, one thread, %s oscillator-steps per point" % "about 2e5"}
 
 
-def extras(R, W, torch):
+def extras(R, W, torch, only=()):
     out = {}
     for name, fn in (("config3_bare_generators", extra_config3), ("config4_batched", extra_config4),
                      ("config5_adjoint", extra_config5), ("fig6_breakdown", extra_fig6_breakdown)):
+        if only and name not in only:
+            continue
         try:
             out[name] = fn(R, W, torch)
             log("%s: %s" % (name, json.dumps(out[name])))
@@ -471,7 +485,7 @@ def main():
     log("config 2 value %.4g osc-steps/s; per generator ms: %s" %
         (value, {k: round(v["ms_per_run"], 2) for k, v in per_gen.items()}))
     if not args.no_extras:
-        res["extras"] = extras(R, W, torch)
+        res["extras"] = extras(R, W, torch, tuple(e for e in args.extras.split(",") if e))
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(W)
         res["cpu_baseline"]["gpu_over_cpu"] = value / res["cpu_baseline"]["value"]

@@ -245,15 +245,19 @@ RNGLD_API int ld_plan_destroy(rngld_plan *plan);
 /*
  * Loss L_e = mean over steps t_begin..t_end (1 <= t_begin <= t_end <= n_steps) of <x^2>_e (mean
  * over the ensemble's 3n coordinates of the positions after t steps); checkpoints every K steps.
+ * flags: 0, or RNGLD_ADJ_REPLAY to make ld_run_backward use the replay path for every ensemble.
  */
 typedef struct ld_loss {
     uint32_t t_begin;
     uint32_t t_end;
     uint32_t K;
-    uint32_t pad;
+    uint32_t flags;
 } ld_loss;
 
-/* Checkpoint buffer: ceil(n_steps/K) records, record c = state at step c*K:
+#define RNGLD_ADJ_REPLAY 1u
+
+/* Checkpoint buffer: ceil(n_steps/K) + 1 records, record c = state at step min(c*K, n_steps)
+ * (the last record is the state at the end of the run):
  * float x[3][n_total], float v[3][n_total], then the generator state in the layout above with
  * S = n_total. */
 RNGLD_API int ld_ckpt_bytes(const rngld_cfg *cfg, uint64_t n_total, uint32_t n_steps, uint32_t K, size_t *bytes);
@@ -268,8 +272,20 @@ RNGLD_API int ld_run_ckpt(const rngld_cfg *cfg, void *d_state, size_t state_byte
 
 /*
  * Reverse-mode pathwise gradient d_grad[n_ens][3] = (dL/dk, dL/dgamma, dL/dkT) (double) of the
- * losses of ld_run_ckpt, replaying each K-step segment's noise bit-exactly from its checkpoint
- * (no noise is stored across segments).  d_ckpt is read only.
+ * losses of ld_run_ckpt; the noise of every step is regenerated bit-exactly.  d_ckpt is read only.
+ * Two paths, chosen per ensemble:
+ *  - register-only (Hybrid Taus): each K-step segment is swept backward from the checkpoint at
+ *    its end, running the generator backward with the inverse Tausworthe and LCG steps and the
+ *    integrator backward (x = x' - dt v', v = (v' + (k dt/m) x - sig g) / (1 - gamma dt)); the
+ *    checkpoint at the segment's start re-anchors the next segment.  Used when rounding errors
+ *    cannot grow by more than 8 over K inverse steps (max over j <= K of the Frobenius norm of
+ *    the inverse step matrix to the power j, for the ensemble's FP32 coefficients), e.g.
+ *    gamma dt <= 0.02 at K = 100 and dt = 0.01.  No scratch.
+ *  - replay: each segment is rerun forward from the checkpoint at its start into a scratch of
+ *    9 floats per oscillator-step and swept backward from there (Ran2; Hybrid Taus otherwise or
+ *    with RNGLD_ADJ_REPLAY).
+ * ld_adjoint_workspace_bytes includes the scratch only when some ensemble takes the replay path,
+ * so it depends on the ensembles' parameters and the flags.
  */
 RNGLD_API int ld_run_backward(const rngld_cfg *cfg, const void *d_ckpt, size_t ckpt_bytes, const ld_ensemble *h_ens,
                     uint32_t n_ens, uint64_t n_total, uint32_t n_steps, const ld_loss *loss, double *d_grad,

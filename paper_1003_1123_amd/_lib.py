@@ -57,7 +57,10 @@ class Tuning(C.Structure):
 
 
 class Loss(C.Structure):
-    _fields_ = [("t_begin", C.c_uint32), ("t_end", C.c_uint32), ("K", C.c_uint32), ("pad", C.c_uint32)]
+    _fields_ = [("t_begin", C.c_uint32), ("t_end", C.c_uint32), ("K", C.c_uint32), ("flags", C.c_uint32)]
+
+
+ADJ_REPLAY = 1  # ld_loss.flags: backward by segment replay for every ensemble
 
 
 def _load():

@@ -1,9 +1,11 @@
 """Pathwise gradients of an LD loss w.r.t. (k, gamma, kT) as a torch.autograd.Function.
 
-Forward runs ld_run_ckpt (checkpoints x, v and the generator state every K steps); backward runs
-ld_run_backward, which replays each segment's noise bit-exactly from its checkpoint and sweeps the
-adjoint recursion backward.  The loss of ensemble e is the mean over steps t_begin..t_end of
-<x^2>_e (per component, over the ensemble's 3n coordinates).
+Forward runs ld_run_ckpt (checkpoints x, v and the generator state every K steps and at the end);
+backward runs ld_run_backward, which regenerates each segment's noise bit-exactly -- backwards from
+the segment's end with the inverse generator steps (Hybrid Taus, weakly damped ensembles), else by
+replaying it from the segment's start -- and sweeps the adjoint recursion backward.  The loss of
+ensemble e is the mean over steps t_begin..t_end of <x^2>_e (per component, over the ensemble's 3n
+coordinates).
 """
 from __future__ import annotations
 
@@ -19,12 +21,13 @@ class AdjointRun:
     starts from the current x, v and generator state and advances them.
     """
 
-    def __init__(self, kind, ensembles, n_steps: int, t_begin: int, t_end: int, K: int, device="cuda"):
+    def __init__(self, kind, ensembles, n_steps: int, t_begin: int, t_end: int, K: int, device="cuda",
+                 replay: bool = False):
         self.kind = kind
         self.ens_shape = list(ensembles)
         self.n_total = sum(n for n, _, _, _ in self.ens_shape)
         self.n_steps, self.device = n_steps, device
-        self.loss = R.Loss(t_begin, t_end, K, 0)
+        self.loss = R.Loss(t_begin, t_end, K, R.ADJ_REPLAY if replay else 0)
         self.cfg = R.make_cfg(kind, n_streams=self.n_total)
         self.state = R.new_state(self.cfg, device)
         self.x = torch.zeros(3 * self.n_total, dtype=torch.float32, device=device)
@@ -34,8 +37,14 @@ class AdjointRun:
         R.rng_init_ensembles(self.cfg, self.state, ens, n_ens)
         self.ckpt = torch.empty(max(R.ld_ckpt_bytes(self.cfg, self.n_total, n_steps, K), 1), dtype=torch.uint8,
                                 device=device)
-        self.ws = torch.empty(max(R.ld_adjoint_workspace_bytes(self.cfg, ens, n_ens, self.n_total, n_steps,
-                                                               self.loss), 256), dtype=torch.uint8, device=device)
+        self.ws = torch.empty(0, dtype=torch.uint8, device=device)
+
+    def workspace(self, ens, n_ens) -> torch.Tensor:
+        """The workspace for these ensembles (its size depends on their parameters)."""
+        need = max(R.ld_adjoint_workspace_bytes(self.cfg, ens, n_ens, self.n_total, self.n_steps, self.loss), 256)
+        if self.ws.numel() < need:
+            self.ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self.ws
 
     def _ensembles(self, k, gamma, kT):
         specs, off = [], 0
@@ -54,7 +63,7 @@ class LDAdjoint(torch.autograd.Function):
         ens, n_ens = run._ensembles(kh, gh, th)
         out = torch.empty(n_ens, dtype=torch.float64, device=run.device)
         R.ld_run_ckpt(run.cfg, run.state, ens, n_ens, run.n_total, run.n_steps, run.x, run.v, run.loss, run.ckpt,
-                      out, run.ws)
+                      out, run.workspace(ens, n_ens))
         ctx.run, ctx.ens, ctx.n_ens = run, ens, n_ens
         ctx.meta = tuple((t.dtype, t.device) for t in (k, gamma, kT))
         return out
@@ -63,7 +72,8 @@ class LDAdjoint(torch.autograd.Function):
     def backward(ctx, grad_out):
         run = ctx.run
         g = torch.empty((ctx.n_ens, 3), dtype=torch.float64, device=run.device)
-        R.ld_run_backward(run.cfg, run.ckpt, ctx.ens, ctx.n_ens, run.n_total, run.n_steps, run.loss, g, run.ws)
+        R.ld_run_backward(run.cfg, run.ckpt, ctx.ens, ctx.n_ens, run.n_total, run.n_steps, run.loss, g,
+                          run.workspace(ctx.ens, ctx.n_ens))
         go = grad_out.to(device=run.device, dtype=torch.float64)
         grads = [(go * g[:, i]).to(device=dev, dtype=dt) for i, (dt, dev) in enumerate(ctx.meta)]
         return grads[0], grads[1], grads[2], None

@@ -900,11 +900,37 @@ struct AdjLayout {
     std::vector<EnsDev> ens;
     std::vector<AdjCoef> adj;
     uint32_t n_tiles = 0;
+    bool any_replay = false, any_inverse = false;
     size_t off_ens = 0, off_adj = 0, off_partials = 0, off_scratch = 0, bytes = 0;
 };
 
-int layout_adj(const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total, uint32_t K, bool with_scratch,
-               AdjLayout *L) {
+// Largest growth of a perturbation of (x, v) over 1..K backward steps of the underdamped
+// integrator with these FP32 coefficients: max_j |M^j|_F, M the inverse of the step matrix
+// A = [[1 - h kap, h c], [-kap, c]] acting on (x, v) (v' = c v - kap x, x' = x + h v').
+// Returns as soon as the growth exceeds `limit`.
+double reverse_growth(const LdCoef &q, uint32_t K, double limit) {
+    const double c = q.c, kap = q.kap, h = q.h;
+    if (!(c > 0.0)) return HUGE_VAL;
+    const double a11 = 1.0 - h * kap, a12 = h * c, a21 = -kap, a22 = c;
+    const double det = a11 * a22 - a12 * a21;  // = c
+    const double m11 = a22 / det, m12 = -a12 / det, m21 = -a21 / det, m22 = a11 / det;
+    double p11 = 1, p12 = 0, p21 = 0, p22 = 1, worst = 0;
+    for (uint32_t j = 0; j < K; ++j) {
+        const double n11 = m11 * p11 + m12 * p21, n12 = m11 * p12 + m12 * p22;
+        const double n21 = m21 * p11 + m22 * p21, n22 = m21 * p12 + m22 * p22;
+        p11 = n11, p12 = n12, p21 = n21, p22 = n22;
+        worst = std::max(worst, std::sqrt(p11 * p11 + p12 * p12 + p21 * p21 + p22 * p22));
+        if (worst > limit) return worst;
+    }
+    return worst;
+}
+
+constexpr double kAdjGrowthLimit = 8.0;
+constexpr uint32_t kAdjInverseMaxK = 1u << 22;
+
+int layout_adj(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total, const ld_loss &loss,
+               bool backward, AdjLayout *L) {
+    const uint32_t K = loss.K;
     L->ens.resize(n_ens);
     L->adj.resize(n_ens);
     uint64_t acc = 0;
@@ -925,6 +951,13 @@ int layout_adj(const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total, uint3
         const double sig = std::sqrt(2.0 * p.gamma * static_cast<double>(p.kT) * p.dt / p.m);
         A.dsig_dgamma = static_cast<float>(sig / (2.0 * p.gamma));
         A.dsig_dkT = static_cast<float>(sig / (2.0 * p.kT));
+        A.inv_c = static_cast<float>(1.0 / static_cast<double>(A.f.c));
+        A.inverse = g.kind == RNGLD_HYBRID_TAUS && !(loss.flags & RNGLD_ADJ_REPLAY) && K <= kAdjInverseMaxK &&
+                    reverse_growth(A.f, K, kAdjGrowthLimit) <= kAdjGrowthLimit;
+        if (E.n) {
+            L->any_inverse |= A.inverse != 0;
+            L->any_replay |= A.inverse == 0;
+        }
     }
     if (acc >= (1ull << 31)) return fail(RNGLD_EINVAL, "too many tiles");
     L->n_tiles = static_cast<uint32_t>(acc);
@@ -932,7 +965,7 @@ int layout_adj(const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total, uint3
     L->off_adj = align_up(sizeof(EnsDev) * n_ens);
     L->off_partials = align_up(L->off_adj + sizeof(AdjCoef) * n_ens);
     L->off_scratch = align_up(L->off_partials + 3 * sizeof(double) * std::max<uint32_t>(L->n_tiles, 1));
-    L->bytes = L->off_scratch + (with_scratch ? align_up(9ull * K * n_total * sizeof(float)) : 0);
+    L->bytes = L->off_scratch + (backward && L->any_replay ? align_up(9ull * K * n_total * sizeof(float)) : 0);
     return RNGLD_OK;
 }
 
@@ -963,7 +996,7 @@ extern "C" int ld_ckpt_bytes(const rngld_cfg *cfg, uint64_t n_total, uint32_t n_
         return fail(RNGLD_ENOTSUP, "gradients are implemented for Hybrid Taus and Ran2");
     if (!bytes) return fail(RNGLD_EINVAL, "bytes is NULL");
     if (K == 0) return fail(RNGLD_EINVAL, "K must be positive");
-    const uint64_t nrec = (static_cast<uint64_t>(n_steps) + K - 1) / K;
+    const uint64_t nrec = (static_cast<uint64_t>(n_steps) + K - 1) / K + 1;  // + the end state
     *bytes = nrec * ckpt_record_bytes(g, n_total);
     return RNGLD_OK;
 }
@@ -974,7 +1007,7 @@ extern "C" int ld_adjoint_workspace_bytes(const rngld_cfg *cfg, const ld_ensembl
     RNGLD_TRY(check_adj_common(cfg, &g, h_ens, n_ens, n_total, n_steps, loss));
     if (!bytes) return fail(RNGLD_EINVAL, "bytes is NULL");
     AdjLayout L;
-    RNGLD_TRY(layout_adj(h_ens, n_ens, n_total, loss->K, true, &L));
+    RNGLD_TRY(layout_adj(g, h_ens, n_ens, n_total, *loss, true, &L));
     *bytes = L.bytes;
     return RNGLD_OK;
 }
@@ -991,7 +1024,7 @@ extern "C" int ld_run_ckpt(const rngld_cfg *cfg, void *d_state, size_t state_byt
     RNGLD_TRY(ld_ckpt_bytes(cfg, n_total, n_steps, loss->K, &need_ck));
     if (ckpt_bytes < need_ck) return fail(RNGLD_ESIZE, "checkpoint buffer %zu < %zu bytes", ckpt_bytes, need_ck);
     AdjLayout L;
-    RNGLD_TRY(layout_adj(h_ens, n_ens, n_total, loss->K, false, &L));
+    RNGLD_TRY(layout_adj(g, h_ens, n_ens, n_total, *loss, false, &L));
     if (ws_bytes < L.bytes) return fail(RNGLD_ESIZE, "workspace %zu bytes < %zu required", ws_bytes, L.bytes);
     if (!d_ws || !d_loss || (n_total && (!d_x || !d_v || !d_ckpt))) return fail(RNGLD_EINVAL, "NULL buffer");
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1030,7 +1063,7 @@ extern "C" int ld_run_backward(const rngld_cfg *cfg, const void *d_ckpt, size_t 
     RNGLD_TRY(ld_ckpt_bytes(cfg, n_total, n_steps, loss->K, &need_ck));
     if (ckpt_bytes < need_ck) return fail(RNGLD_ESIZE, "checkpoint buffer %zu < %zu bytes", ckpt_bytes, need_ck);
     AdjLayout L;
-    RNGLD_TRY(layout_adj(h_ens, n_ens, n_total, loss->K, true, &L));
+    RNGLD_TRY(layout_adj(g, h_ens, n_ens, n_total, *loss, true, &L));
     if (ws_bytes < L.bytes) return fail(RNGLD_ESIZE, "workspace %zu bytes < %zu required", ws_bytes, L.bytes);
     if (!d_ws || !d_grad || (n_total && !d_ckpt)) return fail(RNGLD_EINVAL, "NULL buffer");
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1049,9 +1082,10 @@ extern "C" int ld_run_backward(const rngld_cfg *cfg, const void *d_ckpt, size_t 
     a.t_end = loss->t_end;
     a.ckpt = const_cast<uint8_t *>(static_cast<const uint8_t *>(d_ckpt));
     a.rec_bytes = ckpt_record_bytes(g, n_total);
-    a.scratch = reinterpret_cast<float *>(ws + L.off_scratch);
+    a.scratch = L.any_replay ? reinterpret_cast<float *>(ws + L.off_scratch) : nullptr;
     a.partials = reinterpret_cast<double *>(ws + L.off_partials);
-    if (n_steps > 0) RNGLD_TRY_HIP(launch_ld_adjoint(g.kind, a, kAdjTile, st));
+    // n_steps >= 1 (check_loss); every tile's partials are written by exactly one of the kernels
+    RNGLD_TRY_HIP(launch_ld_adjoint(g.kind, a, L.any_replay, L.any_inverse, st));
     RNGLD_TRY_HIP(launch_adj_finalize(a.partials, L.n_tiles, 3, a.ens, n_ens,
                                       static_cast<double>(loss->t_end - loss->t_begin + 1), d_grad, st));
     return RNGLD_OK;

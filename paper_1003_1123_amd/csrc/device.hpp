@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "gen_int.hpp"
+
 namespace rngld {
 
 // ---- per-stream seeding: SplitMix64 (Steele, Lea & Flood 2014) in counter form -----------------
@@ -29,45 +31,6 @@ __device__ __forceinline__ uint32_t stream_seed_word(uint64_t seed, uint64_t j, 
     return static_cast<uint32_t>(splitmix_finalize(seed + (4ull * j + i + 1ull) * kGoldenGamma) >> 32);
 }
 
-// ---- LCG of Eq. 1, m = 2^32 -----------------------------------------------------------------------
-constexpr uint32_t kLcgMul = 1664525u;
-constexpr uint32_t kLcgAdd = 1013904223u;
-
-__device__ __forceinline__ uint32_t lcg_next(uint32_t x) { return kLcgMul * x + kLcgAdd; }
-
-// x advanced by n steps: the affine map x -> a x + c composed with itself by binary powering
-// (a - 1 is even, so the geometric-sum closed form cannot use a modular inverse).
-__device__ __forceinline__ uint32_t lcg_skip(uint32_t x, uint64_t n) {
-    uint32_t mul = 1u, add = 0u;            // accumulated map
-    uint32_t pm = kLcgMul, pa = kLcgAdd;    // map for 2^bit steps
-    while (n) {
-        if (n & 1u) {
-            mul = pm * mul;
-            add = pm * add + pa;
-        }
-        pa = pm * pa + pa;
-        pm = pm * pm;
-        n >>= 1;
-    }
-    return mul * x + add;
-}
-
-// ---- Tausworthe component for the trinomial x^K + x^Q + 1 with step S (Eq. 2) -----------------
-// The state occupies the top K bits; the low 32-K bits are dropped before the left shift.
-template <int Q, int S, int K>
-__device__ __forceinline__ uint32_t tausworthe(uint32_t z) {
-    constexpr uint32_t kTop = ~((1u << (32 - K)) - 1u);
-    const uint32_t feedback = ((z << Q) ^ z) >> (K - S);
-    return ((z & kTop) << S) ^ feedback;
-}
-
-// smallest word whose top K bits are not all zero
-template <int K>
-__device__ __forceinline__ uint32_t tausworthe_lift(uint32_t z) {
-    constexpr uint32_t kFloor = 1u << (32 - K);
-    return z < kFloor ? z + kFloor : z;
-}
-
 struct HybridTaus {
     uint32_t t1, t2, t3, lcg;
     static constexpr int kRows = 4;
@@ -78,6 +41,17 @@ struct HybridTaus {
         t3 = tausworthe<3, 17, 28>(t3);
         lcg = lcg_next(lcg);
         return t1 ^ t2 ^ t3 ^ lcg;
+    }
+    // the output of the current state, then one step back: repeated calls return the outputs of
+    // the preceding next() calls in reverse order, all of them exactly; only the seeded state
+    // itself comes back with different bits below each component's top K
+    __device__ __forceinline__ uint32_t prev() {
+        const uint32_t w = t1 ^ t2 ^ t3 ^ lcg;
+        t1 = tausworthe_inv<13, 12, 31>(t1);
+        t2 = tausworthe_inv<2, 4, 29>(t2);
+        t3 = tausworthe_inv<3, 17, 28>(t3);
+        lcg = lcg_prev(lcg);
+        return w;
     }
     // state rows: uint32 [4][S]
     __device__ __forceinline__ void load(const uint32_t *st, uint64_t S, uint64_t j) {

@@ -1,0 +1,91 @@
+// gen_int.hpp -- the integer steps of the per-thread generators, forward and inverse.
+//
+// LCG of Eq. 1 with m = 2^32 (Sec. II.B), and the Tausworthe components of Hybrid Taus (Sec. II.D,
+// Eq. 2 in L'Ecuyer's shift form; Appendix A Alg. 1).  The inverse steps let a reverse sweep
+// regenerate a path's noise backwards from its end state instead of storing it.
+//
+// Plain C++, so that a CPU test can use it as well as the kernels.
+#pragma once
+
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#define RNGLD_HDI __host__ __device__ __forceinline__
+#else
+#define RNGLD_HDI inline
+#endif
+
+namespace rngld {
+
+// ---- LCG of Eq. 1, m = 2^32 -------------------------------------------------------------------------
+constexpr uint32_t kLcgMul = 1664525u;
+constexpr uint32_t kLcgAdd = 1013904223u;
+
+// inverse of an odd a modulo 2^32 by Newton's iteration inv <- inv (2 - a inv): each step doubles
+// the number of correct low bits, starting from a * a = 1 mod 8
+constexpr uint32_t odd_inverse_u32(uint32_t a) {
+    uint32_t inv = a;
+    for (int i = 0; i < 5; ++i) inv *= 2u - a * inv;
+    return inv;
+}
+constexpr uint32_t kLcgMulInv = odd_inverse_u32(kLcgMul);
+static_assert(kLcgMul * kLcgMulInv == 1u, "a must be invertible modulo 2^32");
+
+RNGLD_HDI uint32_t lcg_next(uint32_t x) { return kLcgMul * x + kLcgAdd; }
+RNGLD_HDI uint32_t lcg_prev(uint32_t x) { return kLcgMulInv * (x - kLcgAdd); }
+
+// x advanced by n steps: the affine map x -> a x + c composed with itself by binary powering
+// (a - 1 is even, so the geometric-sum closed form cannot use a modular inverse).
+RNGLD_HDI uint32_t lcg_skip(uint32_t x, uint64_t n) {
+    uint32_t mul = 1u, add = 0u;            // accumulated map
+    uint32_t pm = kLcgMul, pa = kLcgAdd;    // map for 2^bit steps
+    while (n) {
+        if (n & 1u) {
+            mul = pm * mul;
+            add = pm * add + pa;
+        }
+        pa = pm * pa + pa;
+        pm = pm * pm;
+        n >>= 1;
+    }
+    return mul * x + add;
+}
+
+// ---- Tausworthe component for the trinomial x^K + x^Q + 1 with step S (Eq. 2) ---------------------
+// The state occupies the top K bits; the low 32-K bits are dropped before the left shift.
+//
+// In terms of the component's bit sequence y (y_m = y_{m-K+Q} xor y_{m-K}), a word produced by
+// this step holds 32 consecutive sequence bits, oldest in bit 31: its top K bits are the state
+// and the low 32-K bits the next bits of the same sequence (the feedback computes them from state
+// bits only, since S + 32 + Q <= 2K for the three components).  A seeded word is such a window
+// only in its top K bits.
+template <int Q, int S, int K>
+RNGLD_HDI uint32_t tausworthe(uint32_t z) {
+    constexpr uint32_t kTop = ~((1u << (32 - K)) - 1u);
+    const uint32_t feedback = ((z << Q) ^ z) >> (K - S);
+    return ((z & kTop) << S) ^ feedback;
+}
+
+// The inverse step on a produced word w = (y_{n} .. y_{n+31}): the previous word is
+// (y_{n-S} .. y_{n+31-S}), i.e. w >> S with the S older bits on top.  Each older bit follows from
+// the recurrence solved for its oldest term, y_j = y_{j+K} xor y_{j+Q}.  The y_{j+K} all lie in w;
+// y_{j+Q} lies in w >> S unless it is itself one of the S new bits (Q < S), so the top bits t
+// satisfy t = c xor (t << Q) on the top S bits, solved by t = c (1 + L^Q)(1 + L^2Q)(1 + L^4Q)...
+// Exact for any word that tausworthe() produced from another produced word.
+template <int Q, int S, int K>
+RNGLD_HDI uint32_t tausworthe_inv(uint32_t w) {
+    static_assert(S <= K && K <= 32 && Q > 0, "component parameters");
+    constexpr uint32_t kTopS = ~0u << (32 - S);
+    uint32_t t = ((w << (K - S)) ^ ((w >> S) << Q)) & kTopS;
+    for (int sh = Q; sh < S; sh *= 2) t ^= t << sh;
+    return t | (w >> S);
+}
+
+// smallest word whose top K bits are not all zero
+template <int K>
+RNGLD_HDI uint32_t tausworthe_lift(uint32_t z) {
+    constexpr uint32_t kFloor = 1u << (32 - K);
+    return z < kFloor ? z + kFloor : z;
+}
+
+}  // namespace rngld

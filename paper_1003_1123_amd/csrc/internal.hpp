@@ -108,6 +108,8 @@ struct AdjCoef {
     float dc_dgamma;  // -h
     float dsig_dgamma;
     float dsig_dkT;
+    float inv_c;       // 1 / c, for the backward step of the register-only path
+    uint32_t inverse;  // 1: register-only backward for this ensemble, 0: replay
 };
 
 struct AdjArgs {
@@ -122,12 +124,14 @@ struct AdjArgs {
     uint32_t t_begin, t_end;
     uint8_t *ckpt;
     uint64_t rec_bytes;  // bytes per checkpoint record
-    float *scratch;      // backward: [K][9][NT]
+    float *scratch;      // backward, replay path: [K][9][NT]
     double *partials;    // [n_tiles][3] (loss uses slot 0)
 };
 
 hipError_t launch_ld_ckpt(int kind, const AdjArgs &a, uint32_t block, hipStream_t st);
-hipError_t launch_ld_adjoint(int kind, const AdjArgs &a, uint32_t block, hipStream_t st);
+// backward: the replay kernel for ensembles with inverse == 0, the register-only kernel (Hybrid
+// Taus) for those with inverse == 1
+hipError_t launch_ld_adjoint(int kind, const AdjArgs &a, bool any_replay, bool any_inverse, hipStream_t st);
 hipError_t launch_adj_finalize(const double *partials, uint32_t n_tiles, uint32_t width, const EnsDev *ens,
                                uint32_t n_ens, double denom_steps, double *out, hipStream_t st);
 

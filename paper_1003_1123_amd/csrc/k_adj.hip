@@ -6,10 +6,17 @@
 // With mu = lam_v' + h lam_x' (adjoints of the step's outputs), one reverse step is
 //     lam_x = lam_x' - kap mu + dL/dx,  lam_v = c mu,
 //     dL/dtheta += mu (dc/dtheta v - dkap/dtheta x + dsig/dtheta g).
-// The forward kernel writes (x, v, generator state) every K steps.  The backward kernel walks the
-// segments last to first: it restores a checkpoint, replays the segment with the same generator,
-// Box-Muller and update code (so the noise is bit-identical), keeps the segment's path in a
-// per-thread scratch column, and sweeps it backward.  No noise is kept across segments.
+// The forward kernel writes (x, v, generator state) every K steps and at the end.  The backward
+// kernels walk the segments last to first, in one of two ways per ensemble:
+//  * register-only (Hybrid Taus): start from the checkpoint at the segment's end and step both
+//    the generator (inverse Tausworthe and LCG steps, so the noise is bit-identical) and the
+//    integrator backward, x = x' - h v', v = (v' + kap x - sig g) / c, while sweeping the adjoint;
+//    the next segment restarts from its own end checkpoint, which bounds the growth of rounding
+//    errors in the reconstructed path to K steps (the host admits an ensemble only if that growth
+//    stays small).  Nothing is stored.
+//  * replay: restore the checkpoint at the segment's start, rerun the segment with the same
+//    generator, Box-Muller and update code, keep its path in a per-thread scratch column, and
+//    sweep it backward.
 // Gradients accumulate in FP64 per thread and reduce in a fixed order (no atomics).
 #include <type_traits>
 
@@ -132,12 +139,17 @@ __global__ __launch_bounds__(BLOCK) void ld_ckpt_kernel(AdjArgs a) {
             for (int d = 0; d < 3; ++d) lsum += static_cast<double>(x[d]) * x[d];
     }
     if (act) {
+        // the end state: the live buffers and the last checkpoint record
+        float *rx = reinterpret_cast<float *>(a.ckpt + static_cast<uint64_t>((a.n_steps + a.K - 1) / a.K) * a.rec_bytes);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             a.x[d * a.NT + i] = x[d];
             a.v[d * a.NT + i] = v[d];
+            rx[d * a.NT + i] = x[d];
+            rx[(3 + d) * a.NT + i] = v[d];
         }
         store_state(g, a.state, a.S, i);
+        store_state(g, rx + 6 * a.NT, a.NT, i);
     }
     double qv[3] = {act ? lsum : 0.0, 0.0, 0.0};
     block_sum3<BLOCK>(qv, red, a.partials + static_cast<uint64_t>(tile) * 3);
@@ -151,6 +163,7 @@ __global__ __launch_bounds__(BLOCK) void ld_adjoint_kernel(AdjArgs a) {
     const uint32_t e = find_ensemble(a.ens, a.n_ens, tile);
     const EnsDev &E = a.ens[e];
     const AdjCoef A = a.adj[e];
+    if (A.inverse) return;  // the register-only kernel owns this tile
     const float h = A.f.h, c = A.f.c, kap = A.f.kap;
     const uint64_t i = E.offset + static_cast<uint64_t>(tile - E.tile_begin) * BLOCK + threadIdx.x;
     const bool act = i < E.offset + E.n;
@@ -212,6 +225,65 @@ __global__ __launch_bounds__(BLOCK) void ld_adjoint_kernel(AdjArgs a) {
     block_sum3<BLOCK>(qv, red, a.partials + static_cast<uint64_t>(tile) * 3);
 }
 
+// register-only backward sweep (Hybrid Taus): no replay and no scratch
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void ld_adjoint_inv_kernel(AdjArgs a) {
+    __shared__ double red[BLOCK / 64][3];
+    const uint32_t tile = blockIdx.x;
+    const uint32_t e = find_ensemble(a.ens, a.n_ens, tile);
+    const EnsDev &E = a.ens[e];
+    const AdjCoef A = a.adj[e];
+    if (!A.inverse) return;  // the replay kernel owns this tile
+    const float h = A.f.h, c = A.f.c, kap = A.f.kap, sig = A.f.sig, inv_c = A.inv_c;
+    const uint64_t i = E.offset + static_cast<uint64_t>(tile - E.tile_begin) * BLOCK + threadIdx.x;
+    const bool act = i < E.offset + E.n;
+    const uint64_t col = act ? i : E.offset;  // inactive lanes follow a valid column
+    const uint64_t NT = a.NT;
+    HybridTaus g;
+    float lx[3] = {0, 0, 0}, lv[3] = {0, 0, 0};
+    double gk = 0.0, gg = 0.0, gT = 0.0;
+    const uint32_t nseg = (a.n_steps + a.K - 1) / a.K;
+    for (uint32_t seg = nseg; seg-- > 0;) {
+        const uint32_t s0 = seg * a.K;
+        const uint32_t s1 = (s0 + a.K < a.n_steps) ? s0 + a.K : a.n_steps;
+        // record seg + 1 holds the state at s1 (the end state for the last segment)
+        const float *rec = reinterpret_cast<const float *>(a.ckpt + static_cast<uint64_t>(seg + 1) * a.rec_bytes);
+        float x[3], v[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            x[d] = rec[d * NT + col];
+            v[d] = rec[(3 + d) * NT + col];
+        }
+        g.load(reinterpret_cast<const uint32_t *>(rec + 6 * NT), NT, col);
+        // x, v hold the state after step s on entry to step s
+        for (uint32_t s = s1; s-- > s0;) {
+            const bool in_loss = (s + 1 >= a.t_begin) && (s + 1 <= a.t_end);
+            const uint32_t w3 = g.prev();
+            const uint32_t w2 = g.prev();
+            const uint32_t w1 = g.prev();
+            const uint32_t w0 = g.prev();
+            float gf[3];
+            gaussian_forces(w0, w1, w2, w3, gf[0], gf[1], gf[2]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                if (in_loss) lx[d] += 2.0f * x[d];
+                const float xs = x[d] - h * v[d];
+                const float vs = (v[d] + kap * xs - sig * gf[d]) * inv_c;
+                const float mu = lv[d] + h * lx[d];
+                gk += static_cast<double>(mu) * static_cast<double>(-A.dkap_dk * xs);
+                gg += static_cast<double>(mu) * static_cast<double>(A.dc_dgamma * vs + A.dsig_dgamma * gf[d]);
+                gT += static_cast<double>(mu) * static_cast<double>(A.dsig_dkT * gf[d]);
+                lx[d] = lx[d] - kap * mu;
+                lv[d] = c * mu;
+                x[d] = xs;
+                v[d] = vs;
+            }
+        }
+    }
+    double qv[3] = {act ? gk : 0.0, act ? gg : 0.0, act ? gT : 0.0};
+    block_sum3<BLOCK>(qv, red, a.partials + static_cast<uint64_t>(tile) * 3);
+}
+
 __global__ __launch_bounds__(64) void adj_finalize_kernel(const double *partials, uint32_t width, const EnsDev *ens,
                                                           double denom_steps, double *out) {
     const uint32_t e = blockIdx.x;
@@ -239,13 +311,17 @@ hipError_t launch_ld_ckpt(int kind, const AdjArgs &a, uint32_t block, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_ld_adjoint(int kind, const AdjArgs &a, uint32_t block, hipStream_t st) {
-    (void)block;
+hipError_t launch_ld_adjoint(int kind, const AdjArgs &a, bool any_replay, bool any_inverse, hipStream_t st) {
     if (a.n_tiles == 0) return hipSuccess;
-    if (kind == RNGLD_RAN2)
-        ld_adjoint_kernel<Ran2, kAdjBlock><<<a.n_tiles, kAdjBlock, kR2Tab * kAdjBlock * 4, st>>>(a);
-    else
-        ld_adjoint_kernel<HybridTaus, kAdjBlock><<<a.n_tiles, kAdjBlock, 0, st>>>(a);
+    if (any_replay) {
+        if (kind == RNGLD_RAN2)
+            ld_adjoint_kernel<Ran2, kAdjBlock><<<a.n_tiles, kAdjBlock, kR2Tab * kAdjBlock * 4, st>>>(a);
+        else
+            ld_adjoint_kernel<HybridTaus, kAdjBlock><<<a.n_tiles, kAdjBlock, 0, st>>>(a);
+        const hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    if (any_inverse && kind == RNGLD_HYBRID_TAUS) ld_adjoint_inv_kernel<kAdjBlock><<<a.n_tiles, kAdjBlock, 0, st>>>(a);
     return hipGetLastError();
 }
 

@@ -13,8 +13,8 @@
 //    (256 positions each) of every step; once all its numbers of step s are loaded it publishes
 //    cons[w] = s + 1 (steps done).
 //
-// A producer handles nb links per iteration (nb sl <= ll, so their long-lag sources lie before
-// them) and publishes once per iteration.
+// A producer handles one link per iteration and publishes after each.  (The CPU checker also
+// simulates nb = 2 links per iteration, with the conditions below read with nb sl for sl.)
 // A ring slot of R >= ll + sl words holds position P; the producer writing P overwrites P - R.
 // The waits that make the run equal to the sequential recurrence, for a producer about to write
 // positions P of link j:
@@ -25,9 +25,9 @@
 //   (d) for P - R + sl in link 0: its producer, which reads P - R from the ring once at the start.
 // A consumer wave's step waits for the producers of its (at most 256 Kc) positions.
 //
-// No deadlock, given R >= ll + nb sl and R >= nb sl + 256 Kc - 1: every wait of an iteration over
-// links [j0, j0 + nb) is for producers' iterations that end by link j0 (a: sources lie nb sl back;
-// c: the readers of P - R lie R - ll >= nb sl back; d: P - R + sl in link 0 puts P beyond link nb)
+// No deadlock, given R >= ll + sl and R >= sl + 256 Kc - 1: every wait of an iteration over link
+// j0 is for producers' iterations that end by link j0 (a: sources lie at least sl back; c: the
+// readers of P - R lie R - ll >= sl back; d: P - R + sl in link 0 puts P beyond link 0)
 // or for a consumer step whose positions lie wholly before link j0 (b: a consumer's positions of a
 // step end within 256 Kc - 1 positions of P - R).  A consumer waits only for the producers of its
 // own positions and holds nothing while it waits.  So every wait points to earlier work, and with

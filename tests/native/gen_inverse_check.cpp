@@ -1,0 +1,70 @@
+// CPU check of the inverse generator steps in paper_1003_1123_amd/csrc/gen_int.hpp: for random
+// seeds, stepping each Tausworthe component and the LCG forward and then back with the inverse
+// steps returns every produced word exactly, and a seeded word's top K bits.  Also checks the
+// produced words against the component's bit recurrence y_m = y_{m-K+Q} xor y_{m-K} (Eq. 2), which
+// the inverse relies on.  Prints "ok" on success.
+#include <cstdio>
+#include <cstdint>
+#include <vector>
+
+#include "../../paper_1003_1123_amd/csrc/gen_int.hpp"
+
+using namespace rngld;
+
+static uint64_t sm_state = 0x1234567887654321ull;
+static uint32_t rnd() {
+    uint64_t z = (sm_state += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return static_cast<uint32_t>((z ^ (z >> 31)) >> 32);
+}
+
+template <int Q, int S, int K>
+static int check_component(int n_seeds, int n_steps) {
+    int bad = 0;
+    for (int t = 0; t < n_seeds; ++t) {
+        const uint32_t z0 = tausworthe_lift<K>(rnd());
+        std::vector<uint32_t> w(n_steps + 1);
+        w[0] = z0;
+        for (int n = 1; n <= n_steps; ++n) w[n] = tausworthe<Q, S, K>(w[n - 1]);
+        // produced words are 32-bit windows of the bit sequence, S bits apart
+        for (int n = 1; n < n_steps && bad < 10; ++n) {
+            // bit i of the sequence window of word n (i = 0 oldest) is bit 31 - i
+            auto bit = [&](int word, int i) { return (w[word] >> (31 - i)) & 1u; };
+            for (int i = 0; i + S < 32; ++i)
+                if (bit(n, i + S) != bit(n + 1, i)) ++bad;  // overlap of consecutive windows
+            for (int i = K; i < 32; ++i)
+                if (bit(n, i) != (bit(n, i - K + Q) ^ bit(n, i - K))) ++bad;  // recurrence inside one word
+        }
+        // the inverse walks back through every produced word
+        uint32_t x = w[n_steps];
+        for (int n = n_steps; n > 1; --n) {
+            x = tausworthe_inv<Q, S, K>(x);
+            if (x != w[n - 1]) ++bad;
+        }
+        constexpr uint32_t kTop = ~((1u << (32 - K)) - 1u);
+        if ((tausworthe_inv<Q, S, K>(x) & kTop) != (z0 & kTop)) ++bad;
+        // and forward again
+        if (n_steps >= 2 && tausworthe<Q, S, K>(tausworthe_inv<Q, S, K>(w[2])) != w[2]) ++bad;
+    }
+    if (bad) std::printf("component (%d,%d,%d): %d mismatches\n", Q, S, K, bad);
+    return bad;
+}
+
+int main() {
+    int bad = 0;
+    bad += check_component<13, 12, 31>(2000, 60);
+    bad += check_component<2, 4, 29>(2000, 60);
+    bad += check_component<3, 17, 28>(2000, 60);
+    for (int t = 0; t < 100000; ++t) {
+        const uint32_t x = rnd();
+        if (lcg_prev(lcg_next(x)) != x || lcg_next(lcg_prev(x)) != x) ++bad;
+    }
+    if (kLcgMul * kLcgMulInv != 1u) ++bad;
+    if (bad) {
+        std::printf("FAILED: %d\n", bad);
+        return 1;
+    }
+    std::printf("ok\n");
+    return 0;
+}

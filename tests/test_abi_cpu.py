@@ -166,12 +166,22 @@ def test_tuning_roundtrip_and_validation():
 
 def test_adjoint_sizing_and_validation():
     c = R.make_cfg("taus", n_streams=1000)
-    assert R.ld_ckpt_bytes(c, 1000, 2000, 100) == 20 * 1000 * (6 + 4) * 4
+    # 20 checkpoints plus the end state
+    assert R.ld_ckpt_bytes(c, 1000, 2000, 100) == 21 * 1000 * (6 + 4) * 4
+    assert R.ld_ckpt_bytes(c, 1000, 2001, 100) == 22 * 1000 * (6 + 4) * 4
     p = R.make_params()
     ens, n = R.make_ensembles([(0, 1000, p, 1)])
     loss = R.Loss(1001, 2000, 100, 0)
+    scratch = 9 * 100 * 1000 * 4
+    # weakly damped Hybrid Taus: register-only backward, no scratch
     ws = R.ld_adjoint_workspace_bytes(c, ens, n, 1000, 2000, loss)
-    assert ws >= 9 * 100 * 1000 * 4
+    assert ws < scratch
+    # forced replay, strong damping (gamma dt = 0.05 at K = 100) and Ran2 need the scratch
+    assert R.ld_adjoint_workspace_bytes(c, ens, n, 1000, 2000, R.Loss(1001, 2000, 100, R.ADJ_REPLAY)) >= scratch
+    ens5, n5 = R.make_ensembles([(0, 500, p, 1), (500, 500, R.make_params(gamma=5.0), 2)])
+    assert R.ld_adjoint_workspace_bytes(c, ens5, n5, 1000, 2000, loss) >= scratch
+    c2 = R.make_cfg("ran2", n_streams=1000)
+    assert R.ld_adjoint_workspace_bytes(c2, ens, n, 1000, 2000, loss) >= scratch
     with pytest.raises(R.RngldError) as e:
         R.ld_adjoint_workspace_bytes(c, ens, n, 1000, 2000, R.Loss(0, 2000, 100, 0))
     assert e.value.code == R.EINVAL

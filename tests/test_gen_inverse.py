@@ -1,0 +1,24 @@
+"""CPU check of the inverse generator steps (paper_1003_1123_amd/csrc/gen_int.hpp) used by the
+register-only adjoint: Tausworthe components and the LCG stepped forward and back return every
+produced word; produced words are windows of the component's bit recurrence (Eq. 2).  Compiled
+with the host compiler."""
+import os
+import shutil
+import subprocess
+import tempfile
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def test_inverse_steps_walk_back_every_word():
+    cxx = shutil.which("g++") or shutil.which("c++")
+    if cxx is None:
+        pytest.skip("no host C++ compiler")
+    with tempfile.TemporaryDirectory() as d:
+        exe = os.path.join(d, "gen_inverse_check")
+        subprocess.check_call([cxx, "-O2", "-std=c++17", "-Wall", "-Werror", "-o", exe,
+                               os.path.join(HERE, "native", "gen_inverse_check.cpp")])
+        r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout

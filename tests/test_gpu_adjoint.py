@@ -98,3 +98,55 @@ def test_config5_gradients():
     fd = np.array(fd)
     _say("config5 FD", fd)
     assert np.all(np.abs(fd - grad) <= 2e-3 * np.max(np.abs(grad)) + 1e-4 * np.abs(grad))
+
+
+def _grads(kind, shape, params, T, tb, te, K, replay=False):
+    run = A.AdjointRun(kind, shape, T, tb, te, K, replay=replay)
+    k = torch.tensor([p[0] for p in params], dtype=torch.float64, requires_grad=True)
+    g = torch.tensor([p[1] for p in params], dtype=torch.float64, requires_grad=True)
+    kT = torch.tensor([p[2] for p in params], dtype=torch.float64, requires_grad=True)
+    L = A.LDAdjoint.apply(k, g, kT, run)
+    L.sum().backward()
+    torch.cuda.synchronize()
+    return run, L.detach().cpu().numpy(), np.stack([k.grad.numpy(), g.grad.numpy(), kT.grad.numpy()], axis=1)
+
+
+def test_register_only_backward_equals_replay():
+    """The register-only backward (inverse generator steps, backward integration from each
+    segment's end checkpoint) against the replay backward on the same forward run: the noise is
+    the same bit for bit, so the gradients differ only by the rounding of the reconstructed path."""
+    T, tb, te, K = 500, 101, 500, 64
+    shape = [(3000, 1.0, 0.01, 5), (1000, 1.0, 0.01, 6)]
+    params = [(1.0, 1.0, 1.0), (2.0, 1.5, 0.7)]
+    run_i, Li, gi = _grads("taus", shape, params, T, tb, te, K)
+    run_r, Lr, gr = _grads("taus", shape, params, T, tb, te, K, replay=True)
+    assert run_i.ws.numel() < run_r.ws.numel()  # no replay scratch on the register-only path
+    assert np.array_equal(Li, Lr)
+    err = np.max(np.abs(gi - gr) / np.max(np.abs(gr), axis=1, keepdims=True))
+    _say("register-only vs replay: max relative gradient difference", err)
+    assert err <= 2e-5, (gi, gr)
+
+
+def test_checkpoint_end_record_is_the_final_state():
+    N, T, K = 777, 130, 50  # records at steps 0, 50, 100 and the end state (step 130)
+    run, _, _ = _grads("taus", [(N, 1.0, 0.01, 9)], [(1.0, 1.0, 1.0)], T, 1, T, K)
+    rec = (6 + 4) * N * 4
+    last = run.ckpt[3 * rec:4 * rec]
+    assert torch.equal(last[:3 * N * 4].view(torch.float32), run.x)
+    assert torch.equal(last[3 * N * 4:6 * N * 4].view(torch.float32), run.v)
+    assert torch.equal(last[6 * N * 4:], run.state[:4 * N * 4])
+
+
+def test_mixed_paths_match_the_oracle():
+    """A strongly damped ensemble (gamma dt = 0.06: replay) batched with a weakly damped one
+    (register-only); each against the FP64 oracle adjoint."""
+    T, tb, te, K = 300, 1, 300, 100
+    shape = [(800, 1.0, 0.01, 21), (600, 1.0, 0.01, 22)]
+    params = [(1.0, 0.5, 1.0), (1.5, 6.0, 0.8)]
+    _, L, grad = _grads("taus", shape, params, T, tb, te, K)
+    for e, ((n, m, dt, seed), (k, gm, kT)) in enumerate(zip(shape, params)):
+        pd = W.LDParams(m=m, k=k, gamma=gm, kT=kT, dt=dt).as_f32().asdict()
+        Lo, go = orc.ld_adjoint("taus", orc.seed_states("taus", seed, np.arange(n)), n, T, pd, tb, te)
+        assert abs(L[e] - Lo) <= 1e-4 * abs(Lo)
+        scale = np.max(np.abs(go))
+        assert np.all(np.abs(grad[e] - go) <= 1e-3 * np.maximum(np.abs(go), 1e-2 * scale)), (e, grad[e], go)
