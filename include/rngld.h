@@ -72,7 +72,11 @@ extern "C" {
  *                do not depend on W.
  *  lf_ring     : LF ring length R in words; 0 selects 2 (ll + sl), or ll + sl when 2 (ll + sl)
  *                reaches 2^30.  Must satisfy ll + W <= R < 2^31.  A fused LD run uses one
- *                persistent launch when sl >= 256 and ll + sl <= R < 2^30.
+ *                persistent launch when sl >= 256 and its own copy of the sequence (about
+ *                2 (ll + sl) words, each sl-long link padded to a 256-byte boundary, in the
+ *                workspace) stays below 2^30 words; it reads the state's last ll values at the
+ *                start and writes the new last ll values back at the end, so its result does not
+ *                depend on R.
  *  lcg_leap    : LCG only.  0: stream j starts from its own seed word (word 0 of stream j).  L > 0:
  *                the streams divide one sequence (cycle division, Sec. III): stream j starts at
  *                position j * L of the sequence from word 0 of stream 0.  Eq. 1 has a single cycle

@@ -195,9 +195,9 @@ struct RunLayout {
     // LF wave structure
     uint32_t Q = 0, bpp = 0;
     uint64_t Nq = 0;
-    // LF persistent run: 64-oscillator tiles, progress words
+    // LF persistent run: 64-oscillator tiles, progress words, its own ring (0 bytes: none)
     uint32_t flow_tiles = 0;
-    size_t off_flags = 0;
+    size_t off_flags = 0, off_pring = 0, pring_bytes = 0;
 };
 
 int layout_run(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total, uint32_t n_steps,
@@ -241,9 +241,16 @@ int layout_run(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t 
     L->off_partials = align_up(L->off_ens + sizeof(EnsDev) * n_ens);
     L->off_t0 = align_up(L->off_partials + static_cast<size_t>(L->P) * L->n_tiles * RNGLD_NOBS * sizeof(double));
     L->bytes = L->off_t0 + (stride ? align_up(6 * static_cast<size_t>(n_total) * sizeof(float)) : 0);
-    if (g.kind == RNGLD_LAGFIB) {  // producer and consumer progress words
+    if (g.kind == RNGLD_LAGFIB) {  // producer and consumer progress words, the run's own ring
         L->off_flags = L->bytes;
         L->bytes += align_up(2 * static_cast<size_t>(kLfFlowMaxWaves) * kLfFlagStride * sizeof(uint32_t));
+        const LfPadRing pr = lf_pad_ring(g.ll, g.sl);
+        const uint64_t words = static_cast<uint64_t>(pr.nr) * pr.slp;
+        if (words < (1ull << 30)) {
+            L->off_pring = L->bytes;
+            L->pring_bytes = align_up(words * sizeof(uint32_t));
+            L->bytes += L->pring_bytes;
+        }
     }
     return RNGLD_OK;
 }
@@ -268,19 +275,20 @@ bool debug_enabled() {
     return on;
 }
 
-// the dataflow LF run: returns hipSuccess when launched, hipErrorCooperativeLaunchTooLarge (or
-// another error) when it could not be; the caller then falls back to waves
 // The persistent producer/consumer LF run, if this run fits it: returns 1 when launched, 0 when the
 // wave path must run instead, an RNGLD error otherwise.
 int try_lf_flow(const Gen &g, void *d_state, const RunLayout &L, uint32_t n_steps, float *d_x, float *d_v,
                 uint64_t n_total, uint32_t stride, uint32_t t0, double *partials, float *t0buf, uint32_t *flags,
-                uint32_t *status, hipStream_t st) {
+                uint32_t *pring, uint32_t *status, hipStream_t st) {
     const EnsDev &E = L.ens[0];
     const uint64_t n = E.n;
-    if (n == 0 || g.sl < 256 || g.R >= (1u << 30)) return 0;
-    // producers advance one link (sl positions) at a time; the ring must keep the readers of what
-    // they overwrite behind them
-    if (g.R < static_cast<uint64_t>(g.ll) + g.sl) return 0;
+    // the run keeps the sequence in a ring of its own (nr links of slp words, each link on a
+    // 256-byte boundary); in positions it holds R = nr sl >= 2 (ll + sl), which keeps the readers of
+    // what a producer overwrites behind it
+    if (n == 0 || g.sl < 256 || L.pring_bytes == 0) return 0;
+    const LfPadRing pr = lf_pad_ring(g.ll, g.sl);
+    const uint64_t R_run = static_cast<uint64_t>(pr.nr) * g.sl;
+    if (R_run >= (1ull << 31)) return 0;
     const uint64_t Ptot = 4ull * n * n_steps;
     if ((Ptot + g.sl - 1) / g.sl >= (1ull << 31)) return 0;
     const int cus = device_cus();
@@ -294,7 +302,7 @@ int try_lf_flow(const Gen &g, void *d_state, const RunLayout &L, uint32_t n_step
     if (Gp > kLfFlowMaxWaves || Gc > kLfFlowMaxWaves) return 0;
     uint32_t slice_log2 = 8;  // at least 256 offsets: a consumer tile then spans at most two slices
     while ((static_cast<uint64_t>(Gp) << slice_log2) < g.sl) ++slice_log2;
-    const LfFlowGeom geom = lf_flow_geom(n, n_steps, g.ll, g.sl, g.R, slice_log2, Gc);
+    const LfFlowGeom geom = lf_flow_geom(n, n_steps, g.ll, g.sl, static_cast<uint32_t>(R_run), slice_log2, Gc);
     uint32_t kc = 0;
     for (uint32_t k : {1u, 2u, 4u, 8u})
         if (geom.Kc <= k) {
@@ -302,8 +310,9 @@ int try_lf_flow(const Gen &g, void *d_state, const RunLayout &L, uint32_t n_step
             break;
         }
     if (!kc) return 0;
-    // the ring must also hold a consumer step's positions behind the producers (lf_flow.hpp)
-    if (g.R < static_cast<uint64_t>(g.sl) + 256ull * geom.Kc - 1) return 0;
+    // the ring must also hold a consumer step's positions behind the producers (lf_flow.hpp), and a
+    // consumer's positions of a step span at most two links
+    if (R_run < static_cast<uint64_t>(g.sl) + 256ull * geom.Kc - 1 || 256ull * geom.Kc > g.sl) return 0;
     const size_t lds = static_cast<size_t>(wpb - np) * (geom.Kc * 384u + 256u) * sizeof(float);
     if (lds > 160 * 1024) return 0;
     if (debug_enabled())
@@ -313,6 +322,8 @@ int try_lf_flow(const Gen &g, void *d_state, const RunLayout &L, uint32_t n_step
     LfFlowArgs a{};
     a.L = lf_ring(g, d_state);
     a.geom = geom;
+    a.pring = pring;
+    a.pr = pr;
     a.x = d_x + E.offset;
     a.v = d_v + E.offset;
     a.t0buf = t0buf;
@@ -329,7 +340,7 @@ int try_lf_flow(const Gen &g, void *d_state, const RunLayout &L, uint32_t n_step
     a.pstride = L.n_tiles;
     a.spin_limit = 1u << 20;
     a.np = np;
-    a.step_adv = static_cast<uint32_t>((4ull * n) % g.R);
+    RNGLD_TRY_HIP(launch_lf_pad_in(a.L, pring, pr, st));
     RNGLD_TRY_HIP(launch_fill_u32(a.prod, static_cast<uint64_t>(Gp) * kLfFlagStride, 0u, st));
     RNGLD_TRY_HIP(launch_fill_u32(a.cons, static_cast<uint64_t>(Gc) * kLfFlagStride, 0u, st));
     const hipError_t e = launch_lf_flow(a, static_cast<uint32_t>(cus), kc, static_cast<uint32_t>(lds), st);
@@ -339,6 +350,7 @@ int try_lf_flow(const Gen &g, void *d_state, const RunLayout &L, uint32_t n_step
         return 0;
     }
     if (e != hipSuccess) return fail(RNGLD_EHIP, "persistent LF launch: %s", hipGetErrorString(e));
+    RNGLD_TRY_HIP(launch_lf_pad_out(a.L, pring, pr, Ptot, st));
     return 1;
 }
 
@@ -360,7 +372,8 @@ int enqueue_run(const Gen &g, void *d_state, const RunLayout &L, const ld_tuning
         RNGLD_TRY_HIP(launch_upload(d_ens, ens.data(), sizeof(EnsDev), st));
         uint32_t *flags = reinterpret_cast<uint32_t *>(ws + L.off_flags);
         const int r = try_lf_flow(g, d_state, L, n_steps, d_x, d_v, n_total, stride, t0, partials,
-                                  t0buf + L.ens[0].offset, flags, status, st);
+                                  t0buf + L.ens[0].offset, flags,
+                                  reinterpret_cast<uint32_t *>(ws + L.off_pring), status, st);
         if (r < 0) return r;
         if (r == 1) {
             RNGLD_TRY_HIP(launch_fill_u32(status + 1, 1, kPathDataflow, st));

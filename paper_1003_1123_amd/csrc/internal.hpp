@@ -82,8 +82,10 @@ struct LfLdPhase {
 // persistent dataflow LD run over the shared lagged-Fibonacci sequence (k_lf.hip)
 // the persistent producer/consumer LD run (roles and waits: lf_flow.hpp)
 struct LfFlowArgs {
-    LfRing L;
-    LfFlowGeom geom;
+    LfRing L;              // the state's ring (read by the copy kernels only)
+    LfFlowGeom geom;       // waits, with R = nr sl
+    uint32_t *pring;       // the run's own ring: nr links of slp words
+    LfPadRing pr;
     float *x, *v;          // first oscillator of the run; row stride N
     float *t0buf;          // [6][N] x(t0), v(t0)
     double *partials;      // [P][pstride][6], one row entry per 64-oscillator tile
@@ -98,7 +100,6 @@ struct LfFlowArgs {
     uint32_t pstride;
     uint32_t spin_limit;   // polls of one wait before the run gives up
     uint32_t np;           // producer waves per block: the block's first np waves
-    uint32_t step_adv;     // (4n) mod R
 };
 
 // ---- adjoint (k_adj.hip) ---------------------------------------------------------------------------
@@ -174,6 +175,12 @@ constexpr uint32_t kLfFlagStride = 32;       // words between progress words: on
 // launch the producer/consumer kernel for consumer waves of up to kc tiles each; `lds` bytes of
 // dynamic LDS per block.  hipErrorCooperativeLaunchTooLarge if `grid` blocks cannot be co-resident.
 hipError_t launch_lf_flow(const LfFlowArgs &a, uint32_t grid, uint32_t kc, uint32_t lds, hipStream_t st);
+// copy the window y_{-ll..-1} before a persistent run from the state's ring into the run's ring,
+// and afterwards the window y_{Ptot-ll..Ptot-1} back (slots relative to the run's first position;
+// the header is advanced separately)
+hipError_t launch_lf_pad_in(const LfRing &L, uint32_t *pring, const LfPadRing &pr, hipStream_t st);
+hipError_t launch_lf_pad_out(const LfRing &L, const uint32_t *pring, const LfPadRing &pr, uint64_t Ptot,
+                             hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *dst, uint64_t count, uint32_t value, hipStream_t st);
 
 }  // namespace rngld

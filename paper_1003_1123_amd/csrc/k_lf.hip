@@ -316,37 +316,48 @@ __device__ __forceinline__ bool producer_wait_link(const LfFlowArgs &a, uint32_t
 __device__ __forceinline__ void lf_producer(const LfFlowArgs &a, uint32_t p, uint32_t lane) {
     const LfFlowGeom &g = a.geom;
     if (p >= g.n_slices) return;
-    const uint32_t R = a.L.R, sl = g.sl, ll = a.L.ll;
+    const uint32_t sl = g.sl, lla = g.ll.a, llb = g.ll.b;  // ll = lla sl + llb
+    const uint32_t slp = a.pr.slp, ring_words = a.pr.nr * a.pr.slp;
     const uint32_t o_lo = p << g.slice_log2;
     const uint32_t width = ((1u << g.slice_log2) < sl - o_lo) ? (1u << g.slice_log2) : sl - o_lo;
-    uint32_t *ring = a.L.ring;
+    uint32_t *ring = a.pring;
     auto link_len = [&](uint32_t j) -> uint32_t {
         if (j >= g.n_links) return 0u;
         const uint64_t P_lo = static_cast<uint64_t>(j) * sl + o_lo;
         return P_lo >= g.Ptot ? 0u : (g.Ptot - P_lo < width ? static_cast<uint32_t>(g.Ptot - P_lo) : width);
     };
-    uint32_t slot = wrap_once(a.L.hdr->slot + o_lo, R);  // slot of (link j, o_lo)
-    // y_{P - sl} of link 0 comes from the ring, afterwards from the previous link in registers
+    // words of link j and of link j - lla, the long lag's link for offsets >= llb (advanced
+    // together, link by link)
+    uint32_t base = 0, base_ll = lf_pad_base(a.pr, -static_cast<int64_t>(lla));
+    // y_{P - sl} of link 0 comes from the ring (link -1), afterwards from the previous link in
+    // registers
     uint32_t chain[kFlowM], src[kFlowM];
+    {
+        const uint32_t base_prev = lf_pad_base(a.pr, -1);
 #pragma unroll
-    for (int r = 0; r < kFlowM; ++r) {
-        const uint32_t q = lane + 64u * r;
-        chain[r] = q < width ? ring_get(ring, back(wrap_once(slot + q, R), sl, R)) : 0u;
+        for (int r = 0; r < kFlowM; ++r) {
+            const uint32_t q = lane + 64u * r;
+            chain[r] = q < width ? ring_get(ring, base_prev + o_lo + q) : 0u;
+        }
     }
     int64_t step_R;
     uint64_t off_R;
-    lf_consumer_coord0(g, o_lo, R, step_R, off_R);  // consumer coordinate of (link j, o_lo) - R
+    // consumer coordinate of (link j, o_lo) - R, R = nr sl
+    lf_consumer_coord0(g, o_lo, static_cast<uint64_t>(a.pr.nr) * sl, step_R, off_R);
     LfWaitTemplate tpl;
     lf_wait_template(g, p, o_lo, width, tpl);
     FlowWaits w;
     w.n = 0;
     // kFlowM long-lag loads of a link, always all issued (an unused one reads the link's first
-    // source), so that their count is exact
-    auto load_link = [&](uint32_t slot_j, uint32_t len_j) {
+    // source), so that their count is exact.  Offset o's source is (link - lla, o - llb) when
+    // o >= llb, else (link - lla - 1, o + sl - llb).
+    auto load_link = [&](uint32_t bll, uint32_t len_j) {
+        const uint32_t bll1 = bll >= slp ? bll - slp : bll + ring_words - slp;
 #pragma unroll
         for (int r = 0; r < kFlowM; ++r) {
             const uint32_t q = lane + 64u * r;
-            src[r] = ring_get(ring, back(wrap_once(slot_j + (q < len_j ? q : 0u), R), ll, R));
+            const uint32_t o = o_lo + (q < len_j ? q : 0u);
+            src[r] = ring_get(ring, o >= llb ? bll + (o - llb) : bll1 + (o + (sl - llb)));
         }
     };
     // one read of the first 64 progress words link j1 waits for (lanes without a wait read the
@@ -365,9 +376,10 @@ __device__ __forceinline__ void lf_producer(const LfFlowArgs &a, uint32_t p, uin
         lf_consumer_coord_next(g, sR1, oR1);
         poll_link(1, sR1, oR1);
     }
-    load_link(slot, len);
+    load_link(base_ll, len);
     for (uint32_t j = 0; j < g.n_links; ++j) {
-        const uint32_t next_slot = wrap_once(slot + sl, R);
+        const uint32_t next_base = base + slp < ring_words ? base + slp : 0u;
+        const uint32_t next_base_ll = base_ll + slp < ring_words ? base_ll + slp : 0u;
         int64_t next_sR = step_R;
         uint64_t next_oR = off_R;
         lf_consumer_coord_next(g, next_sR, next_oR);
@@ -382,12 +394,12 @@ __device__ __forceinline__ void lf_producer(const LfFlowArgs &a, uint32_t p, uin
             // a full slice: straight-line stores, so that no store waits for another (a store in
             // a branch of its own can make the compiler wait for the previous one)
 #pragma unroll
-            for (int r = 0; r < kFlowM; ++r) ring_put(ring, wrap_once(slot + lane + 64u * r, R), chain[r]);
+            for (int r = 0; r < kFlowM; ++r) ring_put(ring, base + o_lo + lane + 64u * r, chain[r]);
         } else {
 #pragma unroll
             for (int r = 0; r < kFlowM; ++r) {
                 const uint32_t q = lane + 64u * r;
-                if (q < len) ring_put(ring, wrap_once(slot + q, R), chain[r]);
+                if (q < len) ring_put(ring, base + o_lo + q, chain[r]);
             }
         }
         if (!ready) {
@@ -402,7 +414,7 @@ __device__ __forceinline__ void lf_producer(const LfFlowArgs &a, uint32_t p, uin
             lf_consumer_coord_next(g, sR2, oR2);
             poll_link(j + 2, sR2, oR2);
         }
-        load_link(next_slot, next_len);
+        load_link(next_base_ll, next_len);
         if (ready) {
             // only the poll and link j+1's kFlowM loads, issued after link j's stores, may still be
             // outstanding: link j is stored
@@ -410,7 +422,8 @@ __device__ __forceinline__ void lf_producer(const LfFlowArgs &a, uint32_t p, uin
             asm volatile("s_waitcnt vmcnt(17)" ::: "memory");
             if (lane == 0) agent_store(a.prod + p * kLfFlagStride, j + 1);
         }
-        slot = next_slot;
+        base = next_base;
+        base_ll = next_base_ll;
         step_R = next_sR;
         off_R = next_oR;
         len = next_len;
@@ -451,8 +464,8 @@ __device__ __forceinline__ void tile_observe(const LfFlowArgs &a, const float *t
 template <int KC>
 __device__ __forceinline__ void lf_consumer(const LfFlowArgs &a, uint32_t cw, uint32_t lane, float *xv, uint32_t *tr) {
     const LfFlowGeom &g = a.geom;
-    const uint32_t R = a.L.R, Kc = g.Kc;
-    uint32_t *ring = a.L.ring;
+    const uint32_t Kc = g.Kc, sl = g.sl, slp = a.pr.slp, nr = a.pr.nr, ring_words = nr * slp;
+    uint32_t *ring = a.pring;
     const uint64_t o0 = 64ull * cw * Kc < a.n ? 64ull * cw * Kc : a.n;
     const uint64_t o1 = 64ull * (cw + 1) * Kc < a.n ? 64ull * (cw + 1) * Kc : a.n;
     if (o0 >= o1) return;  // no oscillators: no producer ever waits for this wave
@@ -468,10 +481,11 @@ __device__ __forceinline__ void lf_consumer(const LfFlowArgs &a, uint32_t cw, ui
             xv[(k * 6 + 3 + d) * 64 + lane] = act ? a.v[d * a.N + o] : 0.0f;
         }
     }
-    // the step's first position 4 o0 + s 4n: its link, offset and ring slot
+    // the step's first position 4 o0 + s 4n: its link, offset and the link's first word (a step's
+    // positions span at most two links: 256 Kc <= sl)
     int64_t link = static_cast<int64_t>((4 * o0) / g.sl);
     uint32_t off = static_cast<uint32_t>((4 * o0) % g.sl);
-    uint32_t slot_s = wrap_once(a.L.hdr->slot + static_cast<uint32_t>((4 * o0) % R), R);
+    uint32_t lbase = lf_pad_base(a.pr, link);
     FlowWaits w;
     w.n = 0;
     for (uint32_t s = 0; s < a.n_steps; ++s) {
@@ -505,12 +519,14 @@ __device__ __forceinline__ void lf_consumer(const LfFlowArgs &a, uint32_t cw, ui
         });
         if (!wait_all(w, lane, a)) return;
         uint32_t words[KC][4];
+        const uint32_t nbase = lbase + slp < ring_words ? lbase + slp : 0u;
 #pragma unroll
         for (int k = 0; k < KC; ++k)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const uint32_t q = 256u * k + lane + 64u * r;
-                words[k][r] = q < cnt ? ring_get(ring, wrap_once(slot_s + q, R)) : 0u;
+                const uint32_t o = off + q;
+                words[k][r] = q < cnt ? ring_get(ring, o < sl ? lbase + o : nbase + (o - sl)) : 0u;
             }
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the loads have returned: the slots are free
         if (lane == 0) agent_store(a.cons + cw * kLfFlagStride, s + 1);
@@ -536,8 +552,10 @@ __device__ __forceinline__ void lf_consumer(const LfFlowArgs &a, uint32_t cw, ui
                 }
             }
         }
-        slot_s = wrap_once(slot_s + a.step_adv, R);
+        const int64_t link_before = link;
         lf_link_coord_next_step(g, link, off);
+        lbase += (static_cast<uint32_t>(link - link_before) % nr) * slp;
+        if (lbase >= ring_words) lbase -= ring_words;
     }
     float *t0buf = a.t0buf, *xo = a.x, *vo = a.v;
     asm volatile("" : "+s"(t0buf), "+s"(xo), "+s"(vo));
@@ -573,6 +591,29 @@ __global__ __launch_bounds__(kLfFlowBlock) void lf_pc_kernel(LfFlowArgs a) {
         lf_consumer<KC>(a, __builtin_amdgcn_readfirstlane(blockIdx.x * nc + k), lane, base,
                         reinterpret_cast<uint32_t *>(base + a.geom.Kc * 384u));
     }
+}
+
+// the window before a persistent run: run positions -ll..-1 from the state's ring (slot
+// hdr->slot is run position 0) into the run's ring
+__global__ __launch_bounds__(kBulkBlock) void lf_pad_in_kernel(LfRing L, uint32_t *pring, LfPadRing pr) {
+    const uint64_t i = blockIdx.x * static_cast<uint64_t>(kBulkBlock) + threadIdx.x;
+    if (i >= L.ll) return;
+    const int64_t P = static_cast<int64_t>(i) - L.ll;
+    // (slot + P) mod R with -ll <= P < 0 and ll <= R
+    const uint64_t s = static_cast<uint64_t>(L.hdr->slot) + L.R - L.ll + i;
+    pring[lf_pad_slot(pr, L.sl, P)] = L.ring[s >= L.R ? s - L.R : s];
+}
+
+// after the run: run positions Ptot - ll .. Ptot - 1 back into the state's ring, at the slots
+// relative to run position 0 (still hdr->slot)
+__global__ __launch_bounds__(kBulkBlock) void lf_pad_out_kernel(LfRing L, const uint32_t *pring, LfPadRing pr,
+                                                                uint64_t Ptot) {
+    const uint64_t i = blockIdx.x * static_cast<uint64_t>(kBulkBlock) + threadIdx.x;
+    if (i >= L.ll) return;
+    const int64_t P = static_cast<int64_t>(Ptot) - L.ll + static_cast<int64_t>(i);
+    int64_t s = (static_cast<int64_t>(L.hdr->slot) + P % static_cast<int64_t>(L.R)) % static_cast<int64_t>(L.R);
+    if (s < 0) s += L.R;
+    L.ring[s] = pring[lf_pad_slot(pr, L.sl, P)];
 }
 
 __global__ __launch_bounds__(kBulkBlock) void fill_u32_kernel(uint32_t *dst, uint64_t count, uint32_t value) {
@@ -628,6 +669,17 @@ hipError_t launch_lf_gauss_phase(const LfRing &L, float *out, uint64_t first, ui
     const uint32_t pairs = count / 2;
     if (pairs == 0) return hipSuccess;
     lf_gauss_phase_kernel<<<grid_for(pairs), kBulkBlock, 0, st>>>(L, out, first, off_mod, pairs);
+    return hipGetLastError();
+}
+
+hipError_t launch_lf_pad_in(const LfRing &L, uint32_t *pring, const LfPadRing &pr, hipStream_t st) {
+    lf_pad_in_kernel<<<grid_for(L.ll), kBulkBlock, 0, st>>>(L, pring, pr);
+    return hipGetLastError();
+}
+
+hipError_t launch_lf_pad_out(const LfRing &L, const uint32_t *pring, const LfPadRing &pr, uint64_t Ptot,
+                             hipStream_t st) {
+    lf_pad_out_kernel<<<grid_for(L.ll), kBulkBlock, 0, st>>>(L, pring, pr, Ptot);
     return hipGetLastError();
 }
 

@@ -99,6 +99,38 @@ inline LfFlowGeom lf_flow_geom(uint64_t n, uint32_t n_steps, uint32_t ll, uint32
     return g;
 }
 
+// ---- the run's own ring ------------------------------------------------------------------------------
+// The persistent run keeps the sequence in a ring of nr links of its own: link L (positions
+// [L sl, (L+1) sl) of the run; L < 0 before it) occupies the words [(L mod nr) slp,
+// (L mod nr) slp + sl), slp = sl rounded up to 64 words.  Every link, and so every producer slice
+// (its offsets start at multiples of 2^slice_log2 >= 256), then starts on a 256-byte boundary and a
+// wave's 64 consecutive stores fill whole cache lines.  In position terms the ring holds R = nr sl
+// positions: the R of the waits above, with P - R in the same slot as P.
+struct LfPadRing {
+    uint32_t nr;   // links held
+    uint32_t slp;  // words per link
+};
+
+// nr = ceil(2 (ll + sl) / sl): twice the reach of the lags, so producers can run ahead
+inline LfPadRing lf_pad_ring(uint32_t ll, uint32_t sl) {
+    LfPadRing r;
+    r.nr = static_cast<uint32_t>((2 * (static_cast<uint64_t>(ll) + sl) + sl - 1) / sl);
+    r.slp = (sl + 63u) & ~63u;
+    return r;
+}
+
+RNGLD_HD inline uint32_t lf_pad_base(const LfPadRing &r, int64_t link) {
+    int64_t m = link % static_cast<int64_t>(r.nr);
+    if (m < 0) m += r.nr;
+    return static_cast<uint32_t>(m) * r.slp;
+}
+
+// word of run position P (P < 0: the window before the run)
+RNGLD_HD inline uint32_t lf_pad_slot(const LfPadRing &r, uint32_t sl, int64_t P) {
+    const int64_t link = P >= 0 ? P / sl : -((-P + sl - 1) / static_cast<int64_t>(sl));
+    return lf_pad_base(r, link) + static_cast<uint32_t>(P - link * static_cast<int64_t>(sl));
+}
+
 // (link, off) of position (j, o) - lag; link < 0 means before the run
 RNGLD_HD inline void lf_back(uint32_t j, uint32_t o, LfLag L, uint32_t sl, int64_t &link, uint32_t &off) {
     if (o >= L.b) {

@@ -327,8 +327,71 @@ static int simulate(const Run &r, uint32_t nb, uint32_t slot0) {
     return bad;
 }
 
+// The run's own ring (lf_pad_ring, lf_pad_slot): any R = nr sl consecutive positions occupy
+// distinct words below nr slp, every link starts on a 64-word boundary, and the address rules of the
+// kernels -- producer's own link base and long-lag bases advanced link by link, consumer's step
+// window split over two links -- give lf_pad_slot of the position they mean.
+static int check_pad_ring(uint32_t ll, uint32_t sl) {
+    const LfPadRing pr = lf_pad_ring(ll, sl);
+    const uint64_t R = static_cast<uint64_t>(pr.nr) * sl, words = static_cast<uint64_t>(pr.nr) * pr.slp;
+    int bad = 0;
+    if (R < static_cast<uint64_t>(ll) + sl || pr.slp % 64 || pr.slp < sl) ++bad;
+    for (int64_t P0 : {-static_cast<int64_t>(ll), static_cast<int64_t>(0), 3 * static_cast<int64_t>(sl) + 5}) {
+        std::vector<char> used(words, 0);
+        for (int64_t P = P0; P < P0 + static_cast<int64_t>(R); ++P) {
+            const uint32_t w = lf_pad_slot(pr, sl, P);
+            if (w >= words || used[w]) {
+                ++bad;
+                break;
+            }
+            used[w] = 1;
+            if (((P % sl) + sl) % sl == 0 && w % 64) ++bad;
+        }
+    }
+    const uint32_t lla = ll / sl, llb = ll % sl, slp = pr.slp, rw = pr.nr * pr.slp;
+    uint32_t base = 0, base_ll = lf_pad_base(pr, -static_cast<int64_t>(lla));
+    for (int64_t j = 0; j < 3 * static_cast<int64_t>(pr.nr) + 2; ++j) {
+        if (base != lf_pad_base(pr, j)) ++bad;
+        const uint32_t bll1 = base_ll >= slp ? base_ll - slp : base_ll + rw - slp;
+        for (uint32_t o : {0u, 1u, llb ? llb - 1 : 0u, llb, sl / 2, sl - 1, rnd(sl)}) {
+            const uint32_t idx = o >= llb ? base_ll + (o - llb) : bll1 + (o + (sl - llb));
+            if (idx != lf_pad_slot(pr, sl, j * static_cast<int64_t>(sl) + o - ll)) ++bad;
+            if (base + o != lf_pad_slot(pr, sl, j * static_cast<int64_t>(sl) + o)) ++bad;
+        }
+        base = base + slp < rw ? base + slp : 0u;
+        base_ll = base_ll + slp < rw ? base_ll + slp : 0u;
+    }
+    // consumer: a step of four_n positions from (link, off), the link base advanced with the link
+    for (uint64_t four_n : {static_cast<uint64_t>(4), static_cast<uint64_t>(sl > 8 ? sl - 4 : 5),
+                            static_cast<uint64_t>(sl) + 12, static_cast<uint64_t>(7) * sl + 1000}) {
+        int64_t link = 0;
+        uint32_t off = 0, lbase = lf_pad_base(pr, 0);
+        for (int s = 0; s < 40; ++s) {
+            const uint32_t nbase = lbase + slp < rw ? lbase + slp : 0u;
+            const int64_t P0 = static_cast<int64_t>(s) * static_cast<int64_t>(four_n);
+            // q < sl: the kernel takes a step window of at most sl positions (256 Kc <= sl)
+            for (uint32_t q : {0u, 1u % sl, std::min(255u, sl - 1), sl - 1, rnd(sl)}) {
+                const uint32_t o = off + q;
+                const uint32_t idx = o < sl ? lbase + o : nbase + (o - sl);
+                if (idx != lf_pad_slot(pr, sl, P0 + q)) ++bad;
+            }
+            const int64_t before = link;
+            const uint64_t o2 = off + four_n;
+            link += static_cast<int64_t>(o2 / sl);
+            off = static_cast<uint32_t>(o2 % sl);
+            lbase += (static_cast<uint32_t>(link - before) % pr.nr) * slp;
+            if (lbase >= rw) lbase -= rw;
+        }
+    }
+    if (bad) std::printf("pad ring (%u, %u): %d mismatches\n", ll, sl, bad);
+    return bad;
+}
+
 int main() {
     int bad = 0;
+    for (auto lag : {std::make_pair(7u, 3u), std::make_pair(2281u, 1252u), std::make_pair(9689u, 5502u),
+                     std::make_pair(132049u, 54454u), std::make_pair(3021377u, 1010202u)})
+        bad += check_pad_ring(lag.first, lag.second);
     const uint32_t lags[][2] = {{7, 3}, {17, 5}, {31, 13}, {100, 33}, {2281, 1252}, {4423, 3004}};
     const uint64_t ns[] = {1, 2, 5, 63, 64, 65, 100, 257, 1000};
     for (auto &lag : lags) {
@@ -341,7 +404,9 @@ int main() {
                     // step, and larger ones
                     const uint32_t Kc = static_cast<uint32_t>(((n + 63) / 64 + Gc - 1) / Gc);
                     const uint32_t Rmin = std::max(ll + nb * sl, nb * sl + 256 * Kc - 1);
-                    for (uint32_t extra : {0u, 1u, 7u, ll + sl}) {
+                    // the smallest rings, larger ones, and the ring of whole links the kernel uses
+                    const uint32_t Rpad = lf_pad_ring(ll, sl).nr * sl;
+                    for (uint32_t extra : {0u, 1u, 7u, ll + sl, Rpad > Rmin ? Rpad - Rmin : 0u}) {
                         const uint32_t R = Rmin + extra;
                         for (uint32_t sl2 : {0u, 2u, 6u, 8u, 10u}) {
                             if ((1u << sl2) > sl && sl2) continue;
@@ -356,7 +421,7 @@ int main() {
     }
     // the configuration-2 shape: Table I's last row, n = 1e6, 1024-offset slices, 3072 consumer waves
     {
-        const Run r = make_run(1000000, 2, 3021377, 1010202, 2 * (3021377 + 1010202), 10, 3072);
+        const Run r = make_run(1000000, 2, 3021377, 1010202, lf_pad_ring(3021377, 1010202).nr * 1010202u, 10, 3072);
         bad += check_waits(r);
     }
     std::printf(bad ? "FAILED %d\n" : "ok\n", bad);

@@ -52,6 +52,25 @@ def _setup(kind, N, seed=1234, n_total=None, ll=0, sl=0, x0=None, v0=None, leap=
     return cfg, st, x, v
 
 
+def _lf_state(st):
+    """The meaningful part of a lagged-Fibonacci state: the header's position and the last ll
+    values in sequence order (the rest of the ring is stale by definition)."""
+    b = st.cpu().numpy()
+    pos = int(b[:8].view(np.uint64)[0])
+    slot, ll, sl, R = (int(v) for v in b[8:24].view(np.uint32))
+    ring = b[64:64 + 4 * R].view(np.uint32)
+    return pos, slot, ring[(slot - ll + np.arange(ll)) % R]
+
+
+def _same_state(kind, a, b):
+    """Generator states equal: every byte for per-thread kinds, the position and the last ll values
+    for the lagged Fibonacci ring."""
+    if kind != "lf":
+        return torch.equal(a, b)
+    sa, sb = _lf_state(a), _lf_state(b)
+    return sa[0] == sb[0] and np.array_equal(sa[2], sb[2])
+
+
 def _oracle_states(kind, seed, ids, ll=0):
     return orc.lf_seed(seed, ll) if kind == "lf" else orc.seed_states(kind, seed, ids)
 
@@ -157,7 +176,7 @@ def test_resume_is_bit_exact(kind):
     R.ld_run(cfg_b, st_b, ens, n_ens, N, 77, xb, vb)
     R.ld_run(cfg_b, st_b, ens, n_ens, N, 123, xb, vb)
     torch.cuda.synchronize()
-    assert torch.equal(xa, xb) and torch.equal(va, vb) and torch.equal(st_a, st_b)
+    assert torch.equal(xa, xb) and torch.equal(va, vb) and _same_state(kind, st_a, st_b)
 
 
 @pytest.mark.parametrize("kind", ["taus", "ran2", "lf", "lcg"])
@@ -174,7 +193,7 @@ def test_step_protocol_matches_oracle_and_fused_run(kind):
     ens, n_ens = R.make_ensembles([(0, N, p, 0)])
     R.ld_run(cfg_r, st_r, ens, n_ens, N, T, xr_, vr_)
     torch.cuda.synchronize()
-    assert torch.equal(st_s, st_r)  # identical generator state
+    assert _same_state(kind, st_s, st_r)  # identical generator state
     xo, vo, _ = orc.ld_run(kind, _oracle_states(kind, 1234, np.arange(N), ll), N, T, pp.asdict(), ll=ll, sl=sl)
     assert _close(xs.cpu().numpy().reshape(3, N), xo, math.sqrt(pp.kT / pp.k))[0]
     assert _close(vs.cpu().numpy().reshape(3, N), vo, math.sqrt(pp.kT / pp.m))[0]
@@ -372,7 +391,8 @@ def test_lf_dataflow_equals_waves_and_oracle(n, lags, T):
             R.ld_set_tuning("lf")
     _say("lf dataflow", n, lags, T)
     assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])
-    assert torch.equal(res[0][2], res[1][2])
+    sa, sb = _lf_state(res[0][2]), _lf_state(res[1][2])
+    assert sa[0] == sb[0] == 4 * n * T and sa[1] == sb[1] and np.array_equal(sa[2], sb[2])
     xo, vo, oo = orc.ld_run("lf", orc.lf_seed(1234, ll), n, T, pp.asdict(), stride=stride, t0=t0, ll=ll, sl=sl)
     assert _close(res[0][0].cpu().numpy().reshape(3, n), xo, math.sqrt(pp.kT / pp.k))[0]
     assert _close(res[0][1].cpu().numpy().reshape(3, n), vo, math.sqrt(pp.kT / pp.m))[0]
@@ -399,29 +419,38 @@ def test_lf_dataflow_resume_and_mixed_calls():
 
 
 def test_lf_ring_size_does_not_change_the_run():
-    """The persistent run at the smallest allowed ring (ll + sl), the default ring and a larger one,
-    and the wave path on a ring too small for the persistent run, give the same trajectory bit for
-    bit."""
+    """The state's ring size (the smallest allowed, ll + sl, the default, a larger one, and one only
+    W = 4000 longer than ll) changes neither the persistent run nor the wave path: same trajectory
+    and the same last ll values bit for bit, and a second call continues the sequence alike."""
     n, T, ll, sl = 3001, 150, 9689, 5502
     p = _params(W.LDParams(k=1.3, gamma=0.7, dt=0.01))
     ens, n_ens = R.make_ensembles([(0, n, p, 0)])
     ref = None
-    for ring, path in ((ll + sl, "dataflow"), (0, "dataflow"), (4 * (ll + sl), "dataflow"), (ll + 4000, "waves")):
+    cases = [(ring, waves) for ring in (ll + sl, 0, 4 * (ll + sl), ll + 4000) for waves in (0, 1)]
+    for ring, waves in cases:
         cfg = R.make_cfg("lf", seed=77, ll=ll, sl=sl, ring=ring, wave=4000 if ring == ll + 4000 else 0)
         st = R.new_state(cfg)
         R.rng_init(cfg, st)
         x = torch.zeros(3 * n, dtype=torch.float32, device="cuda")
         v = torch.zeros_like(x)
         ob = torch.zeros((T // 10 + 1) * R.NOBS, dtype=torch.float64, device="cuda")
-        ws = R.ld_run(cfg, st, ens, n_ens, n, T, x, v, R.Obs(10, T // 3), ob)
-        torch.cuda.synchronize()
-        _say("lf ring", ring, R.ws_lf_path(ws))
-        assert R.ws_status(ws) == 0 and R.ws_lf_path(ws) == path
+        R.ld_set_tuning("lf", lf_waves=waves)
+        try:
+            ws = R.ld_run(cfg, st, ens, n_ens, n, T, x, v, R.Obs(10, T // 3), ob)
+            torch.cuda.synchronize()
+            _say("lf ring", ring, R.ws_lf_path(ws))
+            assert R.ws_status(ws) == 0 and R.ws_lf_path(ws) == ("waves" if waves else "dataflow")
+            R.ld_run(cfg, st, ens, n_ens, n, 7, x, v)
+            torch.cuda.synchronize()
+        finally:
+            R.ld_set_tuning("lf")
+        win = _lf_state(st)
         if ref is None:
-            ref = (x.clone(), v.clone(), ob.clone())
+            ref = (x.clone(), v.clone(), ob.clone(), win)
         else:
-            assert torch.equal(x, ref[0]) and torch.equal(v, ref[1])
+            assert torch.equal(x, ref[0]) and torch.equal(v, ref[1]), (ring, waves)
             assert torch.allclose(ob, ref[2], rtol=1e-12, atol=1e-12)
+            assert win[0] == ref[3][0] and np.array_equal(win[2], ref[3][2]), (ring, waves)
 
 
 # ---------------------------------------------------------------------------------------------
