@@ -46,8 +46,9 @@ HBM_PEAK_GBS = 8000.0
 # traffic is reported as null.
 COUNTER_TRAFFIC = {
     "lf_pc_kernel": {
-        "isa_sha256": "1ecb45ba17546127a7ae071a4068e5ced6e466a1fbfbe71093015b1d99ca1132",
-        "fetch_bytes": 158271630 * 1024 * 2, "write_bytes": 177948728 * 1024,
+        "isa_sha256": "e8f134db1a381f04f8b8bbda74a7e4c4c41bef30881e26c84b32fee1a1e338ee",
+        # FETCH_SIZE 160504332.375 KiB x (2^20 / 524310.5), WRITE_SIZE 158418069.71875 KiB x (2^20 / 1048576.03125)
+        "fetch_bytes": 328698766483, "write_bytes": 162220098557,
     },
 }
 
