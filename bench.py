@@ -39,6 +39,10 @@ ALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 LF_ALGO_BYTES_PER_OSC_STEP = 4 * 12
 LF_WAVE_XV_BYTES_PER_OSC_STEP = 48
 HBM_PEAK_GBS = 8000.0
+# Measured peak for the lagged-Fibonacci run's traffic: device-scope loads and stores, two loads per
+# store, over a 32 MB region, stores 256-byte aligned and loads 13 words off (as the run's long-lag
+# reads), from the store-alignment probe (csrc/probes/store_alignment.hip, mode 3).
+LF_MEASURED_PEAK_GBS = 7330.0
 # HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch) at the config-2
 # workload, scaled by what the same counters read for a plain 1 GiB device copy (FETCH_SIZE 0.5 GiB:
 # factor 2; WRITE_SIZE 1 GiB: factor 1).  Valid only for the machine code they were taken on: the
@@ -148,6 +152,8 @@ def roofline_entry(kind, ms_run, N, T, lf_path=None):
         achieved = per_launch_bytes / per_launch_s / 1e9
         return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(kernel), "kernel": kernel,
+                "peak_measured": LF_MEASURED_PEAK_GBS, "frac_measured": achieved / LF_MEASURED_PEAK_GBS,
+                "peak_measured_how": "store-alignment probe, device-scope 2 loads + 1 store per word, 32 MB",
                 "lf_path": lf_path, "launches": launches, "avg_launch_us": per_launch_s * 1e6,
                 "algorithmic_bytes_per_osc_step": per_os, "algorithmic_bytes_per_launch": per_launch_bytes}
     per_launch_s = ms_run / 1e3
@@ -158,6 +164,41 @@ def roofline_entry(kind, ms_run, N, T, lf_path=None):
             "frac": achieved / ALU_PEAK_TOPS, "traffic": counter_traffic(kernel), "kernel": kernel,
             "launches": 1, "avg_launch_us": per_launch_s * 1e6,
             "valu_lane_instr_per_osc_step": VALU_PER_OSC_STEP[kind], "algorithmic_ops_per_launch": ops}
+
+
+def host_cpu():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = None
+    return {"model": model, "nproc": os.cpu_count(), "available_to_process": avail}
+
+
+def measured_hbm_copy(torch):
+    """An elementwise copy of 2 GiB (read + write), best of three: a measured HBM peak.  (An
+    elementwise kernel, so that profiling runs keep the runtime's copy kernel for calibration.)"""
+    src = torch.empty(2**29, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    best = None
+    for _ in range(3):
+        a, b = _ev(torch)
+        a.record()
+        torch.mul(src, 1.0, out=dst)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    return 2 * 2**31 / (best / 1e3) / 1e9
 
 
 def cpu_baseline(W):
@@ -181,6 +222,7 @@ def cpu_baseline(W):
         total_t += dt
         total_os += N * T
     return {"value": total_os / total_t, "unit": "oscillator-steps/s", "cores": 1, "kind": "oracle",
+            "host": host_cpu(),
             "sample": "config-2 workload at N=2e4 oscillators x 1000 steps per generator (3 x 2e7 "
                       "oscillator-steps, %.1f s), FP64, one thread" % total_t,
             "per_generator": per}
@@ -301,10 +343,26 @@ def extra_config5(R, W, torch):
             t2 = time.perf_counter()
         osc = c5["N"] * c5["steps"]
         scratch = 9 * c5["K"] * c5["N"] * 4
+        fd_ms = None
+        if not replay:
+            # the common-random-number central differences the gradient replaces: 6 forward runs
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            for name in ("k", "gamma", "kT"):
+                for sgn in (1, -1):
+                    q = {"k": p5.k, "gamma": p5.gamma, "kT": p5.kT}
+                    q[name] *= 1 + sgn * 1e-2
+                    r = A.AdjointRun("taus", [(c5["N"], p5.m, p5.dt, c5["seed"])], c5["steps"], c5["t_begin"],
+                                     c5["t_end"], c5["K"])
+                    A.LDAdjoint.apply(*(torch.tensor([q[n]], dtype=torch.float64) for n in ("k", "gamma", "kT")), r)
+            torch.cuda.synchronize()
+            fd_ms = (time.perf_counter() - t3) * 1e3
         res = {"backward_path": "replay" if run.ws.numel() >= scratch else "register-only",
                "loss": L.item(), "grad_k_gamma_kT": [k.grad.item(), g.grad.item(), kT.grad.item()],
                "forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3,
                "fwd_plus_bwd_over_fwd": (t2 - t0) / (t1 - t0), "forward_osc_steps_per_s": osc / (t1 - t0)}
+        if fd_ms is not None:
+            res["crn_fd_6_forwards_ms"] = fd_ms
         if replay:
             out["replay"] = res
         else:
@@ -441,6 +499,9 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: %d MiB copied" % args.copy_calibration)
         del src, dst
+    hbm_copy = None if args.copy_calibration else measured_hbm_copy(torch)
+    if hbm_copy:
+        log("measured HBM copy: %.0f GB/s (read + write)" % hbm_copy)
     kinds = tuple(k for k in (args.only.split(",") if args.only else GENERATORS) if k)
     c2 = Config2(R, W, torch, kinds)
     log("config 2: N=%d, %d steps, generators %s" % (c2.N, c2.T, ",".join(kinds)))
@@ -480,6 +541,8 @@ def main():
                                "(dt=0.005, m=k=kT=gamma=1) per generator, observables every 100 steps",
                    "generators": list(kinds), "N": c2.N, "ld_steps_per_run": c2.T, "lf_lags": [c2.ll, c2.sl]},
         "roofline": rooflines[dominant],
+        "measured_peaks": {"hbm_copy_GBps": hbm_copy,
+                           "lf_device_scope_mix_GBps": LF_MEASURED_PEAK_GBS},
         "per_generator": per_gen,
         "rooflines_all": rooflines,
     }

@@ -13,7 +13,7 @@
 __device__ __forceinline__ uint32_t ald(const uint32_t *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 __device__ __forceinline__ void ast(uint32_t *p, uint32_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
-// mode 0: loads + stores; 1: loads only; 2: stores only
+// mode 0: loads + stores; 1: loads only; 2: stores only; 3: two loads per store (two source slices)
 __global__ __launch_bounds__(1024) void slices(uint32_t *buf, uint32_t nchunks, uint32_t iters, uint32_t mis_ld,
                                                uint32_t mis_st, int mode, uint32_t *sink) {
     const uint32_t lane = threadIdx.x & 63u;
@@ -25,7 +25,11 @@ __global__ __launch_bounds__(1024) void slices(uint32_t *buf, uint32_t nchunks, 
         const uint32_t *src = buf + c * 1024u + mis_ld;
         uint32_t *dst = buf + c2 * 1024u + mis_st;
         uint32_t v[16];
-        if (mode != 2) {
+        if (mode == 3) {
+            const uint32_t *src2 = buf + ((c + nchunks / 4) % nchunks) * 1024u + mis_ld;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) v[r] = ald(src + lane + 64 * r) + ald(src2 + lane + 64 * r);
+        } else if (mode != 2) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) v[r] = ald(src + lane + 64 * r);
         } else {
@@ -56,7 +60,7 @@ int main() {
     const uint32_t iters = 400;
     const int blocks = 256;
     const uint32_t mis[][2] = {{0, 0}, {13, 0}, {0, 13}, {13, 13}, {1, 26}, {16, 16}, {32, 32}};
-    for (int mode = 0; mode < 3; ++mode)
+    for (int mode = 0; mode < 4; ++mode)
         for (auto &m : mis) {
             slices<<<blocks, 1024>>>(buf, nchunks, 20, m[0], m[1], mode, sink);  // warm
             CHK(hipEventRecord(e0));
@@ -65,9 +69,10 @@ int main() {
             CHK(hipEventSynchronize(e1));
             float ms;
             CHK(hipEventElapsedTime(&ms, e0, e1));
-            const double bytes = (double)blocks * 16 * iters * 1024 * 4 * (mode == 0 ? 2 : 1);
+            const double bytes = (double)blocks * 16 * iters * 1024 * 4 * (mode == 0 ? 2 : (mode == 3 ? 3 : 1));
             printf("mode %d (%s) mis ld %2u st %2u: %.3f ms, %.2f TB/s\n", mode,
-                   mode == 0 ? "ld+st" : (mode == 1 ? "ld" : "st"), m[0], m[1], ms, bytes / ms / 1e9);
+                   mode == 0 ? "ld+st" : (mode == 1 ? "ld" : (mode == 2 ? "st" : "2ld+st")), m[0], m[1], ms,
+                   bytes / ms / 1e9);
         }
     return 0;
 }
