@@ -516,3 +516,46 @@ def test_fig4_lcg_correlated_seeding_fails_on_the_gpu():
     _say("lcg negative control (max z of <x>, neighbour corr):", res)
     assert res[0][0] < 4.5 and abs(res[0][1]) < 0.1
     assert res[4][0] > 10 and res[4][1] > 0.9
+
+
+def test_fig4_paper_units_fp32_state():
+    """Sec. IV / Fig. 4 in the paper's own units (nm, ns, pN): k = 0.01 pN/nm, kT = 4.14 pN nm
+    (300 K), D = kT / xi = 0.25 nm^2/ns, h = 1 ps, x0 = 10 nm, so that h / tau = 6.0e-7 per step.
+    After 10^7 steps (6 tau) of FP32 state the ensemble mean, <x^2> and the equilibrium correlation
+    stay within 4.5 standard errors of the exact discrete forms at every observation: the FP32
+    update shows no drift at this soft spring.  The noise-free decay in FP32 is compared with FP64
+    (its rounding is deterministic, so it is only bounded loosely and reported)."""
+    N, T, stride, t0 = 10_000, 10_000_000, 100_000, 8_000_000
+    kT, D, k, h = 4.14, 0.25, 0.01, 1e-3
+    pp = W.LDParams(m=1.0, k=k, gamma=kT / D, kT=kT, dt=h).as_f32()
+    pd = dict(m=float(pp.m), k=float(pp.k), gamma=float(pp.gamma), kT=float(pp.kT), dt=float(pp.dt))
+    x0 = np.full((3, N), 10.0, np.float32)
+    ens, n_ens = R.make_ensembles([(0, N, _params(pp, scheme=1), 0)])
+    P = T // stride + 1
+    cfg, st, x, v = _setup("taus", N, x0=x0, v0=np.zeros((3, N), np.float32))
+    ob = torch.zeros(P * R.NOBS, dtype=torch.float64, device="cuda")
+    R.ld_run(cfg, st, ens, n_ens, N, T, x, v, R.Obs(stride, t0), ob)
+    obs = ob.cpu().numpy().reshape(P, R.NOBS)
+    n = 3 * N
+    steps = np.arange(0, T + 1, stride)
+    xi = pd["m"] * pd["gamma"]
+    a = 1.0 - pd["k"] * pd["dt"] / xi
+    b2 = 2.0 * pd["kT"] * pd["dt"] / xi
+    mean = 10.0 * a ** steps
+    var = b2 * (1.0 - a ** (2 * steps)) / (1.0 - a * a)
+    z_mean = np.abs(obs[1:, 3] - mean[1:]) / np.sqrt(var[1:] / n)
+    m2 = var + mean**2
+    z_x2 = np.abs(obs[1:, 0] - m2[1:]) / (np.sqrt(2 * var[1:] ** 2 + 4 * var[1:] * mean[1:] ** 2) / np.sqrt(n))
+    after = steps >= t0
+    c = a ** (steps[after] - t0) * m2[after][0]
+    z_c = np.abs(obs[after, 4] - c) / np.sqrt((m2[after] * m2[after][0] + c**2) / n)
+    _say("fig4 paper units: max z mean %.2f, <x^2> %.2f, corr %.2f; <x^2> at the end %.1f nm^2 (kT/k = %.1f)"
+         % (z_mean.max(), z_x2.max(), z_c.max(), obs[-1, 0], pd["kT"] / pd["k"]))
+    assert z_mean.max() < 4.5 and z_x2.max() < 4.5 and z_c.max() < 4.5
+    # the deterministic part alone: FP32 against the FP64 decay x0 a^T
+    cfg0, st0, x0d, v0d = _setup("none", N, x0=x0, v0=np.zeros((3, N), np.float32))
+    R.ld_run(cfg0, st0, ens, n_ens, N, T, x0d, v0d)
+    xt = float(x0d[0])
+    rel = abs(xt - 10.0 * a**T) / (10.0 * a**T)
+    _say("noise-free FP32 decay after %d steps: %.6g vs FP64 %.6g (relative %.2e)" % (T, xt, 10.0 * a**T, rel))
+    assert float(x0d.std()) == 0.0 and rel < 0.05
