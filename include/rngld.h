@@ -104,7 +104,11 @@ typedef struct rngld_cfg {
  *  NO_NOISE    : none.  0 bytes.
  *  LAGFIB      : 64-byte header { uint64 pos; uint32 slot; uint32 ll, sl, R, W; ... } followed by
  *                uint32 ring[R]; y_n lives in ring[(slot + n - pos) mod R] for the last ll
- *                positions n < pos.  pos counts values generated since rng_init.  64 + 4 R bytes.
+ *                positions n < pos.  pos counts values generated since rng_init.  Then, from the
+ *                next 128-byte boundary, working words of the persistent rng_uniform run: a status
+ *                word (nonzero after a run that gave up waiting; its output is then invalid) and
+ *                8192 progress words 128 bytes apart, undefined between calls.
+ *                64 + 4 R + 128 + 8192 * 128 bytes.
  */
 RNGLD_API int rngld_state_bytes(const rngld_cfg *cfg, size_t *bytes);
 
@@ -116,7 +120,9 @@ RNGLD_API int rng_init(const rngld_cfg *cfg, void *d_state, size_t state_bytes, 
  *  per-thread kinds: per_stream values of every stream, d_out[t*S + j] = value t of stream j;
  *                    out_len >= per_stream*S.  Taus: the xor word; Ran2: iy in [1, 2147483562].
  *  LAGFIB          : per_stream consecutive values of the one sequence, d_out[n] = y_{pos+n};
- *                    d_out doubles as the lag table for the values it holds.
+ *                    d_out doubles as the lag table for the values it holds.  With sl >= 4096
+ *                    and at least 4 sl values (and no stream capture), one persistent launch
+ *                    generates them; otherwise one launch per wave of W values.
  */
 RNGLD_API int rng_uniform(const rngld_cfg *cfg, void *d_state, size_t state_bytes, uint64_t per_stream,
                 uint32_t *d_out, uint64_t out_len, void *stream);

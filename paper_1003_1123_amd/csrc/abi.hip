@@ -94,7 +94,8 @@ int check_cfg(const rngld_cfg *cfg, Gen *g) {
             g->sl = sl;
             g->W = W;
             g->R = static_cast<uint32_t>(R);
-            g->state_bytes = sizeof(LfHeader) + static_cast<size_t>(R) * 4;
+            // header, ring, then the bare-stream run's progress words
+            g->state_bytes = sizeof(LfHeader) + static_cast<size_t>(R) * 4 + kLfStreamFlagBytes;
             return RNGLD_OK;
         }
         default:
@@ -468,6 +469,61 @@ int enqueue_run(const Gen &g, void *d_state, const RunLayout &L, const ld_tuning
 }  // namespace
 
 // =====================================================================================================
+// the status word and progress words that a LAGFIB state keeps after its ring (128-byte aligned)
+uint32_t *lf_stream_flags(const Gen &g, void *d_state) {
+    const uintptr_t p = reinterpret_cast<uintptr_t>(d_state) + sizeof(LfHeader) + static_cast<uintptr_t>(g.R) * 4;
+    return reinterpret_cast<uint32_t *>((p + 127) & ~static_cast<uintptr_t>(127));
+}
+
+// The persistent bare-stream run for count values, if it fits: 1 when launched, 0 when the wave
+// path must run, an RNGLD error otherwise.  Needs links long enough to keep the chip busy.
+int try_lf_stream(const Gen &g, void *d_state, uint32_t *d_out, uint64_t count, hipStream_t st) {
+    if (g.sl < 4096 || count < 4ull * g.sl) return 0;
+    if ((count + g.sl - 1) / g.sl >= (1ull << 31)) return 0;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    if (cs != hipStreamCaptureStatusNone) return 0;
+    const int cus = device_cus();
+    if (cus <= 0) return fail(RNGLD_EHIP, "cannot query the compute-unit count");
+    const uint64_t waves = static_cast<uint64_t>(cus) * (kLfFlowBlock / 64);
+    uint32_t m = 0, slice_log2 = 0;
+    if (waves * 256 >= g.sl) {
+        m = 4;
+        slice_log2 = 8;
+    } else if (waves * 1024 >= g.sl) {
+        m = 16;
+        slice_log2 = 10;
+    } else {
+        return 0;
+    }
+    LfStreamArgs a{};
+    a.L = lf_ring(g, d_state);
+    a.geom.sl = g.sl;
+    a.geom.slice_log2 = slice_log2;
+    a.geom.Ptot = count;
+    a.out = d_out;
+    uint32_t *flags = lf_stream_flags(g, d_state);
+    a.status = flags;
+    a.prod = flags + kLfFlagStride;
+    a.lla = g.ll / g.sl;
+    a.llb = g.ll % g.sl;
+    a.n_slices = static_cast<uint32_t>((static_cast<uint64_t>(g.sl) + (1u << slice_log2) - 1) >> slice_log2);
+    a.n_links = static_cast<uint32_t>((count + g.sl - 1) / g.sl);
+    a.spin_limit = 1u << 20;
+    if (a.n_slices + 1 > kLfFlowMaxWaves) return 0;
+    RNGLD_TRY_HIP(launch_fill_u32(flags, static_cast<uint64_t>(a.n_slices + 1) * kLfFlagStride, 0u, st));
+    const hipError_t e = launch_lf_stream(a, static_cast<uint32_t>(cus), m, st);
+    if (e == hipErrorCooperativeLaunchTooLarge) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    if (e != hipSuccess) return fail(RNGLD_EHIP, "persistent LF stream launch: %s", hipGetErrorString(e));
+    return 1;
+}
+
 extern "C" {
 
 const char *rngld_last_error(void) { return g_last_error.c_str(); }
@@ -528,9 +584,12 @@ int rng_uniform(const rngld_cfg *cfg, void *d_state, size_t state_bytes, uint64_
         if (count == 0) return RNGLD_OK;
         if (!d_out) return fail(RNGLD_EINVAL, "output pointer is NULL");
         const LfRing L = lf_ring(g, d_state);
-        for (uint64_t first = 0; first < count; first += g.W)
-            RNGLD_TRY_HIP(launch_lf_uniform_phase(L, d_out, first,
-                                                  static_cast<uint32_t>(std::min<uint64_t>(g.W, count - first)), st));
+        const int r = try_lf_stream(g, d_state, d_out, count, st);
+        if (r < 0) return r;
+        if (r == 0)
+            for (uint64_t first = 0; first < count; first += g.W)
+                RNGLD_TRY_HIP(launch_lf_uniform_phase(L, d_out, first,
+                                                      static_cast<uint32_t>(std::min<uint64_t>(g.W, count - first)), st));
         const uint64_t m = std::min<uint64_t>(count, g.ll);
         RNGLD_TRY_HIP(launch_lf_ring_store(L, d_out, count, static_cast<uint32_t>((count - m) % g.R), st));
         RNGLD_TRY_HIP(launch_lf_advance(const_cast<LfHeader *>(L.hdr), count, static_cast<uint32_t>(count % g.R), st));

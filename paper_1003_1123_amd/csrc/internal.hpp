@@ -102,6 +102,21 @@ struct LfFlowArgs {
     uint32_t np;           // producer waves per block: the block's first np waves
 };
 
+// persistent bare stream (rng_uniform): out[0, count) = the next count values of the sequence
+struct LfStreamArgs {
+    LfRing L;              // the state's ring: the ll values before the call (read only)
+    LfFlowGeom geom;       // sl, slice_log2 and Ptot = count are used
+    uint32_t *out;         // doubles as the lag table
+    uint32_t *prod;        // [slice * kLfFlagStride] links done, zero at launch
+    uint32_t *status;      // nonzero once a wait gave up
+    uint32_t lla, llb;     // ll = lla sl + llb
+    uint32_t n_slices, n_links;
+    uint32_t spin_limit;
+};
+// progress words the LAGFIB state reserves after its ring for the bare-stream run (bytes)
+constexpr size_t kLfStreamFlagBytes = 128 + static_cast<size_t>(8192) * 32 * sizeof(uint32_t);
+hipError_t launch_lf_stream(const LfStreamArgs &a, uint32_t grid, uint32_t m, hipStream_t st);
+
 // ---- adjoint (k_adj.hip) ---------------------------------------------------------------------------
 struct AdjCoef {
     LdCoef f;         // forward coefficients

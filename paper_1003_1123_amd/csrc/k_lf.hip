@@ -708,6 +708,159 @@ hipError_t launch_fill_u32(uint32_t *dst, uint64_t count, uint32_t value, hipStr
     return hipGetLastError();
 }
 
+namespace {
+
+// ---- persistent bare stream --------------------------------------------------------------------------
+// One cooperative launch writes out[0, count) = y_{pos} .. y_{pos+count-1}; the output doubles as
+// the lag table.  Producer p (one wave) owns offsets [p T, (p+1) T), T = 64 M, of every sl-long link
+// (link j = positions [j sl, (j+1) sl) of the call); its short-lag source is its own number of the
+// previous link, kept in registers, and its long-lag source y_{n-ll} is read from out, or for n < ll
+// from the state's ring (the ll values before the call).  Nothing is overwritten, so the only waits
+// are for the producers of the long-lag sources, which lie in earlier links or, when ll < 2 sl, in
+// the same link of other producers; a producer publishes link j before it blocks on link j+1, so
+// every wait is for work that is published before its producer blocks, and with all waves resident
+// the run always progresses.
+
+__device__ __forceinline__ bool stream_wait(FlowWaits &w, uint32_t lane, const LfStreamArgs &a) {
+    bool ok = true;
+    if (lane < w.n) {
+        uint32_t spins = 0;
+        while (agent_load(w.flag) < w.need) {
+            if (++spins > a.spin_limit || ((spins & 15u) == 0 && agent_load(a.status) != 0u)) {
+                agent_store(a.status, 1u);
+                ok = false;
+                break;
+            }
+            poll_pause(spins);
+        }
+    }
+    w.n = 0;
+    return __all(ok);
+}
+
+template <int M>
+__global__ __launch_bounds__(kLfFlowBlock) void lf_stream_kernel(LfStreamArgs a) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t p = __builtin_amdgcn_readfirstlane(blockIdx.x * (kLfFlowBlock / 64) + (threadIdx.x >> 6));
+    if (p >= a.n_slices) return;
+    constexpr uint32_t T = 64u * M;
+    const LfFlowGeom &g = a.geom;
+    const uint32_t sl = g.sl, o_lo = p * T;
+    const uint32_t width = T < sl - o_lo ? T : sl - o_lo;
+    const uint64_t count = g.Ptot;
+    uint32_t *out = a.out;
+    const uint32_t *ring = a.L.ring;
+    const uint32_t R = a.L.R, ll = a.L.ll;
+    const uint32_t slot0 = a.L.hdr->slot;  // ring slot of y_{pos}
+    // the word holding y_{pos + P}: out for P >= 0, the ring for -ll <= P < 0
+    auto word = [&](int64_t P) -> const uint32_t * {
+        if (P >= 0) return out + P;
+        int64_t s = static_cast<int64_t>(slot0) + P;
+        if (s < 0) s += R;
+        return ring + s;
+    };
+    auto link_len = [&](uint32_t j) -> uint32_t {
+        if (j >= a.n_links) return 0u;
+        const uint64_t n0 = static_cast<uint64_t>(j) * sl + o_lo;
+        return n0 >= count ? 0u : (count - n0 < width ? static_cast<uint32_t>(count - n0) : width);
+    };
+    uint32_t chain[M], src[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+        const uint32_t q = lane + 64u * r;
+        chain[r] = q < width ? agent_load(word(static_cast<int64_t>(o_lo + q) - sl)) : 0u;
+    }
+    FlowWaits w;
+    w.n = 0;
+    // the producers of link j's long-lag sources (positions >= 0 only)
+    auto collect = [&](uint32_t j, uint32_t len) {
+        int64_t link;
+        uint32_t off;
+        lf_back(j, o_lo, LfLag{a.lla, a.llb}, sl, link, off);
+        lf_walk_producers(g, link, off, len, [&](uint32_t slice, uint32_t l) {
+            wait_add(w, lane, a.prod + slice * kLfFlagStride, l + 1, 0);
+            return true;
+        });
+    };
+    // M long-lag loads, always all issued (an unused one reads the link's first source), one
+    // load instruction each, so that their count is exact
+    auto load = [&](uint32_t j, uint32_t len) {
+        const int64_t n0 = static_cast<int64_t>(j) * sl + o_lo - ll;
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            const uint32_t q = lane + 64u * r;
+            src[r] = agent_load(word(n0 + (q < len ? q : 0u)));
+        }
+    };
+    uint32_t len = link_len(0);
+    if (len == 0) return;
+    collect(0, len);
+    if (!stream_wait(w, lane, a)) return;
+    // one read of the first progress word each lane waits for (the status word in lanes without a
+    // wait), for link j1; issued before a link's loads, so it has returned once they have
+    uint32_t seen = 0;
+    auto poll = [&](uint32_t j1) {
+        w.n = 0;
+        collect(j1, link_len(j1));
+        seen = agent_load(lane < w.n ? w.flag : a.status);
+    };
+    poll(1);
+    load(0, len);
+    for (uint32_t j = 0; j < a.n_links; ++j) {
+        const uint32_t next_len = link_len(j + 1);
+#pragma unroll
+        for (int r = 0; r < M; ++r) chain[r] += src[r];
+        // link j+1's waits, read before link j's loads
+        const bool ready = next_len > 0 && w.n <= 64u && __all(lane >= w.n || seen >= w.need);
+        const int64_t n0 = static_cast<int64_t>(j) * sl + o_lo;
+        if (len == T) {
+#pragma unroll
+            for (int r = 0; r < M; ++r) agent_store(out + n0 + lane + 64u * r, chain[r]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < M; ++r) {
+                const uint32_t q = lane + 64u * r;
+                if (q < len) agent_store(out + n0 + q, chain[r]);
+            }
+        }
+        if (!ready) {
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            if (lane == 0) agent_store(a.prod + p * kLfFlagStride, j + 1);
+            if (!next_len) break;
+            // link j+1's waits, in full (a link's sources span at most two slices of each of two
+            // links, so they fit the 64 lanes)
+            w.n = 0;
+            collect(j + 1, next_len);
+            if (!stream_wait(w, lane, a)) return;
+        }
+        poll(j + 2);
+        load(j + 1, next_len);
+        if (ready) {
+            // only the poll and link j+1's M loads, issued after link j's stores, may still be
+            // outstanding: link j is stored
+            asm volatile("s_waitcnt vmcnt(%0)" ::"n"(M + 1) : "memory");
+            if (lane == 0) agent_store(a.prod + p * kLfFlagStride, j + 1);
+        }
+        len = next_len;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_lf_stream(const LfStreamArgs &a, uint32_t grid, uint32_t m, hipStream_t st) {
+    const void *fn = nullptr;
+    if (m == 4) fn = reinterpret_cast<const void *>(&lf_stream_kernel<4>);
+    else if (m == 16) fn = reinterpret_cast<const void *>(&lf_stream_kernel<16>);
+    else return hipErrorInvalidValue;
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kLfFlowBlock, 0);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorCooperativeLaunchTooLarge;
+    LfStreamArgs copy = a;
+    void *args[] = {&copy};
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kLfFlowBlock), args, 0, st);
+}
+
 hipError_t launch_lf_flow(const LfFlowArgs &a, uint32_t grid, uint32_t kc, uint32_t lds, hipStream_t st) {
     const void *fn = lf_pc_fn_for(kc);
     if (!fn) return hipErrorInvalidValue;

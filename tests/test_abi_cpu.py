@@ -60,15 +60,16 @@ def test_state_bytes():
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lcg", n_streams=1000)), C.byref(out)) == 0 and out.value == 4000
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lcg", n_streams=7, leap=4)), C.byref(out)) == 0 and out.value == 28
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("none", n_streams=10**6)), C.byref(out)) == 0 and out.value == 0
+    flags = 128 + 8192 * 32 * 4  # the bare-stream run's status and progress words after the ring
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=2281, sl=1252)), C.byref(out)) == 0
-    assert out.value == 64 + 4 * 2 * (2281 + 1252)
+    assert out.value == 64 + 4 * 2 * (2281 + 1252) + flags
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=2281, sl=1252, wave=101)), C.byref(out)) == 0
-    assert out.value == 64 + 4 * 2 * (2281 + 1252)  # default ring 2 (ll + sl) whatever the wave width
+    assert out.value == 64 + 4 * 2 * (2281 + 1252) + flags  # default ring 2 (ll + sl) whatever the wave width
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=2281, sl=1252, wave=101, ring=2400)), C.byref(out)) == 0
-    assert out.value == 64 + 4 * 2400
+    assert out.value == 64 + 4 * 2400 + flags
     # lags whose doubled sum reaches 2^30 fall back to a ring of ll + sl
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=600_000_001, sl=1000)), C.byref(out)) == 0
-    assert out.value == 64 + 4 * (600_000_001 + 1000)
+    assert out.value == 64 + 4 * (600_000_001 + 1000) + flags
     # ring shorter than ll + W (W = 100 after rounding down to a multiple of 4)
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=2281, sl=1252, wave=101, ring=2380)),
                                    C.byref(out)) == R.ELAG

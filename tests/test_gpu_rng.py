@@ -223,6 +223,39 @@ def test_lf_config3_one_stream_of_2_30():
     del out
 
 
+@pytest.mark.parametrize("lags,count", [((9689, 5502), 4 * 5502 + 777), ((44497, 23463), 10**6 + 3),
+                                        ((132049, 54454), 3 * 10**6 + 17), ((3021377, 1010202), 4 * 1010202)])
+def test_lf_persistent_stream_matches_recurrence(lags, count):
+    """Bare LF streams long enough for the persistent run (sl >= 4096, at least 4 sl values; the
+    first row has ll < 2 sl, so sources also lie in the same link of other producers): every value
+    equals the sequential recurrence, nothing is written past the count, the run's status word
+    stays zero, and the state continues the sequence through a short (wave-path) call and another
+    persistent one."""
+    ll, sl = lags
+    _say("lf persistent stream", lags, count)
+    cfg = _lf_cfg(ll, sl, seed=5)
+    st = R.new_state(cfg)
+    R.rng_init(cfg, st)
+    out = torch.full((count + 64,), -1, dtype=torch.int32, device="cuda")
+    R.rng_uniform(cfg, st, count, out)
+    torch.cuda.synchronize()
+    win = orc.lf_seed(5, ll)
+    assert np.array_equal(_u32(out[:count]), orc.lf_generate(ll, sl, win, count))
+    assert bool((out[count:] == -1).all())
+    hdr = st[:64].cpu().numpy()
+    Rr = int(hdr[20:24].view(np.uint32)[0])
+    flags = (64 + 4 * Rr + 127) // 128 * 128
+    assert int(st[flags:flags + 4].cpu().numpy().view(np.uint32)[0]) == 0
+    nxt = torch.empty(1001, dtype=torch.int32, device="cuda")
+    R.rng_uniform(cfg, st, 1001, nxt)
+    again = torch.empty(count, dtype=torch.int32, device="cuda")
+    R.rng_uniform(cfg, st, count, again)
+    torch.cuda.synchronize()
+    assert np.array_equal(_u32(nxt), orc.lf_generate(ll, sl, win, 1001))
+    assert np.array_equal(_u32(again), orc.lf_generate(ll, sl, win, count))
+    del out, again
+
+
 # ---------------------------------------------------------------------------------------------
 # the transform over its whole input domain
 
