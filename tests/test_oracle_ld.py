@@ -118,8 +118,8 @@ def _fig4_check(obs, N, T, stride, t0, p, x0):
 
 @pytest.mark.parametrize("kind", ["taus", "ran2", "lf", "lcg"])
 def test_fig4_overdamped_statistics_oracle(kind):
-    """Sec. IV / Fig. 4 test in reduced units on the oracle: x0 = 10, tau = xi/k = 100 steps."""
-    p = dict(m=1.0, k=1.0, gamma=1.0, kT=1.0, dt=0.01)
+    """Sec. IV / Fig. 4 test in reduced units on the oracle: x0 = 10, xi = 2, tau = xi/k = 100 steps."""
+    p = dict(m=1.0, k=2.0, gamma=2.0, kT=1.0, dt=0.01)
     N, T, stride, t0 = 3000, 1200, 20, 800
     ll, sl = (132049, 54454) if kind == "lf" else (0, 0)
     st = orc.lf_seed(1234, ll) if kind == "lf" else orc.seed_states(kind, 1234, np.arange(N))
