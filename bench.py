@@ -30,7 +30,7 @@ GENERATORS = ("taus", "ran2", "lf")
 # Work per oscillator-step (the counting is explained in the design doc).
 # Taus and Ran2 are bound by vector-ALU issue: the lane-instructions that the compiled step loop of
 # ld_run_kernel (underdamped scheme, gfx950) issues per oscillator-step, LDS accesses not counted.
-VALU_PER_OSC_STEP = {"taus": 121, "ran2": 146}
+VALU_PER_OSC_STEP = {"taus": 117, "ran2": 146}
 # VALU lane-operation peak: 256 CUs x 128 lanes per clock x 2.4 GHz (the published 157.3 TFLOP/s FP32
 # vector rate counts an FMA as two flops).
 ALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12

@@ -31,6 +31,12 @@ __device__ __forceinline__ uint32_t stream_seed_word(uint64_t seed, uint64_t j, 
     return static_cast<uint32_t>(splitmix_finalize(seed + (4ull * j + i + 1ull) * kGoldenGamma) >> 32);
 }
 
+// a ^ b ^ c ^ d in two instructions: gfx950's three-input bitwise op (truth table 0x96 is the
+// three-way xor), which the compiler does not form from a chain of xors by itself
+__device__ __forceinline__ uint32_t xor4(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96) ^ d;
+}
+
 struct HybridTaus {
     uint32_t t1, t2, t3, lcg;
     static constexpr int kRows = 4;
@@ -40,13 +46,13 @@ struct HybridTaus {
         t2 = tausworthe<2, 4, 29>(t2);
         t3 = tausworthe<3, 17, 28>(t3);
         lcg = lcg_next(lcg);
-        return t1 ^ t2 ^ t3 ^ lcg;
+        return xor4(t1, t2, t3, lcg);
     }
     // the output of the current state, then one step back: repeated calls return the outputs of
     // the preceding next() calls in reverse order, all of them exactly; only the seeded state
     // itself comes back with different bits below each component's top K
     __device__ __forceinline__ uint32_t prev() {
-        const uint32_t w = t1 ^ t2 ^ t3 ^ lcg;
+        const uint32_t w = xor4(t1, t2, t3, lcg);
         t1 = tausworthe_inv<13, 12, 31>(t1);
         t2 = tausworthe_inv<2, 4, 29>(t2);
         t3 = tausworthe_inv<3, 17, 28>(t3);
