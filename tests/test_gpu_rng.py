@@ -256,6 +256,29 @@ def test_lf_persistent_stream_matches_recurrence(lags, count):
     del out, again
 
 
+def test_lf_stream_captured_in_a_graph():
+    """rng_uniform on the shared sequence captured in a CUDA graph (the persistent launch is not
+    used under capture; the waves are recorded): each replay, with eager work in between, yields
+    the next values of the sequence."""
+    ll, sl = 9689, 5502
+    count = 4 * sl + 100
+    cfg = _lf_cfg(ll, sl, seed=3)
+    st = R.new_state(cfg)
+    R.rng_init(cfg, st)
+    out = torch.empty(count, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        R.rng_uniform(cfg, st, count, out)
+    torch.cuda.synchronize()
+    win = orc.lf_seed(3, ll)
+    for rep in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(_u32(out), orc.lf_generate(ll, sl, win, count)), rep
+        _ = float((out.float() * 2).sum())  # unrelated eager work between replays
+
+
 # ---------------------------------------------------------------------------------------------
 # the transform over its whole input domain
 
