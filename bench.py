@@ -202,14 +202,14 @@ def measured_hbm_copy(torch):
 
 
 def cpu_baseline(W):
-    """The FP64 oracle on a bounded sample of config 2: N = 2e4 oscillators x 1000 steps per
-    generator, single thread, same parameters and lags."""
+    """The FP64 oracle on a bounded sample of config 2: N = 3e4 oscillators x 1000 steps per
+    generator (about 12 s), single thread, same parameters and lags."""
     import numpy as np
     import oracle as orc
 
     c = W.C2
     p = c["params"].as_f32().asdict()
-    N, T = 20_000, 1000
+    N, T = 30_000, 1000
     ll, sl = c["lf_lags"]
     total_t, total_os = 0.0, 0
     per = {}
@@ -223,7 +223,7 @@ def cpu_baseline(W):
         total_os += N * T
     return {"value": total_os / total_t, "unit": "oscillator-steps/s", "cores": 1, "kind": "oracle",
             "host": host_cpu(),
-            "sample": "config-2 workload at N=2e4 oscillators x 1000 steps per generator (3 x 2e7 "
+            "sample": "config-2 workload at N=3e4 oscillators x 1000 steps per generator (3 x 3e7 "
                       "oscillator-steps, %.1f s), FP64, one thread" % total_t,
             "per_generator": per}
 
