@@ -131,6 +131,8 @@ RNGLD_API int rng_uniform(const rngld_cfg *cfg, void *d_state, size_t state_byte
  * Gaussian output: values 2i and 2i+1 of a stream are r cos(2 pi u1), r sin(2 pi u1) with
  * r = sqrt(-2 ln u0), u0 = ((w0 >> 8) + 1) 2^-24, u1 = (w1 >> 8) 2^-24 from that stream's words
  * 2i and 2i+1 (Ran2 word: (iy - 1) << 1).  per_stream must be even.  Layout as rng_uniform.
+ * LAGFIB streams that take rng_uniform's persistent launch are generated as integers into d_out
+ * (as the lag table) and then transformed pair by pair in place.
  */
 RNGLD_API int rng_gaussian(const rngld_cfg *cfg, void *d_state, size_t state_bytes, uint64_t per_stream,
                  float *d_out, uint64_t out_len, void *stream);

@@ -621,9 +621,20 @@ int rng_gaussian(const rngld_cfg *cfg, void *d_state, size_t state_bytes, uint64
         if (count == 0) return RNGLD_OK;
         if (!d_out) return fail(RNGLD_EINVAL, "output pointer is NULL");
         const LfRing L = lf_ring(g, d_state);
-        for (uint64_t first = 0; first < count; first += g.W)
-            RNGLD_TRY_HIP(launch_lf_gauss_phase(L, d_out, first, static_cast<uint32_t>(first % g.R),
-                                                static_cast<uint32_t>(std::min<uint64_t>(g.W, count - first)), st));
+        // the persistent stream writes the integers into the output, which doubles as the lag
+        // table; the ring takes the last ll of them, then each pair is transformed in place
+        uint32_t *words = reinterpret_cast<uint32_t *>(d_out);
+        const int r = try_lf_stream(g, d_state, words, count, st);
+        if (r < 0) return r;
+        if (r == 1) {
+            const uint64_t m = std::min<uint64_t>(count, g.ll);
+            RNGLD_TRY_HIP(launch_lf_ring_store(L, words, count, static_cast<uint32_t>((count - m) % g.R), st));
+            RNGLD_TRY_HIP(launch_box_muller_inplace(words, count / 2, st));
+        } else {
+            for (uint64_t first = 0; first < count; first += g.W)
+                RNGLD_TRY_HIP(launch_lf_gauss_phase(L, d_out, first, static_cast<uint32_t>(first % g.R),
+                                                    static_cast<uint32_t>(std::min<uint64_t>(g.W, count - first)), st));
+        }
         RNGLD_TRY_HIP(launch_lf_advance(const_cast<LfHeader *>(L.hdr), count, static_cast<uint32_t>(count % g.R), st));
         return RNGLD_OK;
     }

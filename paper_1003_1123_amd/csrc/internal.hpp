@@ -158,6 +158,7 @@ hipError_t launch_bulk_uniform(int kind, void *state, uint64_t S, uint64_t per_s
                                hipStream_t st);
 hipError_t launch_bulk_gaussian(int kind, void *state, uint64_t S, uint64_t per_stream, float *out, hipStream_t st);
 hipError_t launch_box_muller(const uint32_t *words, uint64_t n_pairs, float *out, hipStream_t st);
+hipError_t launch_box_muller_inplace(uint32_t *buf, uint64_t n_pairs, hipStream_t st);
 
 // ---- launchers (k_ld.hip) --------------------------------------------------------------------------
 hipError_t launch_ld_run(int kind, const LdArgs &a, const ld_tuning &t, uint32_t grid, hipStream_t st);

@@ -119,6 +119,20 @@ __global__ __launch_bounds__(kBulkBlock) void box_muller_kernel(const uint32_t *
     out[2 * i + 1] = r * s;
 }
 
+// the same transform in place: word pair i becomes Gaussian pair i (each thread reads its two
+// words before it writes)
+__global__ __launch_bounds__(kBulkBlock) void box_muller_inplace_kernel(uint32_t *buf, uint64_t n_pairs) {
+    const uint64_t i = blockIdx.x * static_cast<uint64_t>(kBulkBlock) + threadIdx.x;
+    if (i >= n_pairs) return;
+    const uint32_t w0 = buf[2 * i], w1 = buf[2 * i + 1];
+    const float r = box_muller_radius(w0);
+    float c, s;
+    box_muller_angle(w1, c, s);
+    float *out = reinterpret_cast<float *>(buf);
+    out[2 * i] = r * c;
+    out[2 * i + 1] = r * s;
+}
+
 inline dim3 grid_for(uint64_t n) { return dim3(static_cast<unsigned>((n + kBulkBlock - 1) / kBulkBlock)); }
 
 }  // namespace
@@ -161,6 +175,12 @@ hipError_t launch_bulk_gaussian(int kind, void *state, uint64_t S, uint64_t per_
                                                                            per_stream, out);
     else
         ran2_gaussian_kernel<<<grid_for(S), kBulkBlock, 0, st>>>(static_cast<int32_t *>(state), S, per_stream, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_box_muller_inplace(uint32_t *buf, uint64_t n_pairs, hipStream_t st) {
+    if (n_pairs == 0) return hipSuccess;
+    box_muller_inplace_kernel<<<grid_for(n_pairs), kBulkBlock, 0, st>>>(buf, n_pairs);
     return hipGetLastError();
 }
 

@@ -256,6 +256,28 @@ def test_lf_persistent_stream_matches_recurrence(lags, count):
     del out, again
 
 
+@pytest.mark.parametrize("lags,count", [((9689, 5502), 4 * 5502 + 10), ((132049, 54454), 3 * 10**6 + 18)])
+def test_lf_persistent_gaussians(lags, count):
+    """Long LF Gaussian streams: integers by the persistent launch into the output, then Box-Muller
+    pairs in place; every Gaussian within 1e-5 of the FP64 oracle, and the state continues the
+    sequence."""
+    ll, sl = lags
+    cfg = _lf_cfg(ll, sl, seed=8)
+    st = R.new_state(cfg)
+    R.rng_init(cfg, st)
+    out = torch.empty(count, dtype=torch.float32, device="cuda")
+    R.rng_gaussian(cfg, st, count, out)
+    nxt = torch.empty(999, dtype=torch.int32, device="cuda")
+    R.rng_uniform(cfg, st, 999, nxt)
+    torch.cuda.synchronize()
+    win = orc.lf_seed(8, ll)
+    ref = orc.lf_gaussian(ll, sl, win, count)
+    err = float(np.max(np.abs(out.cpu().numpy().astype(np.float64) - ref)))
+    _say("lf persistent gaussians", lags, "max abs err", err)
+    assert err <= GAUSS_TOL
+    assert np.array_equal(_u32(nxt), orc.lf_generate(ll, sl, win, 999))
+
+
 def test_lf_stream_captured_in_a_graph():
     """rng_uniform on the shared sequence captured in a CUDA graph (the persistent launch is not
     used under capture; the waves are recorded): each replay, with eager work in between, yields
