@@ -3,16 +3,19 @@
 // y_n = y_{n-ll} + y_{n-sl} mod 2^32 (Eq. 3).  The state is a ring of R >= ll + W 32-bit words in
 // device memory; slot (slot0 + n - pos) mod R holds y_n.
 //
-// Two ways to run the dependency structure (a position needs the positions sl and ll back):
+// Three ways to run the dependency structure (a position needs the positions sl and ll back):
 //  * waves: W <= sl consecutive positions per launch; every source is in an earlier wave; kernel
 //    boundaries order the waves and make their writes visible across the XCDs' L2 caches.  This is
-//    the device-wide "synchronisation at the end of each step" of Sec. III.A at wave granularity.
+//    the device-wide synchronisation after every step of Sec. III.A, at wave granularity.
 //    (Table I rows do not satisfy the paper's race-free condition ll - sl > RNS N; the ring removes
 //    that condition.)
 //  * producer/consumer (fused LD runs): one persistent launch in which producer waves extend the
-//    sequence slice by slice and consumer waves drive the oscillators, synchronised by progress
-//    words (lf_flow.hpp; lf_pc_kernel below).
-// Both reproduce the one sequential sequence exactly, for any wave width or schedule.
+//    sequence slice by slice in a ring of the run's own, each link on a 256-byte boundary, and
+//    consumer waves drive the oscillators, synchronised by progress words (lf_flow.hpp;
+//    lf_pc_kernel below).
+//  * producers only (long bare streams): one persistent launch in which producer waves write the
+//    sequence straight into the output, which serves as the lag table (lf_stream_kernel below).
+// All reproduce the one sequential sequence exactly, for any wave width or schedule.
 #include "internal.hpp"
 
 namespace rngld {
