@@ -375,7 +375,8 @@ def extra_fig6_breakdown(R, W, torch, cpu=True):
     """Fig. 6 on this GPU: time per 10^3 LD steps against N for the fused full step of each generator,
     the dynamics alone (the no-noise kind: same kernel, zero random force), the generator alone (bare
     uniform streams, 4 words per oscillator-step written to HBM, in chunks), and the paper's
-    one-launch-per-step protocol (ld_step) for Hybrid Taus with and without noise; plus the speedup
+    one-launch-per-step protocol (ld_step) for Hybrid Taus with and without noise (called from Python,
+    and replayed from a captured graph); plus the speedup
     of the fused step over the FP64 oracle (one thread), whose per-oscillator-step time is measured
     on about 2e5 oscillator-steps at each N.  Underdamped, h = 0.005, m = k = kT = gamma = 1, from
     rest, no observables; LF uses the smallest Table I pair with sl > 4N."""
@@ -442,7 +443,16 @@ def extra_fig6_breakdown(R, W, torch, cpu=True):
             R.ld_step(cfg, st, p, N, x, v)
             ms = timed(lambda: [R.ld_step(cfg, st, p, N, x, v) for _ in range(T)])
             row["step_protocol_ms_" + kind] = ms
-            del st
+            # the same 10^3 launches captured in a graph: the device-side cost without the host's
+            # per-call overhead
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                for _ in range(T):
+                    R.ld_step(cfg, st, p, N, x, v)
+            g.replay()
+            row["step_protocol_graph_ms_" + kind] = timed(g.replay)
+            del g, st
         if cpu:
             import oracle as orc
             pd = pp.asdict()
