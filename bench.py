@@ -46,11 +46,11 @@ LF_MEASURED_PEAK_GBS = 7330.0
 # HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch) at the config-2
 # workload, scaled by what the same counters read for a plain 1 GiB device copy (FETCH_SIZE 0.5 GiB:
 # factor 2; WRITE_SIZE 1 GiB: factor 1).  Valid only for the machine code they were taken on: the
-# SHA-256 of the kernel's gfx950 assembly, which the build records in kernel_isa.json; otherwise the
-# traffic is reported as null.
+# SHA-256 of the gfx950 assembly of the kernel's 8-tile instantiation (the one this workload runs),
+# which the build records in kernel_isa.json; otherwise the traffic is reported as null.
 COUNTER_TRAFFIC = {
     "lf_pc_kernel": {
-        "isa_sha256": "e8f134db1a381f04f8b8bbda74a7e4c4c41bef30881e26c84b32fee1a1e338ee",
+        "isa_sha256": "3bb47f7afdd0f1fe7089fd36a7e0592070bcf38e5217a2b918b2c42ed75412fd",
         # FETCH_SIZE 160504332.375 KiB x (2^20 / 524310.5), WRITE_SIZE 158418069.71875 KiB x (2^20 / 1048576.03125)
         "fetch_bytes": 328698766483, "write_bytes": 162220098557,
     },

@@ -24,8 +24,10 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librngld.so")
 ISA_JSON = os.path.join(HERE, "kernel_isa.json")
-# kernels whose machine code is fingerprinted: name -> source file
-FINGERPRINTED = {"lf_pc_kernel": "k_lf.hip", "ld_run_kernel": "k_ld.hip"}
+# kernels whose machine code is fingerprinted: name -> (source file, substring of the mangled
+# symbols covered).  The lagged-Fibonacci entry covers the 8-tile instantiation, the one that runs
+# 10^6 oscillators on 256 CUs.
+FINGERPRINTED = {"lf_pc_kernel": ("k_lf.hip", "lf_pc_kernelILi8E"), "ld_run_kernel": ("k_ld.hip", "ld_run_kernel")}
 ARCH = os.environ.get("RNGLD_OFFLOAD_ARCH", "gfx950")
 
 # Packed-FP32 instructions are disabled for all device code (the compiler would otherwise form
@@ -80,14 +82,14 @@ def _function_bodies(asm: str, name: str):
 def fingerprint_kernels() -> dict:
     """SHA-256 over the sorted assembly bodies of each fingerprinted kernel family."""
     res = {}
-    for name, src in FINGERPRINTED.items():
+    for name, (src, pattern) in FINGERPRINTED.items():
         asm_path = os.path.join(BUILD, src[:-4] + ".gfx950.s")
         cmd = [hipcc()] + [f for f in FLAGS if f != "-fPIC"] + ["--cuda-device-only", "-S",
                                                               os.path.join(CSRC, src), "-o", asm_path]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError("assembly listing failed: %s\n%s" % (" ".join(cmd), r.stderr))
-        bodies = _function_bodies(open(asm_path).read(), name)
+        bodies = _function_bodies(open(asm_path).read(), pattern)
         if not bodies:
             raise RuntimeError("no %s in %s" % (name, asm_path))
         h = hashlib.sha256()

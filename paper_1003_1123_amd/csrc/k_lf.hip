@@ -458,12 +458,15 @@ __device__ __forceinline__ void tile_observe(const LfFlowArgs &a, const float *t
     }
 }
 
-// Consumer wave cw: tiles c = cw + k Gc of 64 oscillators; x, v in LDS as xv[k][6][64]; tr is a
-// 256-word transpose buffer.  Lane l of a tile drives oscillator 64 c + l.
+// s_waitcnt immediates (gfx9 encoding) that wait for vector memory only: vmcnt(1), vmcnt(0)
+constexpr int kWaitVm1 = 0xF71, kWaitVm0 = 0xF70;
+
 // Consumer wave cw: the Kc consecutive tiles cw Kc .. (64 oscillators each, lane l of tile k
 // drives oscillator 64 (cw Kc + k) + l); x, v in LDS as xv[k][6][64]; tr is a 256-word transpose
 // buffer.  Per step: wait for the producers of the wave's positions, load them all, publish, then
-// drive the oscillators.
+// drive the oscillators.  Up to 4 tiles per wave the steps are software-pipelined: the next step's
+// loads go out before this step's LD update whenever a poll issued one step earlier shows its
+// producers published (this takes twice the word registers, which 8 tiles do not have).
 template <int KC>
 __device__ __forceinline__ void lf_consumer(const LfFlowArgs &a, uint32_t cw, uint32_t lane, float *xv, uint32_t *tr) {
     const LfFlowGeom &g = a.geom;
@@ -484,81 +487,216 @@ __device__ __forceinline__ void lf_consumer(const LfFlowArgs &a, uint32_t cw, ui
             xv[(k * 6 + 3 + d) * 64 + lane] = act ? a.v[d * a.N + o] : 0.0f;
         }
     }
-    // the step's first position 4 o0 + s 4n: its link, offset and the link's first word (a step's
-    // positions span at most two links: 256 Kc <= sl)
-    int64_t link = static_cast<int64_t>((4 * o0) / g.sl);
-    uint32_t off = static_cast<uint32_t>((4 * o0) % g.sl);
-    uint32_t lbase = lf_pad_base(a.pr, link);
-    FlowWaits w;
-    w.n = 0;
-    for (uint32_t s = 0; s < a.n_steps; ++s) {
-        // an opaque copy of the pointer keeps the per-tile addresses from being held in registers
-        // across the loop
-        float *t0buf = a.t0buf;
-        asm volatile("" : "+s"(t0buf));
-        if (a.stride && s % a.stride == 0) {
-#pragma unroll 1
-            for (uint32_t k = 0; k < Kw; ++k) {
-                const uint64_t o = o0 + 64ull * k + lane;
-                tile_observe(a, t0buf, xv + k * 384, lane, o, o < o1, s, cw * Kc + k);
-            }
+    if constexpr (KC <= 4) {
+        // coordinates of a step's first position 4 o0 + s 4n: its link, offset and the link's first
+        // word (a step's positions span at most two links: 256 Kc <= sl)
+        struct Coord {
+            int64_t link;
+            uint32_t off, lbase;
+        };
+        auto advance = [&](Coord &c) {
+            const int64_t link_before = c.link;
+            lf_link_coord_next_step(g, c.link, c.off);
+            c.lbase += (static_cast<uint32_t>(c.link - link_before) % nr) * slp;
+            if (c.lbase >= ring_words) c.lbase -= ring_words;
+        };
+        auto collect = [&](FlowWaits &w, const Coord &c) {
+            w.n = 0;
+            lf_walk_producers(g, c.link, c.off, cnt, [&](uint32_t sl_, uint32_t l) {
+                wait_add(w, lane, a.prod + sl_ * kLfFlagStride, l + 1, 0);
+                return true;
+            });
+        };
+        // a step's words, lane-contiguous: always KC x 4 loads (an unused one reads the step's
+        // first word)
+        auto load = [&](uint32_t (&words)[KC][4], const Coord &c) {
+            const uint32_t nbase = c.lbase + slp < ring_words ? c.lbase + slp : 0u;
+#pragma unroll
+            for (int k = 0; k < KC; ++k)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const uint32_t q = 256u * k + lane + 64u * r;
+                    const uint32_t o = c.off + (q < cnt ? q : 0u);
+                    words[k][r] = ring_get(ring, o < sl ? c.lbase + o : nbase + (o - sl));
+                }
+        };
+        // one read of the progress word each lane waits for (the status word in lanes without one)
+        auto poll = [&](FlowWaits &w, uint32_t &seen, const Coord &c) {
+            collect(w, c);
+            seen = agent_load(lane < w.n ? w.flag : a.status);
+        };
+        Coord nxt{static_cast<int64_t>((4 * o0) / g.sl), static_cast<uint32_t>((4 * o0) % g.sl), 0u};
+        nxt.lbase = lf_pad_base(a.pr, nxt.link);
+        FlowWaits w;
+        uint32_t wa[KC][4], wb[KC][4], seen = 0;
+        if (a.n_steps > 0) {
+            collect(w, nxt);
+            if (!wait_all(w, lane, a)) return;
+            load(wa, nxt);
+            advance(nxt);
+            if (a.n_steps > 1) poll(w, seen, nxt);
         }
-        if (a.stride && s == a.t0) {
+        // Step s with its words X in flight (loaded after the producers published them), followed in
+        // issue order only by the poll of step s+1: wait for X, publish, transpose X through LDS into
+        // registers; if the poll shows step s+1 published, issue its loads into Y and the poll of step
+        // s+2 before the LD update of step s, else wait and load after it.  The loads of step s+1 are
+        // issued before this wave publishes s+2, so its slots still hold them.
+        auto step = [&](uint32_t s, uint32_t (&X)[KC][4], uint32_t (&Y)[KC][4]) -> int {
+            if (s >= a.n_steps) return 0;
+            float *t0buf = a.t0buf;
+            asm volatile("" : "+s"(t0buf));
+            if (a.stride && s % a.stride == 0) {
 #pragma unroll 1
-            for (uint32_t k = 0; k < Kw; ++k) {
-                const uint64_t o = o0 + 64ull * k + lane;
-                if (o < o1)
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        t0buf[d * a.N + o] = xv[(k * 6 + d) * 64 + lane];
-                        t0buf[(3 + d) * a.N + o] = xv[(k * 6 + 3 + d) * 64 + lane];
-                    }
-            }
-        }
-        // the producers of this step's positions (a few slices: one wait per lane)
-        lf_walk_producers(g, link, off, cnt, [&](uint32_t sl_, uint32_t l) {
-            wait_add(w, lane, a.prod + sl_ * kLfFlagStride, l + 1, 0);
-            return true;
-        });
-        if (!wait_all(w, lane, a)) return;
-        uint32_t words[KC][4];
-        const uint32_t nbase = lbase + slp < ring_words ? lbase + slp : 0u;
-#pragma unroll
-        for (int k = 0; k < KC; ++k)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const uint32_t q = 256u * k + lane + 64u * r;
-                const uint32_t o = off + q;
-                words[k][r] = q < cnt ? ring_get(ring, o < sl ? lbase + o : nbase + (o - sl)) : 0u;
-            }
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the loads have returned: the slots are free
-        if (lane == 0) agent_store(a.cons + cw * kLfFlagStride, s + 1);
-#pragma unroll
-        for (int k = 0; k < KC; ++k) {
-            if (k >= static_cast<int>(Kw)) break;
-            // lane-contiguous words -> oscillator lane's four words
-#pragma unroll
-            for (int r = 0; r < 4; ++r) tr[lane + 64 * r] = words[k][r];
-            uint32_t u[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) u[r] = tr[4 * lane + r];
-            if (o0 + 64ull * k + lane < o1) {
-                float gf[3];
-                gaussian_forces(u[0], u[1], u[2], u[3], gf[0], gf[1], gf[2]);
-                float *t = xv + k * 384;
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    float x = t[d * 64 + lane], v = t[(3 + d) * 64 + lane];
-                    ld_update(a.coef, x, v, gf[d]);
-                    t[d * 64 + lane] = x;
-                    t[(3 + d) * 64 + lane] = v;
+                for (uint32_t k = 0; k < Kw; ++k) {
+                    const uint64_t o = o0 + 64ull * k + lane;
+                    tile_observe(a, t0buf, xv + k * 384, lane, o, o < o1, s, cw * Kc + k);
                 }
             }
+            if (a.stride && s == a.t0) {
+#pragma unroll 1
+                for (uint32_t k = 0; k < Kw; ++k) {
+                    const uint64_t o = o0 + 64ull * k + lane;
+                    if (o < o1)
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            t0buf[d * a.N + o] = xv[(k * 6 + d) * 64 + lane];
+                            t0buf[(3 + d) * a.N + o] = xv[(k * 6 + 3 + d) * 64 + lane];
+                        }
+                }
+            }
+            const bool more = s + 1 < a.n_steps;
+            // X has returned: with a step s+1 the last two memory operations were X's loads and the
+            // poll of step s+1 (either order of poll and publish), so at most one is outstanding;
+            // the builtin, unlike inline asm, is known to the compiler's wait insertion
+            if (more) __builtin_amdgcn_s_waitcnt(kWaitVm1);
+            else __builtin_amdgcn_s_waitcnt(kWaitVm0);
+            const bool ready = more && w.n <= 64u && __all(lane >= w.n || seen >= w.need);
+            // lane-contiguous words -> each oscillator lane's four words
+            uint32_t u[KC][4];
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                if (k >= static_cast<int>(Kw)) break;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) tr[lane + 64 * r] = X[k][r];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) u[k][r] = tr[4 * lane + r];
+            }
+            Coord far = nxt;
+            advance(far);
+            if (ready) {
+                load(Y, nxt);
+                if (s + 2 < a.n_steps) poll(w, seen, far);
+            }
+            // X's slots are free (published before any wait for step s+1)
+            if (lane == 0) agent_store(a.cons + cw * kLfFlagStride, s + 1);
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                if (k >= static_cast<int>(Kw)) break;
+                if (o0 + 64ull * k + lane < o1) {
+                    float gf[3];
+                    gaussian_forces(u[k][0], u[k][1], u[k][2], u[k][3], gf[0], gf[1], gf[2]);
+                    float *t = xv + k * 384;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        float x = t[d * 64 + lane], v = t[(3 + d) * 64 + lane];
+                        ld_update(a.coef, x, v, gf[d]);
+                        t[d * 64 + lane] = x;
+                        t[(3 + d) * 64 + lane] = v;
+                    }
+                }
+            }
+            if (more && !ready) {
+                collect(w, nxt);
+                if (!wait_all(w, lane, a)) return -1;
+                load(Y, nxt);
+                if (s + 2 < a.n_steps) poll(w, seen, far);
+            }
+            nxt = far;
+            return 1;
+        };
+        for (uint32_t s = 0;; s += 2) {
+            int r = step(s, wa, wb);
+            if (r > 0) r = step(s + 1, wb, wa);
+            if (r < 0) return;
+            if (r == 0) break;
         }
-        const int64_t link_before = link;
-        lf_link_coord_next_step(g, link, off);
-        lbase += (static_cast<uint32_t>(link - link_before) % nr) * slp;
-        if (lbase >= ring_words) lbase -= ring_words;
+    } else {
+        // the step's first position 4 o0 + s 4n: its link, offset and the link's first word (a step's
+        // positions span at most two links: 256 Kc <= sl)
+        int64_t link = static_cast<int64_t>((4 * o0) / g.sl);
+        uint32_t off = static_cast<uint32_t>((4 * o0) % g.sl);
+        uint32_t lbase = lf_pad_base(a.pr, link);
+        FlowWaits w;
+        w.n = 0;
+        for (uint32_t s = 0; s < a.n_steps; ++s) {
+            // an opaque copy of the pointer keeps the per-tile addresses from being held in registers
+            // across the loop
+            float *t0buf = a.t0buf;
+            asm volatile("" : "+s"(t0buf));
+            if (a.stride && s % a.stride == 0) {
+#pragma unroll 1
+                for (uint32_t k = 0; k < Kw; ++k) {
+                    const uint64_t o = o0 + 64ull * k + lane;
+                    tile_observe(a, t0buf, xv + k * 384, lane, o, o < o1, s, cw * Kc + k);
+                }
+            }
+            if (a.stride && s == a.t0) {
+#pragma unroll 1
+                for (uint32_t k = 0; k < Kw; ++k) {
+                    const uint64_t o = o0 + 64ull * k + lane;
+                    if (o < o1)
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            t0buf[d * a.N + o] = xv[(k * 6 + d) * 64 + lane];
+                            t0buf[(3 + d) * a.N + o] = xv[(k * 6 + 3 + d) * 64 + lane];
+                        }
+                }
+            }
+            // the producers of this step's positions (a few slices: one wait per lane)
+            lf_walk_producers(g, link, off, cnt, [&](uint32_t sl_, uint32_t l) {
+                wait_add(w, lane, a.prod + sl_ * kLfFlagStride, l + 1, 0);
+                return true;
+            });
+            if (!wait_all(w, lane, a)) return;
+            uint32_t words[KC][4];
+            const uint32_t nbase = lbase + slp < ring_words ? lbase + slp : 0u;
+#pragma unroll
+            for (int k = 0; k < KC; ++k)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const uint32_t q = 256u * k + lane + 64u * r;
+                    const uint32_t o = off + q;
+                    words[k][r] = q < cnt ? ring_get(ring, o < sl ? lbase + o : nbase + (o - sl)) : 0u;
+                }
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the loads have returned: the slots are free
+            if (lane == 0) agent_store(a.cons + cw * kLfFlagStride, s + 1);
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                if (k >= static_cast<int>(Kw)) break;
+                // lane-contiguous words -> oscillator lane's four words
+#pragma unroll
+                for (int r = 0; r < 4; ++r) tr[lane + 64 * r] = words[k][r];
+                uint32_t u[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) u[r] = tr[4 * lane + r];
+                if (o0 + 64ull * k + lane < o1) {
+                    float gf[3];
+                    gaussian_forces(u[0], u[1], u[2], u[3], gf[0], gf[1], gf[2]);
+                    float *t = xv + k * 384;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        float x = t[d * 64 + lane], v = t[(3 + d) * 64 + lane];
+                        ld_update(a.coef, x, v, gf[d]);
+                        t[d * 64 + lane] = x;
+                        t[(3 + d) * 64 + lane] = v;
+                    }
+                }
+            }
+            const int64_t link_before = link;
+            lf_link_coord_next_step(g, link, off);
+            lbase += (static_cast<uint32_t>(link - link_before) % nr) * slp;
+            if (lbase >= ring_words) lbase -= ring_words;
+        }
     }
     float *t0buf = a.t0buf, *xo = a.x, *vo = a.v;
     asm volatile("" : "+s"(t0buf), "+s"(xo), "+s"(vo));

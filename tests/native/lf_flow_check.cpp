@@ -217,11 +217,15 @@ static int simulate(const Run &r, uint32_t nb, uint32_t slot0) {
         P[p].src.assign((1u << r.slice_log2) * nb, 0);
         lf_consumer_coord0(g, p << r.slice_log2, R, P[p].sR, P[p].oR);
     }
-    std::vector<uint32_t> C(Gc, 0);  // next step
-    auto wave_range = [&](uint32_t w, uint64_t &P0, uint64_t &cnt) {  // positions of wave w in step C[w]
+    // consumer w: C[w] steps published; H[w] the step whose numbers it has read and not yet
+    // published (-1: none).  A consumer reads step C, then either publishes it, or (when the
+    // producers of step C+1 have published) first reads step C+1 and then publishes step C.
+    std::vector<uint32_t> C(Gc, 0);
+    std::vector<int64_t> H(Gc, -1);
+    auto wave_range = [&](uint32_t w, uint64_t step, uint64_t &P0, uint64_t &cnt) {  // positions of wave w
         const uint64_t c0 = static_cast<uint64_t>(w) * g.Kc;
         const uint64_t o0 = std::min<uint64_t>(64 * c0, r.n), o1 = std::min<uint64_t>(64 * (c0 + g.Kc), r.n);
-        P0 = C[w] * g.four_n + 4 * o0;
+        P0 = step * g.four_n + 4 * o0;
         cnt = 4 * (o1 - o0);
     };
     int bad = 0;
@@ -258,17 +262,23 @@ static int simulate(const Run &r, uint32_t nb, uint32_t slot0) {
             }
             if (ok) ready.push_back({0, p});
         }
+        auto published = [&](uint32_t w, uint64_t step) {
+            uint64_t P0, cnt;
+            wave_range(w, step, P0, cnt);
+            if (!cnt) return true;
+            return lf_walk_producers(g, static_cast<int64_t>(P0 / r.sl), static_cast<uint32_t>(P0 % r.sl),
+                                     static_cast<uint32_t>(cnt),
+                                     [&](uint32_t s, uint32_t l) { return prod[s] >= l + 1; });
+        };
         for (uint32_t w = 0; w < Gc; ++w) {
             if (C[w] >= r.T) continue;
             all_done = false;
-            uint64_t P0, cnt;
-            wave_range(w, P0, cnt);
-            bool ok = true;
-            if (cnt)
-                ok = lf_walk_producers(g, static_cast<int64_t>(P0 / r.sl), static_cast<uint32_t>(P0 % r.sl),
-                                       static_cast<uint32_t>(cnt),
-                                       [&](uint32_t s, uint32_t l) { return prod[s] >= l + 1; });
-            if (ok) ready.push_back({1, w});
+            if (H[w] < 0) {
+                if (published(w, C[w])) ready.push_back({1, w});  // read step C
+            } else {
+                ready.push_back({2, w});  // publish step C
+                if (C[w] + 1 < r.T && published(w, C[w] + 1)) ready.push_back({3, w});  // read C+1, publish C
+            }
         }
         if (all_done) break;
         if (ready.empty()) {
@@ -314,14 +324,26 @@ static int simulate(const Run &r, uint32_t nb, uint32_t slot0) {
             }
         } else {
             const uint32_t w = pick.second;
-            uint64_t P0, cnt;
-            wave_range(w, P0, cnt);
-            for (uint64_t pos = P0; pos < P0 + cnt; ++pos)
-                if (read(static_cast<int64_t>(pos)) != expect(static_cast<int64_t>(pos))) {
-                    if (bad < 5) std::printf("consumer read a wrong value at %llu\n", (unsigned long long)pos);
-                    ++bad;
-                }
-            cons[w] = ++C[w];
+            // a consumer's loads are in flight from their issue until it publishes the step, so
+            // each read is checked at both ends
+            auto read_step = [&](uint64_t step) {
+                uint64_t P0, cnt;
+                wave_range(w, step, P0, cnt);
+                for (uint64_t pos = P0; pos < P0 + cnt; ++pos)
+                    if (read(static_cast<int64_t>(pos)) != expect(static_cast<int64_t>(pos))) {
+                        if (bad < 5) std::printf("consumer read a wrong value at %llu\n", (unsigned long long)pos);
+                        ++bad;
+                    }
+            };
+            if (pick.first == 1) {
+                read_step(C[w]);
+                H[w] = C[w];
+            } else {
+                if (pick.first == 3) read_step(C[w] + 1);
+                read_step(C[w]);
+                cons[w] = ++C[w];
+                H[w] = pick.first == 3 ? static_cast<int64_t>(C[w]) : -1;
+            }
         }
     }
     return bad;
