@@ -31,6 +31,12 @@ GENERATORS = ("taus", "ran2", "lf")
 # Taus and Ran2 are bound by vector-ALU issue: the lane-instructions that the compiled step loop of
 # ld_run_kernel (underdamped scheme, gfx950) issues per oscillator-step, LDS accesses not counted.
 VALU_PER_OSC_STEP = {"taus": 117, "ran2": 146}
+# Measured bound of those loops: each instruction class at the issue rate the VALU probe measured
+# for it (csrc/probes/valu_rates.hip), times added (transcendentals do not overlap other VALU work),
+# in oscillator-steps/s.  Class counts per oscillator-step, Taus / Ran2: 7 / 7 transcendental,
+# 4 / 12 32-bit multiplies, 4 / 4 conversions, 16 / 24 three-operand integer ops, 21 / 21 FP32
+# mul/add/fma, 65 / 78 other; Ran2's 8 LDS accesses run on their own pipe, far below its limit.
+VALU_MIX_BOUND_OSC_STEPS = {"taus": 3.65e11, "ran2": 2.88e11}
 # VALU lane-operation peak: 256 CUs x 128 lanes per clock x 2.4 GHz (the published 157.3 TFLOP/s FP32
 # vector rate counts an FMA as two flops).
 ALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
@@ -160,8 +166,11 @@ def roofline_entry(kind, ms_run, N, T, lf_path=None):
     ops = VALU_PER_OSC_STEP[kind] * osc_steps
     achieved = ops / per_launch_s / 1e12
     kernel = "ld_run_kernel<%s>" % kind
+    peak_measured = VALU_PER_OSC_STEP[kind] * VALU_MIX_BOUND_OSC_STEPS[kind] / 1e12
     return {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
             "frac": achieved / ALU_PEAK_TOPS, "traffic": counter_traffic(kernel), "kernel": kernel,
+            "peak_measured": peak_measured, "frac_measured": achieved / peak_measured,
+            "peak_measured_how": "instruction mix of the step loop at the probe's per-class issue rates",
             "launches": 1, "avg_launch_us": per_launch_s * 1e6,
             "valu_lane_instr_per_osc_step": VALU_PER_OSC_STEP[kind], "algorithmic_ops_per_launch": ops}
 
@@ -225,7 +234,51 @@ def cpu_baseline(W):
             "host": host_cpu(),
             "sample": "config-2 workload at N=3e4 oscillators x 1000 steps per generator (3 x 3e7 "
                       "oscillator-steps, %.1f s), FP64, one thread" % total_t,
-            "per_generator": per}
+            "per_generator": per, "all_cores": cpu_all_cores(W, per["lf"])}
+
+
+def _oracle_slice(args):
+    """One worker of the all-cores leg: the oracle on oscillators [lo, hi) (their own streams)."""
+    kind, seed, lo, hi, T, p = args
+    import numpy as np
+    import oracle as orc
+
+    st = orc.seed_states(kind, seed, np.arange(lo, hi))
+    orc.ld_run(kind, st, hi - lo, T, p, stride=100)
+
+
+def _oracle_warm(_):
+    import numpy  # noqa: F401
+    import oracle  # noqa: F401
+
+
+def cpu_all_cores(W, lf_rate):
+    """The same oracle on every host core the process may use: Taus and Ran2 oscillators split over
+    worker processes (each oscillator has its own stream, so the split changes no value); the lagged
+    Fibonacci run stays on one core, its numbers being one sequence."""
+    import multiprocessing as mp
+
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    c = W.C2
+    p = c["params"].as_f32().asdict()
+    per_core, T = 10_000, 1000
+    N = per_core * cores
+    per = {"lf": lf_rate}
+    with mp.get_context("spawn").Pool(cores) as pool:
+        pool.map(_oracle_warm, range(cores), chunksize=1)  # worker start-up is not timed
+        for kind in ("taus", "ran2"):
+            jobs = [(kind, c["seed"], i * per_core, (i + 1) * per_core, T, p) for i in range(cores)]
+            t = time.perf_counter()
+            pool.map(_oracle_slice, jobs, chunksize=1)
+            per[kind] = N * T / (time.perf_counter() - t)
+    value = len(GENERATORS) / sum(1.0 / per[k] for k in GENERATORS)
+    return {"value": value, "unit": "oscillator-steps/s", "cores": cores, "per_generator": per,
+            "sample": "Taus and Ran2: %d processes x 1e4 oscillators x 1000 steps each; lagged Fibonacci: "
+                      "the one-thread figure (one sequence)" % cores}
 
 
 def _ev(torch):
