@@ -74,7 +74,7 @@ extern "C" {
  *                reaches 2^30.  Must satisfy ll + W <= R < 2^31.  A fused LD run uses one
  *                persistent launch when sl >= 256 and its own copy of the sequence (about
  *                2 (ll + sl) words, each sl-long link padded to a 256-byte boundary, in the
- *                workspace) stays below 2^30 words; it reads the state's last ll values at the
+ *                workspace) stays below 2^29 words; it reads the state's last ll values at the
  *                start and writes the new last ll values back at the end, so its result does not
  *                depend on R.
  *  lcg_leap    : LCG only.  0: stream j starts from its own seed word (word 0 of stream j).  L > 0:

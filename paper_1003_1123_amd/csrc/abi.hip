@@ -289,7 +289,8 @@ int try_lf_flow(const Gen &g, void *d_state, const RunLayout &L, uint32_t n_step
     if (n == 0 || g.sl < 256 || L.pring_bytes == 0) return 0;
     const LfPadRing pr = lf_pad_ring(g.ll, g.sl);
     const uint64_t R_run = static_cast<uint64_t>(pr.nr) * g.sl;
-    if (R_run >= (1ull << 31)) return 0;
+    // the kernel addresses the ring with 32-bit byte offsets below 2^31
+    if (R_run >= (1ull << 31) || static_cast<uint64_t>(pr.nr) * pr.slp >= (1ull << 29)) return 0;
     const uint64_t Ptot = 4ull * n * n_steps;
     if ((Ptot + g.sl - 1) / g.sl >= (1ull << 31)) return 0;
     const int cus = device_cus();
@@ -314,7 +315,7 @@ int try_lf_flow(const Gen &g, void *d_state, const RunLayout &L, uint32_t n_step
     // the ring must also hold a consumer step's positions behind the producers (lf_flow.hpp), and a
     // consumer's positions of a step span at most two links
     if (R_run < static_cast<uint64_t>(g.sl) + 256ull * geom.Kc - 1 || 256ull * geom.Kc > g.sl) return 0;
-    const size_t lds = static_cast<size_t>(wpb - np) * (geom.Kc * 384u + 256u) * sizeof(float);
+    const size_t lds = static_cast<size_t>(wpb - np) * geom.Kc * 384u * sizeof(float);
     if (lds > 160 * 1024) return 0;
     if (debug_enabled())
         fprintf(stderr, "[rngld] LF persistent run: %d blocks, %u producer + %u consumer waves each, slice %u, "

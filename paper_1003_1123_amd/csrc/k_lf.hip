@@ -204,16 +204,39 @@ __device__ __forceinline__ void agent_store(uint32_t *p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// ring word `idx` (the dataflow run needs R < 2^30, so the byte offset fits 32 bits and the load
-// takes the ring base from scalar registers and one 32-bit offset register)
-__device__ __forceinline__ uint32_t ring_get(const uint32_t *ring, uint32_t idx) {
-    return agent_load(reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(ring) + (idx << 2)));
-}
+// ring word `idx` (the dataflow run's ring is below 2^29 words, so the byte offset fits 31 bits and
+// the store takes the ring base from scalar registers and one 32-bit offset register)
 __device__ __forceinline__ void ring_put(uint32_t *ring, uint32_t idx, uint32_t v) {
     agent_store(reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(ring) + (idx << 2)), v);
 }
 
 constexpr int kFlowM = kLfFlowSliceMax / 64;  // producer positions per lane per link
+constexpr int kFlowG = kFlowM / 4;             // ... in groups of four consecutive offsets
+
+// The persistent run moves ring words four at a time: 16-byte buffer loads and stores with the
+// sc1 cache policy (device scope, the same policy as the agent-scope word accesses above), lane l
+// taking four consecutive words.  A wave then moves 1 KiB per instruction, which on MI355X
+// sustains the run's two-loads-per-store mix about 10% faster than 4-byte accesses and issues a
+// quarter of the memory instructions.  The resource's size bounds every access (an access past it
+// reads zeros and writes nothing); a 16-byte access needs only 4-byte alignment.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kBufferWord3 = 0x00020000;  // raw 32-bit buffer, gfx9 encoding
+constexpr int kCachePolicySc1 = 16;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t ring_rsrc(uint32_t *ring, uint32_t words) {
+    return __builtin_amdgcn_make_buffer_rsrc(ring, 0, static_cast<int>(words * 4u), kBufferWord3);
+}
+__device__ __forceinline__ u32x4 ring_get4(__amdgpu_buffer_rsrc_t r, uint32_t word) {
+    return __builtin_amdgcn_raw_buffer_load_b128(r, static_cast<int>(word << 2), 0, kCachePolicySc1);
+}
+// the first three words at `word` (a straddling group's second part: at most three words, and a
+// load whose result is all used keeps the compiler from reusing a register it still writes)
+typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
+__device__ __forceinline__ u32x3 ring_get3(__amdgpu_buffer_rsrc_t r, uint32_t word) {
+    return __builtin_amdgcn_raw_buffer_load_b96(r, static_cast<int>(word << 2), 0, kCachePolicySc1);
+}
+__device__ __forceinline__ void ring_put4(__amdgpu_buffer_rsrc_t r, uint32_t word, u32x4 v) {
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, static_cast<int>(word << 2), 0, kCachePolicySc1);
+}
 
 // up to 64 waits of one wave, one per lane; `tile` tags a consumer's wait with its tile
 struct FlowWaits {
@@ -258,22 +281,13 @@ __device__ __forceinline__ bool wait_all(FlowWaits &w, uint32_t lane, const LfFl
     return __all(ok);
 }
 
-__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const uint32_t o = __shfl_xor(v, off);
-        v = o < v ? o : v;
-    }
-    return v;
-}
-
-// Producer p: offsets [p T, min((p+1) T, sl)) of every link; lane takes offsets lane + 64 r.
-// Software-pipelined over links.  When link j is summed, one read of the progress words link j+1
-// waits for and then link j's long-lag loads were issued during link j-1.  If those waits hold,
-// link j's stores are followed at once by the read for link j+2 and link j+1's loads, and
-// s_waitcnt vmcnt(kFlowM + 1) then means that every store of link j has completed (vector memory
-// operations complete in issue order), so link j can be published while link j+1's loads are in
-// flight.  Otherwise link j is published first and only then does the producer block on link
+// Producer p: offsets [p T, min((p+1) T, sl)) of every link; lane takes the four-offset groups
+// 4 lane + 256 r.  Software-pipelined over links.  When link j is summed, one read of the progress
+// words link j+1 waits for and then link j's long-lag loads were issued during link j-1.  If those
+// waits hold, link j's stores are followed at once by the read for link j+2 and link j+1's loads,
+// and s_waitcnt vmcnt(kFlowG + 1) then means that every store of link j has completed (vector
+// memory operations complete in issue order), so link j can be published while link j+1's loads
+// are in flight.  Otherwise link j is published first and only then does the producer block on link
 // j+1's waits: it never blocks with an earlier link unpublished (the no-deadlock argument of
 // lf_flow.hpp with one link per iteration).
 // The waits of link j, 64 per round: from the steady link on, a full slice takes the fixed
@@ -332,16 +346,17 @@ __device__ __forceinline__ void lf_producer(const LfFlowArgs &a, uint32_t p, uin
     // words of link j and of link j - lla, the long lag's link for offsets >= llb (advanced
     // together, link by link)
     uint32_t base = 0, base_ll = lf_pad_base(a.pr, -static_cast<int64_t>(lla));
+    const __amdgpu_buffer_rsrc_t rr = ring_rsrc(ring, ring_words);
+    // lane takes the groups of offsets o_lo + 256 r + 4 lane + (0..3), r < kFlowG; a group that
+    // starts at or past the slice's width is not stored
     // y_{P - sl} of link 0 comes from the ring (link -1), afterwards from the previous link in
     // registers
-    uint32_t chain[kFlowM], src[kFlowM];
+    u32x4 chain[kFlowG], src[kFlowG];
+    u32x3 src_x;
     {
         const uint32_t base_prev = lf_pad_base(a.pr, -1);
 #pragma unroll
-        for (int r = 0; r < kFlowM; ++r) {
-            const uint32_t q = lane + 64u * r;
-            chain[r] = q < width ? ring_get(ring, base_prev + o_lo + q) : 0u;
-        }
+        for (int r = 0; r < kFlowG; ++r) chain[r] = ring_get4(rr, base_prev + o_lo + 256u * r + 4u * lane);
     }
     int64_t step_R;
     uint64_t off_R;
@@ -351,16 +366,44 @@ __device__ __forceinline__ void lf_producer(const LfFlowArgs &a, uint32_t p, uin
     lf_wait_template(g, p, o_lo, width, tpl);
     FlowWaits w;
     w.n = 0;
-    // kFlowM long-lag loads of a link, always all issued (an unused one reads the link's first
-    // source), so that their count is exact.  Offset o's source is (link - lla, o - llb) when
-    // o >= llb, else (link - lla - 1, o + sl - llb).
-    auto load_link = [&](uint32_t bll, uint32_t len_j) {
+    // Long-lag sources: offset o reads (link - lla, o - llb) when o >= llb, else (link - lla - 1,
+    // o + sl - llb), so a group's four sources are consecutive words unless the group straddles llb
+    // (o < llb < o + 4): that one group, in lane xl of load xr, takes its words from o = llb on out
+    // of a second load, of the first three words of link - lla.  kFlowG + 1 loads per lane, always
+    // all issued; a group past the slice's width reads words it never uses.
+    const uint32_t xo = llb > o_lo && llb < o_lo + width && (llb - o_lo) % 4u ? (llb - o_lo) / 4u : ~0u;
+    const uint32_t xr = xo / 64u, xl = xo % 64u, xk = llb - o_lo - 4u * xo;
+    const bool x_here = xo != ~0u && lane == xl;
+    auto load_link = [&](uint32_t bll) {
         const uint32_t bll1 = bll >= slp ? bll - slp : bll + ring_words - slp;
 #pragma unroll
-        for (int r = 0; r < kFlowM; ++r) {
-            const uint32_t q = lane + 64u * r;
-            const uint32_t o = o_lo + (q < len_j ? q : 0u);
-            src[r] = ring_get(ring, o >= llb ? bll + (o - llb) : bll1 + (o + (sl - llb)));
+        for (int r = 0; r < kFlowG; ++r) {
+            const uint32_t o = o_lo + 256u * r + 4u * lane;
+            src[r] = ring_get4(rr, o >= llb ? bll + (o - llb) : bll1 + (o + (sl - llb)));
+        }
+        // issued in every lane so that the count is fixed: past the ring's end (zeros, no memory
+        // access) except in lane xl
+        src_x = ring_get3(rr, x_here ? bll : ring_words);
+    };
+    // y_P = y_{P-sl} + y_{P-ll} for the lane's groups
+    auto sum_link = [&]() {
+#pragma unroll
+        for (int r = 0; r < kFlowG; ++r) {
+            u32x4 s = src[r];
+            if (x_here && xr == static_cast<uint32_t>(r)) {
+                // words k >= xk are offsets k - xk of link - lla
+                if (xk == 1u) {
+                    s.y = src_x.x;
+                    s.z = src_x.y;
+                    s.w = src_x.z;
+                } else if (xk == 2u) {
+                    s.z = src_x.x;
+                    s.w = src_x.y;
+                } else {
+                    s.w = src_x.x;
+                }
+            }
+            chain[r] += s;
         }
     };
     // one read of the first 64 progress words link j1 waits for (lanes without a wait read the
@@ -379,7 +422,7 @@ __device__ __forceinline__ void lf_producer(const LfFlowArgs &a, uint32_t p, uin
         lf_consumer_coord_next(g, sR1, oR1);
         poll_link(1, sR1, oR1);
     }
-    load_link(base_ll, len);
+    load_link(base_ll);
     for (uint32_t j = 0; j < g.n_links; ++j) {
         const uint32_t next_base = base + slp < ring_words ? base + slp : 0u;
         const uint32_t next_base_ll = base_ll + slp < ring_words ? base_ll + slp : 0u;
@@ -387,9 +430,7 @@ __device__ __forceinline__ void lf_producer(const LfFlowArgs &a, uint32_t p, uin
         uint64_t next_oR = off_R;
         lf_consumer_coord_next(g, next_sR, next_oR);
         const uint32_t next_len = link_len(j + 1);
-        // link j: y_P = y_{P-sl} + y_{P-ll}
-#pragma unroll
-        for (int r = 0; r < kFlowM; ++r) chain[r] += src[r];
+        sum_link();
         // link j+1's waits, read before link j's loads (a partial next link takes the plain path)
         const bool ready = next_len == width && total_poll <= 64u && __all(lane >= w.n || seen >= w.need);
         w.n = 0;
@@ -397,12 +438,22 @@ __device__ __forceinline__ void lf_producer(const LfFlowArgs &a, uint32_t p, uin
             // a full slice: straight-line stores, so that no store waits for another (a store in
             // a branch of its own can make the compiler wait for the previous one)
 #pragma unroll
-            for (int r = 0; r < kFlowM; ++r) ring_put(ring, base + o_lo + lane + 64u * r, chain[r]);
-        } else {
+            for (int r = 0; r < kFlowG; ++r) ring_put4(rr, base + o_lo + 256u * r + 4u * lane, chain[r]);
+        } else if (len == width) {
+            // the last slice of a link: a group that reaches past sl writes into the link's
+            // padding (slp is a multiple of 64 words, so round_up(sl, 4) <= slp)
 #pragma unroll
-            for (int r = 0; r < kFlowM; ++r) {
-                const uint32_t q = lane + 64u * r;
-                if (q < len) ring_put(ring, base + o_lo + q, chain[r]);
+            for (int r = 0; r < kFlowG; ++r)
+                if (256u * r + 4u * lane < width) ring_put4(rr, base + o_lo + 256u * r + 4u * lane, chain[r]);
+        } else {
+            // the end of the run: word by word, nothing past the last position
+#pragma unroll
+            for (int r = 0; r < kFlowG; ++r) {
+                const uint32_t q = 256u * r + 4u * lane;
+                if (q < len) ring_put(ring, base + o_lo + q, chain[r].x);
+                if (q + 1u < len) ring_put(ring, base + o_lo + q + 1u, chain[r].y);
+                if (q + 2u < len) ring_put(ring, base + o_lo + q + 2u, chain[r].z);
+                if (q + 3u < len) ring_put(ring, base + o_lo + q + 3u, chain[r].w);
             }
         }
         if (!ready) {
@@ -417,12 +468,12 @@ __device__ __forceinline__ void lf_producer(const LfFlowArgs &a, uint32_t p, uin
             lf_consumer_coord_next(g, sR2, oR2);
             poll_link(j + 2, sR2, oR2);
         }
-        load_link(next_base_ll, next_len);
+        load_link(next_base_ll);
         if (ready) {
-            // only the poll and link j+1's kFlowM loads, issued after link j's stores, may still be
-            // outstanding: link j is stored
-            static_assert(kFlowM == 16, "the wait count below");
-            asm volatile("s_waitcnt vmcnt(17)" ::: "memory");
+            // only the poll and link j+1's kFlowG + 1 loads, issued after link j's stores, may
+            // still be outstanding: link j is stored
+            static_assert(kFlowG == 4, "the wait count below");
+            asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
             if (lane == 0) agent_store(a.prod + p * kLfFlagStride, j + 1);
         }
         base = next_base;
@@ -462,16 +513,19 @@ __device__ __forceinline__ void tile_observe(const LfFlowArgs &a, const float *t
 constexpr int kWaitVm1 = 0xF71, kWaitVm0 = 0xF70;
 
 // Consumer wave cw: the Kc consecutive tiles cw Kc .. (64 oscillators each, lane l of tile k
-// drives oscillator 64 (cw Kc + k) + l); x, v in LDS as xv[k][6][64]; tr is a 256-word transpose
-// buffer.  Per step: wait for the producers of the wave's positions, load them all, publish, then
-// drive the oscillators.  Up to 4 tiles per wave the steps are software-pipelined: the next step's
-// loads go out before this step's LD update whenever a poll issued one step earlier shows its
-// producers published (this takes twice the word registers, which 8 tiles do not have).
+// drives oscillator 64 (cw Kc + k) + l); x, v in LDS as xv[k][6][64].  A step's positions for the
+// wave are the 4 (o1 - o0) consecutive ones from 4 o0 + s 4n, and lane l of tile k loads its
+// oscillator's four as one group.  Per step: wait for the producers of the wave's positions, load
+// them, publish, then drive the oscillators.  Up to 4 tiles per wave the steps are
+// software-pipelined: the next step's loads go out before this step's LD update whenever a poll
+// issued one step earlier shows its producers published (a second set of word registers, which 8
+// tiles do not have).
 template <int KC>
-__device__ __forceinline__ void lf_consumer(const LfFlowArgs &a, uint32_t cw, uint32_t lane, float *xv, uint32_t *tr) {
+__device__ __forceinline__ void lf_consumer(const LfFlowArgs &a, uint32_t cw, uint32_t lane, float *xv) {
+    constexpr bool kPipe = KC <= 4;
     const LfFlowGeom &g = a.geom;
     const uint32_t Kc = g.Kc, sl = g.sl, slp = a.pr.slp, nr = a.pr.nr, ring_words = nr * slp;
-    uint32_t *ring = a.pring;
+    const __amdgpu_buffer_rsrc_t rr = ring_rsrc(a.pring, ring_words);
     const uint64_t o0 = 64ull * cw * Kc < a.n ? 64ull * cw * Kc : a.n;
     const uint64_t o1 = 64ull * (cw + 1) * Kc < a.n ? 64ull * (cw + 1) * Kc : a.n;
     if (o0 >= o1) return;  // no oscillators: no producer ever waits for this wave
@@ -487,129 +541,166 @@ __device__ __forceinline__ void lf_consumer(const LfFlowArgs &a, uint32_t cw, ui
             xv[(k * 6 + 3 + d) * 64 + lane] = act ? a.v[d * a.N + o] : 0.0f;
         }
     }
-    if constexpr (KC <= 4) {
-        // coordinates of a step's first position 4 o0 + s 4n: its link, offset and the link's first
-        // word (a step's positions span at most two links: 256 Kc <= sl)
-        struct Coord {
-            int64_t link;
-            uint32_t off, lbase;
-        };
-        auto advance = [&](Coord &c) {
-            const int64_t link_before = c.link;
-            lf_link_coord_next_step(g, c.link, c.off);
-            c.lbase += (static_cast<uint32_t>(c.link - link_before) % nr) * slp;
-            if (c.lbase >= ring_words) c.lbase -= ring_words;
-        };
-        auto collect = [&](FlowWaits &w, const Coord &c) {
-            w.n = 0;
-            lf_walk_producers(g, c.link, c.off, cnt, [&](uint32_t sl_, uint32_t l) {
-                wait_add(w, lane, a.prod + sl_ * kLfFlagStride, l + 1, 0);
-                return true;
-            });
-        };
-        // a step's words, lane-contiguous: always KC x 4 loads (an unused one reads the step's
-        // first word)
-        auto load = [&](uint32_t (&words)[KC][4], const Coord &c) {
-            const uint32_t nbase = c.lbase + slp < ring_words ? c.lbase + slp : 0u;
+    // coordinates of a step's first position 4 o0 + s 4n: its link, offset and the link's first
+    // word (a step's positions span at most two links: 256 Kc <= sl)
+    struct Coord {
+        int64_t link;
+        uint32_t off, lbase;
+    };
+    auto advance = [&](Coord &c) {
+        const int64_t link_before = c.link;
+        lf_link_coord_next_step(g, c.link, c.off);
+        c.lbase += (static_cast<uint32_t>(c.link - link_before) % nr) * slp;
+        if (c.lbase >= ring_words) c.lbase -= ring_words;
+    };
+    auto collect = [&](FlowWaits &w, const Coord &c) {
+        w.n = 0;
+        lf_walk_producers(g, c.link, c.off, cnt, [&](uint32_t sl_, uint32_t l) {
+            wait_add(w, lane, a.prod + sl_ * kLfFlagStride, l + 1, 0);
+            return true;
+        });
+    };
+    // A step's words: lane l of tile k takes positions 256 k + 4 l .. + 3 of the step (a lane past
+    // the wave's positions reads the step's first group).  The one group that may straddle the end
+    // of the step's first link (o < sl < o + 4) takes its words from sl on from the next link's
+    // first three words: a load of its own, issued once the step's loads have returned and waited
+    // for at once (a few steps in a thousand), before the step is published.
+    struct Words {
+        u32x4 q[KC];
+        uint32_t xk, xt, xw;  // xk > 0: group xt's words k >= xk are the words from xw on
+    };
+    auto load = [&](Words &W, const Coord &c) {
+        const uint32_t nbase = c.lbase + slp < ring_words ? c.lbase + slp : 0u;
+        W.xk = 0u;
+        W.xt = 0u;
+        W.xw = nbase;
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            const uint32_t g0 = 256u * k + 4u * lane;
+            const uint32_t o = c.off + (g0 < cnt ? g0 : 0u);
+            W.q[k] = ring_get4(rr, o < sl ? c.lbase + o : nbase + (o - sl));
+            if (o < sl && sl - o < 4u) {
+                W.xk = sl - o;
+                W.xt = k;
+            }
+        }
+    };
+    auto fix = [&](Words &W) {
+        if (__any(W.xk != 0u)) {
+            const u32x3 x = ring_get3(rr, W.xk ? W.xw : ring_words);
 #pragma unroll
             for (int k = 0; k < KC; ++k)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const uint32_t q = 256u * k + lane + 64u * r;
-                    const uint32_t o = c.off + (q < cnt ? q : 0u);
-                    words[k][r] = ring_get(ring, o < sl ? c.lbase + o : nbase + (o - sl));
+                if (W.xk && W.xt == static_cast<uint32_t>(k)) {
+                    if (W.xk == 1u) {
+                        W.q[k].y = x.x;
+                        W.q[k].z = x.y;
+                        W.q[k].w = x.z;
+                    } else if (W.xk == 2u) {
+                        W.q[k].z = x.x;
+                        W.q[k].w = x.y;
+                    } else {
+                        W.q[k].w = x.x;
+                    }
                 }
-        };
-        // one read of the progress word each lane waits for (the status word in lanes without one)
-        auto poll = [&](FlowWaits &w, uint32_t &seen, const Coord &c) {
-            collect(w, c);
-            seen = agent_load(lane < w.n ? w.flag : a.status);
-        };
-        Coord nxt{static_cast<int64_t>((4 * o0) / g.sl), static_cast<uint32_t>((4 * o0) % g.sl), 0u};
-        nxt.lbase = lf_pad_base(a.pr, nxt.link);
-        FlowWaits w;
-        uint32_t wa[KC][4], wb[KC][4], seen = 0;
+        }
+    };
+    auto observe = [&](uint32_t s) {
+        float *t0buf = a.t0buf;
+        asm volatile("" : "+s"(t0buf));
+        if (a.stride && s % a.stride == 0) {
+#pragma unroll 1
+            for (uint32_t k = 0; k < Kw; ++k) {
+                const uint64_t o = o0 + 64ull * k + lane;
+                tile_observe(a, t0buf, xv + k * 384, lane, o, o < o1, s, cw * Kc + k);
+            }
+        }
+        if (a.stride && s == a.t0) {
+#pragma unroll 1
+            for (uint32_t k = 0; k < Kw; ++k) {
+                const uint64_t o = o0 + 64ull * k + lane;
+                if (o < o1)
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        t0buf[d * a.N + o] = xv[(k * 6 + d) * 64 + lane];
+                        t0buf[(3 + d) * a.N + o] = xv[(k * 6 + 3 + d) * 64 + lane];
+                    }
+            }
+        }
+    };
+    auto update = [&](const Words &W) {
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            if (k >= static_cast<int>(Kw)) break;
+            if (o0 + 64ull * k + lane < o1) {
+                const u32x4 u = W.q[k];
+                float gf[3];
+                gaussian_forces(u.x, u.y, u.z, u.w, gf[0], gf[1], gf[2]);
+                float *t = xv + k * 384;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    float x = t[d * 64 + lane], v = t[(3 + d) * 64 + lane];
+                    ld_update(a.coef, x, v, gf[d]);
+                    t[d * 64 + lane] = x;
+                    t[(3 + d) * 64 + lane] = v;
+                }
+            }
+        }
+    };
+    Coord nxt{static_cast<int64_t>((4 * o0) / g.sl), static_cast<uint32_t>((4 * o0) % g.sl), 0u};
+    nxt.lbase = lf_pad_base(a.pr, nxt.link);
+    FlowWaits w;
+    if constexpr (kPipe) {
+        Words wa, wb;
+        uint32_t seen = 0;
         if (a.n_steps > 0) {
             collect(w, nxt);
             if (!wait_all(w, lane, a)) return;
             load(wa, nxt);
             advance(nxt);
-            if (a.n_steps > 1) poll(w, seen, nxt);
+            if (a.n_steps > 1) {
+                collect(w, nxt);
+                seen = agent_load(lane < w.n ? w.flag : a.status);
+            }
         }
-        // Step s with its words X in flight (loaded after the producers published them), followed in
-        // issue order only by the poll of step s+1: wait for X, publish, transpose X through LDS into
-        // registers; if the poll shows step s+1 published, issue its loads into Y and the poll of step
-        // s+2 before the LD update of step s, else wait and load after it.  The loads of step s+1 are
-        // issued before this wave publishes s+2, so its slots still hold them.
-        auto step = [&](uint32_t s, uint32_t (&X)[KC][4], uint32_t (&Y)[KC][4]) -> int {
+        // Step s with its words X in flight (loaded after the producers published them) and, if
+        // there is a step s+1, the poll of its producers issued after them: wait for X (and the
+        // poll), and if the poll shows step s+1 published, issue its loads into Y and the poll of
+        // step s+2 before the LD update of step s, else wait and load after it.  The loads of step
+        // s+1 are issued before this wave publishes s+1, so their slots still hold them.
+        auto step = [&](uint32_t s, Words &X, Words &Y) -> int {
             if (s >= a.n_steps) return 0;
-            float *t0buf = a.t0buf;
-            asm volatile("" : "+s"(t0buf));
-            if (a.stride && s % a.stride == 0) {
-#pragma unroll 1
-                for (uint32_t k = 0; k < Kw; ++k) {
-                    const uint64_t o = o0 + 64ull * k + lane;
-                    tile_observe(a, t0buf, xv + k * 384, lane, o, o < o1, s, cw * Kc + k);
-                }
-            }
-            if (a.stride && s == a.t0) {
-#pragma unroll 1
-                for (uint32_t k = 0; k < Kw; ++k) {
-                    const uint64_t o = o0 + 64ull * k + lane;
-                    if (o < o1)
-#pragma unroll
-                        for (int d = 0; d < 3; ++d) {
-                            t0buf[d * a.N + o] = xv[(k * 6 + d) * 64 + lane];
-                            t0buf[(3 + d) * a.N + o] = xv[(k * 6 + 3 + d) * 64 + lane];
-                        }
-                }
-            }
+            observe(s);
             const bool more = s + 1 < a.n_steps;
-            // X has returned: with a step s+1 the last two memory operations were X's loads and the
-            // poll of step s+1 (either order of poll and publish), so at most one is outstanding;
             // the builtin, unlike inline asm, is known to the compiler's wait insertion
             if (more) __builtin_amdgcn_s_waitcnt(kWaitVm1);
             else __builtin_amdgcn_s_waitcnt(kWaitVm0);
+            fix(X);
+            // X's registers pass through an empty asm statement: the compiler's wait insertion then
+            // sees them written here, after their loads have returned, and does not hold the LD
+            // update below for the loads of step s+1 issued in between
+#pragma unroll
+            for (int k = 0; k < KC; ++k) asm volatile("" : "+v"(X.q[k]));
             const bool ready = more && w.n <= 64u && __all(lane >= w.n || seen >= w.need);
-            // lane-contiguous words -> each oscillator lane's four words
-            uint32_t u[KC][4];
-#pragma unroll
-            for (int k = 0; k < KC; ++k) {
-                if (k >= static_cast<int>(Kw)) break;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) tr[lane + 64 * r] = X[k][r];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) u[k][r] = tr[4 * lane + r];
-            }
             Coord far = nxt;
             advance(far);
             if (ready) {
                 load(Y, nxt);
-                if (s + 2 < a.n_steps) poll(w, seen, far);
+                if (s + 2 < a.n_steps) {
+                    collect(w, far);
+                    seen = agent_load(lane < w.n ? w.flag : a.status);
+                }
             }
             // X's slots are free (published before any wait for step s+1)
             if (lane == 0) agent_store(a.cons + cw * kLfFlagStride, s + 1);
-#pragma unroll
-            for (int k = 0; k < KC; ++k) {
-                if (k >= static_cast<int>(Kw)) break;
-                if (o0 + 64ull * k + lane < o1) {
-                    float gf[3];
-                    gaussian_forces(u[k][0], u[k][1], u[k][2], u[k][3], gf[0], gf[1], gf[2]);
-                    float *t = xv + k * 384;
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        float x = t[d * 64 + lane], v = t[(3 + d) * 64 + lane];
-                        ld_update(a.coef, x, v, gf[d]);
-                        t[d * 64 + lane] = x;
-                        t[(3 + d) * 64 + lane] = v;
-                    }
-                }
-            }
+            update(X);
             if (more && !ready) {
                 collect(w, nxt);
                 if (!wait_all(w, lane, a)) return -1;
                 load(Y, nxt);
-                if (s + 2 < a.n_steps) poll(w, seen, far);
+                if (s + 2 < a.n_steps) {
+                    collect(w, far);
+                    seen = agent_load(lane < w.n ? w.flag : a.status);
+                }
             }
             nxt = far;
             return 1;
@@ -621,81 +712,19 @@ __device__ __forceinline__ void lf_consumer(const LfFlowArgs &a, uint32_t cw, ui
             if (r == 0) break;
         }
     } else {
-        // the step's first position 4 o0 + s 4n: its link, offset and the link's first word (a step's
-        // positions span at most two links: 256 Kc <= sl)
-        int64_t link = static_cast<int64_t>((4 * o0) / g.sl);
-        uint32_t off = static_cast<uint32_t>((4 * o0) % g.sl);
-        uint32_t lbase = lf_pad_base(a.pr, link);
-        FlowWaits w;
-        w.n = 0;
+        Words W;
         for (uint32_t s = 0; s < a.n_steps; ++s) {
-            // an opaque copy of the pointer keeps the per-tile addresses from being held in registers
-            // across the loop
-            float *t0buf = a.t0buf;
-            asm volatile("" : "+s"(t0buf));
-            if (a.stride && s % a.stride == 0) {
-#pragma unroll 1
-                for (uint32_t k = 0; k < Kw; ++k) {
-                    const uint64_t o = o0 + 64ull * k + lane;
-                    tile_observe(a, t0buf, xv + k * 384, lane, o, o < o1, s, cw * Kc + k);
-                }
-            }
-            if (a.stride && s == a.t0) {
-#pragma unroll 1
-                for (uint32_t k = 0; k < Kw; ++k) {
-                    const uint64_t o = o0 + 64ull * k + lane;
-                    if (o < o1)
-#pragma unroll
-                        for (int d = 0; d < 3; ++d) {
-                            t0buf[d * a.N + o] = xv[(k * 6 + d) * 64 + lane];
-                            t0buf[(3 + d) * a.N + o] = xv[(k * 6 + 3 + d) * 64 + lane];
-                        }
-                }
-            }
+            observe(s);
             // the producers of this step's positions (a few slices: one wait per lane)
-            lf_walk_producers(g, link, off, cnt, [&](uint32_t sl_, uint32_t l) {
-                wait_add(w, lane, a.prod + sl_ * kLfFlagStride, l + 1, 0);
-                return true;
-            });
+            collect(w, nxt);
             if (!wait_all(w, lane, a)) return;
-            uint32_t words[KC][4];
-            const uint32_t nbase = lbase + slp < ring_words ? lbase + slp : 0u;
-#pragma unroll
-            for (int k = 0; k < KC; ++k)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const uint32_t q = 256u * k + lane + 64u * r;
-                    const uint32_t o = off + q;
-                    words[k][r] = q < cnt ? ring_get(ring, o < sl ? lbase + o : nbase + (o - sl)) : 0u;
-                }
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the loads have returned: the slots are free
+            load(W, nxt);
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the loads have returned
+            fix(W);
+            // the step's slots are free
             if (lane == 0) agent_store(a.cons + cw * kLfFlagStride, s + 1);
-#pragma unroll
-            for (int k = 0; k < KC; ++k) {
-                if (k >= static_cast<int>(Kw)) break;
-                // lane-contiguous words -> oscillator lane's four words
-#pragma unroll
-                for (int r = 0; r < 4; ++r) tr[lane + 64 * r] = words[k][r];
-                uint32_t u[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) u[r] = tr[4 * lane + r];
-                if (o0 + 64ull * k + lane < o1) {
-                    float gf[3];
-                    gaussian_forces(u[0], u[1], u[2], u[3], gf[0], gf[1], gf[2]);
-                    float *t = xv + k * 384;
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        float x = t[d * 64 + lane], v = t[(3 + d) * 64 + lane];
-                        ld_update(a.coef, x, v, gf[d]);
-                        t[d * 64 + lane] = x;
-                        t[(3 + d) * 64 + lane] = v;
-                    }
-                }
-            }
-            const int64_t link_before = link;
-            lf_link_coord_next_step(g, link, off);
-            lbase += (static_cast<uint32_t>(link - link_before) % nr) * slp;
-            if (lbase >= ring_words) lbase -= ring_words;
+            update(W);
+            advance(nxt);
         }
     }
     float *t0buf = a.t0buf, *xo = a.x, *vo = a.v;
@@ -728,9 +757,8 @@ __global__ __launch_bounds__(kLfFlowBlock) void lf_pc_kernel(LfFlowArgs a) {
         lf_producer(a, __builtin_amdgcn_readfirstlane(blockIdx.x * a.np + wid), lane);
     } else {
         const uint32_t nc = kLfFlowBlock / 64 - a.np, k = wid - a.np;
-        float *base = flow_lds + static_cast<size_t>(k) * (a.geom.Kc * 384u + 256u);
-        lf_consumer<KC>(a, __builtin_amdgcn_readfirstlane(blockIdx.x * nc + k), lane, base,
-                        reinterpret_cast<uint32_t *>(base + a.geom.Kc * 384u));
+        lf_consumer<KC>(a, __builtin_amdgcn_readfirstlane(blockIdx.x * nc + k), lane,
+                        flow_lds + static_cast<size_t>(k) * a.geom.Kc * 384u);
     }
 }
 
