@@ -45,10 +45,10 @@ ALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 LF_ALGO_BYTES_PER_OSC_STEP = 4 * 12
 LF_WAVE_XV_BYTES_PER_OSC_STEP = 48
 HBM_PEAK_GBS = 8000.0
-# Measured peak for the lagged-Fibonacci run's traffic: device-scope loads and stores, two loads per
-# store, over a 32 MB region, stores 256-byte aligned and loads 13 words off (as the run's long-lag
-# reads), from the store-alignment probe (csrc/probes/store_alignment.hip, mode 3).
-LF_MEASURED_PEAK_GBS = 7330.0
+# Measured peak for the lagged-Fibonacci run's traffic: device-scope 16-byte loads and stores, two
+# loads per store, over a 32 MB region, stores 256-byte aligned and loads 13 words off (as the run's
+# long-lag reads), from the wide-access probe (csrc/probes/wide_access.hip, mode 4).
+LF_MEASURED_PEAK_GBS = 8130.0
 # HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch) at the config-2
 # workload, scaled by what the same counters read for a plain 1 GiB device copy (FETCH_SIZE 0.5 GiB:
 # factor 2; WRITE_SIZE 1 GiB: factor 1).  Valid only for the machine code they were taken on: the
@@ -56,9 +56,9 @@ LF_MEASURED_PEAK_GBS = 7330.0
 # which the build records in kernel_isa.json; otherwise the traffic is reported as null.
 COUNTER_TRAFFIC = {
     "lf_pc_kernel": {
-        "isa_sha256": "3bb47f7afdd0f1fe7089fd36a7e0592070bcf38e5217a2b918b2c42ed75412fd",
-        # FETCH_SIZE 160504332.375 KiB x (2^20 / 524310.5), WRITE_SIZE 158418069.71875 KiB x (2^20 / 1048576.03125)
-        "fetch_bytes": 328698766483, "write_bytes": 162220098557,
+        "isa_sha256": "22bf57e288f5114daacfeb4c98fe10b873fddb3d979a652c62a1229c02a6e043",
+        # FETCH_SIZE 160613349.1875 KiB x (2^20 / 524308.0625), WRITE_SIZE 158418493.40625 KiB x (2^20 / 1048576)
+        "fetch_bytes": 328923552487, "write_bytes": 162220537248,
     },
 }
 
@@ -159,7 +159,7 @@ def roofline_entry(kind, ms_run, N, T, lf_path=None):
         return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(kernel), "kernel": kernel,
                 "peak_measured": LF_MEASURED_PEAK_GBS, "frac_measured": achieved / LF_MEASURED_PEAK_GBS,
-                "peak_measured_how": "store-alignment probe, device-scope 2 loads + 1 store per word, 32 MB",
+                "peak_measured_how": "wide-access probe, device-scope 16-byte accesses, 2 loads + 1 store per word, 32 MB",
                 "lf_path": lf_path, "launches": launches, "avg_launch_us": per_launch_s * 1e6,
                 "algorithmic_bytes_per_osc_step": per_os, "algorithmic_bytes_per_launch": per_launch_bytes}
     per_launch_s = ms_run / 1e3
