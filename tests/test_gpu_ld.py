@@ -374,8 +374,12 @@ def test_no_noise_batched_plan_and_null_state():
 # ---------------------------------------------------------------------------------------------
 # lagged Fibonacci: persistent dataflow run vs one launch per wave
 
+# lags whose short lag is 1 or 3 mod 4 make consumer groups of four straddle a link's end with one,
+# two or three words in it; every b = ll mod sl here is off a multiple of 4, so one producer group per
+# link straddles b
 @pytest.mark.parametrize("n,lags,T", [(1000, (2281, 1252), 200), (1, (2281, 1252), 2000), (3001, (9689, 5502), 150),
-                                      (257, (4423, 3004), 300), (100_000, (132049, 54454), 60)])
+                                      (257, (4423, 3004), 300), (100_000, (132049, 54454), 60),
+                                      (2000, (19937, 10095), 100), (5000, (859433, 288477), 200)])
 def test_lf_dataflow_equals_waves_and_oracle(n, lags, T):
     ll, sl = lags
     pp = W.LDParams(k=1.1, gamma=0.9, kT=1.0, dt=0.01).as_f32()
