@@ -109,24 +109,21 @@ struct NoNoise {
 };
 
 // ---- Ran2 -------------------------------------------------------------------------------------------
-constexpr int32_t kR2M1 = 2147483563, kR2A1 = 40014, kR2Q1 = 53668, kR2R1 = 12211;
-constexpr int32_t kR2M2 = 2147483399, kR2A2 = 40692, kR2Q2 = 52774, kR2R2 = 3791;
+// Ran2's two generators x -> A x mod M with M = 2^31 - C (Numerical Recipes' constants)
+constexpr int32_t kR2M1 = 2147483563, kR2A1 = 40014;
+constexpr int32_t kR2M2 = 2147483399, kR2A2 = 40692;
+constexpr uint32_t kR2C1 = 85, kR2C2 = 249;
+static_assert(kR2M1 == 2147483648ll - kR2C1 && kR2M2 == 2147483648ll - kR2C2, "M = 2^31 - C");
 constexpr int kR2Tab = 32;
 constexpr int32_t kR2Imm1 = kR2M1 - 1;
 constexpr uint32_t kR2Ndiv = 1u + static_cast<uint32_t>(kR2Imm1) / kR2Tab;
 
-// A x mod M for 0 < x < M by Schrage: M = A Q + R with R < Q, so
-// A (x mod Q) - R floor(x / Q) lies in (-M, M).  All products fit in 24-bit multiplies.
-template <int32_t A, int32_t Q, int32_t R, int32_t M>
-__device__ __forceinline__ int32_t schrage(int32_t x) {
-    const uint32_t k = static_cast<uint32_t>(x) / static_cast<uint32_t>(Q);
-    const uint32_t rem = static_cast<uint32_t>(x) - __umul24(k, Q);
-    const int32_t t = static_cast<int32_t>(__umul24(A, rem)) - static_cast<int32_t>(__umul24(k, R));
-    return t < 0 ? t + M : t;
+__device__ __forceinline__ int32_t ran2_lcg1(int32_t x) {
+    return static_cast<int32_t>(mulmod_2p31m<kR2A1, kR2C1>(static_cast<uint32_t>(x)));
 }
-
-__device__ __forceinline__ int32_t ran2_lcg1(int32_t x) { return schrage<kR2A1, kR2Q1, kR2R1, kR2M1>(x); }
-__device__ __forceinline__ int32_t ran2_lcg2(int32_t x) { return schrage<kR2A2, kR2Q2, kR2R2, kR2M2>(x); }
+__device__ __forceinline__ int32_t ran2_lcg2(int32_t x) {
+    return static_cast<int32_t>(mulmod_2p31m<kR2A2, kR2C2>(static_cast<uint32_t>(x)));
+}
 
 // Ran2 stream with its shuffle table in LDS: tab[t * tstride] is entry t of this thread's table.
 struct Ran2 {

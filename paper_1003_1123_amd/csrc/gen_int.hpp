@@ -81,6 +81,19 @@ RNGLD_HDI uint32_t tausworthe_inv(uint32_t w) {
     return t | (w >> S);
 }
 
+// A x mod M for M = 2^31 - C and 0 <= x < M (the multiplicative steps of Ran2's two generators):
+// the product p = A x, below 2^47, is H 2^31 + L, and 2^31 = C (mod M), so p = C H + L (mod M), where
+// C H + L < 2 M takes one conditional subtraction.  One 32 x 32 -> 64-bit multiply and one 24-bit
+// multiply-add, against four multiplies for Schrage's method; the same exact residue.
+template <uint32_t A, uint32_t C>
+RNGLD_HDI uint32_t mulmod_2p31m(uint32_t x) {
+    static_assert(A < (1u << 16) && C < (1u << 14), "C H + L < 2 M");
+    const uint64_t p = static_cast<uint64_t>(A) * x;
+    const uint32_t r = (static_cast<uint32_t>(p) & 0x7fffffffu) + C * static_cast<uint32_t>(p >> 31);
+    constexpr uint32_t m = 0x80000000u - C;
+    return r >= m ? r - m : r;
+}
+
 // smallest word whose top K bits are not all zero
 template <int K>
 RNGLD_HDI uint32_t tausworthe_lift(uint32_t z) {

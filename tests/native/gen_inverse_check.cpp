@@ -2,7 +2,9 @@
 // seeds, stepping each Tausworthe component and the LCG forward and then back with the inverse
 // steps returns every produced word exactly, and a seeded word's top K bits.  Also checks the
 // produced words against the component's bit recurrence y_m = y_{m-K+Q} xor y_{m-K} (Eq. 2), which
-// the inverse relies on.  Prints "ok" on success.
+// the inverse relies on.  And the modular product A x mod (2^31 - C) of Ran2's two generators
+// (mulmod_2p31m) against the plain 64-bit remainder, at random and at the ends of its range.
+// Prints "ok" on success.
 #include <cstdio>
 #include <cstdint>
 #include <vector>
@@ -51,6 +53,25 @@ static int check_component(int n_seeds, int n_steps) {
     return bad;
 }
 
+template <uint32_t A, uint32_t C>
+static int check_mulmod() {
+    const uint64_t m = (1ull << 31) - C;
+    int bad = 0;
+    auto one = [&](uint32_t x) {
+        if (mulmod_2p31m<A, C>(x) != static_cast<uint32_t>(static_cast<uint64_t>(A) * x % m)) ++bad;
+    };
+    for (uint32_t x : {0u, 1u, 2u, 3u, static_cast<uint32_t>(m - 1), static_cast<uint32_t>(m - 2),
+                       static_cast<uint32_t>(m / A), static_cast<uint32_t>(m / A + 1), 0x40000000u})
+        one(x);
+    // every x whose product's high part H = floor(A x / 2^31) changes (the carries into C H)
+    for (uint64_t h = 1; h < A; ++h) {
+        const uint64_t x0 = (h << 31) / A;
+        for (uint64_t x = x0 > 2 ? x0 - 2 : 0; x <= x0 + 2 && x < m; ++x) one(static_cast<uint32_t>(x));
+    }
+    for (int t = 0; t < 1000000; ++t) one(static_cast<uint32_t>(rnd() % m));
+    return bad;
+}
+
 int main() {
     int bad = 0;
     bad += check_component<13, 12, 31>(2000, 60);
@@ -61,6 +82,8 @@ int main() {
         if (lcg_prev(lcg_next(x)) != x || lcg_next(lcg_prev(x)) != x) ++bad;
     }
     if (kLcgMul * kLcgMulInv != 1u) ++bad;
+    bad += check_mulmod<40014, 85>();
+    bad += check_mulmod<40692, 249>();
     if (bad) {
         std::printf("FAILED: %d\n", bad);
         return 1;

@@ -1,7 +1,8 @@
-"""CPU check of the inverse generator steps (paper_1003_1123_amd/csrc/gen_int.hpp) used by the
-register-only adjoint: Tausworthe components and the LCG stepped forward and back return every
-produced word; produced words are windows of the component's bit recurrence (Eq. 2).  Compiled
-with the host compiler."""
+"""CPU check of the integer generator steps in paper_1003_1123_amd/csrc/gen_int.hpp: the inverse
+steps used by the register-only adjoint (Tausworthe components and the LCG stepped forward and back
+return every produced word; produced words are windows of the component's bit recurrence, Eq. 2),
+and the modular product of Ran2's two generators against the 64-bit remainder.  Compiled with the
+host compiler."""
 import os
 import shutil
 import subprocess
