@@ -33,10 +33,12 @@ GENERATORS = ("taus", "ran2", "lf")
 VALU_PER_OSC_STEP = {"taus": 117, "ran2": 126}
 # Measured bound of those loops: each instruction class at the issue rate the VALU probe measured
 # for it (csrc/probes/valu_rates.hip), times added (transcendentals do not overlap other VALU work),
+# except that a 32-bit multiply interleaved with other integer work costs what the probe's mixed
+# multiply + xor kernel shows (1.2e-14 s of chip time per lane-operation, against 3.0e-14 alone);
 # in oscillator-steps/s.  Class counts per oscillator-step, Taus / Ran2: 7 / 7 transcendental,
 # 4 / 12 32-bit multiplies, 4 / 4 conversions, 16 / 24 three-operand integer ops, 21 / 21 FP32
 # mul/add/fma, 65 / 58 other; Ran2's 8 LDS accesses run on their own pipe, far below its limit.
-VALU_MIX_BOUND_OSC_STEPS = {"taus": 3.65e11, "ran2": 3.26e11}
+VALU_MIX_BOUND_OSC_STEPS = {"taus": 3.75e11, "ran2": 3.50e11}
 # VALU lane-operation peak: 256 CUs x 128 lanes per clock x 2.4 GHz (the published 157.3 TFLOP/s FP32
 # vector rate counts an FMA as two flops).
 ALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12

@@ -1,8 +1,8 @@
 // device.hpp -- device-side generators, uniform mapping, Box-Muller and the LD update for gfx950.
 //
 // Hybrid Taus: Sec. II.D (Eq. 2 in L'Ecuyer's shift form) and Appendix A Alg. 1.
-// Ran2: Sec. II.C and Alg. 2, with a*x mod m evaluated by Schrage's decomposition in 24-bit
-//       multiplies (every intermediate stays below 2^31, so 32-bit integers suffice).
+// Ran2: Sec. II.C and Alg. 2, with a*x mod m for m = 2^31 - C evaluated from the 64-bit product
+//       reduced with 2^31 = C (mod m) (gen_int.hpp); the state stays in 32-bit integers.
 // Lagged Fibonacci: Sec. II.E Eq. 3 with addition mod 2^32 (the ring kernels live in k_lf.hip).
 // Box-Muller: Sec. I; four uniforms give one oscillator-step's three force components
 //       (Table II caption).
