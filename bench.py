@@ -45,6 +45,9 @@ ALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 # Lagged Fibonacci: each of the 4 numbers of an oscillator-step reads two earlier numbers and is
 # written once, 4 B each (Alg. 3); the wave path also moves x and v (6 x 4 B each way) per step.
 LF_ALGO_BYTES_PER_OSC_STEP = 4 * 12
+# One launch per LD step (the paper's protocol): per oscillator-step the state is read and written
+# (Taus 4 words, Ran2 35 words: idum, idum2, iy and the 32-entry table) and so are x and v (6 floats).
+STEP_BYTES_PER_OSC_STEP = {"taus": 2 * 4 * 4 + 48, "ran2": 2 * 35 * 4 + 48, "none": 48}
 LF_WAVE_XV_BYTES_PER_OSC_STEP = 48
 HBM_PEAK_GBS = 8000.0
 # Measured peak for the lagged-Fibonacci run's traffic: device-scope 16-byte loads and stores, two
@@ -491,7 +494,7 @@ def extra_fig6_breakdown(R, W, torch, cpu=True):
                     run = lambda: [R.rng_uniform(cfg, st, c, buf) for c in calls]
                 row["rng_only_ms"][kind] = timed(run)
             del st, ws
-        for kind in ("taus", "none"):
+        for kind in ("taus", "ran2", "none"):
             cfg = R.make_cfg(kind, seed=seed, n_streams=N)
             st = R.new_state(cfg)
             R.rng_init(cfg, st)
@@ -507,6 +510,9 @@ def extra_fig6_breakdown(R, W, torch, cpu=True):
                     R.ld_step(cfg, st, p, N, x, v)
             g.replay()
             row["step_protocol_graph_ms_" + kind] = timed(g.replay)
+            # bytes each launch moves per oscillator-step: the generator state and x, v in and out
+            row["step_protocol_graph_GBps_" + kind] = (STEP_BYTES_PER_OSC_STEP[kind] * N * T /
+                                                       (row["step_protocol_graph_ms_" + kind] / 1e3) / 1e9)
             del g, st
         if cpu:
             import oracle as orc
