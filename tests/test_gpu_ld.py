@@ -379,7 +379,10 @@ def test_no_noise_batched_plan_and_null_state():
 # link straddles b
 @pytest.mark.parametrize("n,lags,T", [(1000, (2281, 1252), 200), (1, (2281, 1252), 2000), (3001, (9689, 5502), 150),
                                       (257, (4423, 3004), 300), (100_000, (132049, 54454), 60),
-                                      (2000, (19937, 10095), 100), (5000, (859433, 288477), 200)])
+                                      (2000, (19937, 10095), 100), (5000, (859433, 288477), 200),
+                                      # not Table I rows: short lags whose link padding (to 64 words) is
+                                      # 3 and 1 words, exactly what the last group of a link spills into
+                                      (3000, (2 * 1021 + 517, 1021), 120), (3000, (2 * 1023 + 300, 1023), 120)])
 def test_lf_dataflow_equals_waves_and_oracle(n, lags, T):
     ll, sl = lags
     pp = W.LDParams(k=1.1, gamma=0.9, kT=1.0, dt=0.01).as_f32()
