@@ -45,9 +45,10 @@ ALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 # Lagged Fibonacci: each of the 4 numbers of an oscillator-step reads two earlier numbers and is
 # written once, 4 B each (Alg. 3); the wave path also moves x and v (6 x 4 B each way) per step.
 LF_ALGO_BYTES_PER_OSC_STEP = 4 * 12
-# One launch per LD step (the paper's protocol): per oscillator-step the state is read and written
-# (Taus 4 words, Ran2 35 words: idum, idum2, iy and the 32-entry table) and so are x and v (6 floats).
-STEP_BYTES_PER_OSC_STEP = {"taus": 2 * 4 * 4 + 48, "ran2": 2 * 35 * 4 + 48, "none": 48}
+# One launch per LD step (the paper's protocol), bytes per oscillator-step: x and v (6 floats) read
+# and written, and the generator state: Taus 4 words read and written; Ran2 its 3 words read and
+# written plus, for each of the 4 draws, the one table entry the draw selects (read and written).
+STEP_BYTES_PER_OSC_STEP = {"taus": 2 * 4 * 4 + 48, "ran2": 2 * 3 * 4 + 2 * 4 * 4 + 48, "none": 48}
 LF_WAVE_XV_BYTES_PER_OSC_STEP = 48
 HBM_PEAK_GBS = 8000.0
 # Measured peak for the lagged-Fibonacci run's traffic: device-scope 16-byte loads and stores, two
