@@ -1,0 +1,71 @@
+"""Host logic of bench.py, without a GPU: the one-GPU guard, the roofline arithmetic, the counter
+traffic that is reported only for the machine code it was taken on, and the per-oscillator-step
+byte and instruction counts the roofline uses."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_lf_roofline_is_algorithmic_bytes_over_the_launch_time():
+    N, T, ms = 1_000_000, 10_000, 72.0
+    e = bench.roofline_entry("lf", ms, N, T, "dataflow")
+    # 4 numbers per oscillator-step, each written once and read twice (Eq. 3), 4 bytes each
+    assert e["algorithmic_bytes_per_osc_step"] == 48
+    assert e["algorithmic_bytes_per_launch"] == 48 * N * T
+    assert e["achieved"] == pytest.approx(48 * N * T / (ms / 1e3) / 1e9)
+    assert e["frac"] == pytest.approx(e["achieved"] / 8000.0)
+    assert e["frac_measured"] == pytest.approx(e["achieved"] / bench.LF_MEASURED_PEAK_GBS)
+    assert e["launches"] == 1 and e["avg_launch_us"] == pytest.approx(ms * 1e3)
+    assert e["bound"] == "hbm" and e["unit"] == "GB/s"
+    # the wave path: one launch per wave, x and v through memory as well
+    w = bench.roofline_entry("lf", ms, N, T, "waves")
+    assert w["kernel"] == "lf_ld_phase_kernel" and w["launches"] == 4 * T
+    assert w["algorithmic_bytes_per_osc_step"] == 48 + 48
+
+
+@pytest.mark.parametrize("kind", ["taus", "ran2"])
+def test_valu_roofline_uses_the_loop_counts_and_the_mix_bound(kind):
+    N, T, ms = 1_000_000, 10_000, 30.0
+    e = bench.roofline_entry(kind, ms, N, T)
+    ops = bench.VALU_PER_OSC_STEP[kind] * N * T
+    assert e["achieved"] == pytest.approx(ops / (ms / 1e3) / 1e12)
+    assert e["peak"] == pytest.approx(256 * 128 * 2.4e9 / 1e12)
+    # the measured peak is the mix bound in oscillator-steps/s times the loop's instructions
+    assert e["peak_measured"] == pytest.approx(bench.VALU_PER_OSC_STEP[kind] * bench.VALU_MIX_BOUND_OSC_STEPS[kind]
+                                               / 1e12)
+    assert e["frac_measured"] == pytest.approx((N * T / (ms / 1e3)) / bench.VALU_MIX_BOUND_OSC_STEPS[kind])
+    assert e["traffic"] is None  # no counters are recorded for these kernels
+
+
+def test_counter_traffic_only_for_the_recorded_machine_code(monkeypatch):
+    c = bench.COUNTER_TRAFFIC["lf_pc_kernel"]
+    monkeypatch.setattr(bench, "built_isa", lambda k: c["isa_sha256"])
+    assert bench.counter_traffic("lf_pc_kernel") == c["fetch_bytes"] + c["write_bytes"]
+    monkeypatch.setattr(bench, "built_isa", lambda k: "0" * 64)
+    assert bench.counter_traffic("lf_pc_kernel") is None
+    monkeypatch.setattr(bench, "built_isa", lambda k: None)
+    assert bench.counter_traffic("lf_pc_kernel") is None
+    # the counted bytes stay close to the algorithmic 480 GB of the config-2 run
+    assert 0.98 < (c["fetch_bytes"] + c["write_bytes"]) / 480e9 < 1.1
+
+
+def test_step_protocol_bytes():
+    # x and v (6 floats) in and out, plus the state each launch reads and writes
+    assert bench.STEP_BYTES_PER_OSC_STEP["none"] == 48
+    assert bench.STEP_BYTES_PER_OSC_STEP["taus"] == 48 + 2 * 16
+    assert bench.STEP_BYTES_PER_OSC_STEP["ran2"] == 48 + 2 * 12 + 2 * 4 * 4
