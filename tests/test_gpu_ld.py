@@ -234,6 +234,46 @@ def test_batched_equals_plain_bit_exact(kind):
         assert np.array_equal(obb[i], o1.cpu().numpy().reshape(P, R.NOBS)), i
 
 
+def test_config4_ensemble_statistics():
+    """Config 4 at full size (512 ensembles, 76.7e6 oscillators, 5000 steps from rest, one batched
+    run): each ensemble's <x^2> and <v^2> after the run against the exact discrete second moments
+    of its own (k, gamma, kT, h), cov_n = S - A^n S (A^n)^T with S the stationary covariance
+    (A S A^T + B B^T = S).  x and v are Gaussian with mean 0, so the estimate over 3 n_e coordinates
+    has standard error var sqrt(2 / (3 n_e)); across the ensembles the z-scores must look N(0, 1)."""
+    from scipy.linalg import solve_discrete_lyapunov
+
+    c4 = W.C4
+    ens_list = W.batched_ensembles(c4["n_ens"], c4["draw_seed"], c4["base_seed"], c4["dt"])
+    offs = np.concatenate([[0], np.cumsum([e.n for e in ens_list])])
+    n_total, T = int(offs[-1]), c4["steps"]
+    specs = [(int(offs[i]), e.n, _params(e.params), e.seed) for i, e in enumerate(ens_list)]
+    ens, n_ens = R.make_ensembles(specs)
+    cfg = R.make_cfg("taus", n_streams=n_total)
+    st = R.new_state(cfg)
+    R.rng_init_ensembles(cfg, st, ens, n_ens)
+    x = torch.zeros(3 * n_total, dtype=torch.float32, device="cuda")
+    v = torch.zeros_like(x)
+    ob = torch.zeros(n_ens * 2 * R.NOBS, dtype=torch.float64, device="cuda")
+    _say("config 4 statistics", n_ens, n_total, T)
+    R.ld_run(cfg, st, ens, n_ens, n_total, T, x, v, R.Obs(T, 0), ob)
+    torch.cuda.synchronize()
+    del x, v, st
+    o = ob.cpu().numpy().reshape(n_ens, 2, R.NOBS)[:, 1]
+    z = []
+    for i, e in enumerate(ens_list):
+        p = e.params
+        A, B = mom.scheme_matrices(p.m, p.k, p.gamma, p.kT, p.dt)
+        S = solve_discrete_lyapunov(A, B @ B.T)
+        An = np.linalg.matrix_power(A, T)
+        cov = S - An @ S @ An.T
+        for j, var in ((0, cov[0, 0]), (1, cov[1, 1])):
+            se = var * math.sqrt(2.0 / (3 * e.n))
+            z.append((o[i, j] - var) / se)
+    z = np.array(z)
+    _say("config 4 z: mean %.3f var %.3f max %.2f" % (z.mean(), z.var(), np.abs(z).max()))
+    assert abs(z.mean()) < 0.25 and 0.7 < z.var() < 1.4 and np.abs(z).max() < 5.0
+
+
 @pytest.mark.parametrize("tuning", [(64, 1, 0, 0), (128, 2, 0, 0), (256, 1, 37, 0), (512, 2, 0, 4), (256, 2, 100, 2)])
 def test_tunings_give_identical_trajectories(tuning):
     """Launch shape changes neither the trajectory nor the generator state (observables may differ
