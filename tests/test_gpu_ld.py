@@ -163,6 +163,26 @@ def test_config2_lf_full_size_sampled():
     assert okx and okv
 
 
+def test_config2_lf_full_run_statistics():
+    """The whole config-2 LF run (N = 1e6, 1e4 steps, Table I's last row, the persistent path):
+    completes without a failed wait, and equipartition holds over all 3e6 coordinates at the end,
+    as for the per-thread generators."""
+    N, T = W.C2["N"], W.C2["steps"]
+    ll, sl = W.C2["lf_lags"]
+    p = W.C2["params"].as_f32()
+    _say("config2 lf full run", N, T)
+    cfg, st, x, v = _setup("lf", N, ll=ll, sl=sl)
+    ens, n_ens = R.make_ensembles([(0, N, _params(p), 0)])
+    ws = R.ld_run(cfg, st, ens, n_ens, N, T, x, v)
+    assert R.ws_status(ws) == 0 and R.ws_lf_path(ws) == "dataflow"
+    assert _lf_state(st)[0] == 4 * N * T
+    x2s, v2s, _ = mom.stationary_closed_form(p.m, p.k, p.gamma, p.kT, p.dt)
+    xx = float((x.double() ** 2).mean())
+    vv = float((v.double() ** 2).mean())
+    _say("lf equipartition", xx / x2s, vv / v2s)
+    assert abs(xx - x2s) < 5 * x2s * math.sqrt(2 / (3 * N)) and abs(vv - v2s) < 5 * v2s * math.sqrt(2 / (3 * N))
+
+
 # ---------------------------------------------------------------------------------------------
 # protocol equivalences
 
