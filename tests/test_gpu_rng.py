@@ -3,6 +3,7 @@
 Integer streams must match bit for bit; FP32 Gaussians within 1e-5 absolute of the FP64 oracle.
 """
 import os
+import math
 import sys
 
 import numpy as np
@@ -155,6 +156,59 @@ def test_gaussian_streams_within_tolerance(kind):
     err = np.max(np.abs(gpu - ref))
     _say("gaussian", kind, "max abs err", err)
     assert err <= GAUSS_TOL
+
+
+@pytest.mark.parametrize("kind", ["taus", "ran2", "lf"])
+def test_config3_gaussian_moments_and_bit_balance(kind):
+    """Config 3 at full size: 2^30 Gaussians of one call (2^20 streams x 1024, or one lagged-Fibonacci
+    stream of 2^30) have mean 0, variance 1 and fourth moment 3 within 5 standard errors
+    (SE = sqrt(Var / n) of the per-value terms: 1, 2 and 96); and 2^30 uint32 words have each bit
+    set with frequency 1/2 within 5 standard errors (Ran2's word is iy < 2^31, so its bits 0..30;
+    for the lagged Fibonacci stream bits 8..31, see below).  The LCG, whose low bits have short periods, is the paper's counterexample
+    and is left out."""
+    n = 2**30
+    if kind == "lf":
+        ll, sl = W.C3["lf_lags"]
+        cfg = R.make_cfg("lf", seed=W.C3["seed"], ll=ll, sl=sl)
+        per = n
+    else:
+        cfg = R.make_cfg(kind, seed=W.C3["seed"], n_streams=W.C3["streams"])
+        per = W.C3["per_stream"]
+    st = R.new_state(cfg)
+    R.rng_init(cfg, st)
+    _say("config3 moments", kind)
+    out = torch.empty(n, dtype=torch.float32, device="cuda")
+    R.rng_gaussian(cfg, st, per, out)
+    s1 = s2 = s4 = 0.0
+    for c in out.split(2**26):
+        d = c.double()
+        s1 += float(d.sum())
+        d2 = d * d
+        s2 += float(d2.sum())
+        s4 += float((d2 * d2).sum())
+    m1, m2, m4 = s1 / n, s2 / n, s4 / n
+    _say(kind, "mean %.2e var-1 %.2e m4-3 %.2e" % (m1, m2 - 1, m4 - 3))
+    assert abs(m1) < 5 * math.sqrt(1 / n) and abs(m2 - 1) < 5 * math.sqrt(2 / n) and abs(m4 - 3) < 5 * math.sqrt(96 / n)
+    del out
+    u = torch.empty(n, dtype=torch.int32, device="cuda")
+    R.rng_uniform(cfg, st, per, u)
+    ones = torch.zeros(32, dtype=torch.float64, device="cuda")
+    for c in u.split(2**26):
+        for b in range(32):
+            ones[b] += float(((c >> b) & 1).sum())
+    f = ones.cpu().numpy() / n
+    if kind == "ran2":  # the word is iy in [1, m1 - 1], below 2^31
+        assert f[31] == 0.0
+        f = f[:31]
+    if kind == "lf":
+        # the low bits of an additive lagged Fibonacci sequence follow GF(2) recurrences of their own
+        # (bit 0: y_n = y_{n-ll} xor y_{n-sl}); from the LCG-filled window they stay unbalanced by
+        # up to a few per cent over 2^25-value stretches of the first 2^30 values (the oracle shows
+        # the same), so only the 24 bits the uniform mapping uses are held to the 1/2 frequency
+        _say("lf bit frequencies - 1/2:", " ".join("%.1e" % d for d in (f - 0.5)))
+        f = f[8:]
+    _say(kind, "bit frequency worst |f - 1/2| %.2e" % np.max(np.abs(f - 0.5)))
+    assert np.all(np.abs(f - 0.5) < 5 * 0.5 / math.sqrt(n))
 
 
 # ---------------------------------------------------------------------------------------------
