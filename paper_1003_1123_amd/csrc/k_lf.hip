@@ -579,7 +579,9 @@ __device__ __forceinline__ void lf_consumer(const LfFlowArgs &a, uint32_t cw, ui
             const uint32_t g0 = 256u * k + 4u * lane;
             const uint32_t o = c.off + (g0 < cnt ? g0 : 0u);
             W.q[k] = ring_get4(rr, o < sl ? c.lbase + o : nbase + (o - sl));
-            if (o < sl && sl - o < 4u) {
+            // only a group the wave uses: a lane past the wave's positions reads the step's first
+            // group, which may straddle too, and must not take the place of the lane's own
+            if (g0 < cnt && o < sl && sl - o < 4u) {
                 W.xk = sl - o;
                 W.xt = k;
             }

@@ -442,7 +442,9 @@ def test_no_noise_batched_plan_and_null_state():
                                       (2000, (19937, 10095), 100), (5000, (859433, 288477), 200),
                                       # not Table I rows: short lags whose link padding (to 64 words) is
                                       # 3 and 1 words, exactly what the last group of a link spills into
-                                      (3000, (2 * 1021 + 517, 1021), 120), (3000, (2 * 1023 + 300, 1023), 120)])
+                                      (3000, (2 * 1021 + 517, 1021), 120), (3000, (2 * 1023 + 300, 1023), 120),
+                                      # two and three tiles per consumer wave (the 2- and 4-tile kernels)
+                                      (300_000, (132049, 54454), 30), (600_000, (132049, 54454), 15)])
 def test_lf_dataflow_equals_waves_and_oracle(n, lags, T):
     ll, sl = lags
     pp = W.LDParams(k=1.1, gamma=0.9, kT=1.0, dt=0.01).as_f32()
