@@ -62,9 +62,9 @@ LF_MEASURED_PEAK_GBS = 8130.0
 # which the build records in kernel_isa.json; otherwise the traffic is reported as null.
 COUNTER_TRAFFIC = {
     "lf_pc_kernel": {
-        "isa_sha256": "22bf57e288f5114daacfeb4c98fe10b873fddb3d979a652c62a1229c02a6e043",
-        # FETCH_SIZE 160613349.1875 KiB x (2^20 / 524308.0625), WRITE_SIZE 158418493.40625 KiB x (2^20 / 1048576)
-        "fetch_bytes": 328923552487, "write_bytes": 162220537248,
+        "isa_sha256": "7abbdbbbb4800e4893ac8e59edd9a0011f7616a8ed097ca6c080ced69b677755",
+        # FETCH_SIZE 160337301.9375 KiB x (2^20 / 524308.75), WRITE_SIZE 158418602.0625 KiB x (2^20 / 1048576)
+        "fetch_bytes": 328357798792, "write_bytes": 162220648512,
     },
 }
 
