@@ -443,8 +443,11 @@ def test_no_noise_batched_plan_and_null_state():
                                       # not Table I rows: short lags whose link padding (to 64 words) is
                                       # 3 and 1 words, exactly what the last group of a link spills into
                                       (3000, (2 * 1021 + 517, 1021), 120), (3000, (2 * 1023 + 300, 1023), 120),
-                                      # two and three tiles per consumer wave (the 2- and 4-tile kernels)
-                                      (300_000, (132049, 54454), 30), (600_000, (132049, 54454), 15)])
+                                      # two, three and five tiles per consumer wave (the 2-, 4- and 8-tile
+                                      # kernels); the last two runs each hold a step window that starts
+                                      # 2 words before a link's end, so its first group straddles it
+                                      (300_000, (132049, 54454), 30), (600_000, (132049, 54454), 15),
+                                      (1_000_000, (132049, 54454), 5)])
 def test_lf_dataflow_equals_waves_and_oracle(n, lags, T):
     ll, sl = lags
     pp = W.LDParams(k=1.1, gamma=0.9, kT=1.0, dt=0.01).as_f32()
