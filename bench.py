@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 METRIC = "oscillator-steps/s fused LD+RNG; Gaussians/s; plain vs batched/adjoint"
 GENERATORS = ("taus", "ran2", "lf")
 
-# Work per oscillator-step (the counting is explained in the design doc).
+# Work per oscillator-step.
 # Taus and Ran2 are bound by vector-ALU issue: the lane-instructions that the compiled step loop of
 # ld_run_kernel (underdamped scheme, gfx950) issues per oscillator-step, LDS accesses not counted.
 VALU_PER_OSC_STEP = {"taus": 117, "ran2": 126}
@@ -339,8 +339,8 @@ def extra_config4(R, W, torch):
              for i, e in enumerate(ens_list)]
     ens, n_ens = R.make_ensembles(specs)
     cfg = R.make_cfg("taus", n_streams=n_total)
-    tune = R.ld_autotune(cfg, ens, n_ens, n_total, c4["steps"], os.path.join(ROOT, "gpurun_out", "autotune.txt")
-                         if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None)
+    # RNGLD_AUTOTUNE_CACHE names a file that keeps the chosen launch shape between runs (none by default)
+    tune = R.ld_autotune(cfg, ens, n_ens, n_total, c4["steps"], os.environ.get("RNGLD_AUTOTUNE_CACHE") or None)
     st = R.new_state(cfg)
     x = torch.zeros(3 * n_total, dtype=torch.float32, device="cuda")
     v = torch.zeros_like(x)
@@ -552,8 +552,9 @@ def extras(R, W, torch, only=()):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (each GPU would run "
-              "its own oscillators; see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (each GPU would run "
+              "its own range of oscillators, with one all-reduce of the observables). Run with --gpus 1.",
+              file=sys.stderr)
         sys.exit(2)
     import torch
 
