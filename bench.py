@@ -49,6 +49,10 @@ LF_ALGO_BYTES_PER_OSC_STEP = 4 * 12
 # and written, and the generator state: Taus 4 words read and written; Ran2 its 3 words read and
 # written plus, for each of the 4 draws, the one table entry the draw selects (read and written).
 STEP_BYTES_PER_OSC_STEP = {"taus": 2 * 4 * 4 + 48, "ran2": 2 * 3 * 4 + 2 * 4 * 4 + 48, "none": 48}
+# What the memory system moves for the Ran2 step at 128-byte lines: a line holds one table slot of 32
+# streams and is left alone only if none of them selects that slot in its 4 draws, (7/8)^32 = 1.4%
+# of lines, so the whole 128-byte table row of each stream is read and written.
+STEP_LINE_BYTES_RAN2 = 2 * 3 * 4 + 2 * 32 * 4 + 48
 LF_WAVE_XV_BYTES_PER_OSC_STEP = 48
 HBM_PEAK_GBS = 8000.0
 # Measured peak for the lagged-Fibonacci run's traffic: device-scope 16-byte loads and stores, two
@@ -97,7 +101,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", default="", help="comma list of generators (profiling runs)")
-    ap.add_argument("--extras", default="", help="comma list of extras to run (profiling runs; default all)")
+    ap.add_argument("--extras", default="", help="comma list of extras to run (profiling runs; default: all but step_protocol)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (a plain copy of known size, for scaling "
                          "hardware byte counters)")
@@ -534,11 +538,41 @@ def extra_fig6_breakdown(R, W, torch, cpu=True):
             "cpu": "FP64 oracle, one thread, %s oscillator-steps per point" % "about 2e5"}
 
 
+def extra_step_protocol(R, W, torch):
+    """The one-launch-per-step protocol alone at N = 10^6: 50 eager ld_step launches per kind, for
+    counter runs that need the step kernels without graph replays around them."""
+    N, T = 10**6, 50
+    pp = W.C2["params"].as_f32()
+    p = R.make_params(pp.m, pp.k, pp.gamma, pp.kT, pp.dt)
+    x = torch.zeros(3 * N, dtype=torch.float32, device="cuda")
+    v = torch.zeros_like(x)
+    out = {"N": N, "launches": T, "us_per_launch": {}}
+    for kind in ("taus", "ran2", "none"):
+        cfg = R.make_cfg(kind, seed=W.C2["seed"], n_streams=N)
+        st = R.new_state(cfg)
+        R.rng_init(cfg, st)
+        R.ld_step(cfg, st, p, N, x, v)
+        a, b = _ev(torch)
+        a.record()
+        for _ in range(T):
+            R.ld_step(cfg, st, p, N, x, v)
+        b.record()
+        torch.cuda.synchronize()
+        out["us_per_launch"][kind] = a.elapsed_time(b) * 1e3 / T
+        out.setdefault("GBps_algorithmic", {})[kind] = (STEP_BYTES_PER_OSC_STEP[kind] * N /
+                                                        (out["us_per_launch"][kind] * 1e-6) / 1e9)
+        del st
+    out["GBps_ran2_whole_lines"] = STEP_LINE_BYTES_RAN2 * N / (out["us_per_launch"]["ran2"] * 1e-6) / 1e9
+    return out
+
+
 def extras(R, W, torch, only=()):
     out = {}
+    named_only = {"step_protocol": extra_step_protocol}  # run only when asked for by name
     for name, fn in (("config3_bare_generators", extra_config3), ("config4_batched", extra_config4),
-                     ("config5_adjoint", extra_config5), ("fig6_breakdown", extra_fig6_breakdown)):
-        if only and name not in only:
+                     ("config5_adjoint", extra_config5), ("fig6_breakdown", extra_fig6_breakdown),
+                     *named_only.items()):
+        if (only and name not in only) or (not only and name in named_only):
             continue
         try:
             out[name] = fn(R, W, torch)

@@ -69,3 +69,8 @@ def test_step_protocol_bytes():
     assert bench.STEP_BYTES_PER_OSC_STEP["none"] == 48
     assert bench.STEP_BYTES_PER_OSC_STEP["taus"] == 48 + 2 * 16
     assert bench.STEP_BYTES_PER_OSC_STEP["ran2"] == 48 + 2 * 12 + 2 * 4 * 4
+
+
+def test_ran2_step_line_bytes():
+    # the three state words and the whole 32-entry table row in and out, plus x and v
+    assert bench.STEP_LINE_BYTES_RAN2 == 2 * 12 + 2 * 128 + 48 == 328
