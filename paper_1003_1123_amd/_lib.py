@@ -159,6 +159,13 @@ def _nbytes(t: torch.Tensor) -> int:
     return t.numel() * t.element_size()
 
 
+def _obs_len(obs, n_ens: int, n_steps: int) -> int:
+    """Doubles the library writes to d_obs: [n_ens][n_steps / stride + 1][NOBS]."""
+    if obs is None or obs.stride == 0:
+        return 0
+    return n_ens * (n_steps // obs.stride + 1) * NOBS
+
+
 # ---------------------------------------------------------------------------------------------
 # entry points
 
@@ -218,7 +225,8 @@ def ld_run(cfg: Cfg, state: torch.Tensor, ens, n_ens: int, n_total: int, n_steps
     if ws is None:
         ws = torch.empty(max(ld_workspace_bytes(cfg, ens, n_ens, n_total, n_steps, obs), 256), dtype=torch.uint8,
                          device=x.device)
-    d_obs = _dev(out_obs, torch.float64, "out_obs") if out_obs is not None else None
+    d_obs = (_dev(out_obs, torch.float64, "out_obs", _obs_len(obs, n_ens, n_steps)) if out_obs is not None
+             else None)
     _check(lib.ld_run(C.byref(cfg), _dev(state, torch.uint8, "state"), _nbytes(state), ens, n_ens, n_total, n_steps,
                       _dev(x, torch.float32, "x", 3 * n_total), _dev(v, torch.float32, "v", 3 * n_total),
                       C.byref(obs) if obs else None, d_obs, _dev(ws, torch.uint8, "ws"), _nbytes(ws), _stream()),
@@ -268,7 +276,8 @@ class Plan:
                              dtype=torch.uint8, device=x.device)
         self._keep = (cfg, state, ens, x, v, obs, out_obs, ws)
         self._h = C.c_void_p()
-        d_obs = _dev(out_obs, torch.float64, "out_obs") if out_obs is not None else None
+        d_obs = (_dev(out_obs, torch.float64, "out_obs", _obs_len(obs, n_ens, n_steps)) if out_obs is not None
+                 else None)
         _check(lib.ld_plan_create(C.byref(cfg), _dev(state, torch.uint8, "state"), _nbytes(state), ens, n_ens,
                                   n_total, n_steps, _dev(x, torch.float32, "x", 3 * n_total),
                                   _dev(v, torch.float32, "v", 3 * n_total), C.byref(obs) if obs else None, d_obs,

@@ -193,3 +193,11 @@ def test_adjoint_sizing_and_validation():
     ens0, n0 = R.make_ensembles([(0, 1000, p0, 1)])
     with pytest.raises(R.RngldError):
         R.ld_adjoint_workspace_bytes(c, ens0, n0, 1000, 2000, loss)
+
+
+def test_observable_buffer_length_follows_the_header():
+    # double[n_ens][n_steps / stride + 1][6]
+    assert R._obs_len(R.Obs(stride=10, t0=500), 1, 1000) == 101 * 6
+    assert R._obs_len(R.Obs(stride=100, t0=0), 3, 250) == 3 * 3 * 6
+    assert R._obs_len(None, 4, 1000) == 0
+    assert R.NOBS == 6
