@@ -143,6 +143,13 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _ens(ens, n_ens: int):
+    """The host ensemble table, checked to hold n_ens entries (the library reads that many)."""
+    if n_ens < 0 or (n_ens > 0 and (ens is None or len(ens) < n_ens)):
+        have = None if ens is None else len(ens)
+        raise ValueError("the ensemble table holds %s entries < n_ens = %d" % (have, n_ens))
+
+
 def _dev(t: torch.Tensor, dtype, name: str, min_numel: int = 0):
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError("%s must be a device tensor" % name)
@@ -185,6 +192,7 @@ def rng_init(cfg: Cfg, state: torch.Tensor):
 
 
 def rng_init_ensembles(cfg: Cfg, state: torch.Tensor, ens, n_ens: int):
+    _ens(ens, n_ens)
     _check(lib.rng_init_ensembles(C.byref(cfg), _dev(state, torch.uint8, "state"), _nbytes(state), ens, n_ens,
                                   _stream()), "rng_init_ensembles")
 
@@ -213,6 +221,7 @@ def ld_step(cfg: Cfg, state: torch.Tensor, params: Params, n: int, x: torch.Tens
 
 def ld_workspace_bytes(cfg: Cfg, ens, n_ens: int, n_total: int, n_steps: int, obs: Obs | None = None) -> int:
     out = C.c_size_t()
+    _ens(ens, n_ens)
     _check(lib.ld_workspace_bytes(C.byref(cfg), ens, n_ens, n_total, n_steps, C.byref(obs) if obs else None,
                                   C.byref(out)), "ld_workspace_bytes")
     return out.value
@@ -227,6 +236,7 @@ def ld_run(cfg: Cfg, state: torch.Tensor, ens, n_ens: int, n_total: int, n_steps
                          device=x.device)
     d_obs = (_dev(out_obs, torch.float64, "out_obs", _obs_len(obs, n_ens, n_steps)) if out_obs is not None
              else None)
+    _ens(ens, n_ens)
     _check(lib.ld_run(C.byref(cfg), _dev(state, torch.uint8, "state"), _nbytes(state), ens, n_ens, n_total, n_steps,
                       _dev(x, torch.float32, "x", 3 * n_total), _dev(v, torch.float32, "v", 3 * n_total),
                       C.byref(obs) if obs else None, d_obs, _dev(ws, torch.uint8, "ws"), _nbytes(ws), _stream()),
@@ -262,6 +272,7 @@ def ld_set_tuning(kind, block=256, osc_per_thread=1, steps_per_launch=0, blocks_
 
 def ld_autotune(cfg: Cfg, ens, n_ens: int, n_total: int, n_steps: int, cache_path: str | None = None) -> Tuning:
     t = Tuning()
+    _ens(ens, n_ens)
     _check(lib.ld_autotune(C.byref(cfg), ens, n_ens, n_total, n_steps,
                            cache_path.encode() if cache_path else None, C.byref(t)), "ld_autotune")
     return t
@@ -278,6 +289,7 @@ class Plan:
         self._h = C.c_void_p()
         d_obs = (_dev(out_obs, torch.float64, "out_obs", _obs_len(obs, n_ens, n_steps)) if out_obs is not None
                  else None)
+        _ens(ens, n_ens)
         _check(lib.ld_plan_create(C.byref(cfg), _dev(state, torch.uint8, "state"), _nbytes(state), ens, n_ens,
                                   n_total, n_steps, _dev(x, torch.float32, "x", 3 * n_total),
                                   _dev(v, torch.float32, "v", 3 * n_total), C.byref(obs) if obs else None, d_obs,
@@ -307,12 +319,14 @@ def ld_ckpt_bytes(cfg: Cfg, n_total: int, n_steps: int, K: int) -> int:
 
 def ld_adjoint_workspace_bytes(cfg: Cfg, ens, n_ens: int, n_total: int, n_steps: int, loss: Loss) -> int:
     out = C.c_size_t()
+    _ens(ens, n_ens)
     _check(lib.ld_adjoint_workspace_bytes(C.byref(cfg), ens, n_ens, n_total, n_steps, C.byref(loss), C.byref(out)),
            "ld_adjoint_workspace_bytes")
     return out.value
 
 
 def ld_run_ckpt(cfg: Cfg, state, ens, n_ens, n_total, n_steps, x, v, loss: Loss, ckpt, out_loss, ws):
+    _ens(ens, n_ens)
     _check(lib.ld_run_ckpt(C.byref(cfg), _dev(state, torch.uint8, "state"), _nbytes(state), ens, n_ens, n_total,
                            n_steps, _dev(x, torch.float32, "x", 3 * n_total), _dev(v, torch.float32, "v", 3 * n_total),
                            C.byref(loss), _dev(ckpt, torch.uint8, "ckpt"), _nbytes(ckpt),
@@ -321,6 +335,7 @@ def ld_run_ckpt(cfg: Cfg, state, ens, n_ens, n_total, n_steps, x, v, loss: Loss,
 
 
 def ld_run_backward(cfg: Cfg, ckpt, ens, n_ens, n_total, n_steps, loss: Loss, out_grad, ws):
+    _ens(ens, n_ens)
     _check(lib.ld_run_backward(C.byref(cfg), _dev(ckpt, torch.uint8, "ckpt"), _nbytes(ckpt), ens, n_ens, n_total,
                                n_steps, C.byref(loss), _dev(out_grad, torch.float64, "out_grad", 3 * n_ens),
                                _dev(ws, torch.uint8, "ws"), _nbytes(ws), _stream()), "ld_run_backward")

@@ -201,3 +201,17 @@ def test_observable_buffer_length_follows_the_header():
     assert R._obs_len(R.Obs(stride=100, t0=0), 3, 250) == 3 * 3 * 6
     assert R._obs_len(None, 4, 1000) == 0
     assert R.NOBS == 6
+
+
+def test_ensemble_table_shorter_than_n_ens_is_rejected_before_the_library():
+    p = R.make_params(1.0, 1.0, 1.0, 1.0, 0.01)
+    ens, n = R.make_ensembles([(0, 64, p, 1), (64, 64, p, 2)])
+    assert n == 2
+    R._ens(ens, 2)
+    R._ens(ens, 0)
+    with pytest.raises(ValueError):
+        R._ens(ens, 3)
+    with pytest.raises(ValueError):
+        R._ens(None, 1)
+    with pytest.raises(ValueError):
+        R.ld_workspace_bytes(R.make_cfg("taus", n_streams=128), ens, 3, 128, 10)
