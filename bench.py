@@ -518,6 +518,9 @@ def extra_fig6_breakdown(R, W, torch, cpu=True):
             # bytes each launch moves per oscillator-step: the generator state and x, v in and out
             row["step_protocol_graph_GBps_" + kind] = (STEP_BYTES_PER_OSC_STEP[kind] * N * T /
                                                        (row["step_protocol_graph_ms_" + kind] / 1e3) / 1e9)
+            if kind == "ran2":
+                row["step_protocol_graph_GBps_ran2_whole_lines"] = (
+                    STEP_LINE_BYTES_RAN2 * N * T / (row["step_protocol_graph_ms_ran2"] / 1e3) / 1e9)
             del g, st
         if cpu:
             import oracle as orc
