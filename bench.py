@@ -32,7 +32,7 @@ GENERATORS = ("taus", "ran2", "lf")
 # ld_run_kernel (underdamped scheme, gfx950) issues per oscillator-step, LDS accesses not counted.
 VALU_PER_OSC_STEP = {"taus": 117, "ran2": 126}
 # Measured bound of those loops: each instruction class at the issue rate the VALU probe measured
-# for it (csrc/probes/valu_rates.hip), times added (transcendentals do not overlap other VALU work),
+# for it (profiles/valu_issue_rates.md), times added (transcendentals do not overlap other VALU work),
 # except that a 32-bit multiply interleaved with other integer work costs what the probe's mixed
 # multiply + xor kernel shows (1.2e-14 s of chip time per lane-operation, against 3.0e-14 alone);
 # in oscillator-steps/s.  Class counts per oscillator-step, Taus / Ran2: 7 / 7 transcendental,
@@ -57,7 +57,7 @@ LF_WAVE_XV_BYTES_PER_OSC_STEP = 48
 HBM_PEAK_GBS = 8000.0
 # Measured peak for the lagged-Fibonacci run's traffic: device-scope 16-byte loads and stores, two
 # loads per store, over a 32 MB region, stores 256-byte aligned and loads 13 words off (as the run's
-# long-lag reads), from the wide-access probe (csrc/probes/wide_access.hip, mode 4).
+# long-lag reads), from the wide-access measurement (profiles/wide_access.md, mode 4).
 LF_MEASURED_PEAK_GBS = 8130.0
 # HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch) at the config-2
 # workload, scaled by what the same counters read for a plain 1 GiB device copy (FETCH_SIZE 0.5 GiB:
