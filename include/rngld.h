@@ -215,6 +215,27 @@ RNGLD_API int ld_run(const rngld_cfg *cfg, void *d_state, size_t state_bytes, co
            uint64_t n_total, uint32_t n_steps, float *d_x, float *d_v, const ld_obs *obs, double *d_obs,
            void *d_ws, size_t ws_bytes, void *stream);
 
+/*
+ * Allocation-free ld_run, for callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  The same run as ld_run with the
+ * same arguments, results and tuning, bit for bit, except that the workspace is not the caller's:
+ * the library keeps one array of RNGLD_NOALLOC_SCRATCH_BYTES device bytes on every GPU it runs
+ * on, from the first call on that GPU until the process ends, and the call allocates and frees
+ * nothing.
+ *  d_status : NULL, or caller-owned device memory for two uint32 words that receive what ld_run
+ *             leaves in its workspace's first eight bytes (status word, lagged-Fibonacci path).
+ * A run whose ld_workspace_bytes() exceeds RNGLD_NOALLOC_SCRATCH_BYTES is rejected with
+ * RNGLD_ESIZE before anything is enqueued (e.g. long runs of many oscillators with observables;
+ * a lagged-Fibonacci run with Table I's largest lags and no observables fits).
+ * Every call on one GPU shares that GPU's array and leaves its contents behind; the run clears
+ * what it needs cleared.  Calls that overlap in time on one GPU (other streams, other threads)
+ * race on the array: order them on one stream, or use ld_run with separate workspaces.
+ */
+#define RNGLD_NOALLOC_SCRATCH_BYTES (48u * 1024u * 1024u)
+RNGLD_API int ld_run_noalloc(const rngld_cfg *cfg, void *d_state, size_t state_bytes, const ld_ensemble *h_ens,
+                   uint32_t n_ens, uint64_t n_total, uint32_t n_steps, float *d_x, float *d_v, const ld_obs *obs,
+                   double *d_obs, uint32_t *d_status, void *stream);
+
 /* ---- tuning, hipGraph plans, autotuner ------------------------------------------------------ */
 /*
  * Launch shape of the per-thread LD kernels.  block: threads per block (64, 128, 256 or 512);

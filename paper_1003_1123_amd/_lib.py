@@ -78,6 +78,7 @@ def _load():
         "ld_step": [P(Cfg), vp, sz, P(Params), u64, vp, vp, vp],
         "ld_workspace_bytes": [P(Cfg), P(Ensemble), u32, u64, u32, P(Obs), P(sz)],
         "ld_run": [P(Cfg), vp, sz, P(Ensemble), u32, u64, u32, vp, vp, P(Obs), vp, vp, sz, vp],
+        "ld_run_noalloc": [P(Cfg), vp, sz, P(Ensemble), u32, u64, u32, vp, vp, P(Obs), vp, vp, vp],
         "ld_get_tuning": [i32, P(Tuning)],
         "ld_set_tuning": [i32, P(Tuning)],
         "ld_autotune": [P(Cfg), P(Ensemble), u32, u64, u32, C.c_char_p, P(Tuning)],
@@ -103,7 +104,7 @@ def _load():
 lib = _load()
 
 ENTRY_POINTS = ("rngld_state_bytes", "rng_init", "rng_init_ensembles", "rng_uniform", "rng_gaussian", "ld_step",
-                "ld_workspace_bytes", "ld_run", "ld_get_tuning", "ld_set_tuning", "ld_autotune", "ld_plan_create",
+                "ld_workspace_bytes", "ld_run", "ld_run_noalloc", "ld_get_tuning", "ld_set_tuning", "ld_autotune", "ld_plan_create",
                 "ld_plan_launch", "ld_plan_destroy", "ld_ckpt_bytes", "ld_adjoint_workspace_bytes", "ld_run_ckpt",
                 "ld_run_backward", "rng_box_muller", "rngld_last_error", "rngld_version")
 
@@ -242,6 +243,24 @@ def ld_run(cfg: Cfg, state: torch.Tensor, ens, n_ens: int, n_total: int, n_steps
                       C.byref(obs) if obs else None, d_obs, _dev(ws, torch.uint8, "ws"), _nbytes(ws), _stream()),
            "ld_run")
     return ws
+
+
+NOALLOC_SCRATCH_BYTES = 48 * 1024 * 1024  # RNGLD_NOALLOC_SCRATCH_BYTES
+
+
+def ld_run_noalloc(cfg: Cfg, state: torch.Tensor, ens, n_ens: int, n_total: int, n_steps: int, x: torch.Tensor,
+                   v: torch.Tensor, obs: Obs | None = None, out_obs: torch.Tensor | None = None,
+                   status: torch.Tensor | None = None):
+    """ld_run with the library's own per-GPU workspace (nothing is allocated).  `status`: None or a
+    device tensor of two 32-bit words that receives the status and lagged-Fibonacci path words."""
+    d_obs = (_dev(out_obs, torch.float64, "out_obs", _obs_len(obs, n_ens, n_steps)) if out_obs is not None
+             else None)
+    d_status = _dev(status, (torch.int32, torch.uint32), "status", 2) if status is not None else None
+    _ens(ens, n_ens)
+    _check(lib.ld_run_noalloc(C.byref(cfg), _dev(state, torch.uint8, "state"), _nbytes(state), ens, n_ens, n_total,
+                              n_steps, _dev(x, torch.float32, "x", 3 * n_total),
+                              _dev(v, torch.float32, "v", 3 * n_total), C.byref(obs) if obs else None, d_obs,
+                              d_status, _stream()), "ld_run_noalloc")
 
 
 def ws_status(ws: torch.Tensor) -> int:

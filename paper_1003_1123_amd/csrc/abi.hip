@@ -356,14 +356,15 @@ int try_lf_flow(const Gen &g, void *d_state, const RunLayout &L, uint32_t n_step
     return 1;
 }
 
+// status_words: where the status and path words go (NULL: the workspace's first eight bytes)
 int enqueue_run(const Gen &g, void *d_state, const RunLayout &L, const ld_tuning &t, uint64_t n_total,
                 uint32_t n_steps, float *d_x, float *d_v, const ld_obs *obs, double *d_obs, void *d_ws,
-                hipStream_t st, bool upload, bool allow_flow = true) {
+                hipStream_t st, bool upload, bool allow_flow = true, uint32_t *status_words = nullptr) {
     uint8_t *ws = static_cast<uint8_t *>(d_ws);
     EnsDev *d_ens = reinterpret_cast<EnsDev *>(ws + L.off_ens);
     double *partials = reinterpret_cast<double *>(ws + L.off_partials);
     float *t0buf = reinterpret_cast<float *>(ws + L.off_t0);
-    uint32_t *status = reinterpret_cast<uint32_t *>(ws);
+    uint32_t *status = status_words ? status_words : reinterpret_cast<uint32_t *>(ws);
     const uint32_t stride = obs ? obs->stride : 0, t0 = obs ? obs->t0 : 0;
     RNGLD_TRY_HIP(launch_fill_u32(status, 2, 0u, st));  // status, path
 
@@ -725,6 +726,66 @@ int ld_run(const rngld_cfg *cfg, void *d_state, size_t state_bytes, const ld_ens
     if (L.P && !d_obs) return fail(RNGLD_EINVAL, "observables requested but d_obs is NULL");
     return enqueue_run(g, d_state, L, t, n_total, n_steps, d_x, d_v, obs, d_obs, d_ws,
                        static_cast<hipStream_t>(stream), true);
+}
+
+}  // extern "C"
+
+// ---- allocation-free ld_run ---------------------------------------------------------------------
+// The workspace of ld_run_noalloc: a library-owned device array, one copy on every GPU the library
+// runs on, kept until the process ends.  In host code `scratch` names a host-side stand-in, not
+// device memory: host code uses only the device address that hipGetSymbolAddress returns for the
+// current device (scratch_address below), never the array's name.
+static __device__ __align__(256) uint8_t scratch[RNGLD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of the current GPU's copy of `scratch`, looked up on the first call on that GPU
+int scratch_address(void **out) {
+    int dev = -1;
+    RNGLD_TRY_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(RNGLD_ENOTSUP, "device %d: the allocation-free entry point serves devices 0..%d", dev,
+                    kMaxDevices - 1);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(RNGLD_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return RNGLD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ld_run_noalloc(const rngld_cfg *cfg, void *d_state, size_t state_bytes, const ld_ensemble *h_ens, uint32_t n_ens,
+                   uint64_t n_total, uint32_t n_steps, float *d_x, float *d_v, const ld_obs *obs, double *d_obs,
+                   uint32_t *d_status, void *stream) {
+    Gen g;
+    RNGLD_TRY(check_cfg(cfg, &g));
+    RNGLD_TRY(check_state(g, d_state, state_bytes));
+    RNGLD_TRY(check_run_args(g, h_ens, n_ens, n_total, n_steps, obs));
+    const ld_tuning t = current_tuning(g.kind);
+    RunLayout L;
+    RNGLD_TRY(layout_run(g, h_ens, n_ens, n_total, n_steps, obs, t, &L));
+    if (L.bytes > RNGLD_NOALLOC_SCRATCH_BYTES)
+        return fail(RNGLD_ESIZE, "this run needs %zu bytes of workspace, more than the %zu the allocation-free "
+                                 "entry point holds; call ld_run with a workspace of ld_workspace_bytes()",
+                    L.bytes, static_cast<size_t>(RNGLD_NOALLOC_SCRATCH_BYTES));
+    if (n_total && (!d_x || !d_v)) return fail(RNGLD_EINVAL, "x or v is NULL");
+    if (L.P && !d_obs) return fail(RNGLD_EINVAL, "observables requested but d_obs is NULL");
+    void *ws = nullptr;
+    RNGLD_TRY(scratch_address(&ws));
+    return enqueue_run(g, d_state, L, t, n_total, n_steps, d_x, d_v, obs, d_obs, ws, static_cast<hipStream_t>(stream),
+                       true, true, d_status);
 }
 
 int ld_get_tuning(int32_t kind, ld_tuning *out) {
