@@ -82,6 +82,10 @@ extern "C" {
  *                position j * L of the sequence from word 0 of stream 0.  Eq. 1 has a single cycle
  *                of 2^32, so every stream is a shift of the same sequence; L = 4 makes stream j + 1
  *                the same as stream j one LD step later (the inter-stream correlation of Fig. 4b).
+ *  lf_discard  : LF only, at most 2^40.  rng_init generates the first lf_discard values of the
+ *                sequence from the seeded window and drops them (a warm-up of the initial seeds of
+ *                Alg. 3): value n of the seeded state is then value lf_discard + n of the sequence
+ *                without discard.  0 (default) keeps the window as seeded.
  */
 typedef struct rngld_cfg {
     int32_t kind;
@@ -93,6 +97,7 @@ typedef struct rngld_cfg {
     uint64_t stream_base;
     uint64_t lf_ring;
     uint64_t lcg_leap;
+    uint64_t lf_discard;
 } rngld_cfg;
 
 /*
@@ -112,7 +117,8 @@ typedef struct rngld_cfg {
  */
 RNGLD_API int rngld_state_bytes(const rngld_cfg *cfg, size_t *bytes);
 
-/* Seed the state (Sec. III.B seeding, Alg. 2 initialisation for Ran2, Alg. 3 window for LF). */
+/* Seed the state (Sec. III.B seeding, Alg. 2 initialisation for Ran2, Alg. 3 window for LF, then
+ * lf_discard values of the LF sequence generated and dropped). */
 RNGLD_API int rng_init(const rngld_cfg *cfg, void *d_state, size_t state_bytes, void *stream);
 
 /*
@@ -152,6 +158,11 @@ RNGLD_API int rng_box_muller(const uint32_t *d_words, uint64_t n_pairs, float *d
  * scheme 1: overdamped, Eq. (5) of Sec. IV with xi = m gamma:
  *   x' = x - (k dt / xi) x + sqrt(2 kT dt / xi) g   (v untouched).
  * Requires m > 0, gamma > 0, k >= 0, kT >= 0, dt > 0, all finite.
+ * The step's coefficients (c = 1 - gamma dt, k dt / m, sqrt(2 gamma kT dt / m); for scheme 1
+ * k dt / xi and sqrt(2 kT dt / xi)) are computed in double precision from these binary32 values
+ * and rounded to binary32 once per call; so are the adjoint's partials dt / m, -dt and
+ * s / (2 gamma), s / (2 kT) with s the double-precision noise amplitude.  A run iterates the map
+ * with those rounded coefficients.
  */
 typedef struct ld_params {
     float m, k, gamma, kT, dt;
@@ -257,10 +268,19 @@ RNGLD_API int ld_get_tuning(int32_t kind, ld_tuning *out);
 RNGLD_API int ld_set_tuning(int32_t kind, const ld_tuning *t);
 
 /*
- * Pick the fastest tuning for this workload shape by timing candidate launch shapes on short
- * proxy runs, and install it with ld_set_tuning.  This is set-up code, not the hot path: it
- * allocates and frees its own scratch device memory and synchronises the device.  cache_path (may
- * be NULL) names a text cache keyed by device, kind and workload buckets.
+ * Pick the fastest tuning for this workload (the batched runs of config 4: many ensembles of
+ * uneven size) by measurement, and install it with ld_set_tuning:
+ *  1. block size x oscillators per thread x blocks per CU (0, 4, 8), each timed on a proxy run of
+ *     the same ensembles for min(n_steps, 128) steps in one launch;
+ *  2. steps per launch (0 = one launch, 2500, 1000, 500) for the chosen shape, each timed as a
+ *     hipGraph replay (as ld_plan_create records it) of a proxy run of min(n_steps, 2500) steps
+ *     (halved while it would exceed 2e11 oscillator-steps); the fastest wins, a single launch
+ *     unless splitting is at least 0.5% faster.
+ * Timing uses a private stream.  This is set-up code, not the hot path: it allocates and frees its
+ * own scratch device memory.  cache_path (may be NULL) names a text file of one line per workload,
+ * keyed by device (architecture and compute units), kind, n_total, n_ens, n_steps and a hash of
+ * every ensemble's size and scheme; a key found there is installed without measuring, a new
+ * measurement replaces the key's line (the file is rewritten through a temporary file).
  */
 RNGLD_API int ld_autotune(const rngld_cfg *cfg, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total,
                 uint32_t n_steps, const char *cache_path, ld_tuning *out);
@@ -278,7 +298,10 @@ RNGLD_API int ld_plan_destroy(rngld_plan *plan);
 /*
  * Loss L_e = mean over steps t_begin..t_end (1 <= t_begin <= t_end <= n_steps) of <x^2>_e (mean
  * over the ensemble's 3n coordinates of the positions after t steps); checkpoints every K steps.
- * flags: 0, or RNGLD_ADJ_REPLAY to make ld_run_backward use the replay path for every ensemble.
+ * This differentiates the paper's LD model (Sec. I; the oscillators of Sec. IV) with the noise
+ * held fixed; the paper itself computes no gradients.
+ * flags: any of RNGLD_ADJ_REPLAY (ld_run_backward uses the replay path for every ensemble) and
+ * RNGLD_ADJ_SPREAD (ld_run_backward also returns standard errors, see there).
  */
 typedef struct ld_loss {
     uint32_t t_begin;
@@ -288,6 +311,7 @@ typedef struct ld_loss {
 } ld_loss;
 
 #define RNGLD_ADJ_REPLAY 1u
+#define RNGLD_ADJ_SPREAD 2u
 
 /* Checkpoint buffer: ceil(n_steps/K) + 1 records, record c = state at step min(c*K, n_steps)
  * (the last record is the state at the end of the run):
@@ -306,19 +330,25 @@ RNGLD_API int ld_run_ckpt(const rngld_cfg *cfg, void *d_state, size_t state_byte
 /*
  * Reverse-mode pathwise gradient d_grad[n_ens][3] = (dL/dk, dL/dgamma, dL/dkT) (double) of the
  * losses of ld_run_ckpt; the noise of every step is regenerated bit-exactly.  d_ckpt is read only.
+ * With RNGLD_ADJ_SPREAD in loss->flags d_grad is [n_ens][6]: the three gradients, then the
+ * standard error of each, i.e. sd / sqrt(n) of the n per-oscillator contributions whose mean the
+ * gradient is (the oscillators are independent, so this is the sampling error of the gradient
+ * as an estimate of d E[L] / d theta).
  * Two paths, chosen per ensemble:
  *  - register-only (Hybrid Taus): each K-step segment is swept backward from the checkpoint at
  *    its end, running the generator backward with the inverse Tausworthe and LCG steps and the
- *    integrator backward (x = x' - dt v', v = (v' + (k dt/m) x - sig g) / (1 - gamma dt)); the
- *    checkpoint at the segment's start re-anchors the next segment.  Used when rounding errors
- *    cannot grow by more than 8 over K inverse steps (max over j <= K of the Frobenius norm of
- *    the inverse step matrix to the power j, for the ensemble's FP32 coefficients), e.g.
- *    gamma dt <= 0.02 at K = 100 and dt = 0.01.  No scratch.
+ *    integrator backward (x = x' - dt v', v = (v' + (k dt/m) x - sig g) / (1 - gamma dt)).  Used
+ *    when rounding errors cannot grow by more than 8 over K inverse steps (max over j <= K of the
+ *    Frobenius norm of the inverse step matrix to the power j, for the ensemble's FP32
+ *    coefficients), e.g. gamma dt <= 0.02 at K = 100 and dt = 0.01.  The segments of an
+ *    oscillator are swept concurrently, each from a zero adjoint at its end, and then joined
+ *    (the reverse recursion is linear with a constant step matrix), through a workspace record of
+ *    120 bytes per oscillator and segment.
  *  - replay: each segment is rerun forward from the checkpoint at its start into a scratch of
  *    9 floats per oscillator-step and swept backward from there (Ran2; Hybrid Taus otherwise or
  *    with RNGLD_ADJ_REPLAY).
- * ld_adjoint_workspace_bytes includes the scratch only when some ensemble takes the replay path,
- * so it depends on the ensembles' parameters and the flags.
+ * ld_adjoint_workspace_bytes includes each path's scratch only when some ensemble takes it, so it
+ * depends on the ensembles' parameters and the flags.
  */
 RNGLD_API int ld_run_backward(const rngld_cfg *cfg, const void *d_ckpt, size_t ckpt_bytes, const ld_ensemble *h_ens,
                     uint32_t n_ens, uint64_t n_total, uint32_t n_steps, const ld_loss *loss, double *d_grad,

@@ -68,6 +68,7 @@ def lib():
                 "orc_ran2_next": (i32, [vp]),
                 "orc_lf_seed": (None, [u64, u32, vp]),
                 "orc_lf_generate": (C.c_int, [u32, u32, vp, u64, vp]),
+                "orc_lf_seed_discard": (C.c_int, [u64, u32, u32, u64, vp]),
                 "orc_trinomial_irreducible": (C.c_int, [u32, u32]),
                 "orc_lfsr_period": (u64, [u32, u32, u64]),
                 "orc_u_open": (dbl, [u32]),
@@ -81,8 +82,11 @@ def lib():
                 "orc_ld_run": (C.c_int, [C.c_int, vp, u32, u32, u64, u32, dbl, dbl, dbl, dbl, dbl, C.c_int,
                                           vp, vp, u32, u32, vp]),
                 "orc_ld_forces": (C.c_int, [C.c_int, vp, u32, u32, u64, u32, vp]),
+                "orc_ld_run_lf_sampled": (C.c_int, [u32, u32, vp, u64, u32, dbl, dbl, dbl, dbl, dbl, C.c_int, vp,
+                                                     u64, vp, vp]),
                 "orc_ld_adjoint": (C.c_int, [C.c_int, vp, u64, u32, dbl, dbl, dbl, dbl, dbl, vp, vp, u32, u32,
                                               vp, vp]),
+                "orc_ld_adjoint_coef": (C.c_int, [C.c_int, vp, u64, u32, vp, vp, vp, vp, u32, u32, vp, vp]),
                 "orc_ld_loss": (C.c_int, [C.c_int, vp, u64, u32, dbl, dbl, dbl, dbl, dbl, vp, vp, u32, u32, vp]),
             }
             for name, (res, args) in sig.items():
@@ -229,10 +233,16 @@ def seed_states(kind, seed: int, streams, leap: int = 0) -> np.ndarray:
     return taus_seed(seed, streams) if kind == TAUS else ran2_seed(seed, streams)
 
 
-def lf_seed(seed: int, ll: int) -> np.ndarray:
-    """Window [ll] uint32: y_{-ll} .. y_{-1}."""
+def lf_seed(seed: int, ll: int, sl: int = 0, discard: int = 0) -> np.ndarray:
+    """Window [ll] uint32: y_{-ll} .. y_{-1}; with a discard D (needs sl), the window after the
+    first D values of the sequence are generated and dropped: y_{D-ll} .. y_{D-1}."""
     win = np.zeros(ll, dtype=np.uint32)
-    lib().orc_lf_seed(seed, ll, _p(win))
+    if discard:
+        rc = lib().orc_lf_seed_discard(seed, ll, sl, discard, _p(win))
+        if rc:
+            raise RuntimeError("orc_lf_seed_discard failed: %d" % rc)
+    else:
+        lib().orc_lf_seed(seed, ll, _p(win))
     return win
 
 
@@ -300,6 +310,20 @@ def ld_run(kind, states: np.ndarray, N: int, n_steps: int, params, x=None, v=Non
     return x, v, (obs[:P] if P else None)
 
 
+def ld_run_lf_sampled(win: np.ndarray, ll: int, sl: int, N: int, n_steps: int, params, ids, scheme: int = 0):
+    """The lagged-Fibonacci run of N oscillators from rest, following only oscillators `ids`
+    (ascending): returns (x[3, n], v[3, n]) of those; `win` advances by 4 N n_steps positions."""
+    m, k, g, kT, dt = _params(params)
+    ids = np.ascontiguousarray(ids, dtype=np.uint64)
+    n = ids.size
+    x = np.zeros((3, max(n, 1)))
+    v = np.zeros((3, max(n, 1)))
+    rc = lib().orc_ld_run_lf_sampled(ll, sl, _p(win), N, n_steps, m, k, g, kT, dt, scheme, _p(ids), n, _p(x), _p(v))
+    if rc:
+        raise RuntimeError("orc_ld_run_lf_sampled failed: %d" % rc)
+    return x[:, :n], v[:, :n]
+
+
 def ld_forces(kind, states: np.ndarray, N: int, n_steps: int, ll: int = 0, sl: int = 0) -> np.ndarray:
     """[n_steps, 3, N] Gaussian forces in the order an LD run consumes them."""
     kind = _kind(kind)
@@ -310,14 +334,26 @@ def ld_forces(kind, states: np.ndarray, N: int, n_steps: int, ll: int = 0, sl: i
     return g[:n_steps]
 
 
-def ld_adjoint(kind, states: np.ndarray, N: int, n_steps: int, params, t_begin: int, t_end: int, x0=None, v0=None):
-    """(L, [dL/dk, dL/dgamma, dL/dkT]) by the FP64 reverse sweep; states advance in place."""
+def ld_adjoint(kind, states: np.ndarray, N: int, n_steps: int, params, t_begin: int, t_end: int, x0=None, v0=None,
+               coef=None):
+    """(L, [dL/dk, dL/dgamma, dL/dkT]) by the FP64 reverse sweep; states advance in place.
+    coef: None (the step's coefficients and their partials follow from `params` in FP64), or
+    8 numbers (c, kap, sig, h, dkap/dk, dc/dgamma, dsig/dgamma, dsig/dkT) used as given."""
     kind = _kind(kind)
-    m, k, g, kT, dt = _params(params)
     x0 = np.zeros((3, N)) if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
     v0 = np.zeros((3, N)) if v0 is None else np.ascontiguousarray(v0, dtype=np.float64)
     loss = C.c_double()
     grad = np.zeros(3)
+    if coef is not None:
+        q = np.ascontiguousarray(coef, dtype=np.float64)
+        assert q.shape == (8,)
+        cq, dq = np.ascontiguousarray(q[:4]), np.ascontiguousarray(q[4:])
+        rc = lib().orc_ld_adjoint_coef(kind, _p(states), N, n_steps, _p(cq), _p(dq), _p(x0), _p(v0), t_begin, t_end,
+                                       C.byref(loss), _p(grad))
+        if rc:
+            raise RuntimeError("orc_ld_adjoint_coef failed: %d" % rc)
+        return loss.value, grad
+    m, k, g, kT, dt = _params(params)
     rc = lib().orc_ld_adjoint(kind, _p(states), N, n_steps, m, k, g, kT, dt, _p(x0), _p(v0), t_begin, t_end,
                               C.byref(loss), _p(grad))
     if rc:
@@ -336,3 +372,42 @@ def ld_loss(kind, states: np.ndarray, N: int, n_steps: int, params, t_begin: int
     if rc:
         raise RuntimeError("orc_ld_loss failed: %d" % rc)
     return loss.value
+
+
+# ---------------------------------------------------------------------------------------------
+# the adjoint over many oscillators on several processes
+
+def _adjoint_slice(args):
+    kind, seed, lo, hi, n_steps, params, t_begin, t_end, coef = args
+    L, g = ld_adjoint(kind, seed_states(kind, seed, np.arange(lo, hi)), hi - lo, n_steps, params, t_begin, t_end,
+                      coef=coef)
+    return hi - lo, L, g
+
+
+def ld_adjoint_split(kind, seed: int, N: int, n_steps: int, params, t_begin: int, t_end: int, workers: int = 0,
+                     coef=None):
+    """ld_adjoint of oscillators 0..N-1 of `seed` from rest, the oscillators split into contiguous
+    slices run by separate processes.  Every oscillator has its own stream and the loss and its
+    gradient are means over oscillators, so the split changes only the order of the final sum:
+    the result is the size-weighted mean of the slices' results.  workers = 0: one per available
+    core, at most 16."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    if workers <= 0:
+        try:
+            workers = len(os.sched_getaffinity(0))
+        except AttributeError:
+            workers = os.cpu_count() or 1
+        workers = max(1, min(workers, 16))
+    bounds = np.linspace(0, N, workers + 1).astype(np.int64)
+    coef = None if coef is None else [float(c) for c in coef]
+    jobs = [(kind, seed, int(bounds[i]), int(bounds[i + 1]), n_steps, params, t_begin, t_end, coef)
+            for i in range(workers) if bounds[i + 1] > bounds[i]]
+    build()
+    # an executor (not a pool) so that a worker that dies raises instead of being replaced
+    with cf.ProcessPoolExecutor(max_workers=len(jobs), mp_context=mp.get_context("spawn")) as ex:
+        parts = list(ex.map(_adjoint_slice, jobs))
+    L = sum(n * Lp for n, Lp, _ in parts) / N
+    g = sum(n * gp for n, _, gp in parts) / N
+    return L, g

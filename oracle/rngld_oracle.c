@@ -231,6 +231,18 @@ void orc_lf_seed(uint64_t seed, uint32_t ll, uint32_t *win)
     }
 }
 
+/* The window after a warm-up discard: seeded as above, then the first `discard` values of the
+ * sequence generated from it (Eq. 3) and dropped, so that win[i] = y_{discard-ll+i}.
+ * Pinned by: equality of the continued sequence with the undiscarded one shifted by `discard`,
+ * and the recurrence across the window, in the tests. */
+int orc_lf_generate(uint32_t ll, uint32_t sl, uint32_t *win, uint64_t count, uint32_t *out);
+
+int orc_lf_seed_discard(uint64_t seed, uint32_t ll, uint32_t sl, uint64_t discard, uint32_t *win)
+{
+    orc_lf_seed(seed, ll, win);
+    return orc_lf_generate(ll, sl, win, discard, NULL);
+}
+
 /* Generate count values of the sequence continuing from win; out may be NULL. */
 int orc_lf_generate(uint32_t ll, uint32_t sl, uint32_t *win, uint64_t count, uint32_t *out)
 {
@@ -562,6 +574,56 @@ int orc_ld_run(int kind, void *states, uint32_t ll, uint32_t sl, uint64_t N, uin
     return rc;
 }
 
+/*
+ * The lagged-Fibonacci LD run of orc_ld_run restricted to a few oscillators: the one sequence is
+ * generated in full, in order (Eq. 3), but only the words of the n_sample oscillators ids[]
+ * (ascending, each < N) are kept, and only those oscillators are integrated.  Oscillator i at step
+ * s consumes y_{P + 4i + r}, r = 0..3, P the position at the start of the step, as in orc_ld_run.
+ * x, v are [3][n_sample]; win (the last ll values) advances by 4 N n_steps positions.  Lets a test
+ * follow a few oscillators of a run whose full state would not fit the oracle's time.
+ * Pinned by: equality with orc_ld_run on the same oscillators, in the tests.
+ */
+int orc_ld_run_lf_sampled(uint32_t ll, uint32_t sl, uint32_t *win, uint64_t N, uint32_t n_steps, double m,
+                          double k, double gamma, double kT, double dt, int scheme, const uint64_t *ids,
+                          uint64_t n_sample, double *x, double *v)
+{
+    if (sl == 0 || sl >= ll) return -1;
+    for (uint64_t q = 0; q < n_sample; ++q)
+        if (ids[q] >= N || (q > 0 && ids[q] <= ids[q - 1])) return -1;
+    orc_coef co = make_coef(m, k, gamma, kT, dt, scheme);
+    uint32_t *buf = (uint32_t *)malloc(sizeof(uint32_t) * ll);
+    uint32_t *words = (uint32_t *)malloc(sizeof(uint32_t) * (4 * n_sample + 1));
+    if (!buf || !words) { free(buf); free(words); return -2; }
+    memcpy(buf, win, sizeof(uint32_t) * ll);
+    /* buf[head] = y_{n-ll}; buf[tail] = y_{n-sl}, tail = head + ll - sl (mod ll) */
+    uint32_t head = 0, tail = ll - sl;
+    for (uint32_t s = 0; s < n_steps; ++s) {
+        uint64_t q = 0;
+        for (uint64_t i = 0; i < N; ++i) {
+            int keep = q < n_sample && ids[q] == i;
+            for (int r = 0; r < 4; ++r) {
+                uint32_t y = buf[head] + buf[tail];
+                buf[head] = y;
+                if (++head == ll) head = 0;
+                if (++tail == ll) tail = 0;
+                if (keep) words[4 * q + r] = y;
+            }
+            if (keep) ++q;
+        }
+        for (q = 0; q < n_sample; ++q) {
+            double g[3], xi[3], vi[3];
+            forces_from_words(words + 4 * q, g);
+            for (int d = 0; d < 3; ++d) { xi[d] = x[d * n_sample + q]; vi[d] = v[d * n_sample + q]; }
+            ld_update(&co, xi, vi, g);
+            for (int d = 0; d < 3; ++d) { x[d * n_sample + q] = xi[d]; v[d * n_sample + q] = vi[d]; }
+        }
+    }
+    for (uint32_t i = 0; i < ll; ++i) win[i] = buf[(head + i) % ll];
+    free(buf);
+    free(words);
+    return 0;
+}
+
 /* The Gaussian forces g[s][d][i] an LD run would use (for the exact-solution pin). */
 int orc_ld_forces(int kind, void *states, uint32_t ll, uint32_t sl, uint64_t N, uint32_t n_steps, double *g)
 {
@@ -597,15 +659,24 @@ int orc_ld_forces(int kind, void *states, uint32_t ll, uint32_t sl, uint64_t N, 
  * swept backward before moving to the next one.  grad = [dL/dk, dL/dgamma, dL/dkT].
  * Pinned by: central finite differences under common random numbers and the exact identity
  * dL/dkT = L/kT for x0 = v0 = 0, in the tests. */
-int orc_ld_adjoint(int kind, void *states, uint64_t N, uint32_t n_steps, double m, double k, double gamma,
-                   double kT, double dt, const double *x_init, const double *v_init, uint32_t t_begin,
-                   uint32_t t_end, double *loss, double *grad)
+/* The same with the step's coefficients given directly: cq = {c, kap, sig, h} and their partials
+ * dq = {dkap/dk, dc/dgamma, dsig/dgamma, dsig/dkT} (e.g. a parameter block held at another
+ * precision, whose rounded coefficients define the map actually iterated). */
+int orc_ld_adjoint_coef(int kind, void *states, uint64_t N, uint32_t n_steps, const double *cq, const double *dq,
+                        const double *x_init, const double *v_init, uint32_t t_begin, uint32_t t_end,
+                        double *loss, double *grad)
 {
     if (kind == ORC_LF || t_begin < 1 || t_end < t_begin || t_end > n_steps) return -1;
-    orc_coef q = make_coef(m, k, gamma, kT, dt, 0);
-    double h = dt;
-    double dc_dgamma = -h, dkap_dk = h / m;
-    double dsig_dgamma = q.sig / (2.0 * gamma), dsig_dkT = q.sig / (2.0 * kT);
+    orc_coef q;
+    memset(&q, 0, sizeof(q));
+    q.scheme = 0;
+    q.c = cq[0];
+    q.kap = cq[1];
+    q.sig = cq[2];
+    q.h = cq[3];
+    double h = q.h;
+    double dkap_dk = dq[0], dc_dgamma = dq[1];
+    double dsig_dgamma = dq[2], dsig_dkT = dq[3];
     double scale = 1.0 / ((double)(t_end - t_begin + 1) * 3.0 * (double)N);
     /* path[s] = (x_s, v_s) for s = 0..n_steps; noise[s] = g used in step s -> s+1 */
     double *path = (double *)malloc(sizeof(double) * 6 * ((size_t)n_steps + 1));
@@ -655,6 +726,16 @@ int orc_ld_adjoint(int kind, void *states, uint64_t N, uint32_t n_steps, double 
     grad[1] = gg;
     grad[2] = gT;
     return 0;
+}
+
+int orc_ld_adjoint(int kind, void *states, uint64_t N, uint32_t n_steps, double m, double k, double gamma,
+                   double kT, double dt, const double *x_init, const double *v_init, uint32_t t_begin,
+                   uint32_t t_end, double *loss, double *grad)
+{
+    orc_coef q = make_coef(m, k, gamma, kT, dt, 0);
+    double cq[4] = {q.c, q.kap, q.sig, q.h};
+    double dq[4] = {dt / m, -dt, q.sig / (2.0 * gamma), q.sig / (2.0 * kT)};
+    return orc_ld_adjoint_coef(kind, states, N, n_steps, cq, dq, x_init, v_init, t_begin, t_end, loss, grad);
 }
 
 /* Loss only (forward), for finite differences under common random numbers. */

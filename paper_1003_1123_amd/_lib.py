@@ -31,7 +31,7 @@ class RngldError(RuntimeError):
 class Cfg(C.Structure):
     _fields_ = [("kind", C.c_int32), ("lf_ll", C.c_uint32), ("lf_sl", C.c_uint32), ("lf_wave", C.c_uint32),
                 ("seed", C.c_uint64), ("n_streams", C.c_uint64), ("stream_base", C.c_uint64),
-                ("lf_ring", C.c_uint64), ("lcg_leap", C.c_uint64)]
+                ("lf_ring", C.c_uint64), ("lcg_leap", C.c_uint64), ("lf_discard", C.c_uint64)]
 
 
 class Params(C.Structure):
@@ -61,6 +61,7 @@ class Loss(C.Structure):
 
 
 ADJ_REPLAY = 1  # ld_loss.flags: backward by segment replay for every ensemble
+ADJ_SPREAD = 2  # ld_loss.flags: ld_run_backward also returns the gradients' standard errors
 
 
 def _load():
@@ -122,9 +123,9 @@ def last_error() -> str:
 # argument helpers
 
 def make_cfg(kind, seed: int = 1234, n_streams: int = 0, stream_base: int = 0, ll: int = 0, sl: int = 0,
-             wave: int = 0, ring: int = 0, leap: int = 0) -> Cfg:
+             wave: int = 0, ring: int = 0, leap: int = 0, discard: int = 0) -> Cfg:
     k = KINDS[kind] if isinstance(kind, str) else int(kind)
-    return Cfg(k, ll, sl, wave, seed & (2**64 - 1), n_streams, stream_base, ring, leap)
+    return Cfg(k, ll, sl, wave, seed & (2**64 - 1), n_streams, stream_base, ring, leap, discard)
 
 
 def make_params(m=1.0, k=1.0, gamma=1.0, kT=1.0, dt=0.01, scheme: int = 0) -> Params:
@@ -354,7 +355,9 @@ def ld_run_ckpt(cfg: Cfg, state, ens, n_ens, n_total, n_steps, x, v, loss: Loss,
 
 
 def ld_run_backward(cfg: Cfg, ckpt, ens, n_ens, n_total, n_steps, loss: Loss, out_grad, ws):
+    """out_grad: [n_ens][3] doubles, or [n_ens][6] (gradients, standard errors) with ADJ_SPREAD."""
     _ens(ens, n_ens)
+    width = 6 if loss.flags & ADJ_SPREAD else 3
     _check(lib.ld_run_backward(C.byref(cfg), _dev(ckpt, torch.uint8, "ckpt"), _nbytes(ckpt), ens, n_ens, n_total,
-                               n_steps, C.byref(loss), _dev(out_grad, torch.float64, "out_grad", 3 * n_ens),
+                               n_steps, C.byref(loss), _dev(out_grad, torch.float64, "out_grad", width * n_ens),
                                _dev(ws, torch.uint8, "ws"), _nbytes(ws), _stream()), "ld_run_backward")

@@ -22,12 +22,15 @@ class AdjointRun:
     """
 
     def __init__(self, kind, ensembles, n_steps: int, t_begin: int, t_end: int, K: int, device="cuda",
-                 replay: bool = False):
+                 replay: bool = False, spread: bool = False):
         self.kind = kind
         self.ens_shape = list(ensembles)
         self.n_total = sum(n for n, _, _, _ in self.ens_shape)
         self.n_steps, self.device = n_steps, device
-        self.loss = R.Loss(t_begin, t_end, K, R.ADJ_REPLAY if replay else 0)
+        self.loss = R.Loss(t_begin, t_end, K, (R.ADJ_REPLAY if replay else 0) | (R.ADJ_SPREAD if spread else 0))
+        # with spread: after backward, grad_se[e] = standard errors of (dL/dk, dL/dgamma, dL/dkT)
+        # as estimates of d E[L] / d theta (per-oscillator spread / sqrt(n))
+        self.grad_se = None
         self.cfg = R.make_cfg(kind, n_streams=self.n_total)
         self.state = R.new_state(self.cfg, device)
         self.x = torch.zeros(3 * self.n_total, dtype=torch.float32, device=device)
@@ -71,9 +74,12 @@ class LDAdjoint(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_out):
         run = ctx.run
-        g = torch.empty((ctx.n_ens, 3), dtype=torch.float64, device=run.device)
+        spread = bool(run.loss.flags & R.ADJ_SPREAD)
+        g = torch.empty((ctx.n_ens, 6 if spread else 3), dtype=torch.float64, device=run.device)
         R.ld_run_backward(run.cfg, run.ckpt, ctx.ens, ctx.n_ens, run.n_total, run.n_steps, run.loss, g,
                           run.workspace(ctx.ens, ctx.n_ens))
+        if spread:
+            run.grad_se = g[:, 3:6].clone()
         go = grad_out.to(device=run.device, dtype=torch.float64)
         grads = [(go * g[:, i]).to(device=dev, dtype=dt) for i, (dt, dev) in enumerate(ctx.meta)]
         return grads[0], grads[1], grads[2], None

@@ -546,7 +546,18 @@ int rng_init(const rngld_cfg *cfg, void *d_state, size_t state_bytes, void *stre
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (g.kind == RNGLD_NO_NOISE) return RNGLD_OK;
     if (g.kind == RNGLD_LAGFIB) {
+        if (cfg->lf_discard > (1ull << 40)) return fail(RNGLD_EINVAL, "lf_discard above 2^40");
         RNGLD_TRY_HIP(launch_lf_seed(d_state, g.ll, g.sl, g.R, g.W, cfg->seed, st));
+        const uint64_t D = cfg->lf_discard;
+        if (D) {
+            // waves of W positions (each wave's sources lie in earlier waves or the window), then the
+            // window's newest slot moves D positions on while pos stays 0
+            const LfRing L = lf_ring(g, d_state);
+            for (uint64_t first = 0; first < D; first += g.W)
+                RNGLD_TRY_HIP(launch_lf_discard_phase(L, static_cast<uint32_t>(first % g.R),
+                                                      static_cast<uint32_t>(std::min<uint64_t>(g.W, D - first)), st));
+            RNGLD_TRY_HIP(launch_lf_advance(static_cast<LfHeader *>(d_state), 0, static_cast<uint32_t>(D % g.R), st));
+        }
     } else {
         if (cfg->stream_base > kMaxStreams) return fail(RNGLD_EINVAL, "stream_base too large");
         RNGLD_TRY_HIP(launch_seed(g.kind, d_state, g.S, cfg->seed, cfg->stream_base, 0, g.S, g.leap, st));
@@ -889,18 +900,29 @@ std::string device_name() {
     return s + "_cu" + std::to_string(prop.multiProcessorCount);
 }
 
-int log2_bucket(uint64_t v) {
-    int b = 0;
-    while (v > 1) {
-        v >>= 1;
-        ++b;
+// FNV-1a over the workload shape: every ensemble's size and integrator scheme (the launch shape's
+// speed depends on the tiles, not on the physical parameters)
+uint64_t shape_hash(const ld_ensemble *h_ens, uint32_t n_ens) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](uint64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= (v >> (8 * b)) & 0xFF;
+            h *= 1099511628211ull;
+        }
+    };
+    for (uint32_t e = 0; e < n_ens; ++e) {
+        mix(h_ens[e].n);
+        mix(static_cast<uint64_t>(h_ens[e].p.scheme));
     }
-    return b;
+    return h;
 }
 
-std::string cache_key(int kind, uint64_t n_total, uint32_t n_ens, uint32_t n_steps) {
-    return device_name() + " kind" + std::to_string(kind) + " n" + std::to_string(log2_bucket(n_total)) + " e" +
-           std::to_string(log2_bucket(n_ens)) + " s" + std::to_string(log2_bucket(n_steps));
+// one cache line: "<device> <kind> <n_total> <n_ens> <n_steps> <shape hash> block opt spl bpc"
+std::string cache_key(int kind, uint64_t n_total, uint32_t n_ens, uint32_t n_steps, uint64_t hash) {
+    char buf[256];
+    snprintf(buf, sizeof(buf), "%s kind%d n%llu e%u s%u h%016llx", device_name().c_str(), kind,
+             static_cast<unsigned long long>(n_total), n_ens, n_steps, static_cast<unsigned long long>(hash));
+    return buf;
 }
 
 bool cache_lookup(const char *path, const std::string &key, ld_tuning *t) {
@@ -910,12 +932,13 @@ bool cache_lookup(const char *path, const std::string &key, ld_tuning *t) {
     char line[512];
     bool found = false;
     while (fgets(line, sizeof(line), f)) {
-        char k1[128], k2[32], k3[32], k4[32], k5[32];
+        char k[6][128];
         unsigned b, o, s, c;
-        if (sscanf(line, "%127s %31s %31s %31s %31s %u %u %u %u", k1, k2, k3, k4, k5, &b, &o, &s, &c) == 9) {
-            const std::string k = std::string(k1) + " " + k2 + " " + k3 + " " + k4 + " " + k5;
-            ld_tuning cand{b, o, s, c};
-            if (k == key && valid_tuning(cand)) {
+        if (sscanf(line, "%127s %127s %127s %127s %127s %127s %u %u %u %u", k[0], k[1], k[2], k[3], k[4], k[5], &b, &o,
+                   &s, &c) == 10) {
+            const std::string lk = std::string(k[0]) + " " + k[1] + " " + k[2] + " " + k[3] + " " + k[4] + " " + k[5];
+            ld_tuning cand{b, o, s, c, 0};
+            if (lk == key && valid_tuning(cand)) {
                 *t = cand;
                 found = true;
             }
@@ -925,12 +948,25 @@ bool cache_lookup(const char *path, const std::string &key, ld_tuning *t) {
     return found;
 }
 
+// rewrite the cache with this key's line replaced (or added); other lines are kept as they are
 void cache_store(const char *path, const std::string &key, const ld_tuning &t) {
     if (!path) return;
-    FILE *f = fopen(path, "a");
+    std::vector<std::string> keep;
+    if (FILE *f = fopen(path, "r")) {
+        char line[512];
+        while (fgets(line, sizeof(line), f)) {
+            std::string l(line);
+            if (l.compare(0, key.size() + 1, key + " ") != 0) keep.push_back(l);
+        }
+        fclose(f);
+    }
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
     if (!f) return;
+    for (const std::string &l : keep) fputs(l.c_str(), f);
     fprintf(f, "%s %u %u %u %u\n", key.c_str(), t.block, t.osc_per_thread, t.steps_per_launch, t.blocks_per_cu);
-    fclose(f);
+    const bool ok = fclose(f) == 0;
+    if (ok) rename(tmp.c_str(), path);
 }
 
 struct DeviceScratch {
@@ -946,6 +982,54 @@ struct DeviceScratch {
     }
 };
 
+// timing resources of one autotune call: a private stream (never the legacy default stream) and two
+// events recorded on it
+struct TuneTimer {
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~TuneTimer() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (st) (void)hipStreamDestroy(st);
+    }
+    int init() {
+        RNGLD_TRY_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        RNGLD_TRY_HIP(hipEventCreate(&e0));
+        RNGLD_TRY_HIP(hipEventCreate(&e1));
+        return RNGLD_OK;
+    }
+    // milliseconds of the work `fn` enqueues on st
+    template <class F>
+    int time(F &&fn, float *ms) {
+        RNGLD_TRY_HIP(hipEventRecord(e0, st));
+        RNGLD_TRY(fn());
+        RNGLD_TRY_HIP(hipEventRecord(e1, st));
+        RNGLD_TRY_HIP(hipEventSynchronize(e1));
+        RNGLD_TRY_HIP(hipEventElapsedTime(ms, e0, e1));
+        return RNGLD_OK;
+    }
+};
+
+// capture one run (the shape and chunking of t) into an executable graph on the timer's stream
+int capture_run(const Gen &g, void *state, const RunLayout &L, const ld_tuning &t, uint64_t n_total, uint32_t steps,
+                float *x, float *v, void *ws, hipGraph_t *graph, hipGraphExec_t *exec) {
+    hipStream_t cap = nullptr;
+    RNGLD_TRY_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    int rc = RNGLD_OK;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        rc = enqueue_run(g, state, L, t, n_total, steps, x, v, nullptr, nullptr, ws, cap, false, false);
+        const hipError_t e2 = hipStreamEndCapture(cap, graph);
+        if (rc == RNGLD_OK && e2 != hipSuccess) rc = fail(RNGLD_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+    } else {
+        rc = fail(RNGLD_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    }
+    if (rc == RNGLD_OK && hipGraphInstantiate(exec, *graph, nullptr, nullptr, 0) != hipSuccess)
+        rc = fail(RNGLD_EHIP, "hipGraphInstantiate failed");
+    (void)hipStreamDestroy(cap);
+    return rc;
+}
+
 }  // namespace
 
 extern "C" int ld_autotune(const rngld_cfg *cfg, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total,
@@ -955,15 +1039,14 @@ extern "C" int ld_autotune(const rngld_cfg *cfg, const ld_ensemble *h_ens, uint3
     if (!out) return fail(RNGLD_EINVAL, "out is NULL");
     if (g.kind == RNGLD_LAGFIB) return fail(RNGLD_ENOTSUP, "the lagged-Fibonacci path has no tunable launch shape");
     RNGLD_TRY(check_run_args(g, h_ens, n_ens, n_total, n_steps, nullptr));
-    const std::string key = cache_key(g.kind, n_total, n_ens, n_steps);
+    const std::string key = cache_key(g.kind, n_total, n_ens, n_steps, shape_hash(h_ens, n_ens));
     ld_tuning best{};
     if (cache_lookup(cache_path, key, &best)) {
         RNGLD_TRY(ld_set_tuning(g.kind, &best));
         *out = best;
         return RNGLD_OK;
     }
-    // proxy run: the same ensembles, a shortened step count, on scratch copies
-    const uint32_t proxy_steps = std::max<uint32_t>(1, std::min<uint32_t>(n_steps, 128));
+    // proxy runs: the same ensembles on scratch copies of x, v and the state
     DeviceScratch mem;
     const size_t xv_bytes = 3 * static_cast<size_t>(n_total) * sizeof(float);
     float *x = static_cast<float *>(mem.get(xv_bytes));
@@ -974,54 +1057,85 @@ extern "C" int ld_autotune(const rngld_cfg *cfg, const ld_ensemble *h_ens, uint3
     RNGLD_TRY(check_cfg(&c2, &g2));
     void *state = mem.get(g2.state_bytes);
     if (!x || !v || !state) return fail(RNGLD_EHIP, "autotune scratch allocation failed");
-    RNGLD_TRY_HIP(hipMemset(x, 0, xv_bytes));
-    RNGLD_TRY_HIP(hipMemset(v, 0, xv_bytes));
-    RNGLD_TRY(rng_init(&c2, state, g2.state_bytes, nullptr));
+    TuneTimer tm;
+    RNGLD_TRY(tm.init());
+    RNGLD_TRY_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(x), 3 * n_total, 0u, tm.st));
+    RNGLD_TRY_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(v), 3 * n_total, 0u, tm.st));
+    RNGLD_TRY(rng_init(&c2, state, g2.state_bytes, tm.st));
 
+    // 1) launch shape (block size, oscillators per thread, blocks per CU) on a short proxy, whole run
+    //    in one launch; each candidate's first repetition loads its kernel and is not counted
+    const uint32_t proxy_steps = std::max<uint32_t>(1, std::min<uint32_t>(n_steps, 128));
     std::vector<ld_tuning> cands;
     for (uint32_t b : {64u, 128u, 256u, 512u})
         for (uint32_t o : {1u, 2u})
             for (uint32_t bpc : {0u, 4u, 8u}) {
                 if (g.kind == RNGLD_RAN2 && o * b * kR2Tab * 4 > 64 * 1024) continue;
-                cands.push_back({b, o, 0, bpc});
+                cands.push_back({b, o, 0, bpc, 0});
             }
-    hipEvent_t e0, e1;
-    RNGLD_TRY_HIP(hipEventCreate(&e0));
-    RNGLD_TRY_HIP(hipEventCreate(&e1));
     float best_ms = 1e30f;
-    int rc = RNGLD_OK;
     for (const ld_tuning &t : cands) {
         RunLayout L;
-        rc = layout_run(g2, h_ens, n_ens, n_total, proxy_steps, nullptr, t, &L);
-        if (rc != RNGLD_OK) break;
+        RNGLD_TRY(layout_run(g2, h_ens, n_ens, n_total, proxy_steps, nullptr, t, &L));
         void *ws = mem.get(L.bytes);
-        if (!ws) {
-            rc = fail(RNGLD_EHIP, "autotune scratch allocation failed");
-            break;
-        }
+        if (!ws) return fail(RNGLD_EHIP, "autotune scratch allocation failed");
         float ms = 0.0f;
-        for (int rep = 0; rep < 3 && rc == RNGLD_OK; ++rep) {
-            if (hipEventRecord(e0, nullptr) != hipSuccess) rc = fail(RNGLD_EHIP, "hipEventRecord failed");
-            if (rc == RNGLD_OK)
-                rc = enqueue_run(g2, state, L, t, n_total, proxy_steps, x, v, nullptr, nullptr, ws, nullptr, true);
-            if (rc == RNGLD_OK && hipEventRecord(e1, nullptr) != hipSuccess) rc = fail(RNGLD_EHIP, "hipEventRecord");
-            if (rc == RNGLD_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(RNGLD_EHIP, "hipEventSynchronize");
+        for (int rep = 0; rep < 3; ++rep) {
             float m = 0.0f;
-            if (rc == RNGLD_OK && hipEventElapsedTime(&m, e0, e1) != hipSuccess) rc = fail(RNGLD_EHIP, "elapsed");
-            if (rep > 0) ms += m;  // first repetition warms up
+            RNGLD_TRY(tm.time([&] { return enqueue_run(g2, state, L, t, n_total, proxy_steps, x, v, nullptr, nullptr,
+                                                       ws, tm.st, true); }, &m));
+            if (rep > 0) ms += m;
         }
-        if (rc != RNGLD_OK) break;
         if (ms < best_ms) {
             best_ms = ms;
             best = t;
         }
     }
-    // steps per launch: whole run unless splitting it costs less than 1% (long runs, plan graphs)
-    if (rc == RNGLD_OK && n_steps > 2000) best.steps_per_launch = 1000;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (rc != RNGLD_OK) return rc;
-    if (hipDeviceSynchronize() != hipSuccess) return fail(RNGLD_EHIP, "autotune synchronisation failed");
+
+    // 2) steps per launch: each candidate chunking of a longer proxy run (up to 2500 steps, shortened
+    //    for very large ensembles), captured in a graph as ld_plan_create records it and replayed;
+    //    the fastest replay wins, a single launch on ties within 0.5%
+    uint32_t spl_steps = std::min<uint32_t>(n_steps, 2500);
+    while (spl_steps > 500 && static_cast<double>(n_total) * spl_steps > 2e11) spl_steps /= 2;
+    float spl_best_ms = 1e30f;
+    uint32_t spl_best = 0;
+    for (uint32_t spl : {0u, 2500u, 1000u, 500u}) {
+        if (spl && spl >= spl_steps) continue;
+        ld_tuning t = best;
+        t.steps_per_launch = spl;
+        RunLayout L;
+        RNGLD_TRY(layout_run(g2, h_ens, n_ens, n_total, spl_steps, nullptr, t, &L));
+        void *ws = mem.get(L.bytes);
+        if (!ws) return fail(RNGLD_EHIP, "autotune scratch allocation failed");
+        RNGLD_TRY_HIP(launch_upload(static_cast<uint8_t *>(ws) + L.off_ens, L.ens.data(), sizeof(EnsDev) * L.ens.size(),
+                                    tm.st));
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        int rc = capture_run(g2, state, L, t, n_total, spl_steps, x, v, ws, &graph, &exec);
+        float ms = 1e30f;
+        for (int rep = 0; rep < 3 && rc == RNGLD_OK; ++rep) {
+            float m = 0.0f;
+            rc = tm.time([&] {
+                const hipError_t e = hipGraphLaunch(exec, tm.st);
+                return e == hipSuccess ? RNGLD_OK : fail(RNGLD_EHIP, "hipGraphLaunch: %s", hipGetErrorString(e));
+            }, &m);
+            if (rep > 0) ms = std::min(ms, m);
+        }
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (rc != RNGLD_OK) return rc;
+        if (spl == 0 || ms < spl_best_ms * 0.995f) {
+            spl_best_ms = ms;
+            spl_best = spl;
+        }
+    }
+    best.steps_per_launch = spl_best;
+    if (debug_enabled())
+        fprintf(stderr, "[rngld] autotune %s: block %u, %u per thread, %u blocks per CU, %u steps per launch "
+                        "(%.3f ms for %u proxy steps)\n",
+                key.c_str(), best.block, best.osc_per_thread, best.blocks_per_cu, best.steps_per_launch, spl_best_ms,
+                spl_steps);
+    RNGLD_TRY_HIP(hipStreamSynchronize(tm.st));
     cache_store(cache_path, key, best);
     RNGLD_TRY(ld_set_tuning(g.kind, &best));
     *out = best;
@@ -1036,6 +1150,7 @@ constexpr uint32_t kAdjTile = 256;
 int check_loss(const ld_loss *loss, uint32_t n_steps) {
     if (!loss) return fail(RNGLD_EINVAL, "loss is NULL");
     if (loss->K == 0) return fail(RNGLD_EINVAL, "checkpoint interval K must be positive");
+    if (loss->flags & ~(RNGLD_ADJ_REPLAY | RNGLD_ADJ_SPREAD)) return fail(RNGLD_EINVAL, "unknown loss flags");
     if (loss->t_begin < 1 || loss->t_end < loss->t_begin || loss->t_end > n_steps)
         return fail(RNGLD_EINVAL, "loss window must satisfy 1 <= t_begin <= t_end <= n_steps");
     return RNGLD_OK;
@@ -1046,8 +1161,27 @@ struct AdjLayout {
     std::vector<AdjCoef> adj;
     uint32_t n_tiles = 0;
     bool any_replay = false, any_inverse = false;
-    size_t off_ens = 0, off_adj = 0, off_partials = 0, off_scratch = 0, bytes = 0;
+    size_t off_ens = 0, off_adj = 0, off_partials = 0, off_scratch = 0, off_seg_f = 0, off_seg_d = 0, bytes = 0;
 };
+
+// B^K for the adjoint step matrix B = [[1 - kap h, -kap], [c h, c]] (row-major), the map that
+// carries the adjoint (lam_x, lam_v) at a K-step segment's end to its start with no loss terms;
+// evaluated as the kernels' recursion mu = lam_v + h lam_x, lam_x -= kap mu, lam_v = c mu, in FP64
+void adjoint_propagator(const LdCoef &q, uint32_t K, float phi[4]) {
+    const double h = q.h, c = q.c, kap = q.kap;
+    double c1x = 1, c1v = 0, c2x = 0, c2v = 1;  // images of the unit vectors (columns)
+    for (uint32_t j = 0; j < K; ++j) {
+        const double m1 = c1v + h * c1x, m2 = c2v + h * c2x;
+        c1x -= kap * m1;
+        c1v = c * m1;
+        c2x -= kap * m2;
+        c2v = c * m2;
+    }
+    phi[0] = static_cast<float>(c1x);
+    phi[1] = static_cast<float>(c2x);
+    phi[2] = static_cast<float>(c1v);
+    phi[3] = static_cast<float>(c2v);
+}
 
 // Largest growth of a perturbation of (x, v) over 1..K backward steps of the underdamped
 // integrator with these FP32 coefficients: max_j |M^j|_F, M the inverse of the step matrix
@@ -1073,8 +1207,8 @@ double reverse_growth(const LdCoef &q, uint32_t K, double limit) {
 constexpr double kAdjGrowthLimit = 8.0;
 constexpr uint32_t kAdjInverseMaxK = 1u << 22;
 
-int layout_adj(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total, const ld_loss &loss,
-               bool backward, AdjLayout *L) {
+int layout_adj(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total, uint32_t n_steps,
+               const ld_loss &loss, bool backward, AdjLayout *L) {
     const uint32_t K = loss.K;
     L->ens.resize(n_ens);
     L->adj.resize(n_ens);
@@ -1097,8 +1231,12 @@ int layout_adj(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t 
         A.dsig_dgamma = static_cast<float>(sig / (2.0 * p.gamma));
         A.dsig_dkT = static_cast<float>(sig / (2.0 * p.kT));
         A.inv_c = static_cast<float>(1.0 / static_cast<double>(A.f.c));
+        A.inv_c_lo = static_cast<float>(1.0 / static_cast<double>(A.f.c) - static_cast<double>(A.inv_c));
+        // the register-only backward launches one block row per segment (grid y below 2^16)
+        const uint64_t nseg = (static_cast<uint64_t>(n_steps) + K - 1) / K;
         A.inverse = g.kind == RNGLD_HYBRID_TAUS && !(loss.flags & RNGLD_ADJ_REPLAY) && K <= kAdjInverseMaxK &&
-                    reverse_growth(A.f, K, kAdjGrowthLimit) <= kAdjGrowthLimit;
+                    nseg < 65536 && reverse_growth(A.f, K, kAdjGrowthLimit) <= kAdjGrowthLimit;
+        if (A.inverse) adjoint_propagator(A.f, K, A.phi);
         if (E.n) {
             L->any_inverse |= A.inverse != 0;
             L->any_replay |= A.inverse == 0;
@@ -1109,8 +1247,14 @@ int layout_adj(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t 
     L->off_ens = 0;
     L->off_adj = align_up(sizeof(EnsDev) * n_ens);
     L->off_partials = align_up(L->off_adj + sizeof(AdjCoef) * n_ens);
-    L->off_scratch = align_up(L->off_partials + 3 * sizeof(double) * std::max<uint32_t>(L->n_tiles, 1));
+    L->off_scratch = align_up(L->off_partials + kAdjPartW * sizeof(double) * std::max<uint32_t>(L->n_tiles, 1));
     L->bytes = L->off_scratch + (backward && L->any_replay ? align_up(9ull * K * n_total * sizeof(float)) : 0);
+    if (backward && L->any_inverse) {  // one record per (oscillator, segment)
+        const uint64_t nseg = (static_cast<uint64_t>(n_steps) + K - 1) / K;
+        L->off_seg_f = L->bytes;
+        L->off_seg_d = align_up(L->off_seg_f + nseg * kAdjSegF * n_total * sizeof(float));
+        L->bytes = align_up(L->off_seg_d + nseg * kAdjSegD * n_total * sizeof(double));
+    }
     return RNGLD_OK;
 }
 
@@ -1152,7 +1296,7 @@ extern "C" int ld_adjoint_workspace_bytes(const rngld_cfg *cfg, const ld_ensembl
     RNGLD_TRY(check_adj_common(cfg, &g, h_ens, n_ens, n_total, n_steps, loss));
     if (!bytes) return fail(RNGLD_EINVAL, "bytes is NULL");
     AdjLayout L;
-    RNGLD_TRY(layout_adj(g, h_ens, n_ens, n_total, *loss, true, &L));
+    RNGLD_TRY(layout_adj(g, h_ens, n_ens, n_total, n_steps, *loss, true, &L));
     *bytes = L.bytes;
     return RNGLD_OK;
 }
@@ -1169,7 +1313,7 @@ extern "C" int ld_run_ckpt(const rngld_cfg *cfg, void *d_state, size_t state_byt
     RNGLD_TRY(ld_ckpt_bytes(cfg, n_total, n_steps, loss->K, &need_ck));
     if (ckpt_bytes < need_ck) return fail(RNGLD_ESIZE, "checkpoint buffer %zu < %zu bytes", ckpt_bytes, need_ck);
     AdjLayout L;
-    RNGLD_TRY(layout_adj(g, h_ens, n_ens, n_total, *loss, false, &L));
+    RNGLD_TRY(layout_adj(g, h_ens, n_ens, n_total, n_steps, *loss, false, &L));
     if (ws_bytes < L.bytes) return fail(RNGLD_ESIZE, "workspace %zu bytes < %zu required", ws_bytes, L.bytes);
     if (!d_ws || !d_loss || (n_total && (!d_x || !d_v || !d_ckpt))) return fail(RNGLD_EINVAL, "NULL buffer");
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1194,7 +1338,7 @@ extern "C" int ld_run_ckpt(const rngld_cfg *cfg, void *d_state, size_t state_byt
     a.rec_bytes = ckpt_record_bytes(g, n_total);
     a.partials = reinterpret_cast<double *>(ws + L.off_partials);
     RNGLD_TRY_HIP(launch_ld_ckpt(g.kind, a, kAdjTile, st));
-    RNGLD_TRY_HIP(launch_adj_finalize(a.partials, L.n_tiles, 1, a.ens, n_ens,
+    RNGLD_TRY_HIP(launch_adj_finalize(a.partials, L.n_tiles, 1, false, a.ens, n_ens,
                                       static_cast<double>(loss->t_end - loss->t_begin + 1), d_loss, st));
     return RNGLD_OK;
 }
@@ -1208,7 +1352,7 @@ extern "C" int ld_run_backward(const rngld_cfg *cfg, const void *d_ckpt, size_t 
     RNGLD_TRY(ld_ckpt_bytes(cfg, n_total, n_steps, loss->K, &need_ck));
     if (ckpt_bytes < need_ck) return fail(RNGLD_ESIZE, "checkpoint buffer %zu < %zu bytes", ckpt_bytes, need_ck);
     AdjLayout L;
-    RNGLD_TRY(layout_adj(g, h_ens, n_ens, n_total, *loss, true, &L));
+    RNGLD_TRY(layout_adj(g, h_ens, n_ens, n_total, n_steps, *loss, true, &L));
     if (ws_bytes < L.bytes) return fail(RNGLD_ESIZE, "workspace %zu bytes < %zu required", ws_bytes, L.bytes);
     if (!d_ws || !d_grad || (n_total && !d_ckpt)) return fail(RNGLD_EINVAL, "NULL buffer");
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1228,10 +1372,12 @@ extern "C" int ld_run_backward(const rngld_cfg *cfg, const void *d_ckpt, size_t 
     a.ckpt = const_cast<uint8_t *>(static_cast<const uint8_t *>(d_ckpt));
     a.rec_bytes = ckpt_record_bytes(g, n_total);
     a.scratch = L.any_replay ? reinterpret_cast<float *>(ws + L.off_scratch) : nullptr;
+    a.seg_f = L.any_inverse ? reinterpret_cast<float *>(ws + L.off_seg_f) : nullptr;
+    a.seg_d = L.any_inverse ? reinterpret_cast<double *>(ws + L.off_seg_d) : nullptr;
     a.partials = reinterpret_cast<double *>(ws + L.off_partials);
     // n_steps >= 1 (check_loss); every tile's partials are written by exactly one of the kernels
     RNGLD_TRY_HIP(launch_ld_adjoint(g.kind, a, L.any_replay, L.any_inverse, st));
-    RNGLD_TRY_HIP(launch_adj_finalize(a.partials, L.n_tiles, 3, a.ens, n_ens,
+    RNGLD_TRY_HIP(launch_adj_finalize(a.partials, L.n_tiles, 3, (loss->flags & RNGLD_ADJ_SPREAD) != 0, a.ens, n_ens,
                                       static_cast<double>(loss->t_end - loss->t_begin + 1), d_grad, st));
     return RNGLD_OK;
 }

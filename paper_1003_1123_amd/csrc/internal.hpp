@@ -124,9 +124,24 @@ struct AdjCoef {
     float dc_dgamma;  // -h
     float dsig_dgamma;
     float dsig_dkT;
-    float inv_c;       // 1 / c, for the backward step of the register-only path
+    float inv_c;       // 1 / c = inv_c + inv_c_lo, for the backward step of the register-only path:
+                       // the pair keeps the reconstructed velocity free of the systematic bias that
+                       // a rounded reciprocal would compound over a segment's inverse steps
     uint32_t inverse;  // 1: register-only backward for this ensemble, 0: replay
+    float inv_c_lo;
+    // adjoint propagator over one whole K-step segment with no loss term: the adjoint (lam_x,
+    // lam_v) of the state at a segment's start is phi * (adjoint at its end) + what the segment's
+    // own loss terms contribute; phi = B^K with B = [[1 - kap h, -kap], [c h, c]], row-major
+    float phi[4];
 };
+
+// width of the per-tile FP64 partials of the adjoint kernels: three sums and their squares
+constexpr uint32_t kAdjPartW = 6;
+// per (oscillator, segment) record of the segment-parallel register-only backward: FP32 rows
+// [0, 6) the segment's own adjoint at its start (lam_x[3], lam_v[3]), [6, 24) the responses
+// sum_s a_s z_s and sum_s b_s z_s for z = x, v, g and each component; FP64 rows [0, 3) the
+// gradient sums with a zero adjoint at the segment's end
+constexpr uint32_t kAdjSegF = 24, kAdjSegD = 3;
 
 struct AdjArgs {
     void *state;  // forward: live state (stride S); unused by backward
@@ -141,15 +156,21 @@ struct AdjArgs {
     uint8_t *ckpt;
     uint64_t rec_bytes;  // bytes per checkpoint record
     float *scratch;      // backward, replay path: [K][9][NT]
-    double *partials;    // [n_tiles][3] (loss uses slot 0)
+    float *seg_f;        // backward, register-only path: [nseg][kAdjSegF][NT]
+    double *seg_d;       //                               [nseg][kAdjSegD][NT]
+    double *partials;    // [n_tiles][kAdjPartW]: the loss (forward), or per-oscillator gradient
+                         // sums and sums of squares (backward)
 };
 
 hipError_t launch_ld_ckpt(int kind, const AdjArgs &a, uint32_t block, hipStream_t st);
 // backward: the replay kernel for ensembles with inverse == 0, the register-only kernel (Hybrid
 // Taus) for those with inverse == 1
 hipError_t launch_ld_adjoint(int kind, const AdjArgs &a, bool any_replay, bool any_inverse, hipStream_t st);
-hipError_t launch_adj_finalize(const double *partials, uint32_t n_tiles, uint32_t width, const EnsDev *ens,
-                               uint32_t n_ens, double denom_steps, double *out, hipStream_t st);
+// out[e][0, width) = sums of partial slots 0..width-1 over the ensemble's tiles / (3 n denom_steps);
+// with spread, also out[e][width + q] = the standard error of the mean of slot q's per-oscillator
+// values (slot width + q holding their squares)
+hipError_t launch_adj_finalize(const double *partials, uint32_t n_tiles, uint32_t width, bool spread,
+                               const EnsDev *ens, uint32_t n_ens, double denom_steps, double *out, hipStream_t st);
 
 // ---- launchers (k_rng.hip) -------------------------------------------------------------------------
 hipError_t launch_seed(int kind, void *state, uint64_t S, uint64_t seed, uint64_t stream_base, uint64_t col_offset,
@@ -179,6 +200,8 @@ hipError_t launch_lf_ring_store(const LfRing &L, const uint32_t *out, uint64_t c
 hipError_t launch_lf_gauss_phase(const LfRing &L, float *out, uint64_t first, uint32_t off_mod, uint32_t count,
                                  hipStream_t st);
 hipError_t launch_lf_advance(LfHeader *hdr, uint64_t count, uint32_t count_mod, hipStream_t st);
+// one wave (count <= W) of positions generated into the ring only, slots off_mod + t from the header's
+hipError_t launch_lf_discard_phase(const LfRing &L, uint32_t off_mod, uint32_t count, hipStream_t st);
 hipError_t launch_lf_ld_phase(const LfLdPhase &ph, hipStream_t st);
 hipError_t launch_lf_observe(const LfLdPhase &ph0, uint32_t n_phases, uint64_t phase_osc, uint32_t point,
                              bool t0_now, hipStream_t st);

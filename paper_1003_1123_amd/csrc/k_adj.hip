@@ -11,9 +11,17 @@
 //  * register-only (Hybrid Taus): start from the checkpoint at the segment's end and step both
 //    the generator (inverse Tausworthe and LCG steps, so the noise is bit-identical) and the
 //    integrator backward, x = x' - h v', v = (v' + kap x - sig g) / c, while sweeping the adjoint;
-//    the next segment restarts from its own end checkpoint, which bounds the growth of rounding
+//    each segment restarts from its own end checkpoint, which bounds the growth of rounding
 //    errors in the reconstructed path to K steps (the host admits an ensemble only if that growth
-//    stays small).  Nothing is stored.
+//    stays small).  The segments run in parallel, one thread per (oscillator, segment): the
+//    reverse recursion is linear with a step matrix B that is the same for every step of an
+//    ensemble, so a segment swept with a zero adjoint at its end yields its own contribution, and
+//    the contribution of the adjoint that arrives from later segments is linear in that adjoint:
+//    with mu^hom_s = a_s lam_x + b_s lam_v the part of mu at step s driven by the end adjoint, the
+//    gradient gains sum_s (a_s, b_s) f_s . lam_end, f_s = dc v_s - dkap x_s + dsig g_s.  Each
+//    thread records its segment's own adjoint at the start, its gradient sums and the sums
+//    sum_s a_s z_s, sum_s b_s z_s for z = x, v, g; a per-oscillator pass then walks the segments
+//    from last to first, carrying lam_end(previous) = lam_own + B^K lam_end.
 //  * replay: restore the checkpoint at the segment's start, rerun the segment with the same
 //    generator, Box-Muller and update code, keep its path in a per-thread scratch column, and
 //    sweep it backward.
@@ -74,22 +82,13 @@ __device__ __forceinline__ uint32_t find_ensemble(const EnsDev *ens, uint32_t n_
     return lo;
 }
 
-// reduce up to three FP64 values per thread into partial[tile][0..2]
+// one oscillator's three gradient sums and their squares, summed over the block (fixed order)
 template <int BLOCK>
-__device__ __forceinline__ void block_sum3(const double (&q)[3], double (*red)[3], double *dst) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const double s = wave_sum(q[i]);
-        if (lane == 0) red[wave][i] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-        double s = 0.0;
-        for (int w = 0; w < BLOCK / 64; ++w) s += red[w][threadIdx.x];
-        dst[threadIdx.x] = s;
-    }
-    __syncthreads();
+__device__ __forceinline__ void block_grad_partials(bool act, double gk, double gg, double gT, double (*red)[6],
+                                                    double *dst) {
+    const double q[6] = {act ? gk : 0.0, act ? gg : 0.0, act ? gT : 0.0,
+                         act ? gk * gk : 0.0, act ? gg * gg : 0.0, act ? gT * gT : 0.0};
+    block_sum6<BLOCK>(q, red, dst);
 }
 
 // forward run from the current state with checkpoints every K steps; loss partial = sum of x^2
@@ -97,7 +96,7 @@ __device__ __forceinline__ void block_sum3(const double (&q)[3], double (*red)[3
 template <class Gen, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void ld_ckpt_kernel(AdjArgs a) {
     extern __shared__ int32_t lds[];
-    __shared__ double red[BLOCK / 64][3];
+    __shared__ double red[BLOCK / 64][6];
     const uint32_t tile = blockIdx.x;
     const uint32_t e = find_ensemble(a.ens, a.n_ens, tile);
     const EnsDev &E = a.ens[e];
@@ -151,14 +150,15 @@ __global__ __launch_bounds__(BLOCK) void ld_ckpt_kernel(AdjArgs a) {
         store_state(g, a.state, a.S, i);
         store_state(g, rx + 6 * a.NT, a.NT, i);
     }
-    double qv[3] = {act ? lsum : 0.0, 0.0, 0.0};
-    block_sum3<BLOCK>(qv, red, a.partials + static_cast<uint64_t>(tile) * 3);
+    // the loss sum and its square (the per-oscillator spread of the loss)
+    const double qv[6] = {act ? lsum : 0.0, act ? lsum * lsum : 0.0, 0.0, 0.0, 0.0, 0.0};
+    block_sum6<BLOCK>(qv, red, a.partials + static_cast<uint64_t>(tile) * kAdjPartW);
 }
 
 template <class Gen, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void ld_adjoint_kernel(AdjArgs a) {
     extern __shared__ int32_t lds[];
-    __shared__ double red[BLOCK / 64][3];
+    __shared__ double red[BLOCK / 64][6];
     const uint32_t tile = blockIdx.x;
     const uint32_t e = find_ensemble(a.ens, a.n_ens, tile);
     const EnsDev &E = a.ens[e];
@@ -221,79 +221,169 @@ __global__ __launch_bounds__(BLOCK) void ld_adjoint_kernel(AdjArgs a) {
             }
         }
     }
-    double qv[3] = {act ? gk : 0.0, act ? gg : 0.0, act ? gT : 0.0};
-    block_sum3<BLOCK>(qv, red, a.partials + static_cast<uint64_t>(tile) * 3);
+    block_grad_partials<BLOCK>(act, gk, gg, gT, red, a.partials + static_cast<uint64_t>(tile) * kAdjPartW);
 }
 
-// register-only backward sweep (Hybrid Taus): no replay and no scratch
+// register-only backward sweep (Hybrid Taus), one thread per (oscillator, segment): blockIdx.y is
+// the segment; the record of (oscillator, segment) goes to seg_f / seg_d
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void ld_adjoint_inv_kernel(AdjArgs a) {
-    __shared__ double red[BLOCK / 64][3];
+__global__ __launch_bounds__(BLOCK) void ld_adjoint_seg_kernel(AdjArgs a) {
+    const uint32_t tile = blockIdx.x, seg = blockIdx.y;
+    const uint32_t e = find_ensemble(a.ens, a.n_ens, tile);
+    const EnsDev &E = a.ens[e];
+    const AdjCoef A = a.adj[e];
+    if (!A.inverse) return;  // the replay kernel owns this tile
+    const float h = A.f.h, c = A.f.c, kap = A.f.kap, sig = A.f.sig, inv_c = A.inv_c, inv_c_lo = A.inv_c_lo;
+    const uint64_t i = E.offset + static_cast<uint64_t>(tile - E.tile_begin) * BLOCK + threadIdx.x;
+    const bool act = i < E.offset + E.n;
+    const uint64_t col = act ? i : E.offset;  // inactive lanes follow a valid column
+    const uint64_t NT = a.NT;
+    const uint32_t s0 = seg * a.K;
+    const uint32_t s1 = (s0 + a.K < a.n_steps) ? s0 + a.K : a.n_steps;
+    // record seg + 1 holds the state at s1 (the end state for the last segment)
+    const float *rec = reinterpret_cast<const float *>(a.ckpt + static_cast<uint64_t>(seg + 1) * a.rec_bytes);
+    float x[3], v[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        x[d] = rec[d * NT + col];
+        v[d] = rec[(3 + d) * NT + col];
+    }
+    HybridTaus g;
+    g.load(reinterpret_cast<const uint32_t *>(rec + 6 * NT), NT, col);
+    float lx[3] = {0, 0, 0}, lv[3] = {0, 0, 0};
+    // responses to the end adjoint: z_a[d] = sum_s a_s z_s, z_b[d] = sum_s b_s z_s (z = x, v, g)
+    float xa[3] = {0, 0, 0}, xb[3] = {0, 0, 0}, va[3] = {0, 0, 0}, vb[3] = {0, 0, 0};
+    float ga[3] = {0, 0, 0}, gb[3] = {0, 0, 0};
+    // the two unit end adjoints carried by the homogeneous recursion (the same in every lane):
+    // (p1x, p1v) from (1, 0), (p2x, p2v) from (0, 1); mu of each gives a_s and b_s
+    float p1x = 1.0f, p1v = 0.0f, p2x = 0.0f, p2v = 1.0f;
+    double gk = 0.0, gg = 0.0, gT = 0.0;
+    // x, v hold the state after step s on entry to step s
+    for (uint32_t s = s1; s-- > s0;) {
+        const bool in_loss = (s + 1 >= a.t_begin) && (s + 1 <= a.t_end);
+        const uint32_t w3 = g.prev();
+        const uint32_t w2 = g.prev();
+        const uint32_t w1 = g.prev();
+        const uint32_t w0 = g.prev();
+        float gf[3];
+        gaussian_forces(w0, w1, w2, w3, gf[0], gf[1], gf[2]);
+        const float as = p1v + h * p1x, bs = p2v + h * p2x;
+        p1x = p1x - kap * as;
+        p1v = c * as;
+        p2x = p2x - kap * bs;
+        p2v = c * bs;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (in_loss) lx[d] += 2.0f * x[d];
+            const float xs = x[d] - h * v[d];
+            const float t = v[d] + kap * xs - sig * gf[d];
+            const float vs = __builtin_fmaf(t, inv_c, t * inv_c_lo);
+            const float mu = lv[d] + h * lx[d];
+            gk += static_cast<double>(mu) * static_cast<double>(-A.dkap_dk * xs);
+            gg += static_cast<double>(mu) * static_cast<double>(A.dc_dgamma * vs + A.dsig_dgamma * gf[d]);
+            gT += static_cast<double>(mu) * static_cast<double>(A.dsig_dkT * gf[d]);
+            xa[d] += as * xs;
+            xb[d] += bs * xs;
+            va[d] += as * vs;
+            vb[d] += bs * vs;
+            ga[d] += as * gf[d];
+            gb[d] += bs * gf[d];
+            lx[d] = lx[d] - kap * mu;
+            lv[d] = c * mu;
+            x[d] = xs;
+            v[d] = vs;
+        }
+    }
+    if (!act) return;
+    float *rf = a.seg_f + static_cast<uint64_t>(seg) * kAdjSegF * NT + i;
+    double *rd = a.seg_d + static_cast<uint64_t>(seg) * kAdjSegD * NT + i;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        rf[d * NT] = lx[d];
+        rf[(3 + d) * NT] = lv[d];
+        rf[(6 + d) * NT] = xa[d];
+        rf[(9 + d) * NT] = xb[d];
+        rf[(12 + d) * NT] = va[d];
+        rf[(15 + d) * NT] = vb[d];
+        rf[(18 + d) * NT] = ga[d];
+        rf[(21 + d) * NT] = gb[d];
+    }
+    rd[0] = gk;
+    rd[NT] = gg;
+    rd[2 * NT] = gT;
+}
+
+// per-oscillator pass over the segment records, last segment first: the adjoint arriving at a
+// segment's end is what the later segments hand back; its response terms complete the gradient
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void ld_adjoint_combine_kernel(AdjArgs a) {
+    __shared__ double red[BLOCK / 64][6];
     const uint32_t tile = blockIdx.x;
     const uint32_t e = find_ensemble(a.ens, a.n_ens, tile);
     const EnsDev &E = a.ens[e];
     const AdjCoef A = a.adj[e];
     if (!A.inverse) return;  // the replay kernel owns this tile
-    const float h = A.f.h, c = A.f.c, kap = A.f.kap, sig = A.f.sig, inv_c = A.inv_c;
     const uint64_t i = E.offset + static_cast<uint64_t>(tile - E.tile_begin) * BLOCK + threadIdx.x;
     const bool act = i < E.offset + E.n;
-    const uint64_t col = act ? i : E.offset;  // inactive lanes follow a valid column
     const uint64_t NT = a.NT;
-    HybridTaus g;
-    float lx[3] = {0, 0, 0}, lv[3] = {0, 0, 0};
-    double gk = 0.0, gg = 0.0, gT = 0.0;
     const uint32_t nseg = (a.n_steps + a.K - 1) / a.K;
-    for (uint32_t seg = nseg; seg-- > 0;) {
-        const uint32_t s0 = seg * a.K;
-        const uint32_t s1 = (s0 + a.K < a.n_steps) ? s0 + a.K : a.n_steps;
-        // record seg + 1 holds the state at s1 (the end state for the last segment)
-        const float *rec = reinterpret_cast<const float *>(a.ckpt + static_cast<uint64_t>(seg + 1) * a.rec_bytes);
-        float x[3], v[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            x[d] = rec[d * NT + col];
-            v[d] = rec[(3 + d) * NT + col];
-        }
-        g.load(reinterpret_cast<const uint32_t *>(rec + 6 * NT), NT, col);
-        // x, v hold the state after step s on entry to step s
-        for (uint32_t s = s1; s-- > s0;) {
-            const bool in_loss = (s + 1 >= a.t_begin) && (s + 1 <= a.t_end);
-            const uint32_t w3 = g.prev();
-            const uint32_t w2 = g.prev();
-            const uint32_t w1 = g.prev();
-            const uint32_t w0 = g.prev();
-            float gf[3];
-            gaussian_forces(w0, w1, w2, w3, gf[0], gf[1], gf[2]);
+    const double dk = -static_cast<double>(A.dkap_dk), dcg = A.dc_dgamma, dsg = A.dsig_dgamma, dsT = A.dsig_dkT;
+    double gk = 0.0, gg = 0.0, gT = 0.0;
+    if (act) {
+        double ex[3] = {0, 0, 0}, ev[3] = {0, 0, 0};  // adjoint at the current segment's end
+        for (uint32_t seg = nseg; seg-- > 0;) {
+            const float *rf = a.seg_f + static_cast<uint64_t>(seg) * kAdjSegF * NT + i;
+            const double *rd = a.seg_d + static_cast<uint64_t>(seg) * kAdjSegD * NT + i;
+            gk += rd[0];
+            gg += rd[NT];
+            gT += rd[2 * NT];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                if (in_loss) lx[d] += 2.0f * x[d];
-                const float xs = x[d] - h * v[d];
-                const float vs = (v[d] + kap * xs - sig * gf[d]) * inv_c;
-                const float mu = lv[d] + h * lx[d];
-                gk += static_cast<double>(mu) * static_cast<double>(-A.dkap_dk * xs);
-                gg += static_cast<double>(mu) * static_cast<double>(A.dc_dgamma * vs + A.dsig_dgamma * gf[d]);
-                gT += static_cast<double>(mu) * static_cast<double>(A.dsig_dkT * gf[d]);
-                lx[d] = lx[d] - kap * mu;
-                lv[d] = c * mu;
-                x[d] = xs;
-                v[d] = vs;
+                const double rx = rf[(6 + d) * NT] * ex[d] + rf[(9 + d) * NT] * ev[d];
+                const double rv = rf[(12 + d) * NT] * ex[d] + rf[(15 + d) * NT] * ev[d];
+                const double rg = rf[(18 + d) * NT] * ex[d] + rf[(21 + d) * NT] * ev[d];
+                gk += dk * rx;
+                gg += dcg * rv + dsg * rg;
+                gT += dsT * rg;
+                // every segment but the last is K steps long, and the last one's end adjoint is 0
+                const double nx = rf[d * NT] + A.phi[0] * ex[d] + A.phi[1] * ev[d];
+                const double nv = rf[(3 + d) * NT] + A.phi[2] * ex[d] + A.phi[3] * ev[d];
+                ex[d] = nx;
+                ev[d] = nv;
             }
         }
     }
-    double qv[3] = {act ? gk : 0.0, act ? gg : 0.0, act ? gT : 0.0};
-    block_sum3<BLOCK>(qv, red, a.partials + static_cast<uint64_t>(tile) * 3);
+    block_grad_partials<BLOCK>(act, gk, gg, gT, red, a.partials + static_cast<uint64_t>(tile) * kAdjPartW);
 }
 
-__global__ __launch_bounds__(64) void adj_finalize_kernel(const double *partials, uint32_t width, const EnsDev *ens,
-                                                          double denom_steps, double *out) {
+__global__ __launch_bounds__(64) void adj_finalize_kernel(const double *partials, uint32_t width, bool spread,
+                                                          const EnsDev *ens, double denom_steps, double *out) {
     const uint32_t e = blockIdx.x;
     const EnsDev &E = ens[e];
-    const double denom = denom_steps * 3.0 * static_cast<double>(E.n);
+    const double n = static_cast<double>(E.n);
+    const double per_osc = denom_steps * 3.0;  // a per-oscillator sum over this is its contribution
+    const uint32_t ow = spread ? 2 * width : width;
     for (uint32_t qi = 0; qi < width; ++qi) {
-        double acc = 0.0;
-        for (uint32_t t = threadIdx.x; t < E.n_tiles; t += 64) acc += partials[(E.tile_begin + t) * 3ull + qi];
+        double acc = 0.0, acc2 = 0.0;
+        for (uint32_t t = threadIdx.x; t < E.n_tiles; t += 64) {
+            acc += partials[(E.tile_begin + t) * static_cast<uint64_t>(kAdjPartW) + qi];
+            acc2 += partials[(E.tile_begin + t) * static_cast<uint64_t>(kAdjPartW) + width + qi];
+        }
         acc = wave_sum(acc);
-        if (threadIdx.x == 0) out[static_cast<uint64_t>(e) * width + qi] = E.n ? acc / denom : 0.0;
+        acc2 = wave_sum(acc2);
+        if (threadIdx.x == 0) {
+            const double mean = E.n ? acc / (per_osc * n) : 0.0;
+            out[static_cast<uint64_t>(e) * ow + qi] = mean;
+            if (spread) {
+                // standard error of the mean of the per-oscillator contributions c_i = g_i / per_osc
+                double se = 0.0;
+                if (E.n > 1) {
+                    const double var = (acc2 / (per_osc * per_osc) - n * mean * mean) / (n - 1.0);
+                    se = var > 0.0 ? sqrt(var / n) : 0.0;
+                }
+                out[static_cast<uint64_t>(e) * ow + width + qi] = se;
+            }
+        }
     }
 }
 
@@ -321,15 +411,21 @@ hipError_t launch_ld_adjoint(int kind, const AdjArgs &a, bool any_replay, bool a
         const hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
-    if (any_inverse && kind == RNGLD_HYBRID_TAUS) ld_adjoint_inv_kernel<kAdjBlock><<<a.n_tiles, kAdjBlock, 0, st>>>(a);
+    if (any_inverse && kind == RNGLD_HYBRID_TAUS) {
+        const uint32_t nseg = (a.n_steps + a.K - 1) / a.K;
+        ld_adjoint_seg_kernel<kAdjBlock><<<dim3(a.n_tiles, nseg), kAdjBlock, 0, st>>>(a);
+        const hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+        ld_adjoint_combine_kernel<kAdjBlock><<<a.n_tiles, kAdjBlock, 0, st>>>(a);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_adj_finalize(const double *partials, uint32_t n_tiles, uint32_t width, const EnsDev *ens,
-                               uint32_t n_ens, double denom_steps, double *out, hipStream_t st) {
+hipError_t launch_adj_finalize(const double *partials, uint32_t n_tiles, uint32_t width, bool spread,
+                               const EnsDev *ens, uint32_t n_ens, double denom_steps, double *out, hipStream_t st) {
     (void)n_tiles;
     if (n_ens == 0) return hipSuccess;
-    adj_finalize_kernel<<<n_ens, 64, 0, st>>>(partials, width, ens, denom_steps, out);
+    adj_finalize_kernel<<<n_ens, 64, 0, st>>>(partials, width, spread, ens, denom_steps, out);
     return hipGetLastError();
 }
 

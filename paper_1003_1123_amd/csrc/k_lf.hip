@@ -87,6 +87,15 @@ __global__ __launch_bounds__(kBulkBlock) void lf_gauss_phase_kernel(LfRing L, fl
     out[first + 2 * t + 1] = r * s;
 }
 
+// one wave of the seeding discard: positions pos0 + first + t, t < count, generated into the ring
+// only (slots off_mod + t from pos0's); the header is advanced afterwards
+__global__ __launch_bounds__(kBulkBlock) void lf_discard_phase_kernel(LfRing L, uint32_t off_mod, uint32_t count) {
+    const uint32_t t = blockIdx.x * kBulkBlock + threadIdx.x;
+    if (t >= count) return;
+    const uint32_t s = wrap_once(wrap_once(L.hdr->slot + off_mod, L.R) + t, L.R);
+    L.ring[s] = L.ring[back(s, L.ll, L.R)] + L.ring[back(s, L.sl, L.R)];
+}
+
 __global__ void lf_advance_kernel(LfHeader *hdr, uint64_t count, uint32_t count_mod) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         hdr->pos += count;
@@ -851,6 +860,12 @@ hipError_t launch_lf_pad_in(const LfRing &L, uint32_t *pring, const LfPadRing &p
 hipError_t launch_lf_pad_out(const LfRing &L, const uint32_t *pring, const LfPadRing &pr, uint64_t Ptot,
                              hipStream_t st) {
     lf_pad_out_kernel<<<grid_for(L.ll), kBulkBlock, 0, st>>>(L, pring, pr, Ptot);
+    return hipGetLastError();
+}
+
+hipError_t launch_lf_discard_phase(const LfRing &L, uint32_t off_mod, uint32_t count, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    lf_discard_phase_kernel<<<(count + kBulkBlock - 1) / kBulkBlock, kBulkBlock, 0, st>>>(L, off_mod, count);
     return hipGetLastError();
 }
 

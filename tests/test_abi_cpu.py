@@ -44,7 +44,8 @@ def test_generator_kinds_match_header():
 
 
 def test_struct_layouts_match_header():
-    assert C.sizeof(R.Cfg) == 56 and R.Cfg.lcg_leap.offset == 48 and C.sizeof(R.Params) == 24 and C.sizeof(R.Ensemble) == 56
+    assert C.sizeof(R.Cfg) == 64 and R.Cfg.lcg_leap.offset == 48 and R.Cfg.lf_discard.offset == 56
+    assert C.sizeof(R.Params) == 24 and C.sizeof(R.Ensemble) == 56
     assert C.sizeof(R.Obs) == 8 and C.sizeof(R.Tuning) == 20 and C.sizeof(R.Loss) == 16
     assert R.Ensemble.seed.offset == 48 and R.Ensemble.p.offset == 16
 
@@ -173,18 +174,25 @@ def test_adjoint_sizing_and_validation():
     p = R.make_params()
     ens, n = R.make_ensembles([(0, 1000, p, 1)])
     loss = R.Loss(1001, 2000, 100, 0)
-    scratch = 9 * 100 * 1000 * 4
-    # weakly damped Hybrid Taus: register-only backward, no scratch
+    scratch = 9 * 100 * 1000 * 4  # replay: 9 floats per oscillator-step of one segment
+    records = 20 * 1000 * (24 * 4 + 3 * 8)  # register-only: 120 bytes per (oscillator, segment)
+    small = 64 * 1024  # ensemble tables and per-tile partials
+    # weakly damped Hybrid Taus: register-only backward, segment records only
     ws = R.ld_adjoint_workspace_bytes(c, ens, n, 1000, 2000, loss)
-    assert ws < scratch
-    # forced replay, strong damping (gamma dt = 0.05 at K = 100) and Ran2 need the scratch
-    assert R.ld_adjoint_workspace_bytes(c, ens, n, 1000, 2000, R.Loss(1001, 2000, 100, R.ADJ_REPLAY)) >= scratch
+    assert records <= ws < records + small
+    assert R.ld_adjoint_workspace_bytes(c, ens, n, 1000, 2000, R.Loss(1001, 2000, 100, R.ADJ_SPREAD)) == ws
+    # forced replay, strong damping (gamma dt = 0.05 at K = 100) and Ran2 need the replay scratch
+    ws_r = R.ld_adjoint_workspace_bytes(c, ens, n, 1000, 2000, R.Loss(1001, 2000, 100, R.ADJ_REPLAY))
+    assert scratch <= ws_r < scratch + small
     ens5, n5 = R.make_ensembles([(0, 500, p, 1), (500, 500, R.make_params(gamma=5.0), 2)])
-    assert R.ld_adjoint_workspace_bytes(c, ens5, n5, 1000, 2000, loss) >= scratch
+    assert R.ld_adjoint_workspace_bytes(c, ens5, n5, 1000, 2000, loss) >= scratch + records  # both paths
     c2 = R.make_cfg("ran2", n_streams=1000)
-    assert R.ld_adjoint_workspace_bytes(c2, ens, n, 1000, 2000, loss) >= scratch
+    assert scratch <= R.ld_adjoint_workspace_bytes(c2, ens, n, 1000, 2000, loss) < scratch + small
     with pytest.raises(R.RngldError) as e:
         R.ld_adjoint_workspace_bytes(c, ens, n, 1000, 2000, R.Loss(0, 2000, 100, 0))
+    assert e.value.code == R.EINVAL
+    with pytest.raises(R.RngldError) as e:
+        R.ld_adjoint_workspace_bytes(c, ens, n, 1000, 2000, R.Loss(1001, 2000, 100, 4))  # unknown flag
     assert e.value.code == R.EINVAL
     with pytest.raises(R.RngldError) as e:
         R.ld_ckpt_bytes(R.make_cfg("lf", ll=2281, sl=1252), 1000, 2000, 100)

@@ -163,10 +163,35 @@ def test_config2_lf_full_size_sampled():
     assert okx and okv
 
 
+def test_config2_lf_sampled_after_1000_steps():
+    """LF at config-2 size (N = 1e6, Table I's last row) for 1000 steps on the persistent path: 48
+    sampled oscillators against the oracle, which generates all 4e9 numbers of the one sequence in
+    order and integrates only the sampled oscillators, element by element."""
+    N, T = W.C2["N"], 1000
+    ll, sl = W.C2["lf_lags"]
+    p = W.C2["params"].as_f32()
+    _say("config2 lf sampled", N, T)
+    cfg, st, x, v = _setup("lf", N, ll=ll, sl=sl)
+    ens, n_ens = R.make_ensembles([(0, N, _params(p), 0)])
+    ws = R.ld_run(cfg, st, ens, n_ens, N, T, x, v)
+    assert R.ws_status(ws) == 0 and R.ws_lf_path(ws) == "dataflow"
+    ids = W.sampled_streams(N, 48)
+    win = orc.lf_seed(1234, ll)
+    xr, vr = orc.ld_run_lf_sampled(win, ll, sl, N, T, p.asdict(), ids)
+    idx = torch.as_tensor(ids, device="cuda")
+    okx, wx = _close(x.view(3, N)[:, idx].cpu().numpy(), xr, math.sqrt(p.kT / p.k))
+    okv, wv = _close(v.view(3, N)[:, idx].cpu().numpy(), vr, math.sqrt(p.kT / p.m))
+    _say("lf sampled worst", wx, wv)
+    assert okx and okv
+    pos, _, last = _lf_state(st)
+    assert pos == 4 * N * T and np.array_equal(last, win)
+
+
 def test_config2_lf_full_run_statistics():
     """The whole config-2 LF run (N = 1e6, 1e4 steps, Table I's last row, the persistent path):
-    completes without a failed wait, and equipartition holds over all 3e6 coordinates at the end,
-    as for the per-thread generators."""
+    completes without a failed wait, equals the wave path (one launch per wave of sl positions,
+    pinned to the oracle elsewhere) bit for bit in x, v and the sequence's last ll values, and
+    equipartition holds over all 3e6 coordinates at the end, as for the per-thread generators."""
     N, T = W.C2["N"], W.C2["steps"]
     ll, sl = W.C2["lf_lags"]
     p = W.C2["params"].as_f32()
@@ -181,6 +206,17 @@ def test_config2_lf_full_run_statistics():
     vv = float((v.double() ** 2).mean())
     _say("lf equipartition", xx / x2s, vv / v2s)
     assert abs(xx - x2s) < 5 * x2s * math.sqrt(2 / (3 * N)) and abs(vv - v2s) < 5 * v2s * math.sqrt(2 / (3 * N))
+    _say("config2 lf full run, wave path")
+    cfg_w, st_w, xw, vw = _setup("lf", N, ll=ll, sl=sl)
+    saved = R.ld_get_tuning("lf").astuple()
+    R.ld_set_tuning("lf", lf_waves=1)
+    try:
+        ws_w = R.ld_run(cfg_w, st_w, ens, n_ens, N, T, xw, vw)
+        assert R.ws_lf_path(ws_w) == "waves"
+    finally:
+        R.ld_set_tuning("lf", *saved)
+    assert torch.equal(x, xw) and torch.equal(v, vw)
+    assert _same_state("lf", st, st_w)
 
 
 # ---------------------------------------------------------------------------------------------
@@ -292,6 +328,61 @@ def test_config4_ensemble_statistics():
     z = np.array(z)
     _say("config 4 z: mean %.3f var %.3f max %.2f" % (z.mean(), z.var(), np.abs(z).max()))
     assert abs(z.mean()) < 0.25 and 0.7 < z.var() < 1.4 and np.abs(z).max() < 5.0
+
+
+def test_autotune_chooses_installs_caches_and_keeps_results(tmp_path):
+    """ld_autotune on a batched workload of uneven ensembles: the chosen tuning is valid and
+    installed, it is written to the cache file and read back from it (a second call measures
+    nothing and leaves the file alone; an entry edited in the file is what a third call installs),
+    a run under it equals the default tuning bit for bit in x, v and the generator state, and it
+    matches the oracle on sampled ensembles."""
+    ens_list = W.batched_ensembles(n_ens=24, n_lo=300, n_hi=40_000)
+    offs = np.concatenate([[0], np.cumsum([e.n for e in ens_list])])
+    n_total, T = int(offs[-1]), 3000
+    specs = [(int(offs[i]), e.n, _params(e.params), e.seed) for i, e in enumerate(ens_list)]
+    ens, n_ens = R.make_ensembles(specs)
+    cfg = R.make_cfg("taus", n_streams=n_total)
+    cache = tmp_path / "tune.txt"
+    default = R.ld_get_tuning("taus").astuple()
+    try:
+        t = R.ld_autotune(cfg, ens, n_ens, n_total, T, str(cache)).astuple()
+        _say("autotune", n_total, T, "->", t)
+        assert t[0] in (64, 128, 256, 512) and t[1] in (1, 2) and t[2] in (0, 500, 1000, 2500) and t[3] in (0, 4, 8)
+        assert t[4] == 0
+        assert R.ld_get_tuning("taus").astuple() == t
+        lines = cache.read_text().splitlines()
+        assert len(lines) == 1 and lines[0].split()[-4:] == [str(a) for a in t[:4]]
+        before = cache.stat().st_mtime_ns, cache.read_text()
+        R.ld_set_tuning("taus")
+        assert R.ld_autotune(cfg, ens, n_ens, n_total, T, str(cache)).astuple() == t
+        assert (cache.stat().st_mtime_ns, cache.read_text()) == before
+        edited = (128, 2, 500, 4, 0) if t[:4] != (128, 2, 500, 4) else (256, 1, 0, 0, 0)
+        cache.write_text(" ".join(lines[0].split()[:-4] + [str(a) for a in edited[:4]]) + "\n")
+        assert R.ld_autotune(cfg, ens, n_ens, n_total, T, str(cache)).astuple() == edited
+        assert R.ld_get_tuning("taus").astuple() == edited
+        # a run under the chosen tuning against the default tuning and the oracle
+        runs = []
+        for tune in (t, default):
+            R.ld_set_tuning("taus", *tune)
+            st = R.new_state(cfg)
+            R.rng_init_ensembles(cfg, st, ens, n_ens)
+            x = torch.zeros(3 * n_total, dtype=torch.float32, device="cuda")
+            v = torch.zeros_like(x)
+            R.ld_run(cfg, st, ens, n_ens, n_total, 1000, x, v)
+            torch.cuda.synchronize()
+            runs.append((x, v, st))
+        assert all(torch.equal(a, b) for a, b in zip(runs[0], runs[1]))
+        x = runs[0][0].view(3, n_total)
+        for i in (0, 7, n_ens - 1):
+            e = ens_list[i]
+            ids = np.arange(0, e.n, max(1, e.n // 64))
+            xr, _, _ = orc.ld_run("taus", orc.seed_states("taus", e.seed, ids), len(ids), 1000, e.params.asdict())
+            xg = x[:, int(offs[i]) + torch.as_tensor(ids, device="cuda")].cpu().numpy()
+            ok, worst = _close(xg, xr, math.sqrt(e.params.kT / e.params.k))
+            _say("autotuned ensemble", i, "worst", worst)
+            assert ok
+    finally:
+        R.ld_set_tuning("taus", *default)
 
 
 @pytest.mark.parametrize("tuning", [(64, 1, 0, 0), (128, 2, 0, 0), (256, 1, 37, 0), (512, 2, 0, 4), (256, 2, 100, 2)])

@@ -278,6 +278,54 @@ def test_lf_config3_one_stream_of_2_30():
     del out
 
 
+def _low_bit_balance(words: np.ndarray, bits: int = 8):
+    """Fraction of values with bit b set, b = 0..bits-1."""
+    return [float(((words >> np.uint32(b)) & np.uint32(1)).mean()) for b in range(bits)]
+
+
+@pytest.mark.parametrize("lags", [(2281, 1252), (44497, 23463), (3021377, 1010202)])
+def test_lf_discard_matches_oracle(lags):
+    """Seeding with a warm-up discard of 10 ll values (Alg. 3's initial seeds run forward): the
+    stream and a fused LD run from the seeded state equal the oracle bit for bit (the LD run to the
+    trajectory tolerance), and the state continues the sequence.  Reports the balance of bits 0-7
+    over 2^24 values with and without the discard."""
+    ll, sl = lags
+    D = 10 * ll
+    cfg = R.make_cfg("lf", seed=21, ll=ll, sl=sl, discard=D)
+    st = R.new_state(cfg)
+    R.rng_init(cfg, st)
+    n = 2**24
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    R.rng_uniform(cfg, st, n, out)
+    torch.cuda.synchronize()
+    win = orc.lf_seed(21, ll, sl, D)
+    ref = orc.lf_generate(ll, sl, win, n)
+    assert np.array_equal(_u32(out), ref)
+    nxt = torch.empty(999, dtype=torch.int32, device="cuda")
+    R.rng_uniform(cfg, st, 999, nxt)
+    assert np.array_equal(_u32(nxt), orc.lf_generate(ll, sl, win, 999))
+    cfg0 = R.make_cfg("lf", seed=21, ll=ll, sl=sl)
+    st0 = R.new_state(cfg0)
+    R.rng_init(cfg0, st0)
+    R.rng_uniform(cfg0, st0, n, out)
+    _say("lf discard", lags, "bit balance after the discard", _low_bit_balance(ref),
+         "without", _low_bit_balance(_u32(out)))
+    # a fused LD run from a discarded seeding
+    N, T = 500, 50
+    cfg = R.make_cfg("lf", seed=21, ll=ll, sl=sl, discard=D)
+    st = R.new_state(cfg)
+    R.rng_init(cfg, st)
+    p = W.LDParams().as_f32()
+    x = torch.zeros(3 * N, dtype=torch.float32, device="cuda")
+    v = torch.zeros_like(x)
+    ens, n_ens = R.make_ensembles([(0, N, R.make_params(p.m, p.k, p.gamma, p.kT, p.dt), 0)])
+    R.ld_run(cfg, st, ens, n_ens, N, T, x, v)
+    torch.cuda.synchronize()
+    xr, _, _ = orc.ld_run("lf", orc.lf_seed(21, ll, sl, D), N, T, p.asdict(), ll=ll, sl=sl)
+    err = np.abs(x.cpu().numpy().reshape(3, N).astype(np.float64) - xr)
+    assert np.all(err <= 1e-4 * (np.abs(xr) + 1.0))
+
+
 @pytest.mark.parametrize("lags,count", [((9689, 5502), 4 * 5502 + 777), ((44497, 23463), 10**6 + 3),
                                         ((132049, 54454), 3 * 10**6 + 17), ((3021377, 1010202), 4 * 1010202)])
 def test_lf_persistent_stream_matches_recurrence(lags, count):
@@ -360,15 +408,37 @@ def test_lf_stream_captured_in_a_graph():
 # the transform over its whole input domain
 
 def test_box_muller_exhaustive_24_bit_domain():
-    """Every 24-bit radius input (angle 0) and every 24-bit angle input (largest radius) against the
-    FP64 oracle: the worst case of each factor, so every Gaussian the library can produce is within
-    the bound."""
+    """Every 24-bit radius input (at angle 0) and every 24-bit angle input (at the largest radius)
+    against the FP64 oracle.  A Gaussian r cos(theta) or r sin(theta) is then off by at most
+    err_r + r_max err_trig, with err_r the worst radius error over all radius inputs and err_trig
+    the worst cosine/sine error over all angle inputs (the final FP32 product's rounding included),
+    so that bound covers every pair of words the library can meet."""
     k = np.arange(2**24, dtype=np.uint32) << np.uint32(8)
-    for words in (np.stack([k, np.zeros_like(k)], 1).ravel(), np.stack([np.zeros_like(k), k], 1).ravel()):
-        d = torch.as_tensor(words.view(np.int32), device="cuda")
-        out = torch.empty(words.size, dtype=torch.float32, device="cuda")
-        R.rng_box_muller(d, out)
-        ref = orc.box_muller_many(words)
-        err = float(np.max(np.abs(out.cpu().numpy().astype(np.float64) - ref)))
-        _say("box-muller exhaustive max abs err", err)
-        assert err <= GAUSS_TOL
+    zeros = np.zeros_like(k)
+    # radius pass: cos 0 = 1 and sin 0 = 0 exactly, so g0 is the radius and g1 is 0
+    words = np.stack([k, zeros], 1).ravel()
+    d = torch.as_tensor(words.view(np.int32), device="cuda")
+    out = torch.empty(words.size, dtype=torch.float32, device="cuda")
+    R.rng_box_muller(d, out)
+    g = out.cpu().numpy().astype(np.float64)
+    ref = orc.box_muller_many(words)
+    err_r = float(np.max(np.abs(g[0::2] - ref[0::2])))
+    assert np.all(g[1::2] == 0.0)
+    r_hat = g[0]  # the largest radius the library produces: u = 2^-24
+    r_max = math.sqrt(-2.0 * math.log(2.0**-24))
+    assert abs(r_hat - r_max) <= err_r
+    # angle pass at the largest radius: the cosine and sine as the library applies them
+    words = np.stack([zeros, k], 1).ravel()
+    d = torch.as_tensor(words.view(np.int32), device="cuda")
+    R.rng_box_muller(d, out)
+    g = out.cpu().numpy().astype(np.float64)
+    ref = orc.box_muller_many(words)
+    err_at_rmax = float(np.max(np.abs(g - ref)))
+    theta = 2.0 * math.pi * (k >> np.uint32(8)).astype(np.float64) * 2.0**-24
+    err_trig = float(max(np.max(np.abs(g[0::2] / r_hat - np.cos(theta))),
+                         np.max(np.abs(g[1::2] / r_hat - np.sin(theta)))))
+    bound = err_r + r_max * err_trig
+    _say("box-muller exhaustive: radius err", err_r, "trig err", err_trig, "at r_max", err_at_rmax,
+         "combined bound", bound)
+    assert err_at_rmax <= GAUSS_TOL
+    assert bound <= GAUSS_TOL

@@ -416,6 +416,22 @@ def test_lf_output_satisfies_recurrence():
     assert np.array_equal(win.astype(np.uint64), y[-ll:])
 
 
+@pytest.mark.parametrize("discard", [1, 1251, 1252, 2281, 22810, 100_003])
+def test_lf_discard_shifts_the_sequence(discard):
+    """Seeding with a discard D gives the sequence from position D on: its window is y_{D-ll..D-1}
+    of the undiscarded sequence (which satisfies Eq. 3 across the seeded window), and what it
+    generates next is y_{D}, y_{D+1}, ..."""
+    ll, sl = 2281, 1252
+    win0 = orc.lf_seed(77, ll)
+    hist = win0.astype(np.uint64).copy()
+    y = np.concatenate([hist, orc.lf_generate(ll, sl, win0, discard + 5000).astype(np.uint64)])
+    n = np.arange(ll, len(y))
+    assert np.array_equal(y[n], (y[n - ll] + y[n - sl]) % M32)
+    wd = orc.lf_seed(77, ll, sl, discard)
+    assert np.array_equal(wd.astype(np.uint64), y[discard:discard + ll])  # y[ll + m] = y_m
+    assert np.array_equal(orc.lf_generate(ll, sl, wd, 5000).astype(np.uint64), y[ll + discard:])
+
+
 def test_lf_seed_is_lcg_orbit_of_the_seed_word():
     a, c = CONST["lcg_a"][0], CONST["lcg_c"][0]
     win = orc.lf_seed(1234, 5000)

@@ -156,6 +156,28 @@ def test_lf_forces_consume_the_shared_sequence_in_thread_order():
             assert (g[t, 0, j], g[t, 1, j], g[t, 2, j]) == (gx, gy, gz)
 
 
+@pytest.mark.parametrize("N,T,scheme", [(3000, 60, 0), (1, 500, 0), (257, 40, 1)])
+def test_lf_sampled_run_equals_the_full_run(N, T, scheme):
+    """The sampled lagged-Fibonacci run follows its oscillators exactly as the full run does
+    (same words, same order, same arithmetic), and leaves the sequence at the same place."""
+    ll, sl = 2281, 1252
+    p = dict(m=1.0, k=1.3, gamma=0.7, kT=0.9, dt=0.01)
+    rng = np.random.Generator(np.random.PCG64(5))
+    ids = np.unique(np.concatenate([[0, N - 1], rng.integers(0, N, 20)]))
+    win_s, win_f = orc.lf_seed(8, ll), orc.lf_seed(8, ll)
+    xs, vs = orc.ld_run_lf_sampled(win_s, ll, sl, N, T, p, ids, scheme=scheme)
+    xf, vf, _ = orc.ld_run("lf", win_f, N, T, p, ll=ll, sl=sl, scheme=scheme)
+    assert np.array_equal(xs, xf[:, ids]) and np.array_equal(vs, vf[:, ids])
+    assert np.array_equal(win_s, win_f)
+
+
+def test_lf_sampled_run_rejects_bad_ids():
+    with pytest.raises(RuntimeError):
+        orc.ld_run_lf_sampled(orc.lf_seed(1, 2281), 2281, 1252, 10, 2, P1, [3, 3])
+    with pytest.raises(RuntimeError):
+        orc.ld_run_lf_sampled(orc.lf_seed(1, 2281), 2281, 1252, 10, 2, P1, [10])
+
+
 # ---------------------------------------------------------------------------------------------
 # exact discrete moments
 

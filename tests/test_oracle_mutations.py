@@ -59,6 +59,11 @@ MUTATIONS = [
      "q.ods = sqrt(2.0 * kT * dt * xi);", [L + "test_fig4_overdamped_statistics_oracle"]),
     ("overdamped drift 1% high", "q.odc = k * dt / xi;", "q.odc = k * dt / xi * 1.01;",
      [L + "test_overdamped_noise_free_decay_and_closed_forms"]),
+    ("LF discard one value short", "return orc_lf_generate(ll, sl, win, discard, NULL);",
+     "return orc_lf_generate(ll, sl, win, discard ? discard - 1 : 0, NULL);",
+     [G + "test_lf_discard_shifts_the_sequence"]),
+    ("sampled LF run with the short lag read as ll - sl", "uint32_t head = 0, tail = ll - sl;",
+     "uint32_t head = 0, tail = sl;", [L + "test_lf_sampled_run_equals_the_full_run"]),
 ]
 
 
