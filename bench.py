@@ -29,16 +29,57 @@ GENERATORS = ("taus", "ran2", "lf")
 
 # Work per oscillator-step.
 # Taus and Ran2 are bound by vector-ALU issue: the lane-instructions that the compiled step loop of
-# ld_run_kernel (underdamped scheme, gfx950) issues per oscillator-step, LDS accesses not counted.
-VALU_PER_OSC_STEP = {"taus": 117, "ran2": 126}
+# ld_run_kernel (underdamped scheme, gfx950) issues per oscillator-step, LDS accesses not counted,
+# as the build counts them in the assembly it compiles (kernel_isa.json, "step_loops").
+STEP_LOOP_KERNELS = {"taus": "ld_run_kernel<HybridTaus,256,1>", "ran2": "ld_run_kernel<Ran2,256,1>",
+                     "lcg": "ld_run_kernel<Lcg32,256,1>", "adjoint_forward": "ld_ckpt_kernel<HybridTaus,256>",
+                     "adjoint_backward": "ld_adjoint_seg_kernel<256>"}
 # Measured bound of those loops: each instruction class at the issue rate the VALU probe measured
-# for it (profiles/valu_issue_rates.md), times added (transcendentals do not overlap other VALU work),
-# except that a 32-bit multiply interleaved with other integer work costs what the probe's mixed
-# multiply + xor kernel shows (1.2e-14 s of chip time per lane-operation, against 3.0e-14 alone);
-# in oscillator-steps/s.  Class counts per oscillator-step, Taus / Ran2: 7 / 7 transcendental,
-# 4 / 12 32-bit multiplies, 4 / 4 conversions, 16 / 24 three-operand integer ops, 21 / 21 FP32
-# mul/add/fma, 65 / 58 other; Ran2's 8 LDS accesses run on their own pipe, far below its limit.
-VALU_MIX_BOUND_OSC_STEPS = {"taus": 3.75e11, "ran2": 3.50e11}
+# for it (profiles/valu_issue_rates.md, lane-instructions per second over the chip), times added
+# (transcendentals do not overlap other VALU work), except that a 32-bit multiply interleaved with
+# other integer work costs what the probe's mixed multiply + xor kernel shows (1.2e-14 s of chip
+# time per lane-operation, against 3.0e-14 alone).  Class of each opcode of the compiled loop:
+VALU_CLASS_RATES = {"transcendental": 1.905e13, "mul32": 1.0 / 1.2e-14, "cvt": 3.534e13, "three_operand": 3.433e13,
+                    "fp32": 5.951e13, "other": 4.917e13}
+VALU_CLASSES = {
+    "transcendental": ("v_log_f32", "v_exp_f32", "v_sqrt_f32", "v_rsq_f32", "v_rcp_f32", "v_sin_f32", "v_cos_f32"),
+    "mul32": ("v_mul_lo_u32", "v_mul_hi_u32", "v_mul_hi_i32", "v_mad_u64_u32", "v_mad_i64_i32"),
+    "cvt": ("v_cvt_f32_u32", "v_cvt_f32_i32", "v_cvt_u32_f32", "v_cvt_i32_f32"),
+    "three_operand": ("v_and_or_b32", "v_bitop3_b32", "v_alignbit_b32", "v_mad_u32_u24", "v_lshl_add_u32",
+                      "v_lshl_or_b32", "v_or3_b32", "v_add3_u32", "v_xad_u32", "v_bfe_u32", "v_bfi_b32",
+                      "v_perm_b32", "v_cndmask_b32_e64", "v_add_lshl_u32"),
+    "fp32": ("v_mul_f32", "v_add_f32", "v_sub_f32", "v_fma_f32", "v_fmac_f32", "v_mac_f32", "v_fmamk_f32",
+             "v_fmaak_f32"),
+    "unmeasured": ("v_add_f64", "v_mul_f64", "v_fma_f64", "v_fmac_f64", "v_cvt_f64_f32", "v_cvt_f32_f64"),
+}
+
+
+def valu_classes(by_opcode):
+    """Instruction counts of a loop by issue class."""
+    out = {}
+    for op, n in by_opcode.items():
+        cls = "other"
+        for c, names in VALU_CLASSES.items():
+            if any(op == nm or op.startswith(nm + "_e") for nm in names) or op in names:
+                cls = c
+                break
+        out[cls] = out.get(cls, 0) + n
+    return out
+
+
+def valu_mix_bound(which):
+    """Oscillator-steps/s a step loop's instruction mix allows at the measured per-class issue rates
+    (None when it holds instructions the probe did not measure, e.g. FP64)."""
+    loops = _kernel_isa().get("step_loops", {})
+    name = STEP_LOOP_KERNELS[which]
+    if name not in loops:
+        return None
+    cls = valu_classes(loops[name]["by_opcode"])
+    if cls.get("unmeasured"):
+        return None
+    return 1.0 / sum(n / VALU_CLASS_RATES[c] for c, n in cls.items())
+
+
 # VALU lane-operation peak: 256 CUs x 128 lanes per clock x 2.4 GHz (the published 157.3 TFLOP/s FP32
 # vector rate counts an FMA as two flops).
 ALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
@@ -73,13 +114,38 @@ COUNTER_TRAFFIC = {
 }
 
 
-def built_isa(kernel):
+def _kernel_isa():
     path = os.path.join(ROOT, "paper_1003_1123_amd", "kernel_isa.json")
     try:
         with open(path) as f:
-            return json.load(f).get(kernel, {}).get("sha256")
+            return json.load(f)
     except (OSError, ValueError):
-        return None
+        return {}
+
+
+def built_isa(kernel):
+    return _kernel_isa().get(kernel, {}).get("sha256")
+
+
+def valu_per_osc_step(which):
+    """VALU lane-instructions per iteration of a kernel's compiled step loop (one oscillator-step)."""
+    loops = _kernel_isa().get("step_loops", {})
+    name = STEP_LOOP_KERNELS[which]
+    if name not in loops:
+        raise RuntimeError("kernel_isa.json has no step-loop count for %s: rebuild the library" % name)
+    return loops[name]["valu_per_iteration"]
+
+
+def valu_entry(kernel, valu_per_unit, units, seconds, mix_bound_units_per_s=None):
+    """VALU roofline of `units` oscillator-steps (each `valu_per_unit` lane-instructions) in `seconds`."""
+    achieved = valu_per_unit * units / seconds / 1e12
+    out = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / ALU_PEAK_TOPS,
+           "kernel": kernel, "valu_lane_instr_per_osc_step": valu_per_unit, "osc_steps_per_s": units / seconds}
+    if mix_bound_units_per_s:
+        pm = valu_per_unit * mix_bound_units_per_s / 1e12
+        out.update({"peak_measured": pm, "frac_measured": achieved / pm,
+                    "peak_measured_how": "instruction mix of the step loop at the probe's per-class issue rates"})
+    return out
 
 
 def counter_traffic(kernel):
@@ -152,10 +218,18 @@ class Config2:
     def elapsed(self):
         return {k: self.events[k][0].elapsed_time(self.events[k][1]) for k in self.kinds}
 
+    def check_status(self):
+        """Every run of the step finished without a failed wait (a persistent lagged-Fibonacci run
+        that gives up stops early and marks its results invalid: its time must not be reported)."""
+        for k in self.kinds:
+            st = self.R.ws_status(self.ws[k])
+            if st != 0:
+                raise RuntimeError("the %s run reported status %d: its results are invalid" % (k, st))
+
 
 def roofline_entry(kind, ms_run, N, T, lf_path=None):
-    """Roofline of one ld_run of N oscillators x T steps.  The events bracket the whole ld_run call;
-    its kernel is all but a few microseconds of it."""
+    """Roofline of one ld_run of N oscillators x T steps.  The events bracket the whole ld_run call
+    on the stream its kernels run on; the kernel is all but a few microseconds of it."""
     osc_steps = N * T
     if kind == "lf":
         if lf_path == "dataflow":
@@ -168,21 +242,21 @@ def roofline_entry(kind, ms_run, N, T, lf_path=None):
         achieved = per_launch_bytes / per_launch_s / 1e9
         return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(kernel), "kernel": kernel,
+                "memory_level": ("memory-side cache: the run's ring (about 32 MB) stays resident in the "
+                                 "256 MB infinity cache behind the device-scope accesses, which bypass the "
+                                 "XCDs' L2; 'frac' is against the nominal HBM peak only as the contract's "
+                                 "reference, 'frac_measured' against what this access mix sustains"),
                 "peak_measured": LF_MEASURED_PEAK_GBS, "frac_measured": achieved / LF_MEASURED_PEAK_GBS,
-                "peak_measured_how": "wide-access probe, device-scope 16-byte accesses, 2 loads + 1 store per word, 32 MB",
+                "peak_measured_how": "device-scope 16-byte loads and stores, 2 loads + 1 store per word, over "
+                                     "a 32 MB region (profiles/wide_access.md, mode 4)",
                 "lf_path": lf_path, "launches": launches, "avg_launch_us": per_launch_s * 1e6,
                 "algorithmic_bytes_per_osc_step": per_os, "algorithmic_bytes_per_launch": per_launch_bytes}
     per_launch_s = ms_run / 1e3
-    ops = VALU_PER_OSC_STEP[kind] * osc_steps
-    achieved = ops / per_launch_s / 1e12
-    kernel = "ld_run_kernel<%s>" % kind
-    peak_measured = VALU_PER_OSC_STEP[kind] * VALU_MIX_BOUND_OSC_STEPS[kind] / 1e12
-    return {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
-            "frac": achieved / ALU_PEAK_TOPS, "traffic": counter_traffic(kernel), "kernel": kernel,
-            "peak_measured": peak_measured, "frac_measured": achieved / peak_measured,
-            "peak_measured_how": "instruction mix of the step loop at the probe's per-class issue rates",
-            "launches": 1, "avg_launch_us": per_launch_s * 1e6,
-            "valu_lane_instr_per_osc_step": VALU_PER_OSC_STEP[kind], "algorithmic_ops_per_launch": ops}
+    vpos = valu_per_osc_step(kind)
+    e = valu_entry("ld_run_kernel<%s>" % kind, vpos, osc_steps, per_launch_s, valu_mix_bound(kind))
+    e.update({"traffic": counter_traffic(e["kernel"]), "launches": 1, "avg_launch_us": per_launch_s * 1e6,
+              "algorithmic_ops_per_launch": vpos * osc_steps})
+    return e
 
 
 def host_cpu():
@@ -291,12 +365,109 @@ def cpu_all_cores(W, lf_rate):
                       "the one-thread figure (one sequence)" % cores}
 
 
+def _c3_slice(args):
+    """One worker of the config-3 all-cores leg: uniform streams [lo, hi) of the oracle."""
+    kind, seed, lo, hi, per = args
+    import numpy as np
+    import oracle as orc
+
+    orc.uniform_streams(kind, orc.seed_states(kind, seed, np.arange(lo, hi)), per)
+
+
+def cpu_extras(W):
+    """The oracle on bounded samples of configs 3-5, every figure labelled with what was measured
+    and how it scales: config 3 (bare streams, one core and all cores; the lagged Fibonacci stream
+    on one core, being one sequence), config 4 (8 sampled ensembles, extrapolated to the whole
+    batch), config 5 (adjoint and the common-random-number differences at N = 2000, extrapolated)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    import numpy as np
+    import oracle as orc
+
+    out = {}
+    c3 = W.C3
+    S_s, per = 2**12, 1024  # 4.2e6 values per generator
+    c3o = {}
+    for kind in ("taus", "ran2", "lcg"):
+        st = orc.seed_states(kind, c3["seed"], np.arange(S_s))
+        t = time.perf_counter()
+        orc.uniform_streams(kind, st, per)
+        c3o[kind] = {"uint32_per_s_1core": S_s * per / (time.perf_counter() - t)}
+        st = orc.seed_states(kind, c3["seed"], np.arange(S_s // 4))
+        t = time.perf_counter()
+        orc.gaussian_streams(kind, st, per)
+        c3o[kind]["gaussians_per_s_1core"] = S_s // 4 * per / (time.perf_counter() - t)
+    ll, sl = c3["lf_lags"]
+    win = orc.lf_seed(c3["seed"], ll)
+    t = time.perf_counter()
+    orc.lf_generate(ll, sl, win, 2**23, keep=False)
+    c3o["lf"] = {"uint32_per_s_1core": 2**23 / (time.perf_counter() - t)}
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    with cf.ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("spawn")) as ex:
+        list(ex.map(_c3_slice, [("taus", 1, 0, 8, 8)] * cores))  # worker start-up is not timed
+        for kind in ("taus", "ran2", "lcg"):
+            per_core = 2**14
+            jobs = [(kind, c3["seed"], i * per_core, (i + 1) * per_core, per) for i in range(cores)]
+            t = time.perf_counter()
+            list(ex.map(_c3_slice, jobs))
+            c3o[kind]["uint32_per_s_all_cores"] = cores * per_core * per / (time.perf_counter() - t)
+    out["config3"] = {"per_generator": c3o, "cores": cores,
+                      "sample": "uint32: 4096 streams x 1024 values per generator on one core, 16384 streams x 1024 "
+                                "per core on all cores; Gaussians: 1024 streams x 1024; lagged Fibonacci: 2^23 values "
+                                "of the one sequence on one core"}
+    c4 = W.C4
+    ens_list = W.batched_ensembles(c4["n_ens"], c4["draw_seed"], c4["base_seed"], c4["dt"])
+    total = sum(e.n for e in ens_list) * c4["steps"]
+    n_os, t_os = 0, 0.0
+    for i in range(0, c4["n_ens"], c4["n_ens"] // 8):
+        e = ens_list[i]
+        n = min(e.n, 400)
+        st = orc.seed_states("taus", e.seed, np.arange(n))
+        t = time.perf_counter()
+        orc.ld_run("taus", st, n, c4["steps"], e.params.asdict())
+        t_os += time.perf_counter() - t
+        n_os += n * c4["steps"]
+    out["config4"] = {"osc_steps_per_s_1core": n_os / t_os, "extrapolated_s_whole_batch_1core": total * t_os / n_os,
+                      "sample": "8 ensembles (every 64th), the first min(n, 400) oscillators of each x 5000 steps "
+                                "(%d oscillator-steps), extrapolated to all %d" % (n_os, total)}
+    c5 = W.C5
+    pp = c5["params"].as_f32().asdict()
+    N5 = 2000
+    t = time.perf_counter()
+    orc.ld_adjoint("taus", orc.seed_states("taus", c5["seed"], np.arange(N5)), N5, c5["steps"], pp, c5["t_begin"],
+                   c5["t_end"])
+    t_adj = time.perf_counter() - t
+    t = time.perf_counter()
+    for name in ("k", "gamma", "kT"):
+        for sgn in (1, -1):
+            q = dict(pp)
+            q[name] *= 1 + sgn * 5e-2
+            orc.ld_loss("taus", orc.seed_states("taus", c5["seed"], np.arange(N5)), N5, c5["steps"], q,
+                        c5["t_begin"], c5["t_end"])
+    t_fd = time.perf_counter() - t
+    out["config5"] = {"N": N5, "adjoint_s_1core": t_adj, "crn_fd_6_forwards_s_1core": t_fd,
+                      "extrapolated_to_N_1e5": {"adjoint_s_1core": t_adj * 1e5 / N5,
+                                                "crn_fd_6_forwards_s_1core": t_fd * 1e5 / N5},
+                      "sample": "N = 2000 oscillators, 2000 steps, extrapolated linearly to config 5's N = 1e5"}
+    return out
+
+
 def _ev(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
 def extra_config3(R, W, torch):
-    """Bare generators: 2^30 uint32 and 2^30 Gaussians per generator."""
+    """Bare generators: 2^30 uint32 and 2^30 Gaussians per generator (per-thread kinds: 2^20 streams
+    x 1024 values; lagged Fibonacci: one stream).  Each call is timed with events on the stream it
+    runs on, after an untimed warm-up call.  Bytes per value: the 4 written, plus for the lagged
+    Fibonacci stream the long-lag source read back from the output (its short-lag source stays in
+    registers); the per-thread generators' state (16 or 140 bytes per stream, in and out) adds
+    0.03 and 0.27 bytes per value."""
     ev = lambda: _ev(torch)
     c3 = W.C3
     S, per = c3["streams"], c3["per_stream"]
@@ -304,6 +475,7 @@ def extra_config3(R, W, torch):
     buf_u = torch.empty(n_vals, dtype=torch.int32, device="cuda")
     buf_g = torch.empty(n_vals, dtype=torch.float32, device="cuda")
     bare = {}
+    state_bytes = {"taus": 16, "ran2": 140, "lcg": 4}
     for kind in GENERATORS + ("lcg",):
         if kind == "lf":
             cfg = R.make_cfg("lf", seed=c3["seed"], ll=c3["lf_lags"][0], sl=c3["lf_lags"][1])
@@ -318,14 +490,28 @@ def extra_config3(R, W, torch):
         a.record()
         R.rng_uniform(cfg, st, count, buf_u)
         b.record()
+        if kind == "lf" and R.lf_stream_status(st) != 0:
+            raise RuntimeError("the persistent lagged-Fibonacci stream gave up a wait: invalid output")
         c, d = ev()
         c.record()
         R.rng_gaussian(cfg, st, count, buf_g)
         d.record()
         torch.cuda.synchronize()
-        bare[kind] = {"uint32_per_s": n_vals / (a.elapsed_time(b) / 1e3),
-                      "gaussians_per_s": n_vals / (c.elapsed_time(d) / 1e3),
-                      "uint32_GBps_written": 4 * n_vals / (a.elapsed_time(b) / 1e3) / 1e9}
+        if kind == "lf" and R.lf_stream_status(st) != 0:
+            raise RuntimeError("the persistent lagged-Fibonacci stream gave up a wait: invalid output")
+        tu, tg = a.elapsed_time(b) / 1e3, c.elapsed_time(d) / 1e3
+        if kind == "lf":
+            bpv_u, bpv_g = 8.0, 16.0  # Gaussians: integers written and read back, floats written over them
+        else:
+            bpv_u = bpv_g = 4.0 + 2.0 * state_bytes[kind] * S / n_vals
+        ru, rg = bpv_u * n_vals / tu / 1e9, bpv_g * n_vals / tg / 1e9
+        bare[kind] = {"uint32_per_s": n_vals / tu, "gaussians_per_s": n_vals / tg,
+                      "uint32_GBps_written": 4 * n_vals / tu / 1e9,
+                      "roofline_uint32": {"bound": "hbm", "achieved": ru, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                          "frac": ru / HBM_PEAK_GBS, "bytes_per_value": bpv_u},
+                      "roofline_gaussian": {"bound": "hbm", "achieved": rg, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                            "frac": rg / HBM_PEAK_GBS, "bytes_per_value": bpv_g}}
+        del st
     del buf_u, buf_g
     return bare
 
@@ -344,7 +530,9 @@ def extra_config4(R, W, torch):
     ens, n_ens = R.make_ensembles(specs)
     cfg = R.make_cfg("taus", n_streams=n_total)
     # RNGLD_AUTOTUNE_CACHE names a file that keeps the chosen launch shape between runs (none by default)
+    t_tune = time.perf_counter()
     tune = R.ld_autotune(cfg, ens, n_ens, n_total, c4["steps"], os.environ.get("RNGLD_AUTOTUNE_CACHE") or None)
+    t_tune = time.perf_counter() - t_tune
     st = R.new_state(cfg)
     x = torch.zeros(3 * n_total, dtype=torch.float32, device="cuda")
     v = torch.zeros_like(x)
@@ -373,64 +561,77 @@ def extra_config4(R, W, torch):
     R.ld_set_tuning("taus")
     osc_steps = n_total * c4["steps"]
     res = {"ensembles": n_ens, "oscillators": n_total, "steps": c4["steps"],
-                              "osc_steps": osc_steps, "tuning": list(tune.astuple()),
-                              "batched_graph_osc_steps_per_s": osc_steps / t_batched,
-                              "plain_512_launches_osc_steps_per_s": osc_steps / t_plain,
-                              "speedup_batched_vs_plain": t_plain / t_batched}
+           "osc_steps": osc_steps, "tuning": list(tune.astuple()), "autotune_s": t_tune,
+           "batched_graph_osc_steps_per_s": osc_steps / t_batched,
+           "plain_512_launches_osc_steps_per_s": osc_steps / t_plain,
+           "speedup_batched_vs_plain": t_plain / t_batched,
+           "roofline": valu_entry("ld_run_kernel<HybridTaus> (batched)", valu_per_osc_step("taus"), osc_steps,
+                                  t_batched, valu_mix_bound("taus"))}
     del x, v, st, ws
     return res
 
 
 def extra_config5(R, W, torch):
-    """Adjoint: forward with checkpoints, backward (register-only for config 5's weak damping, and
-    by segment replay for comparison); fwd+bwd over fwd time.  One untimed pass first loads the
-    kernels and sizes the buffers."""
+    """Adjoint at config 5 (N = 1e5, 2000 steps from rest, loss over steps 1001-2000, K = 100):
+    forward with checkpoints and backward, each timed with events on the stream they run on, for
+    the register-only (segment-parallel) backward and the replay backward; every pass starts a fresh
+    run from rest (one untimed pass first loads the kernels).  Also the 6 forward runs of
+    common-random-number central differences that the gradient replaces."""
     from paper_1003_1123_amd import autograd as A
     c5 = W.C5
     p5 = c5["params"].as_f32()
-    out = {"N": c5["N"], "steps": c5["steps"], "K": c5["K"]}
+    N, T = c5["N"], c5["steps"]
+    out = {"N": N, "steps": T, "K": c5["K"]}
+    osc = N * T
+
+    def one(replay):
+        run = A.AdjointRun("taus", [(N, p5.m, p5.dt, c5["seed"])], T, c5["t_begin"], c5["t_end"], c5["K"],
+                           replay=replay, spread=True)
+        k = torch.tensor([p5.k], dtype=torch.float64, requires_grad=True)
+        g = torch.tensor([p5.gamma], dtype=torch.float64, requires_grad=True)
+        kT = torch.tensor([p5.kT], dtype=torch.float64, requires_grad=True)
+        torch.cuda.synchronize()
+        e0, e1 = _ev(torch)
+        e2 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        L = A.LDAdjoint.apply(k, g, kT, run)
+        e1.record()
+        L.sum().backward()
+        e2.record()
+        torch.cuda.synchronize()
+        return run, L.item(), [k.grad.item(), g.grad.item(), kT.grad.item()], e0.elapsed_time(e1), e1.elapsed_time(e2)
+
     for replay in (False, True):
-        run = A.AdjointRun("taus", [(c5["N"], p5.m, p5.dt, c5["seed"])], c5["steps"], c5["t_begin"], c5["t_end"],
-                           c5["K"], replay=replay)
-        for rep in range(2):
-            k = torch.tensor([p5.k], dtype=torch.float64, requires_grad=True)
-            g = torch.tensor([p5.gamma], dtype=torch.float64, requires_grad=True)
-            kT = torch.tensor([p5.kT], dtype=torch.float64, requires_grad=True)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            L = A.LDAdjoint.apply(k, g, kT, run)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            L.sum().backward()
-            torch.cuda.synchronize()
-            t2 = time.perf_counter()
-        osc = c5["N"] * c5["steps"]
-        scratch = 9 * c5["K"] * c5["N"] * 4
-        fd_ms = None
+        one(replay)  # loads the kernels
+        run, L, grad, fwd_ms, bwd_ms = one(replay)
+        res = {"backward_path": "replay" if replay else "register-only, segment-parallel",
+               "loss": L, "grad_k_gamma_kT": grad, "grad_standard_errors": run.grad_se[0].tolist(),
+               "forward_ms": fwd_ms, "backward_ms": bwd_ms, "fwd_plus_bwd_over_fwd": (fwd_ms + bwd_ms) / fwd_ms,
+               "forward_osc_steps_per_s": osc / (fwd_ms / 1e3),
+               "roofline_forward": valu_entry("ld_ckpt_kernel<HybridTaus>", valu_per_osc_step("adjoint_forward"),
+                                              osc, fwd_ms / 1e3)}
         if not replay:
+            res["roofline_backward"] = valu_entry("ld_adjoint_seg_kernel + combine",
+                                                  valu_per_osc_step("adjoint_backward"), osc, bwd_ms / 1e3)
             # the common-random-number central differences the gradient replaces: 6 forward runs
-            torch.cuda.synchronize()
-            t3 = time.perf_counter()
+            e0, e1 = _ev(torch)
+            runs = []
             for name in ("k", "gamma", "kT"):
                 for sgn in (1, -1):
                     q = {"k": p5.k, "gamma": p5.gamma, "kT": p5.kT}
-                    q[name] *= 1 + sgn * 1e-2
-                    r = A.AdjointRun("taus", [(c5["N"], p5.m, p5.dt, c5["seed"])], c5["steps"], c5["t_begin"],
-                                     c5["t_end"], c5["K"])
-                    A.LDAdjoint.apply(*(torch.tensor([q[n]], dtype=torch.float64) for n in ("k", "gamma", "kT")), r)
+                    q[name] *= 1 + sgn * 5e-2
+                    runs.append((A.AdjointRun("taus", [(N, p5.m, p5.dt, c5["seed"])], T, c5["t_begin"], c5["t_end"],
+                                              c5["K"]), q))
             torch.cuda.synchronize()
-            fd_ms = (time.perf_counter() - t3) * 1e3
-        res = {"backward_path": "replay" if run.ws.numel() >= scratch else "register-only",
-               "loss": L.item(), "grad_k_gamma_kT": [k.grad.item(), g.grad.item(), kT.grad.item()],
-               "forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3,
-               "fwd_plus_bwd_over_fwd": (t2 - t0) / (t1 - t0), "forward_osc_steps_per_s": osc / (t1 - t0)}
-        if fd_ms is not None:
-            res["crn_fd_6_forwards_ms"] = fd_ms
-        if replay:
-            out["replay"] = res
-        else:
+            e0.record()
+            for r, q in runs:
+                A.LDAdjoint.apply(*(torch.tensor([q[n]], dtype=torch.float64) for n in ("k", "gamma", "kT")), r)
+            e1.record()
+            torch.cuda.synchronize()
+            res["crn_fd_6_forwards_ms"] = e0.elapsed_time(e1)
             out.update(res)
-        del run
+        else:
+            out["replay"] = res
     return out
 
 
@@ -463,7 +664,8 @@ def extra_fig6_breakdown(R, W, torch, cpu=True):
     chunk_words = 2**28  # bare-stream output buffer: 1 GiB
     buf = torch.empty(chunk_words, dtype=torch.int32, device="cuda")
     for N in Ns:
-        row = {"N": N, "full_ms": {}, "rng_only_ms": {}, "cpu_ms": {}, "speedup_vs_cpu": {}}
+        row = {"N": N, "full_ms": {}, "rng_only_ms": {}, "cpu_ms_extrapolated": {}, "cpu_measured_osc_steps": {},
+               "speedup_vs_cpu": {}}
         ens, n_ens = R.make_ensembles([(0, N, p, 0)])
         x = torch.zeros(3 * N, dtype=torch.float32, device="cuda")
         v = torch.zeros_like(x)
@@ -486,6 +688,8 @@ def extra_fig6_breakdown(R, W, torch, cpu=True):
             if kind == "lf":
                 row["lf_lags"] = [ll, sl]
                 row["lf_path"] = R.ws_lf_path(ws)
+                if R.ws_status(ws) != 0:
+                    raise RuntimeError("the lagged-Fibonacci run at N=%d gave up a wait: invalid results" % N)
             if kind != "none":
                 R.rng_init(cfg, st)
                 total = 4 * N * T
@@ -531,14 +735,16 @@ def extra_fig6_breakdown(R, W, torch, cpu=True):
                 t = time.perf_counter()
                 orc.ld_run(kind, stc, N, n_cpu, pd, ll=ll, sl=sl)
                 per_os = (time.perf_counter() - t) / (N * n_cpu)
-                row["cpu_ms"][kind] = per_os * N * T * 1e3
-                row["speedup_vs_cpu"][kind] = row["cpu_ms"][kind] / row["full_ms"][kind]
+                row["cpu_measured_osc_steps"][kind] = N * n_cpu
+                row["cpu_ms_extrapolated"][kind] = per_os * N * T * 1e3
+                row["speedup_vs_cpu"][kind] = row["cpu_ms_extrapolated"][kind] / row["full_ms"][kind]
         rows.append(row)
         log("fig6 N=%d: %s" % (N, json.dumps(row)))
         del x, v
     del buf
     return {"steps": T, "ms_per_1000_steps": rows,
-            "cpu": "FP64 oracle, one thread, %s oscillator-steps per point" % "about 2e5"}
+            "cpu": "FP64 oracle, one thread: timed on N x max(1, 2e5 // N) oscillator-steps per point "
+                   "(cpu_measured_osc_steps) and extrapolated linearly to N x 1000 (cpu_ms_extrapolated)"}
 
 
 def extra_step_protocol(R, W, torch):
@@ -618,6 +824,7 @@ def main():
     for i in range(args.warmup):
         c2.step()
         torch.cuda.synchronize()
+        c2.check_status()
         log("warmup step %d done" % i)
     acc = {k: 0.0 for k in kinds}
     torch.cuda.synchronize()
@@ -627,6 +834,7 @@ def main():
         torch.cuda.synchronize()
         for k, ms in c2.elapsed().items():
             acc[k] += ms
+        c2.check_status()
         log("step %d done" % i)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -663,6 +871,11 @@ def main():
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(W)
         res["cpu_baseline"]["gpu_over_cpu"] = value / res["cpu_baseline"]["value"]
+        if not args.no_extras:
+            try:
+                res["cpu_baseline"]["configs_3_to_5"] = cpu_extras(W)
+            except Exception as e:  # reported, never hidden
+                res["cpu_baseline"]["configs_3_to_5"] = {"error": "%s: %s" % (type(e).__name__, e)}
     print(json.dumps(res), flush=True)
 
 

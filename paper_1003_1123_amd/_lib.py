@@ -270,6 +270,17 @@ def ws_status(ws: torch.Tensor) -> int:
     return int(ws[:4].cpu().numpy().view("<u4")[0])
 
 
+def lf_stream_status(state: torch.Tensor) -> int:
+    """Status word of the last persistent rng_uniform / rng_gaussian run on a lagged-Fibonacci
+    state (synchronises): nonzero if it gave up a wait, its output then being invalid.  The word
+    sits at the first 128-byte boundary after the header and the ring (include/rngld.h)."""
+    torch.cuda.current_stream().synchronize()
+    R = int(state[20:24].cpu().numpy().view("<u4")[0])
+    base = state.data_ptr()
+    off = ((base + 64 + 4 * R + 127) & ~127) - base
+    return int(state[off:off + 4].cpu().numpy().view("<u4")[0])
+
+
 LF_PATHS = {1: "dataflow", 2: "waves"}
 
 

@@ -28,6 +28,15 @@ ISA_JSON = os.path.join(HERE, "kernel_isa.json")
 # symbols covered).  The lagged-Fibonacci entry covers the 8-tile instantiation, the one that runs
 # 10^6 oscillators on 256 CUs.
 FINGERPRINTED = {"lf_pc_kernel": ("k_lf.hip", "lf_pc_kernelILi8E"), "ld_run_kernel": ("k_ld.hip", "ld_run_kernel")}
+# kernels whose step loop's vector-ALU instructions are counted (the loop that holds the Box-Muller
+# logarithm: one oscillator-step per iteration): name -> (source file, exact mangled symbol)
+STEP_LOOPS = {
+    "ld_run_kernel<HybridTaus,256,1>": ("k_ld.hip", "_ZN5rngld12_GLOBAL__N_113ld_run_kernelINS_10HybridTausELi256ELi1EEEvNS_6LdArgsE"),
+    "ld_run_kernel<Ran2,256,1>": ("k_ld.hip", "_ZN5rngld12_GLOBAL__N_113ld_run_kernelINS_4Ran2ELi256ELi1EEEvNS_6LdArgsE"),
+    "ld_run_kernel<Lcg32,256,1>": ("k_ld.hip", "_ZN5rngld12_GLOBAL__N_113ld_run_kernelINS_5Lcg32ELi256ELi1EEEvNS_6LdArgsE"),
+    "ld_ckpt_kernel<HybridTaus,256>": ("k_adj.hip", "_ZN5rngld12_GLOBAL__N_114ld_ckpt_kernelINS_10HybridTausELi256EEEvNS_7AdjArgsE"),
+    "ld_adjoint_seg_kernel<256>": ("k_adj.hip", "_ZN5rngld12_GLOBAL__N_121ld_adjoint_seg_kernelILi256EEEvNS_7AdjArgsE"),
+}
 ARCH = os.environ.get("RNGLD_OFFLOAD_ARCH", "gfx950")
 
 # Packed-FP32 instructions are disabled for all device code (the compiler would otherwise form
@@ -79,23 +88,67 @@ def _function_bodies(asm: str, name: str):
     return out
 
 
+def step_loop_valu(asm: str, symbol: str) -> dict:
+    """Vector-ALU instructions of the step loop of `symbol`, by opcode: among the loops that contain
+    a v_log_f32 (one oscillator-step per iteration) and no smaller such loop, the largest one (the
+    underdamped scheme where a kernel holds both).  Every instruction of the loop body counts once, including
+    any branch that runs on some iterations only."""
+    lines = asm.splitlines()
+    start = next(i for i, l in enumerate(lines) if l.startswith(symbol + ":"))
+    end = next(i for i in range(start, len(lines)) if lines[i].startswith(".Lfunc_end"))
+    body = [l.split(";")[0].rstrip() for l in lines[start:end]]
+    labels = {m.group(1): i for i, l in enumerate(body) for m in [re.match(r"^(\.LBB\d+_\d+):", l)] if m}
+    spans = []
+    for i, l in enumerate(body):
+        m = re.search(r"s_(?:cbranch_\w+|branch)\s+(\.LBB\d+_\d+)", l)
+        if m and m.group(1) in labels and labels[m.group(1)] < i:
+            spans.append((labels[m.group(1)], i))
+    ops_of = {(a, b): [x.split()[0] for x in body[a:b + 1] if x.strip().startswith("v_")] for a, b in spans}
+    stepping = [sp for sp in spans if "v_log_f32_e32" in ops_of[sp]]
+    best = None
+    for a, b in stepping:
+        if any(a <= c and d <= b and (c, d) != (a, b) for c, d in stepping):
+            continue  # holds another step loop
+        if best is None or len(ops_of[(a, b)]) > len(best):
+            best = ops_of[(a, b)]
+    if best is None:
+        raise RuntimeError("no step loop found in %s" % symbol)
+    counts = {}
+    for op in best:
+        counts[op] = counts.get(op, 0) + 1
+    return {"valu_per_iteration": len(best), "by_opcode": dict(sorted(counts.items()))}
+
+
+def _assembly(src: str) -> str:
+    """The gfx950 assembly listing of one source (written to _build/)."""
+    asm_path = os.path.join(BUILD, src[:-4] + ".gfx950.s")
+    cmd = [hipcc()] + [f for f in FLAGS if f != "-fPIC"] + ["--cuda-device-only", "-S",
+                                                          os.path.join(CSRC, src), "-o", asm_path]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("assembly listing failed: %s\n%s" % (" ".join(cmd), r.stderr))
+    return open(asm_path).read()
+
+
 def fingerprint_kernels() -> dict:
-    """SHA-256 over the sorted assembly bodies of each fingerprinted kernel family."""
+    """SHA-256 over the sorted assembly bodies of each fingerprinted kernel family, and the VALU
+    instruction counts of the step loops."""
+    srcs = sorted({src for src, _ in FINGERPRINTED.values()} | {src for src, _ in STEP_LOOPS.values()})
+    with cf.ThreadPoolExecutor(max_workers=len(srcs)) as ex:
+        asm = dict(zip(srcs, ex.map(_assembly, srcs)))
     res = {}
     for name, (src, pattern) in FINGERPRINTED.items():
-        asm_path = os.path.join(BUILD, src[:-4] + ".gfx950.s")
-        cmd = [hipcc()] + [f for f in FLAGS if f != "-fPIC"] + ["--cuda-device-only", "-S",
-                                                              os.path.join(CSRC, src), "-o", asm_path]
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            raise RuntimeError("assembly listing failed: %s\n%s" % (" ".join(cmd), r.stderr))
-        bodies = _function_bodies(open(asm_path).read(), pattern)
+        bodies = _function_bodies(asm[src], pattern)
         if not bodies:
             raise RuntimeError("no %s in %s" % (name, asm_path))
         h = hashlib.sha256()
         for sym in sorted(bodies):
             h.update(sym.encode() + b"\n" + bodies[sym].encode() + b"\n")
         res[name] = {"sha256": h.hexdigest(), "functions": len(bodies)}
+    loops = {}
+    for name, (src, symbol) in STEP_LOOPS.items():
+        loops[name] = step_loop_valu(asm[src], symbol)
+    res["step_loops"] = loops
     return res
 
 

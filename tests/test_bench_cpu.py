@@ -38,18 +38,44 @@ def test_lf_roofline_is_algorithmic_bytes_over_the_launch_time():
     assert w["algorithmic_bytes_per_osc_step"] == 48 + 48
 
 
+# the opcode histogram of the Hybrid Taus step loop as compiled when the probe's class table was
+# made (117 VALU per oscillator-step)
+TAUS_LOOP = {"v_add_u32_e32": 6, "v_and_b32_e32": 3, "v_and_or_b32": 9, "v_bitop3_b32": 7, "v_cos_f32_e32": 2,
+             "v_cvt_f32_u32_e32": 4, "v_fma_f32": 5, "v_fmac_f32_e32": 4, "v_log_f32_e32": 2,
+             "v_lshlrev_b32_e32": 24, "v_lshrrev_b32_e32": 16, "v_mul_f32_e32": 12, "v_mul_lo_u32": 4,
+             "v_or_b32_e32": 3, "v_sin_f32_e32": 1, "v_sqrt_f32_e32": 2, "v_xor_b32_e32": 13}
+
+
+def test_valu_classes_and_mix_bound():
+    cls = bench.valu_classes(TAUS_LOOP)
+    assert cls == {"transcendental": 7, "mul32": 4, "cvt": 4, "three_operand": 16, "fp32": 21, "other": 65}
+    t = sum(n / bench.VALU_CLASS_RATES[c] for c, n in cls.items())
+    assert 1.0 / t == pytest.approx(3.75e11, rel=2e-3)
+    assert bench.valu_classes({"v_fmac_f64_e32": 3, "v_xor_b32_e32": 1}) == {"unmeasured": 3, "other": 1}
+
+
 @pytest.mark.parametrize("kind", ["taus", "ran2"])
 def test_valu_roofline_uses_the_loop_counts_and_the_mix_bound(kind):
+    if "step_loops" not in bench._kernel_isa():
+        pytest.skip("the library has not been built (no kernel_isa.json)")
     N, T, ms = 1_000_000, 10_000, 30.0
     e = bench.roofline_entry(kind, ms, N, T)
-    ops = bench.VALU_PER_OSC_STEP[kind] * N * T
-    assert e["achieved"] == pytest.approx(ops / (ms / 1e3) / 1e12)
+    vpos = bench.valu_per_osc_step(kind)
+    assert 40 < vpos < 200
+    assert e["achieved"] == pytest.approx(vpos * N * T / (ms / 1e3) / 1e12)
     assert e["peak"] == pytest.approx(256 * 128 * 2.4e9 / 1e12)
     # the measured peak is the mix bound in oscillator-steps/s times the loop's instructions
-    assert e["peak_measured"] == pytest.approx(bench.VALU_PER_OSC_STEP[kind] * bench.VALU_MIX_BOUND_OSC_STEPS[kind]
-                                               / 1e12)
-    assert e["frac_measured"] == pytest.approx((N * T / (ms / 1e3)) / bench.VALU_MIX_BOUND_OSC_STEPS[kind])
+    bound = bench.valu_mix_bound(kind)
+    assert e["peak_measured"] == pytest.approx(vpos * bound / 1e12)
+    assert e["frac_measured"] == pytest.approx((N * T / (ms / 1e3)) / bound)
     assert e["traffic"] is None  # no counters are recorded for these kernels
+
+
+def test_adjoint_loops_have_no_mix_bound():
+    if "step_loops" not in bench._kernel_isa():
+        pytest.skip("the library has not been built (no kernel_isa.json)")
+    assert bench.valu_mix_bound("adjoint_backward") is None  # FP64 accumulation: not in the probe's table
+    assert bench.valu_per_osc_step("adjoint_backward") > bench.valu_per_osc_step("taus")
 
 
 def test_counter_traffic_only_for_the_recorded_machine_code(monkeypatch):
