@@ -37,26 +37,52 @@ __device__ __forceinline__ uint32_t xor4(uint32_t a, uint32_t b, uint32_t c, uin
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96) ^ d;
 }
 
+// The uniform mapping uses a word's top 24 bits only (below): kTop24 keeps them in place.
+constexpr uint32_t kTop24 = 0xFFFFFF00u;
+
+// (a ^ b ^ c ^ d) & kTop24 in two three-input bitwise ops: 0x96 is the three-way xor and 0x28 the
+// truth table of (x ^ y) & z
+__device__ __forceinline__ uint32_t xor4_top24(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+    return __builtin_amdgcn_bitop3_b32(__builtin_amdgcn_bitop3_b32(a, b, c, 0x96), d, kTop24, 0x28);
+}
+
 struct HybridTaus {
     uint32_t t1, t2, t3, lcg;
     static constexpr int kRows = 4;
 
-    __device__ __forceinline__ uint32_t next() {
+    __device__ __forceinline__ void step() {
         t1 = tausworthe<13, 12, 31>(t1);
         t2 = tausworthe<2, 4, 29>(t2);
         t3 = tausworthe<3, 17, 28>(t3);
         lcg = lcg_next(lcg);
+    }
+    __device__ __forceinline__ uint32_t next() {
+        step();
         return xor4(t1, t2, t3, lcg);
+    }
+    // the next word with its low 8 bits cleared (what the uniform mapping reads)
+    __device__ __forceinline__ uint32_t next_top24() {
+        step();
+        return xor4_top24(t1, t2, t3, lcg);
     }
     // the output of the current state, then one step back: repeated calls return the outputs of
     // the preceding next() calls in reverse order, all of them exactly; only the seeded state
     // itself comes back with different bits below each component's top K
-    __device__ __forceinline__ uint32_t prev() {
-        const uint32_t w = xor4(t1, t2, t3, lcg);
+    __device__ __forceinline__ void step_back() {
         t1 = tausworthe_inv<13, 12, 31>(t1);
         t2 = tausworthe_inv<2, 4, 29>(t2);
         t3 = tausworthe_inv<3, 17, 28>(t3);
         lcg = lcg_prev(lcg);
+    }
+    __device__ __forceinline__ uint32_t prev() {
+        const uint32_t w = xor4(t1, t2, t3, lcg);
+        step_back();
+        return w;
+    }
+    // prev() with the word's low 8 bits cleared
+    __device__ __forceinline__ uint32_t prev_top24() {
+        const uint32_t w = xor4_top24(t1, t2, t3, lcg);
+        step_back();
         return w;
     }
     // state rows: uint32 [4][S]
@@ -92,6 +118,7 @@ struct Lcg32 {
         x = lcg_next(x);
         return x;
     }
+    __device__ __forceinline__ uint32_t next_top24() { return next() & kTop24; }
     __device__ __forceinline__ void load(const uint32_t *st, uint64_t, uint64_t j) { x = st[j]; }
     __device__ __forceinline__ void store(uint32_t *st, uint64_t, uint64_t j) const { st[j] = x; }
     __device__ __forceinline__ void seed(uint64_t seed, uint64_t stream, uint64_t leap) {
@@ -145,6 +172,7 @@ struct Ran2 {
     }
     // word fed to the uniform mapping: iy - 1 spans [0, 2^31), doubled
     __device__ __forceinline__ uint32_t next() { return static_cast<uint32_t>(next_iy() - 1) << 1; }
+    __device__ __forceinline__ uint32_t next_top24() { return next() & kTop24; }
 
     // state rows: int32 [35][S]: idum, idum2, iy, iv[0..31]
     __device__ __forceinline__ void load(const int32_t *st, uint64_t S, uint64_t j) {
@@ -176,6 +204,10 @@ struct Ran2 {
 
 // ---- uniform mapping and Box-Muller ----------------------------------------------------------------
 // u_open = ((w >> 8) + 1) 2^-24 in (0, 1]; u_half = (w >> 8) 2^-24 in [0, 1); both exact in FP32.
+// They are evaluated on m = w & kTop24, whose conversion to FP32 is exact (24 significant bits):
+// u_half = float(m) 2^-32 and u_open = float(m) 2^-32 + 2^-24 as one FMA, exact because the result
+// is representable.  A generator that clears the low bits in its last instruction (Hybrid Taus:
+// one three-input bitwise op) so saves the shift and the add of the plain form.
 // The transform uses the hardware transcendentals: -2 ln u = -2 ln(2) log2(u) with v_log_f32 and
 // v_sqrt_f32, and v_cos_f32 / v_sin_f32, whose argument is in revolutions (sin(2 pi x)), so the
 // angle needs no multiply.  Checked over every one of the 2^24 possible inputs of each factor
@@ -183,28 +215,34 @@ struct Ran2 {
 // within 2e-6 of its exact value (r <= sqrt(48 ln 2)).
 constexpr float kMinusTwoLn2 = -1.38629436f;
 
-__device__ __forceinline__ float box_muller_radius(uint32_t w) {
-    const float u = static_cast<float>((w >> 8) + 1u) * 0x1p-24f;
-    return __builtin_amdgcn_sqrtf(kMinusTwoLn2 * __builtin_amdgcn_logf(u));
+__device__ __forceinline__ float u_open_top24(uint32_t m) {
+    return __builtin_fmaf(static_cast<float>(m), 0x1p-32f, 0x1p-24f);
 }
+__device__ __forceinline__ float u_half_top24(uint32_t m) { return static_cast<float>(m) * 0x1p-32f; }
+
+__device__ __forceinline__ float box_muller_radius_top24(uint32_t m) {
+    return __builtin_amdgcn_sqrtf(kMinusTwoLn2 * __builtin_amdgcn_logf(u_open_top24(m)));
+}
+__device__ __forceinline__ float box_muller_radius(uint32_t w) { return box_muller_radius_top24(w & kTop24); }
 __device__ __forceinline__ void box_muller_angle(uint32_t w, float &c, float &s) {
-    const float u = static_cast<float>(w >> 8) * 0x1p-24f;
+    const float u = u_half_top24(w & kTop24);
     c = __builtin_amdgcn_cosf(u);
     s = __builtin_amdgcn_sinf(u);
 }
-__device__ __forceinline__ float box_muller_cos(uint32_t w) {
-    return __builtin_amdgcn_cosf(static_cast<float>(w >> 8) * 0x1p-24f);
-}
 
-// three force components from one oscillator-step's four words
+// three force components from one oscillator-step's four words, given with their low 8 bits clear
+__device__ __forceinline__ void gaussian_forces_top24(uint32_t m0, uint32_t m1, uint32_t m2, uint32_t m3, float &gx,
+                                                      float &gy, float &gz) {
+    const float r0 = box_muller_radius_top24(m0);
+    const float u1 = u_half_top24(m1);
+    gx = r0 * __builtin_amdgcn_cosf(u1);
+    gy = r0 * __builtin_amdgcn_sinf(u1);
+    gz = box_muller_radius_top24(m2) * __builtin_amdgcn_cosf(u_half_top24(m3));
+}
+// the same from whole words
 __device__ __forceinline__ void gaussian_forces(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, float &gx,
                                                 float &gy, float &gz) {
-    const float r0 = box_muller_radius(w0);
-    float c, s;
-    box_muller_angle(w1, c, s);
-    gx = r0 * c;
-    gy = r0 * s;
-    gz = box_muller_radius(w2) * box_muller_cos(w3);
+    gaussian_forces_top24(w0 & kTop24, w1 & kTop24, w2 & kTop24, w3 & kTop24, gx, gy, gz);
 }
 
 // ---- LD update ----------------------------------------------------------------------------------------

@@ -116,10 +116,28 @@ __global__ __launch_bounds__(BLOCK) void ld_ckpt_kernel(AdjArgs a) {
     } else {
         park(g);
     }
+    // steps [s, e) of the run, adding x^2 after each step to lseg when LOSS
+    auto steps = [&](auto loss_tag, uint32_t s, uint32_t e, float &lseg) {
+        constexpr bool LOSS = decltype(loss_tag)::value;
+        for (; s < e; ++s) {
+            const uint32_t w0 = g.next_top24(), w1 = g.next_top24(), w2 = g.next_top24(), w3 = g.next_top24();
+            float gf[3];
+            gaussian_forces_top24(w0, w1, w2, w3, gf[0], gf[1], gf[2]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) ld_update(q, x[d], v[d], gf[d]);
+            if constexpr (LOSS) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) lseg += x[d] * x[d];
+            }
+        }
+    };
+    // the loss takes the positions after steps t_begin..t_end, i.e. steps s in [t_begin - 1, t_end)
+    const uint32_t w_lo = a.t_begin - 1, w_hi = a.t_end;
+    // the loss sum: FP32 within each K-step segment (at most 3K terms of x^2), FP64 across segments
     double lsum = 0.0;
-    for (uint32_t s = 0; s < a.n_steps; ++s) {
-        if (s % a.K == 0 && act) {
-            uint8_t *rec = a.ckpt + static_cast<uint64_t>(s / a.K) * a.rec_bytes;
+    for (uint32_t s0 = 0; s0 < a.n_steps; s0 += a.K) {
+        if (act) {
+            uint8_t *rec = a.ckpt + static_cast<uint64_t>(s0 / a.K) * a.rec_bytes;
             float *rx = reinterpret_cast<float *>(rec);
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -128,14 +146,14 @@ __global__ __launch_bounds__(BLOCK) void ld_ckpt_kernel(AdjArgs a) {
             }
             store_state(g, rx + 6 * a.NT, a.NT, i);
         }
-        const uint32_t w0 = g.next(), w1 = g.next(), w2 = g.next(), w3 = g.next();
-        float gf[3];
-        gaussian_forces(w0, w1, w2, w3, gf[0], gf[1], gf[2]);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) ld_update(q, x[d], v[d], gf[d]);
-        if (s + 1 >= a.t_begin && s + 1 <= a.t_end)
-#pragma unroll
-            for (int d = 0; d < 3; ++d) lsum += static_cast<double>(x[d]) * x[d];
+        const uint32_t s1 = (s0 + a.K < a.n_steps) ? s0 + a.K : a.n_steps;
+        const uint32_t lo = s0 > w_lo ? s0 : (w_lo < s1 ? w_lo : s1);
+        const uint32_t hi = lo > w_hi ? lo : (w_hi < s1 ? w_hi : s1);
+        float lseg = 0.0f;
+        steps(std::false_type{}, s0, lo, lseg);
+        steps(std::true_type{}, lo, hi, lseg);
+        steps(std::false_type{}, hi, s1, lseg);
+        lsum += static_cast<double>(lseg);
     }
     if (act) {
         // the end state: the live buffers and the last checkpoint record
@@ -188,9 +206,9 @@ __global__ __launch_bounds__(BLOCK) void ld_adjoint_kernel(AdjArgs a) {
         // replay: scratch row r holds x_s, v_s, g_s of step s = s0 + r
         for (uint32_t s = s0; s < s1; ++s) {
             float *row = a.scratch + static_cast<uint64_t>(s - s0) * 9 * NT + i;
-            const uint32_t w0 = g.next(), w1 = g.next(), w2 = g.next(), w3 = g.next();
+            const uint32_t w0 = g.next_top24(), w1 = g.next_top24(), w2 = g.next_top24(), w3 = g.next_top24();
             float gf[3];
-            gaussian_forces(w0, w1, w2, w3, gf[0], gf[1], gf[2]);
+            gaussian_forces_top24(w0, w1, w2, w3, gf[0], gf[1], gf[2]);
             if (act)
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
@@ -257,16 +275,18 @@ __global__ __launch_bounds__(BLOCK) void ld_adjoint_seg_kernel(AdjArgs a) {
     // the two unit end adjoints carried by the homogeneous recursion (the same in every lane):
     // (p1x, p1v) from (1, 0), (p2x, p2v) from (0, 1); mu of each gives a_s and b_s
     float p1x = 1.0f, p1v = 0.0f, p2x = 0.0f, p2v = 1.0f;
-    double gk = 0.0, gg = 0.0, gT = 0.0;
+    // the segment's own gradient as sums over its steps and the three components of mu x, mu v and
+    // mu g, scaled by the partials at the end: K terms per component in FP32
+    float smx = 0.0f, smv = 0.0f, smg = 0.0f;
     // x, v hold the state after step s on entry to step s
     for (uint32_t s = s1; s-- > s0;) {
         const bool in_loss = (s + 1 >= a.t_begin) && (s + 1 <= a.t_end);
-        const uint32_t w3 = g.prev();
-        const uint32_t w2 = g.prev();
-        const uint32_t w1 = g.prev();
-        const uint32_t w0 = g.prev();
+        const uint32_t w3 = g.prev_top24();
+        const uint32_t w2 = g.prev_top24();
+        const uint32_t w1 = g.prev_top24();
+        const uint32_t w0 = g.prev_top24();
         float gf[3];
-        gaussian_forces(w0, w1, w2, w3, gf[0], gf[1], gf[2]);
+        gaussian_forces_top24(w0, w1, w2, w3, gf[0], gf[1], gf[2]);
         const float as = p1v + h * p1x, bs = p2v + h * p2x;
         p1x = p1x - kap * as;
         p1v = c * as;
@@ -279,9 +299,9 @@ __global__ __launch_bounds__(BLOCK) void ld_adjoint_seg_kernel(AdjArgs a) {
             const float t = v[d] + kap * xs - sig * gf[d];
             const float vs = __builtin_fmaf(t, inv_c, t * inv_c_lo);
             const float mu = lv[d] + h * lx[d];
-            gk += static_cast<double>(mu) * static_cast<double>(-A.dkap_dk * xs);
-            gg += static_cast<double>(mu) * static_cast<double>(A.dc_dgamma * vs + A.dsig_dgamma * gf[d]);
-            gT += static_cast<double>(mu) * static_cast<double>(A.dsig_dkT * gf[d]);
+            smx += mu * xs;
+            smv += mu * vs;
+            smg += mu * gf[d];
             xa[d] += as * xs;
             xb[d] += bs * xs;
             va[d] += as * vs;
@@ -308,9 +328,9 @@ __global__ __launch_bounds__(BLOCK) void ld_adjoint_seg_kernel(AdjArgs a) {
         rf[(18 + d) * NT] = ga[d];
         rf[(21 + d) * NT] = gb[d];
     }
-    rd[0] = gk;
-    rd[NT] = gg;
-    rd[2 * NT] = gT;
+    rd[0] = -static_cast<double>(A.dkap_dk) * smx;
+    rd[NT] = static_cast<double>(A.dc_dgamma) * smv + static_cast<double>(A.dsig_dgamma) * smg;
+    rd[2 * NT] = static_cast<double>(A.dsig_dkT) * smg;
 }
 
 // per-oscillator pass over the segment records, last segment first: the adjoint arriving at a

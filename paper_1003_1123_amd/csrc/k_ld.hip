@@ -42,11 +42,11 @@ __device__ __forceinline__ void draw_forces(Gen &g, float &gx, float &gy, float 
     if constexpr (IsNoNoise<Gen>::value) {
         gx = gy = gz = 0.0f;
     } else {
-        const uint32_t w0 = g.next();
-        const uint32_t w1 = g.next();
-        const uint32_t w2 = g.next();
-        const uint32_t w3 = g.next();
-        gaussian_forces(w0, w1, w2, w3, gx, gy, gz);
+        const uint32_t m0 = g.next_top24();
+        const uint32_t m1 = g.next_top24();
+        const uint32_t m2 = g.next_top24();
+        const uint32_t m3 = g.next_top24();
+        gaussian_forces_top24(m0, m1, m2, m3, gx, gy, gz);
     }
 }
 
@@ -254,12 +254,12 @@ __global__ __launch_bounds__(kBulkBlock) void ran2_step_kernel(int32_t *st, uint
     g.iy = st[2 * S + i];
     g.tab = st + 3 * S + i;
     g.tstride = S;
-    const uint32_t w0 = g.next(), w1 = g.next(), w2 = g.next(), w3 = g.next();
+    const uint32_t w0 = g.next_top24(), w1 = g.next_top24(), w2 = g.next_top24(), w3 = g.next_top24();
     st[i] = g.idum;
     st[S + i] = g.idum2;
     st[2 * S + i] = g.iy;
     float gf[3];
-    gaussian_forces(w0, w1, w2, w3, gf[0], gf[1], gf[2]);
+    gaussian_forces_top24(w0, w1, w2, w3, gf[0], gf[1], gf[2]);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         float xd = x[d * n + i], vd = v[d * n + i];

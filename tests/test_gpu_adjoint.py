@@ -151,7 +151,7 @@ def test_config5_gradients():
 def test_config5_gradients_match_the_oracle():
     """The config-5 gradients (N = 1e5, 2000 steps, every oscillator) against the FP64 oracle
     adjoint of the same oscillators and noise.  Iterating the binary32 coefficients the run uses,
-    each component agrees within 1e-3 of its own value.  Against the oracle with exact
+    each component agrees within 1e-4 of its own value.  Against the oracle with exact
     coefficients the difference is set by their rounding (see the finite-difference test), which
     the difference of the two oracle runs measures."""
     c = W.C5
@@ -163,7 +163,8 @@ def test_config5_gradients_match_the_oracle():
     _say("config5 GPU", L, grad, "oracle (binary32 coefficients)", L32, g32, "relative", np.abs(grad - g32) / np.abs(g32))
     _say("oracle (exact coefficients)", L64, g64, "relative", np.abs(grad - g64) / np.abs(g64))
     assert abs(L - L32) <= 1e-5 * abs(L32)
-    assert np.all(np.abs(grad - g32) <= 1e-3 * np.abs(g32)), (grad, g32)
+    # measured: 6e-8, 7e-6 and 1.2e-7 of the three values
+    assert np.all(np.abs(grad - g32) <= 1e-4 * np.abs(g32)), (grad, g32)
     assert np.all(np.abs(grad - g64) <= 1e-3 * np.abs(g64) + 2.0 * np.abs(g64 - g32)), (grad, g64, g32)
 
 
@@ -181,7 +182,8 @@ def _grads(kind, shape, params, T, tb, te, K, replay=False):
 def test_register_only_backward_equals_replay():
     """The register-only backward (inverse generator steps, backward integration from each
     segment's end checkpoint) against the replay backward on the same forward run: the noise is
-    the same bit for bit, so the gradients differ only by the rounding of the reconstructed path."""
+    the same bit for bit, so the gradients differ only by the rounding of the reconstructed path,
+    each component within 1e-5 of its own value."""
     T, tb, te, K = 500, 101, 500, 64
     shape = [(3000, 1.0, 0.01, 5), (1000, 1.0, 0.01, 6)]
     params = [(1.0, 1.0, 1.0), (2.0, 1.5, 0.7)]
@@ -189,10 +191,10 @@ def test_register_only_backward_equals_replay():
     run_r, Lr, gr = _grads("taus", shape, params, T, tb, te, K, replay=True)
     assert run_i.ws.numel() < run_r.ws.numel()  # no replay scratch on the register-only path
     assert np.array_equal(Li, Lr)
-    err = np.max(np.abs(gi - gr) / np.max(np.abs(gr), axis=1, keepdims=True))
-    _say("register-only vs replay: max relative gradient difference", err, "per component",
-         np.abs(gi - gr) / np.abs(gr))
-    assert err <= 2e-5, (gi, gr)
+    rel = np.abs(gi - gr) / np.abs(gr)
+    _say("register-only vs replay: relative gradient difference per component", rel)
+    # measured: below 3e-7 of each value
+    assert np.all(rel <= 1e-5), (gi, gr)
 
 
 def test_checkpoint_end_record_is_the_final_state():
