@@ -924,8 +924,19 @@ __device__ __forceinline__ bool stream_wait(FlowWaits &w, uint32_t lane, const L
     return __all(ok);
 }
 
+// Lane l of producer p holds the offsets 4 (l + 64 g) + r of its slice, g < M / 4, r < 4: four
+// consecutive words, moved with one 16-byte buffer access (sc1, as the ring of the fused run) wherever
+// the four lie inside the slice's valid part and, for loads, inside the output; word by word
+// otherwise (the first links, whose long-lag sources are in the state's ring, and ragged ends).
+// Software-pipelined over links: when the waits of link j+1 are already seen to hold, link j's stores
+// are followed at once by the poll for link j+2 and link j+1's loads, and link j is published as soon
+// as only those can still be outstanding (vector memory operations complete in issue order, and a
+// store counts until it has completed); otherwise link j is published first, then the producer blocks
+// on link j+1's waits.
 template <int M>
 __global__ __launch_bounds__(kLfFlowBlock) void lf_stream_kernel(LfStreamArgs a) {
+    static_assert(M % 4 == 0, "groups of four words");
+    constexpr int G = M / 4;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t p = __builtin_amdgcn_readfirstlane(blockIdx.x * (kLfFlowBlock / 64) + (threadIdx.x >> 6));
     if (p >= a.n_slices) return;
@@ -950,12 +961,15 @@ __global__ __launch_bounds__(kLfFlowBlock) void lf_stream_kernel(LfStreamArgs a)
         const uint64_t n0 = static_cast<uint64_t>(j) * sl + o_lo;
         return n0 >= count ? 0u : (count - n0 < width ? static_cast<uint32_t>(count - n0) : width);
     };
-    uint32_t chain[M], src[M];
+    auto q_of = [&](int gi, int r) -> uint32_t { return 4u * (lane + 64u * gi) + r; };
+    u32x4 chain[G], src[G], nxt[G];
 #pragma unroll
-    for (int r = 0; r < M; ++r) {
-        const uint32_t q = lane + 64u * r;
-        chain[r] = q < width ? agent_load(word(static_cast<int64_t>(o_lo + q) - sl)) : 0u;
-    }
+    for (int gi = 0; gi < G; ++gi)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t q = q_of(gi, r);
+            chain[gi][r] = q < width ? agent_load(word(static_cast<int64_t>(o_lo + q) - sl)) : 0u;
+        }
     FlowWaits w;
     w.n = 0;
     // the producers of link j's long-lag sources (positions >= 0 only)
@@ -968,14 +982,39 @@ __global__ __launch_bounds__(kLfFlowBlock) void lf_stream_kernel(LfStreamArgs a)
             return true;
         });
     };
-    // M long-lag loads, always all issued (an unused one reads the link's first source), one
-    // load instruction each, so that their count is exact
-    auto load = [&](uint32_t j, uint32_t len) {
-        const int64_t n0 = static_cast<int64_t>(j) * sl + o_lo - ll;
+    // link j's long-lag sources y_{n - ll}, n = j sl + o_lo + q.  With every source in the output
+    // (j sl + o_lo >= ll) the slice's whole window of T sources is read, 16 bytes per group: it lies
+    // inside the output (it ends before position j sl + o_lo); values past len are not used.
+    auto load = [&](uint32_t j, uint32_t len, u32x4 (&dst)[G]) {
+        const int64_t base = static_cast<int64_t>(j) * sl + o_lo - ll;
+        if (base >= 0) {
+            const __amdgpu_buffer_rsrc_t rs = ring_rsrc(out + base, T);
 #pragma unroll
-        for (int r = 0; r < M; ++r) {
-            const uint32_t q = lane + 64u * r;
-            src[r] = agent_load(word(n0 + (q < len ? q : 0u)));
+            for (int gi = 0; gi < G; ++gi) dst[gi] = ring_get4(rs, 4u * (lane + 64u * gi));
+        } else {
+#pragma unroll
+            for (int gi = 0; gi < G; ++gi)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const uint32_t q = q_of(gi, r);
+                    dst[gi][r] = agent_load(word(base + (q < len ? q : 0u)));
+                }
+        }
+    };
+    // link j's values chain into out[j sl + o_lo + q], q < len
+    auto store = [&](uint32_t j, uint32_t len) {
+        uint32_t *dst = out + static_cast<uint64_t>(j) * sl + o_lo;
+        const __amdgpu_buffer_rsrc_t rs = ring_rsrc(dst, T);
+#pragma unroll
+        for (int gi = 0; gi < G; ++gi) {
+            const uint32_t q0 = 4u * (lane + 64u * gi);
+            if (q0 + 4u <= len) {
+                ring_put4(rs, q0, chain[gi]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (q0 + r < len) agent_store(dst + q0 + r, chain[gi][r]);
+            }
         }
     };
     uint32_t len = link_len(0);
@@ -983,7 +1022,7 @@ __global__ __launch_bounds__(kLfFlowBlock) void lf_stream_kernel(LfStreamArgs a)
     collect(0, len);
     if (!stream_wait(w, lane, a)) return;
     // one read of the first progress word each lane waits for (the status word in lanes without a
-    // wait), for link j1; issued before a link's loads, so it has returned once they have
+    // wait), for link j1
     uint32_t seen = 0;
     auto poll = [&](uint32_t j1) {
         w.n = 0;
@@ -991,24 +1030,14 @@ __global__ __launch_bounds__(kLfFlowBlock) void lf_stream_kernel(LfStreamArgs a)
         seen = agent_load(lane < w.n ? w.flag : a.status);
     };
     poll(1);
-    load(0, len);
+    load(0, len, src);
     for (uint32_t j = 0; j < a.n_links; ++j) {
         const uint32_t next_len = link_len(j + 1);
 #pragma unroll
-        for (int r = 0; r < M; ++r) chain[r] += src[r];
-        // link j+1's waits, read before link j's loads
+        for (int gi = 0; gi < G; ++gi) chain[gi] += src[gi];
+        // link j+1's waits, as read by the last poll (before link j's loads)
         const bool ready = next_len > 0 && w.n <= 64u && __all(lane >= w.n || seen >= w.need);
-        const int64_t n0 = static_cast<int64_t>(j) * sl + o_lo;
-        if (len == T) {
-#pragma unroll
-            for (int r = 0; r < M; ++r) agent_store(out + n0 + lane + 64u * r, chain[r]);
-        } else {
-#pragma unroll
-            for (int r = 0; r < M; ++r) {
-                const uint32_t q = lane + 64u * r;
-                if (q < len) agent_store(out + n0 + q, chain[r]);
-            }
-        }
+        store(j, len);
         if (!ready) {
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
             if (lane == 0) agent_store(a.prod + p * kLfFlagStride, j + 1);
@@ -1020,11 +1049,15 @@ __global__ __launch_bounds__(kLfFlowBlock) void lf_stream_kernel(LfStreamArgs a)
             if (!stream_wait(w, lane, a)) return;
         }
         poll(j + 2);
-        load(j + 1, next_len);
+        const bool fast = static_cast<int64_t>(j + 1) * sl + o_lo >= static_cast<int64_t>(ll);
+        load(j + 1, next_len, src);
         if (ready) {
-            // only the poll and link j+1's M loads, issued after link j's stores, may still be
-            // outstanding: link j is stored
-            asm volatile("s_waitcnt vmcnt(%0)" ::"n"(M + 1) : "memory");
+            // only the poll and link j+1's loads, issued after link j's stores, may still be
+            // outstanding (vector memory operations complete in issue order): link j is stored
+            if (fast)
+                asm volatile("s_waitcnt vmcnt(%0)" ::"n"(G + 1) : "memory");
+            else
+                asm volatile("s_waitcnt vmcnt(%0)" ::"n"(M + 1) : "memory");
             if (lane == 0) agent_store(a.prod + p * kLfFlagStride, j + 1);
         }
         len = next_len;
