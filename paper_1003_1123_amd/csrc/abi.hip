@@ -479,7 +479,9 @@ uint32_t *lf_stream_flags(const Gen &g, void *d_state) {
 
 // The persistent bare-stream run for count values, if it fits: 1 when launched, 0 when the wave
 // path must run, an RNGLD error otherwise.  Needs links long enough to keep the chip busy.
-int try_lf_stream(const Gen &g, void *d_state, uint32_t *d_out, uint64_t count, hipStream_t st) {
+// gauss: the run also turns out[0, keep_from) into Box-Muller pairs in place (needs an even sl)
+int try_lf_stream(const Gen &g, void *d_state, uint32_t *d_out, uint64_t count, hipStream_t st, bool gauss = false,
+                  uint64_t keep_from = 0) {
     if (g.sl < 4096 || count < 4ull * g.sl) return 0;
     if ((count + g.sl - 1) / g.sl >= (1ull << 31)) return 0;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -515,9 +517,11 @@ int try_lf_stream(const Gen &g, void *d_state, uint32_t *d_out, uint64_t count, 
     a.n_slices = static_cast<uint32_t>((static_cast<uint64_t>(g.sl) + (1u << slice_log2) - 1) >> slice_log2);
     a.n_links = static_cast<uint32_t>((count + g.sl - 1) / g.sl);
     a.spin_limit = 1u << 20;
+    a.keep_from = gauss ? keep_from : 0;
     if (a.n_slices + 1 > kLfFlowMaxWaves) return 0;
+    if (gauss && (g.sl % 2 != 0 || keep_from % 2 != 0)) return 0;
     RNGLD_TRY_HIP(launch_fill_u32(flags, static_cast<uint64_t>(a.n_slices + 1) * kLfFlagStride, 0u, st));
-    const hipError_t e = launch_lf_stream(a, static_cast<uint32_t>(cus), m, st);
+    const hipError_t e = launch_lf_stream(a, static_cast<uint32_t>(cus), m, gauss, st);
     if (e == hipErrorCooperativeLaunchTooLarge) {
         (void)hipGetLastError();
         return 0;
@@ -635,14 +639,20 @@ int rng_gaussian(const rngld_cfg *cfg, void *d_state, size_t state_bytes, uint64
         if (!d_out) return fail(RNGLD_EINVAL, "output pointer is NULL");
         const LfRing L = lf_ring(g, d_state);
         // the persistent stream writes the integers into the output, which doubles as the lag
-        // table; the ring takes the last ll of them, then each pair is transformed in place
+        // table; with an even sl it also turns them into Gaussian pairs in place once no producer
+        // reads them, except the pairs from keep_from on: the ring takes the last ll integers, then
+        // those pairs are transformed (with an odd sl every pair is transformed after the run)
         uint32_t *words = reinterpret_cast<uint32_t *>(d_out);
-        const int r = try_lf_stream(g, d_state, words, count, st);
+        const uint64_t m = std::min<uint64_t>(count, g.ll);
+        const uint64_t keep_from = (count - m) & ~1ull;
+        int r = try_lf_stream(g, d_state, words, count, st, true, keep_from);
+        bool fused = r == 1;
+        if (r == 0) r = try_lf_stream(g, d_state, words, count, st);
         if (r < 0) return r;
         if (r == 1) {
-            const uint64_t m = std::min<uint64_t>(count, g.ll);
             RNGLD_TRY_HIP(launch_lf_ring_store(L, words, count, static_cast<uint32_t>((count - m) % g.R), st));
-            RNGLD_TRY_HIP(launch_box_muller_inplace(words, count / 2, st));
+            const uint64_t from = fused ? keep_from : 0;
+            RNGLD_TRY_HIP(launch_box_muller_inplace(words + from, (count - from) / 2, st));
         } else {
             for (uint64_t first = 0; first < count; first += g.W)
                 RNGLD_TRY_HIP(launch_lf_gauss_phase(L, d_out, first, static_cast<uint32_t>(first % g.R),

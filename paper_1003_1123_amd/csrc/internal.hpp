@@ -112,10 +112,14 @@ struct LfStreamArgs {
     uint32_t lla, llb;     // ll = lla sl + llb
     uint32_t n_slices, n_links;
     uint32_t spin_limit;
+    uint32_t pad;
+    uint64_t keep_from;    // Gaussian run: out[P] for P < keep_from (even) is turned into Box-Muller
+                           // pairs in place once no producer still reads it; the rest stays integer
 };
 // progress words the LAGFIB state reserves after its ring for the bare-stream run (bytes)
 constexpr size_t kLfStreamFlagBytes = 128 + static_cast<size_t>(8192) * 32 * sizeof(uint32_t);
-hipError_t launch_lf_stream(const LfStreamArgs &a, uint32_t grid, uint32_t m, hipStream_t st);
+// gauss: also turn out[0, keep_from) into Gaussians in place (needs an even sl)
+hipError_t launch_lf_stream(const LfStreamArgs &a, uint32_t grid, uint32_t m, bool gauss, hipStream_t st);
 
 // ---- adjoint (k_adj.hip) ---------------------------------------------------------------------------
 struct AdjCoef {

@@ -359,17 +359,20 @@ def test_lf_persistent_stream_matches_recurrence(lags, count):
     del out, again
 
 
-@pytest.mark.parametrize("lags,count", [((9689, 5502), 4 * 5502 + 10), ((132049, 54454), 3 * 10**6 + 18)])
+@pytest.mark.parametrize("lags,count", [((9689, 5502), 4 * 5502 + 10), ((132049, 54454), 3 * 10**6 + 18),
+                                        ((3021377, 1010202), 4 * 1010202 + 2), ((19937, 10095), 4 * 10095 + 6)])
 def test_lf_persistent_gaussians(lags, count):
-    """Long LF Gaussian streams: integers by the persistent launch into the output, then Box-Muller
-    pairs in place; every Gaussian within 1e-5 of the FP64 oracle, and the state continues the
-    sequence."""
+    """Long LF Gaussian streams by the persistent launch: integers into the output, turned into
+    Box-Muller pairs in place during the run once no producer reads them (even sl; the last ll
+    values after the run), or all after the run (odd sl, the last case); every Gaussian within 1e-5
+    of the FP64 oracle, the run's status word stays zero, and the state continues the sequence."""
     ll, sl = lags
     cfg = _lf_cfg(ll, sl, seed=8)
     st = R.new_state(cfg)
     R.rng_init(cfg, st)
     out = torch.empty(count, dtype=torch.float32, device="cuda")
     R.rng_gaussian(cfg, st, count, out)
+    assert R.lf_stream_status(st) == 0
     nxt = torch.empty(999, dtype=torch.int32, device="cuda")
     R.rng_uniform(cfg, st, 999, nxt)
     torch.cuda.synchronize()
