@@ -122,7 +122,8 @@ RNGLD_API int rngld_state_bytes(const rngld_cfg *cfg, size_t *bytes);
 RNGLD_API int rng_init(const rngld_cfg *cfg, void *d_state, size_t state_bytes, void *stream);
 
 /*
- * Bare generator output (no dynamics), advancing the state.
+ * Bare generator output (no dynamics), advancing the state: the streams of Sec. III.B (one
+ * generator per thread) and the shared sequence of Sec. III.C (Alg. 3), without the LD step.
  *  per-thread kinds: per_stream values of every stream, d_out[t*S + j] = value t of stream j;
  *                    out_len >= per_stream*S.  Taus: the xor word; Ran2: iy in [1, 2147483562].
  *  LAGFIB          : per_stream consecutive values of the one sequence, d_out[n] = y_{pos+n};
@@ -134,7 +135,8 @@ RNGLD_API int rng_uniform(const rngld_cfg *cfg, void *d_state, size_t state_byte
                 uint32_t *d_out, uint64_t out_len, void *stream);
 
 /*
- * Gaussian output: values 2i and 2i+1 of a stream are r cos(2 pi u1), r sin(2 pi u1) with
+ * Gaussian output by the Box-Muller transform (Sec. I; Sec. II.A on turning uniform variates into
+ * other distributions): values 2i and 2i+1 of a stream are r cos(2 pi u1), r sin(2 pi u1) with
  * r = sqrt(-2 ln u0), u0 = ((w0 >> 8) + 1) 2^-24, u1 = (w1 >> 8) 2^-24 from that stream's words
  * 2i and 2i+1 (Ran2 word: (iy - 1) << 1).  per_stream must be even.  Layout as rng_uniform.
  * LAGFIB streams that take rng_uniform's persistent launch are generated as integers into d_out
@@ -208,8 +210,10 @@ RNGLD_API int ld_step(const rngld_cfg *cfg, void *d_state, size_t state_bytes, c
             float *d_v, void *stream);
 
 /*
- * n_steps LD steps of n_ens ensembles (batched when n_ens > 1) with the generator fused into the
- * update and x, v and the per-thread state held on chip for the whole run.
+ * n_steps LD steps (the oscillators of Sec. IV, the step of ld_params) of n_ens ensembles (batched
+ * when n_ens > 1) with the generator fused into the update, as Sec. III.A argues (numbers generated
+ * inside the simulation kernel, not pre-generated), and x, v and the per-thread state held on chip
+ * for the whole run.  ld_workspace_bytes sizes the caller's workspace for the same arguments.
  *  d_x, d_v   : float[3][n_total]; ensembles must lie inside [0, n_total) and must not overlap.
  *  obs, d_obs : optional observables, d_obs = double[n_ens][P][6], P = n_steps/stride + 1.
  *  d_ws       : workspace of ld_workspace_bytes() bytes (any alignment >= 256).  Its first four
