@@ -49,6 +49,7 @@ __device__ __forceinline__ uint32_t xor4_top24(uint32_t a, uint32_t b, uint32_t 
 struct HybridTaus {
     uint32_t t1, t2, t3, lcg;
     static constexpr int kRows = 4;
+    static constexpr float kTopScale = 0x1p-32f;  // next_top24() is the word with its low 8 bits clear
 
     __device__ __forceinline__ void step() {
         t1 = tausworthe<13, 12, 31>(t1);
@@ -113,6 +114,7 @@ struct HybridTaus {
 struct Lcg32 {
     uint32_t x;
     static constexpr int kRows = 1;
+    static constexpr float kTopScale = 0x1p-32f;
 
     __device__ __forceinline__ uint32_t next() {
         x = lcg_next(x);
@@ -152,39 +154,62 @@ __device__ __forceinline__ int32_t ran2_lcg2(int32_t x) {
     return static_cast<int32_t>(mulmod_2p31m<kR2A2, kR2C2>(static_cast<uint32_t>(x)));
 }
 
+// iy / Ndiv for 1 <= iy < 2^31 as (iy m) >> 57 with m = 2^31 + 65: m Ndiv - 2^57 = 2^26 - 130, so
+// the product overshoots iy / Ndiv by less than iy 2^26 / (Ndiv 2^57) < 1 / Ndiv, never enough to
+// reach the next integer.
+constexpr uint32_t kR2SlotMul = 0x80000041u;
+static_assert(static_cast<unsigned __int128>(kR2SlotMul) * kR2Ndiv - (static_cast<unsigned __int128>(1) << 57) ==
+                  (1u << 26) - 130u,
+              "slot multiplier");
+
 // Ran2 stream with its shuffle table in LDS: tab[t * tstride] is entry t of this thread's table.
+// The last output is kept as iym1 = iy - 1, which is also what the uniform mapping reads.
 struct Ran2 {
-    int32_t idum, idum2, iy;
+    int32_t idum, idum2;
+    uint32_t iym1;
     int32_t *tab;
     uint64_t tstride;
     static constexpr int kRows = 35;
+    // next_top24() returns (iy - 1) with its low 7 bits clear, half of the top-24 word of next()
+    static constexpr float kTopScale = 0x1p-31f;
 
-    __device__ __forceinline__ int32_t next_iy() {
+    // bits 25..29 of the product's high word: one bit-field extract (written out, since the compiler
+    // otherwise folds the extract into the address arithmetic as a shift and a mask)
+    __device__ __forceinline__ static uint32_t slot_of(uint32_t hi) {
+        uint32_t slot;
+        asm("v_bfe_u32 %0, %1, 25, 5" : "=v"(slot) : "v"(hi));
+        return slot;
+    }
+    // one step of Alg. 2; returns iy - 1 in [0, M1 - 2]
+    __device__ __forceinline__ uint32_t next_iym1() {
         idum = ran2_lcg1(idum);
         idum2 = ran2_lcg2(idum2);
-        const uint32_t slot = static_cast<uint32_t>(iy) / kR2Ndiv;
-        int32_t *cell = tab + slot * tstride;
-        int32_t out = *cell - idum2;
+        // entry iy / Ndiv, from the 64-bit (iym1 + 1) m (one multiply-add)
+        const uint64_t prod = static_cast<uint64_t>(iym1) * kR2SlotMul + kR2SlotMul;
+        int32_t *cell = tab + slot_of(static_cast<uint32_t>(prod >> 32)) * tstride;
+        // iy - 1 = entry - idum2 - 1, plus Imm1 when that is negative: as unsigned words the
+        // smaller of e and e + Imm1 (e + Imm1 wraps exactly when e is negative)
+        const uint32_t e = static_cast<uint32_t>(*cell) + ~static_cast<uint32_t>(idum2);
         *cell = idum;
-        out += (out < 1) ? kR2Imm1 : 0;
-        iy = out;
-        return out;
+        const uint32_t f = e + static_cast<uint32_t>(kR2Imm1);
+        iym1 = e < f ? e : f;
+        return iym1;
     }
     // word fed to the uniform mapping: iy - 1 spans [0, 2^31), doubled
-    __device__ __forceinline__ uint32_t next() { return static_cast<uint32_t>(next_iy() - 1) << 1; }
-    __device__ __forceinline__ uint32_t next_top24() { return next() & kTop24; }
+    __device__ __forceinline__ uint32_t next() { return next_iym1() << 1; }
+    __device__ __forceinline__ uint32_t next_top24() { return next_iym1() & (kTop24 >> 1); }
 
     // state rows: int32 [35][S]: idum, idum2, iy, iv[0..31]
     __device__ __forceinline__ void load(const int32_t *st, uint64_t S, uint64_t j) {
         idum = st[j];
         idum2 = st[S + j];
-        iy = st[2 * S + j];
+        iym1 = static_cast<uint32_t>(st[2 * S + j]) - 1u;
         for (int t = 0; t < kR2Tab; ++t) tab[t * tstride] = st[(3 + t) * S + j];
     }
     __device__ __forceinline__ void store(int32_t *st, uint64_t S, uint64_t j) const {
         st[j] = idum;
         st[S + j] = idum2;
-        st[2 * S + j] = iy;
+        st[2 * S + j] = static_cast<int32_t>(iym1 + 1u);
         for (int t = 0; t < kR2Tab; ++t) st[(3 + t) * S + j] = tab[t * tstride];
     }
     // Alg. 2 initialisation: idum2 = idum; 8 discarded LCG1 steps, then 32 filling iv[31]..iv[0]
@@ -198,7 +223,7 @@ struct Ran2 {
             tab[t * tstride] = x;
         }
         idum = x;
-        iy = tab[0];
+        iym1 = static_cast<uint32_t>(tab[0]) - 1u;
     }
 };
 
@@ -215,13 +240,17 @@ struct Ran2 {
 // within 2e-6 of its exact value (r <= sqrt(48 ln 2)).
 constexpr float kMinusTwoLn2 = -1.38629436f;
 
-__device__ __forceinline__ float u_open_top24(uint32_t m) {
-    return __builtin_fmaf(static_cast<float>(m), 0x1p-32f, 0x1p-24f);
+// `scale` is the weight of the word's lowest bit: 2^-32 for a word with its low 8 bits clear, 2^-31
+// for the same bits one place lower (Ran2's iy - 1); either way float(m) scale is exact.
+__device__ __forceinline__ float u_open_top24(uint32_t m, float scale = 0x1p-32f) {
+    return __builtin_fmaf(static_cast<float>(m), scale, 0x1p-24f);
 }
-__device__ __forceinline__ float u_half_top24(uint32_t m) { return static_cast<float>(m) * 0x1p-32f; }
+__device__ __forceinline__ float u_half_top24(uint32_t m, float scale = 0x1p-32f) {
+    return static_cast<float>(m) * scale;
+}
 
-__device__ __forceinline__ float box_muller_radius_top24(uint32_t m) {
-    return __builtin_amdgcn_sqrtf(kMinusTwoLn2 * __builtin_amdgcn_logf(u_open_top24(m)));
+__device__ __forceinline__ float box_muller_radius_top24(uint32_t m, float scale = 0x1p-32f) {
+    return __builtin_amdgcn_sqrtf(kMinusTwoLn2 * __builtin_amdgcn_logf(u_open_top24(m, scale)));
 }
 __device__ __forceinline__ float box_muller_radius(uint32_t w) { return box_muller_radius_top24(w & kTop24); }
 __device__ __forceinline__ void box_muller_angle(uint32_t w, float &c, float &s) {
@@ -231,13 +260,14 @@ __device__ __forceinline__ void box_muller_angle(uint32_t w, float &c, float &s)
 }
 
 // three force components from one oscillator-step's four words, given with their low 8 bits clear
+// (or, with scale 2^-31, the same 24 bits one place lower)
 __device__ __forceinline__ void gaussian_forces_top24(uint32_t m0, uint32_t m1, uint32_t m2, uint32_t m3, float &gx,
-                                                      float &gy, float &gz) {
-    const float r0 = box_muller_radius_top24(m0);
-    const float u1 = u_half_top24(m1);
+                                                      float &gy, float &gz, float scale = 0x1p-32f) {
+    const float r0 = box_muller_radius_top24(m0, scale);
+    const float u1 = u_half_top24(m1, scale);
     gx = r0 * __builtin_amdgcn_cosf(u1);
     gy = r0 * __builtin_amdgcn_sinf(u1);
-    gz = box_muller_radius_top24(m2) * __builtin_amdgcn_cosf(u_half_top24(m3));
+    gz = box_muller_radius_top24(m2, scale) * __builtin_amdgcn_cosf(u_half_top24(m3, scale));
 }
 // the same from whole words
 __device__ __forceinline__ void gaussian_forces(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, float &gx,

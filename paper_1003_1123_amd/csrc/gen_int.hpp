@@ -51,6 +51,15 @@ RNGLD_HDI uint32_t lcg_skip(uint32_t x, uint64_t n) {
     return mul * x + add;
 }
 
+// low 32 bits of the 64-bit concatenation hi : lo shifted right by s, 0 < s < 32 (v_alignbit_b32)
+RNGLD_HDI uint32_t funnel_shift_right(uint32_t hi, uint32_t lo, uint32_t s) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_alignbit(hi, lo, s);
+#else
+    return static_cast<uint32_t>(((static_cast<uint64_t>(hi) << 32) | lo) >> s);
+#endif
+}
+
 // ---- Tausworthe component for the trinomial x^K + x^Q + 1 with step S (Eq. 2) ---------------------
 // The state occupies the top K bits; the low 32-K bits are dropped before the left shift.
 //
@@ -59,26 +68,43 @@ RNGLD_HDI uint32_t lcg_skip(uint32_t x, uint64_t n) {
 // and the low 32-K bits the next bits of the same sequence (the feedback computes them from state
 // bits only, since S + 32 + Q <= 2K for the three components).  A seeded word is such a window
 // only in its top K bits.
+//
+// The step is ((z & top K bits) << S) xor (((z << Q) xor z) >> (K - S)).  The two terms occupy
+// disjoint bits: the first the top K - S bits, the second the 32 - K + S bits below them.  So the
+// new word is the low half of the 64-bit concatenation (z >> (32 - K)) : ((z << Q) xor z) shifted
+// right by K - S, one funnel shift (v_alignbit_b32) in place of a shift and a masked merge.
 template <int Q, int S, int K>
 RNGLD_HDI uint32_t tausworthe(uint32_t z) {
-    constexpr uint32_t kTop = ~((1u << (32 - K)) - 1u);
-    const uint32_t feedback = ((z << Q) ^ z) >> (K - S);
-    return ((z & kTop) << S) ^ feedback;
+    static_assert(0 < S && S < K && K < 32 && 0 < Q, "component parameters");
+    return funnel_shift_right(z >> (32 - K), (z << Q) ^ z, K - S);
 }
 
 // The inverse step on a produced word w = (y_{n} .. y_{n+31}): the previous word is
 // (y_{n-S} .. y_{n+31-S}), i.e. w >> S with the S older bits on top.  Each older bit follows from
 // the recurrence solved for its oldest term, y_j = y_{j+K} xor y_{j+Q}.  The y_{j+K} all lie in w;
 // y_{j+Q} lies in w >> S unless it is itself one of the S new bits (Q < S), so the top bits t
-// satisfy t = c xor (t << Q) on the top S bits, solved by t = c (1 + L^Q)(1 + L^2Q)(1 + L^4Q)...
+// satisfy t = c xor (t << Q) on the top S bits, solved by t = sum of c << kQ over kQ < S.
+// Computed with t in the low S bits of a word: there c = (w >> (32 - K)) xor (w >> (32 - Q)), the
+// sum is built by tripling and doubling its number of terms (t xor t << m xor t << 2m is one
+// three-input op), bits at and above S are junk that only moves up, and one funnel shift puts the
+// S bits on top of w >> S.
 // Exact for any word that tausworthe() produced from another produced word.
 template <int Q, int S, int K>
 RNGLD_HDI uint32_t tausworthe_inv(uint32_t w) {
-    static_assert(S <= K && K <= 32 && Q > 0, "component parameters");
-    constexpr uint32_t kTopS = ~0u << (32 - S);
-    uint32_t t = ((w << (K - S)) ^ ((w >> S) << Q)) & kTopS;
-    for (int sh = Q; sh < S; sh *= 2) t ^= t << sh;
-    return t | (w >> S);
+    static_assert(0 < S && S < K && K < 32 && 0 < Q && Q < 32, "component parameters");
+    uint32_t t = (w >> (32 - K)) ^ (w >> (32 - Q));
+    constexpr int kTerms = (S + Q - 1) / Q;  // k = 0 .. kTerms - 1
+    for (int have = 1; have < kTerms;) {
+        const int sh = have * Q;
+        if (2 * have >= kTerms || 2 * sh >= 32) {
+            t ^= t << sh;
+            have *= 2;
+        } else {
+            t ^= (t << sh) ^ (t << (2 * sh));
+            have *= 3;
+        }
+    }
+    return funnel_shift_right(t, w, S);
 }
 
 // A x mod M for M = 2^31 - C and 0 <= x < M (the multiplicative steps of Ran2's two generators):

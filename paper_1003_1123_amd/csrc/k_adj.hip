@@ -49,7 +49,8 @@ __device__ __forceinline__ void bind_tab(Gen &g, int32_t *lds, int tid, int bloc
 template <class Gen>
 __device__ __forceinline__ void park(Gen &g) {
     if constexpr (IsRan2A<Gen>::value) {
-        g.idum = g.idum2 = g.iy = 1;
+        g.idum = g.idum2 = 1;
+        g.iym1 = 0;
         for (int t = 0; t < kR2Tab; ++t) g.tab[t * g.tstride] = 1;
     } else {
         g.t1 = g.t2 = g.t3 = g.lcg = 0x9E3779B9u;
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(BLOCK) void ld_ckpt_kernel(AdjArgs a) {
         for (; s < e; ++s) {
             const uint32_t w0 = g.next_top24(), w1 = g.next_top24(), w2 = g.next_top24(), w3 = g.next_top24();
             float gf[3];
-            gaussian_forces_top24(w0, w1, w2, w3, gf[0], gf[1], gf[2]);
+            gaussian_forces_top24(w0, w1, w2, w3, gf[0], gf[1], gf[2], Gen::kTopScale);
 #pragma unroll
             for (int d = 0; d < 3; ++d) ld_update(q, x[d], v[d], gf[d]);
             if constexpr (LOSS) {
@@ -208,7 +209,7 @@ __global__ __launch_bounds__(BLOCK) void ld_adjoint_kernel(AdjArgs a) {
             float *row = a.scratch + static_cast<uint64_t>(s - s0) * 9 * NT + i;
             const uint32_t w0 = g.next_top24(), w1 = g.next_top24(), w2 = g.next_top24(), w3 = g.next_top24();
             float gf[3];
-            gaussian_forces_top24(w0, w1, w2, w3, gf[0], gf[1], gf[2]);
+            gaussian_forces_top24(w0, w1, w2, w3, gf[0], gf[1], gf[2], Gen::kTopScale);
             if (act)
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {

@@ -46,7 +46,7 @@ __device__ __forceinline__ void draw_forces(Gen &g, float &gx, float &gy, float 
         const uint32_t m1 = g.next_top24();
         const uint32_t m2 = g.next_top24();
         const uint32_t m3 = g.next_top24();
-        gaussian_forces_top24(m0, m1, m2, m3, gx, gy, gz);
+        gaussian_forces_top24(m0, m1, m2, m3, gx, gy, gz, Gen::kTopScale);
     }
 }
 
@@ -55,7 +55,7 @@ __device__ __forceinline__ void gen_park(Gen &g) {
     if constexpr (IsRan2<Gen>::value) {
         g.idum = 1;
         g.idum2 = 1;
-        g.iy = 1;
+        g.iym1 = 0;
         for (int t = 0; t < kR2Tab; ++t) g.tab[t * g.tstride] = 1;
     } else if constexpr (IsLcg<Gen>::value) {
         g.x = 0x9E3779B9u;
@@ -251,15 +251,15 @@ __global__ __launch_bounds__(kBulkBlock) void ran2_step_kernel(int32_t *st, uint
     Ran2 g;
     g.idum = st[i];
     g.idum2 = st[S + i];
-    g.iy = st[2 * S + i];
+    g.iym1 = static_cast<uint32_t>(st[2 * S + i]) - 1u;
     g.tab = st + 3 * S + i;
     g.tstride = S;
     const uint32_t w0 = g.next_top24(), w1 = g.next_top24(), w2 = g.next_top24(), w3 = g.next_top24();
     st[i] = g.idum;
     st[S + i] = g.idum2;
-    st[2 * S + i] = g.iy;
+    st[2 * S + i] = static_cast<int32_t>(g.iym1 + 1u);
     float gf[3];
-    gaussian_forces_top24(w0, w1, w2, w3, gf[0], gf[1], gf[2]);
+    gaussian_forces_top24(w0, w1, w2, w3, gf[0], gf[1], gf[2], Ran2::kTopScale);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         float xd = x[d * n + i], vd = v[d * n + i];

@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kBulkBlock) void ran2_uniform_kernel(int32_t *st, u
     g.tstride = kBulkBlock;
     g.load(st, S, j);
     uint32_t *o = out + j;
-    for (uint64_t t = 0; t < per_stream; ++t) o[t * S] = static_cast<uint32_t>(g.next_iy());
+    for (uint64_t t = 0; t < per_stream; ++t) o[t * S] = g.next_iym1() + 1u;
     g.store(st, S, j);
 }
 

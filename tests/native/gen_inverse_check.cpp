@@ -3,7 +3,8 @@
 // steps returns every produced word exactly, and a seeded word's top K bits.  Also checks the
 // produced words against the component's bit recurrence y_m = y_{m-K+Q} xor y_{m-K} (Eq. 2), which
 // the inverse relies on.  And the modular product A x mod (2^31 - C) of Ran2's two generators
-// (mulmod_2p31m) against the plain 64-bit remainder, at random and at the ends of its range.
+// (mulmod_2p31m) against the plain 64-bit remainder, at random and at the ends of its range.  And the
+// forward step's funnel-shift form against the masked shift-and-xor of Eq. 2 on arbitrary words.
 // Prints "ok" on success.
 #include <cstdio>
 #include <cstdint>
@@ -24,6 +25,12 @@ static uint32_t rnd() {
 template <int Q, int S, int K>
 static int check_component(int n_seeds, int n_steps) {
     int bad = 0;
+    // the funnel-shift form of the step equals Eq. 2's masked shift-and-xor on arbitrary words
+    for (int t = 0; t < 1 << 16; ++t) {
+        const uint32_t z = t < 64 ? (t < 32 ? 1u << t : ~(1u << (t - 32))) : rnd();
+        const uint32_t plain = ((z & ~((1u << (32 - K)) - 1u)) << S) ^ (((z << Q) ^ z) >> (K - S));
+        if (tausworthe<Q, S, K>(z) != plain) ++bad;
+    }
     for (int t = 0; t < n_seeds; ++t) {
         const uint32_t z0 = tausworthe_lift<K>(rnd());
         std::vector<uint32_t> w(n_steps + 1);

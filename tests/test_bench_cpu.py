@@ -71,11 +71,18 @@ def test_valu_roofline_uses_the_loop_counts_and_the_mix_bound(kind):
     assert e["traffic"] is None  # no counters are recorded for these kernels
 
 
-def test_adjoint_loops_have_no_mix_bound():
+def test_adjoint_loops_mix_bounds():
     if "step_loops" not in bench._kernel_isa():
         pytest.skip("the library has not been built (no kernel_isa.json)")
-    assert bench.valu_mix_bound("adjoint_backward") is None  # FP64 accumulation: not in the probe's table
-    assert bench.valu_per_osc_step("adjoint_backward") > bench.valu_per_osc_step("taus")
+    # the backward sweep regenerates the same four words per step with inverse steps and adds the
+    # adjoint recursion and its FP32 sums: more instructions and a lower bound than the forward
+    assert bench.valu_per_osc_step("adjoint_backward") > bench.valu_per_osc_step("adjoint_forward")
+    assert bench.valu_per_osc_step("adjoint_forward") >= bench.valu_per_osc_step("taus")
+    bwd, fwd = bench.valu_mix_bound("adjoint_backward"), bench.valu_mix_bound("adjoint_forward")
+    assert bwd is not None and fwd is not None
+    assert bwd < fwd <= bench.valu_mix_bound("taus")
+    # an FP64 instruction in a loop leaves it without a bound (the probe measured no FP64 rates)
+    assert bench.valu_classes({"v_fma_f64": 2, "v_xor_b32_e32": 3}) == {"unmeasured": 2, "other": 3}
 
 
 def test_counter_traffic_only_for_the_recorded_machine_code(monkeypatch):
