@@ -136,6 +136,17 @@ def valu_per_osc_step(which):
     return loops[name]["valu_per_iteration"]
 
 
+def adjoint_forward_valu(n_steps, t_begin, t_end):
+    """VALU lane-instructions per oscillator-step of the checkpointing forward run, averaged over
+    the run: its plain step loop (the smallest) outside the loss window, the loop that also
+    accumulates the loss and the adjoint terms (the largest) inside it."""
+    loop = _kernel_isa().get("step_loops", {}).get(STEP_LOOP_KERNELS["adjoint_forward"])
+    if loop is None:
+        raise RuntimeError("kernel_isa.json has no step-loop count for the adjoint forward: rebuild the library")
+    inside = t_end - t_begin + 1
+    return ((n_steps - inside) * min(loop["all_loops"]) + inside * loop["valu_per_iteration"]) / n_steps
+
+
 def valu_entry(kernel, valu_per_unit, units, seconds, mix_bound_units_per_s=None):
     """VALU roofline of `units` oscillator-steps (each `valu_per_unit` lane-instructions) in `seconds`."""
     achieved = valu_per_unit * units / seconds / 1e12
@@ -608,10 +619,10 @@ def extra_config5(R, W, torch):
                "loss": L, "grad_k_gamma_kT": grad, "grad_standard_errors": run.grad_se[0].tolist(),
                "forward_ms": fwd_ms, "backward_ms": bwd_ms, "fwd_plus_bwd_over_fwd": (fwd_ms + bwd_ms) / fwd_ms,
                "forward_osc_steps_per_s": osc / (fwd_ms / 1e3),
-               "roofline_forward": valu_entry("ld_ckpt_kernel<HybridTaus>", valu_per_osc_step("adjoint_forward"),
-                                              osc, fwd_ms / 1e3)}
+               "roofline_forward": valu_entry("ld_ckpt_kernel<HybridTaus>",
+                                              adjoint_forward_valu(T, c5["t_begin"], c5["t_end"]), osc, fwd_ms / 1e3)}
         if not replay:
-            res["roofline_backward"] = valu_entry("ld_adjoint_seg_kernel + combine",
+            res["roofline_backward"] = valu_entry("ld_adjoint_seg_kernel + sum",
                                                   valu_per_osc_step("adjoint_backward"), osc, bwd_ms / 1e3)
             # the common-random-number central differences the gradient replaces: 6 forward runs
             e0, e1 = _ev(torch)

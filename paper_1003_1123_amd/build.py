@@ -105,18 +105,18 @@ def step_loop_valu(asm: str, symbol: str) -> dict:
             spans.append((labels[m.group(1)], i))
     ops_of = {(a, b): [x.split()[0] for x in body[a:b + 1] if x.strip().startswith("v_")] for a, b in spans}
     stepping = [sp for sp in spans if "v_log_f32_e32" in ops_of[sp]]
-    best = None
-    for a, b in stepping:
-        if any(a <= c and d <= b and (c, d) != (a, b) for c, d in stepping):
-            continue  # holds another step loop
-        if best is None or len(ops_of[(a, b)]) > len(best):
-            best = ops_of[(a, b)]
-    if best is None:
+    innermost = [sp for sp in stepping
+                 if not any(sp[0] <= c and d <= sp[1] and (c, d) != sp for c, d in stepping)]
+    if not innermost:
         raise RuntimeError("no step loop found in %s" % symbol)
+    best = max((ops_of[sp] for sp in innermost), key=len)
     counts = {}
     for op in best:
         counts[op] = counts.get(op, 0) + 1
-    return {"valu_per_iteration": len(best), "by_opcode": dict(sorted(counts.items()))}
+    # every step loop's size, for kernels whose steps take different loops (e.g. inside and outside
+    # a loss window)
+    return {"valu_per_iteration": len(best), "by_opcode": dict(sorted(counts.items())),
+            "all_loops": sorted(len(ops_of[sp]) for sp in innermost)}
 
 
 def _assembly(src: str) -> str:
@@ -140,7 +140,7 @@ def fingerprint_kernels() -> dict:
     for name, (src, pattern) in FINGERPRINTED.items():
         bodies = _function_bodies(asm[src], pattern)
         if not bodies:
-            raise RuntimeError("no %s in %s" % (name, asm_path))
+            raise RuntimeError("no %s in the assembly of %s" % (name, src))
         h = hashlib.sha256()
         for sym in sorted(bodies):
             h.update(sym.encode() + b"\n" + bodies[sym].encode() + b"\n")

@@ -1171,7 +1171,7 @@ struct AdjLayout {
     std::vector<AdjCoef> adj;
     uint32_t n_tiles = 0;
     bool any_replay = false, any_inverse = false;
-    size_t off_ens = 0, off_adj = 0, off_partials = 0, off_scratch = 0, off_seg_f = 0, off_seg_d = 0, bytes = 0;
+    size_t off_ens = 0, off_adj = 0, off_partials = 0, off_scratch = 0, off_seg_d = 0, bytes = 0;
 };
 
 // B^K for the adjoint step matrix B = [[1 - kap h, -kap], [c h, c]] (row-major), the map that
@@ -1244,9 +1244,10 @@ int layout_adj(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t 
         A.inv_c_lo = static_cast<float>(1.0 / static_cast<double>(A.f.c) - static_cast<double>(A.inv_c));
         // the register-only backward launches one block row per segment (grid y below 2^16)
         const uint64_t nseg = (static_cast<uint64_t>(n_steps) + K - 1) / K;
-        A.inverse = g.kind == RNGLD_HYBRID_TAUS && !(loss.flags & RNGLD_ADJ_REPLAY) && K <= kAdjInverseMaxK &&
-                    nseg < 65536 && reverse_growth(A.f, K, kAdjGrowthLimit) <= kAdjGrowthLimit;
-        if (A.inverse) adjoint_propagator(A.f, K, A.phi);
+        A.lam = g.kind == RNGLD_HYBRID_TAUS && K <= kAdjInverseMaxK && nseg < 65536 &&
+                reverse_growth(A.f, K, kAdjGrowthLimit) <= kAdjGrowthLimit;
+        A.inverse = A.lam && !(loss.flags & RNGLD_ADJ_REPLAY);
+        if (A.lam) adjoint_propagator(A.f, K, A.phi);
         if (E.n) {
             L->any_inverse |= A.inverse != 0;
             L->any_replay |= A.inverse == 0;
@@ -1261,8 +1262,7 @@ int layout_adj(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t 
     L->bytes = L->off_scratch + (backward && L->any_replay ? align_up(9ull * K * n_total * sizeof(float)) : 0);
     if (backward && L->any_inverse) {  // one record per (oscillator, segment)
         const uint64_t nseg = (static_cast<uint64_t>(n_steps) + K - 1) / K;
-        L->off_seg_f = L->bytes;
-        L->off_seg_d = align_up(L->off_seg_f + nseg * kAdjSegF * n_total * sizeof(float));
+        L->off_seg_d = L->bytes;
         L->bytes = align_up(L->off_seg_d + nseg * kAdjSegD * n_total * sizeof(double));
     }
     return RNGLD_OK;
@@ -1281,8 +1281,10 @@ int check_adj_common(const rngld_cfg *cfg, Gen *g, const ld_ensemble *h_ens, uin
     return RNGLD_OK;
 }
 
+// x[3], v[3], the generator rows and, for Hybrid Taus, the loss adjoint lam_x[3], lam_v[3]
 size_t ckpt_record_bytes(const Gen &g, uint64_t n_total) {
-    const uint32_t rows = g.kind == RNGLD_HYBRID_TAUS ? 4 : 35;
+    const uint32_t rows = g.kind == RNGLD_HYBRID_TAUS ? 4 + 6 : 35;
+    static_assert(kCkptLamRow == 6 + 4, "adjoint rows follow the Hybrid Taus state rows");
     return static_cast<size_t>(n_total) * (6 + rows) * 4;
 }
 
@@ -1382,7 +1384,6 @@ extern "C" int ld_run_backward(const rngld_cfg *cfg, const void *d_ckpt, size_t 
     a.ckpt = const_cast<uint8_t *>(static_cast<const uint8_t *>(d_ckpt));
     a.rec_bytes = ckpt_record_bytes(g, n_total);
     a.scratch = L.any_replay ? reinterpret_cast<float *>(ws + L.off_scratch) : nullptr;
-    a.seg_f = L.any_inverse ? reinterpret_cast<float *>(ws + L.off_seg_f) : nullptr;
     a.seg_d = L.any_inverse ? reinterpret_cast<double *>(ws + L.off_seg_d) : nullptr;
     a.partials = reinterpret_cast<double *>(ws + L.off_partials);
     // n_steps >= 1 (check_loss); every tile's partials are written by exactly one of the kernels

@@ -89,22 +89,24 @@ RNGLD_HDI uint32_t tausworthe(uint32_t z) {
 // three-input op), bits at and above S are junk that only moves up, and one funnel shift puts the
 // S bits on top of w >> S.
 // Exact for any word that tausworthe() produced from another produced word.
+// t holds the sum of c << kQ for k < HAVE; returns it for all kQ < S (resolved at compile time)
+template <int Q, int S, int HAVE>
+RNGLD_HDI uint32_t tausworthe_inv_terms(uint32_t t) {
+    constexpr int kTerms = (S + Q - 1) / Q;
+    constexpr int kShift = HAVE * Q;
+    if constexpr (HAVE >= kTerms)
+        return t;
+    else if constexpr (2 * HAVE >= kTerms || 2 * kShift >= 32)
+        return tausworthe_inv_terms<Q, S, 2 * HAVE>(t ^ (t << kShift));
+    else
+        return tausworthe_inv_terms<Q, S, 3 * HAVE>(t ^ (t << kShift) ^ (t << (2 * kShift)));
+}
+
 template <int Q, int S, int K>
 RNGLD_HDI uint32_t tausworthe_inv(uint32_t w) {
     static_assert(0 < S && S < K && K < 32 && 0 < Q && Q < 32, "component parameters");
-    uint32_t t = (w >> (32 - K)) ^ (w >> (32 - Q));
-    constexpr int kTerms = (S + Q - 1) / Q;  // k = 0 .. kTerms - 1
-    for (int have = 1; have < kTerms;) {
-        const int sh = have * Q;
-        if (2 * have >= kTerms || 2 * sh >= 32) {
-            t ^= t << sh;
-            have *= 2;
-        } else {
-            t ^= (t << sh) ^ (t << (2 * sh));
-            have *= 3;
-        }
-    }
-    return funnel_shift_right(t, w, S);
+    const uint32_t c = (w >> (32 - K)) ^ (w >> (32 - Q));
+    return funnel_shift_right(tausworthe_inv_terms<Q, S, 1>(c), w, S);
 }
 
 // A x mod M for M = 2^31 - C and 0 <= x < M (the multiplicative steps of Ran2's two generators):

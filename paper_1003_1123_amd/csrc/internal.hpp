@@ -137,15 +137,19 @@ struct AdjCoef {
     // lam_v) of the state at a segment's start is phi * (adjoint at its end) + what the segment's
     // own loss terms contribute; phi = B^K with B = [[1 - kap h, -kap], [c h, c]], row-major
     float phi[4];
+    // 1: the forward run writes the loss adjoint into each checkpoint record (the ensemble can take
+    // the register-only backward; inverse is this without RNGLD_ADJ_REPLAY)
+    uint32_t lam;
 };
 
 // width of the per-tile FP64 partials of the adjoint kernels: three sums and their squares
 constexpr uint32_t kAdjPartW = 6;
-// per (oscillator, segment) record of the segment-parallel register-only backward: FP32 rows
-// [0, 6) the segment's own adjoint at its start (lam_x[3], lam_v[3]), [6, 24) the responses
-// sum_s a_s z_s and sum_s b_s z_s for z = x, v, g and each component; FP64 rows [0, 3) the
-// gradient sums with a zero adjoint at the segment's end
-constexpr uint32_t kAdjSegF = 24, kAdjSegD = 3;
+// per (oscillator, segment) record of the segment-parallel register-only backward: FP64 rows
+// [0, 3), the segment's three gradient sums
+constexpr uint32_t kAdjSegD = 3;
+// checkpoint rows of a Hybrid Taus record: x[3], v[3], the 4 generator rows, then the loss adjoint
+// lam_x[3], lam_v[3] of the record's state (written by the forward run for ensembles with lam)
+constexpr uint32_t kCkptLamRow = 10;
 
 struct AdjArgs {
     void *state;  // forward: live state (stride S); unused by backward
@@ -160,8 +164,7 @@ struct AdjArgs {
     uint8_t *ckpt;
     uint64_t rec_bytes;  // bytes per checkpoint record
     float *scratch;      // backward, replay path: [K][9][NT]
-    float *seg_f;        // backward, register-only path: [nseg][kAdjSegF][NT]
-    double *seg_d;       //                               [nseg][kAdjSegD][NT]
+    double *seg_d;       // backward, register-only path: [nseg][kAdjSegD][NT]
     double *partials;    // [n_tiles][kAdjPartW]: the loss (forward), or per-oscillator gradient
                          // sums and sums of squares (backward)
 };

@@ -92,8 +92,30 @@ __device__ __forceinline__ void block_grad_partials(bool act, double gk, double 
     block_sum6<BLOCK>(q, red, dst);
 }
 
+// one step of the adjoint recursion with no loss term: (lam_x, lam_v) <- B (lam_x, lam_v),
+// mu = lam_v + h lam_x, lam_x' = lam_x - kap mu, lam_v' = c mu
+__device__ __forceinline__ void adjoint_step(const LdCoef &q, float &lx, float &lv) {
+    const float mu = lv + q.h * lx;
+    lx = lx - q.kap * mu;
+    lv = q.c * mu;
+}
+
+// the loss window's step range [lo, hi) within steps [s0, s1): the loss takes the positions after
+// steps t_begin..t_end, i.e. steps s in [t_begin - 1, t_end)
+__device__ __forceinline__ void window_part(const AdjArgs &a, uint32_t s0, uint32_t s1, uint32_t &lo, uint32_t &hi) {
+    const uint32_t w_lo = a.t_begin - 1, w_hi = a.t_end;
+    lo = s0 > w_lo ? s0 : (w_lo < s1 ? w_lo : s1);
+    hi = lo > w_hi ? lo : (w_hi < s1 ? w_hi : s1);
+}
+
 // forward run from the current state with checkpoints every K steps; loss partial = sum of x^2
-// over the loss window (scaled on finalisation)
+// over the loss window (scaled on finalisation).
+// For ensembles with lam each record also gets the loss adjoint of its state, the starting point
+// of the register-only backward sweep of the segment that ends there.  The adjoint recursion is
+// linear with the constant matrix B, so what a segment's own loss terms hand to the adjoint at its
+// start is the sum over its window steps j = 1..K of B^j (2 x_j, 0); it is accumulated here from
+// the forward positions (B^j e1 advanced alongside), and a last pass over the records, latest
+// first, adds what the later segments hand back: lam(start) = own + B^K lam(end), in FP64.
 template <class Gen, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void ld_ckpt_kernel(AdjArgs a) {
     extern __shared__ int32_t lds[];
@@ -101,25 +123,32 @@ __global__ __launch_bounds__(BLOCK) void ld_ckpt_kernel(AdjArgs a) {
     const uint32_t tile = blockIdx.x;
     const uint32_t e = find_ensemble(a.ens, a.n_ens, tile);
     const EnsDev &E = a.ens[e];
-    const LdCoef q = a.adj[e].f;
+    const AdjCoef &A = a.adj[e];
+    const LdCoef q = A.f;
+    const bool lam = A.lam != 0;
     const uint64_t i = E.offset + static_cast<uint64_t>(tile - E.tile_begin) * BLOCK + threadIdx.x;
     const bool act = i < E.offset + E.n;
+    const uint64_t NT = a.NT;
     Gen g;
     bind_tab(g, lds, threadIdx.x, BLOCK);
     float x[3] = {0, 0, 0}, v[3] = {0, 0, 0};
     if (act) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            x[d] = a.x[d * a.NT + i];
-            v[d] = a.v[d * a.NT + i];
+            x[d] = a.x[d * NT + i];
+            v[d] = a.v[d * NT + i];
         }
         load_state(g, a.state, a.S, i);
     } else {
         park(g);
     }
-    // steps [s, e) of the run, adding x^2 after each step to lseg when LOSS
-    auto steps = [&](auto loss_tag, uint32_t s, uint32_t e, float &lseg) {
+    // B^j e1 of the current step and the segment's own adjoint sums (without the factor 2)
+    float al = 0.0f, be = 0.0f, ox[3] = {0, 0, 0}, ov[3] = {0, 0, 0};
+    // steps [s, e) of the run, adding x^2 after each step to lseg when LOSS and the step's own
+    // adjoint terms when LAM
+    auto steps = [&](auto loss_tag, auto lam_tag, uint32_t s, uint32_t e, float &lseg) {
         constexpr bool LOSS = decltype(loss_tag)::value;
+        constexpr bool LAM = decltype(lam_tag)::value;
         for (; s < e; ++s) {
             const uint32_t w0 = g.next_top24(), w1 = g.next_top24(), w2 = g.next_top24(), w3 = g.next_top24();
             float gf[3];
@@ -130,44 +159,99 @@ __global__ __launch_bounds__(BLOCK) void ld_ckpt_kernel(AdjArgs a) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) lseg += x[d] * x[d];
             }
+            if constexpr (LAM) {
+                adjoint_step(q, al, be);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    ox[d] += al * x[d];
+                    ov[d] += be * x[d];
+                }
+            }
         }
     };
-    // the loss takes the positions after steps t_begin..t_end, i.e. steps s in [t_begin - 1, t_end)
-    const uint32_t w_lo = a.t_begin - 1, w_hi = a.t_end;
+    auto rec_f = [&](uint32_t r) { return reinterpret_cast<float *>(a.ckpt + static_cast<uint64_t>(r) * a.rec_bytes); };
     // the loss sum: FP32 within each K-step segment (at most 3K terms of x^2), FP64 across segments
     double lsum = 0.0;
     for (uint32_t s0 = 0; s0 < a.n_steps; s0 += a.K) {
+        float *rx = rec_f(s0 / a.K);
         if (act) {
-            uint8_t *rec = a.ckpt + static_cast<uint64_t>(s0 / a.K) * a.rec_bytes;
-            float *rx = reinterpret_cast<float *>(rec);
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                rx[d * a.NT + i] = x[d];
-                rx[(3 + d) * a.NT + i] = v[d];
+                rx[d * NT + i] = x[d];
+                rx[(3 + d) * NT + i] = v[d];
             }
-            store_state(g, rx + 6 * a.NT, a.NT, i);
+            store_state(g, rx + 6 * NT, NT, i);
         }
         const uint32_t s1 = (s0 + a.K < a.n_steps) ? s0 + a.K : a.n_steps;
-        const uint32_t lo = s0 > w_lo ? s0 : (w_lo < s1 ? w_lo : s1);
-        const uint32_t hi = lo > w_hi ? lo : (w_hi < s1 ? w_hi : s1);
+        uint32_t lo, hi;
+        window_part(a, s0, s1, lo, hi);
         float lseg = 0.0f;
-        steps(std::false_type{}, s0, lo, lseg);
-        steps(std::true_type{}, lo, hi, lseg);
-        steps(std::false_type{}, hi, s1, lseg);
+        steps(std::false_type{}, std::false_type{}, s0, lo, lseg);
+        if (lam && hi > lo) {
+            // B^(lo - s0) e1 before the first window step
+            al = 1.0f;
+            be = 0.0f;
+            for (uint32_t j = s0; j < lo; ++j) adjoint_step(q, al, be);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) ox[d] = ov[d] = 0.0f;
+            steps(std::true_type{}, std::true_type{}, lo, hi, lseg);
+            // the segment's own adjoint, parked in its start record until the last pass
+            if (act)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    rx[(kCkptLamRow + d) * NT + i] = 2.0f * ox[d];
+                    rx[(kCkptLamRow + 3 + d) * NT + i] = 2.0f * ov[d];
+                }
+        } else {
+            steps(std::true_type{}, std::false_type{}, lo, hi, lseg);
+        }
+        steps(std::false_type{}, std::false_type{}, hi, s1, lseg);
         lsum += static_cast<double>(lseg);
     }
+    const uint32_t nseg = (a.n_steps + a.K - 1) / a.K;
     if (act) {
         // the end state: the live buffers and the last checkpoint record
-        float *rx = reinterpret_cast<float *>(a.ckpt + static_cast<uint64_t>((a.n_steps + a.K - 1) / a.K) * a.rec_bytes);
+        float *rx = rec_f(nseg);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            a.x[d * a.NT + i] = x[d];
-            a.v[d * a.NT + i] = v[d];
-            rx[d * a.NT + i] = x[d];
-            rx[(3 + d) * a.NT + i] = v[d];
+            a.x[d * NT + i] = x[d];
+            a.v[d * NT + i] = v[d];
+            rx[d * NT + i] = x[d];
+            rx[(3 + d) * NT + i] = v[d];
         }
         store_state(g, a.state, a.S, i);
-        store_state(g, rx + 6 * a.NT, a.NT, i);
+        store_state(g, rx + 6 * NT, NT, i);
+    }
+    if (lam && act) {
+        // latest record first: the end state's adjoint is 0; each segment's start adjoint is its
+        // own part plus B^K times its end adjoint (every segment but the last is K steps long, and
+        // the last one's end adjoint is 0)
+        double lx[3] = {0, 0, 0}, lv[3] = {0, 0, 0};
+        for (uint32_t seg = nseg; seg-- > 0;) {
+            float *r_end = rec_f(seg + 1), *r_start = rec_f(seg);
+            const uint32_t s0 = seg * a.K, s1 = (s0 + a.K < a.n_steps) ? s0 + a.K : a.n_steps;
+            uint32_t lo, hi;
+            window_part(a, s0, s1, lo, hi);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                r_end[(kCkptLamRow + d) * NT + i] = static_cast<float>(lx[d]);
+                r_end[(kCkptLamRow + 3 + d) * NT + i] = static_cast<float>(lv[d]);
+                double nx = A.phi[0] * lx[d] + A.phi[1] * lv[d];
+                double nv = A.phi[2] * lx[d] + A.phi[3] * lv[d];
+                if (hi > lo) {
+                    nx += r_start[(kCkptLamRow + d) * NT + i];
+                    nv += r_start[(kCkptLamRow + 3 + d) * NT + i];
+                }
+                lx[d] = nx;
+                lv[d] = nv;
+            }
+        }
+        float *r0 = rec_f(0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            r0[(kCkptLamRow + d) * NT + i] = static_cast<float>(lx[d]);
+            r0[(kCkptLamRow + 3 + d) * NT + i] = static_cast<float>(lv[d]);
+        }
     }
     // the loss sum and its square (the per-oscillator spread of the loss)
     const double qv[6] = {act ? lsum : 0.0, act ? lsum * lsum : 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -244,7 +328,9 @@ __global__ __launch_bounds__(BLOCK) void ld_adjoint_kernel(AdjArgs a) {
 }
 
 // register-only backward sweep (Hybrid Taus), one thread per (oscillator, segment): blockIdx.y is
-// the segment; the record of (oscillator, segment) goes to seg_f / seg_d
+// the segment.  The sweep starts from the loss adjoint that the forward run left in the record at
+// the segment's end, so each thread's sums are its segment's share of the gradient; they go to
+// seg_d and a second pass adds an oscillator's segments in order.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void ld_adjoint_seg_kernel(AdjArgs a) {
     const uint32_t tile = blockIdx.x, seg = blockIdx.y;
@@ -259,24 +345,19 @@ __global__ __launch_bounds__(BLOCK) void ld_adjoint_seg_kernel(AdjArgs a) {
     const uint64_t NT = a.NT;
     const uint32_t s0 = seg * a.K;
     const uint32_t s1 = (s0 + a.K < a.n_steps) ? s0 + a.K : a.n_steps;
-    // record seg + 1 holds the state at s1 (the end state for the last segment)
+    // record seg + 1 holds the state at s1 (the end state for the last segment) and its adjoint
     const float *rec = reinterpret_cast<const float *>(a.ckpt + static_cast<uint64_t>(seg + 1) * a.rec_bytes);
-    float x[3], v[3];
+    float x[3], v[3], lx[3], lv[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         x[d] = rec[d * NT + col];
         v[d] = rec[(3 + d) * NT + col];
+        lx[d] = rec[(kCkptLamRow + d) * NT + col];
+        lv[d] = rec[(kCkptLamRow + 3 + d) * NT + col];
     }
     HybridTaus g;
     g.load(reinterpret_cast<const uint32_t *>(rec + 6 * NT), NT, col);
-    float lx[3] = {0, 0, 0}, lv[3] = {0, 0, 0};
-    // responses to the end adjoint: z_a[d] = sum_s a_s z_s, z_b[d] = sum_s b_s z_s (z = x, v, g)
-    float xa[3] = {0, 0, 0}, xb[3] = {0, 0, 0}, va[3] = {0, 0, 0}, vb[3] = {0, 0, 0};
-    float ga[3] = {0, 0, 0}, gb[3] = {0, 0, 0};
-    // the two unit end adjoints carried by the homogeneous recursion (the same in every lane):
-    // (p1x, p1v) from (1, 0), (p2x, p2v) from (0, 1); mu of each gives a_s and b_s
-    float p1x = 1.0f, p1v = 0.0f, p2x = 0.0f, p2v = 1.0f;
-    // the segment's own gradient as sums over its steps and the three components of mu x, mu v and
+    // the segment's gradient as sums over its steps and the three components of mu x, mu v and
     // mu g, scaled by the partials at the end: K terms per component in FP32
     float smx = 0.0f, smv = 0.0f, smg = 0.0f;
     // x, v hold the state after step s on entry to step s
@@ -288,11 +369,6 @@ __global__ __launch_bounds__(BLOCK) void ld_adjoint_seg_kernel(AdjArgs a) {
         const uint32_t w0 = g.prev_top24();
         float gf[3];
         gaussian_forces_top24(w0, w1, w2, w3, gf[0], gf[1], gf[2]);
-        const float as = p1v + h * p1x, bs = p2v + h * p2x;
-        p1x = p1x - kap * as;
-        p1v = c * as;
-        p2x = p2x - kap * bs;
-        p2v = c * bs;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             if (in_loss) lx[d] += 2.0f * x[d];
@@ -303,12 +379,6 @@ __global__ __launch_bounds__(BLOCK) void ld_adjoint_seg_kernel(AdjArgs a) {
             smx += mu * xs;
             smv += mu * vs;
             smg += mu * gf[d];
-            xa[d] += as * xs;
-            xb[d] += bs * xs;
-            va[d] += as * vs;
-            vb[d] += bs * vs;
-            ga[d] += as * gf[d];
-            gb[d] += bs * gf[d];
             lx[d] = lx[d] - kap * mu;
             lv[d] = c * mu;
             x[d] = xs;
@@ -316,64 +386,32 @@ __global__ __launch_bounds__(BLOCK) void ld_adjoint_seg_kernel(AdjArgs a) {
         }
     }
     if (!act) return;
-    float *rf = a.seg_f + static_cast<uint64_t>(seg) * kAdjSegF * NT + i;
     double *rd = a.seg_d + static_cast<uint64_t>(seg) * kAdjSegD * NT + i;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        rf[d * NT] = lx[d];
-        rf[(3 + d) * NT] = lv[d];
-        rf[(6 + d) * NT] = xa[d];
-        rf[(9 + d) * NT] = xb[d];
-        rf[(12 + d) * NT] = va[d];
-        rf[(15 + d) * NT] = vb[d];
-        rf[(18 + d) * NT] = ga[d];
-        rf[(21 + d) * NT] = gb[d];
-    }
     rd[0] = -static_cast<double>(A.dkap_dk) * smx;
     rd[NT] = static_cast<double>(A.dc_dgamma) * smv + static_cast<double>(A.dsig_dgamma) * smg;
     rd[2 * NT] = static_cast<double>(A.dsig_dkT) * smg;
 }
 
-// per-oscillator pass over the segment records, last segment first: the adjoint arriving at a
-// segment's end is what the later segments hand back; its response terms complete the gradient
+// per-oscillator sum of the segments' gradient shares in segment order, then the block's partials
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void ld_adjoint_combine_kernel(AdjArgs a) {
+__global__ __launch_bounds__(BLOCK) void ld_adjoint_sum_kernel(AdjArgs a) {
     __shared__ double red[BLOCK / 64][6];
     const uint32_t tile = blockIdx.x;
     const uint32_t e = find_ensemble(a.ens, a.n_ens, tile);
     const EnsDev &E = a.ens[e];
-    const AdjCoef A = a.adj[e];
-    if (!A.inverse) return;  // the replay kernel owns this tile
+    if (!a.adj[e].inverse) return;  // the replay kernel owns this tile
     const uint64_t i = E.offset + static_cast<uint64_t>(tile - E.tile_begin) * BLOCK + threadIdx.x;
     const bool act = i < E.offset + E.n;
     const uint64_t NT = a.NT;
     const uint32_t nseg = (a.n_steps + a.K - 1) / a.K;
-    const double dk = -static_cast<double>(A.dkap_dk), dcg = A.dc_dgamma, dsg = A.dsig_dgamma, dsT = A.dsig_dkT;
     double gk = 0.0, gg = 0.0, gT = 0.0;
-    if (act) {
-        double ex[3] = {0, 0, 0}, ev[3] = {0, 0, 0};  // adjoint at the current segment's end
-        for (uint32_t seg = nseg; seg-- > 0;) {
-            const float *rf = a.seg_f + static_cast<uint64_t>(seg) * kAdjSegF * NT + i;
+    if (act)
+        for (uint32_t seg = 0; seg < nseg; ++seg) {
             const double *rd = a.seg_d + static_cast<uint64_t>(seg) * kAdjSegD * NT + i;
             gk += rd[0];
             gg += rd[NT];
             gT += rd[2 * NT];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const double rx = rf[(6 + d) * NT] * ex[d] + rf[(9 + d) * NT] * ev[d];
-                const double rv = rf[(12 + d) * NT] * ex[d] + rf[(15 + d) * NT] * ev[d];
-                const double rg = rf[(18 + d) * NT] * ex[d] + rf[(21 + d) * NT] * ev[d];
-                gk += dk * rx;
-                gg += dcg * rv + dsg * rg;
-                gT += dsT * rg;
-                // every segment but the last is K steps long, and the last one's end adjoint is 0
-                const double nx = rf[d * NT] + A.phi[0] * ex[d] + A.phi[1] * ev[d];
-                const double nv = rf[(3 + d) * NT] + A.phi[2] * ex[d] + A.phi[3] * ev[d];
-                ex[d] = nx;
-                ev[d] = nv;
-            }
         }
-    }
     block_grad_partials<BLOCK>(act, gk, gg, gT, red, a.partials + static_cast<uint64_t>(tile) * kAdjPartW);
 }
 
@@ -437,7 +475,7 @@ hipError_t launch_ld_adjoint(int kind, const AdjArgs &a, bool any_replay, bool a
         ld_adjoint_seg_kernel<kAdjBlock><<<dim3(a.n_tiles, nseg), kAdjBlock, 0, st>>>(a);
         const hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
-        ld_adjoint_combine_kernel<kAdjBlock><<<a.n_tiles, kAdjBlock, 0, st>>>(a);
+        ld_adjoint_sum_kernel<kAdjBlock><<<a.n_tiles, kAdjBlock, 0, st>>>(a);
     }
     return hipGetLastError();
 }

@@ -168,14 +168,16 @@ def test_tuning_roundtrip_and_validation():
 
 def test_adjoint_sizing_and_validation():
     c = R.make_cfg("taus", n_streams=1000)
-    # 20 checkpoints plus the end state
-    assert R.ld_ckpt_bytes(c, 1000, 2000, 100) == 21 * 1000 * (6 + 4) * 4
-    assert R.ld_ckpt_bytes(c, 1000, 2001, 100) == 22 * 1000 * (6 + 4) * 4
+    # 20 checkpoints plus the end state: x, v, the 4 state rows and the 6 adjoint rows
+    assert R.ld_ckpt_bytes(c, 1000, 2000, 100) == 21 * 1000 * (6 + 4 + 6) * 4
+    assert R.ld_ckpt_bytes(c, 1000, 2001, 100) == 22 * 1000 * (6 + 4 + 6) * 4
+    # Ran2: x, v and the 35 state rows
+    assert R.ld_ckpt_bytes(R.make_cfg("ran2", n_streams=1000), 1000, 2000, 100) == 21 * 1000 * (6 + 35) * 4
     p = R.make_params()
     ens, n = R.make_ensembles([(0, 1000, p, 1)])
     loss = R.Loss(1001, 2000, 100, 0)
     scratch = 9 * 100 * 1000 * 4  # replay: 9 floats per oscillator-step of one segment
-    records = 20 * 1000 * (24 * 4 + 3 * 8)  # register-only: 120 bytes per (oscillator, segment)
+    records = 20 * 1000 * 3 * 8  # register-only: 24 bytes per (oscillator, segment)
     small = 64 * 1024  # ensemble tables and per-tile partials
     # weakly damped Hybrid Taus: register-only backward, segment records only
     ws = R.ld_adjoint_workspace_bytes(c, ens, n, 1000, 2000, loss)

@@ -200,11 +200,53 @@ def test_register_only_backward_equals_replay():
 def test_checkpoint_end_record_is_the_final_state():
     N, T, K = 777, 130, 50  # records at steps 0, 50, 100 and the end state (step 130)
     run, _, _ = _grads("taus", [(N, 1.0, 0.01, 9)], [(1.0, 1.0, 1.0)], T, 1, T, K)
-    rec = (6 + 4) * N * 4
+    rec = (6 + 4 + 6) * N * 4
     last = run.ckpt[3 * rec:4 * rec]
     assert torch.equal(last[:3 * N * 4].view(torch.float32), run.x)
     assert torch.equal(last[3 * N * 4:6 * N * 4].view(torch.float32), run.v)
-    assert torch.equal(last[6 * N * 4:], run.state[:4 * N * 4])
+    assert torch.equal(last[6 * N * 4:10 * N * 4], run.state[:4 * N * 4])
+    # no loss term follows the end state: its adjoint rows are zero
+    assert not last[10 * N * 4:].view(torch.float32).any()
+
+
+def test_checkpoint_adjoint_rows_are_the_window_gradient_of_the_recorded_state():
+    """The adjoint rows of a checkpoint record hold the gradient of the sum of x^2 over the loss
+    window's steps after the record with respect to the record's x and v.  Checked against central
+    differences of the FP64 oracle's loss, run from the record's own state (its generator rows are
+    bit-exact): for fixed noise the loss is quadratic in the starting state, so the difference is
+    exact up to rounding.  The window starts and ends inside segments, and the last one is short."""
+    N, T, tb, te, K = 300, 300, 101, 280, 64  # records at steps 0, 64, 128, 192, 256 and 300
+    pp = W.LDParams(k=1.2, gamma=0.8, kT=1.1, dt=0.01).as_f32()
+    pd = pp.asdict()
+    run = A.AdjointRun("taus", [(N, pp.m, pp.dt, 77)], T, tb, te, K)
+    A.LDAdjoint.apply(*(torch.tensor([a], dtype=torch.float64) for a in (pp.k, pp.gamma, pp.kT)), run)
+    torch.cuda.synchronize()
+    rows = 6 + 4 + 6
+    ck = run.ckpt.cpu()
+    worst = 0.0
+    for r in (0, 1, 2, 4):
+        step = r * K
+        rec = ck[r * rows * N * 4:(r + 1) * rows * N * 4]
+        f = rec.view(torch.float32).numpy().reshape(rows, N)
+        u = rec.view(torch.int32).numpy().view(np.uint32).reshape(rows, N)
+        tb_r, te_r = max(tb - step, 1), te - step
+        scale = 3.0 * (te_r - tb_r + 1)  # the oracle's loss is the mean over 3 coordinates and the window
+        for i in (0, 7, 255, 299):
+            x0 = f[0:3, i:i + 1].astype(np.float64)
+            v0 = f[3:6, i:i + 1].astype(np.float64)
+            st = np.ascontiguousarray(u[6:10, i][None, :])
+
+            def loss(which, d, delta):
+                xx, vv = x0.copy(), v0.copy()
+                (xx if which == 0 else vv)[d, 0] += delta
+                return orc.ld_loss("taus", st.copy(), 1, T - step, pd, tb_r, te_r, xx, vv)
+
+            fd = np.array([[(loss(w, d, 1e-2) - loss(w, d, -1e-2)) / 2e-2 * scale for d in range(3)] for w in (0, 1)])
+            got = f[10:16, i].reshape(2, 3).astype(np.float64)
+            err = np.max(np.abs(got - fd)) / np.max(np.abs(fd))
+            worst = max(worst, err)
+            assert err <= 1e-4, (r, i, got, fd)
+    _say("checkpoint adjoint rows vs oracle differences: worst relative error", worst)
 
 
 def test_mixed_paths_match_the_oracle():
