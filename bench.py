@@ -32,7 +32,7 @@ GENERATORS = ("taus", "ran2", "lf")
 # ld_run_kernel (underdamped scheme, gfx950) issues per oscillator-step, LDS accesses not counted,
 # as the build counts them in the assembly it compiles (kernel_isa.json, "step_loops").
 STEP_LOOP_KERNELS = {"taus": "ld_run_kernel<HybridTaus,256,1>", "ran2": "ld_run_kernel<Ran2,256,1>",
-                     "lcg": "ld_run_kernel<Lcg32,256,1>", "adjoint_forward": "ld_ckpt_kernel<HybridTaus,256>",
+                     "lcg": "ld_run_kernel<Lcg32,256,1>", "adjoint_forward": "ld_fwd_seg_kernel<256>",
                      "adjoint_backward": "ld_adjoint_seg_kernel<256>"}
 # Measured bound of those loops: each instruction class at the issue rate the VALU probe measured
 # for it (profiles/valu_issue_rates.md, lane-instructions per second over the chip), times added
@@ -137,9 +137,9 @@ def valu_per_osc_step(which):
 
 
 def adjoint_forward_valu(n_steps, t_begin, t_end):
-    """VALU lane-instructions per oscillator-step of the checkpointing forward run, averaged over
-    the run: its plain step loop (the smallest) outside the loss window, the loop that also
-    accumulates the loss and the adjoint terms (the largest) inside it."""
+    """VALU lane-instructions per oscillator-step of the segment-parallel checkpointing forward
+    run, averaged over the run: its plain step loop (the smallest) outside the loss window, the
+    loop that also accumulates the window sums (the largest) inside it."""
     loop = _kernel_isa().get("step_loops", {}).get(STEP_LOOP_KERNELS["adjoint_forward"])
     if loop is None:
         raise RuntimeError("kernel_isa.json has no step-loop count for the adjoint forward: rebuild the library")
@@ -619,7 +619,7 @@ def extra_config5(R, W, torch):
                "loss": L, "grad_k_gamma_kT": grad, "grad_standard_errors": run.grad_se[0].tolist(),
                "forward_ms": fwd_ms, "backward_ms": bwd_ms, "fwd_plus_bwd_over_fwd": (fwd_ms + bwd_ms) / fwd_ms,
                "forward_osc_steps_per_s": osc / (fwd_ms / 1e3),
-               "roofline_forward": valu_entry("ld_ckpt_kernel<HybridTaus>",
+               "roofline_forward": valu_entry("ld_fwd_seg_kernel (+ tables and join)",
                                               adjoint_forward_valu(T, c5["t_begin"], c5["t_end"]), osc, fwd_ms / 1e3)}
         if not replay:
             res["roofline_backward"] = valu_entry("ld_adjoint_seg_kernel + sum",

@@ -1170,9 +1170,42 @@ struct AdjLayout {
     std::vector<EnsDev> ens;
     std::vector<AdjCoef> adj;
     uint32_t n_tiles = 0;
-    bool any_replay = false, any_inverse = false;
-    size_t off_ens = 0, off_adj = 0, off_partials = 0, off_scratch = 0, off_seg_d = 0, bytes = 0;
+    bool any_replay = false, any_inverse = false, any_sp = false, any_seq = false;
+    size_t off_ens = 0, off_adj = 0, off_partials = 0, off_jump = 0, off_coef = 0, off_scratch = 0, off_seg_d = 0,
+           bytes = 0;
 };
+
+// The segment-parallel forward's per-ensemble constants, in FP64 from the FP32 coefficients:
+// F^K, F^len of the last segment, B^K, and the seven window sums of a whole segment (each term from
+// the FP32 values of a_j, b_j, alpha_j, beta_j, as the kernels' table holds them).
+void segment_constants(AdjCoef &A, uint32_t K, uint32_t len_last) {
+    const double h = A.f.h, c = A.f.c, kap = A.f.kap;
+    const double F[4] = {1.0 - h * kap, h * c, -kap, c};
+    const double B[4] = {1.0 - kap * h, -kap, c * h, c};
+    double pf[4] = {1, 0, 0, 1}, pb[4] = {1, 0, 0, 1};
+    for (int k = 0; k < 7; ++k) A.full[k] = 0.0;
+    auto mul = [](const double *p, const double *q, double *out) {
+        const double r0 = p[0] * q[0] + p[1] * q[2], r1 = p[0] * q[1] + p[1] * q[3];
+        const double r2 = p[2] * q[0] + p[3] * q[2], r3 = p[2] * q[1] + p[3] * q[3];
+        out[0] = r0, out[1] = r1, out[2] = r2, out[3] = r3;
+    };
+    for (uint32_t j = 1; j <= K; ++j) {
+        mul(pf, F, pf);
+        mul(pb, B, pb);
+        const double ca = static_cast<float>(pf[0]), cb = static_cast<float>(pf[1]);
+        const double cl = static_cast<float>(pb[0]), ce = static_cast<float>(pb[2]);
+        A.full[0] += ca * ca, A.full[1] += ca * cb, A.full[2] += cb * cb;
+        A.full[3] += cl * ca, A.full[4] += cl * cb, A.full[5] += ce * ca, A.full[6] += ce * cb;
+        if (j == len_last)
+            for (int k = 0; k < 4; ++k) A.flast[k] = pf[k];
+    }
+    for (int k = 0; k < 4; ++k) A.fk[k] = pf[k], A.bk[k] = pb[k];
+}
+
+// longest segment the segment-parallel forward takes (its coefficient table has K entries per
+// ensemble), and the fewest segments for which it pays
+constexpr uint32_t kSpMaxK = 1u << 16;
+constexpr uint64_t kSpMinSegments = 2;
 
 // B^K for the adjoint step matrix B = [[1 - kap h, -kap], [c h, c]] (row-major), the map that
 // carries the adjoint (lam_x, lam_v) at a K-step segment's end to its start with no loss terms;
@@ -1218,7 +1251,7 @@ constexpr double kAdjGrowthLimit = 8.0;
 constexpr uint32_t kAdjInverseMaxK = 1u << 22;
 
 int layout_adj(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total, uint32_t n_steps,
-               const ld_loss &loss, bool backward, AdjLayout *L) {
+               const ld_loss &loss, AdjLayout *L) {
     const uint32_t K = loss.K;
     L->ens.resize(n_ens);
     L->adj.resize(n_ens);
@@ -1247,10 +1280,14 @@ int layout_adj(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t 
         A.lam = g.kind == RNGLD_HYBRID_TAUS && K <= kAdjInverseMaxK && nseg < 65536 &&
                 reverse_growth(A.f, K, kAdjGrowthLimit) <= kAdjGrowthLimit;
         A.inverse = A.lam && !(loss.flags & RNGLD_ADJ_REPLAY);
+        A.sp = A.lam && K <= kSpMaxK && nseg >= kSpMinSegments;
         if (A.lam) adjoint_propagator(A.f, K, A.phi);
+        if (A.sp) segment_constants(A, K, static_cast<uint32_t>(n_steps - (nseg - 1) * K));
         if (E.n) {
             L->any_inverse |= A.inverse != 0;
             L->any_replay |= A.inverse == 0;
+            L->any_sp |= A.sp != 0;
+            L->any_seq |= A.sp == 0;
         }
     }
     if (acc >= (1ull << 31)) return fail(RNGLD_EINVAL, "too many tiles");
@@ -1258,13 +1295,17 @@ int layout_adj(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t 
     L->off_ens = 0;
     L->off_adj = align_up(sizeof(EnsDev) * n_ens);
     L->off_partials = align_up(L->off_adj + sizeof(AdjCoef) * n_ens);
-    L->off_scratch = align_up(L->off_partials + kAdjPartW * sizeof(double) * std::max<uint32_t>(L->n_tiles, 1));
-    L->bytes = L->off_scratch + (backward && L->any_replay ? align_up(9ull * K * n_total * sizeof(float)) : 0);
-    if (backward && L->any_inverse) {  // one record per (oscillator, segment)
-        const uint64_t nseg = (static_cast<uint64_t>(n_steps) + K - 1) / K;
-        L->off_seg_d = L->bytes;
-        L->bytes = align_up(L->off_seg_d + nseg * kAdjSegD * n_total * sizeof(double));
-    }
+    const uint64_t nseg = (static_cast<uint64_t>(n_steps) + K - 1) / K;
+    L->off_jump = align_up(L->off_partials + kAdjPartW * sizeof(double) * std::max<uint32_t>(L->n_tiles, 1));
+    L->off_coef = align_up(L->off_jump + (L->any_sp ? nseg * kJumpWords * sizeof(uint32_t) : 0));
+    L->off_scratch = align_up(L->off_coef + (L->any_sp ? static_cast<uint64_t>(n_ens) * K * sizeof(float4) : 0));
+    // the forward's segment records and the backward's scratch share the space after off_scratch;
+    // both calls take the larger size, so one workspace serves both
+    const size_t fwd = L->any_sp ? align_up(nseg * kFwdSegF * n_total * sizeof(float)) : 0;
+    size_t bwd = L->any_replay ? align_up(9ull * K * n_total * sizeof(float)) : 0;
+    L->off_seg_d = L->off_scratch + bwd;
+    if (L->any_inverse) bwd += align_up(nseg * kAdjSegD * n_total * sizeof(double));
+    L->bytes = L->off_scratch + std::max(fwd, bwd);
     return RNGLD_OK;
 }
 
@@ -1308,7 +1349,7 @@ extern "C" int ld_adjoint_workspace_bytes(const rngld_cfg *cfg, const ld_ensembl
     RNGLD_TRY(check_adj_common(cfg, &g, h_ens, n_ens, n_total, n_steps, loss));
     if (!bytes) return fail(RNGLD_EINVAL, "bytes is NULL");
     AdjLayout L;
-    RNGLD_TRY(layout_adj(g, h_ens, n_ens, n_total, n_steps, *loss, true, &L));
+    RNGLD_TRY(layout_adj(g, h_ens, n_ens, n_total, n_steps, *loss, &L));
     *bytes = L.bytes;
     return RNGLD_OK;
 }
@@ -1325,7 +1366,7 @@ extern "C" int ld_run_ckpt(const rngld_cfg *cfg, void *d_state, size_t state_byt
     RNGLD_TRY(ld_ckpt_bytes(cfg, n_total, n_steps, loss->K, &need_ck));
     if (ckpt_bytes < need_ck) return fail(RNGLD_ESIZE, "checkpoint buffer %zu < %zu bytes", ckpt_bytes, need_ck);
     AdjLayout L;
-    RNGLD_TRY(layout_adj(g, h_ens, n_ens, n_total, n_steps, *loss, false, &L));
+    RNGLD_TRY(layout_adj(g, h_ens, n_ens, n_total, n_steps, *loss, &L));
     if (ws_bytes < L.bytes) return fail(RNGLD_ESIZE, "workspace %zu bytes < %zu required", ws_bytes, L.bytes);
     if (!d_ws || !d_loss || (n_total && (!d_x || !d_v || !d_ckpt))) return fail(RNGLD_EINVAL, "NULL buffer");
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1349,7 +1390,10 @@ extern "C" int ld_run_ckpt(const rngld_cfg *cfg, void *d_state, size_t state_byt
     a.ckpt = static_cast<uint8_t *>(d_ckpt);
     a.rec_bytes = ckpt_record_bytes(g, n_total);
     a.partials = reinterpret_cast<double *>(ws + L.off_partials);
-    RNGLD_TRY_HIP(launch_ld_ckpt(g.kind, a, kAdjTile, st));
+    a.jump = reinterpret_cast<uint32_t *>(ws + L.off_jump);
+    a.coef = reinterpret_cast<float4 *>(ws + L.off_coef);
+    a.fwd_seg = reinterpret_cast<float *>(ws + L.off_scratch);
+    RNGLD_TRY_HIP(launch_ld_ckpt(g.kind, a, L.any_sp, L.any_seq, st));
     RNGLD_TRY_HIP(launch_adj_finalize(a.partials, L.n_tiles, 1, false, a.ens, n_ens,
                                       static_cast<double>(loss->t_end - loss->t_begin + 1), d_loss, st));
     return RNGLD_OK;
@@ -1364,7 +1408,7 @@ extern "C" int ld_run_backward(const rngld_cfg *cfg, const void *d_ckpt, size_t 
     RNGLD_TRY(ld_ckpt_bytes(cfg, n_total, n_steps, loss->K, &need_ck));
     if (ckpt_bytes < need_ck) return fail(RNGLD_ESIZE, "checkpoint buffer %zu < %zu bytes", ckpt_bytes, need_ck);
     AdjLayout L;
-    RNGLD_TRY(layout_adj(g, h_ens, n_ens, n_total, n_steps, *loss, true, &L));
+    RNGLD_TRY(layout_adj(g, h_ens, n_ens, n_total, n_steps, *loss, &L));
     if (ws_bytes < L.bytes) return fail(RNGLD_ESIZE, "workspace %zu bytes < %zu required", ws_bytes, L.bytes);
     if (!d_ws || !d_grad || (n_total && !d_ckpt)) return fail(RNGLD_EINVAL, "NULL buffer");
     hipStream_t st = static_cast<hipStream_t>(stream);

@@ -140,6 +140,16 @@ struct AdjCoef {
     // 1: the forward run writes the loss adjoint into each checkpoint record (the ensemble can take
     // the register-only backward; inverse is this without RNGLD_ADJ_REPLAY)
     uint32_t lam;
+    // 1: the forward run is segment-parallel (Hybrid Taus with lam): each K-step segment runs from
+    // a zero state with the generator jumped to its start, and a join pass adds the response to
+    // the true start state.  FP64, row-major, acting on (x, v) column vectors:
+    uint32_t sp;
+    double fk[4];     // F^K, F = [[1 - h kap, h c], [-kap, c]] the forward step matrix
+    double flast[4];  // F^len of the last segment
+    double bk[4];     // B^K, the adjoint step over a whole segment (phi in FP64)
+    // sums over j = 1..K of a^2, a b, b^2, alpha a, alpha b, beta a, beta b with (a_j, b_j) the
+    // first row of F^j and (alpha_j, beta_j) = B^j e1, each term formed from their FP32 values
+    double full[7];
 };
 
 // width of the per-tile FP64 partials of the adjoint kernels: three sums and their squares
@@ -150,6 +160,13 @@ constexpr uint32_t kAdjSegD = 3;
 // checkpoint rows of a Hybrid Taus record: x[3], v[3], the 4 generator rows, then the loss adjoint
 // lam_x[3], lam_v[3] of the record's state (written by the forward run for ensembles with lam)
 constexpr uint32_t kCkptLamRow = 10;
+// segment-parallel forward: per (oscillator, segment) FP32 rows of the zero-start run: x_end[3],
+// v_end[3], sum of x^2 over the window steps, and per component sum a_j x_j, sum b_j x_j,
+// sum alpha_j x_j, sum beta_j x_j over them
+constexpr uint32_t kFwdSegF = 19;
+// per segment: the columns of the three Tausworthe components' jump matrices (3 x 32 words), the
+// LCG's multiplier and increment, two words of padding
+constexpr uint32_t kJumpWords = 100;
 
 struct AdjArgs {
     void *state;  // forward: live state (stride S); unused by backward
@@ -165,11 +182,16 @@ struct AdjArgs {
     uint64_t rec_bytes;  // bytes per checkpoint record
     float *scratch;      // backward, replay path: [K][9][NT]
     double *seg_d;       // backward, register-only path: [nseg][kAdjSegD][NT]
+    uint32_t *jump;      // forward, segment-parallel: [nseg][kJumpWords]
+    float4 *coef;        //   [n_ens][K]: (a_j, b_j, alpha_j, beta_j), j = 1..K
+    float *fwd_seg;      //   [nseg][kFwdSegF][NT]
     double *partials;    // [n_tiles][kAdjPartW]: the loss (forward), or per-oscillator gradient
                          // sums and sums of squares (backward)
 };
 
-hipError_t launch_ld_ckpt(int kind, const AdjArgs &a, uint32_t block, hipStream_t st);
+// forward with checkpoints: the segment-parallel kernels for ensembles with sp (any_sp), the
+// sequential kernel for the others (any_seq)
+hipError_t launch_ld_ckpt(int kind, const AdjArgs &a, bool any_sp, bool any_seq, hipStream_t st);
 // backward: the replay kernel for ensembles with inverse == 0, the register-only kernel (Hybrid
 // Taus) for those with inverse == 1
 hipError_t launch_ld_adjoint(int kind, const AdjArgs &a, bool any_replay, bool any_inverse, hipStream_t st);

@@ -108,6 +108,42 @@ __device__ __forceinline__ void window_part(const AdjArgs &a, uint32_t s0, uint3
     hi = lo > w_hi ? lo : (w_hi < s1 ? w_hi : s1);
 }
 
+// The last pass of a forward run over oscillator i's checkpoint records, latest first: the end
+// state's adjoint is 0, and each segment's start adjoint is its own part (parked in the adjoint
+// rows of its start record by the forward run, for segments with window steps) plus bk = B^K times
+// its end adjoint (every segment but the last is K steps long, and the last one's end adjoint is 0).
+__device__ void adjoint_walk(const AdjArgs &a, uint64_t i, const double bk[4]) {
+    const uint64_t NT = a.NT;
+    const uint32_t nseg = (a.n_steps + a.K - 1) / a.K;
+    auto rec_f = [&](uint32_t r) { return reinterpret_cast<float *>(a.ckpt + static_cast<uint64_t>(r) * a.rec_bytes); };
+    double lx[3] = {0, 0, 0}, lv[3] = {0, 0, 0};
+    for (uint32_t seg = nseg; seg-- > 0;) {
+        float *r_end = rec_f(seg + 1), *r_start = rec_f(seg);
+        const uint32_t s0 = seg * a.K, s1 = (s0 + a.K < a.n_steps) ? s0 + a.K : a.n_steps;
+        uint32_t lo, hi;
+        window_part(a, s0, s1, lo, hi);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            r_end[(kCkptLamRow + d) * NT + i] = static_cast<float>(lx[d]);
+            r_end[(kCkptLamRow + 3 + d) * NT + i] = static_cast<float>(lv[d]);
+            double nx = bk[0] * lx[d] + bk[1] * lv[d];
+            double nv = bk[2] * lx[d] + bk[3] * lv[d];
+            if (hi > lo) {
+                nx += r_start[(kCkptLamRow + d) * NT + i];
+                nv += r_start[(kCkptLamRow + 3 + d) * NT + i];
+            }
+            lx[d] = nx;
+            lv[d] = nv;
+        }
+    }
+    float *r0 = rec_f(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        r0[(kCkptLamRow + d) * NT + i] = static_cast<float>(lx[d]);
+        r0[(kCkptLamRow + 3 + d) * NT + i] = static_cast<float>(lv[d]);
+    }
+}
+
 // forward run from the current state with checkpoints every K steps; loss partial = sum of x^2
 // over the loss window (scaled on finalisation).
 // For ensembles with lam each record also gets the loss adjoint of its state, the starting point
@@ -124,6 +160,7 @@ __global__ __launch_bounds__(BLOCK) void ld_ckpt_kernel(AdjArgs a) {
     const uint32_t e = find_ensemble(a.ens, a.n_ens, tile);
     const EnsDev &E = a.ens[e];
     const AdjCoef &A = a.adj[e];
+    if (A.sp) return;  // the segment-parallel kernels own this tile
     const LdCoef q = A.f;
     const bool lam = A.lam != 0;
     const uint64_t i = E.offset + static_cast<uint64_t>(tile - E.tile_begin) * BLOCK + threadIdx.x;
@@ -223,37 +260,256 @@ __global__ __launch_bounds__(BLOCK) void ld_ckpt_kernel(AdjArgs a) {
         store_state(g, rx + 6 * NT, NT, i);
     }
     if (lam && act) {
-        // latest record first: the end state's adjoint is 0; each segment's start adjoint is its
-        // own part plus B^K times its end adjoint (every segment but the last is K steps long, and
-        // the last one's end adjoint is 0)
-        double lx[3] = {0, 0, 0}, lv[3] = {0, 0, 0};
-        for (uint32_t seg = nseg; seg-- > 0;) {
-            float *r_end = rec_f(seg + 1), *r_start = rec_f(seg);
-            const uint32_t s0 = seg * a.K, s1 = (s0 + a.K < a.n_steps) ? s0 + a.K : a.n_steps;
-            uint32_t lo, hi;
-            window_part(a, s0, s1, lo, hi);
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                r_end[(kCkptLamRow + d) * NT + i] = static_cast<float>(lx[d]);
-                r_end[(kCkptLamRow + 3 + d) * NT + i] = static_cast<float>(lv[d]);
-                double nx = A.phi[0] * lx[d] + A.phi[1] * lv[d];
-                double nv = A.phi[2] * lx[d] + A.phi[3] * lv[d];
-                if (hi > lo) {
-                    nx += r_start[(kCkptLamRow + d) * NT + i];
-                    nv += r_start[(kCkptLamRow + 3 + d) * NT + i];
-                }
-                lx[d] = nx;
-                lv[d] = nv;
-            }
-        }
-        float *r0 = rec_f(0);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            r0[(kCkptLamRow + d) * NT + i] = static_cast<float>(lx[d]);
-            r0[(kCkptLamRow + 3 + d) * NT + i] = static_cast<float>(lv[d]);
-        }
+        const double bk[4] = {A.phi[0], A.phi[1], A.phi[2], A.phi[3]};
+        adjoint_walk(a, i, bk);
     }
     // the loss sum and its square (the per-oscillator spread of the loss)
+    const double qv[6] = {act ? lsum : 0.0, act ? lsum * lsum : 0.0, 0.0, 0.0, 0.0, 0.0};
+    block_sum6<BLOCK>(qv, red, a.partials + static_cast<uint64_t>(tile) * kAdjPartW);
+}
+
+// ---- segment-parallel forward (Hybrid Taus) ---------------------------------------------------------
+// Every Tausworthe step is linear over GF(2) on the 32-bit word (shifts, masks and xors), and the
+// LCG step is affine, so the generator's state after n draws is a fixed 32 x 32 bit matrix per
+// component applied to the state now, plus the LCG's n-step map.  The LD step is linear too:
+// (x, v) after j steps from (x0, v0) is the zero-start run plus F^j (x0, v0).  So each segment runs
+// from a zero state with its generator jumped to the segment's start, all segments at once, and a
+// join pass per oscillator walks the segments in order in FP64, adding F^len times the true start
+// state to each segment's end and the matching terms to its loss and adjoint sums.
+
+// z -> M z over GF(2), M given by its 32 columns
+__device__ __forceinline__ uint32_t gf2_apply(const uint32_t *col, uint32_t z) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int b = 0; b < 32; ++b) r ^= static_cast<uint32_t>(__builtin_amdgcn_sbfe(static_cast<int32_t>(z), b, 1)) & col[b];
+    return r;
+}
+
+// one draw's step of Tausworthe component c of Hybrid Taus
+__device__ __forceinline__ uint32_t taus_component_step(int c, uint32_t z) {
+    return c == 0 ? tausworthe<13, 12, 31>(z) : (c == 1 ? tausworthe<2, 4, 29>(z) : tausworthe<3, 17, 28>(z));
+}
+
+// 2 x 2 row-major products in FP64
+__device__ __forceinline__ void mat2_mul(const double *p, const double *q, double *out) {
+    const double r0 = p[0] * q[0] + p[1] * q[2], r1 = p[0] * q[1] + p[1] * q[3];
+    const double r2 = p[2] * q[0] + p[3] * q[2], r3 = p[2] * q[1] + p[3] * q[3];
+    out[0] = r0, out[1] = r1, out[2] = r2, out[3] = r3;
+}
+
+// Tables of the segment-parallel forward.  Blocks [0, nseg): the jump of segment seg, 4 seg K draws:
+// thread t < 96 follows column t % 32 of component t / 32 through binary powering, with the matrix
+// M^(2^k) squared in LDS each round; thread 96 the LCG's map.  Blocks [nseg, nseg + n_ens): the
+// ensemble's coefficients for j = 1..K, (a_j, b_j) the first row of F^j and (alpha_j, beta_j) =
+// B^j e1, each by binary powering in FP64 and rounded once.
+__global__ __launch_bounds__(128) void adj_prep_kernel(AdjArgs a, uint32_t nseg) {
+    __shared__ uint32_t P[3][32];
+    const uint32_t t = threadIdx.x;
+    if (blockIdx.x < nseg) {
+        const uint64_t n = 4ull * blockIdx.x * a.K;
+        const int c = static_cast<int>(t / 32), b = static_cast<int>(t % 32);
+        uint32_t v = t < 96 ? (1u << b) : 0u;
+        if (t < 96) P[c][b] = taus_component_step(c, 1u << b);
+        __syncthreads();
+        for (uint64_t m = n; m != 0; m >>= 1) {
+            if ((m & 1) && t < 96) v = gf2_apply(P[c], v);
+            const uint32_t sq = t < 96 ? gf2_apply(P[c], P[c][b]) : 0u;
+            __syncthreads();
+            if (t < 96) P[c][b] = sq;
+            __syncthreads();
+        }
+        uint32_t *J = a.jump + static_cast<uint64_t>(blockIdx.x) * kJumpWords;
+        if (t < 96) J[t] = v;
+        if (t == 96) {
+            const uint32_t add = lcg_skip(0u, n);
+            J[96] = lcg_skip(1u, n) - add;
+            J[97] = add;
+            J[98] = J[99] = 0u;
+        }
+        return;
+    }
+    const uint32_t e = blockIdx.x - nseg;
+    const AdjCoef &A = a.adj[e];
+    if (!A.sp) return;
+    const LdCoef q = A.f;
+    const double h = q.h, c = q.c, kap = q.kap;
+    const double F[4] = {1.0 - h * kap, h * c, -kap, c};
+    const double B[4] = {1.0 - kap * h, -kap, c * h, c};
+    for (uint32_t j = 1 + t; j <= a.K; j += 128) {
+        double pf[4] = {1, 0, 0, 1}, pb[4] = {1, 0, 0, 1}, sf[4], sb[4];
+        for (int k = 0; k < 4; ++k) sf[k] = F[k], sb[k] = B[k];
+        for (uint32_t m = j; m != 0; m >>= 1) {
+            if (m & 1) {
+                mat2_mul(pf, sf, pf);
+                mat2_mul(pb, sb, pb);
+            }
+            mat2_mul(sf, sf, sf);
+            mat2_mul(sb, sb, sb);
+        }
+        a.coef[static_cast<uint64_t>(e) * a.K + j - 1] =
+            make_float4(static_cast<float>(pf[0]), static_cast<float>(pf[1]), static_cast<float>(pb[0]),
+                        static_cast<float>(pb[2]));
+    }
+}
+
+// Zero-start run of one segment, one thread per (oscillator, segment), blockIdx.y the segment: the
+// generator jumped to the segment's start (also written to the segment's start record; the last
+// segment writes its end state to the end record), the window sums of the join in kFwdSegF rows.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void ld_fwd_seg_kernel(AdjArgs a) {
+    const uint32_t tile = blockIdx.x, seg = blockIdx.y;
+    const uint32_t e = find_ensemble(a.ens, a.n_ens, tile);
+    const EnsDev &E = a.ens[e];
+    const AdjCoef &A = a.adj[e];
+    if (!A.sp) return;
+    const LdCoef q = A.f;
+    const uint64_t i = E.offset + static_cast<uint64_t>(tile - E.tile_begin) * BLOCK + threadIdx.x;
+    const bool act = i < E.offset + E.n;
+    const uint64_t col = act ? i : E.offset;  // inactive lanes follow a valid column, store nothing
+    const uint64_t NT = a.NT;
+    const uint32_t nseg = gridDim.y;
+    const uint32_t s0 = seg * a.K, s1 = (s0 + a.K < a.n_steps) ? s0 + a.K : a.n_steps;
+    HybridTaus g;
+    g.load(static_cast<const uint32_t *>(a.state), a.S, col);
+    const uint32_t *J = a.jump + static_cast<uint64_t>(seg) * kJumpWords;
+    g.t1 = gf2_apply(J, g.t1);
+    g.t2 = gf2_apply(J + 32, g.t2);
+    g.t3 = gf2_apply(J + 64, g.t3);
+    g.lcg = J[96] * g.lcg + J[97];
+    auto rec_f = [&](uint32_t r) { return reinterpret_cast<float *>(a.ckpt + static_cast<uint64_t>(r) * a.rec_bytes); };
+    if (act) g.store(reinterpret_cast<uint32_t *>(rec_f(seg) + 6 * NT), NT, i);
+    float x[3] = {0, 0, 0}, v[3] = {0, 0, 0};
+    float sxx = 0.0f, sa[3] = {0, 0, 0}, sb[3] = {0, 0, 0}, sal[3] = {0, 0, 0}, sbe[3] = {0, 0, 0};
+    const float4 *cf = a.coef + static_cast<uint64_t>(e) * a.K;
+    auto steps = [&](auto win_tag, uint32_t s, uint32_t end) {
+        constexpr bool WIN = decltype(win_tag)::value;
+        for (; s < end; ++s) {
+            const uint32_t w0 = g.next_top24(), w1 = g.next_top24(), w2 = g.next_top24(), w3 = g.next_top24();
+            float gf[3];
+            gaussian_forces_top24(w0, w1, w2, w3, gf[0], gf[1], gf[2]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) ld_update_s<0>(q, x[d], v[d], gf[d]);
+            if constexpr (WIN) {
+                const float4 k = cf[s - s0];  // j = s - s0 + 1
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    sxx += x[d] * x[d];
+                    sa[d] += k.x * x[d];
+                    sb[d] += k.y * x[d];
+                    sal[d] += k.z * x[d];
+                    sbe[d] += k.w * x[d];
+                }
+            }
+        }
+    };
+    uint32_t lo, hi;
+    window_part(a, s0, s1, lo, hi);
+    steps(std::false_type{}, s0, lo);
+    steps(std::true_type{}, lo, hi);
+    steps(std::false_type{}, hi, s1);
+    if (!act) return;
+    float *fr = a.fwd_seg + static_cast<uint64_t>(seg) * kFwdSegF * NT + i;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        fr[d * NT] = x[d];
+        fr[(3 + d) * NT] = v[d];
+        fr[(7 + d) * NT] = sa[d];
+        fr[(10 + d) * NT] = sb[d];
+        fr[(13 + d) * NT] = sal[d];
+        fr[(16 + d) * NT] = sbe[d];
+    }
+    fr[6 * NT] = sxx;
+    if (seg + 1 == nseg) g.store(reinterpret_cast<uint32_t *>(rec_f(nseg) + 6 * NT), NT, i);
+}
+
+// Join of the segment-parallel forward, one thread per oscillator, FP64: walks the segments in
+// order from the live x, v; writes each record's x, v, the segment's loss and own adjoint (the
+// zero-start sums plus their response to the start state), the end state to the end record and the
+// live buffers, the end record's generator rows to the live state; then the adjoint walk.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void ld_fwd_join_kernel(AdjArgs a) {
+    __shared__ double red[BLOCK / 64][6];
+    const uint32_t tile = blockIdx.x;
+    const uint32_t e = find_ensemble(a.ens, a.n_ens, tile);
+    const EnsDev &E = a.ens[e];
+    const AdjCoef &A = a.adj[e];
+    if (!A.sp) return;
+    const uint64_t i = E.offset + static_cast<uint64_t>(tile - E.tile_begin) * BLOCK + threadIdx.x;
+    const bool act = i < E.offset + E.n;
+    const uint64_t NT = a.NT;
+    const uint32_t nseg = (a.n_steps + a.K - 1) / a.K;
+    auto rec_f = [&](uint32_t r) { return reinterpret_cast<float *>(a.ckpt + static_cast<uint64_t>(r) * a.rec_bytes); };
+    double lsum = 0.0;
+    if (act) {
+        const float4 *cf = a.coef + static_cast<uint64_t>(e) * a.K;
+        double x[3], v[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            x[d] = a.x[d * NT + i];
+            v[d] = a.v[d * NT + i];
+        }
+        for (uint32_t seg = 0; seg < nseg; ++seg) {
+            const uint32_t s0 = seg * a.K, s1 = (s0 + a.K < a.n_steps) ? s0 + a.K : a.n_steps;
+            float *rx = rec_f(seg);
+            const float *fr = a.fwd_seg + static_cast<uint64_t>(seg) * kFwdSegF * NT + i;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                rx[d * NT + i] = static_cast<float>(x[d]);
+                rx[(3 + d) * NT + i] = static_cast<float>(v[d]);
+            }
+            uint32_t lo, hi;
+            window_part(a, s0, s1, lo, hi);
+            if (hi > lo) {
+                // the seven sums over the window steps j = lo - s0 + 1 .. hi - s0
+                double P[7];
+                if (lo == s0 && hi - s0 == a.K) {
+                    for (int k = 0; k < 7; ++k) P[k] = A.full[k];
+                } else {
+                    for (int k = 0; k < 7; ++k) P[k] = 0.0;
+                    for (uint32_t s = lo; s < hi; ++s) {
+                        const float4 k4 = cf[s - s0];
+                        const double ca = k4.x, cb = k4.y, cl = k4.z, ce = k4.w;
+                        P[0] += ca * ca, P[1] += ca * cb, P[2] += cb * cb;
+                        P[3] += cl * ca, P[4] += cl * cb, P[5] += ce * ca, P[6] += ce * cb;
+                    }
+                }
+                double l = fr[6 * NT];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const double x0 = x[d], v0 = v[d];
+                    l += 2.0 * (x0 * fr[(7 + d) * NT] + v0 * fr[(10 + d) * NT]) + x0 * x0 * P[0] +
+                         2.0 * x0 * v0 * P[1] + v0 * v0 * P[2];
+                    rx[(kCkptLamRow + d) * NT + i] =
+                        static_cast<float>(2.0 * (fr[(13 + d) * NT] + P[3] * x0 + P[4] * v0));
+                    rx[(kCkptLamRow + 3 + d) * NT + i] =
+                        static_cast<float>(2.0 * (fr[(16 + d) * NT] + P[5] * x0 + P[6] * v0));
+                }
+                lsum += l;
+            }
+            const double *M = (s1 - s0 == a.K) ? A.fk : A.flast;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double nx = fr[d * NT] + M[0] * x[d] + M[1] * v[d];
+                const double nv = fr[(3 + d) * NT] + M[2] * x[d] + M[3] * v[d];
+                x[d] = nx;
+                v[d] = nv;
+            }
+        }
+        float *rx = rec_f(nseg);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const float xf = static_cast<float>(x[d]), vf = static_cast<float>(v[d]);
+            rx[d * NT + i] = xf;
+            rx[(3 + d) * NT + i] = vf;
+            a.x[d * NT + i] = xf;
+            a.v[d * NT + i] = vf;
+        }
+        const uint32_t *rs = reinterpret_cast<const uint32_t *>(rx + 6 * NT);
+        uint32_t *live = static_cast<uint32_t *>(a.state);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) live[r * a.S + i] = rs[r * NT + i];
+        adjoint_walk(a, i, A.bk);
+    }
     const double qv[6] = {act ? lsum : 0.0, act ? lsum * lsum : 0.0, 0.0, 0.0, 0.0, 0.0};
     block_sum6<BLOCK>(qv, red, a.partials + static_cast<uint64_t>(tile) * kAdjPartW);
 }
@@ -450,13 +706,22 @@ constexpr int kAdjBlock = 256;
 
 }  // namespace
 
-hipError_t launch_ld_ckpt(int kind, const AdjArgs &a, uint32_t block, hipStream_t st) {
-    (void)block;
+hipError_t launch_ld_ckpt(int kind, const AdjArgs &a, bool any_sp, bool any_seq, hipStream_t st) {
     if (a.n_tiles == 0) return hipSuccess;
-    if (kind == RNGLD_RAN2)
-        ld_ckpt_kernel<Ran2, kAdjBlock><<<a.n_tiles, kAdjBlock, kR2Tab * kAdjBlock * 4, st>>>(a);
-    else
-        ld_ckpt_kernel<HybridTaus, kAdjBlock><<<a.n_tiles, kAdjBlock, 0, st>>>(a);
+    if (any_sp && kind == RNGLD_HYBRID_TAUS) {
+        const uint32_t nseg = (a.n_steps + a.K - 1) / a.K;
+        adj_prep_kernel<<<nseg + a.n_ens, 128, 0, st>>>(a, nseg);
+        ld_fwd_seg_kernel<kAdjBlock><<<dim3(a.n_tiles, nseg), kAdjBlock, 0, st>>>(a);
+        ld_fwd_join_kernel<kAdjBlock><<<a.n_tiles, kAdjBlock, 0, st>>>(a);
+        const hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    if (any_seq) {
+        if (kind == RNGLD_RAN2)
+            ld_ckpt_kernel<Ran2, kAdjBlock><<<a.n_tiles, kAdjBlock, kR2Tab * kAdjBlock * 4, st>>>(a);
+        else
+            ld_ckpt_kernel<HybridTaus, kAdjBlock><<<a.n_tiles, kAdjBlock, 0, st>>>(a);
+    }
     return hipGetLastError();
 }
 

@@ -231,6 +231,14 @@ def test_checkpoint_adjoint_rows_are_the_window_gradient_of_the_recorded_state()
         u = rec.view(torch.int32).numpy().view(np.uint32).reshape(rows, N)
         tb_r, te_r = max(tb - step, 1), te - step
         scale = 3.0 * (te_r - tb_r + 1)  # the oracle's loss is the mean over 3 coordinates and the window
+        # the record's generator rows: the seeded streams after 4 draws per step, bit for bit; its
+        # x and v: the oracle's run from rest over the same steps
+        ids = np.arange(N)
+        st_o = orc.seed_states("taus", 77, ids)
+        xo, vo, _ = orc.ld_run("taus", st_o, N, step, pd)
+        assert np.array_equal(u[6:10].T, st_o), r
+        assert np.max(np.abs(f[0:3] - xo)) <= 1e-4 * max(1.0, np.max(np.abs(xo))), r
+        assert np.max(np.abs(f[3:6] - vo)) <= 1e-4 * max(1.0, np.max(np.abs(vo))), r
         for i in (0, 7, 255, 299):
             x0 = f[0:3, i:i + 1].astype(np.float64)
             v0 = f[3:6, i:i + 1].astype(np.float64)
