@@ -136,13 +136,13 @@ def valu_per_osc_step(which):
     return loops[name]["valu_per_iteration"]
 
 
-def adjoint_forward_valu(n_steps, t_begin, t_end):
-    """VALU lane-instructions per oscillator-step of the segment-parallel checkpointing forward
-    run, averaged over the run: its plain step loop (the smallest) outside the loss window, the
-    loop that also accumulates the window sums (the largest) inside it."""
-    loop = _kernel_isa().get("step_loops", {}).get(STEP_LOOP_KERNELS["adjoint_forward"])
+def windowed_valu(which, n_steps, t_begin, t_end):
+    """VALU lane-instructions per oscillator-step of an adjoint kernel (forward or backward),
+    averaged over the run: its plain step loop (the smallest) outside the loss window, the loop
+    that also handles the window's terms (the largest) inside it."""
+    loop = _kernel_isa().get("step_loops", {}).get(STEP_LOOP_KERNELS[which])
     if loop is None:
-        raise RuntimeError("kernel_isa.json has no step-loop count for the adjoint forward: rebuild the library")
+        raise RuntimeError("kernel_isa.json has no step-loop count for %s: rebuild the library" % which)
     inside = t_end - t_begin + 1
     return ((n_steps - inside) * min(loop["all_loops"]) + inside * loop["valu_per_iteration"]) / n_steps
 
@@ -584,9 +584,10 @@ def extra_config4(R, W, torch):
 
 def extra_config5(R, W, torch):
     """Adjoint at config 5 (N = 1e5, 2000 steps from rest, loss over steps 1001-2000, K = 100):
-    forward with checkpoints and backward, each timed with events on the stream they run on, for
-    the register-only (segment-parallel) backward and the replay backward; every pass starts a fresh
-    run from rest (one untimed pass first loads the kernels).  Also the 6 forward runs of
+    forward with checkpoints (segment-parallel) and backward, for the register-only
+    (segment-parallel) backward and the replay backward, each timed with events on the stream
+    around the library call, and end to end through torch's autograd; every pass starts a fresh run
+    from rest (one untimed pass first loads the kernels).  Also the 6 forward runs of
     common-random-number central differences that the gradient replaces."""
     from paper_1003_1123_amd import autograd as A
     c5 = W.C5
@@ -598,6 +599,7 @@ def extra_config5(R, W, torch):
     def one(replay):
         run = A.AdjointRun("taus", [(N, p5.m, p5.dt, c5["seed"])], T, c5["t_begin"], c5["t_end"], c5["K"],
                            replay=replay, spread=True)
+        run.timed = True
         k = torch.tensor([p5.k], dtype=torch.float64, requires_grad=True)
         g = torch.tensor([p5.gamma], dtype=torch.float64, requires_grad=True)
         kT = torch.tensor([p5.kT], dtype=torch.float64, requires_grad=True)
@@ -610,20 +612,26 @@ def extra_config5(R, W, torch):
         L.sum().backward()
         e2.record()
         torch.cuda.synchronize()
-        return run, L.item(), [k.grad.item(), g.grad.item(), kT.grad.item()], e0.elapsed_time(e1), e1.elapsed_time(e2)
+        lib = [p[0].elapsed_time(p[1]) for p in (run.fwd_events, run.bwd_events)]
+        return run, L.item(), [k.grad.item(), g.grad.item(), kT.grad.item()], lib, [e0.elapsed_time(e1),
+                                                                                    e1.elapsed_time(e2)]
 
     for replay in (False, True):
         one(replay)  # loads the kernels
-        run, L, grad, fwd_ms, bwd_ms = one(replay)
+        run, L, grad, (fwd_ms, bwd_ms), (fwd_ag, bwd_ag) = one(replay)
         res = {"backward_path": "replay" if replay else "register-only, segment-parallel",
                "loss": L, "grad_k_gamma_kT": grad, "grad_standard_errors": run.grad_se[0].tolist(),
                "forward_ms": fwd_ms, "backward_ms": bwd_ms, "fwd_plus_bwd_over_fwd": (fwd_ms + bwd_ms) / fwd_ms,
+               "timed": "forward_ms and backward_ms: events on the stream around ld_run_ckpt and ld_run_backward; "
+                        "the *_autograd_ms include torch's autograd engine (LDAdjoint.apply, L.sum().backward())",
+               "forward_autograd_ms": fwd_ag, "backward_autograd_ms": bwd_ag,
                "forward_osc_steps_per_s": osc / (fwd_ms / 1e3),
                "roofline_forward": valu_entry("ld_fwd_seg_kernel (+ tables and join)",
-                                              adjoint_forward_valu(T, c5["t_begin"], c5["t_end"]), osc, fwd_ms / 1e3)}
+                                              windowed_valu("adjoint_forward", T, c5["t_begin"], c5["t_end"]), osc, fwd_ms / 1e3)}
         if not replay:
             res["roofline_backward"] = valu_entry("ld_adjoint_seg_kernel + sum",
-                                                  valu_per_osc_step("adjoint_backward"), osc, bwd_ms / 1e3)
+                                                  windowed_valu("adjoint_backward", T, c5["t_begin"], c5["t_end"]),
+                                                  osc, bwd_ms / 1e3)
             # the common-random-number central differences the gradient replaces: 6 forward runs
             e0, e1 = _ev(torch)
             runs = []

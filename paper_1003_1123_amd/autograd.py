@@ -31,6 +31,10 @@ class AdjointRun:
         # with spread: after backward, grad_se[e] = standard errors of (dL/dk, dL/dgamma, dL/dkT)
         # as estimates of d E[L] / d theta (per-oscillator spread / sqrt(n))
         self.grad_se = None
+        # with timed = True, the forward and backward record a pair of events on the current stream
+        # around the library call itself (fwd_events, bwd_events), leaving out the autograd engine
+        self.timed = False
+        self.fwd_events = self.bwd_events = None
         self.cfg = R.make_cfg(kind, n_streams=self.n_total)
         self.state = R.new_state(self.cfg, device)
         self.x = torch.zeros(3 * self.n_total, dtype=torch.float32, device=device)
@@ -57,6 +61,22 @@ class AdjointRun:
         return R.make_ensembles(specs)
 
 
+def _events(run):
+    if not run.timed:
+        return None
+    e = torch.cuda.Event(enable_timing=True)
+    e.record()
+    return e
+
+
+def _events_end(e0):
+    if e0 is None:
+        return None
+    e1 = torch.cuda.Event(enable_timing=True)
+    e1.record()
+    return e0, e1
+
+
 class LDAdjoint(torch.autograd.Function):
     """loss[n_ens] = LDAdjoint.apply(k[n_ens], gamma[n_ens], kT[n_ens], run)."""
 
@@ -65,8 +85,11 @@ class LDAdjoint(torch.autograd.Function):
         kh, gh, th = (t.detach().to("cpu", torch.float32).tolist() for t in (k, gamma, kT))
         ens, n_ens = run._ensembles(kh, gh, th)
         out = torch.empty(n_ens, dtype=torch.float64, device=run.device)
+        ws = run.workspace(ens, n_ens)
+        ev = _events(run)
         R.ld_run_ckpt(run.cfg, run.state, ens, n_ens, run.n_total, run.n_steps, run.x, run.v, run.loss, run.ckpt,
-                      out, run.workspace(ens, n_ens))
+                      out, ws)
+        run.fwd_events = _events_end(ev)
         ctx.run, ctx.ens, ctx.n_ens = run, ens, n_ens
         ctx.meta = tuple((t.dtype, t.device) for t in (k, gamma, kT))
         return out
@@ -76,8 +99,10 @@ class LDAdjoint(torch.autograd.Function):
         run = ctx.run
         spread = bool(run.loss.flags & R.ADJ_SPREAD)
         g = torch.empty((ctx.n_ens, 6 if spread else 3), dtype=torch.float64, device=run.device)
-        R.ld_run_backward(run.cfg, run.ckpt, ctx.ens, ctx.n_ens, run.n_total, run.n_steps, run.loss, g,
-                          run.workspace(ctx.ens, ctx.n_ens))
+        ws = run.workspace(ctx.ens, ctx.n_ens)
+        ev = _events(run)
+        R.ld_run_backward(run.cfg, run.ckpt, ctx.ens, ctx.n_ens, run.n_total, run.n_steps, run.loss, g, ws)
+        run.bwd_events = _events_end(ev)
         if spread:
             run.grad_se = g[:, 3:6].clone()
         go = grad_out.to(device=run.device, dtype=torch.float64)

@@ -60,6 +60,15 @@ RNGLD_HDI uint32_t funnel_shift_right(uint32_t hi, uint32_t lo, uint32_t s) {
 #endif
 }
 
+// a xor b xor c (one three-input bit operation on gfx950)
+RNGLD_HDI uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+#else
+    return a ^ b ^ c;
+#endif
+}
+
 // ---- Tausworthe component for the trinomial x^K + x^Q + 1 with step S (Eq. 2) ---------------------
 // The state occupies the top K bits; the low 32-K bits are dropped before the left shift.
 //
@@ -99,7 +108,7 @@ RNGLD_HDI uint32_t tausworthe_inv_terms(uint32_t t) {
     else if constexpr (2 * HAVE >= kTerms || 2 * kShift >= 32)
         return tausworthe_inv_terms<Q, S, 2 * HAVE>(t ^ (t << kShift));
     else
-        return tausworthe_inv_terms<Q, S, 3 * HAVE>(t ^ (t << kShift) ^ (t << (2 * kShift)));
+        return tausworthe_inv_terms<Q, S, 3 * HAVE>(xor3(t, t << kShift, t << (2 * kShift)));
 }
 
 template <int Q, int S, int K>

@@ -108,40 +108,48 @@ __device__ __forceinline__ void window_part(const AdjArgs &a, uint32_t s0, uint3
     hi = lo > w_hi ? lo : (w_hi < s1 ? w_hi : s1);
 }
 
-// The last pass of a forward run over oscillator i's checkpoint records, latest first: the end
-// state's adjoint is 0, and each segment's start adjoint is its own part (parked in the adjoint
-// rows of its start record by the forward run, for segments with window steps) plus bk = B^K times
-// its end adjoint (every segment but the last is K steps long, and the last one's end adjoint is 0).
-__device__ void adjoint_walk(const AdjArgs &a, uint64_t i, const double bk[4]) {
+// The last pass of a forward run over component d of oscillator i's checkpoint records, latest
+// first: the end state's adjoint is 0, and each segment's start adjoint is its own part (parked in
+// the adjoint rows of its start record by the forward run, for segments with window steps) plus
+// bk = B^K times its end adjoint (every segment but the last is K steps long, and the last one's
+// end adjoint is 0).  The parked values of the next segment down are loaded one iteration ahead.
+__device__ void adjoint_walk(const AdjArgs &a, uint64_t i, int d, const double bk[4]) {
     const uint64_t NT = a.NT;
     const uint32_t nseg = (a.n_steps + a.K - 1) / a.K;
     auto rec_f = [&](uint32_t r) { return reinterpret_cast<float *>(a.ckpt + static_cast<uint64_t>(r) * a.rec_bytes); };
-    double lx[3] = {0, 0, 0}, lv[3] = {0, 0, 0};
-    for (uint32_t seg = nseg; seg-- > 0;) {
-        float *r_end = rec_f(seg + 1), *r_start = rec_f(seg);
+    auto has_window = [&](uint32_t seg) {
         const uint32_t s0 = seg * a.K, s1 = (s0 + a.K < a.n_steps) ? s0 + a.K : a.n_steps;
         uint32_t lo, hi;
         window_part(a, s0, s1, lo, hi);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            r_end[(kCkptLamRow + d) * NT + i] = static_cast<float>(lx[d]);
-            r_end[(kCkptLamRow + 3 + d) * NT + i] = static_cast<float>(lv[d]);
-            double nx = bk[0] * lx[d] + bk[1] * lv[d];
-            double nv = bk[2] * lx[d] + bk[3] * lv[d];
-            if (hi > lo) {
-                nx += r_start[(kCkptLamRow + d) * NT + i];
-                nv += r_start[(kCkptLamRow + 3 + d) * NT + i];
-            }
-            lx[d] = nx;
-            lv[d] = nv;
+        return hi > lo;
+    };
+    auto own = [&](uint32_t seg, float &ox, float &ov) {
+        ox = ov = 0.0f;
+        if (has_window(seg)) {
+            const float *r = rec_f(seg);
+            ox = r[(kCkptLamRow + d) * NT + i];
+            ov = r[(kCkptLamRow + 3 + d) * NT + i];
         }
+    };
+    double lx = 0.0, lv = 0.0;
+    float ox, ov;
+    own(nseg - 1, ox, ov);
+    for (uint32_t seg = nseg; seg-- > 0;) {
+        float px = 0.0f, pv = 0.0f;
+        if (seg > 0) own(seg - 1, px, pv);
+        float *r_end = rec_f(seg + 1);
+        r_end[(kCkptLamRow + d) * NT + i] = static_cast<float>(lx);
+        r_end[(kCkptLamRow + 3 + d) * NT + i] = static_cast<float>(lv);
+        const double nx = bk[0] * lx + bk[1] * lv + ox;
+        const double nv = bk[2] * lx + bk[3] * lv + ov;
+        lx = nx;
+        lv = nv;
+        ox = px;
+        ov = pv;
     }
     float *r0 = rec_f(0);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        r0[(kCkptLamRow + d) * NT + i] = static_cast<float>(lx[d]);
-        r0[(kCkptLamRow + 3 + d) * NT + i] = static_cast<float>(lv[d]);
-    }
+    r0[(kCkptLamRow + d) * NT + i] = static_cast<float>(lx);
+    r0[(kCkptLamRow + 3 + d) * NT + i] = static_cast<float>(lv);
 }
 
 // forward run from the current state with checkpoints every K steps; loss partial = sum of x^2
@@ -261,7 +269,7 @@ __global__ __launch_bounds__(BLOCK) void ld_ckpt_kernel(AdjArgs a) {
     }
     if (lam && act) {
         const double bk[4] = {A.phi[0], A.phi[1], A.phi[2], A.phi[3]};
-        adjoint_walk(a, i, bk);
+        for (int d = 0; d < 3; ++d) adjoint_walk(a, i, d, bk);
     }
     // the loss sum and its square (the per-oscillator spread of the loss)
     const double qv[6] = {act ? lsum : 0.0, act ? lsum * lsum : 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -422,41 +430,46 @@ __global__ __launch_bounds__(BLOCK) void ld_fwd_seg_kernel(AdjArgs a) {
     if (seg + 1 == nseg) g.store(reinterpret_cast<uint32_t *>(rec_f(nseg) + 6 * NT), NT, i);
 }
 
-// Join of the segment-parallel forward, one thread per oscillator, FP64: walks the segments in
-// order from the live x, v; writes each record's x, v, the segment's loss and own adjoint (the
-// zero-start sums plus their response to the start state), the end state to the end record and the
-// live buffers, the end record's generator rows to the live state; then the adjoint walk.
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void ld_fwd_join_kernel(AdjArgs a) {
-    __shared__ double red[BLOCK / 64][6];
+// Join of the segment-parallel forward, FP64, one thread per (oscillator, component): a block of
+// 3 x TILE threads covers one tile, thread t taking component t / TILE of oscillator t % TILE.  It
+// walks the segments in order from the live x, v, writing each record's x, v, the segment's loss
+// and own adjoint (the zero-start sums plus their response to the start state), the end state to
+// the end record and the live buffers, the end record's generator rows to the live state; then the
+// adjoint walk.  The next segment's sums are loaded one iteration ahead.
+template <int TILE>
+__global__ __launch_bounds__(3 * TILE) void ld_fwd_join_kernel(AdjArgs a) {
+    __shared__ double red[3 * TILE / 64][6];
     const uint32_t tile = blockIdx.x;
     const uint32_t e = find_ensemble(a.ens, a.n_ens, tile);
     const EnsDev &E = a.ens[e];
     const AdjCoef &A = a.adj[e];
     if (!A.sp) return;
-    const uint64_t i = E.offset + static_cast<uint64_t>(tile - E.tile_begin) * BLOCK + threadIdx.x;
+    const int d = static_cast<int>(threadIdx.x / TILE);
+    const uint64_t i = E.offset + static_cast<uint64_t>(tile - E.tile_begin) * TILE + threadIdx.x % TILE;
     const bool act = i < E.offset + E.n;
     const uint64_t NT = a.NT;
     const uint32_t nseg = (a.n_steps + a.K - 1) / a.K;
     auto rec_f = [&](uint32_t r) { return reinterpret_cast<float *>(a.ckpt + static_cast<uint64_t>(r) * a.rec_bytes); };
+    // the zero-start run's rows of one segment for this component (and the x^2 sum for d = 0)
+    struct Rows {
+        float xp, vp, sa, sb, sal, sbe, sxx;
+    };
+    auto load = [&](uint32_t seg) {
+        const float *fr = a.fwd_seg + static_cast<uint64_t>(seg) * kFwdSegF * NT + i;
+        return Rows{fr[d * NT], fr[(3 + d) * NT], fr[(7 + d) * NT], fr[(10 + d) * NT], fr[(13 + d) * NT],
+                    fr[(16 + d) * NT], d == 0 ? fr[6 * NT] : 0.0f};
+    };
     double lsum = 0.0;
     if (act) {
         const float4 *cf = a.coef + static_cast<uint64_t>(e) * a.K;
-        double x[3], v[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            x[d] = a.x[d * NT + i];
-            v[d] = a.v[d * NT + i];
-        }
+        double x = a.x[d * NT + i], v = a.v[d * NT + i];
+        Rows cur = load(0);
         for (uint32_t seg = 0; seg < nseg; ++seg) {
+            const Rows nxt = seg + 1 < nseg ? load(seg + 1) : cur;
             const uint32_t s0 = seg * a.K, s1 = (s0 + a.K < a.n_steps) ? s0 + a.K : a.n_steps;
             float *rx = rec_f(seg);
-            const float *fr = a.fwd_seg + static_cast<uint64_t>(seg) * kFwdSegF * NT + i;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                rx[d * NT + i] = static_cast<float>(x[d]);
-                rx[(3 + d) * NT + i] = static_cast<float>(v[d]);
-            }
+            rx[d * NT + i] = static_cast<float>(x);
+            rx[(3 + d) * NT + i] = static_cast<float>(v);
             uint32_t lo, hi;
             window_part(a, s0, s1, lo, hi);
             if (hi > lo) {
@@ -473,45 +486,32 @@ __global__ __launch_bounds__(BLOCK) void ld_fwd_join_kernel(AdjArgs a) {
                         P[3] += cl * ca, P[4] += cl * cb, P[5] += ce * ca, P[6] += ce * cb;
                     }
                 }
-                double l = fr[6 * NT];
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    const double x0 = x[d], v0 = v[d];
-                    l += 2.0 * (x0 * fr[(7 + d) * NT] + v0 * fr[(10 + d) * NT]) + x0 * x0 * P[0] +
-                         2.0 * x0 * v0 * P[1] + v0 * v0 * P[2];
-                    rx[(kCkptLamRow + d) * NT + i] =
-                        static_cast<float>(2.0 * (fr[(13 + d) * NT] + P[3] * x0 + P[4] * v0));
-                    rx[(kCkptLamRow + 3 + d) * NT + i] =
-                        static_cast<float>(2.0 * (fr[(16 + d) * NT] + P[5] * x0 + P[6] * v0));
-                }
-                lsum += l;
+                lsum += cur.sxx + 2.0 * (x * cur.sa + v * cur.sb) + x * x * P[0] + 2.0 * x * v * P[1] + v * v * P[2];
+                rx[(kCkptLamRow + d) * NT + i] = static_cast<float>(2.0 * (cur.sal + P[3] * x + P[4] * v));
+                rx[(kCkptLamRow + 3 + d) * NT + i] = static_cast<float>(2.0 * (cur.sbe + P[5] * x + P[6] * v));
             }
             const double *M = (s1 - s0 == a.K) ? A.fk : A.flast;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const double nx = fr[d * NT] + M[0] * x[d] + M[1] * v[d];
-                const double nv = fr[(3 + d) * NT] + M[2] * x[d] + M[3] * v[d];
-                x[d] = nx;
-                v[d] = nv;
-            }
+            const double nx = cur.xp + M[0] * x + M[1] * v;
+            const double nv = cur.vp + M[2] * x + M[3] * v;
+            x = nx;
+            v = nv;
+            cur = nxt;
         }
         float *rx = rec_f(nseg);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const float xf = static_cast<float>(x[d]), vf = static_cast<float>(v[d]);
-            rx[d * NT + i] = xf;
-            rx[(3 + d) * NT + i] = vf;
-            a.x[d * NT + i] = xf;
-            a.v[d * NT + i] = vf;
-        }
+        const float xf = static_cast<float>(x), vf = static_cast<float>(v);
+        rx[d * NT + i] = xf;
+        rx[(3 + d) * NT + i] = vf;
+        a.x[d * NT + i] = xf;
+        a.v[d * NT + i] = vf;
+        // the generator rows of the end record to the live state: rows d, and row 3 with d = 0
         const uint32_t *rs = reinterpret_cast<const uint32_t *>(rx + 6 * NT);
         uint32_t *live = static_cast<uint32_t *>(a.state);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) live[r * a.S + i] = rs[r * NT + i];
-        adjoint_walk(a, i, A.bk);
+        live[d * a.S + i] = rs[d * NT + i];
+        if (d == 0) live[3 * a.S + i] = rs[3 * NT + i];
+        adjoint_walk(a, i, d, A.bk);
     }
-    const double qv[6] = {act ? lsum : 0.0, act ? lsum * lsum : 0.0, 0.0, 0.0, 0.0, 0.0};
-    block_sum6<BLOCK>(qv, red, a.partials + static_cast<uint64_t>(tile) * kAdjPartW);
+    const double qv[6] = {act ? lsum : 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    block_sum6<3 * TILE>(qv, red, a.partials + static_cast<uint64_t>(tile) * kAdjPartW);
 }
 
 template <class Gen, int BLOCK>
@@ -616,31 +616,39 @@ __global__ __launch_bounds__(BLOCK) void ld_adjoint_seg_kernel(AdjArgs a) {
     // the segment's gradient as sums over its steps and the three components of mu x, mu v and
     // mu g, scaled by the partials at the end: K terms per component in FP32
     float smx = 0.0f, smv = 0.0f, smg = 0.0f;
-    // x, v hold the state after step s on entry to step s
-    for (uint32_t s = s1; s-- > s0;) {
-        const bool in_loss = (s + 1 >= a.t_begin) && (s + 1 <= a.t_end);
-        const uint32_t w3 = g.prev_top24();
-        const uint32_t w2 = g.prev_top24();
-        const uint32_t w1 = g.prev_top24();
-        const uint32_t w0 = g.prev_top24();
-        float gf[3];
-        gaussian_forces_top24(w0, w1, w2, w3, gf[0], gf[1], gf[2]);
+    // steps s = e - 1 down to b, x and v holding the state after step s on entry to step s; LOSS:
+    // the steps whose end position is a loss term (s + 1 in the window)
+    auto sweep = [&](auto loss_tag, uint32_t b, uint32_t e) {
+        constexpr bool LOSS = decltype(loss_tag)::value;
+        for (uint32_t s = e; s-- > b;) {
+            const uint32_t w3 = g.prev_top24();
+            const uint32_t w2 = g.prev_top24();
+            const uint32_t w1 = g.prev_top24();
+            const uint32_t w0 = g.prev_top24();
+            float gf[3];
+            gaussian_forces_top24(w0, w1, w2, w3, gf[0], gf[1], gf[2]);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            if (in_loss) lx[d] += 2.0f * x[d];
-            const float xs = x[d] - h * v[d];
-            const float t = v[d] + kap * xs - sig * gf[d];
-            const float vs = __builtin_fmaf(t, inv_c, t * inv_c_lo);
-            const float mu = lv[d] + h * lx[d];
-            smx += mu * xs;
-            smv += mu * vs;
-            smg += mu * gf[d];
-            lx[d] = lx[d] - kap * mu;
-            lv[d] = c * mu;
-            x[d] = xs;
-            v[d] = vs;
+            for (int d = 0; d < 3; ++d) {
+                if constexpr (LOSS) lx[d] += 2.0f * x[d];
+                const float xs = x[d] - h * v[d];
+                const float t = v[d] + kap * xs - sig * gf[d];
+                const float vs = __builtin_fmaf(t, inv_c, t * inv_c_lo);
+                const float mu = lv[d] + h * lx[d];
+                smx += mu * xs;
+                smv += mu * vs;
+                smg += mu * gf[d];
+                lx[d] = lx[d] - kap * mu;
+                lv[d] = c * mu;
+                x[d] = xs;
+                v[d] = vs;
+            }
         }
-    }
+    };
+    uint32_t lo, hi;
+    window_part(a, s0, s1, lo, hi);
+    sweep(std::false_type{}, hi, s1);
+    sweep(std::true_type{}, lo, hi);
+    sweep(std::false_type{}, s0, lo);
     if (!act) return;
     double *rd = a.seg_d + static_cast<uint64_t>(seg) * kAdjSegD * NT + i;
     rd[0] = -static_cast<double>(A.dkap_dk) * smx;
@@ -712,7 +720,7 @@ hipError_t launch_ld_ckpt(int kind, const AdjArgs &a, bool any_sp, bool any_seq,
         const uint32_t nseg = (a.n_steps + a.K - 1) / a.K;
         adj_prep_kernel<<<nseg + a.n_ens, 128, 0, st>>>(a, nseg);
         ld_fwd_seg_kernel<kAdjBlock><<<dim3(a.n_tiles, nseg), kAdjBlock, 0, st>>>(a);
-        ld_fwd_join_kernel<kAdjBlock><<<a.n_tiles, kAdjBlock, 0, st>>>(a);
+        ld_fwd_join_kernel<kAdjBlock><<<a.n_tiles, 3 * kAdjBlock, 0, st>>>(a);
         const hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
     }

@@ -118,3 +118,14 @@ def test_step_protocol_extra_runs_only_when_named(monkeypatch):
     ran.clear()
     bench.extras(None, None, None, ("step_protocol",))
     assert ran == ["extra_step_protocol"]
+
+
+def test_windowed_valu_weights_the_window_loop():
+    if "step_loops" not in bench._kernel_isa():
+        pytest.skip("the library has not been built (no kernel_isa.json)")
+    for which in ("adjoint_forward", "adjoint_backward"):
+        loop = bench._kernel_isa()["step_loops"][bench.STEP_LOOP_KERNELS[which]]
+        lo, hi = min(loop["all_loops"]), loop["valu_per_iteration"]
+        assert bench.windowed_valu(which, 2000, 1, 2000) == hi  # the whole run is the window
+        assert bench.windowed_valu(which, 2000, 2000, 2000) == pytest.approx((1999 * lo + hi) / 2000)
+        assert bench.windowed_valu(which, 2000, 1001, 2000) == pytest.approx((lo + hi) / 2)
