@@ -320,13 +320,22 @@ typedef struct ld_loss {
 /* Checkpoint buffer: ceil(n_steps/K) + 1 records, record c = state at step min(c*K, n_steps)
  * (the last record is the state at the end of the run):
  * float x[3][n_total], float v[3][n_total], then the generator state in the layout above with
- * S = n_total. */
+ * S = n_total; for Hybrid Taus then float lam_x[3][n_total], lam_v[3][n_total]: the gradient of the
+ * sum of x^2 over the loss window's steps after the record with respect to the record's x and v
+ * (the loss adjoint the backward sweep of the segment ending there starts from), written by
+ * ld_run_ckpt for ensembles that can take the register-only backward. */
 RNGLD_API int ld_ckpt_bytes(const rngld_cfg *cfg, uint64_t n_total, uint32_t n_steps, uint32_t K, size_t *bytes);
 RNGLD_API int ld_adjoint_workspace_bytes(const rngld_cfg *cfg, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total,
                                uint32_t n_steps, const ld_loss *loss, size_t *bytes);
 
 /* Forward run that writes checkpoints and the losses d_loss[n_ens] (double).  Underdamped,
- * per-thread kinds.  x, v and the state advance as in ld_run. */
+ * per-thread kinds.  x, v and the state advance as in ld_run.  For Hybrid Taus ensembles that can
+ * take the register-only backward (with two or more segments and K <= 65536) the run is
+ * segment-parallel: every Tausworthe step is linear over GF(2) and the LCG step affine, so each
+ * K-step segment starts from its generator state jumped ahead by bit-matrix products, runs from a
+ * zero state, and a join pass adds, in FP64, the response to the true start state (the LD step is
+ * linear).  x and v then agree with a sequential run up to rounding, the noise bit for bit.
+ * d_ws: ld_adjoint_workspace_bytes. */
 RNGLD_API int ld_run_ckpt(const rngld_cfg *cfg, void *d_state, size_t state_bytes, const ld_ensemble *h_ens,
                 uint32_t n_ens, uint64_t n_total, uint32_t n_steps, float *d_x, float *d_v, const ld_loss *loss,
                 void *d_ckpt, size_t ckpt_bytes, double *d_loss, void *d_ws, size_t ws_bytes, void *stream);
@@ -345,14 +354,17 @@ RNGLD_API int ld_run_ckpt(const rngld_cfg *cfg, void *d_state, size_t state_byte
  *    when rounding errors cannot grow by more than 8 over K inverse steps (max over j <= K of the
  *    Frobenius norm of the inverse step matrix to the power j, for the ensemble's FP32
  *    coefficients), e.g. gamma dt <= 0.02 at K = 100 and dt = 0.01.  The segments of an
- *    oscillator are swept concurrently, each from a zero adjoint at its end, and then joined
- *    (the reverse recursion is linear with a constant step matrix), through a workspace record of
- *    120 bytes per oscillator and segment.
+ *    oscillator are swept concurrently, each from the loss adjoint that ld_run_ckpt left in the
+ *    checkpoint at its end (the reverse recursion is linear with a constant step matrix, so the
+ *    forward run can form it), and a workspace record of 24 bytes per oscillator and segment
+ *    collects each segment's share of the gradient.
  *  - replay: each segment is rerun forward from the checkpoint at its start into a scratch of
  *    9 floats per oscillator-step and swept backward from there (Ran2; Hybrid Taus otherwise or
  *    with RNGLD_ADJ_REPLAY).
- * ld_adjoint_workspace_bytes includes each path's scratch only when some ensemble takes it, so it
- * depends on the ensembles' parameters and the flags.
+ * ld_adjoint_workspace_bytes is the workspace of both ld_run_ckpt and ld_run_backward (one buffer
+ * serves both: the segment-parallel forward's 76 bytes per oscillator and segment and the
+ * backward's scratch share their space).  It includes each path's scratch only when some ensemble
+ * takes it, so it depends on the ensembles' parameters and the flags.
  */
 RNGLD_API int ld_run_backward(const rngld_cfg *cfg, const void *d_ckpt, size_t ckpt_bytes, const ld_ensemble *h_ens,
                     uint32_t n_ens, uint64_t n_total, uint32_t n_steps, const ld_loss *loss, double *d_grad,
