@@ -512,7 +512,11 @@ def extra_config3(R, W, torch):
             raise RuntimeError("the persistent lagged-Fibonacci stream gave up a wait: invalid output")
         tu, tg = a.elapsed_time(b) / 1e3, c.elapsed_time(d) / 1e3
         if kind == "lf":
-            bpv_u, bpv_g = 8.0, 16.0  # Gaussians: integers written and read back, floats written over them
+            # uniforms: each value written once and read once as a long-lag source (the output is
+            # the lag table); Gaussians (the producer/consumer run): each integer written into the
+            # run's ring, read there as a long-lag source and by a consumer, and its float written
+            # once to the output: 12 B in the ring (memory-side cache) + 4 B to HBM
+            bpv_u, bpv_g = 8.0, 16.0
         else:
             bpv_u = bpv_g = 4.0 + 2.0 * state_bytes[kind] * S / n_vals
         ru, rg = bpv_u * n_vals / tu / 1e9, bpv_g * n_vals / tg / 1e9

@@ -110,10 +110,14 @@ typedef struct rngld_cfg {
  *  LAGFIB      : 64-byte header { uint64 pos; uint32 slot; uint32 ll, sl, R, W; ... } followed by
  *                uint32 ring[R]; y_n lives in ring[(slot + n - pos) mod R] for the last ll
  *                positions n < pos.  pos counts values generated since rng_init.  Then, from the
- *                next 128-byte boundary, working words of the persistent rng_uniform run: a status
+ *                next 128-byte boundary, working words of the persistent stream runs: a status
  *                word (nonzero after a run that gave up waiting; its output is then invalid) and
- *                8192 progress words 128 bytes apart, undefined between calls.
- *                64 + 4 R + 128 + 8192 * 128 bytes.
+ *                2 x 8192 progress words 128 bytes apart, undefined between calls.  Then, when
+ *                sl >= 256 and it is addressable (nr slp < 2^29 words, nr sl < 2^31), from the
+ *                next 256-byte boundary the Gaussian stream run's own ring: nr = ceil(2 (ll + sl)
+ *                / sl) links of slp = sl rounded up to 64 words, undefined between calls.
+ *                align128(64 + 4 R) + 128 + 2 * 8192 * 128 bytes, + the ring's 4 nr slp bytes
+ *                (256-byte aligned) when present.
  */
 RNGLD_API int rngld_state_bytes(const rngld_cfg *cfg, size_t *bytes);
 
@@ -139,8 +143,12 @@ RNGLD_API int rng_uniform(const rngld_cfg *cfg, void *d_state, size_t state_byte
  * other distributions): values 2i and 2i+1 of a stream are r cos(2 pi u1), r sin(2 pi u1) with
  * r = sqrt(-2 ln u0), u0 = ((w0 >> 8) + 1) 2^-24, u1 = (w1 >> 8) 2^-24 from that stream's words
  * 2i and 2i+1 (Ran2 word: (iy - 1) << 1).  per_stream must be even.  Layout as rng_uniform.
- * LAGFIB streams that take rng_uniform's persistent launch are generated as integers into d_out
- * (as the lag table) and then transformed pair by pair in place.
+ * LAGFIB: with a 16-byte aligned d_out and at least 16 n values (n = 64 x the consumer waves of
+ * the persistent run, x 1, 2 or 4), one persistent producer/consumer launch generates the first
+ * 4 n T of them, T = per_stream / (4 n): producers extend the sequence in the state's own ring as
+ * in the fused LD run and consumers write the Box-Muller pairs once; the rest continue as below.
+ * Other calls that take rng_uniform's persistent launch are generated as integers into d_out (as
+ * the lag table) and then transformed pair by pair in place.
  */
 RNGLD_API int rng_gaussian(const rngld_cfg *cfg, void *d_state, size_t state_bytes, uint64_t per_stream,
                  float *d_out, uint64_t out_len, void *stream);

@@ -56,6 +56,7 @@ struct Gen {
     size_t state_bytes = 0;
     uint32_t rows = 0;  // per-thread state rows
     uint64_t leap = 0;  // LCG cycle division (0: independent seed words)
+    size_t pring_off = 0;  // LAGFIB: byte offset of the bare-stream run's padded ring (0: none)
 };
 
 int check_cfg(const rngld_cfg *cfg, Gen *g) {
@@ -94,8 +95,16 @@ int check_cfg(const rngld_cfg *cfg, Gen *g) {
             g->sl = sl;
             g->W = W;
             g->R = static_cast<uint32_t>(R);
-            // header, ring, then the bare-stream run's progress words
-            g->state_bytes = sizeof(LfHeader) + static_cast<size_t>(R) * 4 + kLfStreamFlagBytes;
+            // header, ring, then (128-byte aligned) the bare-stream runs' progress words and, when
+            // its addressing allows, (256-byte aligned) the producer/consumer stream's own ring
+            const size_t flags = (sizeof(LfHeader) + static_cast<size_t>(R) * 4 + 127) & ~static_cast<size_t>(127);
+            g->state_bytes = flags + kLfStreamFlagBytes;
+            const LfPadRing pr = lf_pad_ring(ll, sl);
+            const uint64_t pr_words = static_cast<uint64_t>(pr.nr) * pr.slp;
+            if (sl >= 256 && pr_words < (1ull << 29) && static_cast<uint64_t>(pr.nr) * sl < (1ull << 31)) {
+                g->pring_off = (g->state_bytes + 255) & ~static_cast<size_t>(255);
+                g->state_bytes = g->pring_off + pr_words * 4;
+            }
             return RNGLD_OK;
         }
         default:
@@ -477,6 +486,75 @@ uint32_t *lf_stream_flags(const Gen &g, void *d_state) {
     return reinterpret_cast<uint32_t *>((p + 127) & ~static_cast<uintptr_t>(127));
 }
 
+// The persistent producer/consumer run as a bare Gaussian stream: producers
+// extend the sequence in the state's padded ring exactly as in the fused LD run, and the consumers,
+// kc tiles of 64 virtual oscillators with four positions per step each, write their positions'
+// Box-Muller pairs to out.  It covers the first 4 n T positions of the call, n = 64 kc
+// times the consumer waves, T = count / (4 n) steps; returns the number of positions launched (0:
+// the run does not fit and nothing was enqueued), an RNGLD error below 0.
+int64_t try_lf_pc_gauss(const Gen &g, void *d_state, uint32_t *d_out, uint64_t count, hipStream_t st) {
+    if (!g.pring_off || (reinterpret_cast<uintptr_t>(d_out) & 15u)) return 0;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    if (cs != hipStreamCaptureStatusNone) return 0;
+    const LfPadRing pr = lf_pad_ring(g.ll, g.sl);
+    const uint64_t R_run = static_cast<uint64_t>(pr.nr) * g.sl;
+    const int cus = device_cus();
+    if (cus <= 0) return fail(RNGLD_EHIP, "cannot query the compute-unit count");
+    const uint32_t wpb = kLfFlowBlock / 64;
+    uint32_t np = 1;
+    while (np < wpb - 1 && static_cast<uint64_t>(np) * cus * kLfFlowSliceMax < g.sl) ++np;
+    if (static_cast<uint64_t>(np) * cus * kLfFlowSliceMax < g.sl) return 0;
+    const uint32_t Gp = np * static_cast<uint32_t>(cus), Gc = (wpb - np) * static_cast<uint32_t>(cus);
+    if (Gp > kLfFlowMaxWaves || Gc > kLfFlowMaxWaves) return 0;
+    // kc tiles of 64 virtual oscillators per consumer wave, as many as leave at least 4 steps: a
+    // step then moves 1 KiB per tile and wave, and the per-step waits and publications are
+    // amortised over kc tiles
+    uint32_t kc = 4;
+    while (kc > 1 && count / (4ull * 64 * Gc * kc) < 4) kc /= 2;
+    const uint64_t n = 64ull * Gc * kc;
+    const uint64_t T = count / (4 * n);
+    if (T < 4 || T >= (1ull << 32)) return 0;
+    const uint64_t Ptot = 4 * n * T;
+    if ((Ptot + g.sl - 1) / g.sl >= (1ull << 31)) return 0;
+    uint32_t slice_log2 = 8;
+    while ((static_cast<uint64_t>(Gp) << slice_log2) < g.sl) ++slice_log2;
+    const LfFlowGeom geom =
+        lf_flow_geom(n, static_cast<uint32_t>(T), g.ll, g.sl, static_cast<uint32_t>(R_run), slice_log2, Gc);
+    if (geom.Kc != kc || R_run < static_cast<uint64_t>(g.sl) + 256ull * kc - 1 || 256ull * kc > g.sl) return 0;
+    LfFlowArgs a{};
+    a.L = lf_ring(g, d_state);
+    a.geom = geom;
+    a.pring = reinterpret_cast<uint32_t *>(static_cast<uint8_t *>(d_state) + g.pring_off);
+    a.pr = pr;
+    uint32_t *flags = lf_stream_flags(g, d_state);
+    a.status = flags;
+    a.prod = flags + kLfFlagStride;
+    a.cons = a.prod + static_cast<size_t>(kLfFlowMaxWaves) * kLfFlagStride;
+    a.N = n;
+    a.n = n;
+    a.n_steps = static_cast<uint32_t>(T);
+    a.spin_limit = 1u << 20;
+    a.np = np;
+    a.out = d_out;
+    RNGLD_TRY_HIP(launch_lf_pad_in(a.L, a.pring, pr, st));
+    RNGLD_TRY_HIP(launch_fill_u32(flags, 1, 0u, st));
+    RNGLD_TRY_HIP(launch_fill_u32(a.prod, static_cast<uint64_t>(Gp) * kLfFlagStride, 0u, st));
+    RNGLD_TRY_HIP(launch_fill_u32(a.cons, static_cast<uint64_t>(Gc) * kLfFlagStride, 0u, st));
+    const hipError_t e = launch_lf_flow(a, static_cast<uint32_t>(cus), kc, 0, st, kFlowGauss);
+    if (e == hipErrorCooperativeLaunchTooLarge) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    if (e != hipSuccess) return fail(RNGLD_EHIP, "persistent LF stream launch: %s", hipGetErrorString(e));
+    RNGLD_TRY_HIP(launch_lf_pad_out(a.L, a.pring, pr, Ptot, st));
+    RNGLD_TRY_HIP(launch_lf_advance(const_cast<LfHeader *>(a.L.hdr), Ptot, static_cast<uint32_t>(Ptot % g.R), st));
+    return static_cast<int64_t>(Ptot);
+}
+
 // The persistent bare-stream run for count values, if it fits: 1 when launched, 0 when the wave
 // path must run, an RNGLD error otherwise.  Needs links long enough to keep the chip busy.
 // gauss: the run also turns out[0, keep_from) into Box-Muller pairs in place (needs an even sl)
@@ -638,6 +716,12 @@ int rng_gaussian(const rngld_cfg *cfg, void *d_state, size_t state_bytes, uint64
         if (count == 0) return RNGLD_OK;
         if (!d_out) return fail(RNGLD_EINVAL, "output pointer is NULL");
         const LfRing L = lf_ring(g, d_state);
+        // long calls: the producer/consumer run (integers in the state's own ring, Gaussian pairs
+        // written once) takes the first 4 n T values; the rest continues from there below
+        const int64_t done = try_lf_pc_gauss(g, d_state, reinterpret_cast<uint32_t *>(d_out), count, st);
+        if (done < 0) return static_cast<int>(done);
+        if (static_cast<uint64_t>(done) == count) return RNGLD_OK;
+        if (done > 0) return rng_gaussian(cfg, d_state, state_bytes, count - done, d_out + done, out_len - done, stream);
         // the persistent stream writes the integers into the output, which doubles as the lag
         // table; with an even sl it also turns them into Gaussian pairs in place once no producer
         // reads them, except the pairs from keep_from on: the ring takes the last ll integers, then

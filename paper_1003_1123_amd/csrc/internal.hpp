@@ -100,7 +100,11 @@ struct LfFlowArgs {
     uint32_t pstride;
     uint32_t spin_limit;   // polls of one wait before the run gives up
     uint32_t np;           // producer waves per block: the block's first np waves
+    uint32_t *out;         // bare-stream modes: run position P to out[P] (16-byte aligned)
 };
+// what the consumers of a persistent run do with their words: drive the LD run, or write their
+// Box-Muller pairs to out
+constexpr int kFlowLd = 0, kFlowGauss = 1;
 
 // persistent bare stream (rng_uniform): out[0, count) = the next count values of the sequence
 struct LfStreamArgs {
@@ -116,8 +120,9 @@ struct LfStreamArgs {
     uint64_t keep_from;    // Gaussian run: out[P] for P < keep_from (even) is turned into Box-Muller
                            // pairs in place once no producer still reads it; the rest stays integer
 };
-// progress words the LAGFIB state reserves after its ring for the bare-stream run (bytes)
-constexpr size_t kLfStreamFlagBytes = 128 + static_cast<size_t>(8192) * 32 * sizeof(uint32_t);
+// progress words the LAGFIB state reserves after its ring for the bare-stream runs (bytes): the
+// status line, then one line per producer and one per consumer
+constexpr size_t kLfStreamFlagBytes = 128 + 2 * static_cast<size_t>(8192) * 32 * sizeof(uint32_t);
 // gauss: also turn out[0, keep_from) into Gaussians in place (needs an even sl)
 hipError_t launch_lf_stream(const LfStreamArgs &a, uint32_t grid, uint32_t m, bool gauss, hipStream_t st);
 
@@ -242,7 +247,8 @@ constexpr uint32_t kLfFlowMaxWaves = 8192;  // progress words reserved per role
 constexpr uint32_t kLfFlagStride = 32;       // words between progress words: one 128-byte line each
 // launch the producer/consumer kernel for consumer waves of up to kc tiles each; `lds` bytes of
 // dynamic LDS per block.  hipErrorCooperativeLaunchTooLarge if `grid` blocks cannot be co-resident.
-hipError_t launch_lf_flow(const LfFlowArgs &a, uint32_t grid, uint32_t kc, uint32_t lds, hipStream_t st);
+hipError_t launch_lf_flow(const LfFlowArgs &a, uint32_t grid, uint32_t kc, uint32_t lds, hipStream_t st,
+                          int mode = kFlowLd);
 // copy the window y_{-ll..-1} before a persistent run from the state's ring into the run's ring,
 // and afterwards the window y_{Ptot-ll..Ptot-1} back (slots relative to the run's first position;
 // the header is advanced separately)

@@ -229,6 +229,21 @@ constexpr int kFlowG = kFlowM / 4;             // ... in groups of four consecut
 // quarter of the memory instructions.  The resource's size bounds every access (an access past it
 // reads zeros and writes nothing); a 16-byte access needs only 4-byte alignment.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Box-Muller pairs of four consecutive words (two whole pairs), as their bit patterns
+__device__ __forceinline__ u32x4 box_muller_pairs4(const u32x4 &wv) {
+    u32x4 gv;
+    float c, sn;
+    float r = box_muller_radius(wv[0]);
+    box_muller_angle(wv[1], c, sn);
+    gv[0] = __float_as_uint(r * c);
+    gv[1] = __float_as_uint(r * sn);
+    r = box_muller_radius(wv[2]);
+    box_muller_angle(wv[3], c, sn);
+    gv[2] = __float_as_uint(r * c);
+    gv[3] = __float_as_uint(r * sn);
+    return gv;
+}
 constexpr int kBufferWord3 = 0x00020000;  // raw 32-bit buffer, gfx9 encoding
 constexpr int kCachePolicySc1 = 16;
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t ring_rsrc(uint32_t *ring, uint32_t words) {
@@ -529,7 +544,10 @@ constexpr int kWaitVm1 = 0xF71, kWaitVm0 = 0xF70;
 // software-pipelined: the next step's loads go out before this step's LD update whenever a poll
 // issued one step earlier shows its producers published (a second set of word registers, which 8
 // tiles do not have).
-template <int KC>
+// MODE kFlowGauss (bare Gaussian streams): no oscillators; lane l of tile k writes its group of four
+// positions 4 (o + n s) .. + 3 to out as two Box-Muller pairs, with one 16-byte nontemporal store
+// (the output is not read again here, and the ring it would otherwise push out of the caches is).
+template <int KC, int MODE>
 __device__ __forceinline__ void lf_consumer(const LfFlowArgs &a, uint32_t cw, uint32_t lane, float *xv) {
     constexpr bool kPipe = KC <= 4;
     const LfFlowGeom &g = a.geom;
@@ -540,14 +558,16 @@ __device__ __forceinline__ void lf_consumer(const LfFlowArgs &a, uint32_t cw, ui
     if (o0 >= o1) return;  // no oscillators: no producer ever waits for this wave
     const uint32_t cnt = static_cast<uint32_t>(4 * (o1 - o0));  // positions per step
     const uint32_t Kw = static_cast<uint32_t>((o1 - o0 + 63) / 64);
+    if constexpr (MODE == kFlowLd) {
 #pragma unroll 1
-    for (uint32_t k = 0; k < Kw; ++k) {
-        const uint64_t o = o0 + 64ull * k + lane;
-        const bool act = o < o1;
+        for (uint32_t k = 0; k < Kw; ++k) {
+            const uint64_t o = o0 + 64ull * k + lane;
+            const bool act = o < o1;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            xv[(k * 6 + d) * 64 + lane] = act ? a.x[d * a.N + o] : 0.0f;
-            xv[(k * 6 + 3 + d) * 64 + lane] = act ? a.v[d * a.N + o] : 0.0f;
+            for (int d = 0; d < 3; ++d) {
+                xv[(k * 6 + d) * 64 + lane] = act ? a.x[d * a.N + o] : 0.0f;
+                xv[(k * 6 + 3 + d) * 64 + lane] = act ? a.v[d * a.N + o] : 0.0f;
+            }
         }
     }
     // coordinates of a step's first position 4 o0 + s 4n: its link, offset and the link's first
@@ -616,6 +636,7 @@ __device__ __forceinline__ void lf_consumer(const LfFlowArgs &a, uint32_t cw, ui
         }
     };
     auto observe = [&](uint32_t s) {
+        if constexpr (MODE != kFlowLd) return;
         float *t0buf = a.t0buf;
         asm volatile("" : "+s"(t0buf));
         if (a.stride && s % a.stride == 0) {
@@ -635,6 +656,18 @@ __device__ __forceinline__ void lf_consumer(const LfFlowArgs &a, uint32_t cw, ui
                         t0buf[d * a.N + o] = xv[(k * 6 + d) * 64 + lane];
                         t0buf[(3 + d) * a.N + o] = xv[(k * 6 + 3 + d) * 64 + lane];
                     }
+            }
+        }
+    };
+    // stream modes: step s of the wave's words to out
+    auto emit = [&](const Words &W, uint32_t s) {
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            if (k >= static_cast<int>(Kw)) break;
+            const uint64_t o = o0 + 64ull * k + lane;
+            if (o < o1) {
+                u32x4 *dst = reinterpret_cast<u32x4 *>(a.out + 4 * (o + a.n * s));
+                __builtin_nontemporal_store(box_muller_pairs4(W.q[k]), dst);
             }
         }
     };
@@ -703,7 +736,10 @@ __device__ __forceinline__ void lf_consumer(const LfFlowArgs &a, uint32_t cw, ui
             }
             // X's slots are free (published before any wait for step s+1)
             if (lane == 0) agent_store(a.cons + cw * kLfFlagStride, s + 1);
-            update(X);
+            if constexpr (MODE == kFlowLd)
+                update(X);
+            else
+                emit(X, s);
             if (more && !ready) {
                 collect(w, nxt);
                 if (!wait_all(w, lane, a)) return -1;
@@ -734,10 +770,14 @@ __device__ __forceinline__ void lf_consumer(const LfFlowArgs &a, uint32_t cw, ui
             fix(W);
             // the step's slots are free
             if (lane == 0) agent_store(a.cons + cw * kLfFlagStride, s + 1);
-            update(W);
+            if constexpr (MODE == kFlowLd)
+                update(W);
+            else
+                emit(W, s);
             advance(nxt);
         }
     }
+    if constexpr (MODE != kFlowLd) return;
     float *t0buf = a.t0buf, *xo = a.x, *vo = a.v;
     asm volatile("" : "+s"(t0buf), "+s"(xo), "+s"(vo));
     if (a.stride && a.n_steps % a.stride == 0) {
@@ -759,7 +799,7 @@ __device__ __forceinline__ void lf_consumer(const LfFlowArgs &a, uint32_t cw, ui
     }
 }
 
-template <int KC>
+template <int KC, int MODE>
 __global__ __launch_bounds__(kLfFlowBlock) void lf_pc_kernel(LfFlowArgs a) {
     extern __shared__ float flow_lds[];
     const uint32_t lane = threadIdx.x & 63u;
@@ -768,7 +808,7 @@ __global__ __launch_bounds__(kLfFlowBlock) void lf_pc_kernel(LfFlowArgs a) {
         lf_producer(a, __builtin_amdgcn_readfirstlane(blockIdx.x * a.np + wid), lane);
     } else {
         const uint32_t nc = kLfFlowBlock / 64 - a.np, k = wid - a.np;
-        lf_consumer<KC>(a, __builtin_amdgcn_readfirstlane(blockIdx.x * nc + k), lane,
+        lf_consumer<KC, MODE>(a, __builtin_amdgcn_readfirstlane(blockIdx.x * nc + k), lane,
                         flow_lds + static_cast<size_t>(k) * a.geom.Kc * 384u);
     }
 }
@@ -803,10 +843,21 @@ __global__ __launch_bounds__(kBulkBlock) void fill_u32_kernel(uint32_t *dst, uin
 
 template <int KC>
 const void *lf_pc_fn() {
-    return reinterpret_cast<const void *>(&lf_pc_kernel<KC>);
+    return reinterpret_cast<const void *>(&lf_pc_kernel<KC, kFlowLd>);
 }
 
-const void *lf_pc_fn_for(uint32_t kc) {
+template <int MODE>
+const void *lf_stream_pc_fn(uint32_t kc) {
+    switch (kc) {
+        case 1: return reinterpret_cast<const void *>(&lf_pc_kernel<1, MODE>);
+        case 2: return reinterpret_cast<const void *>(&lf_pc_kernel<2, MODE>);
+        case 4: return reinterpret_cast<const void *>(&lf_pc_kernel<4, MODE>);
+        default: return nullptr;
+    }
+}
+
+const void *lf_pc_fn_for(uint32_t kc, int mode) {
+    if (mode == kFlowGauss) return lf_stream_pc_fn<kFlowGauss>(kc);
     switch (kc) {
         case 1: return lf_pc_fn<1>();
         case 2: return lf_pc_fn<2>();
@@ -1048,20 +1099,6 @@ __global__ __launch_bounds__(kLfFlowBlock) void lf_stream_kernel(LfStreamArgs a)
         collect_readers(jc);
         cseen = agent_load(lane < cw.n ? cw.flag : a.status);
     };
-    // Box-Muller pairs of one lane's four words (two whole pairs)
-    auto bm4 = [](const u32x4 &wv) -> u32x4 {
-        u32x4 gv;
-        float c, sn;
-        float r = box_muller_radius(wv[0]);
-        box_muller_angle(wv[1], c, sn);
-        gv[0] = __float_as_uint(r * c);
-        gv[1] = __float_as_uint(r * sn);
-        r = box_muller_radius(wv[2]);
-        box_muller_angle(wv[3], c, sn);
-        gv[2] = __float_as_uint(r * c);
-        gv[3] = __float_as_uint(r * sn);
-        return gv;
-    };
     // the conversion of link jc is split in two, one link apart: start loads the slice's whole
     // four-word groups below keep_from (the integers are final: this producer stored them and saw
     // the stores complete), finish waits for the readers and stores the pairs (the few partial
@@ -1087,7 +1124,7 @@ __global__ __launch_bounds__(kLfFlowBlock) void lf_stream_kernel(LfStreamArgs a)
         for (int gi = 0; gi < G; ++gi) {
             const uint32_t q0 = 4u * (lane + 64u * gi);
             if (full_group(jc, lenc, q0)) {
-                ring_put4(rs, q0, bm4(cv[gi]));
+                ring_put4(rs, q0, box_muller_pairs4(cv[gi]));
             } else {
 #pragma unroll
                 for (int r = 0; r < 4; r += 2)
@@ -1194,8 +1231,8 @@ hipError_t launch_lf_stream(const LfStreamArgs &a, uint32_t grid, uint32_t m, bo
     return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kLfFlowBlock), args, 0, st);
 }
 
-hipError_t launch_lf_flow(const LfFlowArgs &a, uint32_t grid, uint32_t kc, uint32_t lds, hipStream_t st) {
-    const void *fn = lf_pc_fn_for(kc);
+hipError_t launch_lf_flow(const LfFlowArgs &a, uint32_t grid, uint32_t kc, uint32_t lds, hipStream_t st, int mode) {
+    const void *fn = lf_pc_fn_for(kc, mode);
     if (!fn) return hipErrorInvalidValue;
     // allow more than 64 KiB of dynamic LDS where the runtime asks for it; the occupancy query
     // below decides whether the block fits

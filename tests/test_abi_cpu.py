@@ -61,16 +61,29 @@ def test_state_bytes():
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lcg", n_streams=1000)), C.byref(out)) == 0 and out.value == 4000
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lcg", n_streams=7, leap=4)), C.byref(out)) == 0 and out.value == 28
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("none", n_streams=10**6)), C.byref(out)) == 0 and out.value == 0
-    flags = 128 + 8192 * 32 * 4  # the bare-stream run's status and progress words after the ring
+    def lf_bytes(ll, sl, R):
+        # header and ring; 128-byte aligned, the bare-stream runs' status line and progress words
+        # (a line per producer and per consumer); 256-byte aligned, the stream run's padded ring of
+        # ceil(2 (ll + sl) / sl) links of sl words rounded up to 64 (when sl >= 256 and it fits)
+        up = lambda v, a: (v + a - 1) // a * a
+        size = up(64 + 4 * R, 128) + 128 + 2 * 8192 * 32 * 4
+        nr, slp = -(-2 * (ll + sl) // sl), up(sl, 64)
+        if sl >= 256 and nr * slp < 2**29 and nr * sl < 2**31:
+            size = up(size, 256) + 4 * nr * slp
+        return size
+
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=2281, sl=1252)), C.byref(out)) == 0
-    assert out.value == 64 + 4 * 2 * (2281 + 1252) + flags
+    assert out.value == lf_bytes(2281, 1252, 2 * (2281 + 1252)) == 2156544
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=2281, sl=1252, wave=101)), C.byref(out)) == 0
-    assert out.value == 64 + 4 * 2 * (2281 + 1252) + flags  # default ring 2 (ll + sl) whatever the wave width
+    assert out.value == lf_bytes(2281, 1252, 2 * (2281 + 1252))  # default ring 2 (ll + sl) whatever the wave width
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=2281, sl=1252, wave=101, ring=2400)), C.byref(out)) == 0
-    assert out.value == 64 + 4 * 2400 + flags
-    # lags whose doubled sum reaches 2^30 fall back to a ring of ll + sl
+    assert out.value == lf_bytes(2281, 1252, 2400)
+    # lags whose doubled sum reaches 2^30 fall back to a ring of ll + sl (and no stream ring: too long)
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=600_000_001, sl=1000)), C.byref(out)) == 0
-    assert out.value == 64 + 4 * (600_000_001 + 1000) + flags
+    assert out.value == lf_bytes(600_000_001, 1000, 600_000_001 + 1000)
+    # short lags: no stream ring (sl < 256)
+    assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=97, sl=33)), C.byref(out)) == 0
+    assert out.value == lf_bytes(97, 33, 2 * (97 + 33)) == 1152 + 128 + 2 * 8192 * 32 * 4
     # ring shorter than ll + W (W = 100 after rounding down to a multiple of 4)
     assert R.lib.rngld_state_bytes(C.byref(R.make_cfg("lf", ll=2281, sl=1252, wave=101, ring=2380)),
                                    C.byref(out)) == R.ELAG

@@ -384,6 +384,33 @@ def test_lf_persistent_gaussians(lags, count):
     assert np.array_equal(_u32(nxt), orc.lf_generate(ll, sl, win, 999))
 
 
+@pytest.mark.parametrize("lags", [(132049, 54454), (19937, 10095)])
+def test_lf_pc_gaussian_stream(lags):
+    """Long LF Gaussian streams by the producer/consumer run: the producers extend the sequence in
+    the state's own ring as in the fused LD run, the consumers write Box-Muller pairs of consecutive
+    positions (odd sl included); the positions past the run's 4 n T come from the waves.  Every
+    Gaussian within 1e-5 of the FP64 oracle, the status word stays zero, and the state continues
+    the sequence."""
+    ll, sl = lags
+    count = 2 * 10**7 + 6
+    cfg = _lf_cfg(ll, sl, seed=12)
+    st = R.new_state(cfg)
+    R.rng_init(cfg, st)
+    out = torch.empty(count, dtype=torch.float32, device="cuda")
+    R.rng_gaussian(cfg, st, count, out)
+    assert R.lf_stream_status(st) == 0
+    nxt = torch.empty(999, dtype=torch.int32, device="cuda")
+    R.rng_uniform(cfg, st, 999, nxt)
+    torch.cuda.synchronize()
+    win = orc.lf_seed(12, ll)
+    ref = orc.lf_gaussian(ll, sl, win, count)
+    err = float(np.max(np.abs(out.cpu().numpy().astype(np.float64) - ref)))
+    _say("lf producer/consumer gaussians", lags, "max abs err", err)
+    assert err <= GAUSS_TOL
+    assert np.array_equal(_u32(nxt), orc.lf_generate(ll, sl, win, 999))
+    del out
+
+
 def test_lf_stream_captured_in_a_graph():
     """rng_uniform on the shared sequence captured in a CUDA graph (the persistent launch is not
     used under capture; the waves are recorded): each replay, with eager work in between, yields
