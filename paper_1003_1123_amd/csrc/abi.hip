@@ -558,8 +558,7 @@ int64_t try_lf_pc_gauss(const Gen &g, void *d_state, uint32_t *d_out, uint64_t c
 // The persistent bare-stream run for count values, if it fits: 1 when launched, 0 when the wave
 // path must run, an RNGLD error otherwise.  Needs links long enough to keep the chip busy.
 // gauss: the run also turns out[0, keep_from) into Box-Muller pairs in place (needs an even sl)
-int try_lf_stream(const Gen &g, void *d_state, uint32_t *d_out, uint64_t count, hipStream_t st, bool gauss = false,
-                  uint64_t keep_from = 0) {
+int try_lf_stream(const Gen &g, void *d_state, uint32_t *d_out, uint64_t count, hipStream_t st) {
     if (g.sl < 4096 || count < 4ull * g.sl) return 0;
     if ((count + g.sl - 1) / g.sl >= (1ull << 31)) return 0;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -595,11 +594,9 @@ int try_lf_stream(const Gen &g, void *d_state, uint32_t *d_out, uint64_t count, 
     a.n_slices = static_cast<uint32_t>((static_cast<uint64_t>(g.sl) + (1u << slice_log2) - 1) >> slice_log2);
     a.n_links = static_cast<uint32_t>((count + g.sl - 1) / g.sl);
     a.spin_limit = 1u << 20;
-    a.keep_from = gauss ? keep_from : 0;
     if (a.n_slices + 1 > kLfFlowMaxWaves) return 0;
-    if (gauss && (g.sl % 2 != 0 || keep_from % 2 != 0)) return 0;
     RNGLD_TRY_HIP(launch_fill_u32(flags, static_cast<uint64_t>(a.n_slices + 1) * kLfFlagStride, 0u, st));
-    const hipError_t e = launch_lf_stream(a, static_cast<uint32_t>(cus), m, gauss, st);
+    const hipError_t e = launch_lf_stream(a, static_cast<uint32_t>(cus), m, st);
     if (e == hipErrorCooperativeLaunchTooLarge) {
         (void)hipGetLastError();
         return 0;
@@ -716,27 +713,22 @@ int rng_gaussian(const rngld_cfg *cfg, void *d_state, size_t state_bytes, uint64
         if (count == 0) return RNGLD_OK;
         if (!d_out) return fail(RNGLD_EINVAL, "output pointer is NULL");
         const LfRing L = lf_ring(g, d_state);
-        // long calls: the producer/consumer run (integers in the state's own ring, Gaussian pairs
-        // written once) takes the first 4 n T values; the rest continues from there below
-        const int64_t done = try_lf_pc_gauss(g, d_state, reinterpret_cast<uint32_t *>(d_out), count, st);
+        // long calls: the producer/consumer run (integers in the state's own ring, each Box-Muller
+        // pair written once by the consumers) takes the first 4 n T values; the rest continue from
+        // there
+        uint32_t *words = reinterpret_cast<uint32_t *>(d_out);
+        const int64_t done = try_lf_pc_gauss(g, d_state, words, count, st);
         if (done < 0) return static_cast<int>(done);
         if (static_cast<uint64_t>(done) == count) return RNGLD_OK;
         if (done > 0) return rng_gaussian(cfg, d_state, state_bytes, count - done, d_out + done, out_len - done, stream);
-        // the persistent stream writes the integers into the output, which doubles as the lag
-        // table; with an even sl it also turns them into Gaussian pairs in place once no producer
-        // reads them, except the pairs from keep_from on: the ring takes the last ll integers, then
-        // those pairs are transformed (with an odd sl every pair is transformed after the run)
-        uint32_t *words = reinterpret_cast<uint32_t *>(d_out);
-        const uint64_t m = std::min<uint64_t>(count, g.ll);
-        const uint64_t keep_from = (count - m) & ~1ull;
-        int r = try_lf_stream(g, d_state, words, count, st, true, keep_from);
-        bool fused = r == 1;
-        if (r == 0) r = try_lf_stream(g, d_state, words, count, st);
+        // the persistent stream of integers into the output (the lag table); the ring takes the last
+        // ll of them, then every pair is transformed in place
+        const int r = try_lf_stream(g, d_state, words, count, st);
         if (r < 0) return r;
         if (r == 1) {
+            const uint64_t m = std::min<uint64_t>(count, g.ll);
             RNGLD_TRY_HIP(launch_lf_ring_store(L, words, count, static_cast<uint32_t>((count - m) % g.R), st));
-            const uint64_t from = fused ? keep_from : 0;
-            RNGLD_TRY_HIP(launch_box_muller_inplace(words + from, (count - from) / 2, st));
+            RNGLD_TRY_HIP(launch_box_muller_inplace(words, count / 2, st));
         } else {
             for (uint64_t first = 0; first < count; first += g.W)
                 RNGLD_TRY_HIP(launch_lf_gauss_phase(L, d_out, first, static_cast<uint32_t>(first % g.R),

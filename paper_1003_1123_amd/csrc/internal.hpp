@@ -106,7 +106,8 @@ struct LfFlowArgs {
 // Box-Muller pairs to out
 constexpr int kFlowLd = 0, kFlowGauss = 1;
 
-// persistent bare stream (rng_uniform): out[0, count) = the next count values of the sequence
+// persistent bare stream: out[0, count) = the next count values of the sequence, out doubling as
+// the lag table
 struct LfStreamArgs {
     LfRing L;              // the state's ring: the ll values before the call (read only)
     LfFlowGeom geom;       // sl, slice_log2 and Ptot = count are used
@@ -117,14 +118,11 @@ struct LfStreamArgs {
     uint32_t n_slices, n_links;
     uint32_t spin_limit;
     uint32_t pad;
-    uint64_t keep_from;    // Gaussian run: out[P] for P < keep_from (even) is turned into Box-Muller
-                           // pairs in place once no producer still reads it; the rest stays integer
 };
 // progress words the LAGFIB state reserves after its ring for the bare-stream runs (bytes): the
 // status line, then one line per producer and one per consumer
 constexpr size_t kLfStreamFlagBytes = 128 + 2 * static_cast<size_t>(8192) * 32 * sizeof(uint32_t);
-// gauss: also turn out[0, keep_from) into Gaussians in place (needs an even sl)
-hipError_t launch_lf_stream(const LfStreamArgs &a, uint32_t grid, uint32_t m, bool gauss, hipStream_t st);
+hipError_t launch_lf_stream(const LfStreamArgs &a, uint32_t grid, uint32_t m, hipStream_t st);
 
 // ---- adjoint (k_adj.hip) ---------------------------------------------------------------------------
 struct AdjCoef {

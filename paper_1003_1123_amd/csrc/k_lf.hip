@@ -984,14 +984,13 @@ __device__ __forceinline__ bool stream_wait(FlowWaits &w, uint32_t lane, const L
 // as only those can still be outstanding (vector memory operations complete in issue order, and a
 // store counts until it has completed); otherwise link j is published first, then the producer blocks
 // on link j+1's waits.
-// Gaussian runs (GAUSS, even sl): a producer also turns its own slice of link j - (lla + 2) into
-// Box-Muller pairs in place after link j, once every producer that reads those values as long-lag
-// sources (positions + ll, in links j' + lla and j' + lla + 1 <= j - 1) has published that link; the
-// poll for the next conversion is issued one link ahead.  A lane's four words hold two whole pairs (links
-// start at even positions).  Positions from keep_from on stay integers: the host copies the last ll
-// of them into the state's ring and converts them afterwards.
+// (A Gaussian variant that kept the integers in a ring and wrote each pair to the output from the
+// producers ran at 2.8e11 values/s against the uint32 stream's 5e11: the output stores complete in
+// issue order with the ring stores, so every link's publication waited for the previous link's
+// output writes.  Long Gaussian streams take the producer/consumer run instead, whose consumers
+// write the pairs.)
 
-template <int M, bool GAUSS>
+template <int M>
 __global__ __launch_bounds__(kLfFlowBlock) void lf_stream_kernel(LfStreamArgs a) {
     static_assert(M % 4 == 0, "groups of four words");
     constexpr int G = M / 4;
@@ -1020,7 +1019,7 @@ __global__ __launch_bounds__(kLfFlowBlock) void lf_stream_kernel(LfStreamArgs a)
         return n0 >= count ? 0u : (count - n0 < width ? static_cast<uint32_t>(count - n0) : width);
     };
     auto q_of = [&](int gi, int r) -> uint32_t { return 4u * (lane + 64u * gi) + r; };
-    u32x4 chain[G], src[G], nxt[G];
+    u32x4 chain[G], src[G];
 #pragma unroll
     for (int gi = 0; gi < G; ++gi)
 #pragma unroll
@@ -1075,73 +1074,6 @@ __global__ __launch_bounds__(kLfFlowBlock) void lf_stream_kernel(LfStreamArgs a)
             }
         }
     };
-    // ---- in-place conversion (GAUSS) ----
-    FlowWaits cw;
-    cw.n = 0;
-    uint32_t cseen = 0;
-    // the readers of link jc's slice: producers of the offsets [x0, x1) + llb of links jc + lla and
-    // jc + lla + 1 that exist in this call
-    auto collect_readers = [&](uint32_t jc) {
-        cw.n = 0;
-        const uint32_t lenc = link_len(jc);
-        if (!lenc) return;
-        auto part = [&](uint32_t L, uint32_t x0, uint32_t x1) {
-            if (x0 >= x1 || L >= a.n_links) return;
-            for (uint32_t sidx = x0 / T; sidx <= (x1 - 1) / T; ++sidx)
-                if (static_cast<uint64_t>(L) * sl + static_cast<uint64_t>(sidx) * T < count)
-                    wait_add(cw, lane, a.prod + sidx * kLfFlagStride, L + 1, 0);
-        };
-        const uint32_t r0 = o_lo + a.llb, r1 = o_lo + lenc + a.llb;  // below 2 sl
-        part(jc + a.lla, r0 < sl ? r0 : sl, r1 < sl ? r1 : sl);
-        if (r1 > sl) part(jc + a.lla + 1, r0 > sl ? r0 - sl : 0u, r1 - sl);
-    };
-    auto cpoll = [&](uint32_t jc) {
-        collect_readers(jc);
-        cseen = agent_load(lane < cw.n ? cw.flag : a.status);
-    };
-    // the conversion of link jc is split in two, one link apart: start loads the slice's whole
-    // four-word groups below keep_from (the integers are final: this producer stored them and saw
-    // the stores complete), finish waits for the readers and stores the pairs (the few partial
-    // groups are read and converted word-pair by word-pair there)
-    u32x4 cv[G];
-    auto full_group = [&](uint32_t jc, uint32_t lenc, uint32_t q0) {
-        return q0 + 4u <= lenc && static_cast<uint64_t>(jc) * sl + o_lo + q0 + 4u <= a.keep_from;
-    };
-    auto start_convert = [&](uint32_t jc) {
-        const uint32_t lenc = link_len(jc);
-        const __amdgpu_buffer_rsrc_t rs = ring_rsrc(out + static_cast<uint64_t>(jc) * sl + o_lo, lenc);
-#pragma unroll
-        for (int gi = 0; gi < G; ++gi) cv[gi] = ring_get4(rs, 4u * (lane + 64u * gi));  // past lenc: zeros
-        cpoll(jc);
-    };
-    auto finish_convert = [&](uint32_t jc) -> bool {
-        if (!__all(lane >= cw.n || cseen >= cw.need) && !stream_wait(cw, lane, a)) return false;
-        const uint32_t lenc = link_len(jc);
-        uint32_t *dst = out + static_cast<uint64_t>(jc) * sl + o_lo;
-        const uint64_t n0 = static_cast<uint64_t>(jc) * sl + o_lo;
-        const __amdgpu_buffer_rsrc_t rs = ring_rsrc(dst, lenc);
-#pragma unroll
-        for (int gi = 0; gi < G; ++gi) {
-            const uint32_t q0 = 4u * (lane + 64u * gi);
-            if (full_group(jc, lenc, q0)) {
-                ring_put4(rs, q0, box_muller_pairs4(cv[gi]));
-            } else {
-#pragma unroll
-                for (int r = 0; r < 4; r += 2)
-                    if (q0 + r + 1 < lenc && n0 + q0 + r + 1 < a.keep_from) {
-                        const uint32_t w0 = agent_load(dst + q0 + r), w1 = agent_load(dst + q0 + r + 1);
-                        float c, sn;
-                        const float rad = box_muller_radius(w0);
-                        box_muller_angle(w1, c, sn);
-                        agent_store(dst + q0 + r, __float_as_uint(rad * c));
-                        agent_store(dst + q0 + r + 1, __float_as_uint(rad * sn));
-                    }
-            }
-        }
-        return true;
-    };
-    uint32_t conv_next = 0;  // the next link of the slice to convert
-    bool pending = false;    // link conv_next - 1's conversion started and not finished
     uint32_t len = link_len(0);
     if (len == 0) return;
     collect(0, len);
@@ -1185,42 +1117,16 @@ __global__ __launch_bounds__(kLfFlowBlock) void lf_stream_kernel(LfStreamArgs a)
                 asm volatile("s_waitcnt vmcnt(%0)" ::"n"(M + 1) : "memory");
             if (lane == 0) agent_store(a.prod + p * kLfFlagStride, j + 1);
         }
-        if constexpr (GAUSS) {
-            // while link j+1's loads are in flight: finish the conversion started one link ago, then
-            // start that of link j + 1 - delay; its readers are in links up to j - 1 - (delay -
-            // lla - 3) = j - 1 for delay = lla + 3, published by producers that never wait for this
-            // one's conversions
-            const uint32_t delay = a.lla + 3u;
-            if (pending) {
-                if (!finish_convert(conv_next - 1)) return;
-                pending = false;
-            }
-            if (j + 1 >= delay && conv_next == j + 1 - delay && link_len(conv_next)) {
-                start_convert(conv_next);
-                ++conv_next;
-                pending = true;
-            }
-        }
         len = next_len;
-    }
-    if constexpr (GAUSS) {
-        // the conversion in flight, then the remaining links, each once its readers have published
-        if (pending && !finish_convert(conv_next - 1)) return;
-        for (; conv_next < a.n_links && link_len(conv_next); ++conv_next) {
-            start_convert(conv_next);
-            if (!finish_convert(conv_next)) return;
-        }
     }
 }
 
 }  // namespace
 
-hipError_t launch_lf_stream(const LfStreamArgs &a, uint32_t grid, uint32_t m, bool gauss, hipStream_t st) {
+hipError_t launch_lf_stream(const LfStreamArgs &a, uint32_t grid, uint32_t m, hipStream_t st) {
     const void *fn = nullptr;
-    if (m == 4) fn = gauss ? reinterpret_cast<const void *>(&lf_stream_kernel<4, true>)
-                           : reinterpret_cast<const void *>(&lf_stream_kernel<4, false>);
-    else if (m == 16) fn = gauss ? reinterpret_cast<const void *>(&lf_stream_kernel<16, true>)
-                                 : reinterpret_cast<const void *>(&lf_stream_kernel<16, false>);
+    if (m == 4) fn = reinterpret_cast<const void *>(&lf_stream_kernel<4>);
+    else if (m == 16) fn = reinterpret_cast<const void *>(&lf_stream_kernel<16>);
     else return hipErrorInvalidValue;
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kLfFlowBlock, 0);

@@ -362,10 +362,11 @@ def test_lf_persistent_stream_matches_recurrence(lags, count):
 @pytest.mark.parametrize("lags,count", [((9689, 5502), 4 * 5502 + 10), ((132049, 54454), 3 * 10**6 + 18),
                                         ((3021377, 1010202), 4 * 1010202 + 2), ((19937, 10095), 4 * 10095 + 6)])
 def test_lf_persistent_gaussians(lags, count):
-    """Long LF Gaussian streams by the persistent launch: integers into the output, turned into
-    Box-Muller pairs in place during the run once no producer reads them (even sl; the last ll
-    values after the run), or all after the run (odd sl, the last case); every Gaussian within 1e-5
-    of the FP64 oracle, the run's status word stays zero, and the state continues the sequence."""
+    """LF Gaussian streams of a few links by the persistent uint32 launch: the integers go into the
+    output (the lag table), the state's ring takes the last ll of them, and every pair is
+    transformed after the run (the third case also starts with the producer/consumer run, whose
+    4 n T values leave the rest to this path).  Every Gaussian within 1e-5 of the FP64 oracle, the
+    run's status word stays zero, and the state continues the sequence."""
     ll, sl = lags
     cfg = _lf_cfg(ll, sl, seed=8)
     st = R.new_state(cfg)
@@ -385,10 +386,10 @@ def test_lf_persistent_gaussians(lags, count):
 
 
 @pytest.mark.parametrize("lags", [(132049, 54454), (19937, 10095)])
-def test_lf_pc_gaussian_stream(lags):
-    """Long LF Gaussian streams by the producer/consumer run: the producers extend the sequence in
-    the state's own ring as in the fused LD run, the consumers write Box-Muller pairs of consecutive
-    positions (odd sl included); the positions past the run's 4 n T come from the waves.  Every
+def test_lf_long_gaussian_streams(lags):
+    """20 million LF Gaussians by the producer/consumer run (the producers extend the sequence in
+    the state's own ring as in the fused LD run, the consumers write the Box-Muller pairs of
+    consecutive positions, odd sl included) and the waves for the positions past its 4 n T.  Every
     Gaussian within 1e-5 of the FP64 oracle, the status word stays zero, and the state continues
     the sequence."""
     ll, sl = lags
