@@ -100,16 +100,18 @@ HBM_PEAK_GBS = 8000.0
 # loads per store, over a 32 MB region, stores 256-byte aligned and loads 13 words off (as the run's
 # long-lag reads), from the wide-access measurement (profiles/wide_access.md, mode 4).
 LF_MEASURED_PEAK_GBS = 8130.0
-# HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch) at the config-2
-# workload, scaled by what the same counters read for a plain 1 GiB device copy (FETCH_SIZE 0.5 GiB:
-# factor 2; WRITE_SIZE 1 GiB: factor 1).  Valid only for the machine code they were taken on: the
-# SHA-256 of the gfx950 assembly of the kernel's 8-tile instantiation (the one this workload runs),
-# which the build records in kernel_isa.json; otherwise the traffic is reported as null.
+# Bytes past the L2 per launch (to the memory-side cache or HBM: the DRAM-destined request counters
+# TCC_EA0_RDREQ_DRAM / TCC_EA0_WRREQ_DRAM count the same requests, and no counter here separates
+# the memory-side cache's hits) from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch) at the
+# config-2 workload, scaled by what the same counters read for a plain 1 GiB device copy
+# (FETCH_SIZE 0.5 GiB: factor 2; WRITE_SIZE 1 GiB: factor 1).  Valid only for the machine code they
+# were taken on: the SHA-256 of the gfx950 assembly of the kernel's 8-tile LD instantiation (the one
+# this workload runs), which the build records in kernel_isa.json; otherwise the traffic is null.
 COUNTER_TRAFFIC = {
     "lf_pc_kernel": {
-        "isa_sha256": "7abbdbbbb4800e4893ac8e59edd9a0011f7616a8ed097ca6c080ced69b677755",
-        # FETCH_SIZE 160337301.9375 KiB x (2^20 / 524308.75), WRITE_SIZE 158418602.0625 KiB x (2^20 / 1048576)
-        "fetch_bytes": 328357798792, "write_bytes": 162220648512,
+        "isa_sha256": "25a307333814a2731e5c60e7c4b706f3aef40a24cd6afbd8aa5f9d0e5bb2c2c2",
+        # FETCH_SIZE 160394855.0625 KiB x (2^20 / 524308.1875), WRITE_SIZE 158418655.1875 KiB x (2^20 / 1048576)
+        "fetch_bytes": 328476015330, "write_bytes": 162220702912,
     },
 }
 
@@ -631,7 +633,8 @@ def extra_config5(R, W, torch):
                "forward_autograd_ms": fwd_ag, "backward_autograd_ms": bwd_ag,
                "forward_osc_steps_per_s": osc / (fwd_ms / 1e3),
                "roofline_forward": valu_entry("ld_fwd_seg_kernel (+ tables and join)",
-                                              windowed_valu("adjoint_forward", T, c5["t_begin"], c5["t_end"]), osc, fwd_ms / 1e3)}
+                                              windowed_valu("adjoint_forward", T, c5["t_begin"], c5["t_end"]), osc,
+                                              fwd_ms / 1e3)}
         if not replay:
             res["roofline_backward"] = valu_entry("ld_adjoint_seg_kernel + sum",
                                                   windowed_valu("adjoint_backward", T, c5["t_begin"], c5["t_end"]),
