@@ -362,11 +362,11 @@ def test_lf_persistent_stream_matches_recurrence(lags, count):
 @pytest.mark.parametrize("lags,count", [((9689, 5502), 4 * 5502 + 10), ((132049, 54454), 3 * 10**6 + 18),
                                         ((3021377, 1010202), 4 * 1010202 + 2), ((19937, 10095), 4 * 10095 + 6)])
 def test_lf_persistent_gaussians(lags, count):
-    """LF Gaussian streams of a few links by the persistent uint32 launch: the integers go into the
-    output (the lag table), the state's ring takes the last ll of them, and every pair is
-    transformed after the run (the third case also starts with the producer/consumer run, whose
-    4 n T values leave the rest to this path).  Every Gaussian within 1e-5 of the FP64 oracle, the
-    run's status word stays zero, and the state continues the sequence."""
+    """LF Gaussian streams of a few links: by the persistent uint32 launch (the integers go into the
+    output, the lag table; the state's ring takes the last ll of them; every pair is transformed
+    after the run), except the third case, whose first 4 n T values come from the producer/consumer
+    run and the rest from the waves.  Every Gaussian within 1e-5 of the FP64 oracle, the run's status
+    word stays zero, and the state continues the sequence."""
     ll, sl = lags
     cfg = _lf_cfg(ll, sl, seed=8)
     st = R.new_state(cfg)
