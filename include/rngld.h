@@ -330,8 +330,8 @@ typedef struct ld_loss {
  * float x[3][n_total], float v[3][n_total], then the generator state in the layout above with
  * S = n_total; for Hybrid Taus then float lam_x[3][n_total], lam_v[3][n_total]: the gradient of the
  * sum of x^2 over the loss window's steps after the record with respect to the record's x and v
- * (the loss adjoint the backward sweep of the segment ending there starts from), written by
- * ld_run_ckpt for ensembles that can take the register-only backward. */
+ * (the loss adjoint the register-only backward of the segment starting there starts from),
+ * written by ld_run_ckpt for ensembles that can take the register-only backward. */
 RNGLD_API int ld_ckpt_bytes(const rngld_cfg *cfg, uint64_t n_total, uint32_t n_steps, uint32_t K, size_t *bytes);
 RNGLD_API int ld_adjoint_workspace_bytes(const rngld_cfg *cfg, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total,
                                uint32_t n_steps, const ld_loss *loss, size_t *bytes);
@@ -356,21 +356,22 @@ RNGLD_API int ld_run_ckpt(const rngld_cfg *cfg, void *d_state, size_t state_byte
  * gradient is (the oscillators are independent, so this is the sampling error of the gradient
  * as an estimate of d E[L] / d theta).
  * Two paths, chosen per ensemble:
- *  - register-only (Hybrid Taus): each K-step segment is swept backward from the checkpoint at
- *    its end, running the generator backward with the inverse Tausworthe and LCG steps and the
- *    integrator backward (x = x' - dt v', v = (v' + (k dt/m) x - sig g) / (1 - gamma dt)).  Used
- *    when rounding errors cannot grow by more than 8 over K inverse steps (max over j <= K of the
- *    Frobenius norm of the inverse step matrix to the power j, for the ensemble's FP32
- *    coefficients), e.g. gamma dt <= 0.02 at K = 100 and dt = 0.01.  The segments of an
- *    oscillator are swept concurrently, each from the loss adjoint that ld_run_ckpt left in the
- *    checkpoint at its end (the reverse recursion is linear with a constant step matrix, so the
- *    forward run can form it), and a workspace record of 24 bytes per oscillator and segment
+ *  - register-only (Hybrid Taus): each K-step segment runs forward from the checkpoint at its
+ *    start, with the generator, Box-Muller and update steps of the forward run, starting from the
+ *    loss adjoint that ld_run_ckpt left in that checkpoint (the reverse recursion is linear with
+ *    a constant step matrix, so the forward run can form it) and carrying the adjoint forward
+ *    through the inverse of the reverse step (mu = lam_v / (1 - gamma dt), lam_x' = lam_x +
+ *    (k dt/m) mu, lam_v' = mu - dt lam_x', less each step's own loss term).  Used when rounding
+ *    errors cannot grow by more than 8 over K such steps (max over j <= K of the Frobenius norm
+ *    of the inverse step matrix to the power j, for the ensemble's FP32 coefficients), e.g.
+ *    gamma dt <= 0.02 at K = 100 and dt = 0.01.  The segments of an oscillator run concurrently
+ *    and store nothing per step; a workspace record of 24 bytes per oscillator and segment
  *    collects each segment's share of the gradient.
  *  - replay: each segment is rerun forward from the checkpoint at its start into a scratch of
  *    9 floats per oscillator-step and swept backward from there (Ran2; Hybrid Taus otherwise or
  *    with RNGLD_ADJ_REPLAY).
  * ld_adjoint_workspace_bytes is the workspace of both ld_run_ckpt and ld_run_backward (one buffer
- * serves both: the segment-parallel forward's 76 bytes per oscillator and segment and the
+ * serves both: the segment-parallel forward's 52 bytes per oscillator and segment and the
  * backward's scratch share their space).  It includes each path's scratch only when some ensemble
  * takes it, so it depends on the ensembles' parameters and the flags.
  */

@@ -1246,20 +1246,19 @@ struct AdjLayout {
     std::vector<EnsDev> ens;
     std::vector<AdjCoef> adj;
     uint32_t n_tiles = 0;
-    bool any_replay = false, any_inverse = false, any_sp = false, any_seq = false;
+    bool any_replay = false, any_reg_only = false, any_sp = false, any_seq = false;
     size_t off_ens = 0, off_adj = 0, off_partials = 0, off_jump = 0, off_coef = 0, off_scratch = 0, off_seg_d = 0,
            bytes = 0;
 };
 
 // The segment-parallel forward's per-ensemble constants, in FP64 from the FP32 coefficients:
-// F^K, F^len of the last segment, B^K, and the seven window sums of a whole segment (each term from
-// the FP32 values of a_j, b_j, alpha_j, beta_j, as the kernels' table holds them).
+// F^K, F^len of the last segment, B^K = (F^K)^T, and the three window sums of a whole segment
+// (each term from the FP32 values of a_j, b_j, as the kernels' table holds them).
 void segment_constants(AdjCoef &A, uint32_t K, uint32_t len_last) {
     const double h = A.f.h, c = A.f.c, kap = A.f.kap;
     const double F[4] = {1.0 - h * kap, h * c, -kap, c};
-    const double B[4] = {1.0 - kap * h, -kap, c * h, c};
-    double pf[4] = {1, 0, 0, 1}, pb[4] = {1, 0, 0, 1};
-    for (int k = 0; k < 7; ++k) A.full[k] = 0.0;
+    double pf[4] = {1, 0, 0, 1};
+    for (int k = 0; k < 3; ++k) A.full[k] = 0.0;
     auto mul = [](const double *p, const double *q, double *out) {
         const double r0 = p[0] * q[0] + p[1] * q[2], r1 = p[0] * q[1] + p[1] * q[3];
         const double r2 = p[2] * q[0] + p[3] * q[2], r3 = p[2] * q[1] + p[3] * q[3];
@@ -1267,15 +1266,13 @@ void segment_constants(AdjCoef &A, uint32_t K, uint32_t len_last) {
     };
     for (uint32_t j = 1; j <= K; ++j) {
         mul(pf, F, pf);
-        mul(pb, B, pb);
         const double ca = static_cast<float>(pf[0]), cb = static_cast<float>(pf[1]);
-        const double cl = static_cast<float>(pb[0]), ce = static_cast<float>(pb[2]);
         A.full[0] += ca * ca, A.full[1] += ca * cb, A.full[2] += cb * cb;
-        A.full[3] += cl * ca, A.full[4] += cl * cb, A.full[5] += ce * ca, A.full[6] += ce * cb;
         if (j == len_last)
             for (int k = 0; k < 4; ++k) A.flast[k] = pf[k];
     }
-    for (int k = 0; k < 4; ++k) A.fk[k] = pf[k], A.bk[k] = pb[k];
+    for (int k = 0; k < 4; ++k) A.fk[k] = pf[k];
+    A.bk[0] = pf[0], A.bk[1] = pf[2], A.bk[2] = pf[1], A.bk[3] = pf[3];
 }
 
 // longest segment the segment-parallel forward takes (its coefficient table has K entries per
@@ -1302,10 +1299,11 @@ void adjoint_propagator(const LdCoef &q, uint32_t K, float phi[4]) {
     phi[3] = static_cast<float>(c2v);
 }
 
-// Largest growth of a perturbation of (x, v) over 1..K backward steps of the underdamped
-// integrator with these FP32 coefficients: max_j |M^j|_F, M the inverse of the step matrix
-// A = [[1 - h kap, h c], [-kap, c]] acting on (x, v) (v' = c v - kap x, x' = x + h v').
-// Returns as soon as the growth exceeds `limit`.
+// Largest growth of a perturbation over 1..K inverse steps of the underdamped integrator with
+// these FP32 coefficients: max_j |M^j|_F, M the inverse of the step matrix A = [[1 - h kap, h c],
+// [-kap, c]] acting on (x, v) (v' = c v - kap x, x' = x + h v').  The register-only backward
+// carries the loss adjoint forward in time through a segment with B^-1 = M^T (the adjoint step is
+// B = A^T), whose powers have the same norms.  Returns as soon as the growth exceeds `limit`.
 double reverse_growth(const LdCoef &q, uint32_t K, double limit) {
     const double c = q.c, kap = q.kap, h = q.h;
     if (!(c > 0.0)) return HUGE_VAL;
@@ -1324,7 +1322,7 @@ double reverse_growth(const LdCoef &q, uint32_t K, double limit) {
 }
 
 constexpr double kAdjGrowthLimit = 8.0;
-constexpr uint32_t kAdjInverseMaxK = 1u << 22;
+constexpr uint32_t kAdjLamMaxK = 1u << 22;
 
 int layout_adj(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t n_total, uint32_t n_steps,
                const ld_loss &loss, AdjLayout *L) {
@@ -1353,15 +1351,15 @@ int layout_adj(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t 
         A.inv_c_lo = static_cast<float>(1.0 / static_cast<double>(A.f.c) - static_cast<double>(A.inv_c));
         // the register-only backward launches one block row per segment (grid y below 2^16)
         const uint64_t nseg = (static_cast<uint64_t>(n_steps) + K - 1) / K;
-        A.lam = g.kind == RNGLD_HYBRID_TAUS && K <= kAdjInverseMaxK && nseg < 65536 &&
+        A.lam = g.kind == RNGLD_HYBRID_TAUS && K <= kAdjLamMaxK && nseg < 65536 &&
                 reverse_growth(A.f, K, kAdjGrowthLimit) <= kAdjGrowthLimit;
-        A.inverse = A.lam && !(loss.flags & RNGLD_ADJ_REPLAY);
+        A.reg_only = A.lam && !(loss.flags & RNGLD_ADJ_REPLAY);
         A.sp = A.lam && K <= kSpMaxK && nseg >= kSpMinSegments;
         if (A.lam) adjoint_propagator(A.f, K, A.phi);
         if (A.sp) segment_constants(A, K, static_cast<uint32_t>(n_steps - (nseg - 1) * K));
         if (E.n) {
-            L->any_inverse |= A.inverse != 0;
-            L->any_replay |= A.inverse == 0;
+            L->any_reg_only |= A.reg_only != 0;
+            L->any_replay |= A.reg_only == 0;
             L->any_sp |= A.sp != 0;
             L->any_seq |= A.sp == 0;
         }
@@ -1374,13 +1372,13 @@ int layout_adj(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t 
     const uint64_t nseg = (static_cast<uint64_t>(n_steps) + K - 1) / K;
     L->off_jump = align_up(L->off_partials + kAdjPartW * sizeof(double) * std::max<uint32_t>(L->n_tiles, 1));
     L->off_coef = align_up(L->off_jump + (L->any_sp ? nseg * kJumpWords * sizeof(uint32_t) : 0));
-    L->off_scratch = align_up(L->off_coef + (L->any_sp ? static_cast<uint64_t>(n_ens) * K * sizeof(float4) : 0));
+    L->off_scratch = align_up(L->off_coef + (L->any_sp ? static_cast<uint64_t>(n_ens) * K * sizeof(float2) : 0));
     // the forward's segment records and the backward's scratch share the space after off_scratch;
     // both calls take the larger size, so one workspace serves both
     const size_t fwd = L->any_sp ? align_up(nseg * kFwdSegF * n_total * sizeof(float)) : 0;
     size_t bwd = L->any_replay ? align_up(9ull * K * n_total * sizeof(float)) : 0;
     L->off_seg_d = L->off_scratch + bwd;
-    if (L->any_inverse) bwd += align_up(nseg * kAdjSegD * n_total * sizeof(double));
+    if (L->any_reg_only) bwd += align_up(nseg * kAdjSegD * n_total * sizeof(double));
     L->bytes = L->off_scratch + std::max(fwd, bwd);
     return RNGLD_OK;
 }
@@ -1467,7 +1465,7 @@ extern "C" int ld_run_ckpt(const rngld_cfg *cfg, void *d_state, size_t state_byt
     a.rec_bytes = ckpt_record_bytes(g, n_total);
     a.partials = reinterpret_cast<double *>(ws + L.off_partials);
     a.jump = reinterpret_cast<uint32_t *>(ws + L.off_jump);
-    a.coef = reinterpret_cast<float4 *>(ws + L.off_coef);
+    a.coef = reinterpret_cast<float2 *>(ws + L.off_coef);
     a.fwd_seg = reinterpret_cast<float *>(ws + L.off_scratch);
     RNGLD_TRY_HIP(launch_ld_ckpt(g.kind, a, L.any_sp, L.any_seq, st));
     RNGLD_TRY_HIP(launch_adj_finalize(a.partials, L.n_tiles, 1, false, a.ens, n_ens,
@@ -1504,10 +1502,10 @@ extern "C" int ld_run_backward(const rngld_cfg *cfg, const void *d_ckpt, size_t 
     a.ckpt = const_cast<uint8_t *>(static_cast<const uint8_t *>(d_ckpt));
     a.rec_bytes = ckpt_record_bytes(g, n_total);
     a.scratch = L.any_replay ? reinterpret_cast<float *>(ws + L.off_scratch) : nullptr;
-    a.seg_d = L.any_inverse ? reinterpret_cast<double *>(ws + L.off_seg_d) : nullptr;
+    a.seg_d = L.any_reg_only ? reinterpret_cast<double *>(ws + L.off_seg_d) : nullptr;
     a.partials = reinterpret_cast<double *>(ws + L.off_partials);
     // n_steps >= 1 (check_loss); every tile's partials are written by exactly one of the kernels
-    RNGLD_TRY_HIP(launch_ld_adjoint(g.kind, a, L.any_replay, L.any_inverse, st));
+    RNGLD_TRY_HIP(launch_ld_adjoint(g.kind, a, L.any_replay, L.any_reg_only, st));
     RNGLD_TRY_HIP(launch_adj_finalize(a.partials, L.n_tiles, 3, (loss->flags & RNGLD_ADJ_SPREAD) != 0, a.ens, n_ens,
                                       static_cast<double>(loss->t_end - loss->t_begin + 1), d_grad, st));
     return RNGLD_OK;

@@ -66,26 +66,6 @@ struct HybridTaus {
         step();
         return xor4_top24(t1, t2, t3, lcg);
     }
-    // the output of the current state, then one step back: repeated calls return the outputs of
-    // the preceding next() calls in reverse order, all of them exactly; only the seeded state
-    // itself comes back with different bits below each component's top K
-    __device__ __forceinline__ void step_back() {
-        t1 = tausworthe_inv<13, 12, 31>(t1);
-        t2 = tausworthe_inv<2, 4, 29>(t2);
-        t3 = tausworthe_inv<3, 17, 28>(t3);
-        lcg = lcg_prev(lcg);
-    }
-    __device__ __forceinline__ uint32_t prev() {
-        const uint32_t w = xor4(t1, t2, t3, lcg);
-        step_back();
-        return w;
-    }
-    // prev() with the word's low 8 bits cleared
-    __device__ __forceinline__ uint32_t prev_top24() {
-        const uint32_t w = xor4_top24(t1, t2, t3, lcg);
-        step_back();
-        return w;
-    }
     // state rows: uint32 [4][S]
     __device__ __forceinline__ void load(const uint32_t *st, uint64_t S, uint64_t j) {
         t1 = st[j];

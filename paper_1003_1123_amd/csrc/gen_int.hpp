@@ -1,8 +1,7 @@
-// gen_int.hpp -- the integer steps of the per-thread generators, forward and inverse.
+// gen_int.hpp -- the integer steps of the per-thread generators.
 //
 // LCG of Eq. 1 with m = 2^32 (Sec. II.B), and the Tausworthe components of Hybrid Taus (Sec. II.D,
-// Eq. 2 in L'Ecuyer's shift form; Appendix A Alg. 1).  The inverse steps let a reverse sweep
-// regenerate a path's noise backwards from its end state instead of storing it.
+// Eq. 2 in L'Ecuyer's shift form; Appendix A Alg. 1).
 //
 // Plain C++, so that a CPU test can use it as well as the kernels.
 #pragma once
@@ -21,18 +20,7 @@ namespace rngld {
 constexpr uint32_t kLcgMul = 1664525u;
 constexpr uint32_t kLcgAdd = 1013904223u;
 
-// inverse of an odd a modulo 2^32 by Newton's iteration inv <- inv (2 - a inv): each step doubles
-// the number of correct low bits, starting from a * a = 1 mod 8
-constexpr uint32_t odd_inverse_u32(uint32_t a) {
-    uint32_t inv = a;
-    for (int i = 0; i < 5; ++i) inv *= 2u - a * inv;
-    return inv;
-}
-constexpr uint32_t kLcgMulInv = odd_inverse_u32(kLcgMul);
-static_assert(kLcgMul * kLcgMulInv == 1u, "a must be invertible modulo 2^32");
-
 RNGLD_HDI uint32_t lcg_next(uint32_t x) { return kLcgMul * x + kLcgAdd; }
-RNGLD_HDI uint32_t lcg_prev(uint32_t x) { return kLcgMulInv * (x - kLcgAdd); }
 
 // x advanced by n steps: the affine map x -> a x + c composed with itself by binary powering
 // (a - 1 is even, so the geometric-sum closed form cannot use a modular inverse).
@@ -60,15 +48,6 @@ RNGLD_HDI uint32_t funnel_shift_right(uint32_t hi, uint32_t lo, uint32_t s) {
 #endif
 }
 
-// a xor b xor c (one three-input bit operation on gfx950)
-RNGLD_HDI uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
-#else
-    return a ^ b ^ c;
-#endif
-}
-
 // ---- Tausworthe component for the trinomial x^K + x^Q + 1 with step S (Eq. 2) ---------------------
 // The state occupies the top K bits; the low 32-K bits are dropped before the left shift.
 //
@@ -86,36 +65,6 @@ template <int Q, int S, int K>
 RNGLD_HDI uint32_t tausworthe(uint32_t z) {
     static_assert(0 < S && S < K && K < 32 && 0 < Q, "component parameters");
     return funnel_shift_right(z >> (32 - K), (z << Q) ^ z, K - S);
-}
-
-// The inverse step on a produced word w = (y_{n} .. y_{n+31}): the previous word is
-// (y_{n-S} .. y_{n+31-S}), i.e. w >> S with the S older bits on top.  Each older bit follows from
-// the recurrence solved for its oldest term, y_j = y_{j+K} xor y_{j+Q}.  The y_{j+K} all lie in w;
-// y_{j+Q} lies in w >> S unless it is itself one of the S new bits (Q < S), so the top bits t
-// satisfy t = c xor (t << Q) on the top S bits, solved by t = sum of c << kQ over kQ < S.
-// Computed with t in the low S bits of a word: there c = (w >> (32 - K)) xor (w >> (32 - Q)), the
-// sum is built by tripling and doubling its number of terms (t xor t << m xor t << 2m is one
-// three-input op), bits at and above S are junk that only moves up, and one funnel shift puts the
-// S bits on top of w >> S.
-// Exact for any word that tausworthe() produced from another produced word.
-// t holds the sum of c << kQ for k < HAVE; returns it for all kQ < S (resolved at compile time)
-template <int Q, int S, int HAVE>
-RNGLD_HDI uint32_t tausworthe_inv_terms(uint32_t t) {
-    constexpr int kTerms = (S + Q - 1) / Q;
-    constexpr int kShift = HAVE * Q;
-    if constexpr (HAVE >= kTerms)
-        return t;
-    else if constexpr (2 * HAVE >= kTerms || 2 * kShift >= 32)
-        return tausworthe_inv_terms<Q, S, 2 * HAVE>(t ^ (t << kShift));
-    else
-        return tausworthe_inv_terms<Q, S, 3 * HAVE>(xor3(t, t << kShift, t << (2 * kShift)));
-}
-
-template <int Q, int S, int K>
-RNGLD_HDI uint32_t tausworthe_inv(uint32_t w) {
-    static_assert(0 < S && S < K && K < 32 && 0 < Q && Q < 32, "component parameters");
-    const uint32_t c = (w >> (32 - K)) ^ (w >> (32 - Q));
-    return funnel_shift_right(tausworthe_inv_terms<Q, S, 1>(c), w, S);
 }
 
 // A x mod M for M = 2^31 - C and 0 <= x < M (the multiplicative steps of Ran2's two generators):

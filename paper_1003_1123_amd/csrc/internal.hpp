@@ -131,17 +131,17 @@ struct AdjCoef {
     float dc_dgamma;  // -h
     float dsig_dgamma;
     float dsig_dkT;
-    float inv_c;       // 1 / c = inv_c + inv_c_lo, for the backward step of the register-only path:
-                       // the pair keeps the reconstructed velocity free of the systematic bias that
-                       // a rounded reciprocal would compound over a segment's inverse steps
-    uint32_t inverse;  // 1: register-only backward for this ensemble, 0: replay
+    float inv_c;       // 1 / c = inv_c + inv_c_lo, for the register-only backward's mu = lam_v / c:
+                       // the pair keeps the carried adjoint free of the systematic bias that a
+                       // rounded reciprocal would compound over a segment's steps
+    uint32_t reg_only;  // 1: register-only backward for this ensemble, 0: replay
     float inv_c_lo;
     // adjoint propagator over one whole K-step segment with no loss term: the adjoint (lam_x,
     // lam_v) of the state at a segment's start is phi * (adjoint at its end) + what the segment's
     // own loss terms contribute; phi = B^K with B = [[1 - kap h, -kap], [c h, c]], row-major
     float phi[4];
     // 1: the forward run writes the loss adjoint into each checkpoint record (the ensemble can take
-    // the register-only backward; inverse is this without RNGLD_ADJ_REPLAY)
+    // the register-only backward; reg_only is this without RNGLD_ADJ_REPLAY)
     uint32_t lam;
     // 1: the forward run is segment-parallel (Hybrid Taus with lam): each K-step segment runs from
     // a zero state with the generator jumped to its start, and a join pass adds the response to
@@ -149,10 +149,11 @@ struct AdjCoef {
     uint32_t sp;
     double fk[4];     // F^K, F = [[1 - h kap, h c], [-kap, c]] the forward step matrix
     double flast[4];  // F^len of the last segment
-    double bk[4];     // B^K, the adjoint step over a whole segment (phi in FP64)
-    // sums over j = 1..K of a^2, a b, b^2, alpha a, alpha b, beta a, beta b with (a_j, b_j) the
-    // first row of F^j and (alpha_j, beta_j) = B^j e1, each term formed from their FP32 values
-    double full[7];
+    double bk[4];     // B^K = (F^K)^T (B = F^T), the adjoint step over a whole segment (phi in FP64)
+    // sums over j = 1..K of a_j^2, a_j b_j, b_j^2 with (a_j, b_j) the first row of F^j, each term
+    // formed from their FP32 values.  B^j e1 is the same row, so the segment's own adjoint uses the
+    // same sums as its loss
+    double full[3];
 };
 
 // width of the per-tile FP64 partials of the adjoint kernels: three sums and their squares
@@ -164,9 +165,9 @@ constexpr uint32_t kAdjSegD = 3;
 // lam_x[3], lam_v[3] of the record's state (written by the forward run for ensembles with lam)
 constexpr uint32_t kCkptLamRow = 10;
 // segment-parallel forward: per (oscillator, segment) FP32 rows of the zero-start run: x_end[3],
-// v_end[3], sum of x^2 over the window steps, and per component sum a_j x_j, sum b_j x_j,
-// sum alpha_j x_j, sum beta_j x_j over them
-constexpr uint32_t kFwdSegF = 19;
+// v_end[3], sum of x^2 over the window steps, and per component sum a_j x_j and sum b_j x_j over
+// them
+constexpr uint32_t kFwdSegF = 13;
 // per segment: the columns of the three Tausworthe components' jump matrices (3 x 32 words), the
 // LCG's multiplier and increment, two words of padding
 constexpr uint32_t kJumpWords = 100;
@@ -186,7 +187,7 @@ struct AdjArgs {
     float *scratch;      // backward, replay path: [K][9][NT]
     double *seg_d;       // backward, register-only path: [nseg][kAdjSegD][NT]
     uint32_t *jump;      // forward, segment-parallel: [nseg][kJumpWords]
-    float4 *coef;        //   [n_ens][K]: (a_j, b_j, alpha_j, beta_j), j = 1..K
+    float2 *coef;        //   [n_ens][K]: (a_j, b_j), the first row of F^j, j = 1..K
     float *fwd_seg;      //   [nseg][kFwdSegF][NT]
     double *partials;    // [n_tiles][kAdjPartW]: the loss (forward), or per-oscillator gradient
                          // sums and sums of squares (backward)
@@ -195,9 +196,9 @@ struct AdjArgs {
 // forward with checkpoints: the segment-parallel kernels for ensembles with sp (any_sp), the
 // sequential kernel for the others (any_seq)
 hipError_t launch_ld_ckpt(int kind, const AdjArgs &a, bool any_sp, bool any_seq, hipStream_t st);
-// backward: the replay kernel for ensembles with inverse == 0, the register-only kernel (Hybrid
-// Taus) for those with inverse == 1
-hipError_t launch_ld_adjoint(int kind, const AdjArgs &a, bool any_replay, bool any_inverse, hipStream_t st);
+// backward: the replay kernel for ensembles with reg_only == 0, the register-only kernel (Hybrid
+// Taus) for those with reg_only == 1
+hipError_t launch_ld_adjoint(int kind, const AdjArgs &a, bool any_replay, bool any_reg_only, hipStream_t st);
 // out[e][0, width) = sums of partial slots 0..width-1 over the ensemble's tiles / (3 n denom_steps);
 // with spread, also out[e][width + q] = the standard error of the mean of slot q's per-oscillator
 // values (slot width + q holding their squares)

@@ -6,25 +6,19 @@
 // With mu = lam_v' + h lam_x' (adjoints of the step's outputs), one reverse step is
 //     lam_x = lam_x' - kap mu + dL/dx,  lam_v = c mu,
 //     dL/dtheta += mu (dc/dtheta v - dkap/dtheta x + dsig/dtheta g).
-// The forward kernel writes (x, v, generator state) every K steps and at the end.  The backward
-// kernels walk the segments last to first, in one of two ways per ensemble:
-//  * register-only (Hybrid Taus): start from the checkpoint at the segment's end and step both
-//    the generator (inverse Tausworthe and LCG steps, so the noise is bit-identical) and the
-//    integrator backward, x = x' - h v', v = (v' + kap x - sig g) / c, while sweeping the adjoint;
-//    each segment restarts from its own end checkpoint, which bounds the growth of rounding
-//    errors in the reconstructed path to K steps (the host admits an ensemble only if that growth
-//    stays small).  The segments run in parallel, one thread per (oscillator, segment): the
-//    reverse recursion is linear with a step matrix B that is the same for every step of an
-//    ensemble, so a segment swept with a zero adjoint at its end yields its own contribution, and
-//    the contribution of the adjoint that arrives from later segments is linear in that adjoint:
-//    with mu^hom_s = a_s lam_x + b_s lam_v the part of mu at step s driven by the end adjoint, the
-//    gradient gains sum_s (a_s, b_s) f_s . lam_end, f_s = dc v_s - dkap x_s + dsig g_s.  Each
-//    thread records its segment's own adjoint at the start, its gradient sums and the sums
-//    sum_s a_s z_s, sum_s b_s z_s for z = x, v, g; a per-oscillator pass then walks the segments
-//    from last to first, carrying lam_end(previous) = lam_own + B^K lam_end.
+// The forward kernels write (x, v, generator state) every K steps and at the end.  The backward
+// kernels take one of two ways per ensemble:
+//  * register-only (Hybrid Taus): the forward run also leaves in each record the loss adjoint of
+//    the record's state (the recursion is linear with a step matrix B that is the same for every
+//    step of an ensemble, so each segment's own share, summed over its window steps, plus B^K
+//    times the adjoint at its end gives the adjoint at its start, walked last to first in FP64).
+//    Every segment then runs on its own, one thread per (oscillator, segment), forward in time
+//    from its start record: the same generator, Box-Muller and update code give the noise and the
+//    path bit for bit, and the adjoint is carried forward by solving the reverse step for lam'.
+//    Nothing is stored per step.
 //  * replay: restore the checkpoint at the segment's start, rerun the segment with the same
 //    generator, Box-Muller and update code, keep its path in a per-thread scratch column, and
-//    sweep it backward.
+//    sweep it backward, segments last to first.
 // Gradients accumulate in FP64 per thread and reduce in a fixed order (no atomics).
 #include <type_traits>
 
@@ -308,8 +302,8 @@ __device__ __forceinline__ void mat2_mul(const double *p, const double *q, doubl
 // Tables of the segment-parallel forward.  Blocks [0, nseg): the jump of segment seg, 4 seg K draws:
 // thread t < 96 follows column t % 32 of component t / 32 through binary powering, with the matrix
 // M^(2^k) squared in LDS each round; thread 96 the LCG's map.  Blocks [nseg, nseg + n_ens): the
-// ensemble's coefficients for j = 1..K, (a_j, b_j) the first row of F^j and (alpha_j, beta_j) =
-// B^j e1, each by binary powering in FP64 and rounded once.
+// ensemble's coefficients for j = 1..K, (a_j, b_j) the first row of F^j (also B^j e1, since the
+// adjoint step is B = F^T), each by binary powering in FP64 and rounded once.
 __global__ __launch_bounds__(128) void adj_prep_kernel(AdjArgs a, uint32_t nseg) {
     __shared__ uint32_t P[3][32];
     const uint32_t t = threadIdx.x;
@@ -342,21 +336,14 @@ __global__ __launch_bounds__(128) void adj_prep_kernel(AdjArgs a, uint32_t nseg)
     const LdCoef q = A.f;
     const double h = q.h, c = q.c, kap = q.kap;
     const double F[4] = {1.0 - h * kap, h * c, -kap, c};
-    const double B[4] = {1.0 - kap * h, -kap, c * h, c};
     for (uint32_t j = 1 + t; j <= a.K; j += 128) {
-        double pf[4] = {1, 0, 0, 1}, pb[4] = {1, 0, 0, 1}, sf[4], sb[4];
-        for (int k = 0; k < 4; ++k) sf[k] = F[k], sb[k] = B[k];
+        double pf[4] = {1, 0, 0, 1}, sf[4];
+        for (int k = 0; k < 4; ++k) sf[k] = F[k];
         for (uint32_t m = j; m != 0; m >>= 1) {
-            if (m & 1) {
-                mat2_mul(pf, sf, pf);
-                mat2_mul(pb, sb, pb);
-            }
+            if (m & 1) mat2_mul(pf, sf, pf);
             mat2_mul(sf, sf, sf);
-            mat2_mul(sb, sb, sb);
         }
-        a.coef[static_cast<uint64_t>(e) * a.K + j - 1] =
-            make_float4(static_cast<float>(pf[0]), static_cast<float>(pf[1]), static_cast<float>(pb[0]),
-                        static_cast<float>(pb[2]));
+        a.coef[static_cast<uint64_t>(e) * a.K + j - 1] = make_float2(static_cast<float>(pf[0]), static_cast<float>(pf[1]));
     }
 }
 
@@ -387,8 +374,8 @@ __global__ __launch_bounds__(BLOCK) void ld_fwd_seg_kernel(AdjArgs a) {
     auto rec_f = [&](uint32_t r) { return reinterpret_cast<float *>(a.ckpt + static_cast<uint64_t>(r) * a.rec_bytes); };
     if (act) g.store(reinterpret_cast<uint32_t *>(rec_f(seg) + 6 * NT), NT, i);
     float x[3] = {0, 0, 0}, v[3] = {0, 0, 0};
-    float sxx = 0.0f, sa[3] = {0, 0, 0}, sb[3] = {0, 0, 0}, sal[3] = {0, 0, 0}, sbe[3] = {0, 0, 0};
-    const float4 *cf = a.coef + static_cast<uint64_t>(e) * a.K;
+    float sxx = 0.0f, sa[3] = {0, 0, 0}, sb[3] = {0, 0, 0};
+    const float2 *cf = a.coef + static_cast<uint64_t>(e) * a.K;
     auto steps = [&](auto win_tag, uint32_t s, uint32_t end) {
         constexpr bool WIN = decltype(win_tag)::value;
         for (; s < end; ++s) {
@@ -398,14 +385,12 @@ __global__ __launch_bounds__(BLOCK) void ld_fwd_seg_kernel(AdjArgs a) {
 #pragma unroll
             for (int d = 0; d < 3; ++d) ld_update_s<0>(q, x[d], v[d], gf[d]);
             if constexpr (WIN) {
-                const float4 k = cf[s - s0];  // j = s - s0 + 1
+                const float2 k = cf[s - s0];  // j = s - s0 + 1
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
                     sxx += x[d] * x[d];
                     sa[d] += k.x * x[d];
                     sb[d] += k.y * x[d];
-                    sal[d] += k.z * x[d];
-                    sbe[d] += k.w * x[d];
                 }
             }
         }
@@ -423,8 +408,6 @@ __global__ __launch_bounds__(BLOCK) void ld_fwd_seg_kernel(AdjArgs a) {
         fr[(3 + d) * NT] = v[d];
         fr[(7 + d) * NT] = sa[d];
         fr[(10 + d) * NT] = sb[d];
-        fr[(13 + d) * NT] = sal[d];
-        fr[(16 + d) * NT] = sbe[d];
     }
     fr[6 * NT] = sxx;
     if (seg + 1 == nseg) g.store(reinterpret_cast<uint32_t *>(rec_f(nseg) + 6 * NT), NT, i);
@@ -452,16 +435,15 @@ __global__ __launch_bounds__(3 * TILE) void ld_fwd_join_kernel(AdjArgs a) {
     auto rec_f = [&](uint32_t r) { return reinterpret_cast<float *>(a.ckpt + static_cast<uint64_t>(r) * a.rec_bytes); };
     // the zero-start run's rows of one segment for this component (and the x^2 sum for d = 0)
     struct Rows {
-        float xp, vp, sa, sb, sal, sbe, sxx;
+        float xp, vp, sa, sb, sxx;
     };
     auto load = [&](uint32_t seg) {
         const float *fr = a.fwd_seg + static_cast<uint64_t>(seg) * kFwdSegF * NT + i;
-        return Rows{fr[d * NT], fr[(3 + d) * NT], fr[(7 + d) * NT], fr[(10 + d) * NT], fr[(13 + d) * NT],
-                    fr[(16 + d) * NT], d == 0 ? fr[6 * NT] : 0.0f};
+        return Rows{fr[d * NT], fr[(3 + d) * NT], fr[(7 + d) * NT], fr[(10 + d) * NT], d == 0 ? fr[6 * NT] : 0.0f};
     };
     double lsum = 0.0;
     if (act) {
-        const float4 *cf = a.coef + static_cast<uint64_t>(e) * a.K;
+        const float2 *cf = a.coef + static_cast<uint64_t>(e) * a.K;
         double x = a.x[d * NT + i], v = a.v[d * NT + i];
         Rows cur = load(0);
         for (uint32_t seg = 0; seg < nseg; ++seg) {
@@ -473,22 +455,23 @@ __global__ __launch_bounds__(3 * TILE) void ld_fwd_join_kernel(AdjArgs a) {
             uint32_t lo, hi;
             window_part(a, s0, s1, lo, hi);
             if (hi > lo) {
-                // the seven sums over the window steps j = lo - s0 + 1 .. hi - s0
-                double P[7];
+                // the sums of a_j^2, a_j b_j, b_j^2 over the window steps j = lo - s0 + 1 .. hi - s0
+                double P[3];
                 if (lo == s0 && hi - s0 == a.K) {
-                    for (int k = 0; k < 7; ++k) P[k] = A.full[k];
+                    for (int k = 0; k < 3; ++k) P[k] = A.full[k];
                 } else {
-                    for (int k = 0; k < 7; ++k) P[k] = 0.0;
+                    for (int k = 0; k < 3; ++k) P[k] = 0.0;
                     for (uint32_t s = lo; s < hi; ++s) {
-                        const float4 k4 = cf[s - s0];
-                        const double ca = k4.x, cb = k4.y, cl = k4.z, ce = k4.w;
+                        const float2 k2 = cf[s - s0];
+                        const double ca = k2.x, cb = k2.y;
                         P[0] += ca * ca, P[1] += ca * cb, P[2] += cb * cb;
-                        P[3] += cl * ca, P[4] += cl * cb, P[5] += ce * ca, P[6] += ce * cb;
                     }
                 }
+                // the segment's loss terms sum_j (x0_j + a_j x + b_j v)^2 (x0 the zero-start path)
+                // and their gradient with respect to the start state (x, v), its own adjoint
                 lsum += cur.sxx + 2.0 * (x * cur.sa + v * cur.sb) + x * x * P[0] + 2.0 * x * v * P[1] + v * v * P[2];
-                rx[(kCkptLamRow + d) * NT + i] = static_cast<float>(2.0 * (cur.sal + P[3] * x + P[4] * v));
-                rx[(kCkptLamRow + 3 + d) * NT + i] = static_cast<float>(2.0 * (cur.sbe + P[5] * x + P[6] * v));
+                rx[(kCkptLamRow + d) * NT + i] = static_cast<float>(2.0 * (cur.sa + P[0] * x + P[1] * v));
+                rx[(kCkptLamRow + 3 + d) * NT + i] = static_cast<float>(2.0 * (cur.sb + P[1] * x + P[2] * v));
             }
             const double *M = (s1 - s0 == a.K) ? A.fk : A.flast;
             const double nx = cur.xp + M[0] * x + M[1] * v;
@@ -522,7 +505,7 @@ __global__ __launch_bounds__(BLOCK) void ld_adjoint_kernel(AdjArgs a) {
     const uint32_t e = find_ensemble(a.ens, a.n_ens, tile);
     const EnsDev &E = a.ens[e];
     const AdjCoef A = a.adj[e];
-    if (A.inverse) return;  // the register-only kernel owns this tile
+    if (A.reg_only) return;  // the register-only kernel owns this tile
     const float h = A.f.h, c = A.f.c, kap = A.f.kap;
     const uint64_t i = E.offset + static_cast<uint64_t>(tile - E.tile_begin) * BLOCK + threadIdx.x;
     const bool act = i < E.offset + E.n;
@@ -583,26 +566,32 @@ __global__ __launch_bounds__(BLOCK) void ld_adjoint_kernel(AdjArgs a) {
     block_grad_partials<BLOCK>(act, gk, gg, gT, red, a.partials + static_cast<uint64_t>(tile) * kAdjPartW);
 }
 
-// register-only backward sweep (Hybrid Taus), one thread per (oscillator, segment): blockIdx.y is
-// the segment.  The sweep starts from the loss adjoint that the forward run left in the record at
-// the segment's end, so each thread's sums are its segment's share of the gradient; they go to
-// seg_d and a second pass adds an oscillator's segments in order.
+// register-only backward (Hybrid Taus), one thread per (oscillator, segment): blockIdx.y is the
+// segment.  The record at the segment's start holds its state and the loss adjoint A_s0 of that
+// state (the gradient of the loss terms after it), so the segment runs forward in time: the same
+// generator, Box-Muller and update steps as the forward run give the noise and the path, and the
+// adjoint recursion A_s = B A'_{s+1} is solved for the adjoint of the step's outputs,
+//     mu = lam_v / c,  A'_x = lam_x + kap mu,  A'_v = mu - h A'_x,
+// then the loss term of the step's end position is taken off, A_{s+1} = A' - (2 x_{s+1}, 0).  The
+// powers of B's inverse have the norms of the forward step matrix's inverse powers (B is its
+// transpose): the error growth the host bounds over K steps.  Each thread's sums are its segment's share of the gradient;
+// they go to seg_d and a second pass adds an oscillator's segments in order.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void ld_adjoint_seg_kernel(AdjArgs a) {
     const uint32_t tile = blockIdx.x, seg = blockIdx.y;
     const uint32_t e = find_ensemble(a.ens, a.n_ens, tile);
     const EnsDev &E = a.ens[e];
     const AdjCoef A = a.adj[e];
-    if (!A.inverse) return;  // the replay kernel owns this tile
-    const float h = A.f.h, c = A.f.c, kap = A.f.kap, sig = A.f.sig, inv_c = A.inv_c, inv_c_lo = A.inv_c_lo;
+    if (!A.reg_only) return;  // the replay kernel owns this tile
+    const LdCoef q = A.f;
+    const float h = q.h, kap = q.kap, inv_c = A.inv_c, inv_c_lo = A.inv_c_lo;
     const uint64_t i = E.offset + static_cast<uint64_t>(tile - E.tile_begin) * BLOCK + threadIdx.x;
     const bool act = i < E.offset + E.n;
     const uint64_t col = act ? i : E.offset;  // inactive lanes follow a valid column
     const uint64_t NT = a.NT;
     const uint32_t s0 = seg * a.K;
     const uint32_t s1 = (s0 + a.K < a.n_steps) ? s0 + a.K : a.n_steps;
-    // record seg + 1 holds the state at s1 (the end state for the last segment) and its adjoint
-    const float *rec = reinterpret_cast<const float *>(a.ckpt + static_cast<uint64_t>(seg + 1) * a.rec_bytes);
+    const float *rec = reinterpret_cast<const float *>(a.ckpt + static_cast<uint64_t>(seg) * a.rec_bytes);
     float x[3], v[3], lx[3], lv[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -616,39 +605,31 @@ __global__ __launch_bounds__(BLOCK) void ld_adjoint_seg_kernel(AdjArgs a) {
     // the segment's gradient as sums over its steps and the three components of mu x, mu v and
     // mu g, scaled by the partials at the end: K terms per component in FP32
     float smx = 0.0f, smv = 0.0f, smg = 0.0f;
-    // steps s = e - 1 down to b, x and v holding the state after step s on entry to step s; LOSS:
-    // the steps whose end position is a loss term (s + 1 in the window)
+    // steps [b, e); LOSS: the steps whose end position is a loss term
     auto sweep = [&](auto loss_tag, uint32_t b, uint32_t e) {
         constexpr bool LOSS = decltype(loss_tag)::value;
-        for (uint32_t s = e; s-- > b;) {
-            const uint32_t w3 = g.prev_top24();
-            const uint32_t w2 = g.prev_top24();
-            const uint32_t w1 = g.prev_top24();
-            const uint32_t w0 = g.prev_top24();
+        for (uint32_t s = b; s < e; ++s) {
+            const uint32_t w0 = g.next_top24(), w1 = g.next_top24(), w2 = g.next_top24(), w3 = g.next_top24();
             float gf[3];
             gaussian_forces_top24(w0, w1, w2, w3, gf[0], gf[1], gf[2]);
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                if constexpr (LOSS) lx[d] += 2.0f * x[d];
-                const float xs = x[d] - h * v[d];
-                const float t = v[d] + kap * xs - sig * gf[d];
-                const float vs = __builtin_fmaf(t, inv_c, t * inv_c_lo);
-                const float mu = lv[d] + h * lx[d];
-                smx += mu * xs;
-                smv += mu * vs;
+                const float mu = __builtin_fmaf(lv[d], inv_c, lv[d] * inv_c_lo);
+                const float ax = lx[d] + kap * mu;
+                lv[d] = mu - h * ax;
+                smx += mu * x[d];
+                smv += mu * v[d];
                 smg += mu * gf[d];
-                lx[d] = lx[d] - kap * mu;
-                lv[d] = c * mu;
-                x[d] = xs;
-                v[d] = vs;
+                ld_update_s<0>(q, x[d], v[d], gf[d]);
+                lx[d] = LOSS ? ax - 2.0f * x[d] : ax;
             }
         }
     };
     uint32_t lo, hi;
     window_part(a, s0, s1, lo, hi);
-    sweep(std::false_type{}, hi, s1);
-    sweep(std::true_type{}, lo, hi);
     sweep(std::false_type{}, s0, lo);
+    sweep(std::true_type{}, lo, hi);
+    sweep(std::false_type{}, hi, s1);
     if (!act) return;
     double *rd = a.seg_d + static_cast<uint64_t>(seg) * kAdjSegD * NT + i;
     rd[0] = -static_cast<double>(A.dkap_dk) * smx;
@@ -663,7 +644,7 @@ __global__ __launch_bounds__(BLOCK) void ld_adjoint_sum_kernel(AdjArgs a) {
     const uint32_t tile = blockIdx.x;
     const uint32_t e = find_ensemble(a.ens, a.n_ens, tile);
     const EnsDev &E = a.ens[e];
-    if (!a.adj[e].inverse) return;  // the replay kernel owns this tile
+    if (!a.adj[e].reg_only) return;  // the replay kernel owns this tile
     const uint64_t i = E.offset + static_cast<uint64_t>(tile - E.tile_begin) * BLOCK + threadIdx.x;
     const bool act = i < E.offset + E.n;
     const uint64_t NT = a.NT;
@@ -733,7 +714,7 @@ hipError_t launch_ld_ckpt(int kind, const AdjArgs &a, bool any_sp, bool any_seq,
     return hipGetLastError();
 }
 
-hipError_t launch_ld_adjoint(int kind, const AdjArgs &a, bool any_replay, bool any_inverse, hipStream_t st) {
+hipError_t launch_ld_adjoint(int kind, const AdjArgs &a, bool any_replay, bool any_reg_only, hipStream_t st) {
     if (a.n_tiles == 0) return hipSuccess;
     if (any_replay) {
         if (kind == RNGLD_RAN2)
@@ -743,7 +724,7 @@ hipError_t launch_ld_adjoint(int kind, const AdjArgs &a, bool any_replay, bool a
         const hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
-    if (any_inverse && kind == RNGLD_HYBRID_TAUS) {
+    if (any_reg_only && kind == RNGLD_HYBRID_TAUS) {
         const uint32_t nseg = (a.n_steps + a.K - 1) / a.K;
         ld_adjoint_seg_kernel<kAdjBlock><<<dim3(a.n_tiles, nseg), kAdjBlock, 0, st>>>(a);
         const hipError_t err = hipGetLastError();

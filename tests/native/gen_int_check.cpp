@@ -1,11 +1,10 @@
-// CPU check of the inverse generator steps in paper_1003_1123_amd/csrc/gen_int.hpp: for random
-// seeds, stepping each Tausworthe component and the LCG forward and then back with the inverse
-// steps returns every produced word exactly, and a seeded word's top K bits.  Also checks the
-// produced words against the component's bit recurrence y_m = y_{m-K+Q} xor y_{m-K} (Eq. 2), which
-// the inverse relies on.  And the modular product A x mod (2^31 - C) of Ran2's two generators
-// (mulmod_2p31m) against the plain 64-bit remainder, at random and at the ends of its range.  And the
-// forward step's funnel-shift form against the masked shift-and-xor of Eq. 2 on arbitrary words.
-// Prints "ok" on success.
+// CPU check of the integer generator steps in paper_1003_1123_amd/csrc/gen_int.hpp: the Tausworthe
+// step's funnel-shift form against the masked shift-and-xor of Eq. 2 on arbitrary words; the words
+// it produces from random seeds against the component's bit recurrence y_m = y_{m-K+Q} xor y_{m-K}
+// (consecutive words are windows of one bit sequence, S bits apart); the LCG's n-step map (the
+// generator jump of the segment-parallel runs) against n single steps; and the modular product
+// A x mod (2^31 - C) of Ran2's two generators (mulmod_2p31m) against the plain 64-bit remainder,
+// at random and at the ends of its range.  Prints "ok" on success.
 #include <cstdio>
 #include <cstdint>
 #include <vector>
@@ -45,16 +44,6 @@ static int check_component(int n_seeds, int n_steps) {
             for (int i = K; i < 32; ++i)
                 if (bit(n, i) != (bit(n, i - K + Q) ^ bit(n, i - K))) ++bad;  // recurrence inside one word
         }
-        // the inverse walks back through every produced word
-        uint32_t x = w[n_steps];
-        for (int n = n_steps; n > 1; --n) {
-            x = tausworthe_inv<Q, S, K>(x);
-            if (x != w[n - 1]) ++bad;
-        }
-        constexpr uint32_t kTop = ~((1u << (32 - K)) - 1u);
-        if ((tausworthe_inv<Q, S, K>(x) & kTop) != (z0 & kTop)) ++bad;
-        // and forward again
-        if (n_steps >= 2 && tausworthe<Q, S, K>(tausworthe_inv<Q, S, K>(w[2])) != w[2]) ++bad;
     }
     if (bad) std::printf("component (%d,%d,%d): %d mismatches\n", Q, S, K, bad);
     return bad;
@@ -84,11 +73,20 @@ int main() {
     bad += check_component<13, 12, 31>(2000, 60);
     bad += check_component<2, 4, 29>(2000, 60);
     bad += check_component<3, 17, 28>(2000, 60);
-    for (int t = 0; t < 100000; ++t) {
-        const uint32_t x = rnd();
-        if (lcg_prev(lcg_next(x)) != x || lcg_next(lcg_prev(x)) != x) ++bad;
+    // the LCG's n-step map against n single steps, for every n up to 4096 and at random seeds
+    for (int t = 0; t < 16; ++t) {
+        const uint32_t x0 = rnd();
+        uint32_t x = x0;
+        for (uint64_t n = 0; n <= 4096; ++n) {
+            if (lcg_skip(x0, n) != x) ++bad;
+            x = lcg_next(x);
+        }
     }
-    if (kLcgMul * kLcgMulInv != 1u) ++bad;
+    // and composed: n = 2^40 + 12345 as 2^40 then 12345 steps
+    {
+        const uint32_t x0 = rnd();
+        if (lcg_skip(lcg_skip(x0, 1ull << 40), 12345) != lcg_skip(x0, (1ull << 40) + 12345)) ++bad;
+    }
     bad += check_mulmod<40014, 85>();
     bad += check_mulmod<40692, 249>();
     if (bad) {

@@ -191,7 +191,7 @@ def test_adjoint_sizing_and_validation():
     loss = R.Loss(1001, 2000, 100, 0)
     scratch = 9 * 100 * 1000 * 4  # replay: 9 floats per oscillator-step of one segment
     records = 20 * 1000 * 3 * 8  # register-only backward: 24 bytes per (oscillator, segment)
-    fwd_records = 20 * 1000 * 19 * 4  # segment-parallel forward: 76 bytes per (oscillator, segment)
+    fwd_records = 20 * 1000 * 13 * 4  # segment-parallel forward: 52 bytes per (oscillator, segment)
     small = 64 * 1024  # ensemble tables, per-tile partials, jump and coefficient tables
     # weakly damped Hybrid Taus: segment-parallel forward and register-only backward share the space
     ws = R.ld_adjoint_workspace_bytes(c, ens, n, 1000, 2000, loss)

@@ -74,8 +74,8 @@ def test_valu_roofline_uses_the_loop_counts_and_the_mix_bound(kind):
 def test_adjoint_loops_mix_bounds():
     if "step_loops" not in bench._kernel_isa():
         pytest.skip("the library has not been built (no kernel_isa.json)")
-    # the backward sweep regenerates the same four words per step with inverse steps and adds the
-    # adjoint recursion and its FP32 sums: more instructions and a lower bound than the forward
+    # the backward reruns each segment's generator, Box-Muller and update steps and adds the
+    # carried adjoint and its FP32 sums: more instructions and a lower bound than the forward
     assert bench.valu_per_osc_step("adjoint_backward") > bench.valu_per_osc_step("adjoint_forward")
     assert bench.valu_per_osc_step("adjoint_forward") >= bench.valu_per_osc_step("taus")
     bwd, fwd = bench.valu_mix_bound("adjoint_backward"), bench.valu_mix_bound("adjoint_forward")
