@@ -20,7 +20,17 @@ namespace rngld {
 constexpr uint32_t kLcgMul = 1664525u;
 constexpr uint32_t kLcgAdd = 1013904223u;
 
-RNGLD_HDI uint32_t lcg_next(uint32_t x) { return kLcgMul * x + kLcgAdd; }
+// On the device the multiply and the add are one v_mad_u64_u32 (the low word of a x + c) where
+// the compiler would emit a 32-bit multiply and an add.
+RNGLD_HDI uint32_t lcg_next(uint32_t x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    uint64_t r;
+    asm("v_mad_u64_u32 %0, vcc, %1, %2, %3" : "=v"(r) : "v"(x), "s"(kLcgMul), "v"(static_cast<uint64_t>(kLcgAdd)) : "vcc");
+    return static_cast<uint32_t>(r);
+#else
+    return kLcgMul * x + kLcgAdd;
+#endif
+}
 
 // x advanced by n steps: the affine map x -> a x + c composed with itself by binary powering
 // (a - 1 is even, so the geometric-sum closed form cannot use a modular inverse).
@@ -69,13 +79,23 @@ RNGLD_HDI uint32_t tausworthe(uint32_t z) {
 
 // A x mod M for M = 2^31 - C and 0 <= x < M (the multiplicative steps of Ran2's two generators):
 // the product p = A x, below 2^47, is H 2^31 + L, and 2^31 = C (mod M), so p = C H + L (mod M), where
-// C H + L < 2 M takes one conditional subtraction.  One 32 x 32 -> 64-bit multiply and one 24-bit
-// multiply-add, against four multiplies for Schrage's method; the same exact residue.
+// C H + L < 2 M takes one conditional subtraction.  One 32 x 32 -> 64-bit multiply and one
+// multiply-add, against four multiplies for Schrage's method; the same exact residue.  On the
+// device the multiply-add is one v_mad_u64_u32 on the whole product: the low word of
+// p + H (C + 2^31) is L + C H, since the low word of p is L + (H mod 2) 2^31 and H 2^31 adds the
+// same bit again (mod 2^32), so no mask is needed.
 template <uint32_t A, uint32_t C>
 RNGLD_HDI uint32_t mulmod_2p31m(uint32_t x) {
     static_assert(A < (1u << 16) && C < (1u << 14), "C H + L < 2 M");
     const uint64_t p = static_cast<uint64_t>(A) * x;
-    const uint32_t r = (static_cast<uint32_t>(p) & 0x7fffffffu) + C * static_cast<uint32_t>(p >> 31);
+    const uint32_t H = static_cast<uint32_t>(p >> 31);
+#if defined(__HIP_DEVICE_COMPILE__)
+    uint64_t q;
+    asm("v_mad_u64_u32 %0, vcc, %1, %2, %3" : "=v"(q) : "v"(H), "s"(C + 0x80000000u), "v"(p) : "vcc");
+    const uint32_t r = static_cast<uint32_t>(q);
+#else
+    const uint32_t r = (static_cast<uint32_t>(p) & 0x7fffffffu) + C * H;
+#endif
     constexpr uint32_t m = 0x80000000u - C;
     return r >= m ? r - m : r;
 }

@@ -4,7 +4,8 @@
 // (consecutive words are windows of one bit sequence, S bits apart); the LCG's n-step map (the
 // generator jump of the segment-parallel runs) against n single steps; and the modular product
 // A x mod (2^31 - C) of Ran2's two generators (mulmod_2p31m) against the plain 64-bit remainder,
-// at random and at the ends of its range.  Prints "ok" on success.
+// at random and at the ends of its range, with the device's mask-free form of its reduction.
+// Prints "ok" on success.
 #include <cstdio>
 #include <cstdint>
 #include <vector>
@@ -55,6 +56,11 @@ static int check_mulmod() {
     int bad = 0;
     auto one = [&](uint32_t x) {
         if (mulmod_2p31m<A, C>(x) != static_cast<uint32_t>(static_cast<uint64_t>(A) * x % m)) ++bad;
+        // the device's form of the reduction: the low word of p + H (C + 2^31) equals L + C H
+        const uint64_t p = static_cast<uint64_t>(A) * x;
+        const uint32_t H = static_cast<uint32_t>(p >> 31);
+        const uint32_t dev = static_cast<uint32_t>(p + static_cast<uint64_t>(H) * (C + 0x80000000u));
+        if (dev != (static_cast<uint32_t>(p) & 0x7fffffffu) + C * H) ++bad;
     };
     for (uint32_t x : {0u, 1u, 2u, 3u, static_cast<uint32_t>(m - 1), static_cast<uint32_t>(m - 2),
                        static_cast<uint32_t>(m / A), static_cast<uint32_t>(m / A + 1), 0x40000000u})
