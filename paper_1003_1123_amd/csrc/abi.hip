@@ -557,7 +557,6 @@ int64_t try_lf_pc_gauss(const Gen &g, void *d_state, uint32_t *d_out, uint64_t c
 
 // The persistent bare-stream run for count values, if it fits: 1 when launched, 0 when the wave
 // path must run, an RNGLD error otherwise.  Needs links long enough to keep the chip busy.
-// gauss: the run also turns out[0, keep_from) into Box-Muller pairs in place (needs an even sl)
 int try_lf_stream(const Gen &g, void *d_state, uint32_t *d_out, uint64_t count, hipStream_t st) {
     if (g.sl < 4096 || count < 4ull * g.sl) return 0;
     if ((count + g.sl - 1) / g.sl >= (1ull << 31)) return 0;
