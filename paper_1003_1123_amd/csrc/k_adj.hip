@@ -149,7 +149,7 @@ __device__ void adjoint_walk(const AdjArgs &a, uint64_t i, int d, const double b
 // forward run from the current state with checkpoints every K steps; loss partial = sum of x^2
 // over the loss window (scaled on finalisation).
 // For ensembles with lam each record also gets the loss adjoint of its state, the starting point
-// of the register-only backward sweep of the segment that ends there.  The adjoint recursion is
+// of the register-only backward of the segment that starts there.  The adjoint recursion is
 // linear with the constant matrix B, so what a segment's own loss terms hand to the adjoint at its
 // start is the sum over its window steps j = 1..K of B^j (2 x_j, 0); it is accumulated here from
 // the forward positions (B^j e1 advanced alongside), and a last pass over the records, latest
