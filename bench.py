@@ -33,7 +33,7 @@ GENERATORS = ("taus", "ran2", "lf")
 # as the build counts them in the assembly it compiles (kernel_isa.json, "step_loops").
 STEP_LOOP_KERNELS = {"taus": "ld_run_kernel<HybridTaus,256,1>", "ran2": "ld_run_kernel<Ran2,256,1>",
                      "lcg": "ld_run_kernel<Lcg32,256,1>", "adjoint_forward": "ld_fwd_seg_kernel<256>",
-                     "adjoint_backward": "ld_adjoint_seg_kernel<256>"}
+                     "adjoint_backward": "ld_adjoint_seg_kernel<HybridTaus,256>"}
 # Measured bound of those loops: each instruction class at the issue rate the VALU probe measured
 # for it (profiles/valu_issue_rates.md, lane-instructions per second over the chip), times added
 # (transcendentals do not overlap other VALU work), except that a 32-bit multiply interleaved with
@@ -594,7 +594,8 @@ def extra_config5(R, W, torch):
     (segment-parallel) backward and the replay backward, each timed with events on the stream
     around the library call, and end to end through torch's autograd; every pass starts a fresh run
     from rest (one untimed pass first loads the kernels).  Also the 6 forward runs of
-    common-random-number central differences that the gradient replaces."""
+    common-random-number central differences that the gradient replaces, and both backward paths
+    for Ran2 after its sequential forward."""
     from paper_1003_1123_amd import autograd as A
     c5 = W.C5
     p5 = c5["params"].as_f32()
@@ -602,8 +603,8 @@ def extra_config5(R, W, torch):
     out = {"N": N, "steps": T, "K": c5["K"]}
     osc = N * T
 
-    def one(replay):
-        run = A.AdjointRun("taus", [(N, p5.m, p5.dt, c5["seed"])], T, c5["t_begin"], c5["t_end"], c5["K"],
+    def one(replay, kind="taus"):
+        run = A.AdjointRun(kind, [(N, p5.m, p5.dt, c5["seed"])], T, c5["t_begin"], c5["t_end"], c5["K"],
                            replay=replay, spread=True)
         run.timed = True
         k = torch.tensor([p5.k], dtype=torch.float64, requires_grad=True)
@@ -658,6 +659,15 @@ def extra_config5(R, W, torch):
             out.update(res)
         else:
             out["replay"] = res
+    # the same workload with Ran2: a sequential forward (its shuffle table has no jump-ahead), then
+    # the register-only or the replay backward
+    r2 = {}
+    for replay in (False, True):
+        one(replay, "ran2")
+        _, L, grad, (fwd_ms, bwd_ms), _ = one(replay, "ran2")
+        r2["replay" if replay else "register_only"] = {"loss": L, "grad_k_gamma_kT": grad, "forward_ms": fwd_ms,
+                                                       "backward_ms": bwd_ms}
+    out["ran2"] = r2
     return out
 
 

@@ -328,7 +328,7 @@ typedef struct ld_loss {
 /* Checkpoint buffer: ceil(n_steps/K) + 1 records, record c = state at step min(c*K, n_steps)
  * (the last record is the state at the end of the run):
  * float x[3][n_total], float v[3][n_total], then the generator state in the layout above with
- * S = n_total; for Hybrid Taus then float lam_x[3][n_total], lam_v[3][n_total]: the gradient of the
+ * S = n_total, then float lam_x[3][n_total], lam_v[3][n_total]: the gradient of the
  * sum of x^2 over the loss window's steps after the record with respect to the record's x and v
  * (the loss adjoint the register-only backward of the segment starting there starts from),
  * written by ld_run_ckpt for ensembles that can take the register-only backward. */
@@ -356,7 +356,7 @@ RNGLD_API int ld_run_ckpt(const rngld_cfg *cfg, void *d_state, size_t state_byte
  * gradient is (the oscillators are independent, so this is the sampling error of the gradient
  * as an estimate of d E[L] / d theta).
  * Two paths, chosen per ensemble:
- *  - register-only (Hybrid Taus): each K-step segment runs forward from the checkpoint at its
+ *  - register-only (Hybrid Taus, Ran2): each K-step segment runs forward from the checkpoint at its
  *    start, with the generator, Box-Muller and update steps of the forward run, starting from the
  *    loss adjoint that ld_run_ckpt left in that checkpoint (the reverse recursion is linear with
  *    a constant step matrix, so the forward run can form it) and carrying the adjoint forward
@@ -368,8 +368,8 @@ RNGLD_API int ld_run_ckpt(const rngld_cfg *cfg, void *d_state, size_t state_byte
  *    and store nothing per step; a workspace record of 24 bytes per oscillator and segment
  *    collects each segment's share of the gradient.
  *  - replay: each segment is rerun forward from the checkpoint at its start into a scratch of
- *    9 floats per oscillator-step and swept backward from there (Ran2; Hybrid Taus otherwise or
- *    with RNGLD_ADJ_REPLAY).
+ *    9 floats per oscillator-step and swept backward from there (ensembles whose errors could
+ *    grow more, or every ensemble with RNGLD_ADJ_REPLAY).
  * ld_adjoint_workspace_bytes is the workspace of both ld_run_ckpt and ld_run_backward (one buffer
  * serves both: the segment-parallel forward's 52 bytes per oscillator and segment and the
  * backward's scratch share their space).  It includes each path's scratch only when some ensemble

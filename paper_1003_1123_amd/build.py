@@ -35,7 +35,8 @@ STEP_LOOPS = {
     "ld_run_kernel<Ran2,256,1>": ("k_ld.hip", "_ZN5rngld12_GLOBAL__N_113ld_run_kernelINS_4Ran2ELi256ELi1EEEvNS_6LdArgsE"),
     "ld_run_kernel<Lcg32,256,1>": ("k_ld.hip", "_ZN5rngld12_GLOBAL__N_113ld_run_kernelINS_5Lcg32ELi256ELi1EEEvNS_6LdArgsE"),
     "ld_fwd_seg_kernel<256>": ("k_adj.hip", "_ZN5rngld12_GLOBAL__N_117ld_fwd_seg_kernelILi256EEEvNS_7AdjArgsE"),
-    "ld_adjoint_seg_kernel<256>": ("k_adj.hip", "_ZN5rngld12_GLOBAL__N_121ld_adjoint_seg_kernelILi256EEEvNS_7AdjArgsE"),
+    "ld_adjoint_seg_kernel<HybridTaus,256>": ("k_adj.hip",
+                                              "_ZN5rngld12_GLOBAL__N_121ld_adjoint_seg_kernelINS_10HybridTausELi256EEEvNS_7AdjArgsE"),
 }
 ARCH = os.environ.get("RNGLD_OFFLOAD_ARCH", "gfx950")
 

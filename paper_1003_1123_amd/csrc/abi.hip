@@ -1350,10 +1350,11 @@ int layout_adj(const Gen &g, const ld_ensemble *h_ens, uint32_t n_ens, uint64_t 
         A.inv_c_lo = static_cast<float>(1.0 / static_cast<double>(A.f.c) - static_cast<double>(A.inv_c));
         // the register-only backward launches one block row per segment (grid y below 2^16)
         const uint64_t nseg = (static_cast<uint64_t>(n_steps) + K - 1) / K;
-        A.lam = g.kind == RNGLD_HYBRID_TAUS && K <= kAdjLamMaxK && nseg < 65536 &&
+        A.lam = (g.kind == RNGLD_HYBRID_TAUS || g.kind == RNGLD_RAN2) && K <= kAdjLamMaxK && nseg < 65536 &&
                 reverse_growth(A.f, K, kAdjGrowthLimit) <= kAdjGrowthLimit;
         A.reg_only = A.lam && !(loss.flags & RNGLD_ADJ_REPLAY);
-        A.sp = A.lam && K <= kSpMaxK && nseg >= kSpMinSegments;
+        // the segment-parallel forward jumps Hybrid Taus over GF(2); Ran2's shuffle table has no such jump
+        A.sp = A.lam && g.kind == RNGLD_HYBRID_TAUS && K <= kSpMaxK && nseg >= kSpMinSegments;
         if (A.lam) adjoint_propagator(A.f, K, A.phi);
         if (A.sp) segment_constants(A, K, static_cast<uint32_t>(n_steps - (nseg - 1) * K));
         if (E.n) {
@@ -1395,11 +1396,10 @@ int check_adj_common(const rngld_cfg *cfg, Gen *g, const ld_ensemble *h_ens, uin
     return RNGLD_OK;
 }
 
-// x[3], v[3], the generator rows and, for Hybrid Taus, the loss adjoint lam_x[3], lam_v[3]
+// x[3], v[3], the generator rows, then the loss adjoint lam_x[3], lam_v[3]
+uint32_t ckpt_lam_row(const Gen &g) { return g.kind == RNGLD_HYBRID_TAUS ? kCkptLamRow : kCkptLamRowRan2; }
 size_t ckpt_record_bytes(const Gen &g, uint64_t n_total) {
-    const uint32_t rows = g.kind == RNGLD_HYBRID_TAUS ? 4 + 6 : 35;
-    static_assert(kCkptLamRow == 6 + 4, "adjoint rows follow the Hybrid Taus state rows");
-    return static_cast<size_t>(n_total) * (6 + rows) * 4;
+    return static_cast<size_t>(n_total) * (ckpt_lam_row(g) + 6) * 4;
 }
 
 }  // namespace
@@ -1462,6 +1462,7 @@ extern "C" int ld_run_ckpt(const rngld_cfg *cfg, void *d_state, size_t state_byt
     a.t_end = loss->t_end;
     a.ckpt = static_cast<uint8_t *>(d_ckpt);
     a.rec_bytes = ckpt_record_bytes(g, n_total);
+    a.lam_row = ckpt_lam_row(g);
     a.partials = reinterpret_cast<double *>(ws + L.off_partials);
     a.jump = reinterpret_cast<uint32_t *>(ws + L.off_jump);
     a.coef = reinterpret_cast<float2 *>(ws + L.off_coef);
@@ -1500,6 +1501,7 @@ extern "C" int ld_run_backward(const rngld_cfg *cfg, const void *d_ckpt, size_t 
     a.t_end = loss->t_end;
     a.ckpt = const_cast<uint8_t *>(static_cast<const uint8_t *>(d_ckpt));
     a.rec_bytes = ckpt_record_bytes(g, n_total);
+    a.lam_row = ckpt_lam_row(g);
     a.scratch = L.any_replay ? reinterpret_cast<float *>(ws + L.off_scratch) : nullptr;
     a.seg_d = L.any_reg_only ? reinterpret_cast<double *>(ws + L.off_seg_d) : nullptr;
     a.partials = reinterpret_cast<double *>(ws + L.off_partials);

@@ -161,9 +161,11 @@ constexpr uint32_t kAdjPartW = 6;
 // per (oscillator, segment) record of the segment-parallel register-only backward: FP64 rows
 // [0, 3), the segment's three gradient sums
 constexpr uint32_t kAdjSegD = 3;
-// checkpoint rows of a Hybrid Taus record: x[3], v[3], the 4 generator rows, then the loss adjoint
-// lam_x[3], lam_v[3] of the record's state (written by the forward run for ensembles with lam)
-constexpr uint32_t kCkptLamRow = 10;
+// checkpoint rows of a record: x[3], v[3], the generator rows (4 for Hybrid Taus, 35 for Ran2), then
+// the loss adjoint lam_x[3], lam_v[3] of the record's state (written by the forward run for
+// ensembles with lam); AdjArgs::lam_row is the first adjoint row of the run's kind
+constexpr uint32_t kCkptLamRow = 6 + 4;
+constexpr uint32_t kCkptLamRowRan2 = 6 + 35;
 // segment-parallel forward: per (oscillator, segment) FP32 rows of the zero-start run: x_end[3],
 // v_end[3], sum of x^2 over the window steps, and per component sum a_j x_j and sum b_j x_j over
 // them
@@ -184,6 +186,7 @@ struct AdjArgs {
     uint32_t t_begin, t_end;
     uint8_t *ckpt;
     uint64_t rec_bytes;  // bytes per checkpoint record
+    uint32_t lam_row;    // first adjoint row of a record (kCkptLamRow or kCkptLamRowRan2)
     float *scratch;      // backward, replay path: [K][9][NT]
     double *seg_d;       // backward, register-only path: [nseg][kAdjSegD][NT]
     uint32_t *jump;      // forward, segment-parallel: [nseg][kJumpWords]

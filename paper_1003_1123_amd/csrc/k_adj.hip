@@ -8,10 +8,11 @@
 //     dL/dtheta += mu (dc/dtheta v - dkap/dtheta x + dsig/dtheta g).
 // The forward kernels write (x, v, generator state) every K steps and at the end.  The backward
 // kernels take one of two ways per ensemble:
-//  * register-only (Hybrid Taus): the forward run also leaves in each record the loss adjoint of
-//    the record's state (the recursion is linear with a step matrix B that is the same for every
-//    step of an ensemble, so each segment's own share, summed over its window steps, plus B^K
-//    times the adjoint at its end gives the adjoint at its start, walked last to first in FP64).
+//  * register-only (Hybrid Taus, Ran2): the forward run also leaves in each record the loss
+//    adjoint of the record's state (the recursion is linear with a step matrix B that is the same
+//    for every step of an ensemble, so each segment's own share, summed over its window steps,
+//    plus B^K times the adjoint at its end gives the adjoint at its start, walked last to first
+//    in FP64).
 //    Every segment then runs on its own, one thread per (oscillator, segment), forward in time
 //    from its start record: the same generator, Box-Muller and update code give the noise and the
 //    path bit for bit, and the adjoint is carried forward by solving the reverse step for lam'.
@@ -121,8 +122,8 @@ __device__ void adjoint_walk(const AdjArgs &a, uint64_t i, int d, const double b
         ox = ov = 0.0f;
         if (has_window(seg)) {
             const float *r = rec_f(seg);
-            ox = r[(kCkptLamRow + d) * NT + i];
-            ov = r[(kCkptLamRow + 3 + d) * NT + i];
+            ox = r[(a.lam_row + d) * NT + i];
+            ov = r[(a.lam_row + 3 + d) * NT + i];
         }
     };
     double lx = 0.0, lv = 0.0;
@@ -132,8 +133,8 @@ __device__ void adjoint_walk(const AdjArgs &a, uint64_t i, int d, const double b
         float px = 0.0f, pv = 0.0f;
         if (seg > 0) own(seg - 1, px, pv);
         float *r_end = rec_f(seg + 1);
-        r_end[(kCkptLamRow + d) * NT + i] = static_cast<float>(lx);
-        r_end[(kCkptLamRow + 3 + d) * NT + i] = static_cast<float>(lv);
+        r_end[(a.lam_row + d) * NT + i] = static_cast<float>(lx);
+        r_end[(a.lam_row + 3 + d) * NT + i] = static_cast<float>(lv);
         const double nx = bk[0] * lx + bk[1] * lv + ox;
         const double nv = bk[2] * lx + bk[3] * lv + ov;
         lx = nx;
@@ -142,8 +143,8 @@ __device__ void adjoint_walk(const AdjArgs &a, uint64_t i, int d, const double b
         ov = pv;
     }
     float *r0 = rec_f(0);
-    r0[(kCkptLamRow + d) * NT + i] = static_cast<float>(lx);
-    r0[(kCkptLamRow + 3 + d) * NT + i] = static_cast<float>(lv);
+    r0[(a.lam_row + d) * NT + i] = static_cast<float>(lx);
+    r0[(a.lam_row + 3 + d) * NT + i] = static_cast<float>(lv);
 }
 
 // forward run from the current state with checkpoints every K steps; loss partial = sum of x^2
@@ -238,8 +239,8 @@ __global__ __launch_bounds__(BLOCK) void ld_ckpt_kernel(AdjArgs a) {
             if (act)
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    rx[(kCkptLamRow + d) * NT + i] = 2.0f * ox[d];
-                    rx[(kCkptLamRow + 3 + d) * NT + i] = 2.0f * ov[d];
+                    rx[(a.lam_row + d) * NT + i] = 2.0f * ox[d];
+                    rx[(a.lam_row + 3 + d) * NT + i] = 2.0f * ov[d];
                 }
         } else {
             steps(std::true_type{}, std::false_type{}, lo, hi, lseg);
@@ -470,8 +471,8 @@ __global__ __launch_bounds__(3 * TILE) void ld_fwd_join_kernel(AdjArgs a) {
                 // the segment's loss terms sum_j (x0_j + a_j x + b_j v)^2 (x0 the zero-start path)
                 // and their gradient with respect to the start state (x, v), its own adjoint
                 lsum += cur.sxx + 2.0 * (x * cur.sa + v * cur.sb) + x * x * P[0] + 2.0 * x * v * P[1] + v * v * P[2];
-                rx[(kCkptLamRow + d) * NT + i] = static_cast<float>(2.0 * (cur.sa + P[0] * x + P[1] * v));
-                rx[(kCkptLamRow + 3 + d) * NT + i] = static_cast<float>(2.0 * (cur.sb + P[1] * x + P[2] * v));
+                rx[(a.lam_row + d) * NT + i] = static_cast<float>(2.0 * (cur.sa + P[0] * x + P[1] * v));
+                rx[(a.lam_row + 3 + d) * NT + i] = static_cast<float>(2.0 * (cur.sb + P[1] * x + P[2] * v));
             }
             const double *M = (s1 - s0 == a.K) ? A.fk : A.flast;
             const double nx = cur.xp + M[0] * x + M[1] * v;
@@ -566,8 +567,8 @@ __global__ __launch_bounds__(BLOCK) void ld_adjoint_kernel(AdjArgs a) {
     block_grad_partials<BLOCK>(act, gk, gg, gT, red, a.partials + static_cast<uint64_t>(tile) * kAdjPartW);
 }
 
-// register-only backward (Hybrid Taus), one thread per (oscillator, segment): blockIdx.y is the
-// segment.  The record at the segment's start holds its state and the loss adjoint A_s0 of that
+// register-only backward (Hybrid Taus, Ran2), one thread per (oscillator, segment): blockIdx.y is
+// the segment.  The record at the segment's start holds its state and the loss adjoint A_s0 of that
 // state (the gradient of the loss terms after it), so the segment runs forward in time: the same
 // generator, Box-Muller and update steps as the forward run give the noise and the path, and the
 // adjoint recursion A_s = B A'_{s+1} is solved for the adjoint of the step's outputs,
@@ -576,8 +577,9 @@ __global__ __launch_bounds__(BLOCK) void ld_adjoint_kernel(AdjArgs a) {
 // powers of B's inverse have the norms of the forward step matrix's inverse powers (B is its
 // transpose): the error growth the host bounds over K steps.  Each thread's sums are its segment's share of the gradient;
 // they go to seg_d and a second pass adds an oscillator's segments in order.
-template <int BLOCK>
+template <class Gen, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void ld_adjoint_seg_kernel(AdjArgs a) {
+    extern __shared__ int32_t lds[];  // Ran2: the threads' shuffle tables, [32][BLOCK]
     const uint32_t tile = blockIdx.x, seg = blockIdx.y;
     const uint32_t e = find_ensemble(a.ens, a.n_ens, tile);
     const EnsDev &E = a.ens[e];
@@ -597,11 +599,12 @@ __global__ __launch_bounds__(BLOCK) void ld_adjoint_seg_kernel(AdjArgs a) {
     for (int d = 0; d < 3; ++d) {
         x[d] = rec[d * NT + col];
         v[d] = rec[(3 + d) * NT + col];
-        lx[d] = rec[(kCkptLamRow + d) * NT + col];
-        lv[d] = rec[(kCkptLamRow + 3 + d) * NT + col];
+        lx[d] = rec[(a.lam_row + d) * NT + col];
+        lv[d] = rec[(a.lam_row + 3 + d) * NT + col];
     }
-    HybridTaus g;
-    g.load(reinterpret_cast<const uint32_t *>(rec + 6 * NT), NT, col);
+    Gen g;
+    bind_tab(g, lds, threadIdx.x, BLOCK);
+    load_state(g, rec + 6 * NT, NT, col);
     // the segment's gradient as sums over its steps and the three components of mu x, mu v and
     // mu g, scaled by the partials at the end: K terms per component in FP32
     float smx = 0.0f, smv = 0.0f, smg = 0.0f;
@@ -611,7 +614,7 @@ __global__ __launch_bounds__(BLOCK) void ld_adjoint_seg_kernel(AdjArgs a) {
         for (uint32_t s = b; s < e; ++s) {
             const uint32_t w0 = g.next_top24(), w1 = g.next_top24(), w2 = g.next_top24(), w3 = g.next_top24();
             float gf[3];
-            gaussian_forces_top24(w0, w1, w2, w3, gf[0], gf[1], gf[2]);
+            gaussian_forces_top24(w0, w1, w2, w3, gf[0], gf[1], gf[2], Gen::kTopScale);
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const float mu = __builtin_fmaf(lv[d], inv_c, lv[d] * inv_c_lo);
@@ -724,9 +727,12 @@ hipError_t launch_ld_adjoint(int kind, const AdjArgs &a, bool any_replay, bool a
         const hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
-    if (any_reg_only && kind == RNGLD_HYBRID_TAUS) {
+    if (any_reg_only) {
         const uint32_t nseg = (a.n_steps + a.K - 1) / a.K;
-        ld_adjoint_seg_kernel<kAdjBlock><<<dim3(a.n_tiles, nseg), kAdjBlock, 0, st>>>(a);
+        if (kind == RNGLD_RAN2)
+            ld_adjoint_seg_kernel<Ran2, kAdjBlock><<<dim3(a.n_tiles, nseg), kAdjBlock, kR2Tab * kAdjBlock * 4, st>>>(a);
+        else
+            ld_adjoint_seg_kernel<HybridTaus, kAdjBlock><<<dim3(a.n_tiles, nseg), kAdjBlock, 0, st>>>(a);
         const hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
         ld_adjoint_sum_kernel<kAdjBlock><<<a.n_tiles, kAdjBlock, 0, st>>>(a);

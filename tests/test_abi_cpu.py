@@ -184,8 +184,8 @@ def test_adjoint_sizing_and_validation():
     # 20 checkpoints plus the end state: x, v, the 4 state rows and the 6 adjoint rows
     assert R.ld_ckpt_bytes(c, 1000, 2000, 100) == 21 * 1000 * (6 + 4 + 6) * 4
     assert R.ld_ckpt_bytes(c, 1000, 2001, 100) == 22 * 1000 * (6 + 4 + 6) * 4
-    # Ran2: x, v and the 35 state rows
-    assert R.ld_ckpt_bytes(R.make_cfg("ran2", n_streams=1000), 1000, 2000, 100) == 21 * 1000 * (6 + 35) * 4
+    # Ran2: x, v, the 35 state rows and the 6 adjoint rows
+    assert R.ld_ckpt_bytes(R.make_cfg("ran2", n_streams=1000), 1000, 2000, 100) == 21 * 1000 * (6 + 35 + 6) * 4
     p = R.make_params()
     ens, n = R.make_ensembles([(0, 1000, p, 1)])
     loss = R.Loss(1001, 2000, 100, 0)
@@ -197,13 +197,15 @@ def test_adjoint_sizing_and_validation():
     ws = R.ld_adjoint_workspace_bytes(c, ens, n, 1000, 2000, loss)
     assert max(records, fwd_records) <= ws < max(records, fwd_records) + small
     assert R.ld_adjoint_workspace_bytes(c, ens, n, 1000, 2000, R.Loss(1001, 2000, 100, R.ADJ_SPREAD)) == ws
-    # forced replay, strong damping (gamma dt = 0.05 at K = 100) and Ran2 need the replay scratch
+    # forced replay and strong damping (gamma dt = 0.05 at K = 100) need the replay scratch
     ws_r = R.ld_adjoint_workspace_bytes(c, ens, n, 1000, 2000, R.Loss(1001, 2000, 100, R.ADJ_REPLAY))
     assert scratch <= ws_r < scratch + small
     ens5, n5 = R.make_ensembles([(0, 500, p, 1), (500, 500, R.make_params(gamma=5.0), 2)])
     assert R.ld_adjoint_workspace_bytes(c, ens5, n5, 1000, 2000, loss) >= scratch + records  # both paths
+    # weakly damped Ran2: sequential forward, register-only backward (no replay scratch)
     c2 = R.make_cfg("ran2", n_streams=1000)
-    assert scratch <= R.ld_adjoint_workspace_bytes(c2, ens, n, 1000, 2000, loss) < scratch + small
+    assert records <= R.ld_adjoint_workspace_bytes(c2, ens, n, 1000, 2000, loss) < records + small
+    assert scratch <= R.ld_adjoint_workspace_bytes(c2, ens, n, 1000, 2000, R.Loss(1001, 2000, 100, R.ADJ_REPLAY))
     with pytest.raises(R.RngldError) as e:
         R.ld_adjoint_workspace_bytes(c, ens, n, 1000, 2000, R.Loss(0, 2000, 100, 0))
     assert e.value.code == R.EINVAL

@@ -179,7 +179,8 @@ def _grads(kind, shape, params, T, tb, te, K, replay=False):
     return run, L.detach().cpu().numpy(), np.stack([k.grad.numpy(), g.grad.numpy(), kT.grad.numpy()], axis=1)
 
 
-def test_register_only_backward_equals_replay():
+@pytest.mark.parametrize("kind", ["taus", "ran2"])
+def test_register_only_backward_equals_replay(kind):
     """The register-only backward (each segment rerun forward from its start checkpoint, the loss
     adjoint carried forward from the one the forward run left there) against the replay backward
     on the same forward run: noise and path are the same bit for bit, so the gradients differ only
@@ -187,41 +188,50 @@ def test_register_only_backward_equals_replay():
     T, tb, te, K = 500, 101, 500, 64
     shape = [(3000, 1.0, 0.01, 5), (1000, 1.0, 0.01, 6)]
     params = [(1.0, 1.0, 1.0), (2.0, 1.5, 0.7)]
-    run_i, Li, gi = _grads("taus", shape, params, T, tb, te, K)
-    run_r, Lr, gr = _grads("taus", shape, params, T, tb, te, K, replay=True)
+    run_i, Li, gi = _grads(kind, shape, params, T, tb, te, K)
+    run_r, Lr, gr = _grads(kind, shape, params, T, tb, te, K, replay=True)
     assert run_i.ws.numel() < run_r.ws.numel()  # no replay scratch on the register-only path
     assert np.array_equal(Li, Lr)
     rel = np.abs(gi - gr) / np.abs(gr)
-    _say("register-only vs replay: relative gradient difference per component", rel)
+    _say(kind, "register-only vs replay: relative gradient difference per component", rel)
     # measured: about 1e-8 of each value
     assert np.all(rel <= 1e-5), (gi, gr)
 
 
-def test_checkpoint_end_record_is_the_final_state():
+STATE_ROWS = {"taus": 4, "ran2": 35}
+
+
+@pytest.mark.parametrize("kind", ["taus", "ran2"])
+def test_checkpoint_end_record_is_the_final_state(kind):
     N, T, K = 777, 130, 50  # records at steps 0, 50, 100 and the end state (step 130)
-    run, _, _ = _grads("taus", [(N, 1.0, 0.01, 9)], [(1.0, 1.0, 1.0)], T, 1, T, K)
-    rec = (6 + 4 + 6) * N * 4
+    S = STATE_ROWS[kind]
+    run, _, _ = _grads(kind, [(N, 1.0, 0.01, 9)], [(1.0, 1.0, 1.0)], T, 1, T, K)
+    rec = (6 + S + 6) * N * 4
     last = run.ckpt[3 * rec:4 * rec]
     assert torch.equal(last[:3 * N * 4].view(torch.float32), run.x)
     assert torch.equal(last[3 * N * 4:6 * N * 4].view(torch.float32), run.v)
-    assert torch.equal(last[6 * N * 4:10 * N * 4], run.state[:4 * N * 4])
+    assert torch.equal(last[6 * N * 4:(6 + S) * N * 4], run.state[:S * N * 4])
     # no loss term follows the end state: its adjoint rows are zero
-    assert not last[10 * N * 4:].view(torch.float32).any()
+    assert not last[(6 + S) * N * 4:].view(torch.float32).any()
 
 
-def test_checkpoint_adjoint_rows_are_the_window_gradient_of_the_recorded_state():
+@pytest.mark.parametrize("kind", ["taus", "ran2"])
+def test_checkpoint_adjoint_rows_are_the_window_gradient_of_the_recorded_state(kind):
     """The adjoint rows of a checkpoint record hold the gradient of the sum of x^2 over the loss
     window's steps after the record with respect to the record's x and v.  Checked against central
     differences of the FP64 oracle's loss, run from the record's own state (its generator rows are
     bit-exact): for fixed noise the loss is quadratic in the starting state, so the difference is
-    exact up to rounding.  The window starts and ends inside segments, and the last one is short."""
+    exact up to rounding.  The window starts and ends inside segments, and the last one is short.
+    Hybrid Taus records come from the segment-parallel forward, Ran2 records from the sequential
+    one."""
     N, T, tb, te, K = 300, 300, 101, 280, 64  # records at steps 0, 64, 128, 192, 256 and 300
+    S = STATE_ROWS[kind]
     pp = W.LDParams(k=1.2, gamma=0.8, kT=1.1, dt=0.01).as_f32()
     pd = pp.asdict()
-    run = A.AdjointRun("taus", [(N, pp.m, pp.dt, 77)], T, tb, te, K)
+    run = A.AdjointRun(kind, [(N, pp.m, pp.dt, 77)], T, tb, te, K)
     A.LDAdjoint.apply(*(torch.tensor([a], dtype=torch.float64) for a in (pp.k, pp.gamma, pp.kT)), run)
     torch.cuda.synchronize()
-    rows = 6 + 4 + 6
+    rows = 6 + S + 6
     ck = run.ckpt.cpu()
     worst = 0.0
     for r in (0, 1, 2, 4):
@@ -234,27 +244,27 @@ def test_checkpoint_adjoint_rows_are_the_window_gradient_of_the_recorded_state()
         # the record's generator rows: the seeded streams after 4 draws per step, bit for bit; its
         # x and v: the oracle's run from rest over the same steps
         ids = np.arange(N)
-        st_o = orc.seed_states("taus", 77, ids)
-        xo, vo, _ = orc.ld_run("taus", st_o, N, step, pd)
-        assert np.array_equal(u[6:10].T, st_o), r
+        st_o = orc.seed_states(kind, 77, ids)
+        xo, vo, _ = orc.ld_run(kind, st_o, N, step, pd)
+        assert np.array_equal(u[6:6 + S].T, st_o.view(np.uint32)), r
         assert np.max(np.abs(f[0:3] - xo)) <= 1e-4 * max(1.0, np.max(np.abs(xo))), r
         assert np.max(np.abs(f[3:6] - vo)) <= 1e-4 * max(1.0, np.max(np.abs(vo))), r
         for i in (0, 7, 255, 299):
             x0 = f[0:3, i:i + 1].astype(np.float64)
             v0 = f[3:6, i:i + 1].astype(np.float64)
-            st = np.ascontiguousarray(u[6:10, i][None, :])
+            st = np.ascontiguousarray(u[6:6 + S, i][None, :]).view(st_o.dtype)
 
             def loss(which, d, delta):
                 xx, vv = x0.copy(), v0.copy()
                 (xx if which == 0 else vv)[d, 0] += delta
-                return orc.ld_loss("taus", st.copy(), 1, T - step, pd, tb_r, te_r, xx, vv)
+                return orc.ld_loss(kind, st.copy(), 1, T - step, pd, tb_r, te_r, xx, vv)
 
             fd = np.array([[(loss(w, d, 1e-2) - loss(w, d, -1e-2)) / 2e-2 * scale for d in range(3)] for w in (0, 1)])
-            got = f[10:16, i].reshape(2, 3).astype(np.float64)
+            got = f[6 + S:12 + S, i].reshape(2, 3).astype(np.float64)
             err = np.max(np.abs(got - fd)) / np.max(np.abs(fd))
             worst = max(worst, err)
             assert err <= 1e-4, (r, i, got, fd)
-    _say("checkpoint adjoint rows vs oracle differences: worst relative error", worst)
+    _say(kind, "checkpoint adjoint rows vs oracle differences: worst relative error", worst)
 
 
 def test_mixed_paths_match_the_oracle():
