@@ -67,7 +67,9 @@ __global__ __launch_bounds__(kBulkBlock) void ran2_uniform_kernel(int32_t *st, u
     g.tstride = kBulkBlock;
     g.load(st, S, j);
     uint32_t *o = out + j;
-    for (uint64_t t = 0; t < per_stream; ++t) o[t * S] = g.next_iym1() + 1u;
+    // streaming stores: 1.24-1.29e12 values/s at 2^20 streams x 1024 against 1.14e12 with ordinary
+    // ones (the Hybrid Taus, LCG and Gaussian kernels measured no faster or slower with them)
+    for (uint64_t t = 0; t < per_stream; ++t) __builtin_nontemporal_store(g.next_iym1() + 1u, o + t * S);
     g.store(st, S, j);
 }
 
