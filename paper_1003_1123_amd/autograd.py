@@ -4,9 +4,9 @@ Forward runs ld_run_ckpt (checkpoints x, v and the generator state every K steps
 backward runs ld_run_backward, which regenerates each segment's noise bit-exactly from the
 checkpoint at its start -- either carrying the loss adjoint that the forward run left there forward
 in time through the segment, all segments at once and nothing stored per step (weakly damped
-ensembles), or replaying the segment into a scratch and sweeping the adjoint recursion backward.  The loss of
-ensemble e is the mean over steps t_begin..t_end of <x^2>_e (per component, over the ensemble's 3n
-coordinates).
+ensembles), or replaying the segment into a scratch and sweeping the adjoint recursion backward.
+The loss of ensemble e is the mean over steps t_begin..t_end of <x^2>_e (per component, over the
+ensemble's 3n coordinates).
 """
 from __future__ import annotations
 

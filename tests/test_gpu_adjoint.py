@@ -267,16 +267,17 @@ def test_checkpoint_adjoint_rows_are_the_window_gradient_of_the_recorded_state(k
     _say(kind, "checkpoint adjoint rows vs oracle differences: worst relative error", worst)
 
 
-def test_mixed_paths_match_the_oracle():
+@pytest.mark.parametrize("kind", ["taus", "ran2"])
+def test_mixed_paths_match_the_oracle(kind):
     """A strongly damped ensemble (gamma dt = 0.06: replay) batched with a weakly damped one
     (register-only); each against the FP64 oracle adjoint."""
     T, tb, te, K = 300, 1, 300, 100
     shape = [(800, 1.0, 0.01, 21), (600, 1.0, 0.01, 22)]
     params = [(1.0, 0.5, 1.0), (1.5, 6.0, 0.8)]
-    _, L, grad = _grads("taus", shape, params, T, tb, te, K)
+    _, L, grad = _grads(kind, shape, params, T, tb, te, K)
     for e, ((n, m, dt, seed), (k, gm, kT)) in enumerate(zip(shape, params)):
         pd = W.LDParams(m=m, k=k, gamma=gm, kT=kT, dt=dt).as_f32().asdict()
-        Lo, go = orc.ld_adjoint("taus", orc.seed_states("taus", seed, np.arange(n)), n, T, pd, tb, te)
+        Lo, go = orc.ld_adjoint(kind, orc.seed_states(kind, seed, np.arange(n)), n, T, pd, tb, te)
         assert abs(L[e] - Lo) <= 1e-4 * abs(Lo)
         scale = np.max(np.abs(go))
         assert np.all(np.abs(grad[e] - go) <= 1e-3 * np.maximum(np.abs(go), 1e-2 * scale)), (e, grad[e], go)
