@@ -12,11 +12,10 @@
 //    adjoint of the record's state (the recursion is linear with a step matrix B that is the same
 //    for every step of an ensemble, so each segment's own share, summed over its window steps,
 //    plus B^K times the adjoint at its end gives the adjoint at its start, walked last to first
-//    in FP64).
-//    Every segment then runs on its own, one thread per (oscillator, segment), forward in time
-//    from its start record: the same generator, Box-Muller and update code give the noise and the
-//    path bit for bit, and the adjoint is carried forward by solving the reverse step for lam'.
-//    Nothing is stored per step.
+//    in FP64).  Every segment then runs on its own, one thread per (oscillator, segment), forward
+//    in time from its start record: the same generator, Box-Muller and update code give the noise
+//    and the path bit for bit, and the adjoint is carried forward by solving the reverse step for
+//    lam'.  Nothing is stored per step.
 //  * replay: restore the checkpoint at the segment's start, rerun the segment with the same
 //    generator, Box-Muller and update code, keep its path in a per-thread scratch column, and
 //    sweep it backward, segments last to first.
@@ -344,7 +343,8 @@ __global__ __launch_bounds__(128) void adj_prep_kernel(AdjArgs a, uint32_t nseg)
             if (m & 1) mat2_mul(pf, sf, pf);
             mat2_mul(sf, sf, sf);
         }
-        a.coef[static_cast<uint64_t>(e) * a.K + j - 1] = make_float2(static_cast<float>(pf[0]), static_cast<float>(pf[1]));
+        a.coef[static_cast<uint64_t>(e) * a.K + j - 1] =
+            make_float2(static_cast<float>(pf[0]), static_cast<float>(pf[1]));
     }
 }
 
