@@ -86,12 +86,13 @@ __device__ __forceinline__ void block_grad_partials(bool act, double gk, double 
     block_sum6<BLOCK>(q, red, dst);
 }
 
-// one step of the adjoint recursion with no loss term: (lam_x, lam_v) <- B (lam_x, lam_v),
-// mu = lam_v + h lam_x, lam_x' = lam_x - kap mu, lam_v' = c mu
-__device__ __forceinline__ void adjoint_step(const LdCoef &q, float &lx, float &lv) {
-    const float mu = lv + q.h * lx;
-    lx = lx - q.kap * mu;
-    lv = q.c * mu;
+// one step of the adjoint recursion with no loss term, in FP64 with the ensemble's binary32
+// coefficients: (lam_x, lam_v) <- B (lam_x, lam_v), mu = lam_v + h lam_x, lam_x' = lam_x - kap mu,
+// lam_v' = c mu
+__device__ __forceinline__ void adjoint_step(const LdCoef &q, double &lx, double &lv) {
+    const double mu = lv + static_cast<double>(q.h) * lx;
+    lx = lx - static_cast<double>(q.kap) * mu;
+    lv = static_cast<double>(q.c) * mu;
 }
 
 // the loss window's step range [lo, hi) within steps [s0, s1): the loss takes the positions after
@@ -181,8 +182,9 @@ __global__ __launch_bounds__(BLOCK) void ld_ckpt_kernel(AdjArgs a) {
     } else {
         park(g);
     }
-    // B^j e1 of the current step and the segment's own adjoint sums (without the factor 2)
-    float al = 0.0f, be = 0.0f, ox[3] = {0, 0, 0}, ov[3] = {0, 0, 0};
+    // B^j e1 of the current step and the segment's own adjoint sums (without the factor 2), in FP64:
+    // they are the starting adjoint of the register-only backward, carried over up to K steps
+    double al = 0.0, be = 0.0, ox[3] = {0, 0, 0}, ov[3] = {0, 0, 0};
     // steps [s, e) of the run, adding x^2 after each step to lseg when LOSS and the step's own
     // adjoint terms when LAM
     auto steps = [&](auto loss_tag, auto lam_tag, uint32_t s, uint32_t e, float &lseg) {
@@ -228,18 +230,18 @@ __global__ __launch_bounds__(BLOCK) void ld_ckpt_kernel(AdjArgs a) {
         steps(std::false_type{}, std::false_type{}, s0, lo, lseg);
         if (lam && hi > lo) {
             // B^(lo - s0) e1 before the first window step
-            al = 1.0f;
-            be = 0.0f;
+            al = 1.0;
+            be = 0.0;
             for (uint32_t j = s0; j < lo; ++j) adjoint_step(q, al, be);
 #pragma unroll
-            for (int d = 0; d < 3; ++d) ox[d] = ov[d] = 0.0f;
+            for (int d = 0; d < 3; ++d) ox[d] = ov[d] = 0.0;
             steps(std::true_type{}, std::true_type{}, lo, hi, lseg);
             // the segment's own adjoint, parked in its start record until the last pass
             if (act)
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    rx[(a.lam_row + d) * NT + i] = 2.0f * ox[d];
-                    rx[(a.lam_row + 3 + d) * NT + i] = 2.0f * ov[d];
+                    rx[(a.lam_row + d) * NT + i] = static_cast<float>(2.0 * ox[d]);
+                    rx[(a.lam_row + 3 + d) * NT + i] = static_cast<float>(2.0 * ov[d]);
                 }
         } else {
             steps(std::true_type{}, std::false_type{}, lo, hi, lseg);

@@ -86,10 +86,10 @@ def test_adjoint_batched_equals_plain():
                                                                     kT.grad[e].item())
 
 
-def _config5_grad(spread=False):
+def _config5_grad(spread=False, kind="taus"):
     c = W.C5
     pp = c["params"].as_f32()
-    run = A.AdjointRun("taus", [(c["N"], pp.m, pp.dt, c["seed"])], c["steps"], c["t_begin"], c["t_end"], c["K"],
+    run = A.AdjointRun(kind, [(c["N"], pp.m, pp.dt, c["seed"])], c["steps"], c["t_begin"], c["t_end"], c["K"],
                        spread=spread)
     k = torch.tensor([pp.k], dtype=torch.float64, requires_grad=True)
     g = torch.tensor([pp.gamma], dtype=torch.float64, requires_grad=True)
@@ -148,22 +148,26 @@ def test_config5_gradients():
     assert np.all(np.abs(fd[5e-2] - grad) <= 1e-2 * np.abs(grad) + trunc + floor), (fd, grad, floor)
 
 
-def test_config5_gradients_match_the_oracle():
+@pytest.mark.parametrize("kind", ["taus", "ran2"])
+def test_config5_gradients_match_the_oracle(kind):
     """The config-5 gradients (N = 1e5, 2000 steps, every oscillator) against the FP64 oracle
     adjoint of the same oscillators and noise.  Iterating the binary32 coefficients the run uses,
     each component agrees within 1e-4 of its own value.  Against the oracle with exact
     coefficients the difference is set by their rounding (see the finite-difference test), which
-    the difference of the two oracle runs measures."""
+    the difference of the two oracle runs measures.  Config 5 names Hybrid Taus (segment-parallel
+    forward); the same workload with Ran2 checks its sequential forward and register-only
+    backward at full size."""
     c = W.C5
     pp = c["params"].as_f32()
-    _, L, grad = _config5_grad()
-    args = ("taus", c["seed"], c["N"], c["steps"], pp.asdict(), c["t_begin"], c["t_end"])
+    _, L, grad = _config5_grad(kind=kind)
+    args = (kind, c["seed"], c["N"], c["steps"], pp.asdict(), c["t_begin"], c["t_end"])
     L32, g32 = orc.ld_adjoint_split(*args, coef=_f32_coef(pp))
     L64, g64 = orc.ld_adjoint_split(*args)
-    _say("config5 GPU", L, grad, "oracle (binary32 coefficients)", L32, g32, "relative", np.abs(grad - g32) / np.abs(g32))
+    _say(kind, "config5 GPU", L, grad, "oracle (binary32 coefficients)", L32, g32, "relative",
+         np.abs(grad - g32) / np.abs(g32))
     _say("oracle (exact coefficients)", L64, g64, "relative", np.abs(grad - g64) / np.abs(g64))
     assert abs(L - L32) <= 1e-5 * abs(L32)
-    # measured: 3e-8, 4e-6 and 4e-8 of the three values
+    # measured (Hybrid Taus): 3e-8, 4e-6 and 4e-8 of the three values
     assert np.all(np.abs(grad - g32) <= 1e-4 * np.abs(g32)), (grad, g32)
     assert np.all(np.abs(grad - g64) <= 1e-3 * np.abs(g64) + 2.0 * np.abs(g64 - g32)), (grad, g64, g32)
 
