@@ -180,7 +180,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", default="", help="comma list of generators (profiling runs)")
-    ap.add_argument("--extras", default="", help="comma list of extras to run (profiling runs; default: all but step_protocol)")
+    ap.add_argument("--extras", default="", help="comma list of extras to run (profiling runs; default: all but step_protocol and wave_rounds)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (a plain copy of known size, for scaling "
                          "hardware byte counters)")
@@ -811,9 +811,54 @@ def extra_step_protocol(R, W, torch):
     return out
 
 
+def extra_wave_rounds(R, W, torch):
+    """The fused Hybrid Taus and Ran2 runs of config 2 (10^4 steps, observables every 100) at
+    N = 10^6 and at the nearest N below it whose waves spread evenly over the SIMDs (15 per SIMD on
+    256 CUs).  At N = 10^6 the 15,625 waves leave 265 SIMDs a 16th wave, which runs after the others
+    have finished; the even N shows the step loop's rate without that tail."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    simds = 4 * cus
+    N_even = (10**6 // (64 * simds)) * 64 * simds
+    c = W.C2
+    pp = c["params"].as_f32()
+    p = R.make_params(pp.m, pp.k, pp.gamma, pp.kT, pp.dt)
+    T, stride = c["steps"], 100
+    out = {"simds": simds, "steps": T, "runs": []}
+    for kind in ("taus", "ran2"):
+        bound = valu_mix_bound(kind)
+        for N in (N_even, 10**6):
+            cfg = R.make_cfg(kind, seed=c["seed"], n_streams=N)
+            st = R.new_state(cfg)
+            ens, n_ens = R.make_ensembles([(0, N, p, 0)])
+            x = torch.zeros(3 * N, dtype=torch.float32, device="cuda")
+            v = torch.zeros_like(x)
+            obs = torch.zeros((T // stride + 1) * R.NOBS, dtype=torch.float64, device="cuda")
+            ws = torch.empty(max(R.ld_workspace_bytes(cfg, ens, n_ens, N, T, R.Obs(stride, 0)), 256),
+                             dtype=torch.uint8, device="cuda")
+            ms = []
+            for rep in range(3):  # the first run is a warm-up
+                R.rng_init(cfg, st)
+                x.zero_()
+                v.zero_()
+                a, b = _ev(torch)
+                a.record()
+                R.ld_run(cfg, st, ens, n_ens, N, T, x, v, R.Obs(stride, 0), obs, ws)
+                b.record()
+                torch.cuda.synchronize()
+                if rep:
+                    ms.append(a.elapsed_time(b))
+            rate = N * T / (min(ms) * 1e-3)
+            out["runs"].append({"kind": kind, "N": N, "waves_per_simd": N / 64 / simds, "ms": min(ms),
+                                "osc_steps_per_s": rate,
+                                "frac_of_mix_bound": rate / bound if bound else None})
+            del st, x, v, obs, ws
+    return out
+
+
 def extras(R, W, torch, only=()):
     out = {}
-    named_only = {"step_protocol": extra_step_protocol}  # run only when asked for by name
+    named_only = {"step_protocol": extra_step_protocol,  # run only when asked for by name
+                  "wave_rounds": extra_wave_rounds}
     for name, fn in (("config3_bare_generators", extra_config3), ("config4_batched", extra_config4),
                      ("config5_adjoint", extra_config5), ("fig6_breakdown", extra_fig6_breakdown),
                      *named_only.items()):

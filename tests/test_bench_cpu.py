@@ -109,15 +109,19 @@ def test_ran2_step_line_bytes():
     assert bench.STEP_LINE_BYTES_RAN2 == 2 * 12 + 2 * 128 + 48 == 328
 
 
-def test_step_protocol_extra_runs_only_when_named(monkeypatch):
+def test_profiling_extras_run_only_when_named(monkeypatch):
     ran = []
-    for name in ("extra_config3", "extra_config4", "extra_config5", "extra_fig6_breakdown", "extra_step_protocol"):
+    for name in ("extra_config3", "extra_config4", "extra_config5", "extra_fig6_breakdown", "extra_step_protocol",
+                 "extra_wave_rounds"):
         monkeypatch.setattr(bench, name, lambda R, W, torch, _n=name: ran.append(_n) or {})
     bench.extras(None, None, None)
     assert ran == ["extra_config3", "extra_config4", "extra_config5", "extra_fig6_breakdown"]
     ran.clear()
     bench.extras(None, None, None, ("step_protocol",))
     assert ran == ["extra_step_protocol"]
+    ran.clear()
+    bench.extras(None, None, None, ("wave_rounds",))
+    assert ran == ["extra_wave_rounds"]
 
 
 def test_windowed_valu_weights_the_window_loop():
