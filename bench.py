@@ -391,7 +391,7 @@ def cpu_extras(W):
     """The oracle on bounded samples of configs 3-5, every figure labelled with what was measured
     and how it scales: config 3 (bare streams, one core and all cores; the lagged Fibonacci stream
     on one core, being one sequence), config 4 (8 sampled ensembles, extrapolated to the whole
-    batch), config 5 (adjoint and the common-random-number differences at N = 2000, extrapolated)."""
+    batch), config 5 (adjoint and the common-random-number differences at N = 10^4, extrapolated)."""
     import concurrent.futures as cf
     import multiprocessing as mp
 
@@ -450,7 +450,7 @@ def cpu_extras(W):
                                 "(%d oscillator-steps), extrapolated to all %d" % (n_os, total)}
     c5 = W.C5
     pp = c5["params"].as_f32().asdict()
-    N5 = 2000
+    N5 = 10**4
     t = time.perf_counter()
     orc.ld_adjoint("taus", orc.seed_states("taus", c5["seed"], np.arange(N5)), N5, c5["steps"], pp, c5["t_begin"],
                    c5["t_end"])
@@ -466,7 +466,7 @@ def cpu_extras(W):
     out["config5"] = {"N": N5, "adjoint_s_1core": t_adj, "crn_fd_6_forwards_s_1core": t_fd,
                       "extrapolated_to_N_1e5": {"adjoint_s_1core": t_adj * 1e5 / N5,
                                                 "crn_fd_6_forwards_s_1core": t_fd * 1e5 / N5},
-                      "sample": "N = 2000 oscillators, 2000 steps, extrapolated linearly to config 5's N = 1e5"}
+                      "sample": "N = 1e4 oscillators, 2000 steps, extrapolated linearly to config 5's N = 1e5"}
     return out
 
 
