@@ -91,7 +91,7 @@ def _function_bodies(asm: str, name: str):
 
 def step_loop_valu(asm: str, symbol: str) -> dict:
     """Vector-ALU instructions of the step loop of `symbol`, by opcode: among the loops that contain
-    a v_log_f32 (one oscillator-step per iteration) and no smaller such loop, the largest one (the
+    a v_log_f32 (one oscillator-step per iteration) and no other loop, the largest one (the
     underdamped scheme where a kernel holds both).  Every instruction of the loop body counts once, including
     any branch that runs on some iterations only."""
     lines = asm.splitlines()
@@ -106,8 +106,10 @@ def step_loop_valu(asm: str, symbol: str) -> dict:
             spans.append((labels[m.group(1)], i))
     ops_of = {(a, b): [x.split()[0] for x in body[a:b + 1] if x.strip().startswith("v_")] for a, b in spans}
     stepping = [sp for sp in spans if "v_log_f32_e32" in ops_of[sp]]
+    # loops with no loop inside them (a loop around a step loop, or around the code between events
+    # with its reduction loops, is not one)
     innermost = [sp for sp in stepping
-                 if not any(sp[0] <= c and d <= sp[1] and (c, d) != sp for c, d in stepping)]
+                 if not any(sp[0] <= c and d <= sp[1] and (c, d) != sp for c, d in spans)]
     if not innermost:
         raise RuntimeError("no step loop found in %s" % symbol)
     best = max((ops_of[sp] for sp in innermost), key=len)
