@@ -109,7 +109,7 @@ struct Lcg32 {
 };
 
 // ---- no random force ----------------------------------------------------------------------------------
-// The deterministic part of the LD step alone (the "dynamics without random numbers" of Fig. 6): no
+// The deterministic part of the LD step alone (Fig. 6's timing of the dynamics with no random forces): no
 // state, no draws; the kernels use a zero force in place of the Box-Muller output.
 struct NoNoise {
     static constexpr int kRows = 0;

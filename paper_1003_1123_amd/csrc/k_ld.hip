@@ -1,7 +1,7 @@
 // k_ld.hip -- fused RNG + Langevin-dynamics kernels for the per-thread generators.
 //
 // The paper launches one kernel per LD step and keeps generator state in global memory between
-// steps (Sec. III.B; Fig. 2; Sec. IV "synchronized at the end of each step").  Here one launch runs
+// steps (Sec. III.B; Fig. 2; Sec. IV, where all threads synchronise after every step).  Here one launch runs
 // many steps: every thread keeps its oscillators' x, v and its generator state in VGPRs (Ran2's
 // shuffle table in LDS) from the first step of the launch to the last, so device memory is
 // touched once per launch, not once per step.  ld_step_* keeps the paper's per-step protocol.
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(kBulkBlock) void u32_step_kernel(uint32_t *st, uint
 }
 
 // Ran2 with its shuffle table left in device memory and touched at the selected entry only
-// (Alg. 2: "portion of the RNG state in GPU global memory").
+// (Alg. 2 keeps each thread's part of the generator state in global memory between steps).
 __global__ __launch_bounds__(kBulkBlock) void ran2_step_kernel(int32_t *st, uint64_t S, LdCoef q, uint64_t n,
                                                                float *x, float *v) {
     const uint64_t i = blockIdx.x * static_cast<uint64_t>(kBulkBlock) + threadIdx.x;
@@ -269,18 +269,25 @@ __global__ __launch_bounds__(kBulkBlock) void ran2_step_kernel(int32_t *st, uint
     }
 }
 
-__global__ __launch_bounds__(64) void obs_finalize_kernel(const double *partials, uint32_t n_tiles, uint32_t P,
-                                                          const EnsDev *ens, double *out) {
+// One block per (point, ensemble): thread j sums the six observables of the ensemble's tiles j,
+// j + 256, ... in tile order (one tile's six partials are 48 contiguous bytes, so a wave reads
+// consecutive tiles' whole records), then the block adds its threads' sums in a fixed order.  The
+// order depends only on the ensemble's tile count.
+constexpr int kFinBlock = 256;
+__global__ __launch_bounds__(kFinBlock) void obs_finalize_kernel(const double *partials, uint32_t n_tiles,
+                                                                 uint32_t P, const EnsDev *ens, double *out) {
+    __shared__ double red[kFinBlock / 64][kNobs];
     const uint32_t p = blockIdx.x, e = blockIdx.y;
     const EnsDev &E = ens[e];
-    const double denom = 3.0 * static_cast<double>(E.n);
-    for (int qi = 0; qi < kNobs; ++qi) {
-        double acc = 0.0;
-        for (uint32_t t = threadIdx.x; t < E.n_tiles; t += 64)
-            acc += partials[(static_cast<uint64_t>(p) * n_tiles + E.tile_begin + t) * kNobs + qi];
-        acc = wave_sum(acc);
-        if (threadIdx.x == 0) out[(static_cast<uint64_t>(e) * P + p) * kNobs + qi] = E.n ? acc / denom : 0.0;
-    }
+    const double *src = partials + (static_cast<uint64_t>(p) * n_tiles + E.tile_begin) * kNobs;
+    double acc[kNobs] = {0, 0, 0, 0, 0, 0};
+#pragma unroll 4
+    for (uint32_t t = threadIdx.x; t < E.n_tiles; t += kFinBlock)
+#pragma unroll
+        for (int qi = 0; qi < kNobs; ++qi) acc[qi] += src[static_cast<uint64_t>(t) * kNobs + qi];
+    double *dst = out + (static_cast<uint64_t>(e) * P + p) * kNobs;
+    block_sum6<kFinBlock>(acc, red, dst);
+    if (threadIdx.x < kNobs) dst[threadIdx.x] = E.n ? dst[threadIdx.x] / (3.0 * static_cast<double>(E.n)) : 0.0;
 }
 
 struct UploadBlob {
@@ -333,7 +340,7 @@ hipError_t launch_ld_run(int kind, const LdArgs &a, const ld_tuning &t, uint32_t
 hipError_t launch_obs_finalize(const double *partials, uint32_t n_tiles, uint32_t P, const EnsDev *ens,
                                uint32_t n_ens, double *out, hipStream_t st) {
     if (P == 0 || n_ens == 0) return hipSuccess;
-    obs_finalize_kernel<<<dim3(P, n_ens), 64, 0, st>>>(partials, n_tiles, P, ens, out);
+    obs_finalize_kernel<<<dim3(P, n_ens), kFinBlock, 0, st>>>(partials, n_tiles, P, ens, out);
     return hipGetLastError();
 }
 
