@@ -426,6 +426,86 @@ def test_graph_plan_replays_advance_the_run(kind):
     plan.close()
 
 
+def _moments(x, v, n_total, lo, n, x0=None, v0=None):
+    """The six observables of oscillators [lo, lo + n) from state vectors ([3][n_total] layout), in
+    FP64: means over their 3n coordinates of x^2, v^2, x v, x, x x0, v v0."""
+    xs = x.double().view(3, n_total)[:, lo:lo + n]
+    vs = v.double().view(3, n_total)[:, lo:lo + n]
+    m = [float((xs * xs).mean()), float((vs * vs).mean()), float((xs * vs).mean()), float(xs.mean())]
+    if x0 is None:
+        return m + [0.0, 0.0]
+    x0s = x0.double().view(3, n_total)[:, lo:lo + n]
+    v0s = v0.double().view(3, n_total)[:, lo:lo + n]
+    return m + [float((xs * x0s).mean()), float((vs * v0s).mean())]
+
+
+@pytest.mark.parametrize("kind", ["taus", "ran2", "lf"])
+def test_observables_equal_the_moments_of_the_returned_state(kind):
+    """The observables' reduction (per-tile partials, then the fixed-order sum over an ensemble's
+    tiles) against the same means taken directly from the state the run returns: N = 300,000
+    oscillators (a ragged last tile; more tiles than the final sum has threads, so each thread
+    adds several), random initial x and v, observation points 0, 10, 20 with t0 = 10.  Point 0 is
+    the initial state, point 20 the returned one, and its x(t0) terms come from a second run of the
+    same stream stopped at step 10.  Only the order of the FP64 additions differs, so the two agree
+    to about 1e-13."""
+    N, T, stride, t0 = 300_000, 20, 10, 10
+    rng = np.random.default_rng(5)
+    xi = rng.standard_normal(3 * N).astype(np.float32)
+    vi = rng.standard_normal(3 * N).astype(np.float32)
+    p = W.C1["params"].as_f32()
+    lags = dict(zip(("ll", "sl"), _lf_lags(N))) if kind == "lf" else {}
+    ens, n_ens = R.make_ensembles([(0, N, _params(p), 0)])
+    obs = R.Obs(stride, t0)
+    _say("observables vs state moments", kind, N, T)
+    cfg, st, x, v = _setup(kind, N, x0=xi, v0=vi, **lags)
+    x_init, v_init = x.clone(), v.clone()
+    out = torch.zeros(n_ens * (T // stride + 1) * R.NOBS, dtype=torch.float64, device="cuda")
+    ws = R.ld_run(cfg, st, ens, n_ens, N, T, x, v, obs, out)
+    assert R.ws_status(ws) == 0
+    cfg_h, st_h, xh, vh = _setup(kind, N, x0=xi, v0=vi, **lags)
+    R.ld_run(cfg_h, st_h, ens, n_ens, N, t0, xh, vh)
+    o = out.cpu().numpy().reshape(T // stride + 1, R.NOBS)
+    want0 = _moments(x_init, v_init, N, 0, N)
+    want2 = _moments(x, v, N, 0, N, xh, vh)
+    err = max(abs(o[0, q] - want0[q]) / max(abs(want0[q]), 1e-3) for q in range(R.NOBS))
+    err = max(err, max(abs(o[2, q] - want2[q]) / max(abs(want2[q]), 1e-3) for q in range(R.NOBS)))
+    _say("largest relative difference", err)
+    assert err < 1e-11
+
+
+def test_batched_observables_equal_the_moments_of_each_ensemble():
+    """The same check for a batched run of three uneven Hybrid Taus ensembles (the final sum over
+    each ensemble's own tiles, starting at its first tile): point 0 and the last point of each
+    ensemble against the means over that ensemble's oscillators."""
+    sizes = (70_001, 129_999, 100_000)
+    n_total, T, stride = sum(sizes), 20, 20
+    rng = np.random.default_rng(6)
+    xi = rng.standard_normal(3 * n_total).astype(np.float32)
+    vi = rng.standard_normal(3 * n_total).astype(np.float32)
+    specs, off = [], 0
+    for e, n in enumerate(sizes):
+        specs.append((off, n, R.make_params(1.0, 0.5 + e, 0.3 + e, 1.0 + 0.25 * e, 0.01), 1234 + e))
+        off += n
+    ens, n_ens = R.make_ensembles(specs)
+    cfg = R.make_cfg("taus", n_streams=n_total)
+    st = R.new_state(cfg)
+    R.rng_init_ensembles(cfg, st, ens, n_ens)
+    x = torch.as_tensor(xi).cuda()
+    v = torch.as_tensor(vi).cuda()
+    x_init, v_init = x.clone(), v.clone()
+    out = torch.zeros(n_ens * 2 * R.NOBS, dtype=torch.float64, device="cuda")
+    _say("batched observables vs state moments", sizes, T)
+    R.ld_run(cfg, st, ens, n_ens, n_total, T, x, v, R.Obs(stride, 0), out)
+    o = out.cpu().numpy().reshape(n_ens, 2, R.NOBS)
+    err = 0.0
+    for e, (lo, n, _, _) in enumerate(specs):
+        for pt, want in ((0, _moments(x_init, v_init, n_total, lo, n, x_init, v_init)),
+                         (1, _moments(x, v, n_total, lo, n, x_init, v_init))):
+            err = max(err, max(abs(o[e, pt, q] - want[q]) / max(abs(want[q]), 1e-3) for q in range(R.NOBS)))
+    _say("largest relative difference", err)
+    assert err < 1e-11
+
+
 def test_edge_cases():
     p = _params(W.LDParams())
     # one oscillator
